@@ -1,0 +1,185 @@
+"""Python access to the reference interpreter in ``vc_oracle.c``.
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this module.  The library under test never loads it.
+
+Every function here marshals numpy arrays into the C interpreter and back; no
+arithmetic of the checked method is done in Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "vc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no vectorisation flags needed)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def load(path: str):
+    """Load an oracle shared object and declare its signatures."""
+    L = C.CDLL(path)
+    P = C.c_void_p
+    u64, u32, i32 = C.c_uint64, C.c_uint32, C.c_int
+    pu64 = C.POINTER(C.c_uint64)
+    L.oracle_check.argtypes = [P, u64, u32, P, P, P, P, u64, pu64, pu64, pu64]
+    L.oracle_check.restype = i32
+    L.oracle_check_count.argtypes = [P, u64, u32, P]
+    L.oracle_check_count.restype = u64
+    L.oracle_translate.argtypes = [P, u64, P, u32, P, P, P, u64, pu64, pu64]
+    L.oracle_translate.restype = i32
+    L.oracle_overlap_sets.argtypes = [P, P, u32, P, P, u64]
+    L.oracle_overlap_sets.restype = u64
+    L.oracle_check_overlap.argtypes = [P, u64, u32, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
+    L.oracle_check_overlap.restype = i32
+    L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
+    L.oracle_overlap_extend.restype = i32
+    return L
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build(force=True)
+        _lib = load(LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class OracleError(ValueError):
+    pass
+
+
+@dataclass
+class CheckResult:
+    status: np.ndarray      # uint8 per event: post | pre << 2 | stuck << 7
+    final: np.ndarray       # uint8 per id
+    violations: np.ndarray  # uint32 ascending event indices of stuck events
+    first: int              # first stuck index, n if none
+    n_induced: int = 0
+    n_induced_stuck: int = 0
+
+
+def check(events: np.ndarray, n_ids: int, init: np.ndarray | None = None) -> CheckResult:
+    """Plain check: rules Effect / Remote Effect from the initial store."""
+    ev = np.ascontiguousarray(events, dtype=np.uint32)
+    n = ev.size
+    ini = None if init is None else np.ascontiguousarray(init, dtype=np.uint8)
+    st = np.empty(n, dtype=np.uint8)
+    fin = np.empty(max(n_ids, 1), dtype=np.uint8)
+    viol = np.empty(max(n, 1), dtype=np.uint32)
+    nv, first, bad = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    rc = lib().oracle_check(_p(ev), n, n_ids, _p(ini), _p(st), _p(fin), _p(viol), viol.size,
+                            C.byref(nv), C.byref(first), C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed event at index {bad.value}")
+    if rc != 0:
+        raise OracleError(f"oracle_check failed: {rc}")
+    return CheckResult(st, fin[:n_ids], viol[:nv.value].copy(), first.value)
+
+
+def check_count(events: np.ndarray, n_ids: int) -> int:
+    ev = np.ascontiguousarray(events, dtype=np.uint32)
+    return int(lib().oracle_check_count(_p(ev), ev.size, n_ids, None))
+
+
+def translate(comp_off: np.ndarray, decls: np.ndarray, n_vars: int, body_off: np.ndarray | None = None,
+              body: np.ndarray | None = None) -> np.ndarray:
+    """Translated core trace of a component program (ids: real v, abstract n_vars + v)."""
+    co = np.ascontiguousarray(comp_off, dtype=np.uint64)
+    de = np.ascontiguousarray(decls, dtype=np.uint32)
+    bo = None if body_off is None else np.ascontiguousarray(body_off, dtype=np.uint64)
+    bd = None if body is None else np.ascontiguousarray(body, dtype=np.uint32)
+    n_comp = co.size - 1
+    nout, bad = C.c_uint64(), C.c_uint64()
+    cap = int(de.size) * 5 + (0 if bd is None else int(bd.size))
+    out = np.empty(max(cap, 1), dtype=np.uint32)
+    rc = lib().oracle_translate(_p(co), n_comp, _p(de), n_vars, _p(bo), _p(bd), _p(out), out.size,
+                                C.byref(nout), C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed declaration/body at index {bad.value}")
+    if rc != 0:
+        raise OracleError(f"oracle_translate failed: {rc}")
+    return out[:nout.value].copy()
+
+
+def overlap_sets(lo: np.ndarray, hi: np.ndarray):
+    """CSR (off, nbr) of the overlap sets O(x) by the O(n^2) pair test."""
+    lo = np.ascontiguousarray(lo, dtype=np.uint32)
+    hi = np.ascontiguousarray(hi, dtype=np.uint32)
+    n = lo.size
+    off = np.empty(n + 1, dtype=np.uint64)
+    k = int(lib().oracle_overlap_sets(_p(lo), _p(hi), n, None, None, 0))
+    nbr = np.empty(max(k, 1), dtype=np.uint32)
+    lib().oracle_overlap_sets(_p(lo), _p(hi), n, _p(off), _p(nbr), nbr.size)
+    return off, nbr[:k]
+
+
+def check_overlap(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, init: np.ndarray | None = None,
+                  sets=None) -> CheckResult:
+    """Check over arrays with the overlap rule for writes (induced RW on each
+    overlapping array after the write)."""
+    ev = np.ascontiguousarray(events, dtype=np.uint32)
+    n_arrays = int(np.asarray(lo).size)
+    off, nbr = overlap_sets(lo, hi) if sets is None else sets
+    off = np.ascontiguousarray(off, dtype=np.uint64)
+    nbr = np.ascontiguousarray(nbr if nbr.size else np.zeros(1, np.uint32), dtype=np.uint32)
+    ini = None if init is None else np.ascontiguousarray(init, dtype=np.uint8)
+    n = ev.size
+    st = np.empty(n, dtype=np.uint8)
+    fin = np.empty(max(n_arrays, 1), dtype=np.uint8)
+    viol = np.empty(max(n, 1), dtype=np.uint32)
+    nv, first, ni, nis, bad = (C.c_uint64() for _ in range(5))
+    rc = lib().oracle_check_overlap(_p(ev), n, n_arrays, _p(off), _p(nbr), _p(ini), _p(st), _p(fin), _p(viol),
+                                    viol.size, C.byref(nv), C.byref(first), C.byref(ni), C.byref(nis),
+                                    C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed event at index {bad.value}")
+    if rc != 0:
+        raise OracleError(f"oracle_check_overlap failed: {rc}")
+    return CheckResult(st, fin[:n_arrays], viol[:nv.value].copy(), first.value, ni.value, nis.value)
+
+
+def overlap_extend(m: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """O(M): the declaration set M extended for overlapping arrays."""
+    m = np.ascontiguousarray(m, dtype=np.uint32)
+    lo = np.ascontiguousarray(lo, dtype=np.uint32)
+    hi = np.ascontiguousarray(hi, dtype=np.uint32)
+    cap = m.size + 2 * lo.size
+    out = np.empty(max(cap, 1), dtype=np.uint32)
+    k = lib().oracle_overlap_extend(_p(m), m.size, _p(lo), _p(hi), lo.size, _p(out), out.size)
+    if k < 0:
+        raise OracleError("overlap_extend capacity")
+    return out[:k].copy()
+
+
+# status byte fields
+def post(st):
+    return np.asarray(st) & 3
+
+
+def pre(st):
+    return (np.asarray(st) >> 2) & 3
+
+
+def stuck(st):
+    return (np.asarray(st) >> 7) & 1

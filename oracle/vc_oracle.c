@@ -1,0 +1,463 @@
+/*
+ * vc_oracle.c -- reference interpreter of the validity-status effect system.
+ *
+ * TEST INFRASTRUCTURE.  This file is the oracle that the GPU library is checked
+ * against.  Only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it; the library never does, and it shares no code, header,
+ * table or helper with the library.  It is deliberately plain: sequential loops,
+ * a literal pattern unifier over the printed effect signatures, an If-interpreter
+ * for the translation of access modes, and an O(n^2) pair test for overlaps.
+ *
+ * Paper: Henrio, Kessler, Li, "Leveraging Access Mode Declarations in a Model for
+ * Memory Consistency in Heterogeneous Systems" (arXiv 1910.11110).
+ *
+ * Encodings shared with the callers (wire formats, not arithmetic):
+ *   event word : bits 0-23 variable id, bits 24-26 op (0 r, 1 w, 2 Push, 3 Pull,
+ *                4 Noop), bit 27 side (0 = local/CPU, 1 = remote/GPU), bits 28-31 0.
+ *   decl word  : bits 0-23 variable, bits 24-25 mode (0 R, 1 W, 2 RW), bit 27 side.
+ *   status code: bit 0 = CPU copy valid, bit 1 = GPU copy valid, i.e.
+ *                (I,I)=0, (V,I)=1, (I,V)=2, (V,V)=3 with the pair written
+ *                (CPU, GPU) -- the CPU is the "local" memory.
+ *   status byte: post | pre << 2 | stuck << 7.
+ *
+ * Readings of the paper that the oracle fixes (each is discussed in the design
+ * notes of the repository):
+ *   - a stuck step (no unification) is flagged, leaves the store unchanged and the
+ *     trace continues ("flag and skip"); the first flagged index is the paper's
+ *     stuck configuration.
+ *   - a GPU event "E x" is the remote statement rem(E x).
+ *   - translation emits fixed arity: the not-taken branch of an R/RW guard is two
+ *     Noop events (on x and on its abstract variable); transfers in the taken branch
+ *     are local (CPU-side) Push/Pull as printed; W/RW add w on the abstract variable.
+ *   - overlap on core events: a write w_s x is followed, for every array y that
+ *     overlaps x, by the induced declaration RW_s y (acquire y on side s if it is not
+ *     valid there, then write y on side s).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------------
+ * Effects and their signatures (Section "An effect system for consistency between
+ * memory locations"): each effect is a pattern over (local, remote) pairs.
+ * A pattern term is V, I or a universally quantified variable X or Y.
+ * ------------------------------------------------------------------------------ */
+enum term { TI = 0, TV = 1, TX = 2, TY = 3 };
+
+struct pair { enum term loc, rem; };
+struct signature { struct pair in, out; };
+
+enum op { OP_R = 0, OP_W = 1, OP_PUSH = 2, OP_PULL = 3, OP_NOOP = 4 };
+
+static const struct signature SIG[5] = {
+    /* r    : (V,X) -> (V,X) */ { { TV, TX }, { TV, TX } },
+    /* w    : (X,Y) -> (V,I) */ { { TX, TY }, { TV, TI } },
+    /* Push : (V,X) -> (V,V) */ { { TV, TX }, { TV, TV } },
+    /* Pull : (X,V) -> (V,V) */ { { TX, TV }, { TV, TV } },
+    /* Noop : (X,Y) -> (X,Y) */ { { TX, TY }, { TX, TY } },
+};
+
+/* Bind one concrete value (TV or TI) against one pattern term. */
+static int unify_term(enum term concrete, enum term pattern, int bind[4])
+{
+    if (pattern == TV || pattern == TI)
+        return concrete == pattern;
+    if (bind[pattern] < 0) {
+        bind[pattern] = (int)concrete;
+        return 1;
+    }
+    return bind[pattern] == (int)concrete;
+}
+
+/* Unification of a status with an effect's input pattern (the paper's definition of
+ * applying a signature).  Returns 1 and the bindings on success. */
+static int unify(struct pair status, struct pair pattern, int bind[4])
+{
+    bind[TX] = bind[TY] = -1;
+    return unify_term(status.loc, pattern.loc, bind) && unify_term(status.rem, pattern.rem, bind);
+}
+
+static enum term instantiate_term(enum term t, const int bind[4])
+{
+    return (t == TV || t == TI) ? t : (enum term)bind[t];
+}
+
+static struct pair instantiate(struct pair p, const int bind[4])
+{
+    struct pair r = { instantiate_term(p.loc, bind), instantiate_term(p.rem, bind) };
+    return r;
+}
+
+static struct pair swap(struct pair p)
+{
+    struct pair r = { p.rem, p.loc };
+    return r;
+}
+
+/* status code <-> (CPU, GPU) pair; the CPU is the local memory */
+static struct pair from_code(int code)
+{
+    struct pair p = { (code & 1) ? TV : TI, (code & 2) ? TV : TI };
+    return p;
+}
+
+static int to_code(struct pair p)
+{
+    return (p.loc == TV ? 1 : 0) | (p.rem == TV ? 2 : 0);
+}
+
+/* One step of rule Effect (side 0) or rule Remote Effect (side 1) on status code
+ * `pre`.  Remote Effect applies the signature to the swapped pair and swaps the
+ * result back.  Returns the new status; *stuck is set when no unification exists
+ * (Property "Progress"), in which case the status is left unchanged. */
+static int apply_effect(int op, int side, int pre, int *stuck)
+{
+    struct pair s = from_code(pre);
+    int bind[4];
+    if (side)
+        s = swap(s);
+    if (!unify(s, SIG[op].in, bind)) {
+        *stuck = 1;
+        return pre;
+    }
+    *stuck = 0;
+    struct pair r = instantiate(SIG[op].out, bind);
+    if (side)
+        r = swap(r);
+    return to_code(r);
+}
+
+/* Rules valid / invalid / rem-valid / rem-invalid */
+static int is_valid(int code) { return from_code(code).loc == TV; }
+static int rem_is_valid(int code) { return from_code(code).rem == TV; }
+
+/* Induced RW_s y (overlap rule for a write on an overlapping array, applied to one
+ * array-granular status): (If valid-on-s y then Noop else transfer y); w_s y, where
+ * the transfer is the local Pull (s = CPU) or the local Push (s = GPU), exactly as
+ * in the translation of RW / rem(RW).  *stuck reports a stuck transfer. */
+static int apply_induced_rw(int side, int pre, int *stuck)
+{
+    int st = 0, cur = pre;
+    int cond = side ? rem_is_valid(cur) : is_valid(cur);
+    if (!cond)
+        cur = apply_effect(side ? OP_PUSH : OP_PULL, 0, cur, &st);
+    int st2 = 0;
+    cur = apply_effect(OP_W, side, cur, &st2);
+    *stuck = st || st2;
+    return cur;
+}
+
+/* ------------------------------------------------------------------------------
+ * Plain check of a trace.
+ * Returns 0 on success, -1 on a malformed event (index in *bad), -5 if the
+ * violation buffer is too small (all counts still valid).
+ * ------------------------------------------------------------------------------ */
+int oracle_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
+                 uint8_t *status_out, uint8_t *final_out, uint32_t *viol_out, uint64_t viol_cap,
+                 uint64_t *n_viol, uint64_t *first_viol, uint64_t *bad)
+{
+    uint8_t *sigma = (uint8_t *)malloc(n_ids ? n_ids : 1);
+    if (!sigma)
+        return -2;
+    for (uint32_t v = 0; v < n_ids; v++)
+        sigma[v] = init ? init[v] : 1; /* initial store: every variable at (V,I) */
+    uint64_t nv = 0, first = n;
+    int rc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t e = events[i];
+        uint32_t v = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+        if ((e >> 28) != 0 || op > 4 || v >= n_ids) {
+            if (bad)
+                *bad = i;
+            free(sigma);
+            return -1;
+        }
+        int pre = sigma[v], stuck = 0;
+        int post = apply_effect((int)op, (int)side, pre, &stuck);
+        sigma[v] = (uint8_t)post;
+        if (status_out)
+            status_out[i] = (uint8_t)(post | (pre << 2) | (stuck << 7));
+        if (stuck) {
+            if (nv < viol_cap && viol_out)
+                viol_out[nv] = (uint32_t)i;
+            else if (viol_out)
+                rc = -5;
+            if (first == n)
+                first = i;
+            nv++;
+        }
+    }
+    if (final_out)
+        memcpy(final_out, sigma, n_ids);
+    if (n_viol)
+        *n_viol = nv;
+    if (first_viol)
+        *first_viol = first;
+    free(sigma);
+    return rc;
+}
+
+/* Status after each event only (no flags, no violations): used for timing the
+ * oracle on a bounded sample and for long brute-force sweeps. */
+uint64_t oracle_check_count(const uint32_t *events, uint64_t n, uint32_t n_ids, uint8_t *final_out)
+{
+    uint64_t nv = 0;
+    oracle_check(events, n, n_ids, NULL, NULL, final_out, NULL, 0, &nv, NULL, NULL);
+    return nv;
+}
+
+/* ------------------------------------------------------------------------------
+ * Translation of access-mode declarations (Figure "Semantics of access modes and
+ * programs"):  [[M1{S1}; M2{S2}; ...]] = [[M1]]; S1; [[M2]]; S2; ...
+ *   [[R x#]]       = If isValid x# then Noop else (Pull x; Pull x#)
+ *   [[rem(R x#)]]  = If remIsValid x# then Noop else (Push x; Push x#)
+ *   [[RW x#]]      = [[R x#]]; w x#          [[rem(RW x#)]] = [[rem(R x#)]]; rem(w x#)
+ *   [[W x#]]       = w x#                    [[rem(W x#)]]  = rem(w x#)
+ * Real variable v has id v, its abstract variable has id n_vars + v; both start at
+ * (V,I).  The If is evaluated on the live store (rules IF-True / IF-False) while the
+ * trace is produced.  A conjunction of declarations is translated in declaration
+ * order.  The not-taken branch emits Noop on x and on x# (fixed arity).
+ * Bodies: body_off == NULL gives the canonical body of each declaration in order
+ * (R: r x, W: w x, RW: r x; w x, on the component's side); otherwise component c's
+ * body is body[body_off[c] .. body_off[c+1]) verbatim (ids < n_vars).
+ * Returns 0, -1 on a malformed input (index in *bad), -5 if out_cap is too small
+ * (then *n_out is the required size and nothing beyond out_cap is written).
+ * ------------------------------------------------------------------------------ */
+static uint32_t mk_event(uint32_t id, int op, int side)
+{
+    return id | ((uint32_t)op << 24) | ((uint32_t)side << 27);
+}
+
+struct emitter {
+    uint32_t *out;
+    uint64_t cap, n;
+    uint8_t *sigma;
+};
+
+static void emit(struct emitter *em, uint32_t id, int op, int side)
+{
+    int stuck;
+    em->sigma[id] = (uint8_t)apply_effect(op, side, em->sigma[id], &stuck);
+    if (em->n < em->cap)
+        em->out[em->n] = mk_event(id, op, side);
+    em->n++;
+}
+
+int oracle_translate(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
+                     const uint64_t *body_off, const uint32_t *body, uint32_t *out, uint64_t out_cap,
+                     uint64_t *n_out, uint64_t *bad)
+{
+    if ((uint64_t)n_vars * 2 > (1u << 24))
+        return -1;
+    struct emitter em = { out, out_cap, 0, (uint8_t *)malloc((size_t)n_vars * 2 + 1) };
+    if (!em.sigma)
+        return -2;
+    for (uint64_t v = 0; v < (uint64_t)n_vars * 2; v++)
+        em.sigma[v] = 1; /* real and abstract variables start at (V,I) */
+    for (uint64_t c = 0; c < n_comp; c++) {
+        uint64_t a = comp_off[c], b = comp_off[c + 1];
+        if (b < a) {
+            if (bad) *bad = c;
+            free(em.sigma);
+            return -1;
+        }
+        for (uint64_t d = a; d < b; d++) {
+            uint32_t w = decls[d];
+            uint32_t v = w & 0xFFFFFFu, mode = (w >> 24) & 3u, side = (w >> 27) & 1u;
+            if (v >= n_vars || mode > 2 || (w & 0xF4000000u) != 0) {
+                if (bad) *bad = d;
+                free(em.sigma);
+                return -1;
+            }
+            uint32_t abs_v = n_vars + v;
+            if (mode == 0 || mode == 2) { /* R or RW: guarded transfer */
+                int cond = side ? rem_is_valid(em.sigma[abs_v]) : is_valid(em.sigma[abs_v]);
+                if (cond) {
+                    emit(&em, v, OP_NOOP, (int)side);
+                    emit(&em, abs_v, OP_NOOP, (int)side);
+                } else {
+                    int t = side ? OP_PUSH : OP_PULL;
+                    emit(&em, v, t, 0);
+                    emit(&em, abs_v, t, 0);
+                }
+            }
+            if (mode == 1 || mode == 2) /* W or RW: record the write on x# */
+                emit(&em, abs_v, OP_W, (int)side);
+        }
+        if (!body_off) {
+            for (uint64_t d = a; d < b; d++) {
+                uint32_t w = decls[d];
+                uint32_t v = w & 0xFFFFFFu, mode = (w >> 24) & 3u, side = (w >> 27) & 1u;
+                if (mode == 0 || mode == 2)
+                    emit(&em, v, OP_R, (int)side);
+                if (mode == 1 || mode == 2)
+                    emit(&em, v, OP_W, (int)side);
+            }
+        } else {
+            for (uint64_t j = body_off[c]; j < body_off[c + 1]; j++) {
+                uint32_t e = body[j];
+                uint32_t v = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+                if ((e >> 28) != 0 || op > 4 || v >= n_vars) {
+                    if (bad) *bad = j;
+                    free(em.sigma);
+                    return -1;
+                }
+                emit(&em, v, (int)op, (int)side);
+            }
+        }
+    }
+    *n_out = em.n;
+    free(em.sigma);
+    return em.n > out_cap ? -5 : 0;
+}
+
+/* ------------------------------------------------------------------------------
+ * Overlapping arrays (Section "Overlapping arrays").
+ * Arrays are half-open intervals [lo, hi); x and y overlap iff x != y and
+ * lo_x < hi_y and lo_y < hi_x.  Overlap sets by the O(n^2) pair test, as CSR with
+ * neighbours in ascending id order.
+ * ------------------------------------------------------------------------------ */
+static int overlaps(const uint32_t *lo, const uint32_t *hi, uint32_t x, uint32_t y)
+{
+    return x != y && lo[x] < hi[y] && lo[y] < hi[x];
+}
+
+/* off has n+1 entries; nbr capacity nbr_cap; returns total neighbour count. */
+uint64_t oracle_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, uint64_t *off, uint32_t *nbr,
+                             uint64_t nbr_cap)
+{
+    uint64_t k = 0;
+    for (uint32_t x = 0; x < n; x++) {
+        if (off)
+            off[x] = k;
+        for (uint32_t y = 0; y < n; y++) {
+            if (overlaps(lo, hi, x, y)) {
+                if (nbr && k < nbr_cap)
+                    nbr[k] = y;
+                k++;
+            }
+        }
+    }
+    if (off)
+        off[n] = k;
+    return k;
+}
+
+/* Check of a trace over arrays with the overlap rule applied on core events.
+ * Each event is evaluated by the plain rule; after a write w_s x, every y in O(x)
+ * receives the induced RW_s y.  Outputs are per event of the trace (primary
+ * events); *n_induced_stuck counts stuck induced transfers (only possible from an
+ * initial (I,I)).  off/nbr: overlap sets as produced by oracle_overlap_sets. */
+int oracle_check_overlap(const uint32_t *events, uint64_t n, uint32_t n_arrays, const uint64_t *off,
+                         const uint32_t *nbr, const uint8_t *init, uint8_t *status_out, uint8_t *final_out,
+                         uint32_t *viol_out, uint64_t viol_cap, uint64_t *n_viol, uint64_t *first_viol,
+                         uint64_t *n_induced, uint64_t *n_induced_stuck, uint64_t *bad)
+{
+    uint8_t *sigma = (uint8_t *)malloc(n_arrays ? n_arrays : 1);
+    if (!sigma)
+        return -2;
+    for (uint32_t v = 0; v < n_arrays; v++)
+        sigma[v] = init ? init[v] : 1;
+    uint64_t nv = 0, first = n, ni = 0, nis = 0;
+    int rc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t e = events[i];
+        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+        if ((e >> 28) != 0 || op > 4 || x >= n_arrays) {
+            if (bad) *bad = i;
+            free(sigma);
+            return -1;
+        }
+        int pre = sigma[x], stuck = 0;
+        int post = apply_effect((int)op, (int)side, pre, &stuck);
+        sigma[x] = (uint8_t)post;
+        if (status_out)
+            status_out[i] = (uint8_t)(post | (pre << 2) | (stuck << 7));
+        if (stuck) {
+            if (viol_out && nv < viol_cap)
+                viol_out[nv] = (uint32_t)i;
+            else if (viol_out)
+                rc = -5;
+            if (first == n)
+                first = i;
+            nv++;
+        }
+        if (op == OP_W) {
+            for (uint64_t j = off[x]; j < off[x + 1]; j++) {
+                uint32_t y = nbr[j];
+                int st = 0;
+                sigma[y] = (uint8_t)apply_induced_rw((int)side, sigma[y], &st);
+                ni++;
+                nis += (uint64_t)st;
+            }
+        }
+    }
+    if (final_out)
+        memcpy(final_out, sigma, n_arrays);
+    if (n_viol) *n_viol = nv;
+    if (first_viol) *first_viol = first;
+    if (n_induced) *n_induced = ni;
+    if (n_induced_stuck) *n_induced_stuck = nis;
+    free(sigma);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------
+ * Extension of a declaration set for overlapping arrays (Table "Extension of access
+ * mode annotations to deal with overlapping arrays"), the smallest set closed under:
+ *   E x# in M                               =>  E x# in O(M)
+ *   W x# in M, W y# not in M, x, y overlap  =>  RW y# in O(M)
+ *   RW x# in M, x, y overlap                =>  RW y# in O(M)
+ * and the same three rules for remote declarations.  Premises quantify over M, so
+ * the closure is one step.  An inferred RW on a y that M already declares on the
+ * same side replaces that entry (upgrade in place); otherwise it is appended, in
+ * ascending order of y, after the entries of M.
+ * Input/outputs are decl words (array id, mode, side).  Returns the size of O(M),
+ * or -1 if the output capacity is too small.
+ * ------------------------------------------------------------------------------ */
+static int find_decl(const uint32_t *set, int n, uint32_t y, uint32_t side)
+{
+    for (int i = 0; i < n; i++)
+        if ((set[i] & 0xFFFFFFu) == y && ((set[i] >> 27) & 1u) == side)
+            return i;
+    return -1;
+}
+
+int oracle_overlap_extend(const uint32_t *m, int n_m, const uint32_t *lo, const uint32_t *hi, uint32_t n_arrays,
+                          uint32_t *out, int out_cap)
+{
+    int n = 0;
+    if (n_m > out_cap)
+        return -1;
+    for (int i = 0; i < n_m; i++)
+        out[n++] = m[i];
+    for (uint32_t side = 0; side < 2; side++) {
+        for (uint32_t y = 0; y < n_arrays; y++) {
+            int need_rw = 0;
+            for (int i = 0; i < n_m; i++) {
+                uint32_t x = m[i] & 0xFFFFFFu, mode = (m[i] >> 24) & 3u, s = (m[i] >> 27) & 1u;
+                if (s != side || !overlaps(lo, hi, x, y))
+                    continue;
+                if (mode == 2) /* RW x# */
+                    need_rw = 1;
+                if (mode == 1) { /* W x#, and W y# not in M */
+                    int j = find_decl(m, n_m, y, side);
+                    if (!(j >= 0 && ((m[j] >> 24) & 3u) == 1))
+                        need_rw = 1;
+                }
+            }
+            if (!need_rw)
+                continue;
+            uint32_t rw = y | (2u << 24) | (side << 27);
+            int j = find_decl(out, n, y, side);
+            if (j >= 0) {
+                out[j] = rw;
+            } else {
+                if (n >= out_cap)
+                    return -1;
+                out[n++] = rw;
+            }
+        }
+    }
+    return n;
+}

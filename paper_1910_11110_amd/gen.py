@@ -1,0 +1,261 @@
+"""Seeded synthetic inputs for the validity-status checker.
+
+This module draws the *inputs* of the workloads (event traces, access-mode
+declarations, array intervals, trace shapes, arrival times).  It contains none of
+the checked method's arithmetic: no status, no effect, no transfer decision.  Both
+the CPU oracle and the HIP path consume what it produces, and neither imports the
+other.
+
+Random numbers come from a counter-based SplitMix64 (G. Steele, D. Lea, C. Flood,
+"Fast splittable pseudorandom number generators", OOPSLA 2014).  Draw ``i`` of
+stream ``(seed, stream)`` is ``mix64(base + (i + 1) * GAMMA)`` where
+``base = mix64(mix64(seed) ^ (stream * GAMMA))``.  Every field of every workload
+uses its own stream, so any slice of a workload can be regenerated without the
+rest.
+
+Wire formats produced here (they are the library's input formats):
+
+* event   : bits 0-23 variable id, bits 24-26 op (0 r, 1 w, 2 Push, 3 Pull,
+            4 Noop), bit 27 side (0 = CPU / local, 1 = GPU / remote), bits 28-31 zero.
+* decl    : bits 0-23 variable, bits 24-25 mode (0 R, 1 W, 2 RW), bit 27 side.
+* comp_off: uint64 CSR offsets of each component's declarations.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+# stream identifiers (one per drawn field)
+S_VAR, S_OP, S_SIDE = 1, 2, 3
+S_K, S_ZIPF, S_MODE, S_CSIDE = 10, 11, 12, 13
+S_LEN, S_LO, S_ARR = 20, 21, 22
+S_TLEN, S_TVARS, S_TARR, S_TSEED = 30, 31, 32, 33
+S_ARRIVE = 40
+
+OP_R, OP_W, OP_PUSH, OP_PULL, OP_NOOP = 0, 1, 2, 3, 4
+MODE_R, MODE_W, MODE_RW = 0, 1, 2
+CPU, GPU = 0, 1
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def _stream_base(seed: int, stream: int) -> np.uint64:
+    with np.errstate(over="ignore"):
+        s = _mix64(np.array([seed & 0xFFFFFFFFFFFFFFFF], dtype=np.uint64))
+        t = np.array([stream & 0xFFFFFFFFFFFFFFFF], dtype=np.uint64) * GAMMA
+        return _mix64(s ^ t)[0]
+
+
+def draws(seed: int, stream: int, start: int, count: int) -> np.ndarray:
+    """``count`` 64-bit draws of stream (seed, stream), starting at draw ``start``."""
+    base = _stream_base(seed, stream)
+    idx = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix64(base + idx * GAMMA)
+
+
+def draws_at(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
+    """Draws of stream (seed, stream) at the given counter indices."""
+    base = _stream_base(seed, stream)
+    with np.errstate(over="ignore"):
+        return _mix64(base + (np.asarray(idx, dtype=np.uint64) + np.uint64(1)) * GAMMA)
+
+
+def below(u: np.ndarray, n: int) -> np.ndarray:
+    """Map 64-bit draws to integers in [0, n) by multiply-shift of the top 32 bits."""
+    assert 0 < n <= (1 << 32)
+    hi = (u >> np.uint64(32)).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        return ((hi * np.uint64(n)) >> np.uint64(32)).astype(np.int64)
+
+
+def unit(u: np.ndarray) -> np.ndarray:
+    """Map 64-bit draws to floats in [0, 1) with 53 random bits."""
+    return (u >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def pack_events(var, op, side) -> np.ndarray:
+    var = np.asarray(var, dtype=np.uint32)
+    op = np.asarray(op, dtype=np.uint32)
+    side = np.asarray(side, dtype=np.uint32)
+    return (var | (op << np.uint32(24)) | (side << np.uint32(27))).astype(np.uint32)
+
+
+def pack_decls(var, mode, side) -> np.ndarray:
+    var = np.asarray(var, dtype=np.uint32)
+    mode = np.asarray(mode, dtype=np.uint32)
+    side = np.asarray(side, dtype=np.uint32)
+    return (var | (mode << np.uint32(24)) | (side << np.uint32(27))).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------------------
+# plain traces: uniform variable, uniform op over the five effects, fair side
+# --------------------------------------------------------------------------------------
+def plain_events(n: int, n_ids: int, seed: int, start: int = 0, chunk: int = 1 << 24) -> np.ndarray:
+    """Events ``start .. start+n`` of the plain-trace law (variable uniform in
+    [0, n_ids), op uniform over r/w/Push/Pull/Noop, side CPU/GPU with p = 0.5)."""
+    out = np.empty(n, dtype=np.uint32)
+    for a in range(0, n, chunk):
+        m = min(chunk, n - a)
+        var = below(draws(seed, S_VAR, start + a, m), n_ids)
+        op = below(draws(seed, S_OP, start + a, m), 5)
+        side = draws(seed, S_SIDE, start + a, m) >> np.uint64(63)
+        out[a:a + m] = pack_events(var, op, side)
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# component traces: declarations of VectorPU-style components
+# --------------------------------------------------------------------------------------
+_zipf_cache: dict = {}
+
+
+def zipf_cdf(n_vars: int, s: float) -> np.ndarray:
+    """Cumulative distribution of P(k) proportional to (k+1)^-s over k in [0, n_vars)."""
+    key = (n_vars, s)
+    if key not in _zipf_cache:
+        w = np.power(np.arange(1, n_vars + 1, dtype=np.float64), -s)
+        c = np.cumsum(w)
+        c /= c[-1]
+        c[-1] = 1.0
+        _zipf_cache[key] = c
+    return _zipf_cache[key]
+
+
+@dataclass
+class ComponentTrace:
+    n_vars: int
+    comp_off: np.ndarray  # uint64, n_comp + 1
+    decls: np.ndarray     # uint32
+
+    @property
+    def n_comp(self) -> int:
+        return len(self.comp_off) - 1
+
+
+def component_trace(n_comp: int, n_vars: int, seed: int, kmax: int = 8, zipf_s: float = 1.1,
+                     p_modes=(0.5, 0.3, 0.2)) -> ComponentTrace:
+    """``n_comp`` components; each declares k ~ U{1..kmax} distinct variables drawn by
+    Zipf(zipf_s) over [0, n_vars) (a repeated draw is redrawn until distinct); each
+    declaration gets mode R/W/RW with probabilities ``p_modes``; each component is
+    placed on CPU or GPU with p = 0.5."""
+    assert kmax <= n_vars
+    cdf = zipf_cdf(n_vars, zipf_s)
+    k = below(draws(seed, S_K, 0, n_comp), kmax) + 1
+    ids = np.empty((n_comp, kmax), dtype=np.int64)
+    col_u = unit(draws(seed, S_ZIPF, 0, n_comp * kmax)).reshape(n_comp, kmax)
+    ids[:] = np.minimum(np.searchsorted(cdf, col_u, side="right"), n_vars - 1)
+    del col_u
+    attempt = 1
+    for j in range(1, kmax):
+        live = k > j
+        while True:
+            dup = np.zeros(n_comp, dtype=bool)
+            for i in range(j):
+                dup |= ids[:, j] == ids[:, i]
+            dup &= live
+            rows = np.nonzero(dup)[0]
+            if rows.size == 0:
+                break
+            # redraws come from a per-attempt stream, indexed by (row, column)
+            u = unit(draws_at(seed, S_ZIPF + 1000 * attempt, rows.astype(np.uint64) * np.uint64(kmax) + np.uint64(j)))
+            ids[rows, j] = np.minimum(np.searchsorted(cdf, u, side="right"), n_vars - 1)
+            attempt += 1
+    mask = np.arange(kmax)[None, :] < k[:, None]
+    var = ids[mask]
+    n_decl = var.size
+    mu = unit(draws(seed, S_MODE, 0, n_decl))
+    mode = np.where(mu < p_modes[0], MODE_R, np.where(mu < p_modes[0] + p_modes[1], MODE_W, MODE_RW))
+    cside = (draws(seed, S_CSIDE, 0, n_comp) >> np.uint64(63)).astype(np.int64)
+    side = np.repeat(cside, k)
+    comp_off = np.zeros(n_comp + 1, dtype=np.uint64)
+    np.cumsum(k, out=comp_off[1:])
+    return ComponentTrace(n_vars, comp_off, pack_decls(var, mode, side))
+
+
+# --------------------------------------------------------------------------------------
+# overlapping arrays
+# --------------------------------------------------------------------------------------
+def intervals(n_arrays: int, seed: int, space: int = 1 << 24, max_len: int = 4096):
+    """Half-open intervals [lo, hi): length log-uniform integer in [1, max_len]
+    (floor of exp(u ln(max_len + 1))), then lo uniform in [0, space - len]."""
+    u = unit(draws(seed, S_LEN, 0, n_arrays))
+    ln = np.floor(np.exp(u * math.log(max_len + 1))).astype(np.int64)
+    ln = np.clip(ln, 1, max_len)
+    lo = np.empty(n_arrays, dtype=np.int64)
+    ulo = draws(seed, S_LO, 0, n_arrays)
+    # per-element bound space - len + 1
+    hi32 = (ulo >> np.uint64(32)).astype(np.uint64)
+    bound = (space - ln + 1).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        lo[:] = ((hi32 * bound) >> np.uint64(32)).astype(np.int64)
+    return lo.astype(np.uint32), (lo + ln).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------------------
+# batched / served trace shapes
+# --------------------------------------------------------------------------------------
+@dataclass
+class TraceShape:
+    length: int
+    n_vars: int
+    has_arrays: bool
+    seed: int
+
+
+def _log_uniform_int(u: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    v = np.floor(np.exp(math.log(lo) + u * (math.log(hi + 1) - math.log(lo)))).astype(np.int64)
+    return np.clip(v, lo, hi)
+
+
+def trace_shapes(n_traces: int, seed: int, len_range=(100, 1_000_000), vars_range=(8, 65536),
+                 p_arrays: float = 0.2, start: int = 0) -> list:
+    """Shapes of independent traces: length and variable count log-uniform integers in
+    the given ranges, a fraction ``p_arrays`` of traces carrying array intervals."""
+    lens = _log_uniform_int(unit(draws(seed, S_TLEN, start, n_traces)), *len_range)
+    nv = _log_uniform_int(unit(draws(seed, S_TVARS, start, n_traces)), *vars_range)
+    arr = unit(draws(seed, S_TARR, start, n_traces)) < p_arrays
+    tseed = draws(seed, S_TSEED, start, n_traces)
+    return [TraceShape(int(lens[i]), int(nv[i]), bool(arr[i]), int(tseed[i] & np.uint64(0x7FFFFFFFFFFFFFFF)))
+            for i in range(n_traces)]
+
+
+def trace_inputs(shape: TraceShape):
+    """Events (and intervals if the trace carries arrays) of one trace shape."""
+    ev = plain_events(shape.length, shape.n_vars, shape.seed)
+    if shape.has_arrays:
+        lo, hi = intervals(shape.n_vars, shape.seed)
+        return ev, lo, hi
+    return ev, None, None
+
+
+def poisson_arrivals(rate: float, duration: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of the given rate over [0, duration)."""
+    n_est = int(rate * duration * 1.5 + 64)
+    u = unit(draws(seed, S_ARRIVE, 0, n_est))
+    gaps = -np.log1p(-u) / rate
+    t = np.cumsum(gaps)
+    return t[t < duration]
+
+
+# --------------------------------------------------------------------------------------
+# workload presets (sizes of the workloads the checker is measured on)
+# --------------------------------------------------------------------------------------
+PLAIN_SMALL = dict(n=10_000, n_ids=64)              # single trace, 64 scalar variables
+PLAIN_LARGE = dict(n=1 << 28, n_ids=64)             # same law at 2^28 events (1 GiB)
+COMPONENTS = dict(n_comp=1 << 23, n_vars=1 << 20)   # VectorPU-style component trace
+OVERLAP = dict(n_arrays=1 << 16, n_events=1 << 24)  # overlapping arrays
+BATCH = dict(n_traces=4096)                         # batched traces
+SERVE = dict(rate=2000.0, duration=60.0, chunk=1 << 16, budget=64 << 30)

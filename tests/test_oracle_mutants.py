@@ -1,0 +1,75 @@
+"""The pins are strong enough: a plausible mistake planted in a copy of the oracle (on
+the CPU) makes at least one pin fail.  Each mutant is a one-line edit of the C source."""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+from oracle import oracle as O
+from tests import test_oracle_pins as T
+from tests.helpers import load_yaml
+
+MUTANTS = {
+    "push-output-keeps-remote": ("/* Push : (V,X) -> (V,V) */ { { TV, TX }, { TV, TV } }",
+                                 "/* Push : (V,X) -> (V,V) */ { { TV, TX }, { TV, TX } }"),
+    "pull-pattern-transposed": ("/* Pull : (X,V) -> (V,V) */ { { TX, TV }, { TV, TV } }",
+                                "/* Pull : (X,V) -> (V,V) */ { { TV, TX }, { TV, TV } }"),
+    "w-invalidates-local": ("/* w    : (X,Y) -> (V,I) */ { { TX, TY }, { TV, TI } }",
+                            "/* w    : (X,Y) -> (V,I) */ { { TX, TY }, { TI, TV } }"),
+    "remote-no-swap-back": ("    if (side)\n        r = swap(r);\n", "\n"),
+    "remote-no-swap": ("    if (side)\n        s = swap(s);\n", "\n"),
+    "stuck-not-flagged": ("        *stuck = 1;\n        return pre;", "        *stuck = 0;\n        return pre;"),
+    "initial-store-valid-both": ("sigma[v] = init ? init[v] : 1;", "sigma[v] = init ? init[v] : 3;"),
+    "translate-transfer-on-decl-side": ("emit(&em, v, t, 0);", "emit(&em, v, t, (int)side);"),
+    "translate-guard-on-real-var": ("int cond = side ? rem_is_valid(em.sigma[abs_v]) : is_valid(em.sigma[abs_v]);",
+                                    "int cond = side ? rem_is_valid(em.sigma[v]) : is_valid(em.sigma[v]);"),
+    "translate-guard-sides-swapped": ("int cond = side ? rem_is_valid(em.sigma[abs_v]) : is_valid(em.sigma[abs_v]);",
+                                      "int cond = side ? is_valid(em.sigma[abs_v]) : rem_is_valid(em.sigma[abs_v]);"),
+    "translate-no-abstract-write": ("emit(&em, abs_v, OP_W, (int)side);", "emit(&em, abs_v, OP_NOOP, (int)side);"),
+    "overlap-rule3-ignores-premise": ("if (!(j >= 0 && ((m[j] >> 24) & 3u) == 1))", "if (1)"),
+    "overlap-rw-not-inferred": ("if (mode == 2) /* RW x# */\n                    need_rw = 1;", "\n"),
+    "induced-rw-wrong-side": ("cur = apply_effect(OP_W, side, cur, &st2);", "cur = apply_effect(OP_W, !side, cur, &st2);"),
+    "overlap-inclusive-upper": ("return x != y && lo[x] < hi[y] && lo[y] < hi[x];",
+                                "return x != y && lo[x] <= hi[y] && lo[y] <= hi[x];"),
+}
+
+
+def _pins():
+    T.test_effect_table_matches_printed_signatures()
+    for ex in load_yaml("worked_examples.yaml"):
+        T.test_worked_examples(ex)
+    for ex in load_yaml("translation_examples.yaml"):
+        T.test_translation_examples(ex)
+    T.test_overlap_extension_pvector_example()
+    T.test_safety_no_unsafe_state_from_safe_start()
+    T.test_side_swap_symmetry()
+    T.test_theorems_on_well_declared_component_traces(0)
+    T.test_vectorpu_coherence_code_matches_abstract_status()
+    T.test_overlap_write_makes_overlapping_arrays_valid_on_side_only()
+    T.test_overlap_rules_keep_element_model_consistent_pvector()
+    T.test_overlap_sets_brute_force_small()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_fails_a_pin(name):
+    old, new = MUTANTS[name]
+    src = open(O.SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {name}"
+    src = src.replace(old, new, 1)
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "m.c")
+        so = os.path.join(d, "m.so")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-O1", "-std=c99", "-w", "-fPIC", "-shared", c, "-o", so])
+        saved = O._lib
+        O._lib = O.load(so)
+        try:
+            with pytest.raises((AssertionError, O.OracleError)):
+                _pins()
+        finally:
+            O._lib = saved
+
+
+def test_unmutated_oracle_passes_all_pins():
+    _pins()

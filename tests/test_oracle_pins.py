@@ -1,0 +1,402 @@
+"""Pins of the CPU oracle against what the paper fixes: the printed effect signatures,
+its worked examples, its properties and theorems, the VectorPU coherence code, and
+exhaustive small programs."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1910_11110_amd import gen
+from tests import pin_models as PM
+from tests.helpers import PAIRS, decl, effect_table, ev, load_yaml, parse_events
+
+
+# --------------------------------------------------------------------------- effect table
+def test_effect_table_matches_printed_signatures():
+    rows = effect_table()
+    assert len(rows) == 40
+    for op, side, pre, post, stuck in rows:
+        e = np.array([op << 24 | side << 27], dtype=np.uint32)
+        r = O.check(e, 1, init=np.array([pre], np.uint8))
+        assert O.post(r.status)[0] == post, (op, side, pre)
+        assert O.pre(r.status)[0] == pre
+        assert O.stuck(r.status)[0] == stuck, (op, side, pre)
+        assert r.final[0] == post
+
+
+# ------------------------------------------------------------------------ worked examples
+@pytest.mark.parametrize("ex", load_yaml("worked_examples.yaml"), ids=lambda e: e["name"])
+def test_worked_examples(ex):
+    ids = {v: i for i, v in enumerate(ex["vars"])}
+    init = np.ones(len(ids), np.uint8)  # initial store: every variable at (V,I)
+    for v, s in ex.get("init", {}).items():
+        init[ids[v]] = PAIRS[s]
+    events = parse_events(ex["events"], ids)
+    r = O.check(events, len(ids), init=init)
+    assert list(O.post(r.status)) == [PAIRS[s] for s in ex["post"]]
+    assert list(r.violations) == ex["stuck"]
+    assert r.first == (ex["stuck"][0] if ex["stuck"] else len(events))
+
+
+def _components(ex, ids):
+    n_vars = len(ex["vars"])
+    comp_off, decls, body_off, body = [0], [], [0], []
+    for c in ex["components"]:
+        for d in c["decls"]:
+            mode, side, var = d.split()
+            decls.append(decl(mode, side, ids[var]))
+        comp_off.append(len(decls))
+        for b in c["body"]:
+            op, side, var = b.split()
+            body.append(ev(op, side, ids[var]))
+        body_off.append(len(body))
+    return (np.array(comp_off, np.uint64), np.array(decls, np.uint32), n_vars, np.array(body_off, np.uint64),
+            np.array(body, np.uint32))
+
+
+@pytest.mark.parametrize("ex", load_yaml("translation_examples.yaml"), ids=lambda e: e["name"])
+def test_translation_examples(ex):
+    ids = {v: i for i, v in enumerate(ex["vars"])}
+    n_vars = len(ids)
+    all_ids = dict(ids)
+    all_ids.update({v + "#": n_vars + i for v, i in ids.items()})
+    co, de, nv, bo, bd = _components(ex, ids)
+    tr = O.translate(co, de, nv, bo, bd)
+    assert list(tr) == list(parse_events(ex["translated"], all_ids))
+    r = O.check(tr, 2 * n_vars)
+    assert list(O.post(r.status)) == [PAIRS[s] for s in ex["post"]]
+    assert list(r.violations) == ex["stuck"]
+    for v, s in ex["final"].items():
+        assert r.final[all_ids[v]] == PAIRS[s]
+
+
+def test_overlap_extension_pvector_example():
+    ex = load_yaml("overlap_example.yaml")
+    names = list(ex["arrays"])
+    ids = {n: i for i, n in enumerate(names)}
+    lo = np.array([ex["arrays"][n][0] for n in names], np.uint32)
+    hi = np.array([ex["arrays"][n][1] for n in names], np.uint32)
+    off, nbr = O.overlap_sets(lo, hi)
+    pairs = {(x, int(y)) for x in range(len(names)) for y in nbr[off[x]:off[x + 1]]}
+    expect = set()
+    for a, b in ex["overlapping_pairs"]:
+        expect |= {(ids[a], ids[b]), (ids[b], ids[a])}
+    assert pairs == expect
+    for call in ex["calls"]:
+        m = np.array([decl(*d.split()[:2], ids[d.split()[2]]) for d in call["decls"]], np.uint32)
+        got = O.overlap_extend(m, lo, hi)
+        want = [decl(*d.split()[:2], ids[d.split()[2]]) for d in call["extended"]]
+        assert list(got) == want, call["name"]
+
+
+# ------------------------------------------------------------------- identities/properties
+def _random_trace(n, n_ids, seed):
+    return gen.plain_events(n, n_ids, seed)
+
+
+def test_pull_is_remote_push():
+    """Pull is the same as rem Push (Section 3.2, after the rules)."""
+    e = _random_trace(20000, 16, 3)
+    op = (e >> 24) & 7
+    side = (e >> 27) & 1
+    swapped = e.copy()
+    is_pull = op == 3
+    swapped[is_pull] = (e[is_pull] & 0xFFFFFF) | (2 << 24) | ((1 - side[is_pull]) << 27)
+    a = O.check(e, 16)
+    b = O.check(swapped, 16)
+    assert np.array_equal(a.status, b.status) and np.array_equal(a.final, b.final)
+
+
+def test_safety_no_unsafe_state_from_safe_start():
+    """Property Safety: (I,I) is unreachable from a store without (I,I)."""
+    for seed in range(4):
+        e = _random_trace(50000, 32, seed)
+        init = (gen.below(gen.draws(seed, 99, 0, 32), 3) + 1).astype(np.uint8)
+        r = O.check(e, 32, init=init)
+        assert (O.post(r.status) != 0).all() and (O.pre(r.status) != 0).all()
+
+
+def test_unsafe_start_only_noop_and_w_proceed():
+    """From (I,I) only Noop (unchanged) and w (leaves (I,I)) are applicable (proof of Safety)."""
+    e = _random_trace(5000, 8, 7)
+    r = O.check(e, 8, init=np.zeros(8, np.uint8))
+    op = (e >> 24) & 7
+    pre = O.pre(r.status)
+    at0 = pre == 0
+    assert (O.stuck(r.status)[at0 & (op != 1) & (op != 4)] == 1).all()
+    assert (O.stuck(r.status)[at0 & ((op == 1) | (op == 4))] == 0).all()
+
+
+def test_side_swap_symmetry():
+    """Remote Effect is Effect on the swapped pair: flipping every side and swapping
+    every initial pair swaps every output pair and keeps every flag."""
+    e = _random_trace(30000, 16, 11)
+    init = (gen.below(gen.draws(11, 98, 0, 16), 4)).astype(np.uint8)
+    sw = np.array([0, 2, 1, 3], np.uint8)
+    a = O.check(e, 16, init=init)
+    b = O.check(e ^ np.uint32(1 << 27), 16, init=sw[init])
+    assert np.array_equal(sw[O.post(a.status)], O.post(b.status))
+    assert np.array_equal(sw[O.pre(a.status)], O.pre(b.status))
+    assert np.array_equal(O.stuck(a.status), O.stuck(b.status))
+
+
+def test_variables_are_independent():
+    """The store maps each variable separately: a variable's outputs do not depend on
+    events of other variables (relabelling + interleaving invariance)."""
+    e = _random_trace(20000, 8, 5)
+    full = O.check(e, 8)
+    for v in range(8):
+        sel = (e & 0xFFFFFF) == v
+        sub = (e[sel] & ~np.uint32(0xFFFFFF))  # relabel to id 0
+        r = O.check(sub, 1)
+        assert np.array_equal(r.status, full.status[sel])
+        assert r.final[0] == full.final[v]
+
+
+def test_flagged_prefix_equals_halting_semantics_exhaustive():
+    """Every program of length <= 4 over 2 variables: up to the first stuck statement the
+    oracle's outputs equal the literal small-step reduction, and the first flagged index
+    is exactly where the literal reduction gets stuck (Property Progress)."""
+    for length in range(1, 5):
+        progs = list(PM.all_programs(length))
+        words = []
+        for p, prog in enumerate(progs):
+            for (op, remote, v) in prog:
+                words.append((2 * p + v) | (PM.OPS.index(op) << 24) | (int(remote) << 27))
+        e = np.array(words, np.uint32)
+        r = O.check(e, 2 * len(progs))
+        post = O.post(r.status).reshape(len(progs), length)
+        flag = O.stuck(r.status).reshape(len(progs), length)
+        for p, prog in enumerate(progs):
+            posts, stuck_at = PM.halting_run(prog, {0: "VI", 1: "VI"})
+            k = len(posts)
+            assert [PM.str_of(c) for c in post[p, :k]] == posts
+            fl = np.nonzero(flag[p])[0]
+            assert (fl[0] if fl.size else None) == stuck_at
+
+
+def test_exhaustive_length5_invariants():
+    """All 20^5 programs of length 5 over 2 variables (each shorter program is a prefix):
+    Safety holds, and a flagged step leaves the status unchanged."""
+    alphabet = np.array([(op << 24) | (side << 27) | v for v in range(2) for op in range(5) for side in range(2)],
+                        np.uint32)
+    L = 5
+    idx = np.indices((20,) * L).reshape(L, -1).T  # (20^5, 5)
+    words = alphabet[idx]
+    prog = np.arange(idx.shape[0], dtype=np.uint32)[:, None]
+    words = (words & ~np.uint32(0xFFFFFF)) | ((words & 1) + 2 * prog)
+    e = words.reshape(-1).astype(np.uint32)
+    r = O.check(e, 2 * idx.shape[0])
+    assert (O.post(r.status) != 0).all()
+    fl = O.stuck(r.status) == 1
+    assert (O.post(r.status)[fl] == O.pre(r.status)[fl]).all()
+    # stationary sanity: about 3/10 of steps from (V,I)/(I,V) are stuck, none from (V,V)
+    pre = O.pre(r.status)
+    assert not fl[pre == 3].any()
+
+
+# ---------------------------------------------------------------- theorems on components
+def _boundary_checks(ct, tr, r):
+    """Replays the checked translated trace component by component: Theorem 1
+    (abstraction sigma(x#) <= sigma(x) at every component boundary) and coherence after
+    [[M]] (a variable declared R/RW is valid on the component's side before the body)."""
+    n_vars = ct.n_vars
+    decls = ct.decls
+    mode = (decls >> 24) & 3
+    arity_slot = np.where(mode == 0, 2, np.where(mode == 1, 1, 3))
+    arity_body = np.where(mode == 2, 2, 1)
+    sigma = np.ones(2 * n_vars, np.uint8)
+    pos = 0
+    post = O.post(r.status)
+    ids = tr & 0xFFFFFF
+    for c in range(ct.n_comp):
+        a, b = int(ct.comp_off[c]), int(ct.comp_off[c + 1])
+        ns = int(arity_slot[a:b].sum())
+        nb = int(arity_body[a:b].sum())
+        for k in range(pos, pos + ns):
+            sigma[ids[k]] = post[k]
+        for d in range(a, b):
+            v = int(decls[d] & 0xFFFFFF)
+            side = int((decls[d] >> 27) & 1)
+            if mode[d] in (0, 2):
+                assert sigma[v] & (1 << side), "declared variable not valid on its side after [[M]]"
+        for k in range(pos + ns, pos + ns + nb):
+            sigma[ids[k]] = post[k]
+        pos += ns + nb
+        real, absv = sigma[:n_vars], sigma[n_vars:]
+        ok = (absv == real) | ((real == 3) & ((absv == 1) | (absv == 2)))
+        assert ok.all(), f"abstraction broken after component {c}"
+    assert pos == tr.size
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_theorems_on_well_declared_component_traces(seed):
+    """Theorem 1 (subject reduction) and Theorem 2 (progress) on canonical well-declared
+    component programs."""
+    ct = gen.component_trace(3000, 64, seed)
+    tr = O.translate(ct.comp_off, ct.decls, ct.n_vars)
+    r = O.check(tr, 2 * ct.n_vars)
+    assert r.violations.size == 0 and r.first == tr.size
+    _boundary_checks(ct, tr, r)
+
+
+def test_translation_fixed_arity():
+    """Fixed-arity reading: R -> 2 slot + 1 body, W -> 1 + 1, RW -> 3 + 2 events."""
+    ct = gen.component_trace(2000, 256, 4)
+    tr = O.translate(ct.comp_off, ct.decls, ct.n_vars)
+    mode = (ct.decls >> 24) & 3
+    assert tr.size == int(np.where(mode == 0, 3, np.where(mode == 1, 2, 5)).sum())
+
+
+def test_ill_declared_body_is_caught():
+    """A component that writes x on the GPU under an R declaration is not well-declared;
+    a later CPU read of x through R x# finds x# valid and gets stuck (the check sees the
+    stale read that the declarations hid)."""
+    co = np.array([0, 1, 2], np.uint64)
+    de = np.array([decl("R", "GPU", 0), decl("R", "CPU", 0)], np.uint32)
+    bo = np.array([0, 1, 2], np.uint64)
+    bd = np.array([ev("w", "GPU", 0), ev("r", "CPU", 0)], np.uint32)
+    tr = O.translate(co, de, 1, bo, bd)
+    r = O.check(tr, 2)
+    assert r.violations.size == 1 and tr[r.first] == ev("r", "CPU", 0)
+
+
+# ----------------------------------------------------------------------- VectorPU flags
+def test_vectorpu_coherence_code_matches_abstract_status():
+    """The coherence-flag code of VectorPU computes the abstract status that the
+    translation records on x#, from every non-(I,I) starting pair (the flags start
+    from the same pair; VectorPU's own default is (true, true))."""
+    # prefix components that bring x# to (V,I), (I,V), (V,V) from the initial store
+    prefixes = {1: [], 2: [("W", "GPU", "w GPU")], 3: [("W", "CPU", "w CPU"), ("R", "GPU", "r GPU")]}
+    for start, prefix in prefixes.items():
+        for mode in ("R", "W", "RW"):
+            for side in ("CPU", "GPU"):
+                comps = [(m, s, [b]) for m, s, b in prefix]
+                body = {"R": [f"r {side}"], "W": [f"w {side}"], "RW": [f"r {side}", f"w {side}"]}[mode]
+                comps.append((mode, side, body))
+                co = np.arange(len(comps) + 1, dtype=np.uint64)
+                de = np.array([decl(m, s, 0) for m, s, _ in comps], np.uint32)
+                bodies = [b for _, _, bb in comps for b in bb]
+                bo = np.cumsum([0] + [len(bb) for _, _, bb in comps]).astype(np.uint64)
+                bd = np.array([ev(*b.split(), 0) for b in bodies], np.uint32)
+                tr = O.translate(co, de, 1, bo, bd)
+                r = O.check(tr, 2)
+                assert r.violations.size == 0
+                # status of x# before the last component
+                n_last = {"R": 3, "W": 2, "RW": 5}[mode]
+                before = O.check(tr[:tr.size - n_last], 2).final[1] if tr.size > n_last else 1
+                assert before == start
+                flags = PM.vectorpu_step((bool(start & 1), bool(start & 2)), mode, side)
+                want = (1 if flags[0] else 0) | (2 if flags[1] else 0)
+                assert r.final[1] == want, (start, mode, side)
+
+
+# -------------------------------------------------------------------- overlapping arrays
+def test_overlap_write_makes_overlapping_arrays_valid_on_side_only():
+    lo, hi = gen.intervals(300, 5, space=1 << 14, max_len=256)
+    e = gen.plain_events(4000, 300, 6)
+    r = O.check_overlap(e, lo, hi)
+    off, nbr = O.overlap_sets(lo, hi)
+    # replay: after each write, every overlapping array is valid on the write's side only
+    sigma = np.ones(300, np.uint8)
+    for i, w in enumerate(e):
+        x = int(w & 0xFFFFFF)
+        op, side = int((w >> 24) & 7), int((w >> 27) & 1)
+        assert O.pre(r.status)[i] == sigma[x]
+        sigma[x] = O.post(r.status)[i]
+        if op == 1:
+            for y in nbr[off[x]:off[x + 1]]:
+                sigma[y] = 1 << side
+    assert np.array_equal(sigma, r.final)
+    assert r.n_induced_stuck == 0
+
+
+def test_overlap_without_overlaps_is_plain_check():
+    lo = np.arange(0, 400, 4, dtype=np.uint32)
+    hi = lo + 4
+    e = gen.plain_events(5000, 100, 8)
+    a = O.check_overlap(e, lo, hi)
+    b = O.check(e, 100)
+    assert a.n_induced == 0 and np.array_equal(a.status, b.status) and np.array_equal(a.final, b.final)
+
+
+def test_overlap_sets_brute_force_small():
+    lo, hi = gen.intervals(200, 9, space=2000, max_len=64)
+    off, nbr = O.overlap_sets(lo, hi)
+    for x in range(200):
+        want = [y for y in range(200) if y != x and lo[x] < hi[y] and lo[y] < hi[x]]
+        assert list(nbr[off[x]:off[x + 1]]) == want
+
+
+def _element_program(model, comps, extend, lo, hi, names):
+    ids = {n: i for i, n in enumerate(names)}
+    for side, decls, body in comps:
+        m = np.array([decl(mode, side, ids[a]) for mode, a in decls], np.uint32)
+        full = O.overlap_extend(m, lo, hi) if extend else m
+        for w in full:
+            mode = ["R", "W", "RW"][(w >> 24) & 3]
+            model.declare(mode, side, names[w & 0xFFFFFF])
+        for op, a, i in body:
+            model.access(op, side, a, i)
+        yield model
+
+
+def test_overlap_rules_keep_element_model_consistent_pvector():
+    """Theorem on overlapping arrays (Section 4.2) on the pvector example with f2 moved to
+    the GPU: with O(M) every element access succeeds and the abstraction stays correct;
+    with M alone the CPU read in f3 hits stale elements."""
+    ex = load_yaml("overlap_example.yaml")
+    names = list(ex["arrays"])
+    lo = np.array([ex["arrays"][n][0] for n in names], np.uint32)
+    hi = np.array([ex["arrays"][n][1] for n in names], np.uint32)
+    comps = [
+        ("CPU", [("R", "pv1"), ("R", "pv2")], [("r", "pv1", 3), ("r", "pv2", 5)]),
+        ("GPU", [("W", "pv3")], [("w", "pv3", 7), ("w", "pv3", 8)]),
+        ("CPU", [("RW", "pv4"), ("R", "pv2")], [("r", "pv2", 7), ("w", "pv4", 2)]),
+    ]
+    arrays = {n: tuple(ex["arrays"][n]) for n in names}
+    good = PM.ElementModel(10, arrays)
+    for m in _element_program(good, comps, True, lo, hi, names):
+        assert m.abstraction_ok()
+    assert good.stuck == []
+    bad = PM.ElementModel(10, arrays)
+    oks = [m.abstraction_ok() for m in _element_program(bad, comps, False, lo, hi, names)]
+    assert not all(oks)
+    assert ("r", "pv2", 7) in bad.stuck
+
+
+def test_overlap_rules_random_element_programs():
+    """Random well-declared component programs over overlapping arrays: with O(M), no
+    element step is stuck and sigma(y#) <= sigma(y[i]) for every element after every
+    component (Theorem "overlapping arrays")."""
+    rng = np.random.default_rng(12)
+    for trial in range(150):
+        n_arr = int(rng.integers(2, 6))
+        lo = rng.integers(0, 12, n_arr).astype(np.uint32)
+        hi = (lo + rng.integers(1, 6, n_arr)).astype(np.uint32)
+        names = [f"a{i}" for i in range(n_arr)]
+        arrays = {names[i]: (int(lo[i]), int(hi[i])) for i in range(n_arr)}
+        comps = []
+        for _ in range(int(rng.integers(1, 7))):
+            side = "CPU" if rng.random() < 0.5 else "GPU"
+            k = int(rng.integers(1, n_arr + 1))
+            chosen = rng.choice(n_arr, size=k, replace=False)
+            decls, body = [], []
+            for a in chosen:
+                mode = ["R", "W", "RW"][int(rng.integers(0, 3))]
+                decls.append((mode, names[a]))
+                l, h = arrays[names[a]]
+                if mode == "R":
+                    body += [("r", names[a], int(i)) for i in range(l, h) if rng.random() < 0.5]
+                elif mode == "W":
+                    body += [("w", names[a], i) for i in range(l, h)]  # W: every element written
+                else:
+                    for i in range(l, h):
+                        if rng.random() < 0.5:
+                            body.append(("r", names[a], i))
+                        if rng.random() < 0.5:
+                            body.append(("w", names[a], i))
+            comps.append((side, decls, body))
+        model = PM.ElementModel(int(hi.max()) + 1, arrays)
+        for m in _element_program(model, comps, True, lo, hi, names):
+            assert m.abstraction_ok(), trial
+        assert model.stuck == [], trial
