@@ -1,0 +1,213 @@
+/*
+ * vcheck.h -- C ABI of libvcheck, a checker for the validity-status effect system of
+ * Henrio, Kessler and Li, "Leveraging Access Mode Declarations in a Model for Memory
+ * Consistency in Heterogeneous Systems" (arXiv 1910.11110), evaluated by HIP kernels
+ * on an MI355X (gfx950).
+ *
+ * Every variable has a validity pair (CPU copy, GPU copy), each V or I (Section 3.1).
+ * A trace is a sequence of effects r, w, Push, Pull, Noop, each on one variable and
+ * run on the CPU (local) or the GPU (remote, rule "Remote Effect").  Checking a trace
+ * applies rules Effect / Remote Effect (Figure "Operational semantics of validity
+ * status") from the initial store and flags every step whose status does not unify
+ * with the effect's signature (Property "Progress").  A flagged step leaves the
+ * status unchanged and the check continues; the first flagged index is where the
+ * paper's semantics gets stuck.
+ *
+ * Encodings
+ *   event word  (uint32): bits 0-23 variable id, bits 24-26 op (0 r, 1 w, 2 Push,
+ *                3 Pull, 4 Noop), bit 27 side (0 CPU/local, 1 GPU/remote), bits 28-31
+ *                must be 0.  Ops 5-7 are rejected.
+ *   decl word   (uint32): bits 0-23 variable, bits 24-25 mode (0 R, 1 W, 2 RW), bit 27
+ *                side; bit 26 and bits 28-31 must be 0.  VectorPU annotations map as
+ *                R->R, W->W, RW->RW (side CPU) and GR, GW, GRW -> the same modes on
+ *                side GPU; iterator forms share their pointer form's mode; NA is
+ *                simply not declared.
+ *   status code (uint8): bit 0 = CPU copy valid, bit 1 = GPU copy valid:
+ *                (I,I)=0, (V,I)=1, (I,V)=2, (V,V)=3.
+ *   status byte (uint8, per event): post | pre << 2 | stuck << 7.
+ *
+ * Conventions
+ *   - Every function returns VC_OK (0) or a negative vc_status; vc_last_error() gives a
+ *     message for the calling thread's last failure (it names the first bad index
+ *     for malformed input).
+ *   - Host buffers passed in are owned by the caller and copied during the call.
+ *     Buffers flagged as device pointers are borrowed: they must stay valid and
+ *     unchanged until the next vc_sync() on the context.  Device buffers the library
+ *     allocates belong to the handle and are freed by vc_trace_free / vc_ctx_destroy.
+ *   - Work is enqueued on the context's HIP stream; vc_check, vc_translate and
+ *     vc_batch_check return before the GPU finishes.  vc_sync waits and reports
+ *     errors found on the device (malformed device-resident input).
+ *   - A handle is not thread-safe; use one context per host thread.  The server is
+ *     thread-safe.
+ */
+#ifndef VCHECK_H
+#define VCHECK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum vc_status {
+    VC_OK = 0,
+    VC_EINVAL = -1,  /* malformed argument or input word */
+    VC_ENOMEM = -2,  /* device or host allocation failed */
+    VC_EDEVICE = -3, /* HIP runtime error */
+    VC_ESTATE = -4,  /* call out of order (e.g. read before check) */
+    VC_ETRUNC = -5,  /* output capacity too small; the true size is still reported */
+    VC_EBUDGET = -6, /* server admission refused by the memory budget */
+    VC_EAGAIN = -7   /* nothing ready yet */
+};
+
+/* flags of vc_trace_load / vc_trace_set_arrays / vc_translate */
+#define VC_DEVICE_INPUT 1u  /* input pointers are device pointers (borrowed) */
+#define VC_DEVICE_INIT 2u   /* init pointer is a device pointer (borrowed) */
+#define VC_TRANSLATE_CHECK 4u /* vc_translate also checks the translated trace */
+
+typedef struct vc_ctx vc_ctx;
+typedef struct vc_trace vc_trace;
+typedef struct vc_server vc_server;
+
+/* ---------------------------------------------------------------------------------
+ * Context: one HIP device and one stream.
+ * hip_stream: NULL to let the library create its own stream, or a borrowed
+ * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream).
+ * --------------------------------------------------------------------------------- */
+int vc_ctx_create(int hip_device, void *hip_stream, vc_ctx **out);
+int vc_ctx_destroy(vc_ctx *ctx);
+const char *vc_last_error(void);
+/* blocks until all work enqueued on the context's stream is done; returns the first
+ * device-side error of that work (VC_EINVAL with the bad index in vc_last_error) */
+int vc_sync(vc_ctx *ctx);
+
+/* ---------------------------------------------------------------------------------
+ * Plain method (rules Effect / Remote Effect from the initial store, Section 3.2).
+ * events : n event words (host, or device with VC_DEVICE_INPUT).
+ * n_ids  : number of variables; every id must be < n_ids, n_ids <= 2^24.
+ * init   : n_ids status codes, or NULL for the paper's initial store (every variable
+ *          at (V,I) = 1).  Host, or device with VC_DEVICE_INIT.
+ * Host events are validated here (VC_EINVAL, bad index in the message); device
+ * events are validated by the first kernel and reported by vc_sync.
+ * n must be < 2^32.
+ * --------------------------------------------------------------------------------- */
+int vc_trace_load(vc_ctx *ctx, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
+                  uint32_t flags, vc_trace **out);
+
+/* Arrays as half-open intervals [lo[i], hi[i]) with lo < hi, one per id (Section 4:
+ * one status per array; arrays x != y overlap iff lo_x < hi_y and lo_y < hi_x).
+ * Once set, vc_check applies the overlapping-array rule to core events: a write
+ * w_s x is followed, for every array y overlapping x, by the induced declaration
+ * RW_s y (acquire y on side s if it is not valid there, then write it on side s),
+ * the extension O(M) of Table "Extension of access mode annotations..." applied to
+ * the one-declaration component of each event.  The overlap sets are computed on the
+ * device by an interval sweep and stay resident with the trace. */
+int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi, uint32_t flags);
+
+/* Overlap sets computed for the arrays, as CSR: off has n_ids + 1 entries (host),
+ * nbr receives off[n_ids] ascending neighbour ids per array. */
+int vc_read_overlap_sets(vc_trace *t, uint64_t *off, uint32_t *nbr, uint64_t cap, uint64_t *n_nbr);
+
+/* ---------------------------------------------------------------------------------
+ * Translation of access-mode declarations (Figure "Semantics of access modes and
+ * programs"): [[M1{S1}; M2{S2}; ...]] = [[M1]]; S1; [[M2]]; S2; ...
+ *   [[R x#]]  = If isValid x# then Noop else (Pull x; Pull x#)
+ *   [[W x#]]  = w x#         [[RW x#]] = [[R x#]]; w x#       and the rem(...) twins
+ *   with remIsValid and local Push.
+ * comp_off : n_comp + 1 CSR offsets (uint64, non-decreasing, comp_off[0] = 0) of each
+ *            component's declarations in decls.
+ * decls    : comp_off[n_comp] decl words; a variable appears at most once per component.
+ * n_vars   : real variables are ids [0, n_vars); the abstract variable of v is n_vars + v
+ *            (2 * n_vars <= 2^24).  Real and abstract variables start at (V,I).
+ * body_off / body : NULL for the canonical body of each declaration in order
+ *            (R: r v, W: w v, RW: r v; w v, on the declaration's side), or CSR offsets
+ *            (n_comp + 1) and event words (ids < n_vars) of each component's body.
+ * Fixed arity: a guard whose condition holds emits "Noop v; Noop v#" on the
+ * declaration's side; otherwise "Pull v; Pull v#" (CPU) or "Push v; Push v#" (GPU),
+ * both as local (CPU-side) events as printed.
+ * The result is a new trace with n_ids = 2 * n_vars; its events can be read back with
+ * vc_read_events.  With VC_TRANSLATE_CHECK the translated trace is also checked (as by
+ * vc_check) in the same enqueue.  VC_DEVICE_INPUT: comp_off/decls/body_off/body are
+ * device pointers.
+ * --------------------------------------------------------------------------------- */
+int vc_translate(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
+                 const uint64_t *body_off, const uint32_t *body, uint32_t flags, vc_trace **out);
+
+/* Checks the trace (asynchronous).  Results are read after vc_sync. */
+int vc_check(vc_trace *t);
+
+/* number of events (after translation: the translated length) and of ids */
+int vc_trace_info(vc_trace *t, uint64_t *n_events, uint32_t *n_ids);
+
+/* ---------------------------------------------------------------------------------
+ * Reading results (synchronous copies to host buffers owned by the caller).
+ * --------------------------------------------------------------------------------- */
+int vc_read_events(vc_trace *t, uint32_t *out, uint64_t cap, uint64_t *n);
+/* one status byte per event: post | pre << 2 | stuck << 7 */
+int vc_read_event_status(vc_trace *t, uint8_t *out, uint64_t cap);
+/* ascending indices of stuck events; *n_total = their number, *first = the first one
+ * or the trace length if none.  VC_ETRUNC if cap < *n_total (first cap written). */
+int vc_read_violations(vc_trace *t, uint32_t *out, uint64_t cap, uint64_t *n_total, uint64_t *first);
+/* status of every id after the trace (the final store) */
+int vc_read_final_status(vc_trace *t, uint8_t *out, uint32_t cap);
+/* stuck acquisitions of induced RW (only possible from an initial (I,I)) */
+int vc_read_induced_stuck(vc_trace *t, uint64_t *n);
+/* device pointers of the results (valid until vc_trace_free) for callers that keep
+ * results on the GPU; any argument may be NULL */
+int vc_trace_device_results(vc_trace *t, void **status, void **final_status, void **violations);
+int vc_trace_free(vc_trace *t);
+
+/* ---------------------------------------------------------------------------------
+ * Batched check: n independent traces of uneven length checked together in one
+ * enqueued pipeline (ids of each trace are relocated to a private range; tiles of
+ * the persistent kernels never mix state of two traces).  Each trace's results are
+ * then read with the vc_read_* functions as if vc_check had run on it alone.
+ * The launch sequence is captured once per batch shape in a hipGraph and replayed.
+ * --------------------------------------------------------------------------------- */
+int vc_batch_check(vc_ctx *ctx, vc_trace *const *traces, uint32_t n);
+
+/* ---------------------------------------------------------------------------------
+ * Serving: streams of trace chunks checked as they arrive, with continuous batching.
+ * A stream owns a status table (n_ids bytes) resident on the device between chunks;
+ * each chunk is checked from the table and leaves its final store there.  A server
+ * thread admits chunks while the bytes they need fit in hbm_budget_bytes, packs the
+ * ready chunks (at most one per stream, in order) into one batched launch, and
+ * overlaps the copies of the next batch with the current one.
+ * --------------------------------------------------------------------------------- */
+struct vc_completion {
+    uint64_t stream;        /* stream id */
+    uint64_t chunk;         /* chunk id returned by vc_stream_submit */
+    uint64_t first_event;   /* index of the chunk's first event within its stream */
+    uint64_t n_events;
+    uint64_t n_violations;
+    uint64_t first_violation; /* stream-relative index, or first_event + n_events if none */
+    double t_submit;        /* seconds on the server clock */
+    double t_start;         /* launch of the batch that carried the chunk */
+    double t_done;          /* results visible on the host */
+    int status;             /* VC_OK or an error */
+};
+
+int vc_server_create(vc_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_batch_events, vc_server **out);
+int vc_server_destroy(vc_server *srv);
+/* lo/hi: optional intervals (host, n_ids each) applying the overlap rule; init: optional
+ * initial statuses (host), NULL = (V,I) */
+int vc_stream_open(vc_server *srv, uint32_t n_ids, const uint32_t *lo, const uint32_t *hi, const uint8_t *init,
+                   uint64_t *stream);
+/* queues a chunk (events copied).  status_out: NULL, or a host buffer of n bytes owned
+ * by the caller that receives the per-event status bytes before the completion is
+ * reported.  VC_EBUDGET if the chunk can never fit the budget. */
+int vc_stream_submit(vc_server *srv, uint64_t stream, const uint32_t *events, uint32_t n, uint8_t *status_out,
+                     uint64_t *chunk);
+/* non-blocking; returns up to cap completions in completion order */
+int vc_poll(vc_server *srv, struct vc_completion *out, uint32_t cap, uint32_t *n);
+/* waits for the stream's chunks, copies its final status table (n_ids bytes) and
+ * releases it */
+int vc_stream_close(vc_server *srv, uint64_t stream, uint8_t *final_out);
+/* seconds on the server clock */
+double vc_server_now(vc_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VCHECK_H */

@@ -1,0 +1,489 @@
+// abi.cpp -- the C ABI of libvcheck: handles, ownership, validation, enqueueing of
+// the device pipelines, result read-back.
+#include "../../include/vcheck.h"
+
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "abi_internal.h"
+#include "internal.h"
+
+using namespace vc;
+
+static thread_local std::string g_err;
+
+int vc_fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+extern "C" const char *vc_last_error(void) { return g_err.c_str(); }
+
+int vc_hip_fail(hipError_t e, const char *what)
+{
+    return vc_fail(e == hipErrorOutOfMemory ? VC_ENOMEM : VC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int devbuf_reserve(DevBuf &b, size_t bytes)
+{
+    if (bytes <= b.bytes && b.p)
+        return VC_OK;
+    if (b.p)
+        (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    size_t want = bytes ? bytes : 256;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return vc_hip_fail(e, "hipMalloc");
+    }
+    b.bytes = want;
+    return VC_OK;
+}
+
+void devbuf_free(DevBuf &b)
+{
+    if (b.p)
+        (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+uint32_t key_bits_for(uint32_t n_ids)
+{
+    if (n_ids <= 1)
+        return 0;
+    return 32u - (uint32_t)__builtin_clz(n_ids - 1);
+}
+
+// ------------------------------------------------------------------------------ ctx
+extern "C" int vc_ctx_create(int hip_device, void *hip_stream, vc_ctx **out)
+{
+    if (!out)
+        return vc_fail(VC_EINVAL, "vc_ctx_create: out is NULL");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "hipGetDeviceCount");
+    if (hip_device < 0 || hip_device >= ndev)
+        return vc_fail(VC_EINVAL, "vc_ctx_create: device %d not present (%d devices)", hip_device, ndev);
+    if ((e = hipSetDevice(hip_device)) != hipSuccess)
+        return vc_hip_fail(e, "hipSetDevice");
+    vc_ctx *c = new vc_ctx();
+    c->device = hip_device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+            delete c;
+            return vc_hip_fail(e, "hipStreamCreate");
+        }
+        c->own_stream = true;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
+        c->cu_count = prop.multiProcessorCount;
+    *out = c;
+    return VC_OK;
+}
+
+extern "C" int vc_ctx_destroy(vc_ctx *c)
+{
+    if (!c)
+        return VC_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    batch_release(c);
+    if (c->own_stream)
+        (void)hipStreamDestroy(c->stream);
+    delete c;
+    return VC_OK;
+}
+
+extern "C" int vc_sync(vc_ctx *c)
+{
+    if (!c)
+        return vc_fail(VC_EINVAL, "vc_sync: NULL context");
+    (void)hipSetDevice(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "hipStreamSynchronize");
+    int rc = VC_OK;
+    for (vc_trace *t : c->pending) {
+        int r = trace_collect(t);
+        if (r != VC_OK && rc == VC_OK)
+            rc = r;
+    }
+    c->pending.clear();
+    if (rc != VC_OK)
+        return rc;
+    return VC_OK;
+}
+
+// gathers the device-side counters of a finished check into the handle
+int trace_collect(vc_trace *t)
+{
+    Control h;
+    hipError_t e = hipMemcpy(&h, t->ctl, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "hipMemcpy(control)");
+    t->pending = false;
+    uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
+    if (bad != ~0ull) {
+        t->checked = false;
+        t->error = VC_EINVAL;
+        return vc_fail(VC_EINVAL, "malformed input word at index %llu", (unsigned long long)bad);
+    }
+    if (t->translate_pending) {
+        t->translate_pending = false;
+    }
+    if (t->check_pending) {
+        t->check_pending = false;
+        t->n_viol = h.n_viol;
+        t->n_induced_stuck = h.n_induced_stuck;
+        t->first = t->n;
+        if (t->n_viol) {
+            uint32_t f = 0;
+            e = hipMemcpy(&f, t->viol.p, sizeof f, hipMemcpyDeviceToHost);
+            if (e != hipSuccess)
+                return vc_hip_fail(e, "hipMemcpy(first violation)");
+            t->first = f;
+        }
+        t->checked = true;
+        t->error = VC_OK;
+    }
+    return VC_OK;
+}
+
+// --------------------------------------------------------------------------- traces
+static int trace_alloc_common(vc_ctx *c, vc_trace *t)
+{
+    hipError_t e;
+    if ((e = hipMalloc(&t->ctl, sizeof(Control))) != hipSuccess)
+        return vc_hip_fail(e, "hipMalloc(control)");
+    (void)c;
+    return VC_OK;
+}
+
+static int validate_events_host(const uint32_t *ev, uint64_t n, uint32_t n_ids)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t w = ev[i];
+        if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= n_ids)
+            return vc_fail(VC_EINVAL, "malformed event word 0x%08x at index %llu (n_ids %u)", w,
+                           (unsigned long long)i, n_ids);
+    }
+    return VC_OK;
+}
+
+int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags)
+{
+    if (!init) {
+        t->init = nullptr;
+        return VC_OK;
+    }
+    if (flags & VC_DEVICE_INIT) {
+        t->init = const_cast<uint8_t *>(init);
+        t->own_init = false;
+        return VC_OK;
+    }
+    for (uint32_t i = 0; i < t->n_ids; i++)
+        if (init[i] > 3)
+            return vc_fail(VC_EINVAL, "init status %u at id %u is not a status code", init[i], i);
+    hipError_t e;
+    if ((e = hipMalloc(&t->init, t->n_ids ? t->n_ids : 1)) != hipSuccess)
+        return vc_hip_fail(e, "hipMalloc(init)");
+    t->own_init = true;
+    if ((e = hipMemcpy(t->init, init, t->n_ids, hipMemcpyHostToDevice)) != hipSuccess)
+        return vc_hip_fail(e, "hipMemcpy(init)");
+    return VC_OK;
+}
+
+extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
+                             uint32_t flags, vc_trace **out)
+{
+    if (!c || !out)
+        return vc_fail(VC_EINVAL, "vc_trace_load: NULL argument");
+    if (n && !events)
+        return vc_fail(VC_EINVAL, "vc_trace_load: events is NULL");
+    if (n_ids > (1u << 24))
+        return vc_fail(VC_EINVAL, "vc_trace_load: n_ids %u exceeds 2^24", n_ids);
+    if (n >= (1ull << 32))
+        return vc_fail(VC_EINVAL, "vc_trace_load: n %llu must be < 2^32", (unsigned long long)n);
+    if (n && n_ids == 0)
+        return vc_fail(VC_EINVAL, "vc_trace_load: events but n_ids is 0");
+    (void)hipSetDevice(c->device);
+    if (!(flags & VC_DEVICE_INPUT)) {
+        int r = validate_events_host(events, n, n_ids);
+        if (r != VC_OK)
+            return r;
+    }
+    vc_trace *t = new vc_trace();
+    t->ctx = c;
+    t->n = n;
+    t->n_ids = n_ids;
+    int r = trace_alloc_common(c, t);
+    if (r == VC_OK)
+        r = trace_set_init(t, init, flags);
+    if (r == VC_OK) {
+        if (flags & VC_DEVICE_INPUT) {
+            t->events = const_cast<uint32_t *>(events);
+            t->own_events = false;
+        } else {
+            hipError_t e = hipMalloc(&t->events, n ? n * 4 : 4);
+            if (e != hipSuccess)
+                r = vc_hip_fail(e, "hipMalloc(events)");
+            else if (n && (e = hipMemcpy(t->events, events, n * 4, hipMemcpyHostToDevice)) != hipSuccess)
+                r = vc_hip_fail(e, "hipMemcpy(events)");
+            t->own_events = true;
+        }
+    }
+    if (r != VC_OK) {
+        vc_trace_free(t);
+        return r;
+    }
+    *out = t;
+    return VC_OK;
+}
+
+extern "C" int vc_trace_info(vc_trace *t, uint64_t *n_events, uint32_t *n_ids)
+{
+    if (!t)
+        return vc_fail(VC_EINVAL, "vc_trace_info: NULL trace");
+    if (n_events)
+        *n_events = t->n;
+    if (n_ids)
+        *n_ids = t->n_ids;
+    return VC_OK;
+}
+
+// outputs and scratch of a check of m items over the trace's n events
+int trace_reserve(vc_trace *t, uint64_t m)
+{
+    int r;
+    if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(t->viol, (t->n ? t->n : 1) * 4)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(t->items_a, (m ? m : 1) * 8)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(t->items_b, (m ? m : 1) * 8)) != VC_OK)
+        return r;
+    size_t sc = std::max({ sort_scratch_bytes(m), scan_scratch_bytes(m), compact_scratch_bytes(t->n) });
+    if ((r = devbuf_reserve(t->scratch, sc)) != VC_OK)
+        return r;
+    return VC_OK;
+}
+
+// enqueues the check pipeline on items already built in t->items_a (m items)
+void enqueue_check_items(vc_trace *t, uint64_t m, hipStream_t s)
+{
+    uint64_t *items = (uint64_t *)t->items_a.p;
+    uint64_t *sorted = sort_items(items, (uint64_t *)t->items_b.p, m, (int)key_bits_for(t->n_ids), t->scratch.p,
+                                  t->ctl, s);
+    uint8_t *fin = (uint8_t *)t->fin.p;
+    if (t->init)
+        (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
+    else
+        launch_fill_u8(fin, 1, t->n_ids, s);
+    launch_segscan(sorted, m, t->init, t->n_ids, SCAN_STATUS, (uint8_t *)t->status.p, fin, t->scratch.p, t->ctl, s);
+    launch_compact((uint8_t *)t->status.p, t->n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
+}
+
+int enqueue_check(vc_trace *t, hipStream_t s)
+{
+    int r;
+    uint64_t m = t->n;
+    if (t->has_arrays) {
+        m = overlap_combined_size(t);
+        if (m == ~0ull)
+            return vc_fail(VC_EDEVICE, "overlap expansion sizing failed");
+    }
+    if ((r = trace_reserve(t, m)) != VC_OK)
+        return r;
+    launch_reset_control(t->ctl, s);
+    if (t->has_arrays)
+        overlap_enqueue_items(t, m, s);
+    else
+        launch_make_items_events(t->events, t->n, t->n_ids, (uint64_t *)t->items_a.p, t->ctl, s);
+    enqueue_check_items(t, m, s);
+    return VC_OK;
+}
+
+extern "C" int vc_check(vc_trace *t)
+{
+    if (!t)
+        return vc_fail(VC_EINVAL, "vc_check: NULL trace");
+    vc_ctx *c = t->ctx;
+    (void)hipSetDevice(c->device);
+    int r = enqueue_check(t, c->stream);
+    if (r != VC_OK)
+        return r;
+    t->check_pending = true;
+    t->checked = false;
+    if (!t->pending) {
+        t->pending = true;
+        c->pending.push_back(t);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "kernel launch");
+    return VC_OK;
+}
+
+static int require_checked(vc_trace *t, const char *fn)
+{
+    if (!t)
+        return vc_fail(VC_EINVAL, "%s: NULL trace", fn);
+    if (t->pending) {
+        int r = vc_sync(t->ctx);
+        if (r != VC_OK)
+            return r;
+    }
+    if (t->error != VC_OK)
+        return vc_fail(t->error, "%s: the last check failed", fn);
+    if (!t->checked)
+        return vc_fail(VC_ESTATE, "%s: trace has not been checked", fn);
+    return VC_OK;
+}
+
+extern "C" int vc_read_events(vc_trace *t, uint32_t *out, uint64_t cap, uint64_t *n)
+{
+    if (!t)
+        return vc_fail(VC_EINVAL, "vc_read_events: NULL trace");
+    if (t->pending) {
+        int r = vc_sync(t->ctx);
+        if (r != VC_OK)
+            return r;
+    }
+    if (n)
+        *n = t->n;
+    if (!out)
+        return VC_OK;
+    uint64_t k = std::min(cap, t->n);
+    if (k) {
+        hipError_t e = hipMemcpy(out, t->events, k * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(events)");
+    }
+    return (out && cap < t->n) ? vc_fail(VC_ETRUNC, "vc_read_events: capacity %llu < %llu", (unsigned long long)cap,
+                                (unsigned long long)t->n)
+                      : VC_OK;
+}
+
+extern "C" int vc_read_event_status(vc_trace *t, uint8_t *out, uint64_t cap)
+{
+    int r = require_checked(t, "vc_read_event_status");
+    if (r != VC_OK)
+        return r;
+    uint64_t k = std::min(cap, t->n);
+    if (k && out) {
+        hipError_t e = hipMemcpy(out, t->status.p, k, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(status)");
+    }
+    return cap < t->n ? vc_fail(VC_ETRUNC, "vc_read_event_status: capacity too small") : VC_OK;
+}
+
+extern "C" int vc_read_violations(vc_trace *t, uint32_t *out, uint64_t cap, uint64_t *n_total, uint64_t *first)
+{
+    int r = require_checked(t, "vc_read_violations");
+    if (r != VC_OK)
+        return r;
+    if (n_total)
+        *n_total = t->n_viol;
+    if (first)
+        *first = t->first;
+    uint64_t k = std::min(cap, t->n_viol);
+    if (k && out) {
+        hipError_t e = hipMemcpy(out, t->viol.p, k * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(violations)");
+    }
+    return (out && cap < t->n_viol) ? vc_fail(VC_ETRUNC, "vc_read_violations: capacity %llu < %llu",
+                                     (unsigned long long)cap, (unsigned long long)t->n_viol)
+                           : VC_OK;
+}
+
+extern "C" int vc_read_final_status(vc_trace *t, uint8_t *out, uint32_t cap)
+{
+    int r = require_checked(t, "vc_read_final_status");
+    if (r != VC_OK)
+        return r;
+    uint32_t k = std::min(cap, t->n_ids);
+    if (k && out) {
+        hipError_t e = hipMemcpy(out, t->fin.p, k, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(final)");
+    }
+    return cap < t->n_ids ? vc_fail(VC_ETRUNC, "vc_read_final_status: capacity too small") : VC_OK;
+}
+
+extern "C" int vc_read_induced_stuck(vc_trace *t, uint64_t *n)
+{
+    int r = require_checked(t, "vc_read_induced_stuck");
+    if (r != VC_OK)
+        return r;
+    if (n)
+        *n = t->n_induced_stuck;
+    return VC_OK;
+}
+
+extern "C" int vc_trace_device_results(vc_trace *t, void **status, void **final_status, void **violations)
+{
+    if (!t)
+        return vc_fail(VC_EINVAL, "vc_trace_device_results: NULL trace");
+    if (status)
+        *status = t->status.p;
+    if (final_status)
+        *final_status = t->fin.p;
+    if (violations)
+        *violations = t->viol.p;
+    return VC_OK;
+}
+
+extern "C" int vc_trace_free(vc_trace *t)
+{
+    if (!t)
+        return VC_OK;
+    vc_ctx *c = t->ctx;
+    if (c) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        auto &p = c->pending;
+        p.erase(std::remove(p.begin(), p.end(), t), p.end());
+    }
+    if (t->own_events && t->events)
+        (void)hipFree(t->events);
+    if (t->own_init && t->init)
+        (void)hipFree(t->init);
+    if (t->ctl)
+        (void)hipFree(t->ctl);
+    overlap_release(t);
+    devbuf_free(t->status);
+    devbuf_free(t->fin);
+    devbuf_free(t->viol);
+    devbuf_free(t->items_a);
+    devbuf_free(t->items_b);
+    devbuf_free(t->scratch);
+    devbuf_free(t->aux);
+    delete t;
+    return VC_OK;
+}

@@ -1,0 +1,76 @@
+// abi_internal.h -- handle layouts and helpers shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/vcheck.h"
+#include "internal.h"
+
+// grow-only device buffer owned by a handle
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct BatchState; // batched pipeline: captured graphs and descriptor buffers
+
+struct vc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cu_count = 256;
+    std::vector<vc_trace *> pending; // traces with enqueued work not yet collected
+    BatchState *batch = nullptr;
+};
+
+struct vc_trace {
+    vc_ctx *ctx = nullptr;
+    uint64_t n = 0;       // events
+    uint32_t n_ids = 0;
+    uint32_t *events = nullptr;
+    bool own_events = false;
+    uint8_t *init = nullptr;
+    bool own_init = false;
+    vc::Control *ctl = nullptr;
+
+    // overlapping arrays
+    bool has_arrays = false;
+    uint32_t *lo = nullptr, *hi = nullptr;
+    vc::OverlapSets sets{};
+    uint64_t n_induced = 0; // induced events of the last expansion
+
+    // outputs
+    DevBuf status, fin, viol;
+    // scratch
+    DevBuf items_a, items_b, scratch, aux;
+
+    // state
+    bool pending = false;
+    bool check_pending = false;
+    bool translate_pending = false;
+    bool checked = false;
+    int error = VC_OK;
+    uint64_t n_viol = 0, first = 0, n_induced_stuck = 0;
+};
+
+int vc_fail(int code, const char *fmt, ...);
+int vc_hip_fail(hipError_t e, const char *what);
+int devbuf_reserve(DevBuf &b, size_t bytes);
+void devbuf_free(DevBuf &b);
+uint32_t key_bits_for(uint32_t n_ids);
+int trace_collect(vc_trace *t);
+int trace_reserve(vc_trace *t, uint64_t m);
+int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags);
+void enqueue_check_items(vc_trace *t, uint64_t m, hipStream_t s);
+int enqueue_check(vc_trace *t, hipStream_t s);
+
+// overlap (overlap_abi.cpp)
+uint64_t overlap_combined_size(vc_trace *t);
+void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s);
+void overlap_release(vc_trace *t);
+
+// batch (batch.cpp)
+void batch_release(vc_ctx *c);

@@ -1,0 +1,103 @@
+// internal.h -- host-side launch interface between the C-ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace vc {
+
+constexpr int BLOCK = 256;       // threads per workgroup (4 waves of 64)
+constexpr int SORT_ITEMS = 16;   // items per thread in a sort tile
+constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
+constexpr int SCAN_ITEMS = 16;   // items per thread in a scan tile
+constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
+constexpr int RADIX_BITS_MAX = 8;
+constexpr int RADIX = 1 << RADIX_BITS_MAX;
+
+inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// control block: counters zeroed at the start of each pipeline run
+struct Control {
+    uint32_t tickets[16];         // tile tickets, one per kernel of the pipeline
+    uint32_t err_index_lo;        // first malformed input index (low/high), 0xFFFFFFFF.. if none
+    uint32_t err_index_hi;
+    uint32_t err_code;
+    uint32_t pad0;
+    unsigned long long n_viol;    // violations found
+    unsigned long long n_induced_stuck;
+    unsigned long long n_out;     // produced element count (translation)
+    unsigned long long pad[3];
+};
+
+// ------------------------------- utilities ----------------------------------------
+void launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
+void launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s);
+void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+void launch_reset_control(Control *c, hipStream_t s);
+
+// exclusive scan of n uint32 counts into n+1 uint64 offsets (out[n] = total, also
+// stored to *total when non-null); scratch of excl_scan_scratch_bytes(n)
+size_t excl_scan_scratch_bytes(uint64_t n);
+void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total, void *scratch, uint32_t *ticket,
+                      hipStream_t s);
+
+// ------------------------------- radix sort ---------------------------------------
+// Stable LSD sort of 64-bit items by their 28-bit key (see device.h), key_bits
+// significant bits.  Returns the buffer that holds the sorted items (a or b).
+size_t sort_scratch_bytes(uint64_t n);
+uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *scratch, Control *ctl,
+                     hipStream_t s);
+
+// items from a plain event trace: key = key_base + id, fcode = op*2+side,
+// payload = payload_base + index
+void launch_make_items_events(const uint32_t *events, uint64_t n, uint32_t n_ids, uint64_t *items, Control *ctl,
+                              hipStream_t s, uint32_t key_base = 0, uint64_t payload_base = 0);
+
+// ------------------------------- segmented scan -----------------------------------
+enum ScanOut { SCAN_STATUS = 0, SCAN_PRE = 1 };
+size_t scan_scratch_bytes(uint64_t n);
+// Evaluates sorted items segment by segment (segment = equal key) from init[key]
+// (1 = (V,I) when init is null).  mode SCAN_STATUS: status[payload] = post|pre<<2|flag<<7
+// for payload != NO_PAYLOAD, induced-stuck counted otherwise; final[key] = last post.
+// mode SCAN_PRE: pre[payload] = status before the item.
+void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, int mode,
+                    uint8_t *out, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s);
+
+// ------------------------------- compaction ---------------------------------------
+size_t compact_scratch_bytes(uint64_t n);
+// ascending indices of status bytes with bit 7 set; count into ctl->n_viol
+void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s);
+
+// ------------------------------- translation --------------------------------------
+// sort items of the declarations: key = variable, fcode = the declaration's effect
+// on the abstract variable, payload = declaration index
+void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint64_t *items, Control *ctl,
+                             hipStream_t s);
+// per component: number of translated events
+void launch_translate_count(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                            const uint64_t *body_off, uint32_t *cnt, Control *ctl, hipStream_t s);
+// writes the translated trace (positions = exclusive scan of the counts)
+void launch_translate_emit(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                           uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *body_off, const uint32_t *body,
+                           const uint64_t *pos, uint32_t *out, Control *ctl, hipStream_t s);
+
+// ------------------------------- overlap ------------------------------------------
+struct OverlapSets {
+    uint64_t *off = nullptr; // n_arrays + 1
+    uint32_t *nbr = nullptr; // off[n_arrays] neighbours, ascending per array
+    uint64_t n_nbr = 0;
+};
+// overlap CSR of [lo, hi) intervals (device pointers) by interval sweep; allocates
+// out's buffers; synchronizes the stream once to size the pair list.  Returns 0 or -3.
+int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n_arrays, int key_bits, OverlapSets *out,
+                       Control *ctl, hipStream_t s);
+void free_overlap_sets(OverlapSets *o);
+// cnt[i] = number of induced events after event i
+void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, uint32_t *cnt,
+                          uint64_t index_base, Control *ctl, hipStream_t s);
+// combined items at position i + pos[i] (pos = exclusive scan of cnt); cap = item capacity
+void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
+                         uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, Control *ctl,
+                         hipStream_t s);
+
+} // namespace vc
