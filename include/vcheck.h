@@ -89,7 +89,7 @@ int vc_sync(vc_ctx *ctx);
  *          at (V,I) = 1).  Host, or device with VC_DEVICE_INIT.
  * Host events are validated here (VC_EINVAL, bad index in the message); device
  * events are validated by the first kernel and reported by vc_sync.
- * n must be < 2^32.
+ * n must be < 2^31.
  * --------------------------------------------------------------------------------- */
 int vc_trace_load(vc_ctx *ctx, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
                   uint32_t flags, vc_trace **out);
@@ -132,6 +132,11 @@ int vc_read_overlap_sets(vc_trace *t, uint64_t *off, uint32_t *nbr, uint64_t cap
  * --------------------------------------------------------------------------------- */
 int vc_translate(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
                  const uint64_t *body_off, const uint32_t *body, uint32_t flags, vc_trace **out);
+
+/* Re-runs the translation of a trace made by vc_translate (and its check if it was
+ * created with VC_TRANSLATE_CHECK) on the same inputs, reusing every buffer.  Borrowed
+ * device inputs may have been rewritten in place with the same sizes. */
+int vc_translate_run(vc_trace *t);
 
 /* Checks the trace (asynchronous).  Results are read after vc_sync. */
 int vc_check(vc_trace *t);

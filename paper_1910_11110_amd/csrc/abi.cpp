@@ -139,18 +139,33 @@ extern "C" int vc_sync(vc_ctx *c)
 int trace_collect(vc_trace *t)
 {
     Control h;
-    hipError_t e = hipMemcpy(&h, t->ctl, sizeof h, hipMemcpyDeviceToHost);
+    hipError_t e;
+    t->pending = false;
+    if (t->translate_pending) {
+        t->translate_pending = false;
+        if ((e = hipMemcpy(&h, t->tr->ctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(control)");
+        uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
+        if (bad != ~0ull) {
+            t->checked = false;
+            t->check_pending = false;
+            t->error = VC_EINVAL;
+            return vc_fail(VC_EINVAL, "malformed declaration, component offset or body word at index %llu",
+                           (unsigned long long)bad);
+        }
+        t->error = VC_OK;
+    }
+    if (!t->check_pending)
+        return VC_OK;
+    e = hipMemcpy(&h, t->ctl, sizeof h, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return vc_hip_fail(e, "hipMemcpy(control)");
-    t->pending = false;
     uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
     if (bad != ~0ull) {
         t->checked = false;
+        t->check_pending = false;
         t->error = VC_EINVAL;
         return vc_fail(VC_EINVAL, "malformed input word at index %llu", (unsigned long long)bad);
-    }
-    if (t->translate_pending) {
-        t->translate_pending = false;
     }
     if (t->check_pending) {
         t->check_pending = false;
@@ -223,8 +238,8 @@ extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint
         return vc_fail(VC_EINVAL, "vc_trace_load: events is NULL");
     if (n_ids > (1u << 24))
         return vc_fail(VC_EINVAL, "vc_trace_load: n_ids %u exceeds 2^24", n_ids);
-    if (n >= (1ull << 32))
-        return vc_fail(VC_EINVAL, "vc_trace_load: n %llu must be < 2^32", (unsigned long long)n);
+    if (n >= (1ull << 31))
+        return vc_fail(VC_EINVAL, "vc_trace_load: n %llu must be < 2^31", (unsigned long long)n);
     if (n && n_ids == 0)
         return vc_fail(VC_EINVAL, "vc_trace_load: events but n_ids is 0");
     (void)hipSetDevice(c->device);
@@ -477,6 +492,7 @@ extern "C" int vc_trace_free(vc_trace *t)
     if (t->ctl)
         (void)hipFree(t->ctl);
     overlap_release(t);
+    translate_release(t);
     devbuf_free(t->status);
     devbuf_free(t->fin);
     devbuf_free(t->viol);

@@ -17,6 +17,18 @@ struct DevBuf {
 
 struct BatchState; // batched pipeline: captured graphs and descriptor buffers
 
+// inputs and work buffers of a translation, kept so that it can be re-run
+struct TranslateState {
+    uint64_t n_comp = 0, n_decl = 0;
+    uint32_t n_vars = 0;
+    bool check = false;
+    bool own_inputs = false;
+    uint64_t *comp_off = nullptr, *body_off = nullptr;
+    uint32_t *decls = nullptr, *body = nullptr;
+    vc::Control *ctl = nullptr;
+    DevBuf cnt, pos, pre_abs, items_a, items_b, scratch;
+};
+
 struct vc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -31,7 +43,9 @@ struct vc_trace {
     uint64_t n = 0;       // events
     uint32_t n_ids = 0;
     uint32_t *events = nullptr;
+    uint64_t events_cap = 0;
     bool own_events = false;
+    TranslateState *tr = nullptr; // set for traces produced by vc_translate
     uint8_t *init = nullptr;
     bool own_init = false;
     vc::Control *ctl = nullptr;
@@ -39,6 +53,7 @@ struct vc_trace {
     // overlapping arrays
     bool has_arrays = false;
     uint32_t *lo = nullptr, *hi = nullptr;
+    bool own_arrays = false;
     vc::OverlapSets sets{};
     uint64_t n_induced = 0; // induced events of the last expansion
 
@@ -71,6 +86,10 @@ int enqueue_check(vc_trace *t, hipStream_t s);
 uint64_t overlap_combined_size(vc_trace *t);
 void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s);
 void overlap_release(vc_trace *t);
+
+// translation (translate_abi.cpp)
+int translate_enqueue(vc_trace *t, hipStream_t s);
+void translate_release(vc_trace *t);
 
 // batch (batch.cpp)
 void batch_release(vc_ctx *c);

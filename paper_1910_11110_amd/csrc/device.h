@@ -180,6 +180,8 @@ __device__ __forceinline__ uint32_t item_key(uint64_t it) { return (uint32_t)(it
 __device__ __forceinline__ uint32_t item_fcode(uint64_t it) { return (uint32_t)(it >> 60); }
 __device__ __forceinline__ uint32_t item_payload(uint64_t it) { return (uint32_t)it; }
 
-constexpr uint32_t NO_PAYLOAD = 0xFFFFFFFFu;
+// payload of an induced item (overlap rule): high bit set, low bits = index of the
+// trace it belongs to (for per-trace counts of stuck induced acquisitions)
+constexpr uint32_t INDUCED_BIT = 0x80000000u;
 
 } // namespace vc

@@ -44,9 +44,13 @@ void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *t
 // ------------------------------- radix sort ---------------------------------------
 // Stable LSD sort of 64-bit items by their 28-bit key (see device.h), key_bits
 // significant bits.  Returns the buffer that holds the sorted items (a or b).
+struct SortTuning {
+    int max_bits = RADIX_BITS_MAX; // digit bits per pass (4..8)
+    unsigned grid_cap = 0;         // persistent grid bound (0 = one workgroup per tile)
+};
 size_t sort_scratch_bytes(uint64_t n);
 uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *scratch, Control *ctl,
-                     hipStream_t s);
+                     hipStream_t s, const SortTuning *tune = nullptr);
 
 // items from a plain event trace: key = key_base + id, fcode = op*2+side,
 // payload = payload_base + index
@@ -58,10 +62,13 @@ enum ScanOut { SCAN_STATUS = 0, SCAN_PRE = 1 };
 size_t scan_scratch_bytes(uint64_t n);
 // Evaluates sorted items segment by segment (segment = equal key) from init[key]
 // (1 = (V,I) when init is null).  mode SCAN_STATUS: status[payload] = post|pre<<2|flag<<7
-// for payload != NO_PAYLOAD, induced-stuck counted otherwise; final[key] = last post.
+// for primary items, stuck induced items counted per trace; final[key] = last post.
 // mode SCAN_PRE: pre[payload] = status before the item.
+// ind_counts: per-trace counters of stuck induced items (payload low bits index it),
+// &ctl->n_induced_stuck when null.  grid_cap bounds the persistent grid.
 void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, int mode,
-                    uint8_t *out, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s);
+                    uint8_t *out, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s,
+                    unsigned long long *ind_counts = nullptr, unsigned grid_cap = 1u << 30);
 
 // ------------------------------- compaction ---------------------------------------
 size_t compact_scratch_bytes(uint64_t n);
@@ -97,7 +104,7 @@ void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
                           uint64_t index_base, Control *ctl, hipStream_t s);
 // combined items at position i + pos[i] (pos = exclusive scan of cnt); cap = item capacity
 void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
-                         uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, Control *ctl,
-                         hipStream_t s);
+                         uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, uint32_t trace_index,
+                         Control *ctl, hipStream_t s);
 
 } // namespace vc

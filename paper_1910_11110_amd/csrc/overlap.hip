@@ -11,7 +11,7 @@
 // induced read-write RW_s y for every y overlapping x (the extension O(M) of the
 // overlapping-array rules applied to the write's one-declaration component).  Counts
 // are scanned into positions, and the combined stream is written as sort items whose
-// payload is the primary event's index (NO_PAYLOAD for induced items).
+// payload is the primary event's index (INDUCED_BIT | trace index for induced items).
 #include <algorithm>
 
 #include "device.h"
@@ -111,7 +111,7 @@ __global__ void k_expand_count(const uint32_t *__restrict__ ev, uint64_t n, uint
 __global__ void k_expand_emit(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_arrays,
                               const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
                               const uint64_t *__restrict__ pos, uint64_t *__restrict__ items, uint64_t cap,
-                              uint32_t key_base, uint64_t payload_base, Control *ctl)
+                              uint32_t key_base, uint64_t payload_base, uint32_t trace_index, Control *ctl)
 {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -133,7 +133,7 @@ __global__ void k_expand_emit(const uint32_t *__restrict__ ev, uint64_t n, uint3
         items[p] = make_item(key_base + x, fcode(op, side), (uint32_t)(payload_base + i));
         uint64_t o = off[x];
         for (uint64_t k = 0; k < c; k++)
-            items[p + 1 + k] = make_item(key_base + nbr[o + k], fcode(OP_RWIND, side), NO_PAYLOAD);
+            items[p + 1 + k] = make_item(key_base + nbr[o + k], fcode(OP_RWIND, side), INDUCED_BIT | trace_index);
     }
 }
 
@@ -237,12 +237,12 @@ void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
 }
 
 void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
-                         uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, Control *ctl,
-                         hipStream_t s)
+                         uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, uint32_t trace_index,
+                         Control *ctl, hipStream_t s)
 {
     if (n)
         k_expand_emit<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, pos, items, cap,
-                                                                 key_base, payload_base, ctl);
+                                                                 key_base, payload_base, trace_index, ctl);
 }
 
 } // namespace vc

@@ -25,26 +25,26 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
                                                    const uint8_t *__restrict__ init, uint32_t n_ids,
                                                    uint8_t *__restrict__ out, uint8_t *__restrict__ final_out,
                                                    uint64_t *__restrict__ lb, uint32_t *__restrict__ ticket,
-                                                   Control *ctl)
+                                                   uint64_t ntiles, unsigned long long *__restrict__ ind_counts)
 {
     __shared__ uint64_t s_it[SCAN_TILE + SCAN_TILE / PAD + 1];
     __shared__ uint32_t s_f4[16], s_stuck[16];
     __shared__ uint32_t s_wagg[BLOCK / WAVE];
     __shared__ uint32_t s_tile, s_carry, s_prevkey, s_nextkey;
-    __shared__ unsigned long long s_ind;
 
-    const uint32_t tile = take_ticket(ticket, &s_tile);
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    const uint64_t base = (uint64_t)tile * SCAN_TILE;
-
     if (tid < 16) {
         s_f4[tid] = TABLE.f4[tid];
         s_stuck[tid] = TABLE.stuck[tid];
     }
+    for (;;) {
+    const uint32_t tile = take_ticket(ticket, &s_tile);
+    if (tile >= ntiles)
+        break;
+    const uint64_t base = (uint64_t)tile * SCAN_TILE;
     if (tid == 0) {
         s_prevkey = base > 0 ? item_key(items[base - 1]) : 0xFFFFFFFFu;
         s_nextkey = base + SCAN_TILE < n ? item_key(items[base + SCAN_TILE]) : 0xFFFFFFFFu;
-        s_ind = 0;
     }
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
@@ -121,7 +121,6 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
     // status entering this thread's first item (meaningful unless that item is a head)
     uint32_t state = fapply(fcompose(texc, s_carry), 0);
     uint32_t knext = tid == BLOCK - 1 ? s_nextkey : item_key(s_it[padi(first + SCAN_ITEMS)]);
-    uint32_t ind_stuck = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
         uint64_t g = base + first + j;
@@ -132,10 +131,10 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
         uint32_t flag = (s_stuck[fc[j]] >> pre) & 1u;
         state = post;
         if (MODE == SCAN_STATUS) {
-            if (pay[j] != NO_PAYLOAD)
+            if (!(pay[j] & INDUCED_BIT))
                 out[pay[j]] = (uint8_t)(post | (pre << 2) | (flag << 7));
-            else
-                ind_stuck += flag;
+            else if (flag)
+                atomicAdd(&ind_counts[pay[j] & ~INDUCED_BIT], 1ull);
         } else {
             out[pay[j]] = (uint8_t)pre;
         }
@@ -143,11 +142,8 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
         if ((kn != key[j] || g + 1 == n) && final_out && key[j] < n_ids)
             final_out[key[j]] = (uint8_t)post;
     }
-    if (MODE == SCAN_STATUS && ind_stuck)
-        atomicAdd(&s_ind, (unsigned long long)ind_stuck);
     __syncthreads();
-    if (tid == 0 && s_ind)
-        atomicAdd(&ctl->n_induced_stuck, s_ind);
+    }
 }
 
 } // namespace
@@ -155,7 +151,8 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
 size_t scan_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, SCAN_TILE) * sizeof(uint64_t); }
 
 void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, int mode, uint8_t *out,
-                    uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s)
+                    uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, unsigned long long *ind_counts,
+                    unsigned grid_cap)
 {
     if (n == 0)
         return;
@@ -163,12 +160,15 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
     launch_fill_u64(lb, 0, tiles, s);
     launch_fill_u32(&ctl->tickets[1], 0, 1, s);
+    unsigned grid = (unsigned)(tiles < grid_cap ? tiles : grid_cap);
+    if (!ind_counts)
+        ind_counts = &ctl->n_induced_stuck;
     if (mode == SCAN_STATUS)
-        k_segscan<SCAN_STATUS><<<(unsigned)tiles, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb,
-                                                                  &ctl->tickets[1], ctl);
+        k_segscan<SCAN_STATUS><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1],
+                                                      tiles, ind_counts);
     else
-        k_segscan<SCAN_PRE><<<(unsigned)tiles, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb,
-                                                               &ctl->tickets[1], ctl);
+        k_segscan<SCAN_PRE><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1], tiles,
+                                                   ind_counts);
 }
 
 } // namespace vc

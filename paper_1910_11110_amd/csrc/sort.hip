@@ -104,7 +104,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp,
 __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                      uint64_t n, int shift, int bits,
                                                      const uint32_t *__restrict__ hist, uint64_t *__restrict__ lb,
-                                                     uint32_t *__restrict__ ticket)
+                                                     uint32_t *__restrict__ ticket, uint64_t ntiles)
 {
     __shared__ uint64_t s_items[SORT_TILE];
     __shared__ uint32_t s_cnt[BLOCK / WAVE][RADIX];
@@ -113,10 +113,13 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict_
     __shared__ uint32_t s_tmp[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
 
-    const uint32_t tile = take_ticket(ticket, &s_tile);
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    const uint64_t base = (uint64_t)tile * SORT_TILE;
     const uint32_t dmask = (1u << bits) - 1u;
+    for (;;) {
+    const uint32_t tile = take_ticket(ticket, &s_tile);
+    if (tile >= ntiles)
+        break;
+    const uint64_t base = (uint64_t)tile * SORT_TILE;
 
     for (int i = tid; i < (BLOCK / WAVE) * RADIX; i += BLOCK)
         (&s_cnt[0][0])[i] = 0;
@@ -210,6 +213,8 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict_
             out[(uint64_t)(s_gbase[dd] + pos)] = x;
         }
     }
+    __syncthreads();
+    }
 }
 
 __global__ void k_make_items_events(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
@@ -278,11 +283,13 @@ size_t sort_scratch_bytes(uint64_t n)
 }
 
 uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *scratch, Control *ctl,
-                     hipStream_t s)
+                     hipStream_t s, const SortTuning *tune)
 {
     if (n <= 1 || key_bits <= 0)
         return a;
-    int passes = (key_bits + RADIX_BITS_MAX - 1) / RADIX_BITS_MAX;
+    int max_bits = tune && tune->max_bits >= 4 && tune->max_bits <= RADIX_BITS_MAX ? tune->max_bits : RADIX_BITS_MAX;
+    unsigned grid_cap = tune && tune->grid_cap ? tune->grid_cap : (1u << 30);
+    int passes = (key_bits + max_bits - 1) / max_bits;
     int bits = (key_bits + passes - 1) / passes;
     SortScratch *sc = reinterpret_cast<SortScratch *>(scratch);
     uint64_t *lb = reinterpret_cast<uint64_t *>(sc + 1);
@@ -294,7 +301,8 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
         launch_fill_u64(lb, 0, tiles * RADIX, s);
         uint32_t *ticket = &ctl->tickets[0];
         launch_fill_u32(ticket, 0, 1, s);
-        k_sort_pass<<<(unsigned)tiles, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket);
+        unsigned grid = (unsigned)(tiles < grid_cap ? tiles : grid_cap);
+        k_sort_pass<<<grid, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket, tiles);
         uint64_t *t = src;
         src = dst;
         dst = t;

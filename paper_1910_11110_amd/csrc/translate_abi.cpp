@@ -1,0 +1,245 @@
+// translate_abi.cpp -- vc_translate: declarations -> translated trace (+ optional check).
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <algorithm>
+
+#include "abi_internal.h"
+#include "internal.h"
+
+using namespace vc;
+
+namespace {
+
+int copy_in(const void *host, size_t bytes, void **dev)
+{
+    hipError_t e = hipMalloc(dev, bytes ? bytes : 8);
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "hipMalloc(translation input)");
+    if (bytes && (e = hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice)) != hipSuccess)
+        return vc_hip_fail(e, "hipMemcpy(translation input)");
+    return VC_OK;
+}
+
+int validate_host(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
+                  const uint64_t *body_off, const uint32_t *body)
+{
+    if (comp_off[0] != 0)
+        return vc_fail(VC_EINVAL, "vc_translate: comp_off[0] must be 0");
+    for (uint64_t c = 0; c < n_comp; c++)
+        if (comp_off[c + 1] < comp_off[c])
+            return vc_fail(VC_EINVAL, "vc_translate: comp_off decreases at component %llu", (unsigned long long)c);
+    uint64_t n_decl = comp_off[n_comp];
+    for (uint64_t d = 0; d < n_decl; d++) {
+        uint32_t w = decls[d];
+        if ((w & 0xF4000000u) != 0 || ((w >> 24) & 3u) > 2u || (w & 0xFFFFFFu) >= n_vars)
+            return vc_fail(VC_EINVAL, "vc_translate: malformed declaration 0x%08x at index %llu", w,
+                           (unsigned long long)d);
+    }
+    if (body_off) {
+        if (body_off[0] != 0)
+            return vc_fail(VC_EINVAL, "vc_translate: body_off[0] must be 0");
+        for (uint64_t c = 0; c < n_comp; c++)
+            if (body_off[c + 1] < body_off[c])
+                return vc_fail(VC_EINVAL, "vc_translate: body_off decreases at component %llu",
+                               (unsigned long long)c);
+        uint64_t nb = body_off[n_comp];
+        for (uint64_t j = 0; j < nb; j++) {
+            uint32_t e = body[j];
+            if ((e >> 28) != 0 || ((e >> 24) & 7u) > 4u || (e & 0xFFFFFFu) >= n_vars)
+                return vc_fail(VC_EINVAL, "vc_translate: malformed body event 0x%08x at index %llu", e,
+                               (unsigned long long)j);
+        }
+    }
+    return VC_OK;
+}
+
+} // namespace
+
+// Re-runs the translation recorded in t (inputs in t->tr) and, if requested, the check.
+int translate_enqueue(vc_trace *t, hipStream_t s)
+{
+    TranslateState &tr = *t->tr;
+    int r;
+    uint64_t n_decl = tr.n_decl, n_comp = tr.n_comp;
+    // counts and positions of each component's translated events
+    if ((r = devbuf_reserve(tr.cnt, (n_comp ? n_comp : 1) * 4)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(tr.pos, (n_comp + 1) * 8)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(tr.pre_abs, n_decl ? n_decl : 1)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(tr.items_a, (n_decl ? n_decl : 1) * 8)) != VC_OK)
+        return r;
+    if ((r = devbuf_reserve(tr.items_b, (n_decl ? n_decl : 1) * 8)) != VC_OK)
+        return r;
+    size_t sc = std::max({ sort_scratch_bytes(n_decl), scan_scratch_bytes(n_decl), excl_scan_scratch_bytes(n_comp) });
+    if ((r = devbuf_reserve(tr.scratch, sc)) != VC_OK)
+        return r;
+    launch_reset_control(tr.ctl, s);
+    launch_translate_count(tr.comp_off, n_comp, tr.decls, n_decl, tr.body_off, (uint32_t *)tr.cnt.p, tr.ctl, s);
+    launch_excl_scan((uint32_t *)tr.cnt.p, n_comp, (uint64_t *)tr.pos.p, nullptr, tr.scratch.p, &tr.ctl->tickets[4], s);
+    uint64_t total = 0;
+    hipError_t e = hipMemcpyAsync(&total, (uint64_t *)tr.pos.p + n_comp, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "translation size");
+    if (total >= (1ull << 31))
+        return vc_fail(VC_EINVAL, "vc_translate: translated trace of %llu events exceeds 2^31 - 1",
+                       (unsigned long long)total);
+    // translated events are the trace's own event buffer
+    if (!t->events || total > t->events_cap) {
+        if (t->events)
+            (void)hipFree(t->events);
+        t->events = nullptr;
+        if ((e = hipMalloc(&t->events, (total ? total : 1) * 4)) != hipSuccess)
+            return vc_hip_fail(e, "hipMalloc(translated events)");
+        t->events_cap = total;
+        t->own_events = true;
+    }
+    t->n = total;
+    // status of each declaration's abstract variable before it (segmented scan)
+    launch_make_items_decls(tr.decls, n_decl, tr.n_vars, (uint64_t *)tr.items_a.p, tr.ctl, s);
+    uint64_t *sorted = sort_items((uint64_t *)tr.items_a.p, (uint64_t *)tr.items_b.p, n_decl,
+                                  (int)key_bits_for(tr.n_vars), tr.scratch.p, tr.ctl, s);
+    launch_segscan(sorted, n_decl, nullptr, tr.n_vars, SCAN_PRE, (uint8_t *)tr.pre_abs.p, nullptr, tr.scratch.p,
+                   tr.ctl, s);
+    launch_translate_emit(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, tr.body_off,
+                          tr.body, (uint64_t *)tr.pos.p, t->events, tr.ctl, s);
+    return VC_OK;
+}
+
+extern "C" int vc_translate(vc_ctx *c, const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls,
+                            uint32_t n_vars, const uint64_t *body_off, const uint32_t *body, uint32_t flags,
+                            vc_trace **out)
+{
+    if (!c || !out || !comp_off)
+        return vc_fail(VC_EINVAL, "vc_translate: NULL argument");
+    if (n_vars == 0 || (uint64_t)n_vars * 2 > (1u << 24))
+        return vc_fail(VC_EINVAL, "vc_translate: n_vars %u must be in [1, 2^23]", n_vars);
+    if (!body_off && body)
+        return vc_fail(VC_EINVAL, "vc_translate: body given without body_off");
+    (void)hipSetDevice(c->device);
+    bool dev = flags & VC_DEVICE_INPUT;
+    uint64_t n_decl = 0, n_body = 0;
+    if (dev) {
+        hipError_t e = hipMemcpy(&n_decl, comp_off + n_comp, 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && body_off)
+            e = hipMemcpy(&n_body, body_off + n_comp, 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "vc_translate: reading sizes");
+    } else {
+        int r = validate_host(comp_off, n_comp, decls, n_vars, body_off, body);
+        if (r != VC_OK)
+            return r;
+        n_decl = comp_off[n_comp];
+        n_body = body_off ? body_off[n_comp] : 0;
+    }
+    if (n_decl >= (1ull << 32))
+        return vc_fail(VC_EINVAL, "vc_translate: %llu declarations exceed 2^32 - 1", (unsigned long long)n_decl);
+    if (n_decl && !decls)
+        return vc_fail(VC_EINVAL, "vc_translate: decls is NULL");
+    if (n_body && !body)
+        return vc_fail(VC_EINVAL, "vc_translate: body is NULL");
+
+    vc_trace *t = new vc_trace();
+    t->ctx = c;
+    t->n_ids = 2 * n_vars;
+    t->tr = new TranslateState();
+    TranslateState &tr = *t->tr;
+    tr.n_comp = n_comp;
+    tr.n_decl = n_decl;
+    tr.n_vars = n_vars;
+    tr.check = flags & VC_TRANSLATE_CHECK;
+    int r = VC_OK;
+    hipError_t e;
+    if ((e = hipMalloc(&t->ctl, sizeof(Control))) != hipSuccess)
+        r = vc_hip_fail(e, "hipMalloc(control)");
+    if (r == VC_OK && (e = hipMalloc(&tr.ctl, sizeof(Control))) != hipSuccess)
+        r = vc_hip_fail(e, "hipMalloc(control)");
+    if (r == VC_OK) {
+        if (dev) {
+            tr.comp_off = const_cast<uint64_t *>(comp_off);
+            tr.decls = const_cast<uint32_t *>(decls);
+            tr.body_off = const_cast<uint64_t *>(body_off);
+            tr.body = const_cast<uint32_t *>(body);
+            tr.own_inputs = false;
+        } else {
+            tr.own_inputs = true;
+            void *p = nullptr;
+            r = copy_in(comp_off, (n_comp + 1) * 8, &p);
+            tr.comp_off = (uint64_t *)p;
+            if (r == VC_OK) {
+                r = copy_in(decls, n_decl * 4, &p);
+                tr.decls = (uint32_t *)p;
+            }
+            if (r == VC_OK && body_off) {
+                r = copy_in(body_off, (n_comp + 1) * 8, &p);
+                tr.body_off = (uint64_t *)p;
+                if (r == VC_OK) {
+                    r = copy_in(body, n_body * 4, &p);
+                    tr.body = (uint32_t *)p;
+                }
+            }
+        }
+    }
+    if (r == VC_OK)
+        r = vc_translate_run(t);
+    if (r != VC_OK) {
+        vc_trace_free(t);
+        return r;
+    }
+    *out = t;
+    return VC_OK;
+}
+
+extern "C" int vc_translate_run(vc_trace *t)
+{
+    if (!t || !t->tr)
+        return vc_fail(VC_EINVAL, "vc_translate_run: not a translated trace");
+    vc_ctx *c = t->ctx;
+    (void)hipSetDevice(c->device);
+    int r = translate_enqueue(t, c->stream);
+    if (r != VC_OK)
+        return r;
+    t->translate_pending = true;
+    if (t->tr->check) {
+        if ((r = enqueue_check(t, c->stream)) != VC_OK)
+            return r;
+        t->check_pending = true;
+        t->checked = false;
+    }
+    if (!t->pending) {
+        t->pending = true;
+        c->pending.push_back(t);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "kernel launch");
+    return VC_OK;
+}
+
+void translate_release(vc_trace *t)
+{
+    if (!t->tr)
+        return;
+    TranslateState &tr = *t->tr;
+    if (tr.own_inputs) {
+        if (tr.comp_off) (void)hipFree(tr.comp_off);
+        if (tr.decls) (void)hipFree(tr.decls);
+        if (tr.body_off) (void)hipFree(tr.body_off);
+        if (tr.body) (void)hipFree(tr.body);
+    }
+    if (tr.ctl)
+        (void)hipFree(tr.ctl);
+    devbuf_free(tr.cnt);
+    devbuf_free(tr.pos);
+    devbuf_free(tr.pre_abs);
+    devbuf_free(tr.items_a);
+    devbuf_free(tr.items_b);
+    devbuf_free(tr.scratch);
+    delete t->tr;
+    t->tr = nullptr;
+}

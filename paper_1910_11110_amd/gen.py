@@ -43,12 +43,52 @@ MODE_R, MODE_W, MODE_RW = 0, 1, 2
 CPU, GPU = 0, 1
 
 
-def _mix64(z: np.ndarray) -> np.ndarray:
-    z = np.asarray(z, dtype=np.uint64)
+def _mix64_inplace(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser, in place on a uint64 array."""
+    t = np.empty_like(z)
     with np.errstate(over="ignore"):
-        z = (z ^ (z >> np.uint64(30))) * _M1
-        z = (z ^ (z >> np.uint64(27))) * _M2
-    return z ^ (z >> np.uint64(31))
+        np.right_shift(z, np.uint64(30), out=t)
+        z ^= t
+        z *= _M1
+        np.right_shift(z, np.uint64(27), out=t)
+        z ^= t
+        z *= _M2
+        np.right_shift(z, np.uint64(31), out=t)
+        z ^= t
+    return z
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    return _mix64_inplace(np.array(z, dtype=np.uint64, copy=True))
+
+
+_POOL = None
+_CHUNK = 1 << 22
+
+
+def _pool():
+    global _POOL
+    if _POOL is None:
+        import concurrent.futures as cf
+        import os
+        _POOL = cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1))
+    return _POOL
+
+
+def _chunked(n: int, fn, out: np.ndarray) -> np.ndarray:
+    """Fills out[a:b] = fn(a, b) over chunks, in parallel (numpy releases the GIL)."""
+    if n <= _CHUNK:
+        if n:
+            out[:n] = fn(0, n)
+        return out
+    spans = [(a, min(n, a + _CHUNK)) for a in range(0, n, _CHUNK)]
+
+    def run(ab):
+        a, b = ab
+        out[a:b] = fn(a, b)
+
+    list(_pool().map(run, spans))
+    return out
 
 
 def _stream_base(seed: int, stream: int) -> np.uint64:
@@ -61,9 +101,15 @@ def _stream_base(seed: int, stream: int) -> np.uint64:
 def draws(seed: int, stream: int, start: int, count: int) -> np.ndarray:
     """``count`` 64-bit draws of stream (seed, stream), starting at draw ``start``."""
     base = _stream_base(seed, stream)
-    idx = np.arange(start + 1, start + 1 + count, dtype=np.uint64)
-    with np.errstate(over="ignore"):
-        return _mix64(base + idx * GAMMA)
+
+    def fn(a, b):
+        z = np.arange(start + a + 1, start + b + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z *= GAMMA
+            z += base
+        return _mix64_inplace(z)
+
+    return _chunked(count, fn, np.empty(count, dtype=np.uint64))
 
 
 def draws_at(seed: int, stream: int, idx: np.ndarray) -> np.ndarray:
@@ -130,8 +176,31 @@ def zipf_cdf(n_vars: int, s: float) -> np.ndarray:
         c = np.cumsum(w)
         c /= c[-1]
         c[-1] = 1.0
-        _zipf_cache[key] = c
-    return _zipf_cache[key]
+        guide_n = 1 << 22
+        guide = np.searchsorted(c, np.arange(guide_n, dtype=np.float64) / guide_n, side="right")
+        _zipf_cache[key] = (c, guide)
+    return _zipf_cache[key][0]
+
+
+def zipf_inverse(u: np.ndarray, n_vars: int, s: float) -> np.ndarray:
+    """Inverse CDF: the smallest k with cdf[k] > u (searchsorted side='right'), found
+    from a guide table and a short forward walk; identical to a binary search."""
+    zipf_cdf(n_vars, s)
+    c, guide = _zipf_cache[(n_vars, s)]
+    gn = guide.size
+
+    def fn(a, b):
+        uu = u[a:b]
+        k = guide[np.minimum((uu * gn).astype(np.int64), gn - 1)]
+        while True:
+            k_ok = np.minimum(k, n_vars - 1)
+            step = (c[k_ok] <= uu) & (k < n_vars - 1)
+            if not step.any():
+                break
+            k = k + step
+        return np.minimum(k, n_vars - 1)
+
+    return _chunked(u.size, fn, np.empty(u.size, dtype=np.int64))
 
 
 @dataclass
@@ -152,27 +221,25 @@ def component_trace(n_comp: int, n_vars: int, seed: int, kmax: int = 8, zipf_s: 
     declaration gets mode R/W/RW with probabilities ``p_modes``; each component is
     placed on CPU or GPU with p = 0.5."""
     assert kmax <= n_vars
-    cdf = zipf_cdf(n_vars, zipf_s)
     k = below(draws(seed, S_K, 0, n_comp), kmax) + 1
-    ids = np.empty((n_comp, kmax), dtype=np.int64)
-    col_u = unit(draws(seed, S_ZIPF, 0, n_comp * kmax)).reshape(n_comp, kmax)
-    ids[:] = np.minimum(np.searchsorted(cdf, col_u, side="right"), n_vars - 1)
-    del col_u
+    # column j holds the j-th declared variable of every component
+    cols = zipf_inverse(unit(draws(seed, S_ZIPF, 0, n_comp * kmax)), n_vars, zipf_s).reshape(n_comp, kmax).T.copy()
     attempt = 1
     for j in range(1, kmax):
-        live = k > j
-        while True:
-            dup = np.zeros(n_comp, dtype=bool)
+        # rows whose j-th draw repeats an earlier one are redrawn until distinct
+        rows = np.nonzero(k > j)[0]
+        while rows.size:
+            cj = cols[j, rows]
+            dup = np.zeros(rows.size, dtype=bool)
             for i in range(j):
-                dup |= ids[:, j] == ids[:, i]
-            dup &= live
-            rows = np.nonzero(dup)[0]
+                dup |= cj == cols[i, rows]
+            rows = rows[dup]
             if rows.size == 0:
                 break
-            # redraws come from a per-attempt stream, indexed by (row, column)
             u = unit(draws_at(seed, S_ZIPF + 1000 * attempt, rows.astype(np.uint64) * np.uint64(kmax) + np.uint64(j)))
-            ids[rows, j] = np.minimum(np.searchsorted(cdf, u, side="right"), n_vars - 1)
+            cols[j, rows] = zipf_inverse(u, n_vars, zipf_s)
             attempt += 1
+    ids = cols.T
     mask = np.arange(kmax)[None, :] < k[:, None]
     var = ids[mask]
     n_decl = var.size

@@ -1,0 +1,136 @@
+"""Parity of the translation of access-mode declarations (HIP path) with the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1910_11110_amd import gen
+from tests.helpers import decl, ev, load_yaml, parse_events
+from tests.test_oracle_pins import _components
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1910_11110_amd import vcheck as V
+    c = V.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_translate(ctx, comp_off, decls, n_vars, body_off=None, body=None, check=True):
+    from paper_1910_11110_amd import vcheck as V
+    t = V.translate(ctx, comp_off, decls, n_vars, body_off, body, check=check)
+    ctx.sync()
+    return t
+
+
+def assert_translation(ctx, comp_off, decls, n_vars, body_off=None, body=None, label=""):
+    say(f"[translate] {label} comps={len(comp_off) - 1} decls={len(decls)} n_vars={n_vars}")
+    t = gpu_translate(ctx, comp_off, decls, n_vars, body_off, body)
+    ref_tr = O.translate(comp_off, decls, n_vars, body_off, body)
+    got = t.events()
+    assert got.size == ref_tr.size, f"{label}: {got.size} vs {ref_tr.size} events"
+    if not np.array_equal(got, ref_tr):
+        bad = np.nonzero(got != ref_tr)[0]
+        raise AssertionError(f"{label}: translated trace differs at {bad.size} events, first {bad[0]}: "
+                             f"gpu {got[bad[0]]:#x} oracle {ref_tr[bad[0]]:#x}")
+    ref = O.check(ref_tr, 2 * n_vars)
+    st = t.status()
+    assert np.array_equal(st, ref.status), f"{label}: status differs"
+    assert np.array_equal(t.final(), ref.final), f"{label}: final differs"
+    v = t.violations()
+    assert v.total == ref.violations.size and np.array_equal(v.indices, ref.violations) and v.first == ref.first
+    t.free()
+    return ref
+
+
+@pytest.mark.parametrize("ex", load_yaml("translation_examples.yaml"), ids=lambda e: e["name"])
+def test_translation_worked_examples(ctx, ex):
+    ids = {v: i for i, v in enumerate(ex["vars"])}
+    co, de, nv, bo, bd = _components(ex, ids)
+    all_ids = dict(ids)
+    all_ids.update({v + "#": nv + i for v, i in ids.items()})
+    t = gpu_translate(ctx, co, de, nv, bo, bd)
+    assert list(t.events()) == list(parse_events(ex["translated"], all_ids))
+    assert list(t.violations().indices) == ex["stuck"]
+    t.free()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_translation_small_canonical(ctx, seed):
+    ct = gen.component_trace(5000, 64, seed)
+    ref = assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, label=f"small seed {seed}")
+    assert ref.violations.size == 0  # Theorem 2 on well-declared programs
+
+
+@pytest.mark.parametrize("n_comp,n_vars", [(1, 1), (3, 2), (4097, 8), (70_000, 1 << 12), (300_001, 1 << 20)])
+def test_translation_shapes(ctx, n_comp, n_vars):
+    ct = gen.component_trace(n_comp, n_vars, n_comp % 11, kmax=min(8, n_vars))
+    assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, label=f"{n_comp}x{n_vars}")
+
+
+def test_translation_empty_components(ctx):
+    co = np.array([0, 0, 2, 2, 3, 3], np.uint64)
+    de = np.array([decl("R", "GPU", 0), decl("W", "CPU", 1), decl("RW", "GPU", 1)], np.uint32)
+    assert_translation(ctx, co, de, 2, label="empty components")
+
+
+def test_translation_explicit_bodies(ctx):
+    """Random (often ill-declared) explicit bodies: violations appear and must match."""
+    ct = gen.component_trace(20_000, 128, 7)
+    n_comp = ct.n_comp
+    blen = gen.below(gen.draws(7, 200, 0, n_comp), 5)
+    body_off = np.zeros(n_comp + 1, np.uint64)
+    body_off[1:] = np.cumsum(blen)
+    nb = int(body_off[-1])
+    body = gen.plain_events(nb, 128, 7)
+    ref = assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, body_off, body, label="explicit bodies")
+    assert ref.violations.size > 0
+
+
+def test_translation_device_input_and_rerun(ctx):
+    """Declarations resident on the device; re-running the translation reuses every buffer
+    and gives the same bytes."""
+    import torch
+    from paper_1910_11110_amd import vcheck as V
+    ct = gen.component_trace(200_000, 1 << 14, 3)
+    co = torch.from_numpy(ct.comp_off.view(np.int64)).cuda()
+    de = torch.from_numpy(ct.decls.view(np.int32)).cuda()
+    torch.cuda.synchronize()
+    t = V.translate(ctx, co, de, ct.n_vars, check=True)
+    ctx.sync()
+    ref_tr = O.translate(ct.comp_off, ct.decls, ct.n_vars)
+    ref = O.check(ref_tr, 2 * ct.n_vars)
+    for rep in range(3):
+        say(f"[translate] device input run {rep}")
+        assert np.array_equal(t.events(), ref_tr)
+        assert np.array_equal(t.status(), ref.status)
+        assert np.array_equal(t.final(), ref.final)
+        V._check(V.lib().vc_translate_run(t.h))
+        ctx.sync()
+    t.free()
+
+
+def test_translation_malformed_declaration(ctx):
+    from paper_1910_11110_amd import vcheck as V
+    co = np.array([0, 2], np.uint64)
+    de = np.array([decl("R", "CPU", 0), 3 << 24], np.uint32)  # mode 3 does not exist
+    with pytest.raises(V.VCError) as ex:
+        V.translate(ctx, co, de, 4)
+    assert ex.value.code == V.VC_EINVAL and "index 1" in str(ex.value)
+
+
+def test_translation_component_workload_full_size(ctx):
+    """The component workload at full size: 2^23 components over 2^20 variables."""
+    say("[translate] generating 2^23 components")
+    ct = gen.component_trace(1 << 23, 1 << 20, 0)
+    ref = assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, label="full 2^23")
+    assert ref.violations.size == 0
