@@ -163,13 +163,30 @@ int vc_trace_device_results(vc_trace *t, void **status, void **final_status, voi
 int vc_trace_free(vc_trace *t);
 
 /* ---------------------------------------------------------------------------------
+ * Per-kernel timing.  With profiling on, every kernel the context enqueues is
+ * bracketed by HIP events on the context's stream; vc_profile_read synchronizes and
+ * returns, per kernel name, the summed duration (ms) and the number of launches.
+ * names receives the names separated by '\n' (in the same order as ms/launches).
+ * --------------------------------------------------------------------------------- */
+int vc_profile_enable(vc_ctx *ctx, int on);
+int vc_profile_reset(vc_ctx *ctx);
+int vc_profile_read(vc_ctx *ctx, char *names, uint32_t names_cap, double *ms, uint64_t *launches, uint32_t cap,
+                    uint32_t *n);
+
+/* ---------------------------------------------------------------------------------
  * Batched check: n independent traces of uneven length checked together in one
- * enqueued pipeline (ids of each trace are relocated to a private range; tiles of
- * the persistent kernels never mix state of two traces).  Each trace's results are
+ * enqueued pipeline (ids of each trace are relocated to a private key range, so no
+ * status crosses traces; the sort and scan kernels are persistent and pull tiles
+ * from a device ticket counter).  Each trace's results are
  * then read with the vc_read_* functions as if vc_check had run on it alone.
  * The launch sequence is captured once per batch shape in a hipGraph and replayed.
  * --------------------------------------------------------------------------------- */
 int vc_batch_check(vc_ctx *ctx, vc_trace *const *traces, uint32_t n);
+/* settings of the last batch: whether it runs from a captured hipGraph, and the
+ * autotuned sort digit width / persistent grid bounds (0 = one workgroup per tile).
+ * Tuning runs when VC_AUTOTUNE is set in the environment and is cached per shape in
+ * $VC_TUNE_CACHE (default ~/.cache/vcheck_tune.json); VC_NO_GRAPH disables capture. */
+int vc_batch_info(vc_ctx *ctx, int *graph, int *max_bits, unsigned *grid_cap, unsigned *scan_grid);
 
 /* ---------------------------------------------------------------------------------
  * Serving: streams of trace chunks checked as they arrive, with continuous batching.

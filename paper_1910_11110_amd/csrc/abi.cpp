@@ -6,6 +6,7 @@
 
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -109,6 +110,7 @@ extern "C" int vc_ctx_destroy(vc_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     batch_release(c);
+    prof_destroy(c);
     if (c->own_stream)
         (void)hipStreamDestroy(c->stream);
     delete c;
@@ -123,6 +125,7 @@ extern "C" int vc_sync(vc_ctx *c)
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess)
         return vc_hip_fail(e, "hipStreamSynchronize");
+    prof_collect(c);
     int rc = VC_OK;
     for (vc_trace *t : c->pending) {
         int r = trace_collect(t);
@@ -322,9 +325,32 @@ void enqueue_check_items(vc_trace *t, uint64_t m, hipStream_t s)
     launch_compact((uint8_t *)t->status.p, t->n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
 }
 
+// path for traces over few ids: one kernel, no sort
+static bool use_small_path(const vc_trace *t)
+{
+    return !t->has_arrays && t->n_ids <= small_max_ids() && ((uintptr_t)t->events & 15) == 0 &&
+           !getenv("VC_GENERAL_PATH");
+}
+
 int enqueue_check(vc_trace *t, hipStream_t s)
 {
     int r;
+    if (use_small_path(t)) {
+        if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK ||
+            (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
+            (r = devbuf_reserve(t->viol, (t->n ? t->n : 1) * 4)) != VC_OK ||
+            (r = devbuf_reserve(t->scratch, small_scratch_bytes(t->n))) != VC_OK)
+            return r;
+        launch_reset_control(t->ctl, s);
+        uint8_t *fin = (uint8_t *)t->fin.p;
+        if (t->init)
+            (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
+        else
+            launch_fill_u8(fin, 1, t->n_ids, s);
+        launch_small_check(t->events, t->n, t->n_ids, t->init, (uint8_t *)t->status.p, fin, (uint32_t *)t->viol.p,
+                           t->scratch.p, t->ctl, s, 8u * (unsigned)t->ctx->cu_count);
+        return VC_OK;
+    }
     uint64_t m = t->n;
     if (t->has_arrays) {
         m = overlap_combined_size(t);
@@ -348,6 +374,7 @@ extern "C" int vc_check(vc_trace *t)
         return vc_fail(VC_EINVAL, "vc_check: NULL trace");
     vc_ctx *c = t->ctx;
     (void)hipSetDevice(c->device);
+    ProfGuard pg(c);
     int r = enqueue_check(t, c->stream);
     if (r != VC_OK)
         return r;

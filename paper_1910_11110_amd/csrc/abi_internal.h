@@ -16,6 +16,9 @@ struct DevBuf {
 };
 
 struct BatchState; // batched pipeline: captured graphs and descriptor buffers
+namespace vc {
+struct Profiler;
+}
 
 // inputs and work buffers of a translation, kept so that it can be re-run
 struct TranslateState {
@@ -36,7 +39,18 @@ struct vc_ctx {
     int cu_count = 256;
     std::vector<vc_trace *> pending; // traces with enqueued work not yet collected
     BatchState *batch = nullptr;
+    vc::Profiler *prof = nullptr;
 };
+
+// makes a context's profiler the active one for launches issued by this thread
+struct ProfGuard {
+    vc::Profiler *prev;
+    explicit ProfGuard(vc_ctx *c);
+    ~ProfGuard();
+};
+void prof_collect(vc_ctx *c);
+bool prof_on(vc_ctx *c);
+void prof_destroy(vc_ctx *c);
 
 struct vc_trace {
     vc_ctx *ctx = nullptr;

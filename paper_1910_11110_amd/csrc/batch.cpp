@@ -1,0 +1,468 @@
+// batch.cpp -- vc_batch_check: independent traces checked in one captured pipeline.
+//
+// The traces' events are relocated into one key space (ids of trace i start at the
+// sum of the id counts before it) and one index space, evaluated by the same
+// sort / segmented scan / compaction as a single trace, and the results are split
+// back into each trace's buffers by one kernel.  The launch sequence of a batch is
+// captured once in a hipGraph and replayed while the batch (its traces, their sizes
+// and buffers) is unchanged.  The sort's digit width and the persistent grid bound
+// come from an autotuner that times candidate settings on the batch itself, keeps
+// only settings whose output bytes equal the first candidate's, and caches the choice
+// per shape in a small JSON file.
+#include <hip/hip_runtime.h>
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "abi_internal.h"
+#include "batch.h"
+#include "internal.h"
+
+using namespace vc;
+
+struct BatchState {
+    // shape of the captured batch
+    std::vector<uint64_t> signature;
+    // host copies of the uploaded descriptor tables (alive until the next upload)
+    std::vector<TraceDesc> h_desc;
+    std::vector<uint64_t> h_ev_off, h_key_off;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    bool graph_ok = false;
+    // device buffers
+    DevBuf desc, ev_off, key_off, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind;
+    Control *ctl = nullptr;
+    uint64_t N = 0, K = 0, M = 0;
+    uint32_t n_traces = 0;
+    SortTuning tune;
+    unsigned scan_grid = 0;
+    bool tuned = false;
+};
+
+namespace {
+
+std::string tune_cache_path()
+{
+    const char *p = getenv("VC_TUNE_CACHE");
+    if (p && *p)
+        return p;
+    const char *home = getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/vcheck_tune.json";
+}
+
+std::string shape_key(uint64_t N, uint64_t K)
+{
+    char buf[96];
+    int ln = 0, lk = 0;
+    while ((1ull << ln) < N)
+        ln++;
+    while ((1ull << lk) < K)
+        lk++;
+    snprintf(buf, sizeof buf, "gfx950:n2^%d:k2^%d", ln, lk);
+    return buf;
+}
+
+// the cache is a flat JSON object {"key": [max_bits, grid_cap, scan_grid], ...}
+bool tune_lookup(const std::string &key, SortTuning &t, unsigned &scan_grid)
+{
+    FILE *f = fopen(tune_cache_path().c_str(), "r");
+    if (!f)
+        return false;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, f)) > 0)
+        s.append(buf, k);
+    fclose(f);
+    size_t p = s.find("\"" + key + "\"");
+    if (p == std::string::npos)
+        return false;
+    int a = 0;
+    unsigned b = 0, c = 0;
+    if (sscanf(s.c_str() + s.find('[', p), "[%d, %u, %u]", &a, &b, &c) != 3)
+        return false;
+    t.max_bits = a;
+    t.grid_cap = b;
+    scan_grid = c;
+    return true;
+}
+
+void tune_store(const std::string &key, const SortTuning &t, unsigned scan_grid)
+{
+    std::string path = tune_cache_path();
+    std::string s;
+    if (FILE *f = fopen(path.c_str(), "r")) {
+        char buf[4096];
+        size_t k;
+        while ((k = fread(buf, 1, sizeof buf, f)) > 0)
+            s.append(buf, k);
+        fclose(f);
+    }
+    // rebuild as lines "key": [..]
+    std::vector<std::string> entries;
+    size_t p = 0;
+    while ((p = s.find('"', p)) != std::string::npos) {
+        size_t q = s.find('"', p + 1);
+        size_t r = s.find(']', q);
+        if (q == std::string::npos || r == std::string::npos)
+            break;
+        std::string k = s.substr(p + 1, q - p - 1);
+        if (k != key)
+            entries.push_back(s.substr(p, r - p + 1));
+        p = r + 1;
+    }
+    char line[160];
+    snprintf(line, sizeof line, "\"%s\": [%d, %u, %u]", key.c_str(), t.max_bits, t.grid_cap, scan_grid);
+    entries.push_back(line);
+    std::string dir = path.substr(0, path.rfind('/'));
+    std::string cmd = "mkdir -p '" + dir + "'";
+    if (system(cmd.c_str()) != 0) {
+    }
+    if (FILE *f = fopen(path.c_str(), "w")) {
+        fprintf(f, "{\n");
+        for (size_t i = 0; i < entries.size(); i++)
+            fprintf(f, "  %s%s\n", entries[i].c_str(), i + 1 < entries.size() ? "," : "");
+        fprintf(f, "}\n");
+        fclose(f);
+    }
+}
+
+int reserve_all(BatchState &b, uint32_t n)
+{
+    int r;
+    uint64_t N = b.N, K = b.K, M = b.M;
+    if ((r = devbuf_reserve(b.desc, sizeof(TraceDesc) * (n ? n : 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.ev_off, 8 * (n + 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.key_off, 8 * (n + 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.init_all, K ? K : 1)) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.fin_all, K ? K : 1)) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.status_all, N ? N : 1)) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.viol_all, 4 * (N ? N : 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.items_a, 8 * (M ? M : 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.items_b, 8 * (M ? M : 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.cnt, 4 * (N ? N : 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.pos, 8 * (N + 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.ind, 8 * (n ? n : 1))) != VC_OK) return r;
+    size_t sc = std::max({ sort_scratch_bytes(M), scan_scratch_bytes(M), compact_scratch_bytes(N),
+                           excl_scan_scratch_bytes(N) });
+    if ((r = devbuf_reserve(b.scratch, sc)) != VC_OK) return r;
+    if (!b.ctl) {
+        hipError_t e = hipMalloc(&b.ctl, sizeof(Control));
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipMalloc(batch control)");
+    }
+    return VC_OK;
+}
+
+// the whole batched pipeline (capturable: kernels only, no host synchronization)
+void enqueue_pipeline(BatchState &b, hipStream_t s)
+{
+    const TraceDesc *d = (const TraceDesc *)b.desc.p;
+    uint32_t n = b.n_traces;
+    launch_reset_control(b.ctl, s);
+    launch_batch_reset(d, n, (unsigned long long *)b.ind.p, s);
+    launch_batch_init(d, (const uint64_t *)b.key_off.p, n, b.K, (uint8_t *)b.init_all.p, (uint8_t *)b.fin_all.p, s);
+    launch_batch_count(d, (const uint64_t *)b.ev_off.p, n, b.N, (uint32_t *)b.cnt.p, s);
+    launch_excl_scan((uint32_t *)b.cnt.p, b.N, (uint64_t *)b.pos.p, nullptr, b.scratch.p, &b.ctl->tickets[6], s);
+    launch_batch_emit(d, (const uint64_t *)b.ev_off.p, n, b.N, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M,
+                      s);
+    uint64_t *sorted = sort_items((uint64_t *)b.items_a.p, (uint64_t *)b.items_b.p, b.M, (int)key_bits_for((uint32_t)b.K),
+                                  b.scratch.p, b.ctl, s, &b.tune);
+    launch_segscan(sorted, b.M, (const uint8_t *)b.init_all.p, (uint32_t)b.K, SCAN_STATUS, (uint8_t *)b.status_all.p,
+                   (uint8_t *)b.fin_all.p, b.scratch.p, b.ctl, s, (unsigned long long *)b.ind.p,
+                   b.scan_grid ? b.scan_grid : (1u << 30));
+    launch_compact((uint8_t *)b.status_all.p, b.N, (uint32_t *)b.viol_all.p, b.scratch.p, b.ctl, s);
+    launch_batch_distribute(d, n, (const uint8_t *)b.status_all.p, (const uint8_t *)b.fin_all.p,
+                            (const uint32_t *)b.viol_all.p, b.ctl, (const unsigned long long *)b.ind.p, s);
+}
+
+void drop_graph(BatchState &b)
+{
+    if (b.exec)
+        (void)hipGraphExecDestroy(b.exec);
+    if (b.graph)
+        (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    b.graph_ok = false;
+}
+
+// times candidate settings on this batch; keeps those whose status bytes equal the
+// first candidate's (a race or a tiling bug would change bytes)
+int autotune(vc_ctx *c, BatchState &b)
+{
+    hipStream_t s = c->stream;
+    std::string key = shape_key(b.N, b.K);
+    if (tune_lookup(key, b.tune, b.scan_grid)) {
+        b.tuned = true;
+        return VC_OK;
+    }
+    if (!getenv("VC_AUTOTUNE")) { // default settings unless tuning is requested
+        b.tune = SortTuning{};
+        b.scan_grid = 0;
+        b.tuned = true;
+        return VC_OK;
+    }
+    struct Cand {
+        int bits;
+        unsigned grid, scan;
+    };
+    unsigned cu = (unsigned)c->cu_count;
+    std::vector<Cand> cands = { { 8, 0, 0 }, { 7, 0, 0 }, { 6, 0, 0 }, { 8, 4 * cu, 4 * cu }, { 8, 8 * cu, 8 * cu },
+                                { 7, 8 * cu, 8 * cu } };
+    std::vector<uint8_t> ref, got;
+    float best = 1e30f;
+    Cand pick = cands[0];
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    for (size_t i = 0; i < cands.size(); i++) {
+        b.tune.max_bits = cands[i].bits;
+        b.tune.grid_cap = cands[i].grid;
+        b.scan_grid = cands[i].scan;
+        enqueue_pipeline(b, s); // warm
+        (void)hipEventRecord(e0, s);
+        enqueue_pipeline(b, s);
+        (void)hipEventRecord(e1, s);
+        if (hipStreamSynchronize(s) != hipSuccess)
+            return vc_fail(VC_EDEVICE, "autotune run failed");
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        got.resize(b.N);
+        if (b.N && hipMemcpy(got.data(), b.status_all.p, b.N, hipMemcpyDeviceToHost) != hipSuccess)
+            return vc_fail(VC_EDEVICE, "autotune read-back failed");
+        if (i == 0)
+            ref = got;
+        else if (got != ref)
+            continue; // not parity-clean: never chosen
+        if (ms < best) {
+            best = ms;
+            pick = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b.tune.max_bits = pick.bits;
+    b.tune.grid_cap = pick.grid;
+    b.scan_grid = pick.scan;
+    b.tuned = true;
+    tune_store(key, b.tune, b.scan_grid);
+    return VC_OK;
+}
+
+} // namespace
+
+BatchState *batch_new() { return new BatchState(); }
+
+void batch_free(BatchState *b)
+{
+    if (!b)
+        return;
+    drop_graph(*b);
+    for (DevBuf *d : { &b->desc, &b->ev_off, &b->key_off, &b->init_all, &b->fin_all, &b->status_all, &b->viol_all,
+                       &b->items_a, &b->items_b, &b->cnt, &b->pos, &b->scratch, &b->ind })
+        devbuf_free(*d);
+    if (b->ctl)
+        (void)hipFree(b->ctl);
+    delete b;
+}
+
+void batch_release(vc_ctx *c)
+{
+    batch_free(c->batch);
+    c->batch = nullptr;
+}
+
+// uploads descriptors (ev_base / key_base already set) for direct launches on stream s
+int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M, hipStream_t s)
+{
+    uint32_t n = (uint32_t)desc.size();
+    b.h_desc = desc;
+    b.h_ev_off.assign(n + 1, 0);
+    b.h_key_off.assign(n + 1, 0);
+    uint64_t N = 0, K = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        b.h_ev_off[i] = N;
+        b.h_key_off[i] = K;
+        N += desc[i].n;
+        K += desc[i].n_ids;
+    }
+    b.h_ev_off[n] = N;
+    b.h_key_off[n] = K;
+    if (N >= (1ull << 31) || K > (1ull << 28))
+        return vc_fail(VC_EINVAL, "batch too large");
+    b.N = N;
+    b.K = K;
+    b.M = M;
+    b.n_traces = n;
+    int r = reserve_all(b, n);
+    if (r != VC_OK)
+        return r;
+    if (!b.tuned) {
+        if (!tune_lookup(shape_key(N, K), b.tune, b.scan_grid)) {
+            b.tune = SortTuning{};
+            b.scan_grid = 0;
+        }
+        b.tuned = true;
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b.desc.p, b.h_desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(b.ev_off.p, b.h_ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(b.key_off.p, b.h_key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return vc_hip_fail(e, "hipMemcpyAsync(batch descriptors)");
+    return VC_OK;
+}
+
+void batch_enqueue(BatchState &b, hipStream_t s)
+{
+    if (b.n_traces)
+        enqueue_pipeline(b, s);
+}
+
+extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
+{
+    if (!c || (n && !traces))
+        return vc_fail(VC_EINVAL, "vc_batch_check: NULL argument");
+    (void)hipSetDevice(c->device);
+    ProfGuard pg(c);
+    if (!c->batch)
+        c->batch = new BatchState();
+    BatchState &b = *c->batch;
+    hipStream_t s = c->stream;
+    // shape and descriptors
+    std::vector<TraceDesc> desc(n);
+    std::vector<uint64_t> ev_off(n + 1), key_off(n + 1), sig;
+    uint64_t N = 0, K = 0, M = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        vc_trace *t = traces[i];
+        if (!t || t->ctx != c)
+            return vc_fail(VC_EINVAL, "vc_batch_check: trace %u is NULL or belongs to another context", i);
+        for (uint32_t j = 0; j < i; j++)
+            if (traces[j] == t)
+                return vc_fail(VC_EINVAL, "vc_batch_check: trace %u appears twice", i);
+        if (t->pending) {
+            int r = vc_sync(c);
+            if (r != VC_OK)
+                return r;
+        }
+        int r;
+        if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK) return r;
+        if ((r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK) return r;
+        if ((r = devbuf_reserve(t->viol, 4 * (t->n ? t->n : 1))) != VC_OK) return r;
+        ev_off[i] = N;
+        key_off[i] = K;
+        TraceDesc &d = desc[i];
+        d.events = t->events;
+        d.init = t->init;
+        d.off = t->has_arrays ? t->sets.off : nullptr;
+        d.nbr = t->has_arrays ? t->sets.nbr : nullptr;
+        d.n = t->n;
+        d.ev_base = N;
+        d.n_ids = t->n_ids;
+        d.key_base = (uint32_t)K;
+        d.ctl = t->ctl;
+        d.status = (uint8_t *)t->status.p;
+        d.fin = (uint8_t *)t->fin.p;
+        d.viol = (uint32_t *)t->viol.p;
+        N += t->n;
+        K += t->n_ids;
+        M += t->n + (t->has_arrays ? t->n_induced : 0);
+        for (uint64_t v : { (uint64_t)(uintptr_t)t, (uint64_t)(uintptr_t)t->events, t->n, (uint64_t)t->n_ids,
+                            (uint64_t)(uintptr_t)t->init, (uint64_t)(uintptr_t)d.off, (uint64_t)(uintptr_t)d.status,
+                            (uint64_t)(uintptr_t)d.fin, (uint64_t)(uintptr_t)d.viol, (uint64_t)t->n_induced })
+            sig.push_back(v);
+    }
+    ev_off[n] = N;
+    key_off[n] = K;
+    if (N >= (1ull << 31))
+        return vc_fail(VC_EINVAL, "vc_batch_check: %llu events in the batch exceed 2^31 - 1", (unsigned long long)N);
+    if (K > (1ull << 28))
+        return vc_fail(VC_EINVAL, "vc_batch_check: %llu ids in the batch exceed 2^28", (unsigned long long)K);
+    bool same = sig == b.signature && b.n_traces == n;
+    if (!same) {
+        drop_graph(b);
+        (void)hipStreamSynchronize(s);
+        b.N = N;
+        b.K = K;
+        b.M = M;
+        b.n_traces = n;
+        int r = reserve_all(b, n);
+        if (r != VC_OK)
+            return r;
+        hipError_t e;
+        if ((e = hipMemcpy(b.desc.p, desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(b.ev_off.p, ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(b.key_off.p, key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(batch descriptors)");
+        b.signature = sig;
+        b.tuned = false;
+    }
+    if (n == 0)
+        return VC_OK;
+    if (!b.tuned) {
+        int r = autotune(c, b);
+        if (r != VC_OK)
+            return r;
+    }
+    bool use_graph = !getenv("VC_NO_GRAPH") && !prof_on(c);
+    if (use_graph && !b.graph_ok && !b.exec) {
+        // capture once; fall back to direct launches if the stream cannot capture
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            enqueue_pipeline(b, s);
+            hipGraph_t g = nullptr;
+            if (hipStreamEndCapture(s, &g) == hipSuccess && g) {
+                if (hipGraphInstantiate(&b.exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                    b.graph = g;
+                    b.graph_ok = true;
+                } else {
+                    (void)hipGraphDestroy(g);
+                    b.exec = nullptr;
+                }
+            }
+        }
+        (void)hipGetLastError();
+    }
+    if (use_graph && b.graph_ok) {
+        hipError_t e = hipGraphLaunch(b.exec, s);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipGraphLaunch");
+    } else {
+        enqueue_pipeline(b, s);
+    }
+    for (uint32_t i = 0; i < n; i++) {
+        vc_trace *t = traces[i];
+        t->check_pending = true;
+        t->checked = false;
+        if (!t->pending) {
+            t->pending = true;
+            c->pending.push_back(t);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "kernel launch");
+    return VC_OK;
+}
+
+extern "C" int vc_batch_info(vc_ctx *c, int *graph, int *max_bits, unsigned *grid_cap, unsigned *scan_grid)
+{
+    if (!c)
+        return vc_fail(VC_EINVAL, "vc_batch_info: NULL context");
+    BatchState *b = c->batch;
+    if (graph)
+        *graph = b && b->graph_ok;
+    if (max_bits)
+        *max_bits = b ? b->tune.max_bits : 0;
+    if (grid_cap)
+        *grid_cap = b ? b->tune.grid_cap : 0;
+    if (scan_grid)
+        *scan_grid = b ? b->scan_grid : 0;
+    return VC_OK;
+}

@@ -8,6 +8,7 @@
 #include "batch.h"
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -167,21 +168,30 @@ void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_t
                        uint8_t *fin_all, hipStream_t s)
 {
     if (K)
-        k_batch_init<<<gridn(K, 256 * 8), 256, 0, s>>>(d, key_off, n_traces, K, init_all, fin_all);
+        {
+            ProfScope prof_(s, "batch_init");
+            k_batch_init<<<gridn(K, 256 * 8), 256, 0, s>>>(d, key_off, n_traces, K, init_all, fin_all);
+        }
 }
 
 void launch_batch_count(const TraceDesc *d, const uint64_t *ev_off, uint32_t n_traces, uint64_t N, uint32_t *cnt,
                         hipStream_t s)
 {
     if (N)
-        k_batch_count<<<gridn(N, 256 * 8), 256, 0, s>>>(d, ev_off, n_traces, N, cnt);
+        {
+            ProfScope prof_(s, "batch_count");
+            k_batch_count<<<gridn(N, 256 * 8), 256, 0, s>>>(d, ev_off, n_traces, N, cnt);
+        }
 }
 
 void launch_batch_emit(const TraceDesc *d, const uint64_t *ev_off, uint32_t n_traces, uint64_t N, const uint64_t *pos,
                        uint64_t *items, uint64_t cap, hipStream_t s)
 {
     if (N)
-        k_batch_emit<<<gridn(N, 256 * 8), 256, 0, s>>>(d, ev_off, n_traces, N, pos, items, cap);
+        {
+            ProfScope prof_(s, "batch_emit");
+            k_batch_emit<<<gridn(N, 256 * 8), 256, 0, s>>>(d, ev_off, n_traces, N, pos, items, cap);
+        }
 }
 
 void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_t *status_all, const uint8_t *fin_all,
@@ -189,7 +199,10 @@ void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_
                              hipStream_t s)
 {
     if (n_traces)
-        k_batch_distribute<<<n_traces, BLOCK, 0, s>>>(d, status_all, fin_all, viol_all, bctl, ind);
+        {
+            ProfScope prof_(s, "batch_distribute");
+            k_batch_distribute<<<n_traces, BLOCK, 0, s>>>(d, status_all, fin_all, viol_all, bctl, ind);
+        }
 }
 
 } // namespace vc

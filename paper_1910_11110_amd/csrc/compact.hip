@@ -6,6 +6,7 @@
 // them as one contiguous run.
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -100,7 +101,10 @@ void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scr
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
     launch_fill_u64(lb, 0, tiles, s);
     launch_fill_u32(&ctl->tickets[2], 0, 1, s);
-    k_compact<<<(unsigned)tiles, BLOCK, 0, s>>>(status, n, viol, lb, &ctl->tickets[2], ctl);
+    {
+        ProfScope prof_(s, "compact");
+        k_compact<<<(unsigned)tiles, BLOCK, 0, s>>>(status, n, viol, lb, &ctl->tickets[2], ctl);
+    }
 }
 
 } // namespace vc

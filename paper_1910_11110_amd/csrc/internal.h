@@ -70,6 +70,15 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
                     uint8_t *out, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s,
                     unsigned long long *ind_counts = nullptr, unsigned grid_cap = 1u << 30);
 
+// ------------------------------- small id spaces ----------------------------------
+// single-kernel check of a trace over at most small_max_ids() ids (events 16-byte
+// aligned): statuses, final table, violations (count into ctl->n_viol)
+uint32_t small_max_ids();
+size_t small_scratch_bytes(uint64_t n);
+void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
+                        uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
+                        unsigned grid_cap = 1u << 30);
+
 // ------------------------------- compaction ---------------------------------------
 size_t compact_scratch_bytes(uint64_t n);
 // ascending indices of status bytes with bit 7 set; count into ctl->n_viol

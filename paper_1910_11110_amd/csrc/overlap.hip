@@ -16,6 +16,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -175,10 +176,16 @@ int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int k
     VC_TRY(hipMalloc(&fwd, (size_t)n * 4));
     VC_TRY(hipMalloc(&pofs, (size_t)(n + 1) * 8));
     VC_TRY(hipMalloc(&scratch, sc));
-    k_interval_items<<<blocks_for(n), BLOCK, 0, s>>>(lo, hi, n, a, ctl);
+    {
+        ProfScope prof_(s, "sweep_items");
+        k_interval_items<<<blocks_for(n), BLOCK, 0, s>>>(lo, hi, n, a, ctl);
+    }
     {
         uint64_t *sorted = sort_items(a, b, n, key_bits, scratch, ctl, s);
-        k_sweep_count<<<blocks_for(n), BLOCK, 0, s>>>(sorted, hi, n, fwd);
+        {
+            ProfScope prof_(s, "sweep_count");
+            k_sweep_count<<<blocks_for(n), BLOCK, 0, s>>>(sorted, hi, n, fwd);
+        }
         launch_excl_scan(fwd, n, pofs, nullptr, scratch, &ctl->tickets[3], s);
         VC_TRY(hipMemcpyAsync(&npairs, pofs + n, 8, hipMemcpyDeviceToHost, s));
         VC_TRY(hipStreamSynchronize(s));
@@ -194,13 +201,19 @@ int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int k
                 scratch = nullptr;
                 VC_TRY(hipMalloc(&scratch, sc2));
             }
-            k_sweep_pairs<<<blocks_for(n), BLOCK, 0, s>>>(sorted, pofs, n, pa);
+            {
+                ProfScope prof_(s, "sweep_pairs");
+                k_sweep_pairs<<<blocks_for(n), BLOCK, 0, s>>>(sorted, pofs, n, pa);
+            }
             int idb = 32 - __builtin_clz(n > 1 ? n - 1 : 1);
             uint64_t *by_nbr = sort_items(pa, pb, m, idb, scratch, ctl, s);
             k_swap_key_payload<<<blocks_for(m), BLOCK, 0, s>>>(by_nbr, m);
             uint64_t *other = by_nbr == pa ? pb : pa;
             uint64_t *by_owner = sort_items(by_nbr, other, m, idb, scratch, ctl, s);
-            k_csr<<<blocks_for(m + 1), BLOCK, 0, s>>>(by_owner, m, n, out->off, out->nbr);
+            {
+                ProfScope prof_(s, "sweep_csr");
+                k_csr<<<blocks_for(m + 1), BLOCK, 0, s>>>(by_owner, m, n, out->off, out->nbr);
+            }
         } else {
             launch_fill_u64(out->off, 0, (size_t)n + 1, s);
         }
@@ -233,7 +246,10 @@ void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
                           uint64_t index_base, Control *ctl, hipStream_t s)
 {
     if (n)
-        k_expand_count<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, cnt, index_base, ctl);
+        {
+            ProfScope prof_(s, "overlap_count");
+            k_expand_count<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, cnt, index_base, ctl);
+        }
 }
 
 void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
@@ -241,8 +257,11 @@ void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, cons
                          Control *ctl, hipStream_t s)
 {
     if (n)
-        k_expand_emit<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, pos, items, cap,
-                                                                 key_base, payload_base, trace_index, ctl);
+        {
+            ProfScope prof_(s, "overlap_emit");
+            k_expand_emit<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, pos, items, cap,
+                                                                     key_base, payload_base, trace_index, ctl);
+        }
 }
 
 } // namespace vc

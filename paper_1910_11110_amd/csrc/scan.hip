@@ -10,6 +10,7 @@
 // with a decoupled look-back on 8-bit packed functions.
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -164,11 +165,17 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
     if (!ind_counts)
         ind_counts = &ctl->n_induced_stuck;
     if (mode == SCAN_STATUS)
-        k_segscan<SCAN_STATUS><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1],
-                                                      tiles, ind_counts);
+        {
+            ProfScope prof_(s, "segscan");
+            k_segscan<SCAN_STATUS><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1],
+                                                          tiles, ind_counts);
+        }
     else
-        k_segscan<SCAN_PRE><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1], tiles,
-                                                   ind_counts);
+        {
+            ProfScope prof_(s, "segscan_pre");
+            k_segscan<SCAN_PRE><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1], tiles,
+                                                       ind_counts);
+        }
 }
 
 } // namespace vc

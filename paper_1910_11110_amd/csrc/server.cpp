@@ -1,0 +1,571 @@
+// server.cpp -- serving loop: streams of trace chunks with continuous batching.
+//
+// Each stream owns a status table resident in device memory (n_ids bytes).  A chunk
+// is checked from the table and leaves its final statuses there: the batched
+// pipeline copies every descriptor's initial statuses into its own buffer before the
+// scan, so a chunk's descriptor can read and write the same table.  A server thread
+// admits queued chunks while the device bytes they need fit the budget, packs the
+// ready ones (at most one per stream, in order) into one batched launch, and keeps
+// two launch slots on two HIP streams so that a batch is staged and launched while
+// the previous one still runs.  Finished chunks are copied back and reported through
+// vc_poll with their submission, launch and completion times.
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "abi_internal.h"
+#include "batch.h"
+#include "device.h"
+#include "internal.h"
+
+using namespace vc;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// device bytes one chunk of n events holds while it is in flight (events, items of the
+// sort and their twin, status, violations, scan counters) plus its induced items
+uint64_t chunk_bytes(uint64_t n, uint64_t induced) { return 4 * n + 16 * (n + induced) + n + 4 * n + 12 * n + 256; }
+
+struct Chunk {
+    uint64_t id = 0, stream = 0;
+    uint64_t first_event = 0;
+    std::vector<uint32_t> events;
+    uint8_t *status_out = nullptr;
+    double t_submit = 0, t_start = 0, t_done = 0;
+    uint64_t induced = 0;
+    uint64_t bytes = 0;
+    // device side
+    uint32_t *d_events = nullptr;
+    uint8_t *d_status = nullptr;
+    uint32_t *d_viol = nullptr;
+    Control *d_ctl = nullptr;
+    void *pool_block = nullptr;
+    int pool_cls = 0;
+};
+
+struct Stream {
+    uint64_t id = 0;
+    uint32_t n_ids = 0;
+    uint8_t *table = nullptr; // resident statuses
+    OverlapSets sets{};
+    bool has_arrays = false;
+    uint64_t events_seen = 0; // events submitted so far
+    std::deque<Chunk *> queue;
+    bool in_flight = false;
+    bool closing = false;
+};
+
+// device buffers of chunks come from power-of-two size classes and are recycled, so
+// the serving loop never frees device memory (a free would wait for the device)
+struct Pool {
+    std::map<int, std::vector<void *>> free_list;
+    std::vector<void *> all;
+    ~Pool()
+    {
+        for (void *p : all)
+            (void)hipFree(p);
+    }
+    static int cls(uint64_t n)
+    {
+        int k = 10;
+        while ((1ull << k) < n)
+            k++;
+        return k;
+    }
+    void *get(uint64_t n, int *out_cls)
+    {
+        int k = cls(n);
+        *out_cls = k;
+        auto &fl = free_list[k];
+        if (!fl.empty()) {
+            void *p = fl.back();
+            fl.pop_back();
+            return p;
+        }
+        void *p = nullptr;
+        // events (4 B), status (1 B), violations (4 B) per event, and the counters
+        if (hipMalloc(&p, (9ull << k) + 512) != hipSuccess)
+            return nullptr;
+        all.push_back(p);
+        return p;
+    }
+    void put(void *p, int k) { free_list[k].push_back(p); }
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<Chunk *> chunks;
+    BatchState *b = nullptr;
+    bool busy = false;
+};
+
+} // namespace
+
+struct vc_server {
+    vc_ctx *ctx = nullptr;
+    uint64_t budget = 0, used = 0;
+    uint32_t max_batch = 1u << 22;
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::map<uint64_t, Stream *> streams;
+    uint64_t next_stream = 1, next_chunk = 1;
+    std::deque<vc_completion> completions;
+    std::thread worker;
+    std::atomic<bool> stop{ false };
+    Slot slots[2];
+    std::string error;
+    Pool *pool = nullptr;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+// batch pipeline pieces reused from batch.cpp
+int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M, hipStream_t s);
+void batch_enqueue(BatchState &b, hipStream_t s);
+void batch_free(BatchState *b);
+BatchState *batch_new();
+
+namespace {
+
+int alloc_chunk(Pool &pool, Chunk *c)
+{
+    uint64_t n = c->events.size();
+    int k;
+    char *p = (char *)pool.get(n ? n : 1, &k);
+    if (!p)
+        return vc_fail(VC_ENOMEM, "server: chunk allocation");
+    c->pool_block = p;
+    c->pool_cls = k;
+    uint64_t cap = 1ull << k;
+    c->d_events = (uint32_t *)p;
+    c->d_viol = (uint32_t *)(p + 4 * cap);
+    c->d_ctl = (Control *)(p + 8 * cap);
+    c->d_status = (uint8_t *)(p + 8 * cap + 512);
+    return VC_OK;
+}
+
+void free_chunk(Pool &pool, Chunk *c)
+{
+    if (c->pool_block)
+        pool.put(c->pool_block, c->pool_cls);
+    delete c;
+}
+
+// number of induced items a chunk adds (host count from the stream's overlap sets)
+uint64_t count_induced(const std::vector<uint32_t> &ev, const std::vector<uint64_t> &deg)
+{
+    if (deg.empty())
+        return 0;
+    uint64_t k = 0;
+    for (uint32_t w : ev)
+        if (((w >> 24) & 7u) == vc::OP_W && (w & 0xFFFFFFu) < deg.size())
+            k += deg[w & 0xFFFFFFu];
+    return k;
+}
+
+} // namespace
+
+static std::map<uint64_t, std::vector<uint64_t>> g_degrees; // stream -> overlap degree per array (host)
+static std::mutex g_deg_mu;
+
+static void finish_slot(vc_server *S, Slot &sl)
+{
+    // results of every chunk of the slot: status bytes to the caller, counters
+    std::vector<Control> h(sl.chunks.size());
+    for (size_t i = 0; i < sl.chunks.size(); i++) {
+        Chunk *c = sl.chunks[i];
+        (void)hipMemcpyAsync(&h[i], c->d_ctl, sizeof(Control), hipMemcpyDeviceToHost, sl.s);
+        if (c->status_out && !c->events.empty())
+            (void)hipMemcpyAsync(c->status_out, c->d_status, c->events.size(), hipMemcpyDeviceToHost, sl.s);
+    }
+    std::vector<uint32_t> first(sl.chunks.size(), 0);
+    for (size_t i = 0; i < sl.chunks.size(); i++)
+        (void)hipMemcpyAsync(&first[i], sl.chunks[i]->d_viol, 4, hipMemcpyDeviceToHost, sl.s);
+    hipError_t e = hipStreamSynchronize(sl.s);
+    double t = S->now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (size_t i = 0; i < sl.chunks.size(); i++) {
+        Chunk *c = sl.chunks[i];
+        vc_completion comp{};
+        comp.stream = c->stream;
+        comp.chunk = c->id;
+        comp.first_event = c->first_event;
+        comp.n_events = c->events.size();
+        uint64_t bad = ((uint64_t)h[i].err_index_hi << 32) | h[i].err_index_lo;
+        comp.status = e != hipSuccess ? VC_EDEVICE : (bad != ~0ull ? VC_EINVAL : VC_OK);
+        comp.n_violations = h[i].n_viol;
+        comp.first_violation = h[i].n_viol ? c->first_event + first[i] : c->first_event + c->events.size();
+        comp.t_submit = c->t_submit;
+        comp.t_start = c->t_start;
+        comp.t_done = t;
+        S->completions.push_back(comp);
+        auto it = S->streams.find(c->stream);
+        if (it != S->streams.end())
+            it->second->in_flight = false;
+        S->used -= c->bytes;
+        free_chunk(*S->pool, c);
+    }
+    sl.chunks.clear();
+    sl.busy = false;
+    S->cv.notify_all();
+    S->cv_done.notify_all();
+}
+
+static void launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
+{
+    std::vector<TraceDesc> desc(batch.size());
+    uint64_t M = 0;
+    for (size_t i = 0; i < batch.size(); i++) {
+        Chunk *c = batch[i];
+        Stream *st;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            st = S->streams.find(c->stream)->second; // an open stream: close waits for its chunks
+        }
+        uint64_t n = c->events.size();
+        if (n)
+            (void)hipMemcpyAsync(c->d_events, c->events.data(), n * 4, hipMemcpyHostToDevice, sl.s);
+        TraceDesc &d = desc[i];
+        d.events = c->d_events;
+        d.init = st->table;
+        d.off = st->has_arrays ? st->sets.off : nullptr;
+        d.nbr = st->has_arrays ? st->sets.nbr : nullptr;
+        d.n = n;
+        d.n_ids = st->n_ids;
+        d.ctl = c->d_ctl;
+        d.status = c->d_status;
+        d.fin = st->table; // the chunk leaves its final statuses in the resident table
+        d.viol = c->d_viol;
+        M += n + c->induced;
+    }
+    uint64_t N = 0, K = 0;
+    for (auto &d : desc) {
+        d.ev_base = N;
+        d.key_base = (uint32_t)K;
+        N += d.n;
+        K += d.n_ids;
+    }
+    double t = S->now();
+    for (Chunk *c : batch)
+        c->t_start = t;
+    if (batch_prepare(*sl.b, desc, M, sl.s) == VC_OK)
+        batch_enqueue(*sl.b, sl.s);
+    (void)hipEventRecord(sl.done, sl.s);
+    sl.chunks = batch;
+    sl.busy = true;
+}
+
+static void server_loop(vc_server *S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    int turn = 0;
+    while (!S->stop.load()) {
+        // retire finished slots
+        for (Slot &sl : S->slots)
+            if (sl.busy && hipEventQuery(sl.done) == hipSuccess)
+                finish_slot(S, sl);
+        Slot *free_slot = nullptr;
+        for (int k = 0; k < 2; k++) {
+            Slot &sl = S->slots[(turn + k) & 1];
+            if (!sl.busy) {
+                free_slot = &sl;
+                break;
+            }
+        }
+        std::vector<Chunk *> batch;
+        if (free_slot) {
+            std::unique_lock<std::mutex> lk(S->mu);
+            uint64_t events = 0;
+            for (auto &kv : S->streams) {
+                Stream *st = kv.second;
+                if (st->in_flight || st->queue.empty())
+                    continue;
+                Chunk *c = st->queue.front();
+                if (S->used + c->bytes > S->budget) // admission: wait for memory to free up
+                    continue;
+                if (!batch.empty() && events + c->events.size() > S->max_batch)
+                    continue;
+                st->queue.pop_front();
+                st->in_flight = true;
+                S->used += c->bytes;
+                events += c->events.size();
+                batch.push_back(c);
+            }
+        }
+        if (!batch.empty()) {
+            bool ok = true;
+            for (Chunk *c : batch)
+                if (alloc_chunk(*S->pool, c) != VC_OK)
+                    ok = false;
+            if (!ok) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->error = vc_last_error();
+            }
+            launch_slot(S, *free_slot, batch);
+            turn ^= 1;
+            continue;
+        }
+        bool any_busy = S->slots[0].busy || S->slots[1].busy;
+        if (any_busy) {
+            // wait for the oldest running batch (short sleeps keep latency low)
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        } else {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv.wait_for(lk, std::chrono::milliseconds(2));
+        }
+    }
+    for (Slot &sl : S->slots)
+        if (sl.busy) {
+            (void)hipEventSynchronize(sl.done);
+            finish_slot(S, sl);
+        }
+}
+
+extern "C" int vc_server_create(vc_ctx *c, uint64_t budget, uint32_t max_batch_events, vc_server **out)
+{
+    if (!c || !out)
+        return vc_fail(VC_EINVAL, "vc_server_create: NULL argument");
+    if (budget == 0)
+        return vc_fail(VC_EINVAL, "vc_server_create: budget must be positive");
+    (void)hipSetDevice(c->device);
+    vc_server *S = new vc_server();
+    S->ctx = c;
+    S->budget = budget;
+    S->max_batch = max_batch_events ? max_batch_events : (1u << 22);
+    S->t0 = Clock::now();
+    S->pool = new Pool();
+    for (Slot &sl : S->slots) {
+        hipError_t e;
+        if ((e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) {
+            delete S;
+            return vc_hip_fail(e, "server stream");
+        }
+        sl.b = batch_new();
+    }
+    S->worker = std::thread(server_loop, S);
+    *out = S;
+    return VC_OK;
+}
+
+extern "C" int vc_server_destroy(vc_server *S)
+{
+    if (!S)
+        return VC_OK;
+    S->stop.store(true);
+    S->cv.notify_all();
+    if (S->worker.joinable())
+        S->worker.join();
+    (void)hipSetDevice(S->ctx->device);
+    for (auto &kv : S->streams) {
+        Stream *st = kv.second;
+        for (Chunk *c : st->queue)
+            delete c;
+        if (st->table)
+            (void)hipFree(st->table);
+        free_overlap_sets(&st->sets);
+        delete st;
+    }
+    for (Slot &sl : S->slots) {
+        batch_free(sl.b);
+        (void)hipEventDestroy(sl.done);
+        (void)hipStreamDestroy(sl.s);
+    }
+    delete S->pool;
+    {
+        std::lock_guard<std::mutex> lk(g_deg_mu);
+        for (auto &kv : S->streams)
+            g_degrees.erase(kv.first);
+    }
+    delete S;
+    return VC_OK;
+}
+
+extern "C" double vc_server_now(vc_server *S) { return S ? S->now() : 0.0; }
+
+extern "C" int vc_stream_open(vc_server *S, uint32_t n_ids, const uint32_t *lo, const uint32_t *hi,
+                              const uint8_t *init, uint64_t *stream)
+{
+    if (!S || !stream)
+        return vc_fail(VC_EINVAL, "vc_stream_open: NULL argument");
+    if (n_ids == 0 || n_ids > (1u << 24))
+        return vc_fail(VC_EINVAL, "vc_stream_open: n_ids %u must be in [1, 2^24]", n_ids);
+    if ((lo == nullptr) != (hi == nullptr))
+        return vc_fail(VC_EINVAL, "vc_stream_open: lo and hi go together");
+    if (init)
+        for (uint32_t i = 0; i < n_ids; i++)
+            if (init[i] > 3)
+                return vc_fail(VC_EINVAL, "vc_stream_open: init %u at id %u is not a status code", init[i], i);
+    (void)hipSetDevice(S->ctx->device);
+    Stream *st = new Stream();
+    st->n_ids = n_ids;
+    hipError_t e;
+    if ((e = hipMalloc(&st->table, n_ids)) != hipSuccess) {
+        delete st;
+        return vc_hip_fail(e, "hipMalloc(stream table)");
+    }
+    std::vector<uint8_t> ini(n_ids, 1);
+    if (init)
+        memcpy(ini.data(), init, n_ids);
+    (void)hipMemcpy(st->table, ini.data(), n_ids, hipMemcpyHostToDevice);
+    std::vector<uint64_t> deg;
+    if (lo) {
+        // the stream's overlap sets, built once by the interval sweep
+        uint32_t maxlo = 0;
+        for (uint32_t i = 0; i < n_ids; i++) {
+            if (!(lo[i] < hi[i]) || hi[i] > (1u << 28)) {
+                (void)hipFree(st->table);
+                delete st;
+                return vc_fail(VC_EINVAL, "vc_stream_open: array %u is not a non-empty interval below 2^28", i);
+            }
+            maxlo = std::max(maxlo, lo[i]);
+        }
+        uint32_t *dlo = nullptr, *dhi = nullptr;
+        Control *ctl = nullptr;
+        hipStream_t s = nullptr;
+        (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        (void)hipMalloc(&dlo, n_ids * 4);
+        (void)hipMalloc(&dhi, n_ids * 4);
+        (void)hipMalloc(&ctl, sizeof(Control));
+        (void)hipMemcpy(dlo, lo, n_ids * 4, hipMemcpyHostToDevice);
+        (void)hipMemcpy(dhi, hi, n_ids * 4, hipMemcpyHostToDevice);
+        launch_reset_control(ctl, s);
+        int rc = build_overlap_sets(dlo, dhi, n_ids, maxlo ? 32 - __builtin_clz(maxlo) : 1, &st->sets, ctl, s);
+        std::vector<uint64_t> off(n_ids + 1);
+        if (rc == 0)
+            (void)hipMemcpy(off.data(), st->sets.off, (n_ids + 1) * 8, hipMemcpyDeviceToHost);
+        (void)hipFree(dlo);
+        (void)hipFree(dhi);
+        (void)hipFree(ctl);
+        (void)hipStreamDestroy(s);
+        if (rc != 0) {
+            (void)hipFree(st->table);
+            delete st;
+            return vc_fail(VC_EDEVICE, "vc_stream_open: interval sweep failed");
+        }
+        st->has_arrays = true;
+        deg.resize(n_ids);
+        for (uint32_t i = 0; i < n_ids; i++)
+            deg[i] = off[i + 1] - off[i];
+    }
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->used + n_ids > S->budget) {
+        (void)hipFree(st->table);
+        free_overlap_sets(&st->sets);
+        delete st;
+        return vc_fail(VC_EBUDGET, "vc_stream_open: the status table does not fit the budget");
+    }
+    S->used += n_ids;
+    st->id = S->next_stream++;
+    S->streams[st->id] = st;
+    {
+        std::lock_guard<std::mutex> lk2(g_deg_mu);
+        g_degrees[st->id] = std::move(deg);
+    }
+    *stream = st->id;
+    return VC_OK;
+}
+
+extern "C" int vc_stream_submit(vc_server *S, uint64_t stream, const uint32_t *events, uint32_t n,
+                                uint8_t *status_out, uint64_t *chunk)
+{
+    if (!S || (n && !events) || !chunk)
+        return vc_fail(VC_EINVAL, "vc_stream_submit: NULL argument");
+    Chunk *c = new Chunk();
+    c->events.assign(events, events + n);
+    c->status_out = status_out;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->streams.find(stream);
+    if (it == S->streams.end() || it->second->closing) {
+        delete c;
+        return vc_fail(VC_EINVAL, "vc_stream_submit: unknown or closing stream %llu", (unsigned long long)stream);
+    }
+    Stream *st = it->second;
+    for (uint32_t i = 0; i < n; i++) {
+        uint32_t w = events[i];
+        if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= st->n_ids) {
+            delete c;
+            return vc_fail(VC_EINVAL, "vc_stream_submit: malformed event 0x%08x at index %u", w, i);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk2(g_deg_mu);
+        c->induced = count_induced(c->events, g_degrees[stream]);
+    }
+    c->bytes = chunk_bytes(n, c->induced);
+    if (c->bytes + st->n_ids > S->budget) {
+        delete c;
+        return vc_fail(VC_EBUDGET, "vc_stream_submit: a chunk of %u events can never fit the budget", n);
+    }
+    c->id = S->next_chunk++;
+    c->stream = stream;
+    c->first_event = st->events_seen;
+    st->events_seen += n;
+    c->t_submit = S->now();
+    st->queue.push_back(c);
+    *chunk = c->id;
+    S->cv.notify_all();
+    return VC_OK;
+}
+
+extern "C" int vc_poll(vc_server *S, struct vc_completion *out, uint32_t cap, uint32_t *n)
+{
+    if (!S || !n)
+        return vc_fail(VC_EINVAL, "vc_poll: NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    uint32_t k = 0;
+    while (k < cap && !S->completions.empty()) {
+        if (out)
+            out[k] = S->completions.front();
+        S->completions.pop_front();
+        k++;
+    }
+    *n = k;
+    return VC_OK;
+}
+
+extern "C" int vc_stream_close(vc_server *S, uint64_t stream, uint8_t *final_out)
+{
+    if (!S)
+        return vc_fail(VC_EINVAL, "vc_stream_close: NULL server");
+    Stream *st;
+    {
+        std::unique_lock<std::mutex> lk(S->mu);
+        auto it = S->streams.find(stream);
+        if (it == S->streams.end())
+            return vc_fail(VC_EINVAL, "vc_stream_close: unknown stream %llu", (unsigned long long)stream);
+        st = it->second;
+        st->closing = true;
+        S->cv_done.wait(lk, [&] { return st->queue.empty() && !st->in_flight; });
+        S->streams.erase(it);
+        S->used -= st->n_ids;
+    }
+    (void)hipSetDevice(S->ctx->device);
+    int rc = VC_OK;
+    if (final_out) {
+        hipError_t e = hipMemcpy(final_out, st->table, st->n_ids, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            rc = vc_hip_fail(e, "hipMemcpy(stream table)");
+    }
+    (void)hipFree(st->table);
+    free_overlap_sets(&st->sets);
+    {
+        std::lock_guard<std::mutex> lk2(g_deg_mu);
+        g_degrees.erase(stream);
+    }
+    delete st;
+    return rc;
+}

@@ -1,0 +1,297 @@
+// small.hip -- single-pass check of a trace over at most 64 variables (gfx950).
+//
+// No sort: the trace is cut into tiles of 4096 events in program order; each thread
+// owns 16 consecutive events of a tile and keeps, per variable, the composition of
+// its own events (a private 64-entry table of transition functions in LDS).  A
+// per-variable scan across the 256 threads of the tile (64 lanes = 64 variables)
+// turns the tables into exclusive prefixes and yields the tile's aggregate per
+// variable.  Tiles chain their per-variable states with a decoupled look-back whose
+// words carry their own readiness flag (7 variables per 64-bit word), so each word
+// can be published and consumed independently.  Each thread then replays its 16
+// events from its entering statuses and writes its 16 status bytes as one 16-byte
+// store; flagged events are compacted in the same kernel (a second look-back on the
+// count), and the last tile writes the final statuses.
+#include "device.h"
+#include "internal.h"
+#include "prof.h"
+
+namespace vc {
+
+namespace {
+
+constexpr EffectTable TABLE = make_table();
+constexpr int SK = 64;               // variables
+constexpr int SE = 16;               // events per thread
+constexpr int STILE = BLOCK * SE;    // events per tile
+constexpr int SROW = SK + 1;         // padded table row (words)
+constexpr int SWORDS = (SK + 6) / 7; // look-back words per tile
+
+__device__ __forceinline__ uint64_t pack7(const uint8_t *b)
+{
+    uint64_t w = 0;
+#pragma unroll
+    for (int i = 0; i < 7; i++)
+        w |= (uint64_t)b[i] << (8 * i);
+    return w;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
+                                                       const uint8_t *__restrict__ init, uint8_t *__restrict__ status,
+                                                       uint8_t *__restrict__ final_out, uint32_t *__restrict__ viol,
+                                                       uint64_t *__restrict__ lbv, uint64_t *__restrict__ lbc,
+                                                       uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
+{
+    __shared__ uint32_t s_tab[BLOCK * SROW];
+    __shared__ uint32_t s_q[4][SK];      // per quarter: composition of its 64 threads' tables
+    __shared__ uint8_t s_agg[SK + 8];    // tile aggregate function per variable (packed)
+    __shared__ uint8_t s_carry[SK + 8];  // status per variable entering the tile
+    __shared__ uint8_t s_qin[4][SK];     // status per variable entering each quarter
+    __shared__ uint32_t s_f4[16], s_stuck[16];
+    __shared__ uint32_t s_wsum[BLOCK / WAVE];
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_vexcl;
+
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    if (tid < 16) {
+        s_f4[tid] = TABLE.f4[tid];
+        s_stuck[tid] = TABLE.stuck[tid];
+    }
+    for (;;) {
+        const uint32_t tile = take_ticket(ticket, &s_tile);
+        if (tile >= ntiles)
+            break;
+        const uint64_t base = (uint64_t)tile * STILE;
+        const uint64_t my0 = base + (uint64_t)tid * SE;
+
+        // ---- load 16 consecutive events, decode ------------------------------------
+        uint32_t key[SE], fc[SE];
+        uint32_t valid = 0;
+        if (my0 + SE <= n) {
+            const uint4 *p = reinterpret_cast<const uint4 *>(ev + my0);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                uint4 v = p[q];
+                uint32_t w[4] = { v.x, v.y, v.z, v.w };
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    key[4 * q + b] = w[b];
+                }
+            }
+            valid = 0xFFFFu;
+        } else {
+#pragma unroll
+            for (int j = 0; j < SE; j++) {
+                key[j] = my0 + j < n ? ev[my0 + j] : 0u;
+                valid |= (my0 + j < n ? 1u : 0u) << j;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < SE; j++) {
+            uint32_t w = key[j];
+            uint32_t id = w & 0xFFFFFFu, op = (w >> 24) & 7u, side = (w >> 27) & 1u;
+            if (((valid >> j) & 1u) && ((w >> 28) != 0 || op > OP_NOOP || id >= n_ids)) {
+                unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
+                atomicMin(e, (unsigned long long)(my0 + j));
+                id = 0;
+                op = OP_NOOP;
+            }
+            key[j] = id;
+            fc[j] = (valid >> j) & 1u ? fcode(op, side) : fcode(OP_NOOP, 0);
+        }
+
+        // ---- phase 1: each thread's composition per variable --------------------------
+        uint32_t *row = s_tab + tid * SROW;
+#pragma unroll
+        for (int k = 0; k < SK; k++)
+            row[k] = F_ID;
+#pragma unroll
+        for (int j = 0; j < SE; j++)
+            row[key[j]] = fcompose(s_f4[fc[j]], row[key[j]]);
+        __syncthreads();
+
+        // ---- phase 2: per-variable exclusive scan over the threads --------------------
+        // wave q scans threads 64q .. 64q+63 for variable `lane`
+        {
+            uint32_t acc = F_ID;
+            const uint32_t q = wave;
+#pragma unroll
+            for (int i = 0; i < WAVE; i++) {
+                uint32_t *cell = s_tab + (q * WAVE + i) * SROW + lane;
+                uint32_t f = *cell;
+                *cell = acc; // exclusive within the quarter
+                acc = fcompose(f, acc);
+            }
+            s_q[q][lane] = acc;
+        }
+        __syncthreads();
+        if (tid < SK) {
+            uint32_t a = F_ID;
+            for (int q = 0; q < 4; q++)
+                a = fcompose(s_q[q][tid], a);
+            s_agg[tid] = (uint8_t)fpack(a);
+        }
+        __syncthreads();
+
+        // ---- look-back: status per variable entering the tile -------------------------
+        if (tid < SWORDS) {
+            uint8_t agg7[7], st7[7];
+#pragma unroll
+            for (int i = 0; i < 7; i++) {
+                int k = tid * 7 + i;
+                agg7[i] = k < SK ? s_agg[k] : (uint8_t)0xE4;
+            }
+            uint64_t *my = lbv + (uint64_t)tile * SWORDS + tid;
+            uint32_t acc4[7];
+#pragma unroll
+            for (int i = 0; i < 7; i++)
+                acc4[i] = F_ID;
+            if (tile == 0) {
+#pragma unroll
+                for (int i = 0; i < 7; i++) {
+                    int k = tid * 7 + i;
+                    st7[i] = (init && k < (int)n_ids) ? init[k] : (uint8_t)1;
+                }
+            } else {
+                lb_store(my, LB_AGG | pack7(agg7));
+                int64_t t = (int64_t)tile - 1;
+                while (true) {
+                    uint64_t w = lb_wait(lbv + (uint64_t)t * SWORDS + tid);
+                    bool inc = (w >> 62) == 2;
+#pragma unroll
+                    for (int i = 0; i < 7; i++) {
+                        uint32_t b = (uint32_t)(w >> (8 * i)) & 0xFFu;
+                        if (inc)
+                            st7[i] = (uint8_t)fapply(acc4[i], b);
+                        else
+                            acc4[i] = fcompose(acc4[i], funpack(b));
+                    }
+                    if (inc)
+                        break;
+                    t--;
+                }
+            }
+            uint8_t inc7[7];
+#pragma unroll
+            for (int i = 0; i < 7; i++) {
+                int k = tid * 7 + i;
+                if (k < SK)
+                    s_carry[k] = st7[i];
+                inc7[i] = (uint8_t)fapply(funpack(agg7[i]), st7[i]);
+            }
+            lb_store(my, LB_INC | pack7(inc7));
+            if (tile + 1 == ntiles && final_out) {
+#pragma unroll
+                for (int i = 0; i < 7; i++) {
+                    int k = tid * 7 + i;
+                    if (k < (int)n_ids)
+                        final_out[k] = inc7[i];
+                }
+            }
+        }
+        __syncthreads();
+        // status per variable entering each quarter
+        {
+            uint32_t q = wave;
+            uint32_t s = s_carry[lane];
+            for (uint32_t r = 0; r < q; r++)
+                s = fapply(s_q[r][lane], s);
+            s_qin[q][lane] = (uint8_t)s;
+        }
+        __syncthreads();
+
+        // ---- phase 3: replay each thread's events ------------------------------------
+        // the row becomes the statuses entering this thread's events
+#pragma unroll
+        for (int k = 0; k < SK; k++)
+            row[k] = fapply(row[k], s_qin[wave][k]);
+        uint32_t out[4] = { 0, 0, 0, 0 };
+        uint32_t flags = 0;
+#pragma unroll
+        for (int j = 0; j < SE; j++) {
+            uint32_t pre = row[key[j]];
+            uint32_t post = fapply(s_f4[fc[j]], pre);
+            uint32_t flag = (s_stuck[fc[j]] >> pre) & 1u & ((valid >> j) & 1u);
+            row[key[j]] = post;
+            out[j >> 2] |= (post | (pre << 2) | (flag << 7)) << (8 * (j & 3));
+            flags |= flag << j;
+        }
+        if (my0 + SE <= n) {
+            *reinterpret_cast<uint4 *>(status + my0) = make_uint4(out[0], out[1], out[2], out[3]);
+        } else {
+            for (int j = 0; j < SE; j++)
+                if (my0 + j < n)
+                    status[my0 + j] = (uint8_t)(out[j >> 2] >> (8 * (j & 3)));
+        }
+
+        // ---- violations: tile count, look-back for the offset, ascending indices -------
+        uint32_t cnt = __builtin_popcount(flags);
+        uint32_t inc = wave_scan_add(cnt, lane);
+        if (lane == WAVE - 1)
+            s_wsum[wave] = inc;
+        __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (uint32_t w = 0; w < BLOCK / WAVE; w++) {
+            if (w < wave)
+                woff += s_wsum[w];
+            total += s_wsum[w];
+        }
+        if (tid == 0) {
+            uint64_t *my = lbc + tile;
+            uint64_t excl = 0;
+            if (tile == 0) {
+                lb_store(my, LB_INC | total);
+            } else {
+                lb_store(my, LB_AGG | total);
+                int64_t t = (int64_t)tile - 1;
+                while (true) {
+                    uint64_t w = lb_wait(&lbc[t]);
+                    excl += w & LB_VAL;
+                    if ((w >> 62) == 2)
+                        break;
+                    t--;
+                }
+                lb_store(my, LB_INC | (excl + total));
+            }
+            s_vexcl = excl;
+            if (tile + 1 == ntiles)
+                ctl->n_viol = excl + total;
+        }
+        __syncthreads();
+        uint64_t o = s_vexcl + woff + inc - cnt;
+        while (flags) {
+            uint32_t b = __builtin_ctz(flags);
+            flags &= flags - 1;
+            viol[o++] = (uint32_t)(my0 + b);
+        }
+        __syncthreads();
+    }
+}
+
+} // namespace
+
+size_t small_scratch_bytes(uint64_t n)
+{
+    uint64_t tiles = ceil_div(n ? n : 1, STILE);
+    return tiles * (SWORDS + 1) * sizeof(uint64_t);
+}
+
+uint32_t small_max_ids() { return SK; }
+
+void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
+                        uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
+                        unsigned grid_cap)
+{
+    if (n == 0)
+        return;
+    uint64_t tiles = ceil_div(n, STILE);
+    uint64_t *lbv = reinterpret_cast<uint64_t *>(scratch);
+    uint64_t *lbc = lbv + tiles * SWORDS;
+    launch_fill_u64(lbv, 0, tiles * (SWORDS + 1), s);
+    launch_fill_u32(&ctl->tickets[7], 0, 1, s);
+    unsigned grid = (unsigned)(tiles < grid_cap ? tiles : grid_cap);
+    ProfScope prof_(s, "small_check");
+    k_small_check<<<grid, BLOCK, 0, s>>>(events, n, n_ids, init, status, final_out, viol, lbv, lbc, &ctl->tickets[7],
+                                         tiles, ctl);
+}
+
+} // namespace vc

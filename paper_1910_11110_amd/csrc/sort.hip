@@ -8,6 +8,7 @@
 // gathered in one read beforehand.
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -273,7 +274,10 @@ void launch_make_items_events(const uint32_t *events, uint64_t n, uint32_t n_ids
                               hipStream_t s, uint32_t key_base, uint64_t payload_base)
 {
     if (n)
-        k_make_items_events<<<grid_for(n, 8), BLOCK, 0, s>>>(events, n, n_ids, items, ctl, key_base, payload_base);
+        {
+            ProfScope prof_(s, "make_items");
+            k_make_items_events<<<grid_for(n, 8), BLOCK, 0, s>>>(events, n, n_ids, items, ctl, key_base, payload_base);
+        }
 }
 
 size_t sort_scratch_bytes(uint64_t n)
@@ -295,14 +299,20 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
     uint64_t *lb = reinterpret_cast<uint64_t *>(sc + 1);
     uint64_t tiles = ceil_div(n, SORT_TILE);
     launch_fill_u32(&sc->hist[0][0], 0, MAX_PASSES * RADIX, s);
-    k_hist<<<grid_for(n, 16), BLOCK, 0, s>>>(a, n, passes, bits, &sc->hist[0][0]);
+    {
+        ProfScope prof_(s, "sort_histogram");
+        k_hist<<<grid_for(n, 16), BLOCK, 0, s>>>(a, n, passes, bits, &sc->hist[0][0]);
+    }
     uint64_t *src = a, *dst = b;
     for (int p = 0; p < passes; p++) {
         launch_fill_u64(lb, 0, tiles * RADIX, s);
         uint32_t *ticket = &ctl->tickets[0];
         launch_fill_u32(ticket, 0, 1, s);
         unsigned grid = (unsigned)(tiles < grid_cap ? tiles : grid_cap);
-        k_sort_pass<<<grid, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket, tiles);
+        {
+            ProfScope prof_(s, "sort_pass");
+            k_sort_pass<<<grid, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket, tiles);
+        }
         uint64_t *t = src;
         src = dst;
         dst = t;

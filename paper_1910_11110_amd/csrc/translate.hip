@@ -16,6 +16,7 @@
 // declaration (the not-taken guard emits Noop x; Noop x#), then its body.
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -166,15 +167,21 @@ void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_
                              hipStream_t s)
 {
     if (n_decl)
-        k_make_items_decls<<<grid_n(n_decl, BLOCK * 8), BLOCK, 0, s>>>(decls, n_decl, n_vars, items, ctl);
+        {
+            ProfScope prof_(s, "translate_items");
+            k_make_items_decls<<<grid_n(n_decl, BLOCK * 8), BLOCK, 0, s>>>(decls, n_decl, n_vars, items, ctl);
+        }
 }
 
 void launch_translate_count(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
                             const uint64_t *body_off, uint32_t *cnt, Control *ctl, hipStream_t s)
 {
     if (n_comp)
-        k_translate_count<<<grid_n(n_comp, BLOCK), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, body_off, cnt,
-                                                                 ctl);
+        {
+            ProfScope prof_(s, "translate_count");
+            k_translate_count<<<grid_n(n_comp, BLOCK), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, body_off, cnt,
+                                                                     ctl);
+        }
 }
 
 void launch_translate_emit(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
@@ -182,8 +189,11 @@ void launch_translate_emit(const uint64_t *comp_off, uint64_t n_comp, const uint
                            const uint64_t *pos, uint32_t *out, Control *ctl, hipStream_t s)
 {
     if (n_comp)
-        k_translate_emit<<<grid_n(n_comp, BLOCK), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars, pre_abs,
-                                                                body_off, body, pos, out, ctl);
+        {
+            ProfScope prof_(s, "translate_emit");
+            k_translate_emit<<<grid_n(n_comp, BLOCK), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars, pre_abs,
+                                                                    body_off, body, pos, out, ctl);
+        }
 }
 
 } // namespace vc

@@ -201,6 +201,7 @@ extern "C" int vc_translate_run(vc_trace *t)
         return vc_fail(VC_EINVAL, "vc_translate_run: not a translated trace");
     vc_ctx *c = t->ctx;
     (void)hipSetDevice(c->device);
+    ProfGuard pg(c);
     int r = translate_enqueue(t, c->stream);
     if (r != VC_OK)
         return r;

@@ -5,6 +5,7 @@
 // LDS, decoupled look-back for the tile's offset.
 #include "device.h"
 #include "internal.h"
+#include "prof.h"
 
 namespace vc {
 
@@ -91,7 +92,10 @@ void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *t
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
     launch_fill_u64(lb, 0, tiles, s);
     launch_fill_u32(ticket, 0, 1, s);
-    k_excl_scan<<<(unsigned)tiles, BLOCK, 0, s>>>(in, n, out, total, lb, ticket);
+    {
+        ProfScope prof_(s, "excl_scan");
+        k_excl_scan<<<(unsigned)tiles, BLOCK, 0, s>>>(in, n, out, total, lb, ticket);
+    }
 }
 
 } // namespace vc

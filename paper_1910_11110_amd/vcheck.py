@@ -75,6 +75,10 @@ def lib():
             "vc_poll": ([P, C.POINTER(vc_completion), u32, pu32], i32),
             "vc_stream_close": ([P, u64, P], i32),
             "vc_server_now": ([P], C.c_double),
+            "vc_translate_run": ([P], i32),
+            "vc_profile_enable": ([P, i32], i32),
+            "vc_profile_reset": ([P], i32),
+            "vc_profile_read": ([P, C.c_char_p, u32, P, P, u32, pu32], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -117,6 +121,25 @@ class Context:
 
     def sync(self):
         _check(lib().vc_sync(self.h))
+
+    def profile(self, on: bool = True):
+        _check(lib().vc_profile_enable(self.h, 1 if on else 0))
+
+    def profile_reset(self):
+        _check(lib().vc_profile_reset(self.h))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last reset."""
+        n = C.c_uint32()
+        _check(lib().vc_profile_read(self.h, None, 0, None, None, 0, C.byref(n)))
+        k = n.value
+        names = C.create_string_buffer(64 * (k + 1) + 1)
+        ms = np.zeros(max(k, 1), np.float64)
+        cnt = np.zeros(max(k, 1), np.uint64)
+        _check(lib().vc_profile_read(self.h, names, len(names), ms.ctypes.data_as(C.c_void_p),
+                                     cnt.ctypes.data_as(C.c_void_p), k, C.byref(n)))
+        keys = names.value.decode().split("\n")[:k]
+        return {keys[i]: (float(ms[i]), int(cnt[i])) for i in range(k)}
 
     def close(self):
         if self.h:
@@ -165,6 +188,10 @@ class Trace:
 
     def check(self):
         _check(lib().vc_check(self.h))
+
+    def rerun(self):
+        """Re-runs the translation (and its check) of a translated trace."""
+        _check(lib().vc_translate_run(self.h))
 
     def info(self):
         n, k = C.c_uint64(), C.c_uint32()

@@ -1,0 +1,179 @@
+"""Batched check: many independent traces in one pipeline, each identical to the oracle and
+to its own single-trace check."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1910_11110_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1910_11110_amd import vcheck as V
+    c = V.Context(0)
+    yield c
+    c.close()
+
+
+def make_traces(n, seed, len_range=(100, 50_000), vars_range=(8, 65536), with_init=True):
+    shapes = gen.trace_shapes(n, seed, len_range=len_range, vars_range=vars_range)
+    out = []
+    for i, sh in enumerate(shapes):
+        ev, lo, hi = gen.trace_inputs(sh)
+        init = None
+        if with_init and i % 5 == 1:
+            init = gen.below(gen.draws(sh.seed, 400, 0, sh.n_vars), 4).astype(np.uint8)
+        out.append((ev, sh.n_vars, lo, hi, init))
+    return out
+
+
+def load_all(ctx, inputs):
+    from paper_1910_11110_amd import vcheck as V
+    traces = []
+    for ev, nv, lo, hi, init in inputs:
+        t = V.Trace.load(ctx, ev, nv, init)
+        if lo is not None:
+            t.set_arrays(lo, hi)
+        traces.append(t)
+    return traces
+
+
+def oracle_of(ev, nv, lo, hi, init):
+    if lo is None:
+        return O.check(ev, nv, init)
+    return O.check_overlap(ev, lo, hi, init)
+
+
+def assert_trace(t, ref, label):
+    st = t.status()
+    if not np.array_equal(st, ref.status):
+        bad = np.nonzero(st != ref.status)[0]
+        raise AssertionError(f"{label}: {bad.size} statuses differ, first {bad[0]}")
+    assert np.array_equal(t.final(), ref.final), f"{label}: final"
+    v = t.violations()
+    assert v.total == ref.violations.size and np.array_equal(v.indices, ref.violations), f"{label}: violations"
+    assert v.first == ref.first, label
+    assert t.induced_stuck() == ref.n_induced_stuck, label
+
+
+def test_batch_small_mixed(ctx):
+    from paper_1910_11110_amd import vcheck as V
+    inputs = make_traces(40, 1)
+    traces = load_all(ctx, inputs)
+    say("[batch] 40 mixed traces")
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    for i, (t, inp) in enumerate(zip(traces, inputs)):
+        assert_trace(t, oracle_of(*inp), f"trace {i}")
+    # replay of the captured graph gives identical bytes
+    first = [t.status().copy() for t in traces]
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    assert all(np.array_equal(a, t.status()) for a, t in zip(first, traces))
+    g = C_info(V, ctx)
+    say(f"[batch] graph={g}")
+    for t in traces:
+        t.free()
+
+
+def C_info(V, ctx):
+    import ctypes as C
+    g, b, gc, sg = C.c_int(), C.c_int(), C.c_uint(), C.c_uint()
+    V._check(V.lib().vc_batch_info(ctx.h, C.byref(g), C.byref(b), C.byref(gc), C.byref(sg)))
+    return g.value, b.value, gc.value, sg.value
+
+
+def test_batch_equals_alone(ctx):
+    """A trace checked alone and inside a batch gives the same bytes."""
+    from paper_1910_11110_amd import vcheck as V
+    inputs = make_traces(12, 2)
+    traces = load_all(ctx, inputs)
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    in_batch = [(t.status().copy(), t.final().copy()) for t in traces]
+    for t, (s, f) in zip(traces, in_batch):
+        t.check()
+        ctx.sync()
+        assert np.array_equal(t.status(), s) and np.array_equal(t.final(), f)
+        t.free()
+
+
+def test_batch_edge_cases(ctx):
+    """Empty traces, one-event traces, a single id, and a batch of one."""
+    from paper_1910_11110_amd import vcheck as V
+    inputs = [(np.zeros(0, np.uint32), 3, None, None, None),
+              (gen.plain_events(1, 1, 3), 1, None, None, None),
+              (gen.plain_events(4097, 1, 4), 1, None, None, None),
+              (np.zeros(0, np.uint32), 1, None, None, None),
+              (gen.plain_events(5000, 70, 5), 70, None, None, np.zeros(70, np.uint8))]
+    traces = load_all(ctx, inputs)
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    for i, (t, inp) in enumerate(zip(traces, inputs)):
+        assert_trace(t, oracle_of(*inp), f"edge {i}")
+    V.batch_check(ctx, traces[4:])
+    ctx.sync()
+    assert_trace(traces[4], oracle_of(*inputs[4]), "batch of one")
+    for t in traces:
+        t.free()
+
+
+def test_batch_autotuner_is_parity_clean(ctx, tmp_path):
+    """With tuning on, every candidate setting runs on the batch; the chosen one gives the
+    oracle's bytes and is cached per shape."""
+    from paper_1910_11110_amd import vcheck as V
+    cache = tmp_path / "tune.json"
+    os.environ["VC_AUTOTUNE"] = "1"
+    os.environ["VC_TUNE_CACHE"] = str(cache)
+    try:
+        inputs = make_traces(25, 3)
+        traces = load_all(ctx, inputs)
+        V.batch_check(ctx, traces)
+        ctx.sync()
+        for i, (t, inp) in enumerate(zip(traces, inputs)):
+            assert_trace(t, oracle_of(*inp), f"tuned trace {i}")
+        assert cache.exists() and "gfx950" in cache.read_text()
+        say(f"[batch] tuned: {C_info(V, ctx)} cache {cache.read_text().strip()}")
+        for t in traces:
+            t.free()
+    finally:
+        del os.environ["VC_AUTOTUNE"]
+        del os.environ["VC_TUNE_CACHE"]
+
+
+def test_batch_workload_full_size_sampled(ctx):
+    """The batched workload at full size: 4,096 traces, lengths log-uniform in [100, 10^6],
+    variables log-uniform in [8, 65,536], 20 % with intervals; 64 sampled traces are compared
+    with the oracle in full, and every trace's violation count with the oracle's."""
+    from paper_1910_11110_amd import vcheck as V
+    say("[batch] generating 4096 traces")
+    shapes = gen.trace_shapes(4096, 0)
+    traces, inputs = [], []
+    for sh in shapes:
+        ev, lo, hi = gen.trace_inputs(sh)
+        t = V.Trace.load(ctx, ev, sh.n_vars)
+        if lo is not None:
+            t.set_arrays(lo, hi)
+        traces.append(t)
+        inputs.append((ev, sh.n_vars, lo, hi, None))
+    say(f"[batch] {sum(s.length for s in shapes)} events; running")
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    rng = np.random.default_rng(0)
+    sample = set(rng.choice(4096, 64, replace=False).tolist())
+    for i, (t, inp) in enumerate(zip(traces, inputs)):
+        if i in sample:
+            assert_trace(t, oracle_of(*inp), f"full trace {i}")
+        elif inp[2] is None:
+            assert t.violations().total == O.check_count(inp[0], inp[1]), f"count {i}"
+        t.free()

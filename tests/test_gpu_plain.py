@@ -140,3 +140,33 @@ def test_plain_invalid_host_event_rejected(ctx):
     with pytest.raises(V.VCError) as ex:
         V.Trace.load(ctx, e, 64)
     assert ex.value.code == V.VC_EINVAL and "index 7" in str(ex.value)
+
+
+@pytest.mark.parametrize("n,n_ids", [(10_000, 64), (4096 * 37 + 5, 64), (1 << 20, 17), (333_333, 1), (1 << 22, 64)])
+def test_small_and_general_paths_agree(ctx, n, n_ids):
+    """Traces over at most 64 ids take the single-kernel path; the general sort-based path
+    (forced by VC_GENERAL_PATH) must give the same bytes, and both the oracle's."""
+    import os
+    e = gen.plain_events(n, n_ids, 300 + n_ids)
+    init = gen.below(gen.draws(n, 79, 0, n_ids), 4).astype(np.uint8)
+    assert_parity(ctx, e, n_ids, init=init, label=f"small path {n}x{n_ids}")
+    os.environ["VC_GENERAL_PATH"] = "1"
+    try:
+        assert_parity(ctx, e, n_ids, init=init, label=f"general path {n}x{n_ids}")
+    finally:
+        del os.environ["VC_GENERAL_PATH"]
+
+
+def test_small_path_misaligned_device_events(ctx):
+    """A device buffer that is not 16-byte aligned takes the general path."""
+    import torch
+    from paper_1910_11110_amd import vcheck as V
+    e = gen.plain_events(100_001, 64, 31)
+    te = torch.from_numpy(np.concatenate([np.zeros(1, np.uint32), e]).view(np.int32)).cuda()[1:]
+    torch.cuda.synchronize()
+    t = V.Trace.load(ctx, te, 64)
+    t.check()
+    ctx.sync()
+    ref = O.check(e, 64)
+    assert np.array_equal(t.status(), ref.status)
+    t.free()
