@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "abi_internal.h"
+#include "bucket.h"
 #include "internal.h"
 
 using namespace vc;
@@ -332,6 +333,12 @@ static bool use_small_path(const vc_trace *t)
            !getenv("VC_GENERAL_PATH");
 }
 
+// path for larger id spaces: bucket partition, per-bucket scan, replay
+static bool use_bucket_path(const vc_trace *t)
+{
+    return !t->has_arrays && t->n_ids <= bucket_max_ids() && !getenv("VC_GENERAL_PATH");
+}
+
 int enqueue_check(vc_trace *t, hipStream_t s)
 {
     int r;
@@ -349,6 +356,22 @@ int enqueue_check(vc_trace *t, hipStream_t s)
             launch_fill_u8(fin, 1, t->n_ids, s);
         launch_small_check(t->events, t->n, t->n_ids, t->init, (uint8_t *)t->status.p, fin, (uint32_t *)t->viol.p,
                            t->scratch.p, t->ctl, s, 8u * (unsigned)t->ctx->cu_count);
+        return VC_OK;
+    }
+    if (use_bucket_path(t)) {
+        if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK ||
+            (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
+            (r = devbuf_reserve(t->viol, (t->n ? t->n : 1) * 4)) != VC_OK ||
+            (r = devbuf_reserve(t->scratch, bucket_scratch_bytes(t->n, t->n_ids))) != VC_OK)
+            return r;
+        launch_reset_control(t->ctl, s);
+        uint8_t *fin = (uint8_t *)t->fin.p;
+        if (t->init)
+            (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
+        else
+            launch_fill_u8(fin, 1, t->n_ids, s);
+        launch_bucket_check(t->events, t->n, t->n_ids, t->init, (uint8_t *)t->status.p, fin, (uint32_t *)t->viol.p,
+                            t->scratch.p, t->ctl, s, t->ctx->cu_count);
         return VC_OK;
     }
     uint64_t m = t->n;

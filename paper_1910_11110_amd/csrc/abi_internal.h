@@ -25,11 +25,12 @@ struct TranslateState {
     uint64_t n_comp = 0, n_decl = 0;
     uint32_t n_vars = 0;
     bool check = false;
+    bool fused = false; // check evaluated during the emission (canonical bodies)
     bool own_inputs = false;
     uint64_t *comp_off = nullptr, *body_off = nullptr;
     uint32_t *decls = nullptr, *body = nullptr;
     vc::Control *ctl = nullptr;
-    DevBuf cnt, pos, pre_abs, items_a, items_b, scratch;
+    DevBuf cnt, pos, pre_abs, items_a, items_b, scratch, final_abs;
 };
 
 struct vc_ctx {

@@ -1,0 +1,49 @@
+// bucket.h -- constants and host interface of the bucketed segmented scan.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace vc {
+
+constexpr int LBITS = 12;                 // ids per bucket = 2^LBITS
+constexpr int LOC = 1 << LBITS;
+constexpr int MAX_BUCKETS = 1024;         // ids up to 2^22
+constexpr int P_ITEMS = 16;               // partition / replay: words per thread
+constexpr int PTILE = BLOCK * P_ITEMS;
+constexpr int B_ITEMS = 16;               // bucket scan: words per thread
+constexpr int BTILE = BLOCK * B_ITEMS;
+constexpr int LB_WORDS = (LOC + 19) / 20; // dense look-back words per bucket tile (20 ids each)
+enum { BK_PRE = 0, BK_STATUS = 1 };
+
+struct BucketLayout {
+    int bits = 0;
+    uint32_t nb = 1;
+    uint32_t *hist = nullptr;
+    uint64_t *base = nullptr;
+    uint32_t *tbase = nullptr;
+    uint64_t *lbp = nullptr, *lbv = nullptr, *lbc = nullptr;
+    uint32_t *part = nullptr;
+    uint8_t *res = nullptr;
+    uint64_t ptiles = 0, btiles_max = 0;
+};
+
+uint32_t bucket_max_ids();
+int bucket_bits_for(uint32_t n_ids);
+size_t bucket_scratch_bytes(uint64_t n, uint32_t n_ids);
+BucketLayout bucket_layout(void *scratch, uint64_t n, uint32_t n_ids);
+
+// plain check of n events over n_ids <= bucket_max_ids() ids: status bytes in program
+// order, final table (pre-filled with the initial statuses by the caller), violations
+// (count into ctl->n_viol)
+void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
+                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu);
+
+// status of each declaration's abstract variable before it, in program order, and the
+// final status of every abstract variable (final_out pre-filled by the caller; may be
+// null)
+void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,
+                            void *scratch, Control *ctl, hipStream_t s, int cu);
+
+} // namespace vc

@@ -1,0 +1,862 @@
+// bucket.hip -- segmented scan by variable for large id spaces, in three passes
+// over 32-bit words (gfx950).
+//
+// 1. partition: one stable pass splits the words by bucket = id >> 12 (at most 1024
+//    buckets): each tile ranks its words by bucket with wave64 ballots, reorders them
+//    in LDS and writes every bucket's run contiguously; tile offsets come from a
+//    decoupled look-back whose final inclusive counts are kept for step 3.
+// 2. bucket scan: every bucket (4096 ids) is scanned in its own tiles.  A tile sorts
+//    its words by the low 12 id bits in LDS (two stable 6-bit ballot passes), runs a
+//    segmented scan of the transition functions, and chains the dense per-id state of
+//    its bucket with the previous tile by a decoupled look-back whose 64-bit words
+//    carry 20 ids each (3-bit codes: a transition function of the 7-element monoid,
+//    or a status) plus their own readiness flag.  The result byte of every word goes
+//    back to its position in the partitioned order.
+// 3. replay: each tile of the original order recomputes the partition ranks of its
+//    words (the same ballots), gathers their result bytes from the partitioned order,
+//    and hands them to the consumer in program order (status bytes and violation
+//    compaction for a trace; the translated events for declarations).
+#include "bucket.h"
+#include "device.h"
+#include "internal.h"
+#include "prof.h"
+
+namespace vc {
+
+namespace {
+
+constexpr EffectTable TABLE = make_table();
+
+// ----------------------------------------------------------------------------------
+// word sources: id and transition function of a 32-bit word; malformed words count as
+// Noop on id 0 (their index is reported by the histogram pass)
+// ----------------------------------------------------------------------------------
+struct EventWords {
+    __device__ static bool ok(uint32_t w, uint32_t n_ids)
+    {
+        return (w >> 28) == 0 && ((w >> 24) & 7u) <= OP_NOOP && (w & 0xFFFFFFu) < n_ids;
+    }
+    __device__ static uint32_t key(uint32_t w, uint32_t n_ids) { return ok(w, n_ids) ? (w & 0xFFFFFFu) : 0u; }
+    __device__ static uint32_t fc(uint32_t w, uint32_t n_ids)
+    {
+        return ok(w, n_ids) ? fcode((w >> 24) & 7u, (w >> 27) & 1u) : fcode(OP_NOOP, 0);
+    }
+};
+
+// a declaration acts on its abstract variable: R = guarded transfer toward its side,
+// W and RW end with w on its side
+struct DeclWords {
+    __device__ static bool ok(uint32_t w, uint32_t n_ids)
+    {
+        return (w & 0xF4000000u) == 0 && ((w >> 24) & 3u) <= 2u && (w & 0xFFFFFFu) < n_ids;
+    }
+    __device__ static uint32_t key(uint32_t w, uint32_t n_ids) { return ok(w, n_ids) ? (w & 0xFFFFFFu) : 0u; }
+    __device__ static uint32_t fc(uint32_t w, uint32_t n_ids)
+    {
+        uint32_t mode = ok(w, n_ids) ? (w >> 24) & 3u : 0u, side = ok(w, n_ids) ? (w >> 27) & 1u : 0u;
+        if (mode == 0)
+            return side ? fcode(OP_PUSH, 0) : fcode(OP_PULL, 0);
+        return fcode(OP_W, side);
+    }
+};
+
+// ----------------------------------------------------------------------------------
+// the 7-element monoid of the transition functions, as 3-bit codes
+// ----------------------------------------------------------------------------------
+__device__ __constant__ uint32_t MON_F4[8] = { 0x03020100u, 0x03020300u, 0x03030100u, 0x03030300u,
+                                               0x01010101u, 0x02020202u, 0x03030303u, 0x03020100u };
+
+__device__ __forceinline__ uint32_t mon_code(uint32_t f4)
+{
+    switch (fpack(f4)) {
+    case 0xE4: return 0;
+    case 0xEC: return 1;
+    case 0xF4: return 2;
+    case 0xFC: return 3;
+    case 0x55: return 4;
+    case 0xAA: return 5;
+    case 0xFF: return 6;
+    default: return 7; // not reachable from the effects
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// stable ranking of a tile's words by a digit (striped arrangement: item j of lane l
+// in wave w is tile position w*64*ITEMS + j*64 + l); per-wave digit counters in LDS
+// ----------------------------------------------------------------------------------
+template <int ITEMS, int MAXD>
+__device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t validmask, int bits,
+                                            uint32_t (&rank)[ITEMS], uint32_t *s_cnt /* [4][MAXD] */, uint32_t wave)
+{
+#pragma unroll
+    for (int j = 0; j < ITEMS; j++) {
+        bool valid = (validmask >> j) & 1u;
+        uint64_t m = __ballot(valid);
+        for (int b = 0; b < bits; b++) {
+            bool bit = (d[j] >> b) & 1u;
+            uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t r = mask_rank(m);
+        uint32_t c = __builtin_popcountll(m);
+        uint32_t prev = 0;
+        if (valid)
+            prev = s_cnt[wave * MAXD + d[j]];
+        if (valid && r == 0)
+            s_cnt[wave * MAXD + d[j]] = prev + c;
+        rank[j] = prev + r;
+    }
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_tmp)
+{
+    uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    uint32_t inc = wave_scan_add(v, lane);
+    if (lane == WAVE - 1)
+        s_tmp[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t w = 0; w < wave; w++)
+        off += s_tmp[w];
+    __syncthreads();
+    return off + inc - v;
+}
+
+// ----------------------------------------------------------------------------------
+// 0. histogram of buckets (+ validation)
+// ----------------------------------------------------------------------------------
+template <class SRC>
+__global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
+                                                       uint32_t *__restrict__ hist, Control *ctl)
+{
+    __shared__ uint32_t s_h[MAX_BUCKETS];
+    for (int i = threadIdx.x; i < MAX_BUCKETS; i += BLOCK)
+        s_h[i] = 0;
+    __syncthreads();
+    uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) {
+        uint32_t w = src[i];
+        if (!SRC::ok(w, n_ids)) {
+            unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
+            atomicMin(e, (unsigned long long)i);
+        }
+        atomicAdd(&s_h[SRC::key(w, n_ids) >> LBITS], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < MAX_BUCKETS; i += BLOCK)
+        if (s_h[i])
+            atomicAdd(&hist[i], s_h[i]);
+}
+
+// bucket bases (exclusive scan of the histogram) and first tile of every bucket
+__global__ __launch_bounds__(1024) void k_bucket_bases(const uint32_t *__restrict__ hist, uint32_t nb,
+                                                       uint64_t *__restrict__ base, uint32_t *__restrict__ tbase)
+{
+    __shared__ uint64_t s_a[1024];
+    __shared__ uint32_t s_t[1024];
+    uint32_t i = threadIdx.x;
+    uint64_t c = i < nb ? hist[i] : 0;
+    s_a[i] = c;
+    s_t[i] = (uint32_t)ceil_div(c, BTILE);
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+        uint64_t a = i >= d ? s_a[i - d] : 0;
+        uint32_t t = i >= d ? s_t[i - d] : 0;
+        __syncthreads();
+        s_a[i] += a;
+        s_t[i] += t;
+        __syncthreads();
+    }
+    if (i < nb) {
+        base[i] = s_a[i] - c;
+        tbase[i] = s_t[i] - (uint32_t)ceil_div(c, BTILE);
+    }
+    if (i == nb - 1) {
+        base[nb] = s_a[i];
+        tbase[nb] = s_t[i];
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// 1. partition by bucket
+// ----------------------------------------------------------------------------------
+template <class SRC>
+__global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
+                                                     int bits, const uint64_t *__restrict__ base,
+                                                     uint32_t *__restrict__ dst, uint64_t *__restrict__ lb,
+                                                     uint32_t *__restrict__ ticket, uint64_t ntiles)
+{
+    __shared__ uint32_t s_words[PTILE];
+    __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
+    __shared__ uint32_t s_dstart[MAX_BUCKETS];
+    __shared__ int64_t s_gbase[MAX_BUCKETS];
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    __shared__ uint32_t s_tile;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t nb = 1u << bits;
+    for (;;) {
+        const uint32_t tile = take_ticket(ticket, &s_tile);
+        if (tile >= ntiles)
+            break;
+        const uint64_t tbase = (uint64_t)tile * PTILE;
+        // per-wave counters live at [wave * MAX_BUCKETS + bucket]
+        for (uint32_t i = tid; i < 4 * nb; i += BLOCK)
+            s_cnt[(i / nb) * MAX_BUCKETS + (i % nb)] = 0;
+        __syncthreads();
+        uint32_t w[P_ITEMS], d[P_ITEMS], rank[P_ITEMS];
+        uint32_t valid = 0;
+        const uint64_t wb = tbase + (uint64_t)wave * WAVE * P_ITEMS;
+#pragma unroll
+        for (int j = 0; j < P_ITEMS; j++) {
+            uint64_t g = wb + (uint64_t)j * WAVE + lane;
+            w[j] = g < n ? src[g] : 0u;
+            valid |= (g < n ? 1u : 0u) << j;
+            d[j] = SRC::key(w[j], n_ids) >> LBITS;
+        }
+        rank_digits<P_ITEMS, MAX_BUCKETS>(d, valid, bits, rank, s_cnt, wave);
+        __syncthreads();
+        // per bucket: wave offsets, tile count, publication
+        uint64_t *my = lb + (uint64_t)tile * nb;
+        for (uint32_t b = tid; b < nb; b += BLOCK) {
+            uint32_t tc = 0;
+            for (uint32_t q = 0; q < 4; q++) {
+                uint32_t c = s_cnt[q * MAX_BUCKETS + b];
+                s_cnt[q * MAX_BUCKETS + b] = tc;
+                tc += c;
+            }
+            s_dstart[b] = tc; // tile count, turned into starts below
+            lb_store(&my[b], (tile == 0 ? LB_INC : LB_AGG) | tc);
+        }
+        __syncthreads();
+        // exclusive scan of the tile counts over buckets (nb <= 1024, 4 per thread)
+        {
+            uint32_t v[4], sum = 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                uint32_t b = tid * 4 + k;
+                v[k] = b < nb ? s_dstart[b] : 0;
+                sum += v[k];
+            }
+            uint32_t ex = block_excl_scan_u32(sum, s_tmp);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                uint32_t b = tid * 4 + k;
+                if (b < nb)
+                    s_dstart[b] = ex;
+                ex += v[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < P_ITEMS; j++) {
+            uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
+            if (((valid >> j) & 1u) && li < PTILE)
+                s_words[li] = w[j];
+        }
+        // look-back per bucket
+        for (uint32_t b = tid; b < nb; b += BLOCK) {
+            uint64_t excl = 0;
+            uint32_t tc = (uint32_t)(__hip_atomic_load(&my[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & LB_VAL);
+            if (tile > 0) {
+                int64_t t = (int64_t)tile - 1;
+                while (true) {
+                    uint64_t x = lb_wait(&lb[(uint64_t)t * nb + b]);
+                    excl += x & LB_VAL;
+                    if ((x >> 62) == 2)
+                        break;
+                    t--;
+                }
+                lb_store(&my[b], LB_INC | (excl + tc));
+            }
+            s_gbase[b] = (int64_t)base[b] + (int64_t)excl - (int64_t)s_dstart[b];
+        }
+        __syncthreads();
+        uint64_t vn = n - tbase < (uint64_t)PTILE ? n - tbase : (uint64_t)PTILE;
+        for (uint32_t pos = tid; pos < vn; pos += BLOCK) {
+            uint32_t x = s_words[pos];
+            uint32_t b = SRC::key(x, n_ids) >> LBITS;
+            int64_t gi = s_gbase[b] + pos;
+            if (gi >= 0 && (uint64_t)gi < n) // always true for consistent counts; never write outside
+                dst[(uint64_t)gi] = x;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// 2. scan inside every bucket
+// ----------------------------------------------------------------------------------
+// in-LDS stable sort of a tile's packed items (local id 12 bits | fcode 4 | pos 12 |
+// 4 spare) by the local id: two 6-bit passes
+__device__ __forceinline__ uint32_t loc_of(uint32_t p) { return p & 0xFFFu; }
+
+template <int MODE, class SRC>
+__global__ __launch_bounds__(BLOCK) void k_bucket_scan(const uint32_t *__restrict__ part, uint32_t n_ids,
+                                                       uint32_t nb, const uint64_t *__restrict__ base,
+                                                       const uint32_t *__restrict__ tbase,
+                                                       const uint8_t *__restrict__ init, uint8_t *__restrict__ out,
+                                                       uint8_t *__restrict__ final_out, uint64_t *__restrict__ lbv,
+                                                       uint32_t *__restrict__ ticket)
+{
+    __shared__ uint32_t s_a[BTILE];
+    __shared__ uint32_t s_b[BTILE];
+    __shared__ uint32_t s_cnt[4 * 64];
+    __shared__ uint32_t s_dst[64];
+    __shared__ uint8_t s_agg[LOC];   // 3-bit monoid code of the tile's function per local id
+    __shared__ uint8_t s_state[LOC]; // status per local id entering the tile
+    __shared__ uint8_t s_res[BTILE];
+    __shared__ uint32_t s_f4[16], s_stuck[16];
+    __shared__ uint32_t s_tbase[MAX_BUCKETS + 1];
+    __shared__ uint32_t s_wagg[BLOCK / WAVE], s_wflag[BLOCK / WAVE];
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    __shared__ uint32_t s_tile;
+
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    if (tid < 16) {
+        s_f4[tid] = TABLE.f4[tid];
+        s_stuck[tid] = TABLE.stuck[tid];
+    }
+    for (uint32_t i = tid; i <= nb; i += BLOCK)
+        s_tbase[i] = tbase[i];
+    __syncthreads();
+    const uint32_t ntiles = s_tbase[nb];
+    for (;;) {
+        const uint32_t g = take_ticket(ticket, &s_tile);
+        if (g >= ntiles)
+            break;
+        // bucket of this tile: largest b with tbase[b] <= g
+        uint32_t lo = 0, hi = nb;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (s_tbase[mid] <= g)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const uint32_t b = lo;
+        const uint32_t ti = g - s_tbase[b];        // tile within the bucket
+        const uint64_t b0 = base[b], b1 = base[b + 1];
+        const uint64_t t0 = b0 + (uint64_t)ti * BTILE;
+        const uint32_t cnt = (uint32_t)(b1 - t0 < (uint64_t)BTILE ? b1 - t0 : (uint64_t)BTILE);
+        const bool last_tile = t0 + cnt == b1;
+
+        // load packed items (striped arrangement)
+        uint32_t it[B_ITEMS], d[B_ITEMS], rank[B_ITEMS];
+        uint32_t valid = 0;
+#pragma unroll
+        for (int j = 0; j < B_ITEMS; j++) {
+            uint32_t pos = wave * WAVE * B_ITEMS + j * WAVE + lane;
+            uint32_t w = pos < cnt ? part[t0 + pos] : 0u;
+            uint32_t key = SRC::key(w, n_ids);
+            it[j] = (key & 0xFFFu) | (SRC::fc(w, n_ids) << 12) | (pos << 16);
+            valid |= (pos < cnt ? 1u : 0u) << j;
+        }
+        for (uint32_t i = tid; i < LOC; i += BLOCK)
+            s_agg[i] = 0; // identity
+        // two stable 6-bit passes: low bits into s_a, then high bits into s_b
+#pragma unroll
+        for (int pass = 0; pass < 2; pass++) {
+            for (uint32_t i = tid; i < 4 * 64; i += BLOCK)
+                s_cnt[i] = 0;
+            __syncthreads();
+            if (pass == 1) {
+#pragma unroll
+                for (int j = 0; j < B_ITEMS; j++) {
+                    uint32_t pos = wave * WAVE * B_ITEMS + j * WAVE + lane;
+                    it[j] = pos < cnt ? s_a[pos] : 0u;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < B_ITEMS; j++)
+                d[j] = (loc_of(it[j]) >> (6 * pass)) & 63u;
+            rank_digits<B_ITEMS, 64>(d, valid, 6, rank, s_cnt, wave);
+            __syncthreads();
+            if (tid < 64) {
+                uint32_t tc = 0;
+                for (uint32_t q = 0; q < 4; q++) {
+                    uint32_t c = s_cnt[q * 64 + tid];
+                    s_cnt[q * 64 + tid] = tc;
+                    tc += c;
+                }
+                s_dst[tid] = tc;
+            }
+            __syncthreads();
+            if (tid < WAVE) {
+                uint32_t v = s_dst[tid];
+                uint32_t inc = wave_scan_add(v, lane);
+                s_dst[tid] = inc - v;
+            }
+            __syncthreads();
+            uint32_t *dstarr = pass == 0 ? s_a : s_b;
+#pragma unroll
+            for (int j = 0; j < B_ITEMS; j++) {
+                uint32_t li = s_dst[d[j]] + s_cnt[wave * 64 + d[j]] + rank[j];
+                if (((valid >> j) & 1u) && li < BTILE)
+                    dstarr[li] = it[j];
+            }
+            __syncthreads();
+        }
+
+        // segmented scan over the sorted items (blocked: thread t owns t*16 ..)
+        const uint32_t first = tid * B_ITEMS;
+        uint32_t acc = F_ID, headseen = 0;
+        uint32_t prevloc = first == 0 ? 0xFFFFu : (first - 1 < cnt ? loc_of(s_b[first - 1]) : 0xFFFFu);
+        uint32_t x[B_ITEMS];
+        uint32_t heads = 0;
+#pragma unroll
+        for (int j = 0; j < B_ITEMS; j++) {
+            uint32_t p = first + j;
+            x[j] = p < cnt ? s_b[p] : 0xFFFFFFFFu;
+            uint32_t loc = p < cnt ? loc_of(x[j]) : 0xFFFEu;
+            if (loc != prevloc && p < cnt) {
+                heads |= 1u << j;
+                acc = F_ID;
+                headseen = 1;
+            }
+            prevloc = loc;
+            if (p < cnt)
+                acc = fcompose(s_f4[(x[j] >> 12) & 15u], acc);
+        }
+        // segmented scan of (flag, function) across threads: a segment restarts the
+        // composition, so the carry into a thread is the composition since the last head
+        uint32_t f = acc, fl = headseen;
+#pragma unroll
+        for (int dd = 1; dd < WAVE; dd <<= 1) {
+            uint32_t g2 = __shfl_up(f, dd);
+            uint32_t fl2 = __shfl_up(fl, dd);
+            if (lane >= (uint32_t)dd && !fl) {
+                f = fcompose(f, g2);
+                fl = fl2;
+            }
+        }
+        uint32_t wexc = __shfl_up(f, 1), wexf = __shfl_up(fl, 1);
+        if (lane == 0) {
+            wexc = F_ID;
+            wexf = 0;
+        }
+        if (lane == WAVE - 1) {
+            s_wagg[wave] = f;
+            s_wflag[wave] = fl;
+        }
+        __syncthreads();
+        // carry from earlier waves (only through waves without a head)
+        uint32_t cw = F_ID;
+        for (int w2 = (int)wave - 1; w2 >= 0; w2--) {
+            cw = fcompose(cw, s_wagg[w2]);
+            if (s_wflag[w2])
+                break;
+        }
+        uint32_t texc = wexf ? wexc : fcompose(wexc, cw);
+        // tile aggregate per local id: inclusive value at each segment's last item
+        {
+            uint32_t a = texc;
+#pragma unroll
+            for (int j = 0; j < B_ITEMS; j++) {
+                uint32_t p = first + j;
+                if (p >= cnt)
+                    break;
+                if ((heads >> j) & 1u)
+                    a = F_ID;
+                a = fcompose(s_f4[(x[j] >> 12) & 15u], a);
+                uint32_t nloc = (j + 1 < B_ITEMS) ? (p + 1 < cnt ? loc_of(x[j + 1]) : 0xFFFFu)
+                                                  : (p + 1 < cnt ? loc_of(s_b[p + 1]) : 0xFFFFu);
+                if (nloc != loc_of(x[j]))
+                    s_agg[loc_of(x[j])] = (uint8_t)mon_code(a);
+            }
+        }
+        __syncthreads();
+
+        // look-back on the dense per-id state of the bucket (20 ids per word)
+        uint64_t *tilew = lbv + (uint64_t)g * LB_WORDS;
+        for (uint32_t wi = tid; wi < LB_WORDS; wi += BLOCK) {
+            uint64_t aw = 0;
+#pragma unroll
+            for (int k = 0; k < 20; k++) {
+                uint32_t l = wi * 20 + k;
+                aw |= (uint64_t)(l < LOC ? s_agg[l] : 0u) << (3 * k);
+            }
+            uint32_t acc20[20];
+            uint32_t st20[20];
+#pragma unroll
+            for (int k = 0; k < 20; k++)
+                acc20[k] = F_ID;
+            if (ti == 0) {
+#pragma unroll
+                for (int k = 0; k < 20; k++) {
+                    uint32_t l = wi * 20 + k;
+                    uint32_t key = b * LOC + l;
+                    st20[k] = (init && key < n_ids) ? init[key] : 1u;
+                }
+            } else {
+                lb_store(&tilew[wi], LB_AGG | aw);
+                int64_t t = (int64_t)g - 1;
+                while (true) {
+                    uint64_t v = lb_wait(lbv + (uint64_t)t * LB_WORDS + wi);
+                    bool inc = (v >> 62) == 2;
+#pragma unroll
+                    for (int k = 0; k < 20; k++) {
+                        uint32_t c3 = (uint32_t)(v >> (3 * k)) & 7u;
+                        if (inc)
+                            st20[k] = fapply(acc20[k], c3);
+                        else
+                            acc20[k] = fcompose(acc20[k], MON_F4[c3]);
+                    }
+                    if (inc)
+                        break;
+                    t--;
+                }
+            }
+            uint64_t iw = 0;
+#pragma unroll
+            for (int k = 0; k < 20; k++) {
+                uint32_t l = wi * 20 + k;
+                uint32_t ag = (uint32_t)(aw >> (3 * k)) & 7u;
+                uint32_t inc = fapply(MON_F4[ag], st20[k]);
+                iw |= (uint64_t)inc << (3 * k);
+                if (l < LOC) {
+                    s_state[l] = (uint8_t)st20[k];
+                    uint32_t key = b * LOC + l;
+                    if (last_tile && final_out && key < n_ids)
+                        final_out[key] = (uint8_t)inc;
+                }
+            }
+            lb_store(&tilew[wi], LB_INC | iw);
+        }
+        __syncthreads();
+
+        // every item: status before it = (composition since its segment's head)(state)
+        {
+            uint32_t a = texc;
+#pragma unroll
+            for (int j = 0; j < B_ITEMS; j++) {
+                uint32_t p = first + j;
+                if (p >= cnt)
+                    break;
+                if ((heads >> j) & 1u)
+                    a = F_ID;
+                uint32_t loc = loc_of(x[j]), fcj = (x[j] >> 12) & 15u;
+                uint32_t pre = fapply(a, s_state[loc]);
+                uint32_t post = fapply(s_f4[fcj], pre);
+                uint32_t flag = (s_stuck[fcj] >> pre) & 1u;
+                a = fcompose(s_f4[fcj], a);
+                uint32_t r = MODE == BK_PRE ? pre : (post | (pre << 2) | (flag << 7));
+                s_res[(x[j] >> 16) & (BTILE - 1)] = (uint8_t)r;
+            }
+        }
+        __syncthreads();
+        // result bytes back to the partitioned order, coalesced
+        for (uint32_t p = tid; p < cnt; p += BLOCK)
+            out[t0 + p] = s_res[p];
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------------
+// 3. replay: partition ranks again, gather result bytes into program order
+// ----------------------------------------------------------------------------------
+template <class SRC>
+__device__ __forceinline__ void replay_tile(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids, int bits,
+                                            const uint64_t *__restrict__ base, const uint64_t *__restrict__ lbp,
+                                            const uint8_t *__restrict__ res, uint32_t tile, uint8_t *s_res,
+                                            uint32_t *s_cnt, uint32_t *s_tmp, int64_t *s_off, uint32_t *s_w)
+{
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t nb = 1u << bits;
+    const uint64_t tbase = (uint64_t)tile * PTILE;
+    // per-wave counters live at [wave * MAX_BUCKETS + bucket]
+    for (uint32_t i = tid; i < 4 * nb; i += BLOCK)
+        s_cnt[(i / nb) * MAX_BUCKETS + (i % nb)] = 0;
+    __syncthreads();
+    uint32_t w[P_ITEMS], d[P_ITEMS], rank[P_ITEMS];
+    uint32_t valid = 0;
+    const uint64_t wb = tbase + (uint64_t)wave * WAVE * P_ITEMS;
+#pragma unroll
+    for (int j = 0; j < P_ITEMS; j++) {
+        uint64_t g = wb + (uint64_t)j * WAVE + lane;
+        w[j] = g < n ? src[g] : 0u;
+        valid |= (g < n ? 1u : 0u) << j;
+        d[j] = SRC::key(w[j], n_ids) >> LBITS;
+    }
+    rank_digits<P_ITEMS, MAX_BUCKETS>(d, valid, bits, rank, s_cnt, wave);
+    __syncthreads();
+    for (uint32_t b = tid; b < nb; b += BLOCK) {
+        uint32_t tc = 0;
+        for (uint32_t q = 0; q < 4; q++) {
+            uint32_t c = s_cnt[q * MAX_BUCKETS + b];
+            s_cnt[q * MAX_BUCKETS + b] = tc;
+            tc += c;
+        }
+        uint64_t inc = lbp[(uint64_t)tile * nb + b] & LB_VAL;
+        s_off[b] = (int64_t)base[b] + (int64_t)inc - (int64_t)tc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < P_ITEMS; j++) {
+        if ((valid >> j) & 1u) {
+            int64_t pos = s_off[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
+            uint32_t tp = wave * WAVE * P_ITEMS + j * WAVE + lane;
+            s_res[tp] = (pos >= 0 && (uint64_t)pos < n) ? res[pos] : (uint8_t)0;
+            if (s_w)
+                s_w[tp] = w[j];
+        }
+    }
+    __syncthreads();
+    (void)s_tmp;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restrict__ src, uint64_t n,
+                                                         uint32_t n_ids, int bits, const uint64_t *__restrict__ base,
+                                                         const uint64_t *__restrict__ lbp,
+                                                         const uint8_t *__restrict__ res, uint8_t *__restrict__ status,
+                                                         uint32_t *__restrict__ viol, uint64_t *__restrict__ lbc,
+                                                         uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
+{
+    __shared__ __align__(16) uint8_t s_res[PTILE];
+    __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
+    __shared__ int64_t s_off[MAX_BUCKETS];
+    __shared__ uint32_t s_wsum[BLOCK / WAVE];
+    __shared__ uint32_t s_tile;
+    __shared__ unsigned long long s_excl;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    for (;;) {
+        const uint32_t tile = take_ticket(ticket, &s_tile);
+        if (tile >= ntiles)
+            break;
+        replay_tile<EventWords>(src, n, n_ids, bits, base, lbp, res, tile, s_res, s_cnt, nullptr, s_off, nullptr);
+        const uint64_t tbase = (uint64_t)tile * PTILE;
+        const uint64_t my0 = tbase + (uint64_t)tid * 16;
+        // 16 consecutive status bytes per thread
+        uint32_t q[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            q[k] = reinterpret_cast<const uint32_t *>(s_res)[tid * 4 + k];
+        uint32_t flags = 0;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            uint32_t byte = (q[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+            if (my0 + k < n)
+                flags |= ((byte >> 7) & 1u) << k;
+        }
+        if (my0 + 16 <= n) {
+            *reinterpret_cast<uint4 *>(status + my0) = make_uint4(q[0], q[1], q[2], q[3]);
+        } else {
+            for (int k = 0; k < 16; k++)
+                if (my0 + k < n)
+                    status[my0 + k] = s_res[tid * 16 + k];
+        }
+        uint32_t c = __builtin_popcount(flags);
+        uint32_t inc = wave_scan_add(c, lane);
+        if (lane == WAVE - 1)
+            s_wsum[wave] = inc;
+        __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (uint32_t w2 = 0; w2 < BLOCK / WAVE; w2++) {
+            if (w2 < wave)
+                woff += s_wsum[w2];
+            total += s_wsum[w2];
+        }
+        if (tid == 0) {
+            uint64_t *my = lbc + tile;
+            uint64_t excl = 0;
+            if (tile == 0) {
+                lb_store(my, LB_INC | total);
+            } else {
+                lb_store(my, LB_AGG | total);
+                int64_t t = (int64_t)tile - 1;
+                while (true) {
+                    uint64_t x = lb_wait(&lbc[t]);
+                    excl += x & LB_VAL;
+                    if ((x >> 62) == 2)
+                        break;
+                    t--;
+                }
+                lb_store(my, LB_INC | (excl + total));
+            }
+            s_excl = excl;
+            if (tile + 1 == ntiles)
+                ctl->n_viol = excl + total;
+        }
+        __syncthreads();
+        uint64_t o = s_excl + woff + inc - c;
+        while (flags) {
+            uint32_t bb = __builtin_ctz(flags);
+            flags &= flags - 1;
+            if (o < n)
+                viol[o] = (uint32_t)(my0 + bb);
+            o++;
+        }
+        __syncthreads();
+    }
+}
+
+unsigned gridn(uint64_t n, unsigned per)
+{
+    uint64_t g = ceil_div(n ? n : 1, per);
+    return (unsigned)(g > 4096 ? 4096 : g);
+}
+
+} // namespace
+
+// ----------------------------------------------------------------------------------
+// host side
+// ----------------------------------------------------------------------------------
+int bucket_bits_for(uint32_t n_ids)
+{
+    uint32_t nb = n_ids <= LOC ? 1u : (uint32_t)ceil_div(n_ids, LOC);
+    int bits = 0;
+    while ((1u << bits) < nb)
+        bits++;
+    return bits;
+}
+
+// one layout routine serves both the size query (base = null) and the carving
+static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
+{
+    BucketLayout L{};
+    int bits = bucket_bits_for(n_ids);
+    uint64_t nb = 1ull << bits;
+    uint64_t ptiles = ceil_div(n ? n : 1, PTILE);
+    uint64_t btiles = ceil_div(n ? n : 1, BTILE) + nb;
+    size_t off = 0;
+    auto take = [&](size_t sz) {
+        char *r = p0 ? p0 + off : nullptr;
+        off += (sz + 255) & ~size_t(255);
+        return r;
+    };
+    L.bits = bits;
+    L.nb = (uint32_t)nb;
+    L.hist = (uint32_t *)take(MAX_BUCKETS * 4);
+    L.base = (uint64_t *)take((MAX_BUCKETS + 1) * 8);
+    L.tbase = (uint32_t *)take((MAX_BUCKETS + 1) * 4);
+    L.lbp = (uint64_t *)take(ptiles * nb * 8);
+    L.lbv = (uint64_t *)take(btiles * LB_WORDS * 8);
+    L.lbc = (uint64_t *)take(ptiles * 8);
+    L.part = (uint32_t *)take((n ? n : 1) * 4);
+    L.res = (uint8_t *)take(n ? n : 1);
+    L.ptiles = ptiles;
+    L.btiles_max = btiles;
+    if (bytes)
+        *bytes = off;
+    return L;
+}
+
+size_t bucket_scratch_bytes(uint64_t n, uint32_t n_ids)
+{
+    size_t bytes = 0;
+    carve(nullptr, n, n_ids, &bytes);
+    return bytes;
+}
+
+BucketLayout bucket_layout(void *scratch, uint64_t n, uint32_t n_ids)
+{
+    return carve(reinterpret_cast<char *>(scratch), n, n_ids, nullptr);
+}
+
+uint32_t bucket_max_ids() { return (uint32_t)MAX_BUCKETS * LOC; }
+
+// histogram, partition and per-bucket scan; result bytes land in L.res (partitioned
+// order), or in `direct_out` (program order) when everything is one bucket
+template <class SRC>
+static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, const uint8_t *init, int mode,
+                               uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
+                               hipStream_t s, int cu)
+{
+    launch_fill_u32(L.hist, 0, MAX_BUCKETS, s);
+    launch_fill_u64(L.lbv, 0, L.btiles_max * LB_WORDS, s);
+    launch_fill_u32(&ctl->tickets[8], 0, 2, s);
+    {
+        ProfScope p(s, "bucket_hist");
+        k_bucket_hist<SRC><<<gridn(n, BLOCK * 16), BLOCK, 0, s>>>(src, n, n_ids, L.hist, ctl);
+    }
+    k_bucket_bases<<<1, 1024, 0, s>>>(L.hist, L.nb, L.base, L.tbase);
+    const uint32_t *part = src;
+    uint8_t *res = direct_out;
+    if (L.nb > 1) {
+        launch_fill_u64(L.lbp, 0, L.ptiles * L.nb, s);
+        ProfScope p(s, "bucket_partition");
+        unsigned grid = (unsigned)(L.ptiles < (uint64_t)cu * 4 ? L.ptiles : (uint64_t)cu * 4);
+        k_partition<SRC><<<grid, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.part, L.lbp, &ctl->tickets[8],
+                                                L.ptiles);
+        part = L.part;
+        res = L.res;
+    }
+    {
+        ProfScope p(s, "bucket_scan");
+        // the bucket tiles are counted on the device (tbase[nb]); surplus workgroups exit
+        // on their first ticket
+        uint64_t btiles = L.btiles_max;
+        unsigned grid = (unsigned)(btiles < (uint64_t)cu * 4 ? btiles : (uint64_t)cu * 4);
+        if (mode == BK_PRE)
+            k_bucket_scan<BK_PRE, SRC><<<grid, BLOCK, 0, s>>>(part, n_ids, L.nb, L.base, L.tbase, init, res,
+                                                              final_out, L.lbv, &ctl->tickets[9]);
+        else
+            k_bucket_scan<BK_STATUS, SRC><<<grid, BLOCK, 0, s>>>(part, n_ids, L.nb, L.base, L.tbase, init, res,
+                                                                 final_out, L.lbv, &ctl->tickets[9]);
+    }
+}
+
+void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
+                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu)
+{
+    if (n == 0)
+        return;
+    BucketLayout L = bucket_layout(scratch, n, n_ids);
+    partition_and_scan<EventWords>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu);
+    if (L.nb == 1) {
+        launch_compact(status, n, viol, L.lbc, ctl, s);
+        return;
+    }
+    launch_fill_u64(L.lbc, 0, L.ptiles, s);
+    launch_fill_u32(&ctl->tickets[10], 0, 1, s);
+    ProfScope p(s, "bucket_replay");
+    unsigned grid = (unsigned)(L.ptiles < (uint64_t)cu * 4 ? L.ptiles : (uint64_t)cu * 4);
+    k_replay_status<<<grid, BLOCK, 0, s>>>(events, n, n_ids, L.bits, L.base, L.lbp, L.res, status, viol, L.lbc,
+                                           &ctl->tickets[10], L.ptiles, ctl);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_replay_bytes(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
+                                                        int bits, const uint64_t *__restrict__ base,
+                                                        const uint64_t *__restrict__ lbp,
+                                                        const uint8_t *__restrict__ res, uint8_t *__restrict__ out,
+                                                        uint32_t *__restrict__ ticket, uint64_t ntiles)
+{
+    __shared__ __align__(16) uint8_t s_res[PTILE];
+    __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
+    __shared__ int64_t s_off[MAX_BUCKETS];
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    __shared__ uint32_t s_tile;
+    const uint32_t tid = threadIdx.x;
+    for (;;) {
+        const uint32_t tile = take_ticket(ticket, &s_tile);
+        if (tile >= ntiles)
+            break;
+        replay_tile<DeclWords>(src, n, n_ids, bits, base, lbp, res, tile, s_res, s_cnt, s_tmp, s_off, nullptr);
+        const uint64_t my0 = (uint64_t)tile * PTILE + (uint64_t)tid * 16;
+        if (my0 + 16 <= n) {
+            *reinterpret_cast<uint4 *>(out + my0) = *reinterpret_cast<const uint4 *>(s_res + tid * 16);
+        } else {
+            for (int k = 0; k < 16; k++)
+                if (my0 + k < n)
+                    out[my0 + k] = s_res[tid * 16 + k];
+        }
+        __syncthreads();
+    }
+}
+
+void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,
+                            void *scratch, Control *ctl, hipStream_t s, int cu)
+{
+    if (n_decl == 0)
+        return;
+    BucketLayout L = bucket_layout(scratch, n_decl, n_vars);
+    partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu);
+    if (L.nb == 1)
+        return;
+    launch_fill_u32(&ctl->tickets[10], 0, 1, s);
+    ProfScope p(s, "bucket_replay");
+    unsigned grid = (unsigned)(L.ptiles < (uint64_t)cu * 4 ? L.ptiles : (uint64_t)cu * 4);
+    k_replay_bytes<<<grid, BLOCK, 0, s>>>(decls, n_decl, n_vars, L.bits, L.base, L.lbp, L.res, pre,
+                                          &ctl->tickets[10], L.ptiles);
+}
+
+} // namespace vc

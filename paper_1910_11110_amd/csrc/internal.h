@@ -14,7 +14,7 @@ constexpr int SCAN_TILE = BLOCK * SCAN_ITEMS;
 constexpr int RADIX_BITS_MAX = 8;
 constexpr int RADIX = 1 << RADIX_BITS_MAX;
 
-inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // control block: counters zeroed at the start of each pipeline run
 struct Control {
@@ -96,6 +96,12 @@ void launch_translate_count(const uint64_t *comp_off, uint64_t n_comp, const uin
 void launch_translate_emit(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
                            uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *body_off, const uint32_t *body,
                            const uint64_t *pos, uint32_t *out, Control *ctl, hipStream_t s);
+
+// canonical bodies: translated events and their status bytes in one pass, from the
+// pre-status of each declaration's abstract variable
+void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                                 uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *pos, uint32_t *out,
+                                 uint8_t *status, hipStream_t s);
 
 // ------------------------------- overlap ------------------------------------------
 struct OverlapSets {

@@ -155,6 +155,109 @@ __global__ void k_translate_emit(const uint64_t *__restrict__ comp_off, uint64_t
     }
 }
 
+// Fused translation + check for canonical bodies.  One workgroup writes 256
+// consecutive components: every thread expands its component's declarations into
+// the translated events and evaluates them on the statuses of v and v# (both equal
+// to the abstract variable's status before the declaration: a canonical body applies
+// to v exactly the function the translation applies to v#, so the two agree at every
+// declaration from the common initial (V,I)), staging events and status bytes in LDS
+// so that the workgroup's output range is written contiguously.
+constexpr EffectTable TABLE = make_table();
+constexpr int FUSED_CAP = 256 * 40; // 8 RW declarations of 5 events per component
+
+__global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *__restrict__ comp_off, uint64_t n_comp,
+                                                               const uint32_t *__restrict__ decls, uint64_t n_decl,
+                                                               uint32_t n_vars, const uint8_t *__restrict__ pre_abs,
+                                                               const uint64_t *__restrict__ pos,
+                                                               uint32_t *__restrict__ out, uint8_t *__restrict__ status)
+{
+    __shared__ uint32_t s_ev[FUSED_CAP];
+    __shared__ uint8_t s_st[FUSED_CAP];
+    __shared__ uint32_t s_f4[16], s_stuck[16];
+    const uint32_t tid = threadIdx.x;
+    if (tid < 16) {
+        s_f4[tid] = TABLE.f4[tid];
+        s_stuck[tid] = TABLE.stuck[tid];
+    }
+    const uint64_t c0 = (uint64_t)blockIdx.x * BLOCK;
+    const uint64_t cend = c0 + BLOCK < n_comp ? c0 + BLOCK : n_comp;
+    const uint64_t base = pos[c0];
+    const uint64_t range = pos[cend] - base;
+    const bool staged = range <= (uint64_t)FUSED_CAP;
+    __syncthreads();
+    const uint64_t c = c0 + tid;
+    if (c < n_comp) {
+        uint64_t a = comp_off[c], b = comp_off[c + 1];
+        uint64_t p = pos[c] - base, end = pos[c + 1] - base;
+        if (b >= a && b <= n_decl) {
+            auto put = [&](uint32_t id, uint32_t op, uint32_t side, uint32_t &st) {
+                uint32_t fc = fcode(op, side);
+                uint32_t post = fapply(s_f4[fc], st);
+                uint32_t flag = (s_stuck[fc] >> st) & 1u;
+                uint32_t w = id | (op << 24) | (side << 27);
+                uint8_t sb = (uint8_t)(post | (st << 2) | (flag << 7));
+                if (p < end) {
+                    if (staged) {
+                        s_ev[p] = w;
+                        s_st[p] = sb;
+                    } else {
+                        out[base + p] = w;
+                        status[base + p] = sb;
+                    }
+                }
+                p++;
+                st = post;
+            };
+            // [[M]] of every declaration, then the canonical bodies
+            for (uint64_t d = a; d < b; d++) {
+                uint32_t wd = decls[d];
+                uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
+                if (!decl_ok(wd, n_vars)) {
+                    v = 0;
+                    mode = 0;
+                }
+                uint32_t sa = pre_abs[d], sr = sa;
+                if (mode == 0 || mode == 2) {
+                    bool valid = (sa >> side) & 1u;
+                    if (valid) {
+                        put(v, OP_NOOP, side, sr);
+                        put(n_vars + v, OP_NOOP, side, sa);
+                    } else {
+                        uint32_t t = side ? OP_PUSH : OP_PULL;
+                        put(v, t, 0, sr);
+                        put(n_vars + v, t, 0, sa);
+                    }
+                }
+                if (mode == 1 || mode == 2)
+                    put(n_vars + v, OP_W, side, sa);
+            }
+            for (uint64_t d = a; d < b; d++) {
+                uint32_t wd = decls[d];
+                uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
+                if (!decl_ok(wd, n_vars)) {
+                    v = 0;
+                    mode = 0;
+                }
+                // the real variable's status after [[M]]: the guard's transfer, if any
+                uint32_t sr = pre_abs[d];
+                if ((mode == 0 || mode == 2) && !((sr >> side) & 1u))
+                    sr = fapply(s_f4[fcode(side ? OP_PUSH : OP_PULL, 0)], sr);
+                if (mode == 0 || mode == 2)
+                    put(v, OP_R, side, sr);
+                if (mode == 1 || mode == 2)
+                    put(v, OP_W, side, sr);
+            }
+        }
+    }
+    __syncthreads();
+    if (staged) {
+        for (uint64_t i = tid; i < range; i += BLOCK) {
+            out[base + i] = s_ev[i];
+            status[base + i] = s_st[i];
+        }
+    }
+}
+
 unsigned grid_n(uint64_t n, unsigned per)
 {
     uint64_t g = ceil_div(n ? n : 1, per);
@@ -162,6 +265,17 @@ unsigned grid_n(uint64_t n, unsigned per)
 }
 
 } // namespace
+
+void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                                 uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *pos, uint32_t *out,
+                                 uint8_t *status, hipStream_t s)
+{
+    if (!n_comp)
+        return;
+    ProfScope prof_(s, "translate_emit_fused");
+    k_translate_emit_fused<<<(unsigned)ceil_div(n_comp, BLOCK), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars,
+                                                                               pre_abs, pos, out, status);
+}
 
 void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint64_t *items, Control *ctl,
                              hipStream_t s)

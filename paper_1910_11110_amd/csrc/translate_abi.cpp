@@ -1,11 +1,13 @@
 // translate_abi.cpp -- vc_translate: declarations -> translated trace (+ optional check).
 #include <hip/hip_runtime.h>
 
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
 
 #include "abi_internal.h"
+#include "bucket.h"
 #include "internal.h"
 
 using namespace vc;
@@ -74,7 +76,9 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         return r;
     if ((r = devbuf_reserve(tr.items_b, (n_decl ? n_decl : 1) * 8)) != VC_OK)
         return r;
-    size_t sc = std::max({ sort_scratch_bytes(n_decl), scan_scratch_bytes(n_decl), excl_scan_scratch_bytes(n_comp) });
+    bool bucketed = tr.n_vars <= bucket_max_ids() && !getenv("VC_GENERAL_PATH");
+    size_t sc = std::max({ bucketed ? bucket_scratch_bytes(n_decl, tr.n_vars) : sort_scratch_bytes(n_decl),
+                           scan_scratch_bytes(n_decl), excl_scan_scratch_bytes(n_comp) });
     if ((r = devbuf_reserve(tr.scratch, sc)) != VC_OK)
         return r;
     launch_reset_control(tr.ctl, s);
@@ -101,11 +105,39 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
     }
     t->n = total;
     // status of each declaration's abstract variable before it (segmented scan)
-    launch_make_items_decls(tr.decls, n_decl, tr.n_vars, (uint64_t *)tr.items_a.p, tr.ctl, s);
-    uint64_t *sorted = sort_items((uint64_t *)tr.items_a.p, (uint64_t *)tr.items_b.p, n_decl,
-                                  (int)key_bits_for(tr.n_vars), tr.scratch.p, tr.ctl, s);
-    launch_segscan(sorted, n_decl, nullptr, tr.n_vars, SCAN_PRE, (uint8_t *)tr.pre_abs.p, nullptr, tr.scratch.p,
-                   tr.ctl, s);
+    // canonical bodies with the check requested: the check is fused into the emission
+    tr.fused = tr.check && !tr.body_off && bucketed && !getenv("VC_UNFUSED");
+    if (tr.fused) {
+        if ((r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK ||
+            (r = devbuf_reserve(t->status, total ? total : 1)) != VC_OK ||
+            (r = devbuf_reserve(t->fin, 2 * (size_t)tr.n_vars)) != VC_OK ||
+            (r = devbuf_reserve(t->viol, (total ? total : 1) * 4)) != VC_OK ||
+            (r = devbuf_reserve(t->scratch, compact_scratch_bytes(total))) != VC_OK)
+            return r;
+        launch_fill_u8((uint8_t *)tr.final_abs.p, 1, tr.n_vars, s);
+    }
+    if (bucketed) {
+        launch_bucket_decl_pre(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
+                               tr.fused ? (uint8_t *)tr.final_abs.p : nullptr, tr.scratch.p, tr.ctl, s,
+                               t->ctx->cu_count);
+    } else {
+        launch_make_items_decls(tr.decls, n_decl, tr.n_vars, (uint64_t *)tr.items_a.p, tr.ctl, s);
+        uint64_t *sorted = sort_items((uint64_t *)tr.items_a.p, (uint64_t *)tr.items_b.p, n_decl,
+                                      (int)key_bits_for(tr.n_vars), tr.scratch.p, tr.ctl, s);
+        launch_segscan(sorted, n_decl, nullptr, tr.n_vars, SCAN_PRE, (uint8_t *)tr.pre_abs.p, nullptr, tr.scratch.p,
+                       tr.ctl, s);
+    }
+    if (tr.fused) {
+        launch_translate_emit_fused(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
+                                    (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, s);
+        // final store: each real variable ends where its abstract variable ends
+        uint8_t *fin = (uint8_t *)t->fin.p;
+        (void)hipMemcpyAsync(fin, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(fin + tr.n_vars, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
+        launch_reset_control(t->ctl, s);
+        launch_compact((uint8_t *)t->status.p, total, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
+        return VC_OK;
+    }
     launch_translate_emit(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, tr.body_off,
                           tr.body, (uint64_t *)tr.pos.p, t->events, tr.ctl, s);
     return VC_OK;
@@ -207,7 +239,7 @@ extern "C" int vc_translate_run(vc_trace *t)
         return r;
     t->translate_pending = true;
     if (t->tr->check) {
-        if ((r = enqueue_check(t, c->stream)) != VC_OK)
+        if (!t->tr->fused && (r = enqueue_check(t, c->stream)) != VC_OK)
             return r;
         t->check_pending = true;
         t->checked = false;
@@ -241,6 +273,7 @@ void translate_release(vc_trace *t)
     devbuf_free(tr.items_a);
     devbuf_free(tr.items_b);
     devbuf_free(tr.scratch);
+    devbuf_free(tr.final_abs);
     delete t->tr;
     t->tr = nullptr;
 }

@@ -170,3 +170,30 @@ def test_small_path_misaligned_device_events(ctx):
     ref = O.check(e, 64)
     assert np.array_equal(t.status(), ref.status)
     t.free()
+
+
+@pytest.mark.parametrize("n,n_ids", [(4097, 65), (100_000, 4096), (100_000, 4097), (1 << 20, 12_345),
+                                     (2_000_003, 1 << 20), (3_000_000, (1 << 22) - 3), (50_000, 1 << 22)])
+def test_bucket_and_general_paths_agree(ctx, n, n_ids):
+    """Id spaces above 64 take the bucket path (partition by id >> 12, per-bucket scan,
+    replay); the general sort-based path must give the same bytes, and both the oracle's."""
+    import os
+    e = gen.plain_events(n, n_ids, 500 + n_ids % 101)
+    init = gen.below(gen.draws(n, 80, 0, n_ids), 4).astype(np.uint8)
+    assert_parity(ctx, e, n_ids, init=init, label=f"bucket path {n}x{n_ids}")
+    os.environ["VC_GENERAL_PATH"] = "1"
+    try:
+        assert_parity(ctx, e, n_ids, init=init, label=f"general path {n}x{n_ids}")
+    finally:
+        del os.environ["VC_GENERAL_PATH"]
+
+
+def test_bucket_path_skewed_ids(ctx):
+    """Most events on a few ids of one bucket, the rest spread thin (long chains of
+    tiles inside one bucket, many nearly empty buckets)."""
+    n, n_ids = 3_000_000, 1 << 20
+    e = gen.plain_events(n, n_ids, 77)
+    hot = gen.plain_events(n, 50, 78)
+    pick = gen.below(gen.draws(77, 81, 0, n), 10) < 8
+    e = np.where(pick, hot, e).astype(np.uint32)
+    assert_parity(ctx, e, n_ids, label="skewed")

@@ -134,3 +134,24 @@ def test_translation_component_workload_full_size(ctx):
     ct = gen.component_trace(1 << 23, 1 << 20, 0)
     ref = assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, label="full 2^23")
     assert ref.violations.size == 0
+
+
+@pytest.mark.parametrize("n_comp,n_vars", [(5000, 64), (100_000, 1 << 14), (400_000, 1 << 20)])
+def test_fused_and_unfused_check_agree(ctx, n_comp, n_vars):
+    """Canonical bodies: the check fused into the emission equals translating first and
+    checking the translated trace as a plain trace."""
+    import os
+    ct = gen.component_trace(n_comp, n_vars, 9)
+    fused = gpu_translate(ctx, ct.comp_off, ct.decls, ct.n_vars)
+    os.environ["VC_UNFUSED"] = "1"
+    try:
+        unfused = gpu_translate(ctx, ct.comp_off, ct.decls, ct.n_vars)
+    finally:
+        del os.environ["VC_UNFUSED"]
+    assert np.array_equal(fused.events(), unfused.events())
+    assert np.array_equal(fused.status(), unfused.status())
+    assert np.array_equal(fused.final(), unfused.final())
+    ref = O.check(O.translate(ct.comp_off, ct.decls, ct.n_vars), 2 * ct.n_vars)
+    assert np.array_equal(fused.status(), ref.status) and np.array_equal(fused.final(), ref.final)
+    fused.free()
+    unfused.free()
