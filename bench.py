@@ -191,7 +191,21 @@ def wl_overlap(args, V, ctx, stream):
                 per_unit=lambda: bytes_alg() / n)
 
 
+def copy_probe(torch, n_words=1 << 28):
+    """One plain elementwise kernel of known traffic (reads and writes 4 * n_words bytes),
+    launched before the workload so that a hardware-counter run of this script also
+    holds the calibration of FETCH_SIZE / WRITE_SIZE against known bytes."""
+    x = torch.ones(n_words, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    return 4 * n_words
+
+
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
+             "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
              "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap}
 
 
@@ -205,6 +219,8 @@ def main():
     ap.add_argument("--comp-log2", type=int, default=23)
     ap.add_argument("--plain-log2", type=int, default=28)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="launch one 1 GiB elementwise kernel first (calibrates hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the checker is a single-GPU path); --gpus {args.gpus} "
@@ -215,6 +231,8 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     ctx = V.Context(0, stream)
+    if args.copy_probe:
+        log(f"[bench] copy probe: {copy_probe(torch)} bytes read and written")
     w = WORKLOADS[args.workload](args, V, ctx, stream)
 
     for _ in range(args.warmup):
