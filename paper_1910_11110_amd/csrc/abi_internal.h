@@ -31,6 +31,8 @@ struct TranslateState {
     uint32_t *decls = nullptr, *body = nullptr;
     vc::Control *ctl = nullptr;
     DevBuf cnt, pos, pre_abs, items_a, items_b, scratch, final_abs;
+    uint64_t *host_total = nullptr;   // pinned: translated size, read while the scan runs
+    hipEvent_t total_ready = nullptr; // recorded after the size copy
 };
 
 struct vc_ctx {

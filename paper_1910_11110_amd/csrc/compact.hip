@@ -56,26 +56,13 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint8_t *__restrict__ s
     }
     uint32_t off = woff + inc - cnt;
 
-    if (tid == 0) {
-        uint64_t *my = lb + tile;
-        uint64_t excl = 0;
-        if (tile == 0) {
-            lb_store(my, LB_INC | total);
-        } else {
-            lb_store(my, LB_AGG | total);
-            int64_t t = (int64_t)tile - 1;
-            while (true) {
-                uint64_t w = lb_wait(&lb[t]);
-                excl += w & LB_VAL;
-                if ((w >> 62) == 2)
-                    break;
-                t--;
-            }
-            lb_store(my, LB_INC | (excl + total));
+    if (wave == 0) {
+        const uint64_t excl = lb_count_exclusive(lb, tile, total);
+        if (lane == 0) {
+            s_excl = excl;
+            if (base + CTILE >= n)
+                ctl->n_viol = excl + total;
         }
-        s_excl = excl;
-        if (base + CTILE >= n)
-            ctl->n_viol = excl + total;
     }
     uint32_t k = off;
     while (bits) {

@@ -149,12 +149,137 @@ __device__ __forceinline__ void lb_store(uint64_t *p, uint64_t w)
     __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ uint64_t lb_wait(const uint64_t *p)
 {
     uint64_t w;
     while (((w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 62) == 0)
         __builtin_amdgcn_s_sleep(1);
     return w;
+}
+
+// Additive look-back run by one whole wave: publishes `total` for `tile` and returns
+// the sum over all earlier tiles.  Lane q polls tile t - q, so one round folds up to
+// 64 predecessors, stopping at the nearest inclusive word (taken) or the nearest
+// unpublished one (polled again next round).  The result is the same in every lane.
+__device__ __forceinline__ uint64_t lb_count_exclusive(uint64_t *lb, uint64_t tile, uint64_t total)
+{
+    const uint32_t lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0)
+            lb_store(&lb[0], LB_INC | total);
+        return 0;
+    }
+    if (lane == 0)
+        lb_store(&lb[tile], LB_AGG | total);
+    uint64_t excl = 0;
+    int64_t t = (int64_t)tile - 1;
+    for (;;) {
+        const int64_t mt = t - (int64_t)lane;
+        const uint64_t w = mt >= 0 ? lb_load(&lb[mt]) : LB_INC;
+        const uint32_t fl = (uint32_t)(w >> 62);
+        const uint64_t stop = __ballot(fl != 1);
+        const uint64_t incm = __ballot(fl == 2);
+        const uint32_t s = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
+        const bool inc_at_s = s < 64 && ((incm >> s) & 1ull);
+        uint64_t v = (lane < s || (lane == s && inc_at_s)) ? (w & LB_VAL) : 0ull;
+#pragma unroll
+        for (int dd = 1; dd < WAVE; dd <<= 1)
+            v += __shfl_xor(v, dd);
+        excl += v;
+        if (inc_at_s)
+            break;
+        if (s == 0)
+            __builtin_amdgcn_s_sleep(1);
+        t -= (int64_t)s;
+    }
+    if (lane == 0)
+        lb_store(&lb[tile], LB_INC | (excl + total));
+    return excl;
+}
+
+// Look-back over transition functions run by one whole wave: publishes the tile's
+// aggregate `tagg` (4-byte form) and returns the composition of all earlier tiles'
+// functions.  Words hold functions in packed 8-bit form; lane q polls tile t - q and
+// the lanes' functions are composed in order (lane 0 = latest) by a shuffle tree.
+__device__ __forceinline__ uint32_t lb_fn_exclusive(uint64_t *lb, uint64_t tile, uint32_t tagg)
+{
+    const uint32_t lane = lane_id();
+    if (tile == 0) {
+        if (lane == 0)
+            lb_store(&lb[0], LB_INC | fpack(tagg));
+        return F_ID;
+    }
+    if (lane == 0)
+        lb_store(&lb[tile], LB_AGG | fpack(tagg));
+    uint32_t carry = F_ID;
+    int64_t t = (int64_t)tile - 1;
+    for (;;) {
+        const int64_t mt = t - (int64_t)lane;
+        const uint64_t w = mt >= 0 ? lb_load(&lb[mt]) : (LB_INC | 0xE4u);
+        const uint32_t fl = (uint32_t)(w >> 62);
+        const uint64_t stop = __ballot(fl != 1);
+        const uint64_t incm = __ballot(fl == 2);
+        const uint32_t s = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
+        const bool inc_at_s = s < 64 && ((incm >> s) & 1ull);
+        uint32_t f = (lane < s || (lane == s && inc_at_s)) ? funpack((uint32_t)(w & 0xFFu)) : F_ID;
+        // lane i ends with f_i o f_(i+1) o ... over its block; lane 0 holds the whole fold
+#pragma unroll
+        for (int dd = 1; dd < WAVE; dd <<= 1) {
+            const uint32_t g = __shfl_down(f, dd);
+            if (lane + dd < WAVE)
+                f = fcompose(f, g);
+        }
+        carry = fcompose(carry, __shfl(f, 0));
+        if (inc_at_s)
+            break;
+        if (s == 0)
+            __builtin_amdgcn_s_sleep(1);
+        t -= (int64_t)s;
+    }
+    if (lane == 0)
+        lb_store(&lb[tile], LB_INC | fpack(fcompose(tagg, carry)));
+    return carry;
+}
+
+// Per-thread additive look-back over one column of a chain of tiles (word of tile u at
+// lb[u * stride]): the sum from tile t down to the nearest inclusive word, never below
+// first_tile (which always publishes an inclusive word).  Reads WIN tiles per round.
+template <int WIN>
+__device__ __forceinline__ uint64_t lb_column_sum(const uint64_t *lb, uint64_t stride, int64_t first_tile, int64_t t)
+{
+    uint64_t excl = 0;
+    for (;;) {
+        uint64_t w[WIN];
+#pragma unroll
+        for (int q = 0; q < WIN; q++)
+            w[q] = t - q >= first_tile ? lb_load(lb + (uint64_t)(t - q) * stride) : 0ull;
+        int adv = 0;
+        bool stop = false, done = false;
+#pragma unroll
+        for (int q = 0; q < WIN; q++) {
+            const uint32_t fl = (uint32_t)(w[q] >> 62);
+            if (!stop) {
+                if (fl == 0) {
+                    stop = true;
+                } else {
+                    excl += w[q] & LB_VAL;
+                    adv++;
+                    if (fl == 2)
+                        done = stop = true;
+                }
+            }
+        }
+        if (done)
+            return excl;
+        if (adv == 0)
+            __builtin_amdgcn_s_sleep(1);
+        t -= adv;
+    }
 }
 
 // dynamic tile ticket: tiles start in index order, so a tile only waits on tiles

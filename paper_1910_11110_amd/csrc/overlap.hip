@@ -177,7 +177,7 @@ int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int k
     VC_TRY(hipMalloc(&pofs, (size_t)(n + 1) * 8));
     VC_TRY(hipMalloc(&scratch, sc));
     {
-        ProfScope prof_(s, "sweep_items");
+        ProfScope prof_(s, "interval_items");
         k_interval_items<<<blocks_for(n), BLOCK, 0, s>>>(lo, hi, n, a, ctl);
     }
     {
@@ -211,7 +211,7 @@ int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int k
             uint64_t *other = by_nbr == pa ? pb : pa;
             uint64_t *by_owner = sort_items(by_nbr, other, m, idb, scratch, ctl, s);
             {
-                ProfScope prof_(s, "sweep_csr");
+                ProfScope prof_(s, "csr");
                 k_csr<<<blocks_for(m + 1), BLOCK, 0, s>>>(by_owner, m, n, out->off, out->nbr);
             }
         } else {
@@ -247,7 +247,7 @@ void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
 {
     if (n)
         {
-            ProfScope prof_(s, "overlap_count");
+            ProfScope prof_(s, "expand_count");
             k_expand_count<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, cnt, index_base, ctl);
         }
 }
@@ -258,7 +258,7 @@ void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, cons
 {
     if (n)
         {
-            ProfScope prof_(s, "overlap_emit");
+            ProfScope prof_(s, "expand_emit");
             k_expand_emit<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, pos, items, cap,
                                                                      key_base, payload_base, trace_index, ctl);
         }

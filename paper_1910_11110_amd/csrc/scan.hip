@@ -98,24 +98,10 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
     }
     uint32_t texc = fcompose(wexc, wpre);
 
-    if (tid == 0) {
-        uint64_t *my = lb + tile;
-        uint32_t carry = F_ID;
-        if (tile == 0) {
-            lb_store(my, LB_INC | fpack(tagg));
-        } else {
-            lb_store(my, LB_AGG | fpack(tagg));
-            int64_t t = (int64_t)tile - 1;
-            while (true) {
-                uint64_t w = lb_wait(&lb[t]);
-                carry = fcompose(carry, funpack((uint32_t)(w & 0xFFu)));
-                if ((w >> 62) == 2)
-                    break;
-                t--;
-            }
-            lb_store(my, LB_INC | fpack(fcompose(tagg, carry)));
-        }
-        s_carry = carry;
+    if (wave == 0) {
+        const uint32_t carry = lb_fn_exclusive(lb, tile, tagg);
+        if (lane == 0)
+            s_carry = carry;
     }
     __syncthreads();
 

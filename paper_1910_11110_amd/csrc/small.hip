@@ -25,6 +25,7 @@ constexpr int SE = 16;               // events per thread
 constexpr int STILE = BLOCK * SE;    // events per tile
 constexpr int SROW = SK + 1;         // padded table row (words)
 constexpr int SWORDS = (SK + 6) / 7; // look-back words per tile
+constexpr int SLB_WIN = 8;           // predecessors read per look-back round
 
 __device__ __forceinline__ uint64_t pack7(const uint8_t *b)
 {
@@ -99,28 +100,54 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
             fc[j] = (valid >> j) & 1u ? fcode(op, side) : fcode(OP_NOOP, 0);
         }
 
-        // ---- phase 1: each thread's composition per variable --------------------------
+        // ---- phase 1: each thread's composition per variable, in registers -------------
+        // before[j]: composition of this thread's earlier events on key[j] (identity if
+        // none); the last event of each key writes the thread's aggregate for that key
+        uint32_t before[SE];
+        uint32_t agg[SE];
+#pragma unroll
+        for (int j = 0; j < SE; j++) {
+            uint32_t acc = F_ID;
+#pragma unroll
+            for (int i = 0; i < j; i++)
+                acc = key[i] == key[j] ? agg[i] : acc;
+            before[j] = acc;
+            agg[j] = fcompose(s_f4[fc[j]], acc);
+        }
         uint32_t *row = s_tab + tid * SROW;
 #pragma unroll
         for (int k = 0; k < SK; k++)
             row[k] = F_ID;
 #pragma unroll
-        for (int j = 0; j < SE; j++)
-            row[key[j]] = fcompose(s_f4[fc[j]], row[key[j]]);
+        for (int j = 0; j < SE; j++) {
+            bool last = true;
+#pragma unroll
+            for (int i = j + 1; i < SE; i++)
+                last = last && key[i] != key[j];
+            if (last)
+                row[key[j]] = agg[j];
+        }
         __syncthreads();
 
         // ---- phase 2: per-variable exclusive scan over the threads --------------------
-        // wave q scans threads 64q .. 64q+63 for variable `lane`
+        // wave q scans threads 64q .. 64q+63 for variable `lane`: all reads first, the
+        // composition chain in registers, then all writes
         {
-            uint32_t acc = F_ID;
             const uint32_t q = wave;
+            uint32_t v[WAVE];
+#pragma unroll
+            for (int i = 0; i < WAVE; i++)
+                v[i] = s_tab[(q * WAVE + i) * SROW + lane];
+            uint32_t acc = F_ID;
 #pragma unroll
             for (int i = 0; i < WAVE; i++) {
-                uint32_t *cell = s_tab + (q * WAVE + i) * SROW + lane;
-                uint32_t f = *cell;
-                *cell = acc; // exclusive within the quarter
+                uint32_t f = v[i];
+                v[i] = acc; // exclusive within the quarter
                 acc = fcompose(f, acc);
             }
+#pragma unroll
+            for (int i = 0; i < WAVE; i++)
+                s_tab[(q * WAVE + i) * SROW + lane] = v[i];
             s_q[q][lane] = acc;
         }
         __syncthreads();
@@ -153,21 +180,41 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
                 }
             } else {
                 lb_store(my, LB_AGG | pack7(agg7));
+                // a round reads SLB_WIN predecessors at once and folds them up to the
+                // nearest inclusive word; an unpublished word ends the round early
                 int64_t t = (int64_t)tile - 1;
-                while (true) {
-                    uint64_t w = lb_wait(lbv + (uint64_t)t * SWORDS + tid);
-                    bool inc = (w >> 62) == 2;
+                bool done = false;
+                while (!done) {
+                    uint64_t w[SLB_WIN];
 #pragma unroll
-                    for (int i = 0; i < 7; i++) {
-                        uint32_t b = (uint32_t)(w >> (8 * i)) & 0xFFu;
-                        if (inc)
-                            st7[i] = (uint8_t)fapply(acc4[i], b);
-                        else
-                            acc4[i] = fcompose(acc4[i], funpack(b));
+                    for (int q = 0; q < SLB_WIN; q++)
+                        w[q] = t - q >= 0 ? lb_load(lbv + (uint64_t)(t - q) * SWORDS + tid) : 0ull;
+                    int adv = 0;
+                    bool stop = false;
+#pragma unroll
+                    for (int q = 0; q < SLB_WIN; q++) {
+                        const uint32_t fl = (uint32_t)(w[q] >> 62);
+                        if (!stop) {
+                            if (fl == 0) {
+                                stop = true;
+                            } else if (fl == 2) {
+#pragma unroll
+                                for (int i = 0; i < 7; i++)
+                                    st7[i] = (uint8_t)fapply(acc4[i], (uint32_t)(w[q] >> (8 * i)) & 0xFFu);
+                                done = stop = true;
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < 7; i++)
+                                    acc4[i] = fcompose(acc4[i], funpack((uint32_t)(w[q] >> (8 * i)) & 0xFFu));
+                                adv++;
+                            }
+                        }
                     }
-                    if (inc)
-                        break;
-                    t--;
+                    if (!done) {
+                        if (adv == 0)
+                            __builtin_amdgcn_s_sleep(1);
+                        t -= adv;
+                    }
                 }
             }
             uint8_t inc7[7];
@@ -200,18 +247,19 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
         __syncthreads();
 
         // ---- phase 3: replay each thread's events ------------------------------------
-        // the row becomes the statuses entering this thread's events
-#pragma unroll
-        for (int k = 0; k < SK; k++)
-            row[k] = fapply(row[k], s_qin[wave][k]);
+        // status of key[j] entering this thread = (thread's exclusive prefix)(status
+        // entering the quarter); then the thread's own earlier events on that key
         uint32_t out[4] = { 0, 0, 0, 0 };
         uint32_t flags = 0;
+        uint32_t enter[SE];
+#pragma unroll
+        for (int j = 0; j < SE; j++)
+            enter[j] = fapply(row[key[j]], s_qin[wave][key[j]]);
 #pragma unroll
         for (int j = 0; j < SE; j++) {
-            uint32_t pre = row[key[j]];
+            uint32_t pre = fapply(before[j], enter[j]);
             uint32_t post = fapply(s_f4[fc[j]], pre);
             uint32_t flag = (s_stuck[fc[j]] >> pre) & 1u & ((valid >> j) & 1u);
-            row[key[j]] = post;
             out[j >> 2] |= (post | (pre << 2) | (flag << 7)) << (8 * (j & 3));
             flags |= flag << j;
         }
@@ -235,26 +283,13 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
                 woff += s_wsum[w];
             total += s_wsum[w];
         }
-        if (tid == 0) {
-            uint64_t *my = lbc + tile;
-            uint64_t excl = 0;
-            if (tile == 0) {
-                lb_store(my, LB_INC | total);
-            } else {
-                lb_store(my, LB_AGG | total);
-                int64_t t = (int64_t)tile - 1;
-                while (true) {
-                    uint64_t w = lb_wait(&lbc[t]);
-                    excl += w & LB_VAL;
-                    if ((w >> 62) == 2)
-                        break;
-                    t--;
-                }
-                lb_store(my, LB_INC | (excl + total));
+        if (wave == 0) {
+            const uint64_t excl = lb_count_exclusive(lbc, tile, total);
+            if (lane == 0) {
+                s_vexcl = excl;
+                if (tile + 1 == ntiles)
+                    ctl->n_viol = excl + total;
             }
-            s_vexcl = excl;
-            if (tile + 1 == ntiles)
-                ctl->n_viol = excl + total;
         }
         __syncthreads();
         uint64_t o = s_vexcl + woff + inc - cnt;

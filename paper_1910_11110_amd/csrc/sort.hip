@@ -152,7 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict_
         if (valid)
             prev = s_cnt[wave][d];
         if (valid && r == 0)
-            s_cnt[wave][d] = prev + c;
+            atomicAdd(&s_cnt[wave][d], c);
         rank[j] = prev + r;
     }
     __syncthreads();
@@ -188,14 +188,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict_
     // look-back: exclusive prefix of this digit over earlier tiles
     uint64_t excl = 0;
     if (tile > 0) {
-        int64_t t = (int64_t)tile - 1;
-        while (true) {
-            uint64_t w = lb_wait(&lb[(uint64_t)t * RADIX + d]);
-            excl += w & LB_VAL;
-            if ((w >> 62) == 2)
-                break;
-            t--;
-        }
+        excl = lb_column_sum<8>(lb + d, RADIX, 0, (int64_t)tile - 1);
         lb_store(&my[d], LB_INC | (excl + tile_cnt));
     }
     // global digit base (exclusive scan of the histogram over digits)
@@ -275,7 +268,7 @@ void launch_make_items_events(const uint32_t *events, uint64_t n, uint32_t n_ids
 {
     if (n)
         {
-            ProfScope prof_(s, "make_items");
+            ProfScope prof_(s, "make_items_events");
             k_make_items_events<<<grid_for(n, 8), BLOCK, 0, s>>>(events, n, n_ids, items, ctl, key_base, payload_base);
         }
 }
@@ -300,7 +293,7 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
     uint64_t tiles = ceil_div(n, SORT_TILE);
     launch_fill_u32(&sc->hist[0][0], 0, MAX_PASSES * RADIX, s);
     {
-        ProfScope prof_(s, "sort_histogram");
+        ProfScope prof_(s, "hist");
         k_hist<<<grid_for(n, 16), BLOCK, 0, s>>>(a, n, passes, bits, &sc->hist[0][0]);
     }
     uint64_t *src = a, *dst = b;

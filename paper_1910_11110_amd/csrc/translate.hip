@@ -155,15 +155,62 @@ __global__ void k_translate_emit(const uint64_t *__restrict__ comp_off, uint64_t
     }
 }
 
-// Fused translation + check for canonical bodies.  One workgroup writes 256
-// consecutive components: every thread expands its component's declarations into
-// the translated events and evaluates them on the statuses of v and v# (both equal
-// to the abstract variable's status before the declaration: a canonical body applies
-// to v exactly the function the translation applies to v#, so the two agree at every
-// declaration from the common initial (V,I)), staging events and status bytes in LDS
-// so that the workgroup's output range is written contiguously.
+// Fused translation + check for canonical bodies.  Every event is evaluated on the
+// statuses of v and v#, both equal to the abstract variable's status before the
+// declaration (a canonical body applies to v exactly the function the translation
+// applies to v#, so the two agree at every declaration from the common initial
+// (V,I)).  One workgroup writes 256 consecutive components.
 constexpr EffectTable TABLE = make_table();
-constexpr int FUSED_CAP = 256 * 40; // 8 RW declarations of 5 events per component
+constexpr int FUSED_COMPS = BLOCK;             // components per workgroup
+constexpr int FUSED_DCAP = 2048;               // declarations staged per workgroup
+constexpr int FD_ITEMS = FUSED_DCAP / BLOCK;   // declarations per thread (contiguous run)
+constexpr int FUSED_CAP = 6144;                // events staged per workgroup
+
+struct FusedTables {
+    uint32_t f4[16], stuck[16];
+};
+
+// the events of one declaration: its [[M]] slot at slot_p, its body at body_p
+// (positions relative to `dst`); `st` is the status of v and v# before it
+__device__ __forceinline__ void emit_decl(uint32_t wd, uint32_t n_vars, uint32_t st, uint64_t slot_p, uint64_t body_p,
+                                          uint64_t end, uint32_t *ev, uint8_t *stat, const FusedTables &T)
+{
+    uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
+    if (!decl_ok(wd, n_vars)) {
+        v = 0;
+        mode = 0;
+    }
+    auto put = [&](uint64_t &p, uint32_t id, uint32_t op, uint32_t sd, uint32_t &s) {
+        const uint32_t fc = fcode(op, sd);
+        const uint32_t post = fapply(T.f4[fc], s);
+        const uint32_t flag = (T.stuck[fc] >> s) & 1u;
+        if (p < end) {
+            ev[p] = id | (op << 24) | (sd << 27);
+            stat[p] = (uint8_t)(post | (s << 2) | (flag << 7));
+        }
+        p++;
+        s = post;
+    };
+    uint32_t sa = st, sr = st;
+    const bool reads = mode == 0 || mode == 2, writes = mode == 1 || mode == 2;
+    if (reads) {
+        if ((st >> side) & 1u) {
+            put(slot_p, v, OP_NOOP, side, sr);
+            put(slot_p, n_vars + v, OP_NOOP, side, sa);
+        } else {
+            const uint32_t t = side ? OP_PUSH : OP_PULL;
+            put(slot_p, v, t, 0, sr);
+            put(slot_p, n_vars + v, t, 0, sa);
+        }
+    }
+    if (writes)
+        put(slot_p, n_vars + v, OP_W, side, sa);
+    // the body acts on v from its status after the guard
+    if (reads)
+        put(body_p, v, OP_R, side, sr);
+    if (writes)
+        put(body_p, v, OP_W, side, sr);
+}
 
 __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *__restrict__ comp_off, uint64_t n_comp,
                                                                const uint32_t *__restrict__ decls, uint64_t n_decl,
@@ -173,89 +220,141 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
 {
     __shared__ uint32_t s_ev[FUSED_CAP];
     __shared__ uint8_t s_st[FUSED_CAP];
-    __shared__ uint32_t s_f4[16], s_stuck[16];
-    const uint32_t tid = threadIdx.x;
+    __shared__ uint32_t s_decl[FUSED_DCAP];
+    __shared__ uint32_t s_scan[FUSED_DCAP + 1]; // exclusive prefix of (slot arity | body arity << 16)
+    __shared__ uint8_t s_pre[FUSED_DCAP];
+    __shared__ uint64_t s_coff[FUSED_COMPS + 1], s_pos[FUSED_COMPS + 1];
+    __shared__ uint32_t s_wsum[BLOCK / WAVE];
+    __shared__ FusedTables T;
+
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     if (tid < 16) {
-        s_f4[tid] = TABLE.f4[tid];
-        s_stuck[tid] = TABLE.stuck[tid];
+        T.f4[tid] = TABLE.f4[tid];
+        T.stuck[tid] = TABLE.stuck[tid];
     }
-    const uint64_t c0 = (uint64_t)blockIdx.x * BLOCK;
-    const uint64_t cend = c0 + BLOCK < n_comp ? c0 + BLOCK : n_comp;
-    const uint64_t base = pos[c0];
-    const uint64_t range = pos[cend] - base;
-    const bool staged = range <= (uint64_t)FUSED_CAP;
+    const uint64_t c0 = (uint64_t)blockIdx.x * FUSED_COMPS;
+    const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
+    for (uint32_t i = tid; i <= nc; i += BLOCK) {
+        s_coff[i] = comp_off[c0 + i];
+        s_pos[i] = pos[c0 + i];
+    }
     __syncthreads();
-    const uint64_t c = c0 + tid;
-    if (c < n_comp) {
-        uint64_t a = comp_off[c], b = comp_off[c + 1];
-        uint64_t p = pos[c] - base, end = pos[c + 1] - base;
-        if (b >= a && b <= n_decl) {
-            auto put = [&](uint32_t id, uint32_t op, uint32_t side, uint32_t &st) {
-                uint32_t fc = fcode(op, side);
-                uint32_t post = fapply(s_f4[fc], st);
-                uint32_t flag = (s_stuck[fc] >> st) & 1u;
-                uint32_t w = id | (op << 24) | (side << 27);
-                uint8_t sb = (uint8_t)(post | (st << 2) | (flag << 7));
-                if (p < end) {
-                    if (staged) {
-                        s_ev[p] = w;
-                        s_st[p] = sb;
-                    } else {
-                        out[base + p] = w;
-                        status[base + p] = sb;
-                    }
+    // staged path: offsets non-decreasing inside [0, n_decl], and few enough
+    // declarations and events to stage
+    bool bad = false;
+    for (uint32_t i = tid; i < nc; i += BLOCK)
+        bad |= s_coff[i + 1] < s_coff[i] || s_pos[i + 1] < s_pos[i];
+    if (tid == 0)
+        bad |= s_coff[nc] > n_decl || s_coff[nc] - s_coff[0] > (uint64_t)FUSED_DCAP ||
+               s_pos[nc] - s_pos[0] > (uint64_t)FUSED_CAP;
+    if (__syncthreads_or(bad)) {
+        // one component per thread, written in place
+        if (tid < nc) {
+            const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
+            if (b >= a && b <= n_decl) {
+                const uint64_t p0 = s_pos[tid], end = s_pos[tid + 1];
+                uint64_t slot = p0;
+                for (uint64_t d = a; d < b; d++) {
+                    uint32_t mode = (decls[d] >> 24) & 3u;
+                    mode = decl_ok(decls[d], n_vars) ? mode : 0u;
+                    slot += slot_arity(mode);
                 }
-                p++;
-                st = post;
-            };
-            // [[M]] of every declaration, then the canonical bodies
-            for (uint64_t d = a; d < b; d++) {
-                uint32_t wd = decls[d];
-                uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
-                if (!decl_ok(wd, n_vars)) {
-                    v = 0;
-                    mode = 0;
+                uint64_t sp = p0, bp = slot;
+                for (uint64_t d = a; d < b; d++) {
+                    const uint32_t wd = decls[d];
+                    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                    emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, T);
+                    sp += slot_arity(mode);
+                    bp += body_arity(mode);
                 }
-                uint32_t sa = pre_abs[d], sr = sa;
-                if (mode == 0 || mode == 2) {
-                    bool valid = (sa >> side) & 1u;
-                    if (valid) {
-                        put(v, OP_NOOP, side, sr);
-                        put(n_vars + v, OP_NOOP, side, sa);
-                    } else {
-                        uint32_t t = side ? OP_PUSH : OP_PULL;
-                        put(v, t, 0, sr);
-                        put(n_vars + v, t, 0, sa);
-                    }
-                }
-                if (mode == 1 || mode == 2)
-                    put(n_vars + v, OP_W, side, sa);
             }
-            for (uint64_t d = a; d < b; d++) {
-                uint32_t wd = decls[d];
-                uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
-                if (!decl_ok(wd, n_vars)) {
-                    v = 0;
-                    mode = 0;
-                }
-                // the real variable's status after [[M]]: the guard's transfer, if any
-                uint32_t sr = pre_abs[d];
-                if ((mode == 0 || mode == 2) && !((sr >> side) & 1u))
-                    sr = fapply(s_f4[fcode(side ? OP_PUSH : OP_PULL, 0)], sr);
-                if (mode == 0 || mode == 2)
-                    put(v, OP_R, side, sr);
-                if (mode == 1 || mode == 2)
-                    put(v, OP_W, side, sr);
-            }
+        }
+        return;
+    }
+    const uint64_t d_lo = s_coff[0];
+    const uint32_t nd = (uint32_t)(s_coff[nc] - d_lo);
+    const uint64_t ebase = s_pos[0];
+    const uint32_t range = (uint32_t)(s_pos[nc] - ebase);
+    for (uint32_t i = tid; i < nd; i += BLOCK) {
+        s_decl[i] = decls[d_lo + i];
+        s_pre[i] = pre_abs[d_lo + i];
+    }
+    __syncthreads();
+    // arities of the thread's run of declarations, block-wide exclusive scan
+    const uint32_t i0 = tid * FD_ITEMS;
+    uint32_t pk[FD_ITEMS];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < FD_ITEMS; j++) {
+        const uint32_t i = i0 + j;
+        uint32_t m = 0;
+        if (i < nd) {
+            const uint32_t wd = s_decl[i];
+            const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+            m = slot_arity(mode) | (body_arity(mode) << 16);
+        }
+        pk[j] = m;
+        run += m;
+    }
+    const uint32_t inc = wave_scan_add(run, lane);
+    if (lane == WAVE - 1)
+        s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t ex = inc - run;
+    for (uint32_t w = 0; w < wave; w++)
+        ex += s_wsum[w];
+#pragma unroll
+    for (int j = 0; j < FD_ITEMS; j++) {
+        const uint32_t i = i0 + j;
+        if (i < nd)
+            s_scan[i] = ex;
+        ex += pk[j];
+    }
+    if (tid == BLOCK - 1)
+        s_scan[nd] = ex;
+    __syncthreads();
+    // emit: the component of the run's first declaration by binary search, then forward
+    if (i0 < nd) {
+        uint32_t lo = 0, hi = nc; // largest j with s_coff[j] - d_lo <= i0
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_coff[mid] - d_lo <= i0)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        uint32_t j = lo;
+        for (int k = 0; k < FD_ITEMS; k++) {
+            const uint32_t i = i0 + k;
+            if (i >= nd)
+                break;
+            while (j + 1 < nc && s_coff[j + 1] - d_lo <= i)
+                j++;
+            const uint32_t cs = (uint32_t)(s_coff[j] - d_lo), ce = (uint32_t)(s_coff[j + 1] - d_lo);
+            const uint32_t base_c = s_scan[cs];
+            const uint32_t pre = s_scan[i] - base_c, tot = s_scan[ce] - base_c;
+            const uint64_t pe = s_pos[j] - ebase, end = s_pos[j + 1] - ebase;
+            emit_decl(s_decl[i], n_vars, s_pre[i], pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16), end,
+                            s_ev, s_st, T);
         }
     }
     __syncthreads();
-    if (staged) {
-        for (uint64_t i = tid; i < range; i += BLOCK) {
-            out[base + i] = s_ev[i];
-            status[base + i] = s_st[i];
-        }
+    for (uint32_t i = tid; i < range; i += BLOCK)
+        out[ebase + i] = s_ev[i];
+    // status bytes: unaligned head, 4-byte words, tail
+    const uint32_t head = (uint32_t)((4u - (ebase & 3u)) & 3u) < range ? (uint32_t)((4u - (ebase & 3u)) & 3u) : range;
+    const uint32_t nwords = (range - head) / 4;
+    if (tid < head)
+        status[ebase + tid] = s_st[tid];
+    uint32_t *sw = reinterpret_cast<uint32_t *>(status + ebase + head);
+    for (uint32_t k = tid; k < nwords; k += BLOCK) {
+        const uint32_t q = head + 4 * k;
+        sw[k] = (uint32_t)s_st[q] | ((uint32_t)s_st[q + 1] << 8) | ((uint32_t)s_st[q + 2] << 16) |
+                ((uint32_t)s_st[q + 3] << 24);
     }
+    const uint32_t tail0 = head + 4 * nwords;
+    if (tid < range - tail0)
+        status[ebase + tail0 + tid] = s_st[tail0 + tid];
 }
 
 unsigned grid_n(uint64_t n, unsigned per)
@@ -273,7 +372,7 @@ void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, cons
     if (!n_comp)
         return;
     ProfScope prof_(s, "translate_emit_fused");
-    k_translate_emit_fused<<<(unsigned)ceil_div(n_comp, BLOCK), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars,
+    k_translate_emit_fused<<<(unsigned)ceil_div(n_comp, FUSED_COMPS), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars,
                                                                                pre_abs, pos, out, status);
 }
 
@@ -282,7 +381,7 @@ void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_
 {
     if (n_decl)
         {
-            ProfScope prof_(s, "translate_items");
+            ProfScope prof_(s, "make_items_decls");
             k_make_items_decls<<<grid_n(n_decl, BLOCK * 8), BLOCK, 0, s>>>(decls, n_decl, n_vars, items, ctl);
         }
 }

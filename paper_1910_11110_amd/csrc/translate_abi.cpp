@@ -81,15 +81,44 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
                            scan_scratch_bytes(n_decl), excl_scan_scratch_bytes(n_comp) });
     if ((r = devbuf_reserve(tr.scratch, sc)) != VC_OK)
         return r;
+    if (!tr.host_total) {
+        hipError_t e = hipHostMalloc((void **)&tr.host_total, 8, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&tr.total_ready, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "translation size buffer");
+    }
+    // canonical bodies with the check requested: the check is fused into the emission
+    tr.fused = tr.check && !tr.body_off && bucketed && !getenv("VC_UNFUSED");
+    if (tr.fused) {
+        if ((r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK)
+            return r;
+        launch_fill_u8((uint8_t *)tr.final_abs.p, 1, tr.n_vars, s);
+    }
     launch_reset_control(tr.ctl, s);
     launch_translate_count(tr.comp_off, n_comp, tr.decls, n_decl, tr.body_off, (uint32_t *)tr.cnt.p, tr.ctl, s);
     launch_excl_scan((uint32_t *)tr.cnt.p, n_comp, (uint64_t *)tr.pos.p, nullptr, tr.scratch.p, &tr.ctl->tickets[4], s);
-    uint64_t total = 0;
-    hipError_t e = hipMemcpyAsync(&total, (uint64_t *)tr.pos.p + n_comp, 8, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(tr.host_total, (uint64_t *)tr.pos.p + n_comp, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(s);
+        e = hipEventRecord(tr.total_ready, s);
     if (e != hipSuccess)
         return vc_hip_fail(e, "translation size");
+    // status of each declaration's abstract variable before it (segmented scan); it
+    // does not depend on the translated size, so it runs while the host reads that size
+    if (bucketed) {
+        launch_bucket_decl_pre(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
+                               tr.fused ? (uint8_t *)tr.final_abs.p : nullptr, tr.scratch.p, tr.ctl, s,
+                               t->ctx->cu_count);
+    } else {
+        launch_make_items_decls(tr.decls, n_decl, tr.n_vars, (uint64_t *)tr.items_a.p, tr.ctl, s);
+        uint64_t *sorted = sort_items((uint64_t *)tr.items_a.p, (uint64_t *)tr.items_b.p, n_decl,
+                                      (int)key_bits_for(tr.n_vars), tr.scratch.p, tr.ctl, s);
+        launch_segscan(sorted, n_decl, nullptr, tr.n_vars, SCAN_PRE, (uint8_t *)tr.pre_abs.p, nullptr, tr.scratch.p,
+                       tr.ctl, s);
+    }
+    if ((e = hipEventSynchronize(tr.total_ready)) != hipSuccess)
+        return vc_hip_fail(e, "translation size");
+    const uint64_t total = *tr.host_total;
     if (total >= (1ull << 31))
         return vc_fail(VC_EINVAL, "vc_translate: translated trace of %llu events exceeds 2^31 - 1",
                        (unsigned long long)total);
@@ -104,28 +133,12 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         t->own_events = true;
     }
     t->n = total;
-    // status of each declaration's abstract variable before it (segmented scan)
-    // canonical bodies with the check requested: the check is fused into the emission
-    tr.fused = tr.check && !tr.body_off && bucketed && !getenv("VC_UNFUSED");
     if (tr.fused) {
-        if ((r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK ||
-            (r = devbuf_reserve(t->status, total ? total : 1)) != VC_OK ||
+        if ((r = devbuf_reserve(t->status, total ? total : 1)) != VC_OK ||
             (r = devbuf_reserve(t->fin, 2 * (size_t)tr.n_vars)) != VC_OK ||
             (r = devbuf_reserve(t->viol, (total ? total : 1) * 4)) != VC_OK ||
             (r = devbuf_reserve(t->scratch, compact_scratch_bytes(total))) != VC_OK)
             return r;
-        launch_fill_u8((uint8_t *)tr.final_abs.p, 1, tr.n_vars, s);
-    }
-    if (bucketed) {
-        launch_bucket_decl_pre(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
-                               tr.fused ? (uint8_t *)tr.final_abs.p : nullptr, tr.scratch.p, tr.ctl, s,
-                               t->ctx->cu_count);
-    } else {
-        launch_make_items_decls(tr.decls, n_decl, tr.n_vars, (uint64_t *)tr.items_a.p, tr.ctl, s);
-        uint64_t *sorted = sort_items((uint64_t *)tr.items_a.p, (uint64_t *)tr.items_b.p, n_decl,
-                                      (int)key_bits_for(tr.n_vars), tr.scratch.p, tr.ctl, s);
-        launch_segscan(sorted, n_decl, nullptr, tr.n_vars, SCAN_PRE, (uint8_t *)tr.pre_abs.p, nullptr, tr.scratch.p,
-                       tr.ctl, s);
     }
     if (tr.fused) {
         launch_translate_emit_fused(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
@@ -274,6 +287,10 @@ void translate_release(vc_trace *t)
     devbuf_free(tr.items_b);
     devbuf_free(tr.scratch);
     devbuf_free(tr.final_abs);
+    if (tr.host_total)
+        (void)hipHostFree(tr.host_total);
+    if (tr.total_ready)
+        (void)hipEventDestroy(tr.total_ready);
     delete t->tr;
     t->tr = nullptr;
 }

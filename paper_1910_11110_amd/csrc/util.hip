@@ -41,28 +41,15 @@ __global__ __launch_bounds__(BLOCK) void k_excl_scan(const uint32_t *__restrict_
             woff += s_wsum[w];
         tot += s_wsum[w];
     }
-    if (tid == 0) {
-        uint64_t *my = lb + tile;
-        uint64_t excl = 0;
-        if (tile == 0) {
-            lb_store(my, LB_INC | tot);
-        } else {
-            lb_store(my, LB_AGG | tot);
-            int64_t t = (int64_t)tile - 1;
-            while (true) {
-                uint64_t w = lb_wait(&lb[t]);
-                excl += w & LB_VAL;
-                if ((w >> 62) == 2)
-                    break;
-                t--;
+    if (wave == 0) {
+        const uint64_t excl = lb_count_exclusive(lb, tile, tot);
+        if (lane == 0) {
+            s_excl = excl;
+            if ((uint64_t)(tile + 1) * XTILE >= n) {
+                out[n] = excl + tot;
+                if (total)
+                    *total = excl + tot;
             }
-            lb_store(my, LB_INC | (excl + tot));
-        }
-        s_excl = excl;
-        if ((uint64_t)(tile + 1) * XTILE >= n) {
-            out[n] = excl + tot;
-            if (total)
-                *total = excl + tot;
         }
     }
     __syncthreads();

@@ -77,6 +77,16 @@ def test_translation_shapes(ctx, n_comp, n_vars):
     assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, label=f"{n_comp}x{n_vars}")
 
 
+@pytest.mark.parametrize("n_comp,n_vars,kmax", [(50_000, 1 << 12, 14), (20_000, 1 << 10, 40)])
+def test_translation_wide_components(ctx, n_comp, n_vars, kmax):
+    """Components with up to 14 or 40 declarations: workgroups of 256 components whose
+    declarations or events exceed what the fused emitter stages take the in-place path,
+    the others the staged one (kmax 14 mixes both, kmax 40 is all in place)."""
+    ct = gen.component_trace(n_comp, n_vars, 17 + kmax, kmax=kmax)
+    ref = assert_translation(ctx, ct.comp_off, ct.decls, ct.n_vars, label=f"{n_comp}x{n_vars} kmax {kmax}")
+    assert ref.violations.size == 0
+
+
 def test_translation_empty_components(ctx):
     co = np.array([0, 0, 2, 2, 3, 3], np.uint64)
     de = np.array([decl("R", "GPU", 0), decl("W", "CPU", 1), decl("RW", "GPU", 1)], np.uint32)
