@@ -28,13 +28,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 PROBE_BYTES = 4 * (1 << 28)  # bench.copy_probe: 2^28 int32 read and written
 
 
+def short_name(name: str) -> str:
+    """kernel symbol without namespaces, return type and parameter list"""
+    n = name.replace("(anonymous namespace)::", "").replace("vc::", "")
+    n = n.split("(")[0]
+    return n[5:] if n.startswith("void ") else n
+
+
 def label_of(name: str) -> str:
     """bench.py's label for a kernel symbol: the function name without the k_ prefix
     (segscan with the pre-status output is segscan_pre); other kernels keep a short name."""
-    head = name.split("(")[0]
-    m = re.search(r"vc::(?:\(anonymous namespace\)::)?k_([A-Za-z0-9_]+)(<([^>]*)>)?", head)
+    head = short_name(name)
+    m = re.search(r"k_([A-Za-z0-9_]+)(<([^>]*)>)?", head)
     if not m:
-        return head.strip()[:80]
+        return head[:80]
     base, targs = m.group(1), m.group(3) or ""
     if base == "segscan" and targs.strip().startswith("1"):
         return "segscan_pre"
@@ -56,7 +63,7 @@ def cmd_stats(a):
     print("| kernel | label | calls | total µs | average µs | % |")
     print("|---|---|---|---|---|---|")
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
-        print(f"| {r['Name'].split('(')[0][:90]} | {label_of(r['Name'])} | {r['Calls']} | "
+        print(f"| {short_name(r['Name'])[:90]} | {label_of(r['Name'])} | {r['Calls']} | "
               f"{float(r['TotalDurationNs']) / 1e3:.1f} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['Percentage']):.1f} |")
 
@@ -79,7 +86,7 @@ def cmd_traffic(a):
     probe_w = [v for k, vs in write.items() if "neg" in k for v in vs]
     if not probe_f or not probe_w:
         sys.exit("copy probe kernel not found; non-checker kernels seen: " +
-                 ", ".join(sorted({k.split('(')[0][:60] for k in fetch if 'vc::' not in k})))
+                 ", ".join(sorted({short_name(k)[:60] for k in fetch if 'vc::' not in k})))
     kf = PROBE_BYTES / (probe_f[0] * 1024.0)
     kw = PROBE_BYTES / (probe_w[0] * 1024.0)
     digest = source_digest()

@@ -147,7 +147,7 @@ int trace_collect(vc_trace *t)
     t->pending = false;
     if (t->translate_pending) {
         t->translate_pending = false;
-        if ((e = hipMemcpy(&h, t->tr->ctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess)
+        if ((e = hipMemcpy(&h, t->tr->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost)) != hipSuccess)
             return vc_hip_fail(e, "hipMemcpy(control)");
         uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
         if (bad != ~0ull) {
@@ -161,7 +161,7 @@ int trace_collect(vc_trace *t)
     }
     if (!t->check_pending)
         return VC_OK;
-    e = hipMemcpy(&h, t->ctl, sizeof h, hipMemcpyDeviceToHost);
+    e = hipMemcpy(&h, t->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return vc_hip_fail(e, "hipMemcpy(control)");
     uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;

@@ -169,7 +169,7 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
     launch_batch_reset(d, n, (unsigned long long *)b.ind.p, s);
     launch_batch_init(d, (const uint64_t *)b.key_off.p, n, b.K, (uint8_t *)b.init_all.p, (uint8_t *)b.fin_all.p, s);
     launch_batch_count(d, (const uint64_t *)b.ev_off.p, n, b.N, (uint32_t *)b.cnt.p, s);
-    launch_excl_scan((uint32_t *)b.cnt.p, b.N, (uint64_t *)b.pos.p, nullptr, b.scratch.p, &b.ctl->tickets[6], s);
+    launch_excl_scan((uint32_t *)b.cnt.p, b.N, (uint64_t *)b.pos.p, nullptr, b.scratch.p, b.ctl->tickets[6], s);
     launch_batch_emit(d, (const uint64_t *)b.ev_off.p, n, b.N, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M,
                       s);
     uint64_t *sorted = sort_items((uint64_t *)b.items_a.p, (uint64_t *)b.items_b.p, b.M, (int)key_bits_for((uint32_t)b.K),

@@ -10,6 +10,7 @@ namespace vc {
 constexpr int LBITS = 12;                 // ids per bucket = 2^LBITS
 constexpr int LOC = 1 << LBITS;
 constexpr int MAX_BUCKETS = 1024;         // ids up to 2^22
+constexpr int HIST_COPIES = 8;            // global copies of the bucket histogram
 constexpr int P_ITEMS = 16;               // partition / replay: words per thread
 constexpr int PTILE = BLOCK * P_ITEMS;
 constexpr int B_ITEMS = 16;               // bucket scan: words per thread

@@ -17,80 +17,90 @@ constexpr int CTILE = BLOCK * CITEMS;
 
 __global__ __launch_bounds__(BLOCK) void k_compact(const uint8_t *__restrict__ status, uint64_t n,
                                                    uint32_t *__restrict__ viol, uint64_t *__restrict__ lb,
-                                                   uint32_t *__restrict__ ticket, Control *ctl)
+                                                   uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl,
+                                                   const unsigned long long *__restrict__ flagged)
 {
     __shared__ uint32_t s_idx[CTILE];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_excl;
 
-    const uint32_t tile = take_ticket(ticket, &s_tile);
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    const uint64_t base = (uint64_t)tile * CTILE;
-    const uint64_t my0 = base + (uint64_t)tid * CITEMS;
+    if (flagged && *flagged == 0)
+        return; // nothing flagged: the list is empty (n_viol stays 0)
+    for (;;) {
+        const uint32_t tile = take_ticket(ticket, &s_tile);
+        if (tile >= ntiles)
+            break;
+        const uint64_t base = (uint64_t)tile * CTILE;
+        const uint64_t my0 = base + (uint64_t)tid * CITEMS;
 
-    uint32_t bits = 0;
-    if (my0 + CITEMS <= n) {
-        uint4 v = *reinterpret_cast<const uint4 *>(status + my0);
-        uint32_t w[4] = { v.x, v.y, v.z, v.w };
+        uint32_t bits = 0;
+        if (my0 + CITEMS <= n) {
+            uint4 v = *reinterpret_cast<const uint4 *>(status + my0);
+            uint32_t w[4] = { v.x, v.y, v.z, v.w };
 #pragma unroll
-        for (int q = 0; q < 4; q++)
+            for (int q = 0; q < 4; q++)
 #pragma unroll
-            for (int b = 0; b < 4; b++)
-                bits |= ((w[q] >> (8 * b + 7)) & 1u) << (4 * q + b);
-    } else {
-        for (int k = 0; k < CITEMS; k++)
-            if (my0 + k < n)
-                bits |= ((status[my0 + k] >> 7) & 1u) << k;
-    }
-    uint32_t cnt = __builtin_popcount(bits);
-    uint32_t inc = wave_scan_add(cnt, lane);
-    if (lane == WAVE - 1)
-        s_wsum[wave] = inc;
-    __syncthreads();
-    uint32_t woff = 0, total = 0;
-    for (uint32_t w = 0; w < BLOCK / WAVE; w++) {
-        if (w < wave)
-            woff += s_wsum[w];
-        total += s_wsum[w];
-    }
-    uint32_t off = woff + inc - cnt;
-
-    if (wave == 0) {
-        const uint64_t excl = lb_count_exclusive(lb, tile, total);
-        if (lane == 0) {
-            s_excl = excl;
-            if (base + CTILE >= n)
-                ctl->n_viol = excl + total;
+                for (int b = 0; b < 4; b++)
+                    bits |= ((w[q] >> (8 * b + 7)) & 1u) << (4 * q + b);
+        } else {
+            for (int k = 0; k < CITEMS; k++)
+                if (my0 + k < n)
+                    bits |= ((status[my0 + k] >> 7) & 1u) << k;
         }
+        uint32_t cnt = __builtin_popcount(bits);
+        uint32_t inc = wave_scan_add(cnt, lane);
+        if (lane == WAVE - 1)
+            s_wsum[wave] = inc;
+        __syncthreads();
+        uint32_t woff = 0, total = 0;
+        for (uint32_t w = 0; w < BLOCK / WAVE; w++) {
+            if (w < wave)
+                woff += s_wsum[w];
+            total += s_wsum[w];
+        }
+        uint32_t off = woff + inc - cnt;
+
+        if (wave == 0) {
+            const uint64_t excl = lb_count_exclusive(lb, tile, total);
+            if (lane == 0) {
+                s_excl = excl;
+                if (base + CTILE >= n)
+                    ctl->n_viol = excl + total;
+            }
+        }
+        uint32_t k = off;
+        while (bits) {
+            uint32_t b = __builtin_ctz(bits);
+            bits &= bits - 1;
+            s_idx[k++] = (uint32_t)(my0 + b);
+        }
+        __syncthreads();
+        uint64_t excl = s_excl;
+        for (uint32_t i = tid; i < total; i += BLOCK)
+            viol[excl + i] = s_idx[i];
+        __syncthreads();
     }
-    uint32_t k = off;
-    while (bits) {
-        uint32_t b = __builtin_ctz(bits);
-        bits &= bits - 1;
-        s_idx[k++] = (uint32_t)(my0 + b);
-    }
-    __syncthreads();
-    uint64_t excl = s_excl;
-    for (uint32_t i = tid; i < total; i += BLOCK)
-        viol[excl + i] = s_idx[i];
 }
 
 } // namespace
 
 size_t compact_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, CTILE) * sizeof(uint64_t); }
 
-void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s)
+void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
+                    const unsigned long long *flagged)
 {
     if (n == 0)
         return;
     uint64_t tiles = ceil_div(n, CTILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
     launch_fill_u64(lb, 0, tiles, s);
-    launch_fill_u32(&ctl->tickets[2], 0, 1, s);
+    launch_fill_u32(ctl->tickets[2], 0, TICKET_WORDS, s);
     {
         ProfScope prof_(s, "compact");
-        k_compact<<<(unsigned)tiles, BLOCK, 0, s>>>(status, n, viol, lb, &ctl->tickets[2], ctl);
+        k_compact<<<resident_grid((const void *)k_compact, tiles), BLOCK, 0, s>>>(status, n, viol, lb, ctl->tickets[2],
+                                                                               tiles, ctl, flagged);
     }
 }
 

@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "internal.h"
+
 namespace vc {
 
 constexpr int WAVE = 64;
@@ -282,12 +284,21 @@ __device__ __forceinline__ uint64_t lb_column_sum(const uint64_t *lb, uint64_t s
     }
 }
 
-// dynamic tile ticket: tiles start in index order, so a tile only waits on tiles
-// whose workgroups are already resident
-__device__ __forceinline__ uint32_t take_ticket(uint32_t *counter, uint32_t *s_slot)
+// Dynamic tile tickets.  One counter per group of workgroups (blockIdx mod
+// TICKET_GROUPS, the round-robin the dispatcher uses across the XCDs), each on its own
+// 128-byte line, so that tickets do not serialize on a single address: group g's k-th
+// ticket is tile k * TICKET_GROUPS + g.  A tile waits only on lower tiles.  Grids that
+// take tickets never exceed what is resident on the device at once and have at least
+// TICKET_GROUPS workgroups, and a workgroup takes its next ticket as soon as its tile is
+// done; so the lowest unfinished tile is either running (all it waits on is finished)
+// or not yet handed out, in which case every workgroup of its group is idle and one of
+// them takes it: every wait ends.
+__device__ __forceinline__ uint32_t take_ticket(uint32_t *counters, uint32_t *s_slot)
 {
-    if (threadIdx.x == 0)
-        *s_slot = atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) {
+        const uint32_t g = blockIdx.x % TICKET_GROUPS;
+        *s_slot = atomicAdd(&counters[g * TICKET_STRIDE], 1u) * TICKET_GROUPS + g;
+    }
     __syncthreads();
     return *s_slot;
 }

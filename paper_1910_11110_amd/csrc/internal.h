@@ -17,8 +17,18 @@ constexpr int RADIX = 1 << RADIX_BITS_MAX;
 __host__ __device__ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
 // control block: counters zeroed at the start of each pipeline run
+// tile ticket counters of one kernel: TICKET_GROUPS counters, TICKET_STRIDE words apart
+constexpr uint32_t TICKET_GROUPS = 8;
+constexpr uint32_t TICKET_STRIDE = 32;
+constexpr uint32_t TICKET_WORDS = TICKET_GROUPS * TICKET_STRIDE;
+
+// Grid of a kernel that takes tile tickets: at most what is resident on the device at
+// once (occupancy of `kernel` at BLOCK threads x compute units), at most `cap` when
+// non-zero, and a multiple of TICKET_GROUPS no smaller than TICKET_GROUPS; tiles beyond
+// the grid are taken in turn by the resident workgroups.
+unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap = 0);
+
 struct Control {
-    uint32_t tickets[16];         // tile tickets, one per kernel of the pipeline
     uint32_t err_index_lo;        // first malformed input index (low/high), 0xFFFFFFFF.. if none
     uint32_t err_index_hi;
     uint32_t err_code;
@@ -26,8 +36,14 @@ struct Control {
     unsigned long long n_viol;    // violations found
     unsigned long long n_induced_stuck;
     unsigned long long n_out;     // produced element count (translation)
-    unsigned long long pad[3];
+    unsigned long long n_flagged; // flagged events counted by a producer (fused translation)
+    unsigned long long pad[2];
+    uint32_t tickets[16][TICKET_WORDS]; // tile ticket counters, one set per kernel of the pipeline
 };
+// the part of Control the host reads back (everything before the ticket counters)
+constexpr size_t CONTROL_HEADER = offsetof(Control, tickets);
+// device bytes reserved for a Control inside a larger allocation
+constexpr size_t CONTROL_BYTES = (sizeof(Control) + 255) / 256 * 256;
 
 // ------------------------------- utilities ----------------------------------------
 void launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
@@ -81,8 +97,11 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
 
 // ------------------------------- compaction ---------------------------------------
 size_t compact_scratch_bytes(uint64_t n);
-// ascending indices of status bytes with bit 7 set; count into ctl->n_viol
-void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s);
+// ascending indices of status bytes with bit 7 set; count into ctl->n_viol.  When
+// `flagged` is given (a count of the flagged bytes the producer kept on the device) and
+// it is zero, the list is empty and the status bytes are not read.
+void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
+                    const unsigned long long *flagged = nullptr);
 
 // ------------------------------- translation --------------------------------------
 // sort items of the declarations: key = variable, fcode = the declaration's effect
@@ -99,9 +118,11 @@ void launch_translate_emit(const uint64_t *comp_off, uint64_t n_comp, const uint
 
 // canonical bodies: translated events and their status bytes in one pass, from the
 // pre-status of each declaration's abstract variable
+// pre-status of each declaration's abstract variable; adds the number of flagged
+// events to ctl->n_flagged
 void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
                                  uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *pos, uint32_t *out,
-                                 uint8_t *status, hipStream_t s);
+                                 uint8_t *status, Control *ctl, hipStream_t s);
 
 // ------------------------------- overlap ------------------------------------------
 struct OverlapSets {

@@ -186,7 +186,7 @@ int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int k
             ProfScope prof_(s, "sweep_count");
             k_sweep_count<<<blocks_for(n), BLOCK, 0, s>>>(sorted, hi, n, fwd);
         }
-        launch_excl_scan(fwd, n, pofs, nullptr, scratch, &ctl->tickets[3], s);
+        launch_excl_scan(fwd, n, pofs, nullptr, scratch, ctl->tickets[3], s);
         VC_TRY(hipMemcpyAsync(&npairs, pofs + n, 8, hipMemcpyDeviceToHost, s));
         VC_TRY(hipStreamSynchronize(s));
         m = 2 * npairs;

@@ -24,12 +24,12 @@ int size_expansion(vc_trace *t)
     uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
     launch_reset_control(t->ctl, s);
     launch_overlap_count(t->events, n, t->n_ids, &t->sets, cnt, 0, t->ctl, s);
-    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, &t->ctl->tickets[5], s);
+    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, t->ctl->tickets[5], s);
     uint64_t total = 0;
     Control h;
     hipError_t e = hipMemcpyAsync(&total, pos + n, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&h, t->ctl, sizeof h, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(&h, t->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)
@@ -89,7 +89,7 @@ extern "C" int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32
     if (build_overlap_sets(t->lo, t->hi, n, key_bits, &t->sets, t->ctl, c->stream) != 0)
         return vc_fail(VC_EDEVICE, "interval sweep failed: %s", hipGetErrorString(hipGetLastError()));
     Control h;
-    if ((e = hipMemcpy(&h, t->ctl, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess)
+    if ((e = hipMemcpy(&h, t->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost)) != hipSuccess)
         return vc_hip_fail(e, "hipMemcpy(control)");
     uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
     if (bad != ~0ull) {
@@ -130,7 +130,7 @@ void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s)
     uint32_t *cnt = (uint32_t *)t->aux.p;
     uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
     launch_overlap_count(t->events, n, t->n_ids, &t->sets, cnt, 0, t->ctl, s);
-    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, &t->ctl->tickets[5], s);
+    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, t->ctl->tickets[5], s);
     launch_overlap_emit(t->events, n, t->n_ids, &t->sets, pos, (uint64_t *)t->items_a.p, m, 0, 0, 0, t->ctl, s);
 }
 

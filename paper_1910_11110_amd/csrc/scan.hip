@@ -146,20 +146,22 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
     uint64_t tiles = ceil_div(n, SCAN_TILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
     launch_fill_u64(lb, 0, tiles, s);
-    launch_fill_u32(&ctl->tickets[1], 0, 1, s);
-    unsigned grid = (unsigned)(tiles < grid_cap ? tiles : grid_cap);
+    launch_fill_u32(ctl->tickets[1], 0, TICKET_WORDS, s);
+    const unsigned grid = resident_grid(mode == SCAN_STATUS ? (const void *)k_segscan<SCAN_STATUS>
+                                                            : (const void *)k_segscan<SCAN_PRE>,
+                                        tiles, grid_cap);
     if (!ind_counts)
         ind_counts = &ctl->n_induced_stuck;
     if (mode == SCAN_STATUS)
         {
             ProfScope prof_(s, "segscan");
-            k_segscan<SCAN_STATUS><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1],
+            k_segscan<SCAN_STATUS><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, ctl->tickets[1],
                                                           tiles, ind_counts);
         }
     else
         {
             ProfScope prof_(s, "segscan_pre");
-            k_segscan<SCAN_PRE><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, &ctl->tickets[1], tiles,
+            k_segscan<SCAN_PRE><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, ctl->tickets[1], tiles,
                                                        ind_counts);
         }
 }

@@ -95,7 +95,7 @@ struct Pool {
         }
         void *p = nullptr;
         // events (4 B), status (1 B), violations (4 B) per event, and the counters
-        if (hipMalloc(&p, (9ull << k) + 512) != hipSuccess)
+        if (hipMalloc(&p, (9ull << k) + CONTROL_BYTES) != hipSuccess)
             return nullptr;
         all.push_back(p);
         return p;
@@ -153,7 +153,7 @@ int alloc_chunk(Pool &pool, Chunk *c)
     c->d_events = (uint32_t *)p;
     c->d_viol = (uint32_t *)(p + 4 * cap);
     c->d_ctl = (Control *)(p + 8 * cap);
-    c->d_status = (uint8_t *)(p + 8 * cap + 512);
+    c->d_status = (uint8_t *)(p + 8 * cap + CONTROL_BYTES);
     return VC_OK;
 }
 
@@ -187,7 +187,7 @@ static void finish_slot(vc_server *S, Slot &sl)
     std::vector<Control> h(sl.chunks.size());
     for (size_t i = 0; i < sl.chunks.size(); i++) {
         Chunk *c = sl.chunks[i];
-        (void)hipMemcpyAsync(&h[i], c->d_ctl, sizeof(Control), hipMemcpyDeviceToHost, sl.s);
+        (void)hipMemcpyAsync(&h[i], c->d_ctl, CONTROL_HEADER, hipMemcpyDeviceToHost, sl.s);
         if (c->status_out && !c->events.empty())
             (void)hipMemcpyAsync(c->status_out, c->d_status, c->events.size(), hipMemcpyDeviceToHost, sl.s);
     }

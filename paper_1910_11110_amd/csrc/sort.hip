@@ -48,11 +48,10 @@ __global__ void k_fill_u8(uint8_t *p, uint8_t v, size_t n)
 __global__ void k_reset_control(Control *c)
 {
     uint32_t *w = reinterpret_cast<uint32_t *>(c);
-    uint32_t t = threadIdx.x;
-    if (t < sizeof(Control) / 4)
+    for (uint32_t t = threadIdx.x; t < sizeof(Control) / 4; t += blockDim.x)
         w[t] = 0;
     __syncthreads();
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         c->err_index_lo = 0xFFFFFFFFu;
         c->err_index_hi = 0xFFFFFFFFu;
     }
@@ -261,7 +260,7 @@ void launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s)
         k_fill_u8<<<grid_for(n, 16), BLOCK, 0, s>>>(p, v, n);
 }
 
-void launch_reset_control(Control *c, hipStream_t s) { k_reset_control<<<1, 64, 0, s>>>(c); }
+void launch_reset_control(Control *c, hipStream_t s) { k_reset_control<<<1, 256, 0, s>>>(c); }
 
 void launch_make_items_events(const uint32_t *events, uint64_t n, uint32_t n_ids, uint64_t *items, Control *ctl,
                               hipStream_t s, uint32_t key_base, uint64_t payload_base)
@@ -285,7 +284,7 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
     if (n <= 1 || key_bits <= 0)
         return a;
     int max_bits = tune && tune->max_bits >= 4 && tune->max_bits <= RADIX_BITS_MAX ? tune->max_bits : RADIX_BITS_MAX;
-    unsigned grid_cap = tune && tune->grid_cap ? tune->grid_cap : (1u << 30);
+    unsigned grid_cap = tune && tune->grid_cap ? tune->grid_cap : 0u;
     int passes = (key_bits + max_bits - 1) / max_bits;
     int bits = (key_bits + passes - 1) / passes;
     SortScratch *sc = reinterpret_cast<SortScratch *>(scratch);
@@ -299,9 +298,9 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
     uint64_t *src = a, *dst = b;
     for (int p = 0; p < passes; p++) {
         launch_fill_u64(lb, 0, tiles * RADIX, s);
-        uint32_t *ticket = &ctl->tickets[0];
-        launch_fill_u32(ticket, 0, 1, s);
-        unsigned grid = (unsigned)(tiles < grid_cap ? tiles : grid_cap);
+        uint32_t *ticket = ctl->tickets[0];
+        launch_fill_u32(ticket, 0, TICKET_WORDS, s);
+        unsigned grid = resident_grid((const void *)k_sort_pass, tiles, grid_cap);
         {
             ProfScope prof_(s, "sort_pass");
             k_sort_pass<<<grid, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket, tiles);

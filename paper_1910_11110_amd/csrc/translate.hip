@@ -161,200 +161,307 @@ __global__ void k_translate_emit(const uint64_t *__restrict__ comp_off, uint64_t
 // applies to v#, so the two agree at every declaration from the common initial
 // (V,I)).  One workgroup writes 256 consecutive components.
 constexpr EffectTable TABLE = make_table();
-constexpr int FUSED_COMPS = BLOCK;             // components per workgroup
-constexpr int FUSED_DCAP = 2048;               // declarations staged per workgroup
-constexpr int FD_ITEMS = FUSED_DCAP / BLOCK;   // declarations per thread (contiguous run)
-constexpr int FUSED_CAP = 6144;                // events staged per workgroup
+constexpr int FUSED_COMPS = BLOCK;             // components per tile
+constexpr int FUSED_DCAP = 2048;               // declarations staged per tile
+constexpr int FD_ITEMS = FUSED_DCAP / BLOCK;   // declarations per thread
+static_assert(FD_ITEMS == 8, "the emitter reads a thread's run of declarations as two 16-byte vectors");
+constexpr int FUSED_CAP = 6144;                // events staged per tile
 
-struct FusedTables {
-    uint32_t f4[16], stuck[16];
-};
+// function (4-byte form) and stuck mask of an effect, as immediates chosen by the side
+template <uint32_t OP>
+__device__ __forceinline__ uint32_t eff_f4(uint32_t side)
+{
+    return side ? TABLE.f4[fcode(OP, 1)] : TABLE.f4[fcode(OP, 0)];
+}
+template <uint32_t OP>
+__device__ __forceinline__ uint32_t eff_stuck(uint32_t side)
+{
+    return side ? TABLE.stuck[fcode(OP, 1)] : TABLE.stuck[fcode(OP, 0)];
+}
 
 // the events of one declaration: its [[M]] slot at slot_p, its body at body_p
 // (positions relative to `dst`); `st` is the status of v and v# before it
 __device__ __forceinline__ void emit_decl(uint32_t wd, uint32_t n_vars, uint32_t st, uint64_t slot_p, uint64_t body_p,
-                                          uint64_t end, uint32_t *ev, uint8_t *stat, const FusedTables &T)
+                                          uint64_t end, uint32_t *ev, uint8_t *stat, uint32_t &nflag)
 {
     uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
     if (!decl_ok(wd, n_vars)) {
         v = 0;
         mode = 0;
     }
-    auto put = [&](uint64_t &p, uint32_t id, uint32_t op, uint32_t sd, uint32_t &s) {
-        const uint32_t fc = fcode(op, sd);
-        const uint32_t post = fapply(T.f4[fc], s);
-        const uint32_t flag = (T.stuck[fc] >> s) & 1u;
+    auto put = [&](uint64_t &p, uint32_t word, uint32_t f4, uint32_t stuck, uint32_t &s) {
+        const uint32_t post = fapply(f4, s);
+        const uint32_t flag = (stuck >> s) & 1u;
         if (p < end) {
-            ev[p] = id | (op << 24) | (sd << 27);
+            ev[p] = word;
             stat[p] = (uint8_t)(post | (s << 2) | (flag << 7));
+            nflag += flag;
         }
         p++;
         s = post;
     };
     uint32_t sa = st, sr = st;
     const bool reads = mode == 0 || mode == 2, writes = mode == 1 || mode == 2;
+    const uint32_t sbit = side << 27, vabs = n_vars + v;
     if (reads) {
         if ((st >> side) & 1u) {
-            put(slot_p, v, OP_NOOP, side, sr);
-            put(slot_p, n_vars + v, OP_NOOP, side, sa);
+            const uint32_t f = eff_f4<OP_NOOP>(side), k = eff_stuck<OP_NOOP>(side);
+            put(slot_p, v | (OP_NOOP << 24) | sbit, f, k, sr);
+            put(slot_p, vabs | (OP_NOOP << 24) | sbit, f, k, sa);
         } else {
-            const uint32_t t = side ? OP_PUSH : OP_PULL;
-            put(slot_p, v, t, 0, sr);
-            put(slot_p, n_vars + v, t, 0, sa);
+            // the transfer toward the side: Push from the CPU, Pull from the GPU (local)
+            const uint32_t op = side ? OP_PUSH : OP_PULL;
+            const uint32_t f = side ? TABLE.f4[fcode(OP_PUSH, 0)] : TABLE.f4[fcode(OP_PULL, 0)];
+            const uint32_t k = side ? TABLE.stuck[fcode(OP_PUSH, 0)] : TABLE.stuck[fcode(OP_PULL, 0)];
+            put(slot_p, v | (op << 24), f, k, sr);
+            put(slot_p, vabs | (op << 24), f, k, sa);
         }
     }
     if (writes)
-        put(slot_p, n_vars + v, OP_W, side, sa);
+        put(slot_p, vabs | (OP_W << 24) | sbit, eff_f4<OP_W>(side), eff_stuck<OP_W>(side), sa);
     // the body acts on v from its status after the guard
     if (reads)
-        put(body_p, v, OP_R, side, sr);
+        put(body_p, v | (OP_R << 24) | sbit, eff_f4<OP_R>(side), eff_stuck<OP_R>(side), sr);
     if (writes)
-        put(body_p, v, OP_W, side, sr);
+        put(body_p, v | (OP_W << 24) | sbit, eff_f4<OP_W>(side), eff_stuck<OP_W>(side), sr);
 }
 
+// adds the wave's flagged events to the global count (one atomic per wave that has any)
+__device__ __forceinline__ void add_flagged(uint32_t nflag, unsigned long long *n_flagged)
+{
+    uint32_t v = nflag;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1)
+        v += __shfl_xor(v, d);
+    if (lane_id() == 0 && v)
+        atomicAdd(n_flagged, (unsigned long long)v);
+}
+
+// what a workgroup loads ahead for one tile of components: offsets and positions (two
+// per thread), the declaration range, and the declarations with their pre-statuses
+struct FusedPrefetch {
+    uint64_t coff[2], pos[2];
+    uint64_t lo, hi;
+    uint32_t decl[FD_ITEMS];
+    uint32_t pre[FD_ITEMS];
+};
+
+__device__ __forceinline__ void fused_load_offsets(FusedPrefetch &f, const uint64_t *comp_off, const uint64_t *pos,
+                                                   uint64_t n_comp, uint64_t tile)
+{
+    const uint64_t c0 = tile * FUSED_COMPS;
+    const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const uint32_t i = threadIdx.x + q * BLOCK;
+        f.coff[q] = i <= nc ? comp_off[c0 + i] : 0ull;
+        f.pos[q] = i <= nc ? pos[c0 + i] : 0ull;
+    }
+    f.lo = comp_off[c0];
+    f.hi = comp_off[c0 + nc];
+}
+
+__device__ __forceinline__ void fused_load_decls(FusedPrefetch &f, const uint32_t *decls, const uint8_t *pre_abs,
+                                                 uint64_t n_decl)
+{
+    const bool fits = f.hi >= f.lo && f.hi <= n_decl && f.hi - f.lo <= (uint64_t)FUSED_DCAP;
+    const uint32_t nd = fits ? (uint32_t)(f.hi - f.lo) : 0u;
+#pragma unroll
+    for (int k = 0; k < FD_ITEMS; k++) {
+        const uint32_t i = threadIdx.x + k * BLOCK;
+        f.decl[k] = i < nd ? decls[f.lo + i] : 0u;
+        f.pre[k] = i < nd ? pre_abs[f.lo + i] : 0u;
+    }
+}
+
+// Persistent: workgroup g writes tiles g, g + G, ...  While it evaluates one tile, the
+// offsets of its next tile are in flight, and the next tile's declarations are
+// requested before the current tile's output is written, so the dependent loads of a
+// tile (offsets, then the declarations they locate) overlap the work on the previous.
 __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *__restrict__ comp_off, uint64_t n_comp,
                                                                const uint32_t *__restrict__ decls, uint64_t n_decl,
                                                                uint32_t n_vars, const uint8_t *__restrict__ pre_abs,
                                                                const uint64_t *__restrict__ pos,
-                                                               uint32_t *__restrict__ out, uint8_t *__restrict__ status)
+                                                               uint32_t *__restrict__ out, uint8_t *__restrict__ status,
+                                                               unsigned long long *__restrict__ n_flagged,
+                                                               uint64_t ntiles)
 {
     __shared__ uint32_t s_ev[FUSED_CAP];
     __shared__ uint8_t s_st[FUSED_CAP];
-    __shared__ uint32_t s_decl[FUSED_DCAP];
+    __shared__ __align__(16) uint32_t s_decl[FUSED_DCAP];
     __shared__ uint32_t s_scan[FUSED_DCAP + 1]; // exclusive prefix of (slot arity | body arity << 16)
-    __shared__ uint8_t s_pre[FUSED_DCAP];
+    __shared__ __align__(16) uint8_t s_pre[FUSED_DCAP];
     __shared__ uint64_t s_coff[FUSED_COMPS + 1], s_pos[FUSED_COMPS + 1];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
-    __shared__ FusedTables T;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    if (tid < 16) {
-        T.f4[tid] = TABLE.f4[tid];
-        T.stuck[tid] = TABLE.stuck[tid];
+    uint32_t nflag = 0;
+    uint64_t tile = blockIdx.x;
+    FusedPrefetch cur, nxt;
+    if (tile < ntiles) {
+        fused_load_offsets(cur, comp_off, pos, n_comp, tile);
+        fused_load_decls(cur, decls, pre_abs, n_decl);
     }
-    const uint64_t c0 = (uint64_t)blockIdx.x * FUSED_COMPS;
-    const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
-    for (uint32_t i = tid; i <= nc; i += BLOCK) {
-        s_coff[i] = comp_off[c0 + i];
-        s_pos[i] = pos[c0 + i];
-    }
-    __syncthreads();
-    // staged path: offsets non-decreasing inside [0, n_decl], and few enough
-    // declarations and events to stage
-    bool bad = false;
-    for (uint32_t i = tid; i < nc; i += BLOCK)
-        bad |= s_coff[i + 1] < s_coff[i] || s_pos[i + 1] < s_pos[i];
-    if (tid == 0)
-        bad |= s_coff[nc] > n_decl || s_coff[nc] - s_coff[0] > (uint64_t)FUSED_DCAP ||
-               s_pos[nc] - s_pos[0] > (uint64_t)FUSED_CAP;
-    if (__syncthreads_or(bad)) {
-        // one component per thread, written in place
-        if (tid < nc) {
-            const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
-            if (b >= a && b <= n_decl) {
-                const uint64_t p0 = s_pos[tid], end = s_pos[tid + 1];
-                uint64_t slot = p0;
-                for (uint64_t d = a; d < b; d++) {
-                    uint32_t mode = (decls[d] >> 24) & 3u;
-                    mode = decl_ok(decls[d], n_vars) ? mode : 0u;
-                    slot += slot_arity(mode);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const uint64_t tnext = tile + gridDim.x;
+        if (tnext < ntiles)
+            fused_load_offsets(nxt, comp_off, pos, n_comp, tnext);
+        const uint64_t c0 = tile * FUSED_COMPS;
+        const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
+#pragma unroll
+        for (int q = 0; q < 2; q++) {
+            const uint32_t i = tid + q * BLOCK;
+            if (i <= nc) {
+                s_coff[i] = cur.coff[q];
+                s_pos[i] = cur.pos[q];
+            }
+        }
+        const bool fits = cur.hi >= cur.lo && cur.hi <= n_decl && cur.hi - cur.lo <= (uint64_t)FUSED_DCAP;
+        const uint32_t nd = fits ? (uint32_t)(cur.hi - cur.lo) : 0u;
+#pragma unroll
+        for (int k = 0; k < FD_ITEMS; k++) {
+            const uint32_t i = tid + k * BLOCK;
+            if (i < nd) {
+                s_decl[i] = cur.decl[k];
+                s_pre[i] = (uint8_t)cur.pre[k];
+            }
+        }
+        __syncthreads();
+        // staged path: offsets non-decreasing inside [0, n_decl], and few enough
+        // declarations and events to stage
+        bool bad = !fits;
+        for (uint32_t i = tid; i < nc; i += BLOCK)
+            bad |= s_coff[i + 1] < s_coff[i] || s_pos[i + 1] < s_pos[i];
+        if (tid == 0)
+            bad |= s_pos[nc] - s_pos[0] > (uint64_t)FUSED_CAP;
+        if (__syncthreads_or(bad)) {
+            // one component per thread, written in place
+            if (tid < nc) {
+                const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
+                if (b >= a && b <= n_decl) {
+                    const uint64_t p0 = s_pos[tid], end = s_pos[tid + 1];
+                    uint64_t slot = p0;
+                    for (uint64_t d = a; d < b; d++) {
+                        const uint32_t wd = decls[d];
+                        slot += slot_arity(decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u);
+                    }
+                    uint64_t sp = p0, bp = slot;
+                    for (uint64_t d = a; d < b; d++) {
+                        const uint32_t wd = decls[d];
+                        const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                        emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, nflag);
+                        sp += slot_arity(mode);
+                        bp += body_arity(mode);
+                    }
                 }
-                uint64_t sp = p0, bp = slot;
-                for (uint64_t d = a; d < b; d++) {
-                    const uint32_t wd = decls[d];
-                    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-                    emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, T);
-                    sp += slot_arity(mode);
-                    bp += body_arity(mode);
+            }
+            if (tnext < ntiles)
+                fused_load_decls(nxt, decls, pre_abs, n_decl);
+            cur = nxt;
+            __syncthreads();
+            continue;
+        }
+        const uint64_t d_lo = s_coff[0];
+        const uint64_t ebase = s_pos[0];
+        const uint32_t range = (uint32_t)(s_pos[nc] - ebase);
+        // arities of the thread's run of declarations, block-wide exclusive scan
+        const uint32_t i0 = tid * FD_ITEMS;
+        uint32_t pk[FD_ITEMS];
+        uint32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < FD_ITEMS; j++) {
+            const uint32_t i = i0 + j;
+            uint32_t m = 0;
+            if (i < nd) {
+                const uint32_t wd = s_decl[i];
+                const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                m = slot_arity(mode) | (body_arity(mode) << 16);
+            }
+            pk[j] = m;
+            run += m;
+        }
+        const uint32_t inc = wave_scan_add(run, lane);
+        if (lane == WAVE - 1)
+            s_wsum[wave] = inc;
+        __syncthreads();
+        uint32_t ex = inc - run;
+        for (uint32_t w = 0; w < wave; w++)
+            ex += s_wsum[w];
+#pragma unroll
+        for (int j = 0; j < FD_ITEMS; j++) {
+            const uint32_t i = i0 + j;
+            if (i < nd)
+                s_scan[i] = ex;
+            ex += pk[j];
+        }
+        if (tid == BLOCK - 1)
+            s_scan[nd] = ex;
+        __syncthreads();
+        // emit into LDS: the component of the run's first declaration by binary search,
+        // then forward; the run's declarations and pre-statuses come in as vectors
+        if (i0 < nd) {
+            uint32_t lo = 0, hi = nc; // largest j with s_coff[j] - d_lo <= i0
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_coff[mid] - d_lo <= i0)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            uint32_t j = lo;
+            uint32_t cnext = (uint32_t)(s_coff[j + 1] - d_lo), base_c = s_scan[s_coff[j] - d_lo];
+            uint32_t tot = s_scan[cnext] - base_c;
+            uint64_t pe = s_pos[j] - ebase, end = s_pos[j + 1] - ebase;
+            const uint4 w0 = *reinterpret_cast<const uint4 *>(&s_decl[i0]);
+            const uint4 w1 = *reinterpret_cast<const uint4 *>(&s_decl[i0 + 4]);
+            const uint2 pr = *reinterpret_cast<const uint2 *>(&s_pre[i0]);
+            const uint32_t wds[FD_ITEMS] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w };
+#pragma unroll
+            for (int k = 0; k < FD_ITEMS; k++) {
+                const uint32_t i = i0 + k;
+                if (i < nd) {
+                    if (cnext <= i) { // next component (skipping empty ones)
+                        do
+                            j++;
+                        while (j + 1 < nc && s_coff[j + 1] - d_lo <= i);
+                        cnext = (uint32_t)(s_coff[j + 1] - d_lo);
+                        base_c = s_scan[s_coff[j] - d_lo];
+                        tot = s_scan[cnext] - base_c;
+                        pe = s_pos[j] - ebase;
+                        end = s_pos[j + 1] - ebase;
+                    }
+                    const uint32_t pre = s_scan[i] - base_c;
+                    const uint32_t st = ((k < 4 ? pr.x : pr.y) >> (8 * (k & 3))) & 0xFFu;
+                    emit_decl(wds[k], n_vars, st, pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16), end, s_ev,
+                              s_st, nflag);
                 }
             }
         }
-        return;
-    }
-    const uint64_t d_lo = s_coff[0];
-    const uint32_t nd = (uint32_t)(s_coff[nc] - d_lo);
-    const uint64_t ebase = s_pos[0];
-    const uint32_t range = (uint32_t)(s_pos[nc] - ebase);
-    for (uint32_t i = tid; i < nd; i += BLOCK) {
-        s_decl[i] = decls[d_lo + i];
-        s_pre[i] = pre_abs[d_lo + i];
-    }
-    __syncthreads();
-    // arities of the thread's run of declarations, block-wide exclusive scan
-    const uint32_t i0 = tid * FD_ITEMS;
-    uint32_t pk[FD_ITEMS];
-    uint32_t run = 0;
-#pragma unroll
-    for (int j = 0; j < FD_ITEMS; j++) {
-        const uint32_t i = i0 + j;
-        uint32_t m = 0;
-        if (i < nd) {
-            const uint32_t wd = s_decl[i];
-            const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-            m = slot_arity(mode) | (body_arity(mode) << 16);
+        // the next tile's declarations are requested before this tile's output is written
+        if (tnext < ntiles)
+            fused_load_decls(nxt, decls, pre_abs, n_decl);
+        __syncthreads();
+        for (uint32_t i = tid; i < range; i += BLOCK)
+            out[ebase + i] = s_ev[i];
+        // status bytes: unaligned head, 4-byte words, tail
+        const uint32_t h0 = (uint32_t)((4u - (ebase & 3u)) & 3u);
+        const uint32_t head = h0 < range ? h0 : range;
+        const uint32_t nwords = (range - head) / 4;
+        if (tid < head)
+            status[ebase + tid] = s_st[tid];
+        uint32_t *sw = reinterpret_cast<uint32_t *>(status + ebase + head);
+        for (uint32_t k = tid; k < nwords; k += BLOCK) {
+            const uint32_t q = head + 4 * k;
+            sw[k] = (uint32_t)s_st[q] | ((uint32_t)s_st[q + 1] << 8) | ((uint32_t)s_st[q + 2] << 16) |
+                    ((uint32_t)s_st[q + 3] << 24);
         }
-        pk[j] = m;
-        run += m;
+        const uint32_t tail0 = head + 4 * nwords;
+        if (tid < range - tail0)
+            status[ebase + tail0 + tid] = s_st[tail0 + tid];
+        cur = nxt;
+        __syncthreads();
     }
-    const uint32_t inc = wave_scan_add(run, lane);
-    if (lane == WAVE - 1)
-        s_wsum[wave] = inc;
-    __syncthreads();
-    uint32_t ex = inc - run;
-    for (uint32_t w = 0; w < wave; w++)
-        ex += s_wsum[w];
-#pragma unroll
-    for (int j = 0; j < FD_ITEMS; j++) {
-        const uint32_t i = i0 + j;
-        if (i < nd)
-            s_scan[i] = ex;
-        ex += pk[j];
-    }
-    if (tid == BLOCK - 1)
-        s_scan[nd] = ex;
-    __syncthreads();
-    // emit: the component of the run's first declaration by binary search, then forward
-    if (i0 < nd) {
-        uint32_t lo = 0, hi = nc; // largest j with s_coff[j] - d_lo <= i0
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_coff[mid] - d_lo <= i0)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        uint32_t j = lo;
-        for (int k = 0; k < FD_ITEMS; k++) {
-            const uint32_t i = i0 + k;
-            if (i >= nd)
-                break;
-            while (j + 1 < nc && s_coff[j + 1] - d_lo <= i)
-                j++;
-            const uint32_t cs = (uint32_t)(s_coff[j] - d_lo), ce = (uint32_t)(s_coff[j + 1] - d_lo);
-            const uint32_t base_c = s_scan[cs];
-            const uint32_t pre = s_scan[i] - base_c, tot = s_scan[ce] - base_c;
-            const uint64_t pe = s_pos[j] - ebase, end = s_pos[j + 1] - ebase;
-            emit_decl(s_decl[i], n_vars, s_pre[i], pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16), end,
-                            s_ev, s_st, T);
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = tid; i < range; i += BLOCK)
-        out[ebase + i] = s_ev[i];
-    // status bytes: unaligned head, 4-byte words, tail
-    const uint32_t head = (uint32_t)((4u - (ebase & 3u)) & 3u) < range ? (uint32_t)((4u - (ebase & 3u)) & 3u) : range;
-    const uint32_t nwords = (range - head) / 4;
-    if (tid < head)
-        status[ebase + tid] = s_st[tid];
-    uint32_t *sw = reinterpret_cast<uint32_t *>(status + ebase + head);
-    for (uint32_t k = tid; k < nwords; k += BLOCK) {
-        const uint32_t q = head + 4 * k;
-        sw[k] = (uint32_t)s_st[q] | ((uint32_t)s_st[q + 1] << 8) | ((uint32_t)s_st[q + 2] << 16) |
-                ((uint32_t)s_st[q + 3] << 24);
-    }
-    const uint32_t tail0 = head + 4 * nwords;
-    if (tid < range - tail0)
-        status[ebase + tail0 + tid] = s_st[tail0 + tid];
+    add_flagged(nflag, n_flagged);
 }
 
 unsigned grid_n(uint64_t n, unsigned per)
@@ -367,13 +474,14 @@ unsigned grid_n(uint64_t n, unsigned per)
 
 void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
                                  uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *pos, uint32_t *out,
-                                 uint8_t *status, hipStream_t s)
+                                 uint8_t *status, Control *ctl, hipStream_t s)
 {
     if (!n_comp)
         return;
     ProfScope prof_(s, "translate_emit_fused");
-    k_translate_emit_fused<<<(unsigned)ceil_div(n_comp, FUSED_COMPS), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars,
-                                                                               pre_abs, pos, out, status);
+    const uint64_t tiles = ceil_div(n_comp, FUSED_COMPS);
+    k_translate_emit_fused<<<resident_grid((const void *)k_translate_emit_fused, tiles), BLOCK, 0, s>>>(
+        comp_off, n_comp, decls, n_decl, n_vars, pre_abs, pos, out, status, &ctl->n_flagged, tiles);
 }
 
 void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint64_t *items, Control *ctl,

@@ -97,7 +97,7 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
     }
     launch_reset_control(tr.ctl, s);
     launch_translate_count(tr.comp_off, n_comp, tr.decls, n_decl, tr.body_off, (uint32_t *)tr.cnt.p, tr.ctl, s);
-    launch_excl_scan((uint32_t *)tr.cnt.p, n_comp, (uint64_t *)tr.pos.p, nullptr, tr.scratch.p, &tr.ctl->tickets[4], s);
+    launch_excl_scan((uint32_t *)tr.cnt.p, n_comp, (uint64_t *)tr.pos.p, nullptr, tr.scratch.p, tr.ctl->tickets[4], s);
     hipError_t e = hipMemcpyAsync(tr.host_total, (uint64_t *)tr.pos.p + n_comp, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipEventRecord(tr.total_ready, s);
@@ -141,14 +141,15 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
             return r;
     }
     if (tr.fused) {
+        launch_reset_control(t->ctl, s);
         launch_translate_emit_fused(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
-                                    (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, s);
+                                    (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, t->ctl, s);
         // final store: each real variable ends where its abstract variable ends
         uint8_t *fin = (uint8_t *)t->fin.p;
         (void)hipMemcpyAsync(fin, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
         (void)hipMemcpyAsync(fin + tr.n_vars, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
-        launch_reset_control(t->ctl, s);
-        launch_compact((uint8_t *)t->status.p, total, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
+        launch_compact((uint8_t *)t->status.p, total, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s,
+                       &t->ctl->n_flagged);
         return VC_OK;
     }
     launch_translate_emit(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, tr.body_off,
