@@ -138,10 +138,13 @@ int vc_translate(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const u
  * device inputs may have been rewritten in place with the same sizes. */
 int vc_translate_run(vc_trace *t);
 
-/* Checks the trace (asynchronous).  Results are read after vc_sync. */
+/* Checks the trace (asynchronous).  Results are read after vc_sync.  On a translated
+ * trace whose translation is still in flight it first waits for it (vc_sync). */
 int vc_check(vc_trace *t);
 
-/* number of events (after translation: the translated length) and of ids */
+/* number of events (after translation: the translated length) and of ids.  For a
+ * translation still in flight this waits for the context's work (as vc_sync does),
+ * since the translated length may only be known on the device. */
 int vc_trace_info(vc_trace *t, uint64_t *n_events, uint32_t *n_ids);
 
 /* ---------------------------------------------------------------------------------

@@ -157,6 +157,8 @@ int trace_collect(vc_trace *t)
             return vc_fail(VC_EINVAL, "malformed declaration, component offset or body word at index %llu",
                            (unsigned long long)bad);
         }
+        if (t->tr && t->tr->device_sized)
+            t->n = h.n_out;
         t->error = VC_OK;
     }
     if (!t->check_pending)
@@ -284,6 +286,11 @@ extern "C" int vc_trace_info(vc_trace *t, uint64_t *n_events, uint32_t *n_ids)
 {
     if (!t)
         return vc_fail(VC_EINVAL, "vc_trace_info: NULL trace");
+    if (t->translate_pending) { // the translated length is known once the work is done
+        int r = vc_sync(t->ctx);
+        if (r != VC_OK)
+            return r;
+    }
     if (n_events)
         *n_events = t->n;
     if (n_ids)
@@ -396,6 +403,11 @@ extern "C" int vc_check(vc_trace *t)
     if (!t)
         return vc_fail(VC_EINVAL, "vc_check: NULL trace");
     vc_ctx *c = t->ctx;
+    if (t->translate_pending) { // a check needs the translated length
+        int r = vc_sync(c);
+        if (r != VC_OK)
+            return r;
+    }
     (void)hipSetDevice(c->device);
     ProfGuard pg(c);
     int r = enqueue_check(t, c->stream);

@@ -26,6 +26,7 @@ struct TranslateState {
     uint32_t n_vars = 0;
     bool check = false;
     bool fused = false; // check evaluated during the emission (canonical bodies)
+    bool device_sized = false; // translated length found on the device (read back at sync)
     bool own_inputs = false;
     uint64_t *comp_off = nullptr, *body_off = nullptr;
     uint32_t *decls = nullptr, *body = nullptr;

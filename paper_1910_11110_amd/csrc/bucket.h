@@ -11,6 +11,7 @@ constexpr int LBITS = 12;                 // ids per bucket = 2^LBITS
 constexpr int LOC = 1 << LBITS;
 constexpr int MAX_BUCKETS = 1024;         // ids up to 2^22
 constexpr int HIST_COPIES = 8;            // global copies of the bucket histogram
+constexpr int HCHUNK = 1024;              // declarations per arity chunk
 constexpr int P_ITEMS = 16;               // partition / replay: words per thread
 constexpr int PTILE = BLOCK * P_ITEMS;
 constexpr int B_ITEMS = 16;               // bucket scan: words per thread
@@ -43,8 +44,9 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
 
 // status of each declaration's abstract variable before it, in program order, and the
 // final status of every abstract variable (final_out pre-filled by the caller; may be
-// null)
+// null).  With chunk_sum (ceil(n_decl / HCHUNK) entries), also the number of events each
+// chunk of HCHUNK declarations translates to (canonical bodies).
 void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,
-                            void *scratch, Control *ctl, hipStream_t s, int cu);
+                            void *scratch, Control *ctl, hipStream_t s, int cu, uint32_t *chunk_sum = nullptr);
 
 } // namespace vc

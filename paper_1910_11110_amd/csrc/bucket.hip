@@ -41,6 +41,7 @@ struct EventWords {
     {
         return ok(w, n_ids) ? fcode((w >> 24) & 7u, (w >> 27) & 1u) : fcode(OP_NOOP, 0);
     }
+    __device__ static uint32_t arity(uint32_t, uint32_t) { return 0; }
 };
 
 // a declaration acts on its abstract variable: R = guarded transfer toward its side,
@@ -58,52 +59,14 @@ struct DeclWords {
             return side ? fcode(OP_PUSH, 0) : fcode(OP_PULL, 0);
         return fcode(OP_W, side);
     }
-};
-
-// ----------------------------------------------------------------------------------
-// the 7-element monoid of the transition functions.  Every function the effects
-// generate is either a constant (a write) or "CPU bit |= a & GPU bit, GPU bit |= b &
-// CPU bit" (identity, Pull, Push or both).  3-bit code T<<2 | X<<1 | Y: T = constant;
-// constant: X = CPU bit, Y = GPU bit of the result; otherwise X = a, Y = b.
-// ----------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t mon_code(uint32_t f4)
-{
-    switch (fpack(f4)) {
-    case 0xE4: return 0;          // identity
-    case 0xEC: return 1;          // GPU |= CPU
-    case 0xF4: return 2;          // CPU |= GPU
-    case 0xFC: return 3;          // both
-    case 0xAA: return 4 | 1;      // constant (I,V)
-    case 0x55: return 4 | 2;      // constant (V,I)
-    case 0xFF: return 4 | 3;      // constant (V,V)
-    default: return 0;            // not generated by the effects
+    // events of the declaration in a translation with canonical bodies: R 2 + 1,
+    // W 1 + 1, RW 3 + 2 (a malformed declaration counts as R)
+    __device__ static uint32_t arity(uint32_t w, uint32_t n_ids)
+    {
+        const uint32_t mode = ok(w, n_ids) ? (w >> 24) & 3u : 0u;
+        return mode == 0 ? 3u : (mode == 1 ? 2u : 5u);
     }
-}
-
-// 20 monoid elements as bit planes (bit k = id k of a look-back word)
-struct Planes {
-    uint32_t t, x, y;
 };
-
-// h o f (f first), 20 ids at once
-__device__ __forceinline__ Planes pl_compose(Planes h, Planes f)
-{
-    const uint32_t ex = f.x | (h.x & (~f.t | f.y));
-    const uint32_t ey = f.y | (h.y & (~f.t | f.x));
-    return Planes{h.t | f.t, (h.t & h.x) | (~h.t & ex), (h.t & h.y) | (~h.t & ey)};
-}
-
-constexpr uint32_t PL_MASK = (1u << 20) - 1;
-
-__device__ __forceinline__ uint64_t pl_pack(Planes p)
-{
-    return (uint64_t)(p.t & PL_MASK) | ((uint64_t)(p.x & PL_MASK) << 20) | ((uint64_t)(p.y & PL_MASK) << 40);
-}
-
-__device__ __forceinline__ Planes pl_unpack(uint64_t w)
-{
-    return Planes{(uint32_t)w & PL_MASK, (uint32_t)(w >> 20) & PL_MASK, (uint32_t)(w >> 40) & PL_MASK};
-}
 
 // predecessors read per look-back round
 constexpr int LB_WIN = 16;
@@ -156,46 +119,84 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_
 // 0. histogram of buckets (+ validation)
 // ----------------------------------------------------------------------------------
 template <class SRC>
+__device__ __forceinline__ void hist_word(uint32_t w, uint64_t i, bool in, uint32_t n_ids, uint32_t *s_h, Control *ctl)
+{
+    if (in && !SRC::ok(w, n_ids)) {
+        unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
+        atomicMin(e, (unsigned long long)i);
+    }
+    // lanes agreeing with the first active lane add once; the others add alone
+    const uint32_t b = SRC::key(w, n_ids) >> LBITS;
+    const uint32_t b0 = __builtin_amdgcn_readfirstlane(in ? b : 0xFFFFFFFFu);
+    const uint64_t same = __ballot(in && b == b0);
+    if (in) {
+        if (b == b0) {
+            if (mask_rank(same) == 0)
+                atomicAdd(&s_h[b0], (uint32_t)__builtin_popcountll(same));
+        } else {
+            atomicAdd(&s_h[b], 1u);
+        }
+    }
+}
+
+// Bucket histogram in LDS, flushed to one of HIST_COPIES global copies (spreads the hot
+// buckets' atomics).  With chunk_sum, the words are read in chunks of HCHUNK and each
+// chunk's total arity (SRC::arity) is stored as well.
+template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
-                                                       uint32_t *__restrict__ hist, Control *ctl)
+                                                       uint32_t *__restrict__ hist, Control *ctl,
+                                                       uint32_t *__restrict__ chunk_sum)
 {
     __shared__ uint32_t s_h[MAX_BUCKETS];
+    __shared__ uint32_t s_ws[BLOCK / WAVE];
     for (int i = threadIdx.x; i < MAX_BUCKETS; i += BLOCK)
         s_h[i] = 0;
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-    // four loads in flight per thread, then the counts
-    for (uint64_t i0 = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i0 < n; i0 += 4 * stride) {
-        uint32_t w[4];
+    if (!chunk_sum) {
+        // four loads in flight per thread, then the counts
+        for (uint64_t i0 = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i0 < n; i0 += 4 * stride) {
+            uint32_t w[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const uint64_t i = i0 + u * stride;
-            w[u] = i < n ? src[i] : 0u;
+            for (int u = 0; u < 4; u++) {
+                const uint64_t i = i0 + u * stride;
+                w[u] = i < n ? src[i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint64_t i = i0 + u * stride;
+                hist_word<SRC>(w[u], i, i < n, n_ids, s_h, ctl);
+            }
         }
+    } else {
+        const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+        const uint64_t nchunks = ceil_div(n, (uint64_t)HCHUNK);
+        for (uint64_t k = blockIdx.x; k < nchunks; k += gridDim.x) {
+            uint32_t w[HCHUNK / BLOCK];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const uint64_t i = i0 + u * stride;
-            const bool in = i < n;
-            if (in && !SRC::ok(w[u], n_ids)) {
-                unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
-                atomicMin(e, (unsigned long long)i);
+            for (int u = 0; u < HCHUNK / BLOCK; u++) {
+                const uint64_t i = k * HCHUNK + u * BLOCK + threadIdx.x;
+                w[u] = i < n ? src[i] : 0u;
             }
-            // lanes agreeing with the first active lane add once; the others add alone
-            const uint32_t b = SRC::key(w[u], n_ids) >> LBITS;
-            const uint32_t b0 = __builtin_amdgcn_readfirstlane(in ? b : 0xFFFFFFFFu);
-            const uint64_t same = __ballot(in && b == b0);
-            if (in) {
-                if (b == b0) {
-                    if (mask_rank(same) == 0)
-                        atomicAdd(&s_h[b0], (uint32_t)__builtin_popcountll(same));
-                } else {
-                    atomicAdd(&s_h[b], 1u);
-                }
+            uint32_t a = 0;
+#pragma unroll
+            for (int u = 0; u < HCHUNK / BLOCK; u++) {
+                const uint64_t i = k * HCHUNK + u * BLOCK + threadIdx.x;
+                hist_word<SRC>(w[u], i, i < n, n_ids, s_h, ctl);
+                a += i < n ? SRC::arity(w[u], n_ids) : 0u;
             }
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1)
+                a += __shfl_xor(a, d);
+            if (lane == 0)
+                s_ws[wave] = a;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                chunk_sum[k] = s_ws[0] + s_ws[1] + s_ws[2] + s_ws[3];
+            __syncthreads();
         }
     }
     __syncthreads();
-    // one of HIST_COPIES global copies per workgroup spreads the hot buckets' atomics
     uint32_t *h = hist + (blockIdx.x % HIST_COPIES) * MAX_BUCKETS;
     for (int i = threadIdx.x; i < MAX_BUCKETS; i += BLOCK)
         if (s_h[i])
@@ -820,7 +821,7 @@ uint32_t bucket_max_ids() { return (uint32_t)MAX_BUCKETS * LOC; }
 template <class SRC>
 static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, const uint8_t *init, int mode,
                                uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
-                               hipStream_t s, int cu)
+                               hipStream_t s, int cu, uint32_t *chunk_sum = nullptr)
 {
     launch_fill_u32(L.hist, 0, HIST_COPIES * MAX_BUCKETS, s);
     launch_fill_u64(L.lbv, 0, L.btiles_max * LB_WORDS, s);
@@ -828,7 +829,7 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     {
         ProfScope p(s, "bucket_hist");
         const uint64_t hg = ceil_div(n ? n : 1, (uint64_t)BLOCK * 16);
-        k_bucket_hist<SRC><<<(unsigned)(hg < 2048 ? hg : 2048), BLOCK, 0, s>>>(src, n, n_ids, L.hist, ctl);
+        k_bucket_hist<SRC><<<(unsigned)(hg < 2048 ? hg : 2048), BLOCK, 0, s>>>(src, n, n_ids, L.hist, ctl, chunk_sum);
     }
     {
         ProfScope p(s, "bucket_bases");
@@ -908,12 +909,12 @@ __global__ __launch_bounds__(BLOCK) void k_replay_bytes(const uint32_t *__restri
 }
 
 void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,
-                            void *scratch, Control *ctl, hipStream_t s, int cu)
+                            void *scratch, Control *ctl, hipStream_t s, int cu, uint32_t *chunk_sum)
 {
     if (n_decl == 0)
         return;
     BucketLayout L = bucket_layout(scratch, n_decl, n_vars);
-    partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu);
+    partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu, chunk_sum);
     if (L.nb == 1)
         return;
     ProfScope p(s, "replay_bytes");

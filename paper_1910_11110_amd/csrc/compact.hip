@@ -18,7 +18,8 @@ constexpr int CTILE = BLOCK * CITEMS;
 __global__ __launch_bounds__(BLOCK) void k_compact(const uint8_t *__restrict__ status, uint64_t n,
                                                    uint32_t *__restrict__ viol, uint64_t *__restrict__ lb,
                                                    uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl,
-                                                   const unsigned long long *__restrict__ flagged)
+                                                   const unsigned long long *__restrict__ flagged,
+                                                   const unsigned long long *__restrict__ n_dev)
 {
     __shared__ uint32_t s_idx[CTILE];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
@@ -28,6 +29,10 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint8_t *__restrict__ s
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     if (flagged && *flagged == 0)
         return; // nothing flagged: the list is empty (n_viol stays 0)
+    if (n_dev && *n_dev < n) {
+        n = *n_dev;
+        ntiles = ceil_div(n, CTILE);
+    }
     for (;;) {
         const uint32_t tile = take_ticket(ticket, &s_tile);
         if (tile >= ntiles)
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint8_t *__restrict__ s
 size_t compact_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, CTILE) * sizeof(uint64_t); }
 
 void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
-                    const unsigned long long *flagged)
+                    const unsigned long long *flagged, const unsigned long long *n_dev)
 {
     if (n == 0)
         return;
@@ -100,7 +105,7 @@ void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scr
     {
         ProfScope prof_(s, "compact");
         k_compact<<<resident_grid((const void *)k_compact, tiles), BLOCK, 0, s>>>(status, n, viol, lb, ctl->tickets[2],
-                                                                               tiles, ctl, flagged);
+                                                                               tiles, ctl, flagged, n_dev);
     }
 }
 

@@ -138,6 +138,52 @@ __device__ __forceinline__ T wave_scan_add(T v, uint32_t lane)
 }
 
 // ---------------------------------------------------------------------------------
+// the 7-element monoid of the transition functions.  Every function the effects
+// generate is either a constant (a write) or "CPU bit |= a & GPU bit, GPU bit |= b &
+// CPU bit" (identity, Pull, Push or both).  3-bit code T<<2 | X<<1 | Y: T = constant;
+// constant: X = CPU bit, Y = GPU bit of the result; otherwise X = a, Y = b.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t mon_code_packed(uint32_t p)
+{
+    switch (p) {
+    case 0xE4: return 0;          // identity
+    case 0xEC: return 1;          // GPU |= CPU
+    case 0xF4: return 2;          // CPU |= GPU
+    case 0xFC: return 3;          // both
+    case 0xAA: return 4 | 1;      // constant (I,V)
+    case 0x55: return 4 | 2;      // constant (V,I)
+    case 0xFF: return 4 | 3;      // constant (V,V)
+    default: return 0;            // not generated by the effects
+    }
+}
+__device__ __forceinline__ uint32_t mon_code(uint32_t f4) { return mon_code_packed(fpack(f4)); }
+
+// 20 monoid elements as bit planes (bit k = id k of a look-back word)
+struct Planes {
+    uint32_t t, x, y;
+};
+
+// h o f (f first), 20 ids at once
+__device__ __forceinline__ Planes pl_compose(Planes h, Planes f)
+{
+    const uint32_t ex = f.x | (h.x & (~f.t | f.y));
+    const uint32_t ey = f.y | (h.y & (~f.t | f.x));
+    return Planes{h.t | f.t, (h.t & h.x) | (~h.t & ex), (h.t & h.y) | (~h.t & ey)};
+}
+
+constexpr uint32_t PL_MASK = (1u << 20) - 1;
+
+__device__ __forceinline__ uint64_t pl_pack(Planes p)
+{
+    return (uint64_t)(p.t & PL_MASK) | ((uint64_t)(p.x & PL_MASK) << 20) | ((uint64_t)(p.y & PL_MASK) << 40);
+}
+
+__device__ __forceinline__ Planes pl_unpack(uint64_t w)
+{
+    return Planes{(uint32_t)w & PL_MASK, (uint32_t)(w >> 20) & PL_MASK, (uint32_t)(w >> 40) & PL_MASK};
+}
+
+// ---------------------------------------------------------------------------------
 // Decoupled look-back words: 64 bits, top 2 bits = state (0 empty, 1 aggregate,
 // 2 inclusive prefix), low 62 bits = value.  Written and polled with agent-scope
 // atomics so that workgroups on different XCDs see each other's words.
@@ -246,6 +292,53 @@ __device__ __forceinline__ uint32_t lb_fn_exclusive(uint64_t *lb, uint64_t tile,
     if (lane == 0)
         lb_store(&lb[tile], LB_INC | fpack(fcompose(tagg, carry)));
     return carry;
+}
+
+// Look-back over per-id transition functions held as bit planes (20 ids per word; a
+// tile publishes `nwords` words, word w of tile u at lb[u * nwords + w]), run by one
+// whole wave for word w.  Publishes the tile's aggregate planes, folds predecessors 64
+// per round (lane q polls tile t - q; lane 0 is the latest, composed outermost) up to
+// the nearest inclusive word, publishes the inclusive planes (aggregate after the
+// entering statuses) and returns the entering statuses as constant planes.  Tile 0
+// enters with `first` (constant planes).  The result is the same in every lane.
+__device__ __forceinline__ Planes lb_planes_exclusive(uint64_t *lb, uint32_t nwords, uint64_t tile, uint32_t w,
+                                                      Planes agg, Planes first)
+{
+    const uint32_t lane = lane_id();
+    Planes acc = first;
+    if (tile > 0) {
+        if (lane == 0)
+            lb_store(&lb[tile * nwords + w], LB_AGG | pl_pack(agg));
+        acc = Planes{0, 0, 0};
+        int64_t t = (int64_t)tile - 1;
+        for (;;) {
+            const int64_t mt = t - (int64_t)lane;
+            const uint64_t v = mt >= 0 ? lb_load(&lb[(uint64_t)mt * nwords + w]) : 0ull;
+            const uint32_t fl = (uint32_t)(v >> 62);
+            const uint64_t stop = __ballot(fl != 1);
+            const uint64_t incm = __ballot(fl == 2);
+            const uint32_t s = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
+            const bool inc_at_s = s < 64 && ((incm >> s) & 1ull);
+            Planes f = (lane < s || (lane == s && inc_at_s)) ? pl_unpack(v) : Planes{0, 0, 0};
+#pragma unroll
+            for (int dd = 1; dd < WAVE; dd <<= 1) {
+                const Planes g{(uint32_t)__shfl_down(f.t, dd), (uint32_t)__shfl_down(f.x, dd),
+                               (uint32_t)__shfl_down(f.y, dd)};
+                if (lane + dd < WAVE)
+                    f = pl_compose(f, g);
+            }
+            const Planes r{(uint32_t)__shfl(f.t, 0), (uint32_t)__shfl(f.x, 0), (uint32_t)__shfl(f.y, 0)};
+            acc = pl_compose(acc, r);
+            if (inc_at_s)
+                break;
+            if (s == 0)
+                __builtin_amdgcn_s_sleep(1);
+            t -= (int64_t)s;
+        }
+    }
+    if (lane == 0)
+        lb_store(&lb[tile * nwords + w], LB_INC | pl_pack(pl_compose(agg, acc)));
+    return acc;
 }
 
 // Per-thread additive look-back over one column of a chain of tiles (word of tile u at

@@ -99,9 +99,11 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
 size_t compact_scratch_bytes(uint64_t n);
 // ascending indices of status bytes with bit 7 set; count into ctl->n_viol.  When
 // `flagged` is given (a count of the flagged bytes the producer kept on the device) and
-// it is zero, the list is empty and the status bytes are not read.
+// it is zero, the list is empty and the status bytes are not read.  When `n_dev` is
+// given, the bytes are the first min(n, *n_dev) (a length known only on the device; n
+// bounds it and sizes the launch).
 void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
-                    const unsigned long long *flagged = nullptr);
+                    const unsigned long long *flagged = nullptr, const unsigned long long *n_dev = nullptr);
 
 // ------------------------------- translation --------------------------------------
 // sort items of the declarations: key = variable, fcode = the declaration's effect
@@ -123,6 +125,14 @@ void launch_translate_emit(const uint64_t *comp_off, uint64_t n_comp, const uint
 void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
                                  uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *pos, uint32_t *out,
                                  uint8_t *status, Control *ctl, hipStream_t s);
+
+// the same with the positions found on the device (no per-component counts): the events
+// before a tile come from chunk_prefix, the exclusive prefix of the per-chunk event counts
+// (HCHUNK declarations a chunk); malformed component offsets go to tr_ctl's error index.
+// `out` and `status` must hold 5 * n_decl entries (the largest possible length).
+void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                                     uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *chunk_prefix,
+                                     uint32_t *out, uint8_t *status, Control *tr_ctl, Control *ctl, hipStream_t s);
 
 // ------------------------------- overlap ------------------------------------------
 struct OverlapSets {

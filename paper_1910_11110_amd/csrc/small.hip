@@ -5,9 +5,9 @@
 // its own events (a private 64-entry table of transition functions in LDS).  A
 // per-variable scan across the 256 threads of the tile (64 lanes = 64 variables)
 // turns the tables into exclusive prefixes and yields the tile's aggregate per
-// variable.  Tiles chain their per-variable states with a decoupled look-back whose
-// words carry their own readiness flag (7 variables per 64-bit word), so each word
-// can be published and consumed independently.  Each thread then replays its 16
+// variable.  Tiles chain their per-variable states with a decoupled look-back: four
+// self-flagged 64-bit words of 20 variables each, the functions as bit planes, one wave
+// per word folding 64 predecessors a round.  Each thread then replays its 16
 // events from its entering statuses and writes its 16 status bytes as one 16-byte
 // store; flagged events are compacted in the same kernel (a second look-back on the
 // count), and the last tile writes the final statuses.
@@ -24,17 +24,9 @@ constexpr int SK = 64;               // variables
 constexpr int SE = 16;               // events per thread
 constexpr int STILE = BLOCK * SE;    // events per tile
 constexpr int SROW = SK + 1;         // padded table row (words)
-constexpr int SWORDS = (SK + 6) / 7; // look-back words per tile
-constexpr int SLB_WIN = 8;           // predecessors read per look-back round
+constexpr int SPW = (SK + 19) / 20;  // look-back words per tile (20 variables each)
+static_assert(SPW == BLOCK / WAVE, "one wave per look-back word");
 
-__device__ __forceinline__ uint64_t pack7(const uint8_t *b)
-{
-    uint64_t w = 0;
-#pragma unroll
-    for (int i = 0; i < 7; i++)
-        w |= (uint64_t)b[i] << (8 * i);
-    return w;
-}
 
 __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ status,
@@ -159,79 +151,26 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
         }
         __syncthreads();
 
-        // ---- look-back: status per variable entering the tile -------------------------
-        if (tid < SWORDS) {
-            uint8_t agg7[7], st7[7];
-#pragma unroll
-            for (int i = 0; i < 7; i++) {
-                int k = tid * 7 + i;
-                agg7[i] = k < SK ? s_agg[k] : (uint8_t)0xE4;
-            }
-            uint64_t *my = lbv + (uint64_t)tile * SWORDS + tid;
-            uint32_t acc4[7];
-#pragma unroll
-            for (int i = 0; i < 7; i++)
-                acc4[i] = F_ID;
+        // ---- look-back: status per variable entering the tile.  Four words of 20
+        // variables as bit planes, one wave per word, 64 predecessors per round ----------
+        {
+            const uint32_t k = wave * 20 + lane; // this lane's variable (lanes < 20)
+            const bool mine = lane < 20 && k < SK;
+            const uint32_t code = mine ? mon_code_packed(s_agg[k]) : 0u;
+            const Planes agg{(uint32_t)__ballot((code >> 2) & 1u) & PL_MASK,
+                             (uint32_t)__ballot((code >> 1) & 1u) & PL_MASK, (uint32_t)__ballot(code & 1u) & PL_MASK};
+            Planes first{PL_MASK, 0, 0};
             if (tile == 0) {
-#pragma unroll
-                for (int i = 0; i < 7; i++) {
-                    int k = tid * 7 + i;
-                    st7[i] = (init && k < (int)n_ids) ? init[k] : (uint8_t)1;
-                }
-            } else {
-                lb_store(my, LB_AGG | pack7(agg7));
-                // a round reads SLB_WIN predecessors at once and folds them up to the
-                // nearest inclusive word; an unpublished word ends the round early
-                int64_t t = (int64_t)tile - 1;
-                bool done = false;
-                while (!done) {
-                    uint64_t w[SLB_WIN];
-#pragma unroll
-                    for (int q = 0; q < SLB_WIN; q++)
-                        w[q] = t - q >= 0 ? lb_load(lbv + (uint64_t)(t - q) * SWORDS + tid) : 0ull;
-                    int adv = 0;
-                    bool stop = false;
-#pragma unroll
-                    for (int q = 0; q < SLB_WIN; q++) {
-                        const uint32_t fl = (uint32_t)(w[q] >> 62);
-                        if (!stop) {
-                            if (fl == 0) {
-                                stop = true;
-                            } else if (fl == 2) {
-#pragma unroll
-                                for (int i = 0; i < 7; i++)
-                                    st7[i] = (uint8_t)fapply(acc4[i], (uint32_t)(w[q] >> (8 * i)) & 0xFFu);
-                                done = stop = true;
-                            } else {
-#pragma unroll
-                                for (int i = 0; i < 7; i++)
-                                    acc4[i] = fcompose(acc4[i], funpack((uint32_t)(w[q] >> (8 * i)) & 0xFFu));
-                                adv++;
-                            }
-                        }
-                    }
-                    if (!done) {
-                        if (adv == 0)
-                            __builtin_amdgcn_s_sleep(1);
-                        t -= adv;
-                    }
-                }
+                const uint32_t s0 = (init && mine && k < n_ids) ? init[k] : 1u;
+                first.x = (uint32_t)__ballot(s0 & 1u) & PL_MASK;
+                first.y = (uint32_t)__ballot((s0 >> 1) & 1u) & PL_MASK;
             }
-            uint8_t inc7[7];
-#pragma unroll
-            for (int i = 0; i < 7; i++) {
-                int k = tid * 7 + i;
-                if (k < SK)
-                    s_carry[k] = st7[i];
-                inc7[i] = (uint8_t)fapply(funpack(agg7[i]), st7[i]);
-            }
-            lb_store(my, LB_INC | pack7(inc7));
-            if (tile + 1 == ntiles && final_out) {
-#pragma unroll
-                for (int i = 0; i < 7; i++) {
-                    int k = tid * 7 + i;
-                    if (k < (int)n_ids)
-                        final_out[k] = inc7[i];
+            const Planes st = lb_planes_exclusive(lbv, SPW, tile, wave, agg, first);
+            if (mine) {
+                s_carry[k] = (uint8_t)(((st.x >> lane) & 1u) | (((st.y >> lane) & 1u) << 1));
+                if (tile + 1 == ntiles && final_out && k < n_ids) {
+                    const Planes inc = pl_compose(agg, st);
+                    final_out[k] = (uint8_t)(((inc.x >> lane) & 1u) | (((inc.y >> lane) & 1u) << 1));
                 }
             }
         }
@@ -307,7 +246,7 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
 size_t small_scratch_bytes(uint64_t n)
 {
     uint64_t tiles = ceil_div(n ? n : 1, STILE);
-    return tiles * (SWORDS + 1) * sizeof(uint64_t);
+    return tiles * (SPW + 1) * sizeof(uint64_t);
 }
 
 uint32_t small_max_ids() { return SK; }
@@ -320,8 +259,8 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
         return;
     uint64_t tiles = ceil_div(n, STILE);
     uint64_t *lbv = reinterpret_cast<uint64_t *>(scratch);
-    uint64_t *lbc = lbv + tiles * SWORDS;
-    launch_fill_u64(lbv, 0, tiles * (SWORDS + 1), s);
+    uint64_t *lbc = lbv + tiles * SPW;
+    launch_fill_u64(lbv, 0, tiles * (SPW + 1), s);
     launch_fill_u32(ctl->tickets[7], 0, TICKET_WORDS, s);
     const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap);
     ProfScope prof_(s, "small_check");

@@ -15,6 +15,7 @@
 // After the scan, each component is written independently: fixed arity per
 // declaration (the not-taken guard emits Noop x; Noop x#), then its body.
 #include "device.h"
+#include "bucket.h"
 #include "internal.h"
 #include "prof.h"
 
@@ -255,7 +256,7 @@ __device__ __forceinline__ void fused_load_offsets(FusedPrefetch &f, const uint6
     for (int q = 0; q < 2; q++) {
         const uint32_t i = threadIdx.x + q * BLOCK;
         f.coff[q] = i <= nc ? comp_off[c0 + i] : 0ull;
-        f.pos[q] = i <= nc ? pos[c0 + i] : 0ull;
+        f.pos[q] = i <= nc && pos ? pos[c0 + i] : 0ull;
     }
     f.lo = comp_off[c0];
     f.hi = comp_off[c0 + nc];
@@ -274,10 +275,185 @@ __device__ __forceinline__ void fused_load_decls(FusedPrefetch &f, const uint32_
     }
 }
 
-// Persistent: workgroup g writes tiles g, g + G, ...  While it evaluates one tile, the
-// offsets of its next tile are in flight, and the next tile's declarations are
-// requested before the current tile's output is written, so the dependent loads of a
-// tile (offsets, then the declarations they locate) overlap the work on the previous.
+// exclusive block scan of packed arities (slot | body << 16) of the tile's declarations
+// (each thread a run of FD_ITEMS) into s_scan[0..nd]
+__device__ __forceinline__ void scan_arities(uint32_t nd, uint32_t n_vars, const uint32_t *s_decl, uint32_t *s_scan,
+                                             uint32_t *s_wsum)
+{
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t i0 = tid * FD_ITEMS;
+    uint32_t pk[FD_ITEMS];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < FD_ITEMS; j++) {
+        const uint32_t i = i0 + j;
+        uint32_t m = 0;
+        if (i < nd) {
+            const uint32_t wd = s_decl[i];
+            const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+            m = slot_arity(mode) | (body_arity(mode) << 16);
+        }
+        pk[j] = m;
+        run += m;
+    }
+    const uint32_t inc = wave_scan_add(run, lane);
+    if (lane == WAVE - 1)
+        s_wsum[wave] = inc;
+    __syncthreads();
+    uint32_t ex = inc - run;
+    for (uint32_t w = 0; w < wave; w++)
+        ex += s_wsum[w];
+#pragma unroll
+    for (int j = 0; j < FD_ITEMS; j++) {
+        const uint32_t i = i0 + j;
+        if (i < nd)
+            s_scan[i] = ex;
+        ex += pk[j];
+    }
+    if (tid == BLOCK - 1)
+        s_scan[nd] = ex;
+}
+
+// the tile's events into LDS (positions relative to ebase): the component of a
+// thread's first declaration by binary search, then forward; the run's declarations
+// and pre-statuses come in as vectors
+__device__ __forceinline__ void emit_staged(uint32_t nd, uint32_t nc, uint64_t d_lo, uint64_t ebase, uint32_t n_vars,
+                                            const uint64_t *s_coff, const uint64_t *s_pos, const uint32_t *s_scan,
+                                            const uint32_t *s_decl, const uint8_t *s_pre, uint32_t *s_ev,
+                                            uint8_t *s_st, uint32_t &nflag)
+{
+    const uint32_t i0 = threadIdx.x * FD_ITEMS;
+    if (i0 >= nd)
+        return;
+    uint32_t lo = 0, hi = nc; // largest j with s_coff[j] - d_lo <= i0
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_coff[mid] - d_lo <= i0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    uint32_t j = lo;
+    uint32_t cnext = (uint32_t)(s_coff[j + 1] - d_lo), base_c = s_scan[s_coff[j] - d_lo];
+    uint32_t tot = s_scan[cnext] - base_c;
+    uint64_t pe = s_pos[j] - ebase, end = s_pos[j + 1] - ebase;
+    const uint4 w0 = *reinterpret_cast<const uint4 *>(&s_decl[i0]);
+    const uint4 w1 = *reinterpret_cast<const uint4 *>(&s_decl[i0 + 4]);
+    const uint2 pr = *reinterpret_cast<const uint2 *>(&s_pre[i0]);
+    const uint32_t wds[FD_ITEMS] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w };
+#pragma unroll
+    for (int k = 0; k < FD_ITEMS; k++) {
+        const uint32_t i = i0 + k;
+        if (i < nd) {
+            if (cnext <= i) { // next component (skipping empty ones)
+                do
+                    j++;
+                while (j + 1 < nc && s_coff[j + 1] - d_lo <= i);
+                cnext = (uint32_t)(s_coff[j + 1] - d_lo);
+                base_c = s_scan[s_coff[j] - d_lo];
+                tot = s_scan[cnext] - base_c;
+                pe = s_pos[j] - ebase;
+                end = s_pos[j + 1] - ebase;
+            }
+            const uint32_t pre = s_scan[i] - base_c;
+            const uint32_t st = ((k < 4 ? pr.x : pr.y) >> (8 * (k & 3))) & 0xFFu;
+            emit_decl(wds[k], n_vars, st, pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16), end, s_ev, s_st,
+                      nflag);
+        }
+    }
+}
+
+// the staged events and status bytes to HBM, coalesced (status: unaligned head,
+// 4-byte words, tail)
+__device__ __forceinline__ void write_staged(uint32_t range, uint64_t ebase, const uint32_t *s_ev, const uint8_t *s_st,
+                                             uint32_t *out, uint8_t *status)
+{
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < range; i += BLOCK)
+        out[ebase + i] = s_ev[i];
+    const uint32_t h0 = (uint32_t)((4u - (ebase & 3u)) & 3u);
+    const uint32_t head = h0 < range ? h0 : range;
+    const uint32_t nwords = (range - head) / 4;
+    if (tid < head)
+        status[ebase + tid] = s_st[tid];
+    uint32_t *sw = reinterpret_cast<uint32_t *>(status + ebase + head);
+    for (uint32_t k = tid; k < nwords; k += BLOCK) {
+        const uint32_t q = head + 4 * k;
+        sw[k] = (uint32_t)s_st[q] | ((uint32_t)s_st[q + 1] << 8) | ((uint32_t)s_st[q + 2] << 16) |
+                ((uint32_t)s_st[q + 3] << 24);
+    }
+    const uint32_t tail0 = head + 4 * nwords;
+    if (tid < range - tail0)
+        status[ebase + tail0 + tid] = s_st[tail0 + tid];
+}
+
+// one component per thread, written in place (tiles that do not fit the staging)
+__device__ __forceinline__ void emit_in_place(uint32_t nc, uint32_t n_vars, uint64_t n_decl, const uint64_t *s_coff,
+                                              const uint64_t *s_pos, const uint32_t *decls, const uint8_t *pre_abs,
+                                              uint32_t *out, uint8_t *status, uint32_t &nflag)
+{
+    const uint32_t tid = threadIdx.x;
+    if (tid >= nc)
+        return;
+    const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
+    if (b < a || b > n_decl)
+        return;
+    const uint64_t p0 = s_pos[tid], end = s_pos[tid + 1];
+    uint64_t slot = p0;
+    for (uint64_t d = a; d < b; d++) {
+        const uint32_t wd = decls[d];
+        slot += slot_arity(decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u);
+    }
+    uint64_t sp = p0, bp = slot;
+    for (uint64_t d = a; d < b; d++) {
+        const uint32_t wd = decls[d];
+        const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+        emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, nflag);
+        sp += slot_arity(mode);
+        bp += body_arity(mode);
+    }
+}
+
+// stages a prefetched tile's offsets (positions too when given) and declarations
+__device__ __forceinline__ void stage_tile(const FusedPrefetch &f, uint32_t nc, uint32_t nd, bool with_pos,
+                                           uint64_t *s_coff, uint64_t *s_pos, uint32_t *s_decl, uint8_t *s_pre)
+{
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+        const uint32_t i = tid + q * BLOCK;
+        if (i <= nc) {
+            s_coff[i] = f.coff[q];
+            if (with_pos)
+                s_pos[i] = f.pos[q];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < FD_ITEMS; k++) {
+        const uint32_t i = tid + k * BLOCK;
+        if (i < nd) {
+            s_decl[i] = f.decl[k];
+            s_pre[i] = (uint8_t)f.pre[k];
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t tile_comps(uint64_t n_comp, uint64_t tile)
+{
+    const uint64_t c0 = tile * FUSED_COMPS;
+    return (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
+}
+
+__device__ __forceinline__ bool decls_fit(const FusedPrefetch &f, uint64_t n_decl)
+{
+    return f.hi >= f.lo && f.hi <= n_decl && f.hi - f.lo <= (uint64_t)FUSED_DCAP;
+}
+
+// Positions given (pos = exclusive scan of the per-component counts).  Persistent:
+// workgroup g writes tiles g, g + G, ...  While it evaluates one tile, the offsets of
+// its next tile are in flight, and the next tile's declarations are requested before
+// the current tile's output is written, so the dependent loads of a tile (offsets,
+// then the declarations they locate) overlap the work on the previous.
 __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *__restrict__ comp_off, uint64_t n_comp,
                                                                const uint32_t *__restrict__ decls, uint64_t n_decl,
                                                                uint32_t n_vars, const uint8_t *__restrict__ pre_abs,
@@ -294,7 +470,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
     __shared__ uint64_t s_coff[FUSED_COMPS + 1], s_pos[FUSED_COMPS + 1];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
 
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t tid = threadIdx.x;
     uint32_t nflag = 0;
     uint64_t tile = blockIdx.x;
     FusedPrefetch cur, nxt;
@@ -306,26 +482,10 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
         const uint64_t tnext = tile + gridDim.x;
         if (tnext < ntiles)
             fused_load_offsets(nxt, comp_off, pos, n_comp, tnext);
-        const uint64_t c0 = tile * FUSED_COMPS;
-        const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
-#pragma unroll
-        for (int q = 0; q < 2; q++) {
-            const uint32_t i = tid + q * BLOCK;
-            if (i <= nc) {
-                s_coff[i] = cur.coff[q];
-                s_pos[i] = cur.pos[q];
-            }
-        }
-        const bool fits = cur.hi >= cur.lo && cur.hi <= n_decl && cur.hi - cur.lo <= (uint64_t)FUSED_DCAP;
+        const uint32_t nc = tile_comps(n_comp, tile);
+        const bool fits = decls_fit(cur, n_decl);
         const uint32_t nd = fits ? (uint32_t)(cur.hi - cur.lo) : 0u;
-#pragma unroll
-        for (int k = 0; k < FD_ITEMS; k++) {
-            const uint32_t i = tid + k * BLOCK;
-            if (i < nd) {
-                s_decl[i] = cur.decl[k];
-                s_pre[i] = (uint8_t)cur.pre[k];
-            }
-        }
+        stage_tile(cur, nc, nd, true, s_coff, s_pos, s_decl, s_pre);
         __syncthreads();
         // staged path: offsets non-decreasing inside [0, n_decl], and few enough
         // declarations and events to stage
@@ -334,131 +494,165 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
             bad |= s_coff[i + 1] < s_coff[i] || s_pos[i + 1] < s_pos[i];
         if (tid == 0)
             bad |= s_pos[nc] - s_pos[0] > (uint64_t)FUSED_CAP;
-        if (__syncthreads_or(bad)) {
-            // one component per thread, written in place
-            if (tid < nc) {
-                const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
-                if (b >= a && b <= n_decl) {
-                    const uint64_t p0 = s_pos[tid], end = s_pos[tid + 1];
-                    uint64_t slot = p0;
-                    for (uint64_t d = a; d < b; d++) {
-                        const uint32_t wd = decls[d];
-                        slot += slot_arity(decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u);
-                    }
-                    uint64_t sp = p0, bp = slot;
-                    for (uint64_t d = a; d < b; d++) {
-                        const uint32_t wd = decls[d];
-                        const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-                        emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, nflag);
-                        sp += slot_arity(mode);
-                        bp += body_arity(mode);
-                    }
-                }
-            }
-            if (tnext < ntiles)
-                fused_load_decls(nxt, decls, pre_abs, n_decl);
-            cur = nxt;
+        const bool in_place = __syncthreads_or(bad);
+        if (in_place) {
+            emit_in_place(nc, n_vars, n_decl, s_coff, s_pos, decls, pre_abs, out, status, nflag);
+        } else {
+            scan_arities(nd, n_vars, s_decl, s_scan, s_wsum);
             __syncthreads();
-            continue;
-        }
-        const uint64_t d_lo = s_coff[0];
-        const uint64_t ebase = s_pos[0];
-        const uint32_t range = (uint32_t)(s_pos[nc] - ebase);
-        // arities of the thread's run of declarations, block-wide exclusive scan
-        const uint32_t i0 = tid * FD_ITEMS;
-        uint32_t pk[FD_ITEMS];
-        uint32_t run = 0;
-#pragma unroll
-        for (int j = 0; j < FD_ITEMS; j++) {
-            const uint32_t i = i0 + j;
-            uint32_t m = 0;
-            if (i < nd) {
-                const uint32_t wd = s_decl[i];
-                const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-                m = slot_arity(mode) | (body_arity(mode) << 16);
-            }
-            pk[j] = m;
-            run += m;
-        }
-        const uint32_t inc = wave_scan_add(run, lane);
-        if (lane == WAVE - 1)
-            s_wsum[wave] = inc;
-        __syncthreads();
-        uint32_t ex = inc - run;
-        for (uint32_t w = 0; w < wave; w++)
-            ex += s_wsum[w];
-#pragma unroll
-        for (int j = 0; j < FD_ITEMS; j++) {
-            const uint32_t i = i0 + j;
-            if (i < nd)
-                s_scan[i] = ex;
-            ex += pk[j];
-        }
-        if (tid == BLOCK - 1)
-            s_scan[nd] = ex;
-        __syncthreads();
-        // emit into LDS: the component of the run's first declaration by binary search,
-        // then forward; the run's declarations and pre-statuses come in as vectors
-        if (i0 < nd) {
-            uint32_t lo = 0, hi = nc; // largest j with s_coff[j] - d_lo <= i0
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_coff[mid] - d_lo <= i0)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            uint32_t j = lo;
-            uint32_t cnext = (uint32_t)(s_coff[j + 1] - d_lo), base_c = s_scan[s_coff[j] - d_lo];
-            uint32_t tot = s_scan[cnext] - base_c;
-            uint64_t pe = s_pos[j] - ebase, end = s_pos[j + 1] - ebase;
-            const uint4 w0 = *reinterpret_cast<const uint4 *>(&s_decl[i0]);
-            const uint4 w1 = *reinterpret_cast<const uint4 *>(&s_decl[i0 + 4]);
-            const uint2 pr = *reinterpret_cast<const uint2 *>(&s_pre[i0]);
-            const uint32_t wds[FD_ITEMS] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w };
-#pragma unroll
-            for (int k = 0; k < FD_ITEMS; k++) {
-                const uint32_t i = i0 + k;
-                if (i < nd) {
-                    if (cnext <= i) { // next component (skipping empty ones)
-                        do
-                            j++;
-                        while (j + 1 < nc && s_coff[j + 1] - d_lo <= i);
-                        cnext = (uint32_t)(s_coff[j + 1] - d_lo);
-                        base_c = s_scan[s_coff[j] - d_lo];
-                        tot = s_scan[cnext] - base_c;
-                        pe = s_pos[j] - ebase;
-                        end = s_pos[j + 1] - ebase;
-                    }
-                    const uint32_t pre = s_scan[i] - base_c;
-                    const uint32_t st = ((k < 4 ? pr.x : pr.y) >> (8 * (k & 3))) & 0xFFu;
-                    emit_decl(wds[k], n_vars, st, pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16), end, s_ev,
-                              s_st, nflag);
-                }
-            }
+            emit_staged(nd, nc, s_coff[0], s_pos[0], n_vars, s_coff, s_pos, s_scan, s_decl, s_pre, s_ev, s_st, nflag);
         }
         // the next tile's declarations are requested before this tile's output is written
         if (tnext < ntiles)
             fused_load_decls(nxt, decls, pre_abs, n_decl);
         __syncthreads();
-        for (uint32_t i = tid; i < range; i += BLOCK)
-            out[ebase + i] = s_ev[i];
-        // status bytes: unaligned head, 4-byte words, tail
-        const uint32_t h0 = (uint32_t)((4u - (ebase & 3u)) & 3u);
-        const uint32_t head = h0 < range ? h0 : range;
-        const uint32_t nwords = (range - head) / 4;
-        if (tid < head)
-            status[ebase + tid] = s_st[tid];
-        uint32_t *sw = reinterpret_cast<uint32_t *>(status + ebase + head);
-        for (uint32_t k = tid; k < nwords; k += BLOCK) {
-            const uint32_t q = head + 4 * k;
-            sw[k] = (uint32_t)s_st[q] | ((uint32_t)s_st[q + 1] << 8) | ((uint32_t)s_st[q + 2] << 16) |
-                    ((uint32_t)s_st[q + 3] << 24);
-        }
-        const uint32_t tail0 = head + 4 * nwords;
-        if (tid < range - tail0)
-            status[ebase + tail0 + tid] = s_st[tail0 + tid];
+        if (!in_place)
+            write_staged((uint32_t)(s_pos[nc] - s_pos[0]), s_pos[0], s_ev, s_st, out, status);
         cur = nxt;
+        __syncthreads();
+    }
+    add_flagged(nflag, n_flagged);
+}
+
+// what is loaded ahead, besides the tile's declarations, when the positions come from
+// per-chunk event counts: the prefix of the counts at the chunk holding the tile's first
+// declaration, and (per thread) the events of the declarations between that chunk's
+// start and the tile's first declaration
+struct ChunkPrefetch {
+    uint64_t cbase;
+    uint32_t part;
+};
+
+__device__ __forceinline__ void fused_load_chunk(ChunkPrefetch &c, const FusedPrefetch &f, const uint32_t *decls,
+                                                 const uint64_t *chunk_prefix, uint64_t n_decl, uint32_t n_vars)
+{
+    c.cbase = 0;
+    c.part = 0;
+    if (f.lo > n_decl)
+        return;
+    const uint64_t first = f.lo - f.lo % HCHUNK;
+    c.cbase = chunk_prefix[f.lo / HCHUNK];
+    const uint32_t np = (uint32_t)(f.lo - first);
+#pragma unroll
+    for (int k = 0; k < HCHUNK / BLOCK; k++) {
+        const uint32_t i = threadIdx.x + k * BLOCK;
+        if (i < np) {
+            const uint32_t wd = decls[first + i];
+            const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+            c.part += slot_arity(mode) + body_arity(mode);
+        }
+    }
+}
+
+// Positions found on the device: the events before a tile are the prefix of the
+// per-chunk event counts (HCHUNK declarations a chunk, counted by the histogram pass)
+// at the chunk of the tile's first declaration plus the events of the declarations of
+// that chunk before it; inside the tile, a block scan.  Persistent and prefetching like
+// k_translate_emit_fused.  Malformed component offsets are reported with the
+// component's index (as the per-component count does on the other path).
+__global__ __launch_bounds__(BLOCK) void k_translate_emit_fused_dev(
+    const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
+    uint32_t n_vars, const uint8_t *__restrict__ pre_abs, const uint64_t *__restrict__ chunk_prefix,
+    uint32_t *__restrict__ out, uint8_t *__restrict__ status, uint64_t ntiles, Control *ctl,
+    unsigned long long *__restrict__ n_flagged, uint64_t cap)
+{
+    __shared__ uint32_t s_ev[FUSED_CAP];
+    __shared__ uint8_t s_st[FUSED_CAP];
+    __shared__ __align__(16) uint32_t s_decl[FUSED_DCAP];
+    __shared__ uint32_t s_scan[FUSED_DCAP + 1];
+    __shared__ __align__(16) uint8_t s_pre[FUSED_DCAP];
+    __shared__ uint64_t s_coff[FUSED_COMPS + 1], s_pos[FUSED_COMPS + 1];
+    __shared__ uint32_t s_wsum[BLOCK / WAVE], s_psum[BLOCK / WAVE];
+
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    uint32_t nflag = 0;
+    uint64_t tile = blockIdx.x;
+    FusedPrefetch cur, nxt;
+    ChunkPrefetch ccur, cnxt;
+    if (tile < ntiles) {
+        fused_load_offsets(cur, comp_off, nullptr, n_comp, tile);
+        fused_load_decls(cur, decls, pre_abs, n_decl);
+        fused_load_chunk(ccur, cur, decls, chunk_prefix, n_decl, n_vars);
+    }
+    for (; tile < ntiles; tile += gridDim.x) {
+        const uint64_t tnext = tile + gridDim.x;
+        if (tnext < ntiles)
+            fused_load_offsets(nxt, comp_off, nullptr, n_comp, tnext);
+        const uint64_t c0 = tile * FUSED_COMPS;
+        const uint32_t nc = tile_comps(n_comp, tile);
+        const bool fits = decls_fit(cur, n_decl);
+        const uint32_t nd = fits ? (uint32_t)(cur.hi - cur.lo) : 0u;
+        stage_tile(cur, nc, nd, false, s_coff, s_pos, s_decl, s_pre);
+        __syncthreads();
+        // malformed offsets: reported; such a component has no events
+        bool bad = !fits;
+        for (uint32_t i = tid; i < nc; i += BLOCK) {
+            const uint64_t a = s_coff[i], b = s_coff[i + 1];
+            if (b < a || b > n_decl || (c0 + i == 0 && a != 0)) {
+                bad = true;
+                report_bad(ctl, c0 + i);
+            }
+        }
+        const bool staged_scan = !__syncthreads_or(bad);
+        if (staged_scan)
+            scan_arities(nd, n_vars, s_decl, s_scan, s_wsum);
+        __syncthreads();
+        // events per component, exclusive block scan; the tile's base
+        uint32_t cnt = 0;
+        if (tid < nc) {
+            const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
+            if (staged_scan) {
+                const uint32_t x = s_scan[b - s_coff[0]], y = s_scan[a - s_coff[0]];
+                cnt = ((x & 0xFFFFu) + (x >> 16)) - ((y & 0xFFFFu) + (y >> 16));
+            } else if (b >= a && b <= n_decl && !(c0 + tid == 0 && a != 0)) {
+                for (uint64_t d = a; d < b; d++) {
+                    const uint32_t wd = decls[d];
+                    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                    cnt += slot_arity(mode) + body_arity(mode);
+                }
+            }
+        }
+        const uint32_t inc = wave_scan_add(cnt, lane);
+        uint32_t part = ccur.part;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1)
+            part += __shfl_xor(part, d);
+        if (lane == WAVE - 1) {
+            s_wsum[wave] = inc;
+            s_psum[wave] = part;
+        }
+        __syncthreads();
+        uint32_t ex = inc - cnt, total = 0;
+        uint64_t base = ccur.cbase;
+        for (uint32_t w = 0; w < BLOCK / WAVE; w++) {
+            if (w < wave)
+                ex += s_wsum[w];
+            total += s_wsum[w];
+            base += s_psum[w];
+        }
+        // positions clamp to the output's capacity: only malformed offsets (reported)
+        // can make the events outnumber 5 per declaration
+        const uint64_t ebase = base < cap ? base : cap;
+        if (tid < nc)
+            s_pos[tid] = base + ex < cap ? base + ex : cap;
+        if (tid == 0)
+            s_pos[nc] = base + total < cap ? base + total : cap;
+        __syncthreads();
+        const bool staged = staged_scan && s_pos[nc] - ebase <= (uint64_t)FUSED_CAP;
+        if (staged)
+            emit_staged(nd, nc, s_coff[0], ebase, n_vars, s_coff, s_pos, s_scan, s_decl, s_pre, s_ev, s_st, nflag);
+        else
+            emit_in_place(nc, n_vars, n_decl, s_coff, s_pos, decls, pre_abs, out, status, nflag);
+        // the next tile's declarations are requested before this tile's output is written
+        if (tnext < ntiles) {
+            fused_load_decls(nxt, decls, pre_abs, n_decl);
+            fused_load_chunk(cnxt, nxt, decls, chunk_prefix, n_decl, n_vars);
+        }
+        __syncthreads();
+        if (staged)
+            write_staged((uint32_t)(s_pos[nc] - ebase), ebase, s_ev, s_st, out, status);
+        cur = nxt;
+        ccur = cnxt;
         __syncthreads();
     }
     add_flagged(nflag, n_flagged);
@@ -482,6 +676,19 @@ void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, cons
     const uint64_t tiles = ceil_div(n_comp, FUSED_COMPS);
     k_translate_emit_fused<<<resident_grid((const void *)k_translate_emit_fused, tiles), BLOCK, 0, s>>>(
         comp_off, n_comp, decls, n_decl, n_vars, pre_abs, pos, out, status, &ctl->n_flagged, tiles);
+}
+
+void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                                     uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *chunk_prefix,
+                                     uint32_t *out, uint8_t *status, Control *tr_ctl, Control *ctl, hipStream_t s)
+{
+    if (!n_comp)
+        return;
+    const uint64_t tiles = ceil_div(n_comp, FUSED_COMPS);
+    ProfScope prof_(s, "translate_emit_fused_dev");
+    k_translate_emit_fused_dev<<<resident_grid((const void *)k_translate_emit_fused_dev, tiles), BLOCK, 0, s>>>(
+        comp_off, n_comp, decls, n_decl, n_vars, pre_abs, chunk_prefix, out, status, tiles, tr_ctl, &ctl->n_flagged,
+        5 * n_decl);
 }
 
 void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint64_t *items, Control *ctl,

@@ -65,6 +65,56 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
     TranslateState &tr = *t->tr;
     int r;
     uint64_t n_decl = tr.n_decl, n_comp = tr.n_comp;
+    const bool bucketed = tr.n_vars <= bucket_max_ids() && !getenv("VC_GENERAL_PATH");
+    // canonical bodies with the check requested: the check is fused into the emission
+    tr.fused = tr.check && !tr.body_off && bucketed && !getenv("VC_UNFUSED");
+    // ... and the positions are found by the emission itself when the largest possible
+    // length (5 events per declaration) stays below 2^31
+    tr.device_sized = tr.fused && 5 * n_decl < (1ull << 31) && !getenv("VC_HOST_SIZED");
+    if (tr.device_sized) {
+        const uint64_t cap = 5 * n_decl ? 5 * n_decl : 1;
+        const uint64_t nchunks = ceil_div(n_decl, (uint64_t)HCHUNK);
+        hipError_t e;
+        // per-chunk event counts and their exclusive prefix (in the count and position
+        // buffers, which this way of placing the events does not otherwise use)
+        if ((r = devbuf_reserve(tr.cnt, (nchunks ? nchunks : 1) * 4)) != VC_OK ||
+            (r = devbuf_reserve(tr.pos, (nchunks + 1) * 8)) != VC_OK ||
+            (r = devbuf_reserve(tr.pre_abs, n_decl ? n_decl : 1)) != VC_OK ||
+            (r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK ||
+            (r = devbuf_reserve(tr.scratch, std::max(bucket_scratch_bytes(n_decl, tr.n_vars),
+                                                     excl_scan_scratch_bytes(nchunks)))) != VC_OK ||
+            (r = devbuf_reserve(t->status, cap)) != VC_OK || (r = devbuf_reserve(t->fin, 2 * (size_t)tr.n_vars)) != VC_OK ||
+            (r = devbuf_reserve(t->viol, cap * 4)) != VC_OK ||
+            (r = devbuf_reserve(t->scratch, compact_scratch_bytes(cap))) != VC_OK)
+            return r;
+        if (!t->events || cap > t->events_cap) {
+            if (t->events)
+                (void)hipFree(t->events);
+            t->events = nullptr;
+            if ((e = hipMalloc(&t->events, cap * 4)) != hipSuccess)
+                return vc_hip_fail(e, "hipMalloc(translated events)");
+            t->events_cap = cap;
+            t->own_events = true;
+        }
+        t->n = 0; // set from the device when the work is collected
+        launch_reset_control(tr.ctl, s);
+        launch_reset_control(t->ctl, s);
+        launch_fill_u8((uint8_t *)tr.final_abs.p, 1, tr.n_vars, s);
+        launch_bucket_decl_pre(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, (uint8_t *)tr.final_abs.p,
+                               tr.scratch.p, tr.ctl, s, t->ctx->cu_count, (uint32_t *)tr.cnt.p);
+        // the translated length lands in tr.ctl->n_out
+        launch_excl_scan((uint32_t *)tr.cnt.p, nchunks, (uint64_t *)tr.pos.p,
+                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), tr.scratch.p, tr.ctl->tickets[4], s);
+        launch_translate_emit_fused_dev(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
+                                        (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, tr.ctl, t->ctl, s);
+        // final store: each real variable ends where its abstract variable ends
+        uint8_t *fin = (uint8_t *)t->fin.p;
+        (void)hipMemcpyAsync(fin, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(fin + tr.n_vars, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
+        launch_compact((uint8_t *)t->status.p, cap, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s,
+                       &t->ctl->n_flagged, &tr.ctl->n_out);
+        return VC_OK;
+    }
     // counts and positions of each component's translated events
     if ((r = devbuf_reserve(tr.cnt, (n_comp ? n_comp : 1) * 4)) != VC_OK)
         return r;
@@ -76,7 +126,6 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         return r;
     if ((r = devbuf_reserve(tr.items_b, (n_decl ? n_decl : 1) * 8)) != VC_OK)
         return r;
-    bool bucketed = tr.n_vars <= bucket_max_ids() && !getenv("VC_GENERAL_PATH");
     size_t sc = std::max({ bucketed ? bucket_scratch_bytes(n_decl, tr.n_vars) : sort_scratch_bytes(n_decl),
                            scan_scratch_bytes(n_decl), excl_scan_scratch_bytes(n_comp) });
     if ((r = devbuf_reserve(tr.scratch, sc)) != VC_OK)
@@ -88,8 +137,6 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         if (e != hipSuccess)
             return vc_hip_fail(e, "translation size buffer");
     }
-    // canonical bodies with the check requested: the check is fused into the emission
-    tr.fused = tr.check && !tr.body_off && bucketed && !getenv("VC_UNFUSED");
     if (tr.fused) {
         if ((r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK)
             return r;

@@ -165,3 +165,54 @@ def test_fused_and_unfused_check_agree(ctx, n_comp, n_vars):
     assert np.array_equal(fused.status(), ref.status) and np.array_equal(fused.final(), ref.final)
     fused.free()
     unfused.free()
+
+
+@pytest.mark.parametrize("n_comp,n_vars,kmax", [(5000, 64, 8), (100_000, 1 << 14, 8), (300_001, 1 << 20, 8),
+                                                (20_000, 1 << 10, 40)])
+def test_device_and_host_sized_agree(ctx, n_comp, n_vars, kmax):
+    """The fused translation finds its positions on the device (tiles look back for their
+    base); with VC_HOST_SIZED it takes the per-component counts and the host-read length
+    instead.  Same bytes, and the oracle's."""
+    import os
+    ct = gen.component_trace(n_comp, n_vars, 23 + kmax, kmax=kmax)
+    say(f"[translate] device vs host sized {n_comp}x{n_vars} kmax {kmax}")
+    dev = gpu_translate(ctx, ct.comp_off, ct.decls, ct.n_vars)
+    os.environ["VC_HOST_SIZED"] = "1"
+    try:
+        host = gpu_translate(ctx, ct.comp_off, ct.decls, ct.n_vars)
+    finally:
+        del os.environ["VC_HOST_SIZED"]
+    ref_tr = O.translate(ct.comp_off, ct.decls, ct.n_vars)
+    ref = O.check(ref_tr, 2 * ct.n_vars)
+    for t in (dev, host):
+        assert t.info()[0] == ref_tr.size
+        assert np.array_equal(t.events(), ref_tr)
+        assert np.array_equal(t.status(), ref.status)
+        assert np.array_equal(t.final(), ref.final)
+        v = t.violations()
+        assert v.total == ref.violations.size and v.first == ref.first
+        t.free()
+
+
+@pytest.mark.parametrize("host_sized", [False, True])
+def test_translation_malformed_offsets_device(ctx, host_sized):
+    """Component offsets in device memory that decrease are reported with the index of
+    the component, on both ways of placing the events."""
+    import os
+    import torch
+    from paper_1910_11110_amd import vcheck as V
+    co = np.array([0, 3, 1, 4], np.uint64)  # component 1 ends before it starts
+    de = np.array([decl("R", "CPU", 0), decl("W", "GPU", 1), decl("RW", "CPU", 2), decl("R", "GPU", 3)], np.uint32)
+    tco = torch.from_numpy(co.view(np.int64)).cuda()
+    tde = torch.from_numpy(de.view(np.int32)).cuda()
+    torch.cuda.synchronize()
+    if host_sized:
+        os.environ["VC_HOST_SIZED"] = "1"
+    try:
+        with pytest.raises(V.VCError) as ex:
+            t = V.translate(ctx, tco, tde, 4, check=True)
+            ctx.sync()
+            t.free()
+    finally:
+        os.environ.pop("VC_HOST_SIZED", None)
+    assert "index 1" in str(ex.value)
