@@ -75,6 +75,8 @@ typedef struct vc_server vc_server;
  * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream).
  * --------------------------------------------------------------------------------- */
 int vc_ctx_create(int hip_device, void *hip_stream, vc_ctx **out);
+/* Waits for the context's work and frees it.  Traces made on it stay valid only to be
+ * passed to vc_trace_free; any other call on them returns VC_ESTATE. */
 int vc_ctx_destroy(vc_ctx *ctx);
 const char *vc_last_error(void);
 /* blocks until all work enqueued on the context's stream is done; returns the first

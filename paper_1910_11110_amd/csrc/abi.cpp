@@ -110,6 +110,11 @@ extern "C" int vc_ctx_destroy(vc_ctx *c)
         return VC_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    // traces outlive their context only to be freed: detach them
+    for (vc_trace *t : c->traces) {
+        t->ctx = nullptr;
+        t->pending = false;
+    }
     batch_release(c);
     prof_destroy(c);
     if (c->own_stream)
@@ -256,6 +261,7 @@ extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint
     }
     vc_trace *t = new vc_trace();
     t->ctx = c;
+    c->traces.push_back(t);
     t->n = n;
     t->n_ids = n_ids;
     int r = trace_alloc_common(c, t);
@@ -282,10 +288,20 @@ extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint
     return VC_OK;
 }
 
-extern "C" int vc_trace_info(vc_trace *t, uint64_t *n_events, uint32_t *n_ids)
+int trace_usable(vc_trace *t, const char *fn)
 {
     if (!t)
-        return vc_fail(VC_EINVAL, "vc_trace_info: NULL trace");
+        return vc_fail(VC_EINVAL, "%s: NULL trace", fn);
+    if (!t->ctx)
+        return vc_fail(VC_ESTATE, "%s: the trace's context has been destroyed", fn);
+    return VC_OK;
+}
+
+extern "C" int vc_trace_info(vc_trace *t, uint64_t *n_events, uint32_t *n_ids)
+{
+    int r0 = trace_usable(t, "vc_trace_info");
+    if (r0 != VC_OK)
+        return r0;
     if (t->translate_pending) { // the translated length is known once the work is done
         int r = vc_sync(t->ctx);
         if (r != VC_OK)
@@ -400,8 +416,9 @@ int enqueue_check(vc_trace *t, hipStream_t s)
 
 extern "C" int vc_check(vc_trace *t)
 {
-    if (!t)
-        return vc_fail(VC_EINVAL, "vc_check: NULL trace");
+    int r0 = trace_usable(t, "vc_check");
+    if (r0 != VC_OK)
+        return r0;
     vc_ctx *c = t->ctx;
     if (t->translate_pending) { // a check needs the translated length
         int r = vc_sync(c);
@@ -427,8 +444,9 @@ extern "C" int vc_check(vc_trace *t)
 
 static int require_checked(vc_trace *t, const char *fn)
 {
-    if (!t)
-        return vc_fail(VC_EINVAL, "%s: NULL trace", fn);
+    int r0 = trace_usable(t, fn);
+    if (r0 != VC_OK)
+        return r0;
     if (t->pending) {
         int r = vc_sync(t->ctx);
         if (r != VC_OK)
@@ -443,8 +461,9 @@ static int require_checked(vc_trace *t, const char *fn)
 
 extern "C" int vc_read_events(vc_trace *t, uint32_t *out, uint64_t cap, uint64_t *n)
 {
-    if (!t)
-        return vc_fail(VC_EINVAL, "vc_read_events: NULL trace");
+    int r0 = trace_usable(t, "vc_read_events");
+    if (r0 != VC_OK)
+        return r0;
     if (t->pending) {
         int r = vc_sync(t->ctx);
         if (r != VC_OK)
@@ -525,8 +544,9 @@ extern "C" int vc_read_induced_stuck(vc_trace *t, uint64_t *n)
 
 extern "C" int vc_trace_device_results(vc_trace *t, void **status, void **final_status, void **violations)
 {
-    if (!t)
-        return vc_fail(VC_EINVAL, "vc_trace_device_results: NULL trace");
+    int r0 = trace_usable(t, "vc_trace_device_results");
+    if (r0 != VC_OK)
+        return r0;
     if (status)
         *status = t->status.p;
     if (final_status)
@@ -546,6 +566,8 @@ extern "C" int vc_trace_free(vc_trace *t)
         (void)hipStreamSynchronize(c->stream);
         auto &p = c->pending;
         p.erase(std::remove(p.begin(), p.end(), t), p.end());
+        auto &l = c->traces;
+        l.erase(std::remove(l.begin(), l.end(), t), l.end());
     }
     if (t->own_events && t->events)
         (void)hipFree(t->events);

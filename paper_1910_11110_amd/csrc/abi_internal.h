@@ -42,6 +42,7 @@ struct vc_ctx {
     bool own_stream = false;
     int cu_count = 256;
     std::vector<vc_trace *> pending; // traces with enqueued work not yet collected
+    std::vector<vc_trace *> traces;  // live traces (detached when the context goes)
     BatchState *batch = nullptr;
     vc::Profiler *prof = nullptr;
 };
@@ -53,6 +54,9 @@ struct ProfGuard {
     ~ProfGuard();
 };
 void prof_collect(vc_ctx *c);
+// VC_OK for a trace whose context is alive; else the error (NULL trace, or a context
+// already destroyed), recorded for vc_last_error under `fn`
+int trace_usable(vc_trace *t, const char *fn);
 bool prof_on(vc_ctx *c);
 void prof_destroy(vc_ctx *c);
 

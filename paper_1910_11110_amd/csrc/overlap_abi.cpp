@@ -48,8 +48,11 @@ int size_expansion(vc_trace *t)
 
 extern "C" int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi, uint32_t flags)
 {
-    if (!t || !lo || !hi)
+    if (!lo || !hi)
         return vc_fail(VC_EINVAL, "vc_trace_set_arrays: NULL argument");
+    int r0 = trace_usable(t, "vc_trace_set_arrays");
+    if (r0 != VC_OK)
+        return r0;
     if (t->tr)
         return vc_fail(VC_EINVAL, "vc_trace_set_arrays: arrays apply to loaded traces, not translations");
     vc_ctx *c = t->ctx;
@@ -107,8 +110,9 @@ extern "C" int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32
 
 extern "C" int vc_read_overlap_sets(vc_trace *t, uint64_t *off, uint32_t *nbr, uint64_t cap, uint64_t *n_nbr)
 {
-    if (!t)
-        return vc_fail(VC_EINVAL, "vc_read_overlap_sets: NULL trace");
+    int r0 = trace_usable(t, "vc_read_overlap_sets");
+    if (r0 != VC_OK)
+        return r0;
     if (!t->has_arrays)
         return vc_fail(VC_ESTATE, "vc_read_overlap_sets: no arrays set");
     hipError_t e;

@@ -227,6 +227,57 @@ __device__ __forceinline__ void emit_decl(uint32_t wd, uint32_t n_vars, uint32_t
         put(body_p, v | (OP_W << 24) | sbit, eff_f4<OP_W>(side), eff_stuck<OP_W>(side), sr);
 }
 
+// The same into LDS, without branches on the mode or the guard: positions are relative
+// to the tile (< FUSED_CAP) and every candidate event is a predicated store.  The guard
+// pair acts on v and v# from the same status; the abstract write follows the guard;
+// the body's r and w act on v from its status after the guard.
+__device__ __forceinline__ void emit_decl_lds(uint32_t wd, uint32_t n_vars, uint32_t st, uint32_t slot_p,
+                                              uint32_t body_p, uint32_t end, uint32_t *ev, uint8_t *stat,
+                                              uint32_t &nflag)
+{
+    const bool ok = decl_ok(wd, n_vars);
+    const uint32_t v = ok ? wd & 0xFFFFFFu : 0u, mode = ok ? (wd >> 24) & 3u : 0u, side = (wd >> 27) & 1u;
+    const bool reads = mode != 1u, writes = mode != 0u;
+    const uint32_t sbit = side << 27, vabs = n_vars + v;
+    const bool valid = (st >> side) & 1u;
+    // guard: Noop on the side when valid, else the local transfer toward the side
+    const uint32_t gop = valid ? OP_NOOP : (side ? OP_PUSH : OP_PULL);
+    const uint32_t gf4 = valid ? TABLE.f4[fcode(OP_NOOP, 0)]
+                               : (side ? TABLE.f4[fcode(OP_PUSH, 0)] : TABLE.f4[fcode(OP_PULL, 0)]);
+    const uint32_t gstk = valid ? 0u : (side ? TABLE.stuck[fcode(OP_PUSH, 0)] : TABLE.stuck[fcode(OP_PULL, 0)]);
+    const uint32_t gpost = fapply(gf4, st), gflag = (gstk >> st) & 1u;
+    const uint32_t gword = (gop << 24) | (valid ? sbit : 0u);
+    const uint8_t gbyte = (uint8_t)(gpost | (st << 2) | (gflag << 7));
+    // status of v and v# after the guard (the declaration's status if it has none)
+    const uint32_t s1 = reads ? gpost : st;
+    const uint32_t wpost = fapply(eff_f4<OP_W>(side), s1); // constant: the side's copy only
+    const uint8_t wbyte = (uint8_t)(wpost | (s1 << 2));    // w is never stuck
+    const uint32_t rflag = (eff_stuck<OP_R>(side) >> s1) & 1u;
+    const uint8_t rbyte = (uint8_t)(fapply(eff_f4<OP_R>(side), s1) | (s1 << 2) | (rflag << 7));
+    const uint32_t pw = slot_p + (reads ? 2u : 0u), pbw = body_p + (reads ? 1u : 0u);
+    if (reads && slot_p < end) {
+        ev[slot_p] = v | gword;
+        stat[slot_p] = gbyte;
+    }
+    if (reads && slot_p + 1 < end) {
+        ev[slot_p + 1] = vabs | gword;
+        stat[slot_p + 1] = gbyte;
+    }
+    if (writes && pw < end) {
+        ev[pw] = vabs | (OP_W << 24) | sbit;
+        stat[pw] = wbyte;
+    }
+    if (reads && body_p < end) {
+        ev[body_p] = v | (OP_R << 24) | sbit;
+        stat[body_p] = rbyte;
+    }
+    if (writes && pbw < end) {
+        ev[pbw] = v | (OP_W << 24) | sbit;
+        stat[pbw] = wbyte;
+    }
+    nflag += reads ? 2u * gflag + rflag : 0u;
+}
+
 // adds the wave's flagged events to the global count (one atomic per wave that has any)
 __device__ __forceinline__ void add_flagged(uint32_t nflag, unsigned long long *n_flagged)
 {
@@ -357,8 +408,8 @@ __device__ __forceinline__ void emit_staged(uint32_t nd, uint32_t nc, uint64_t d
             }
             const uint32_t pre = s_scan[i] - base_c;
             const uint32_t st = ((k < 4 ? pr.x : pr.y) >> (8 * (k & 3))) & 0xFFu;
-            emit_decl(wds[k], n_vars, st, pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16), end, s_ev, s_st,
-                      nflag);
+            emit_decl_lds(wds[k], n_vars, st, (uint32_t)pe + (pre & 0xFFFFu),
+                          (uint32_t)pe + (tot & 0xFFFFu) + (pre >> 16), (uint32_t)end, s_ev, s_st, nflag);
         }
     }
 }

@@ -239,6 +239,7 @@ extern "C" int vc_translate(vc_ctx *c, const uint64_t *comp_off, uint64_t n_comp
 
     vc_trace *t = new vc_trace();
     t->ctx = c;
+    c->traces.push_back(t);
     t->n_ids = 2 * n_vars;
     t->tr = new TranslateState();
     TranslateState &tr = *t->tr;
@@ -290,7 +291,10 @@ extern "C" int vc_translate(vc_ctx *c, const uint64_t *comp_off, uint64_t n_comp
 
 extern "C" int vc_translate_run(vc_trace *t)
 {
-    if (!t || !t->tr)
+    int r0 = trace_usable(t, "vc_translate_run");
+    if (r0 != VC_OK)
+        return r0;
+    if (!t->tr)
         return vc_fail(VC_EINVAL, "vc_translate_run: not a translated trace");
     vc_ctx *c = t->ctx;
     (void)hipSetDevice(c->device);

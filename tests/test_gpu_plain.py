@@ -197,3 +197,19 @@ def test_bucket_path_skewed_ids(ctx):
     pick = gen.below(gen.draws(77, 81, 0, n), 10) < 8
     e = np.where(pick, hot, e).astype(np.uint32)
     assert_parity(ctx, e, n_ids, label="skewed")
+
+
+def test_trace_outlives_context():
+    """A trace whose context was destroyed can only be freed: other calls report
+    VC_ESTATE, and freeing it later is safe."""
+    from paper_1910_11110_amd import vcheck as V
+    c = V.Context(0)
+    t = V.Trace.load(c, gen.plain_events(5000, 64, 3), 64)
+    t.check()
+    c.close()
+    with pytest.raises(V.VCError) as ex:
+        t.info()
+    assert ex.value.code == V.VC_ESTATE
+    with pytest.raises(V.VCError):
+        t.check()
+    t.free()
