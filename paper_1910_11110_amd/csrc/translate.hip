@@ -162,11 +162,18 @@ __global__ void k_translate_emit(const uint64_t *__restrict__ comp_off, uint64_t
 // applies to v#, so the two agree at every declaration from the common initial
 // (V,I)).  One workgroup writes 256 consecutive components.
 constexpr EffectTable TABLE = make_table();
-constexpr int FUSED_COMPS = BLOCK;             // components per tile
-constexpr int FUSED_DCAP = 2048;               // declarations staged per tile
-constexpr int FD_ITEMS = FUSED_DCAP / BLOCK;   // declarations per thread
-static_assert(FD_ITEMS == 8, "the emitter reads a thread's run of declarations as two 16-byte vectors");
-constexpr int FUSED_CAP = 6144;                // events staged per tile
+#ifndef VC_FUSED_WAVES
+#define VC_FUSED_WAVES 5
+#endif
+#ifndef VC_FUSED_COMPS
+#define VC_FUSED_COMPS 128
+#endif
+constexpr int FUSED_COMPS = VC_FUSED_COMPS;             // components per tile
+constexpr int FUSED_DCAP = FUSED_COMPS * 8;             // declarations staged per tile
+constexpr int FD_ITEMS = FUSED_DCAP / BLOCK;            // declarations per thread
+constexpr int FUSED_CAP = FUSED_COMPS * 24;             // events staged per tile
+static_assert(FUSED_COMPS <= BLOCK && FD_ITEMS % 4 == 0,
+              "one component per thread on the in-place path; runs read as 16-byte vectors");
 
 // function (4-byte form) and stuck mask of an effect, as immediates chosen by the side
 template <uint32_t OP>
@@ -291,11 +298,13 @@ __device__ __forceinline__ void add_flagged(uint32_t nflag, unsigned long long *
 
 // what a workgroup loads ahead for one tile of components: offsets and positions (two
 // per thread), the declaration range, and the declarations with their pre-statuses
+constexpr int CO_ITEMS = (FUSED_COMPS + BLOCK) / BLOCK; // offsets per thread (FUSED_COMPS + 1 of them)
+
 struct FusedPrefetch {
-    uint64_t coff[2], pos[2];
+    uint64_t coff[CO_ITEMS], pos[CO_ITEMS];
     uint64_t lo, hi;
     uint32_t decl[FD_ITEMS];
-    uint32_t pre[FD_ITEMS];
+    uint32_t pre4[FD_ITEMS / 4]; // pre-statuses, 4 per word
 };
 
 __device__ __forceinline__ void fused_load_offsets(FusedPrefetch &f, const uint64_t *comp_off, const uint64_t *pos,
@@ -304,7 +313,7 @@ __device__ __forceinline__ void fused_load_offsets(FusedPrefetch &f, const uint6
     const uint64_t c0 = tile * FUSED_COMPS;
     const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)FUSED_COMPS ? n_comp - c0 : (uint64_t)FUSED_COMPS);
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < CO_ITEMS; q++) {
         const uint32_t i = threadIdx.x + q * BLOCK;
         f.coff[q] = i <= nc ? comp_off[c0 + i] : 0ull;
         f.pos[q] = i <= nc && pos ? pos[c0 + i] : 0ull;
@@ -319,10 +328,13 @@ __device__ __forceinline__ void fused_load_decls(FusedPrefetch &f, const uint32_
     const bool fits = f.hi >= f.lo && f.hi <= n_decl && f.hi - f.lo <= (uint64_t)FUSED_DCAP;
     const uint32_t nd = fits ? (uint32_t)(f.hi - f.lo) : 0u;
 #pragma unroll
+    for (int q = 0; q < FD_ITEMS / 4; q++)
+        f.pre4[q] = 0;
+#pragma unroll
     for (int k = 0; k < FD_ITEMS; k++) {
         const uint32_t i = threadIdx.x + k * BLOCK;
         f.decl[k] = i < nd ? decls[f.lo + i] : 0u;
-        f.pre[k] = i < nd ? pre_abs[f.lo + i] : 0u;
+        f.pre4[k >> 2] |= (i < nd ? (uint32_t)pre_abs[f.lo + i] : 0u) << (8 * (k & 3));
     }
 }
 
@@ -388,10 +400,16 @@ __device__ __forceinline__ void emit_staged(uint32_t nd, uint32_t nc, uint64_t d
     uint32_t cnext = (uint32_t)(s_coff[j + 1] - d_lo), base_c = s_scan[s_coff[j] - d_lo];
     uint32_t tot = s_scan[cnext] - base_c;
     uint64_t pe = s_pos[j] - ebase, end = s_pos[j + 1] - ebase;
-    const uint4 w0 = *reinterpret_cast<const uint4 *>(&s_decl[i0]);
-    const uint4 w1 = *reinterpret_cast<const uint4 *>(&s_decl[i0 + 4]);
-    const uint2 pr = *reinterpret_cast<const uint2 *>(&s_pre[i0]);
-    const uint32_t wds[FD_ITEMS] = { w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w };
+    uint32_t wds[FD_ITEMS], prs[FD_ITEMS / 4];
+#pragma unroll
+    for (int q = 0; q < FD_ITEMS / 4; q++) {
+        const uint4 w = *reinterpret_cast<const uint4 *>(&s_decl[i0 + 4 * q]);
+        wds[4 * q] = w.x;
+        wds[4 * q + 1] = w.y;
+        wds[4 * q + 2] = w.z;
+        wds[4 * q + 3] = w.w;
+        prs[q] = *reinterpret_cast<const uint32_t *>(&s_pre[i0 + 4 * q]);
+    }
 #pragma unroll
     for (int k = 0; k < FD_ITEMS; k++) {
         const uint32_t i = i0 + k;
@@ -407,7 +425,7 @@ __device__ __forceinline__ void emit_staged(uint32_t nd, uint32_t nc, uint64_t d
                 end = s_pos[j + 1] - ebase;
             }
             const uint32_t pre = s_scan[i] - base_c;
-            const uint32_t st = ((k < 4 ? pr.x : pr.y) >> (8 * (k & 3))) & 0xFFu;
+            const uint32_t st = (prs[k >> 2] >> (8 * (k & 3))) & 0xFFu;
             emit_decl_lds(wds[k], n_vars, st, (uint32_t)pe + (pre & 0xFFFFu),
                           (uint32_t)pe + (tot & 0xFFFFu) + (pre >> 16), (uint32_t)end, s_ev, s_st, nflag);
         }
@@ -471,7 +489,7 @@ __device__ __forceinline__ void stage_tile(const FusedPrefetch &f, uint32_t nc, 
 {
     const uint32_t tid = threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 2; q++) {
+    for (int q = 0; q < CO_ITEMS; q++) {
         const uint32_t i = tid + q * BLOCK;
         if (i <= nc) {
             s_coff[i] = f.coff[q];
@@ -484,7 +502,7 @@ __device__ __forceinline__ void stage_tile(const FusedPrefetch &f, uint32_t nc, 
         const uint32_t i = tid + k * BLOCK;
         if (i < nd) {
             s_decl[i] = f.decl[k];
-            s_pre[i] = (uint8_t)f.pre[k];
+            s_pre[i] = (uint8_t)(f.pre4[k >> 2] >> (8 * (k & 3)));
         }
     }
 }
@@ -601,7 +619,7 @@ __device__ __forceinline__ void fused_load_chunk(ChunkPrefetch &c, const FusedPr
 // that chunk before it; inside the tile, a block scan.  Persistent and prefetching like
 // k_translate_emit_fused.  Malformed component offsets are reported with the
 // component's index (as the per-component count does on the other path).
-__global__ __launch_bounds__(BLOCK) void k_translate_emit_fused_dev(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(VC_FUSED_WAVES))) void k_translate_emit_fused_dev(
     const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
     uint32_t n_vars, const uint8_t *__restrict__ pre_abs, const uint64_t *__restrict__ chunk_prefix,
     uint32_t *__restrict__ out, uint8_t *__restrict__ status, uint64_t ntiles, Control *ctl,
