@@ -25,6 +25,7 @@ struct BucketLayout {
     uint32_t *hist = nullptr;
     uint64_t *base = nullptr;
     uint32_t *tbase = nullptr;
+    uint32_t *order = nullptr; // bucket tile (bucket-major index) taken by each ticket
     uint64_t *lbp = nullptr, *lbv = nullptr, *lbc = nullptr;
     uint32_t *part = nullptr;
     uint8_t *res = nullptr;

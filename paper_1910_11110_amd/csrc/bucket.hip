@@ -235,6 +235,40 @@ __global__ __launch_bounds__(1024) void k_bucket_bases(const uint32_t *__restric
     }
 }
 
+// Order in which the bucket tiles are taken: round r holds tile r of every bucket that
+// has more than r tiles, in bucket order.  A tile's look-back only waits on earlier
+// tiles of its own bucket, which come in earlier rounds; interleaving the buckets keeps
+// few tiles of one bucket in flight at once, so its walks stay short.  Tile (b, r) goes
+// to position sum_b' min(T_b', r) + #{b' < b : T_b' > r}.
+__global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restrict__ tbase, uint32_t nb,
+                                                        uint32_t *__restrict__ order)
+{
+    __shared__ uint32_t s_t[MAX_BUCKETS + 1];
+    for (uint32_t i = threadIdx.x; i <= nb; i += BLOCK)
+        s_t[i] = tbase[i];
+    __syncthreads();
+    const uint32_t ntiles = s_t[nb];
+    const uint32_t G = blockIdx.x * BLOCK + threadIdx.x;
+    if (G >= ntiles)
+        return;
+    uint32_t lo = 0, hi = nb; // bucket of G: largest b with tbase[b] <= G
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_t[mid] <= G)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const uint32_t b = lo, r = G - s_t[b];
+    uint32_t k = 0;
+    for (uint32_t b2 = 0; b2 < nb; b2++) {
+        const uint32_t t2 = s_t[b2 + 1] - s_t[b2];
+        k += t2 < r ? t2 : r;
+        k += (b2 < b && t2 > r) ? 1u : 0u;
+    }
+    order[k] = G;
+}
+
 // ----------------------------------------------------------------------------------
 // 1. partition by bucket
 // ----------------------------------------------------------------------------------
@@ -347,7 +381,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                                                        const uint32_t *__restrict__ tbase,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ out,
                                                        uint8_t *__restrict__ final_out, uint64_t *__restrict__ lbv,
-                                                       uint32_t *__restrict__ ticket)
+                                                       uint32_t *__restrict__ ticket,
+                                                       const uint32_t *__restrict__ order)
 {
     __shared__ uint32_t s_a[BTILE];
     __shared__ uint32_t s_b[BTILE];
@@ -373,9 +408,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
     __syncthreads();
     const uint32_t ntiles = s_tbase[nb];
     for (;;) {
-        const uint32_t g = take_ticket(ticket, &s_tile);
-        if (g >= ntiles)
+        const uint32_t k = take_ticket(ticket, &s_tile);
+        if (k >= ntiles)
             break;
+        const uint32_t g = order[k]; // bucket-major index of the tile
         // bucket of this tile: largest b with tbase[b] <= g
         uint32_t lo = 0, hi = nb;
         while (hi - lo > 1) {
@@ -790,6 +826,7 @@ static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
     L.hist = (uint32_t *)take(HIST_COPIES * MAX_BUCKETS * 4);
     L.base = (uint64_t *)take((MAX_BUCKETS + 1) * 8);
     L.tbase = (uint32_t *)take((MAX_BUCKETS + 1) * 4);
+    L.order = (uint32_t *)take(btiles * 4);
     L.lbp = (uint64_t *)take(ptiles * nb * 8);
     L.lbv = (uint64_t *)take(btiles * LB_WORDS * 8);
     L.lbc = (uint64_t *)take(ptiles * 8);
@@ -834,6 +871,7 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     {
         ProfScope p(s, "bucket_bases");
         k_bucket_bases<<<1, 1024, 0, s>>>(L.hist, L.nb, L.base, L.tbase);
+        k_bucket_order<<<(unsigned)ceil_div(L.btiles_max, BLOCK), BLOCK, 0, s>>>(L.tbase, L.nb, L.order);
     }
     const uint32_t *part = src;
     uint8_t *res = direct_out;
@@ -856,10 +894,10 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
                                             btiles);
         if (mode == BK_PRE)
             k_bucket_scan<BK_PRE, SRC><<<grid, BLOCK, 0, s>>>(part, n_ids, L.nb, L.base, L.tbase, init, res,
-                                                              final_out, L.lbv, ctl->tickets[9]);
+                                                              final_out, L.lbv, ctl->tickets[9], L.order);
         else
             k_bucket_scan<BK_STATUS, SRC><<<grid, BLOCK, 0, s>>>(part, n_ids, L.nb, L.base, L.tbase, init, res,
-                                                                 final_out, L.lbv, ctl->tickets[9]);
+                                                                 final_out, L.lbv, ctl->tickets[9], L.order);
     }
 }
 
