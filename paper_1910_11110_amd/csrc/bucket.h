@@ -10,7 +10,8 @@ namespace vc {
 constexpr int LBITS = 12;                 // ids per bucket = 2^LBITS
 constexpr int LOC = 1 << LBITS;
 constexpr int MAX_BUCKETS = 1024;         // ids up to 2^22
-constexpr int HIST_COPIES = 8;            // global copies of the bucket histogram
+constexpr int HIST_SPLIT = 4;             // histogram workgroups per partition tile range
+constexpr int MAX_RANGES = 4096;          // rows of per-range bucket counts (histogram workgroups)
 constexpr int HCHUNK = 1024;              // declarations per arity chunk
 constexpr int P_ITEMS = 16;               // partition / replay: words per thread
 constexpr int PTILE = BLOCK * P_ITEMS;
@@ -26,7 +27,9 @@ struct BucketLayout {
     uint64_t *base = nullptr;
     uint32_t *tbase = nullptr;
     uint32_t *order = nullptr; // bucket tile (bucket-major index) taken by each ticket
-    uint64_t *lbp = nullptr, *lbv = nullptr, *lbc = nullptr;
+    uint32_t *gsum = nullptr, *gpre = nullptr; // per tile range: bucket counts, their column prefix
+    uint32_t *tpre = nullptr;                  // per partition tile: start of each bucket's run
+    uint64_t *lbv = nullptr, *lbc = nullptr;
     uint32_t *part = nullptr;
     uint8_t *res = nullptr;
     uint64_t ptiles = 0, btiles_max = 0;

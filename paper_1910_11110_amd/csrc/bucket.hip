@@ -118,6 +118,14 @@ __device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *s_
 // ----------------------------------------------------------------------------------
 // 0. histogram of buckets (+ validation)
 // ----------------------------------------------------------------------------------
+// tiles [lo, hi) of part `part` of `parts` equal parts (sizes differ by at most one) of
+// [0, ntiles)
+__host__ __device__ inline void split_range(uint64_t ntiles, uint64_t parts, uint64_t part, uint64_t &lo, uint64_t &hi)
+{
+    lo = part * ntiles / parts;
+    hi = (part + 1) * ntiles / parts;
+}
+
 template <class SRC>
 __device__ __forceinline__ void hist_word(uint32_t w, uint64_t i, bool in, uint32_t n_ids, uint32_t *s_h, Control *ctl)
 {
@@ -139,68 +147,97 @@ __device__ __forceinline__ void hist_word(uint32_t w, uint64_t i, bool in, uint3
     }
 }
 
-// Bucket histogram in LDS, flushed to one of HIST_COPIES global copies (spreads the hot
-// buckets' atomics).  With chunk_sum, the words are read in chunks of HCHUNK and each
-// chunk's total arity (SRC::arity) is stored as well.
+// Bucket histogram of a static range of tiles: workgroup r counts part r of nrows equal
+// parts of the tiles in LDS and stores its per-bucket counts as row r of gsum (a
+// partition range is HIST_SPLIT consecutive parts).  With chunk_sum, each chunk of
+// HCHUNK words also gets its total arity (SRC::arity).
 template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
-                                                       uint32_t *__restrict__ hist, Control *ctl,
+                                                       uint32_t nb, uint32_t nrows, uint64_t ntiles,
+                                                       uint32_t *__restrict__ gsum, Control *ctl,
                                                        uint32_t *__restrict__ chunk_sum)
 {
     __shared__ uint32_t s_h[MAX_BUCKETS];
-    __shared__ uint32_t s_ws[BLOCK / WAVE];
-    for (int i = threadIdx.x; i < MAX_BUCKETS; i += BLOCK)
+    __shared__ uint32_t s_ws[PTILE / HCHUNK][BLOCK / WAVE];
+    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    for (uint32_t i = threadIdx.x; i < nb; i += BLOCK)
         s_h[i] = 0;
     __syncthreads();
-    const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
-    if (!chunk_sum) {
-        // four loads in flight per thread, then the counts
-        for (uint64_t i0 = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i0 < n; i0 += 4 * stride) {
-            uint32_t w[4];
+    uint64_t t0, t1;
+    split_range(ntiles, nrows, blockIdx.x, t0, t1);
+    for (uint64_t t = t0; t < t1; t++) {
+        // the tile's words, 16 loads in flight per thread (chunk c = items u / 4)
+        uint32_t w[P_ITEMS];
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const uint64_t i = i0 + u * stride;
-                w[u] = i < n ? src[i] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const uint64_t i = i0 + u * stride;
-                hist_word<SRC>(w[u], i, i < n, n_ids, s_h, ctl);
-            }
+        for (int u = 0; u < P_ITEMS; u++) {
+            const uint64_t i = t * PTILE + (uint64_t)u * BLOCK + threadIdx.x;
+            w[u] = i < n ? src[i] : 0u;
         }
-    } else {
-        const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
-        const uint64_t nchunks = ceil_div(n, (uint64_t)HCHUNK);
-        for (uint64_t k = blockIdx.x; k < nchunks; k += gridDim.x) {
-            uint32_t w[HCHUNK / BLOCK];
+        uint32_t a[PTILE / HCHUNK] = {};
 #pragma unroll
-            for (int u = 0; u < HCHUNK / BLOCK; u++) {
-                const uint64_t i = k * HCHUNK + u * BLOCK + threadIdx.x;
-                w[u] = i < n ? src[i] : 0u;
+        for (int u = 0; u < P_ITEMS; u++) {
+            const uint64_t i = t * PTILE + (uint64_t)u * BLOCK + threadIdx.x;
+            hist_word<SRC>(w[u], i, i < n, n_ids, s_h, ctl);
+            a[u / (HCHUNK / BLOCK)] += i < n ? SRC::arity(w[u], n_ids) : 0u;
+        }
+        if (chunk_sum) {
+#pragma unroll
+            for (int c = 0; c < PTILE / HCHUNK; c++) {
+                uint32_t v = a[c];
+#pragma unroll
+                for (int d = 1; d < WAVE; d <<= 1)
+                    v += __shfl_xor(v, d);
+                if (lane == 0)
+                    s_ws[c][wave] = v;
             }
-            uint32_t a = 0;
-#pragma unroll
-            for (int u = 0; u < HCHUNK / BLOCK; u++) {
-                const uint64_t i = k * HCHUNK + u * BLOCK + threadIdx.x;
-                hist_word<SRC>(w[u], i, i < n, n_ids, s_h, ctl);
-                a += i < n ? SRC::arity(w[u], n_ids) : 0u;
-            }
-#pragma unroll
-            for (int d = 1; d < WAVE; d <<= 1)
-                a += __shfl_xor(a, d);
-            if (lane == 0)
-                s_ws[wave] = a;
             __syncthreads();
-            if (threadIdx.x == 0)
-                chunk_sum[k] = s_ws[0] + s_ws[1] + s_ws[2] + s_ws[3];
+            if (threadIdx.x < PTILE / HCHUNK) {
+                const uint64_t ch = t * (PTILE / HCHUNK) + threadIdx.x;
+                if (ch * HCHUNK < n)
+                    chunk_sum[ch] = s_ws[threadIdx.x][0] + s_ws[threadIdx.x][1] + s_ws[threadIdx.x][2] +
+                                    s_ws[threadIdx.x][3];
+            }
             __syncthreads();
         }
     }
     __syncthreads();
-    uint32_t *h = hist + (blockIdx.x % HIST_COPIES) * MAX_BUCKETS;
-    for (int i = threadIdx.x; i < MAX_BUCKETS; i += BLOCK)
-        if (s_h[i])
-            atomicAdd(&h[i], s_h[i]);
+    for (uint32_t i = threadIdx.x; i < nb; i += BLOCK)
+        gsum[(uint64_t)blockIdx.x * nb + i] = s_h[i];
+}
+
+// Column scan of the per-range bucket counts: gpre[j][b] = counts of bucket b in rows
+// before j; tot[b] = all of bucket b.  One wave per bucket, each lane a run of rows
+// (at most 32), a wave scan over the lanes' sums.
+constexpr int COLSCAN_ROWS = MAX_RANGES / WAVE; // rows per lane
+__global__ __launch_bounds__(BLOCK) void k_bucket_colscan(const uint32_t *__restrict__ gsum, uint32_t nb,
+                                                          uint32_t nrows, uint32_t *__restrict__ gpre,
+                                                          uint32_t *__restrict__ tot)
+{
+    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    const uint32_t b = blockIdx.x * (BLOCK / WAVE) + wave;
+    if (b >= nb)
+        return;
+    const uint32_t per = (nrows + WAVE - 1) / WAVE;
+    const uint32_t r0 = lane * per;
+    uint32_t v[COLSCAN_ROWS];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < COLSCAN_ROWS; k++) {
+        const uint32_t j = r0 + k;
+        v[k] = (k < (int)per && j < nrows) ? gsum[(uint64_t)j * nb + b] : 0u;
+        sum += v[k];
+    }
+    const uint32_t inc = wave_scan_add(sum, lane);
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int k = 0; k < COLSCAN_ROWS; k++) {
+        const uint32_t j = r0 + k;
+        if (k < (int)per && j < nrows)
+            gpre[(uint64_t)j * nb + b] = run;
+        run += v[k];
+    }
+    if (lane == WAVE - 1)
+        tot[b] = inc;
 }
 
 // bucket bases (exclusive scan of the histogram) and first tile of every bucket
@@ -210,10 +247,7 @@ __global__ __launch_bounds__(1024) void k_bucket_bases(const uint32_t *__restric
     __shared__ uint64_t s_a[1024];
     __shared__ uint32_t s_t[1024];
     uint32_t i = threadIdx.x;
-    uint64_t c = 0;
-    if (i < nb)
-        for (int k = 0; k < HIST_COPIES; k++)
-            c += hist[k * MAX_BUCKETS + i];
+    uint64_t c = i < nb ? hist[i] : 0;
     s_a[i] = c;
     s_t[i] = (uint32_t)ceil_div(c, BTILE);
     __syncthreads();
@@ -272,25 +306,33 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restri
 // ----------------------------------------------------------------------------------
 // 1. partition by bucket
 // ----------------------------------------------------------------------------------
+// Workgroup j partitions the tiles of histogram parts [j * HIST_SPLIT, (j + 1) *
+// HIST_SPLIT) in order, keeping the running
+// global start of every bucket in LDS (from the column scan): no look-back, no tickets.
+// The start of each bucket's run in every tile is stored as row `tile` of tpre for the
+// replay.
 template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
                                                      int bits, const uint64_t *__restrict__ base,
-                                                     uint32_t *__restrict__ dst, uint64_t *__restrict__ lb,
-                                                     uint32_t *__restrict__ ticket, uint64_t ntiles)
+                                                     const uint32_t *__restrict__ gpre, uint32_t nranges,
+                                                     uint32_t *__restrict__ dst, uint32_t *__restrict__ tpre,
+                                                     uint64_t ntiles)
 {
     __shared__ uint32_t s_words[PTILE];
     __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
     __shared__ uint32_t s_dstart[MAX_BUCKETS];
+    __shared__ uint32_t s_run[MAX_BUCKETS];
     __shared__ int64_t s_gbase[MAX_BUCKETS];
     __shared__ uint32_t s_tmp[BLOCK / WAVE];
-    __shared__ uint32_t s_tile;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t nb = 1u << bits;
-    for (;;) {
-        const uint32_t tile = take_ticket(ticket, &s_tile);
-        if (tile >= ntiles)
-            break;
-        const uint64_t tbase = (uint64_t)tile * PTILE;
+    for (uint32_t b = tid; b < nb; b += BLOCK)
+        s_run[b] = (uint32_t)base[b] + gpre[(uint64_t)blockIdx.x * HIST_SPLIT * nb + b];
+    uint64_t t0, t1;
+    split_range(ntiles, (uint64_t)nranges * HIST_SPLIT, (uint64_t)blockIdx.x * HIST_SPLIT, t0, t1);
+    t1 = ((uint64_t)blockIdx.x + 1) * HIST_SPLIT * ntiles / ((uint64_t)nranges * HIST_SPLIT);
+    for (uint64_t tile = t0; tile < t1; tile++) {
+        const uint64_t tbase = tile * PTILE;
         // per-wave counters live at [wave * MAX_BUCKETS + bucket]
         for (uint32_t i = tid; i < 4 * nb; i += BLOCK)
             s_cnt[(i / nb) * MAX_BUCKETS + (i % nb)] = 0;
@@ -307,8 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
         }
         rank_digits<P_ITEMS, MAX_BUCKETS>(d, valid, bits, rank, s_cnt, wave);
         __syncthreads();
-        // per bucket: wave offsets, tile count, publication
-        uint64_t *my = lb + (uint64_t)tile * nb;
+        // per bucket: wave offsets and the tile's count
         for (uint32_t b = tid; b < nb; b += BLOCK) {
             uint32_t tc = 0;
             for (uint32_t q = 0; q < 4; q++) {
@@ -317,10 +358,10 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
                 tc += c;
             }
             s_dstart[b] = tc; // tile count, turned into starts below
-            lb_store(&my[b], (tile == 0 ? LB_INC : LB_AGG) | tc);
         }
         __syncthreads();
-        // exclusive scan of the tile counts over buckets (nb <= 1024, 4 per thread)
+        // exclusive scan of the tile counts over buckets (nb <= 1024, 4 per thread); the
+        // tile's runs start at s_run (stored for the replay), which then advances
         {
             uint32_t v[4], sum = 0;
 #pragma unroll
@@ -333,8 +374,13 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 uint32_t b = tid * 4 + k;
-                if (b < nb)
+                if (b < nb) {
                     s_dstart[b] = ex;
+                    const uint32_t r = s_run[b];
+                    tpre[tile * nb + b] = r;
+                    s_gbase[b] = (int64_t)r - (int64_t)ex;
+                    s_run[b] = r + v[k];
+                }
                 ex += v[k];
             }
         }
@@ -344,16 +390,6 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
             uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
             if (((valid >> j) & 1u) && li < PTILE)
                 s_words[li] = w[j];
-        }
-        // look-back per bucket
-        for (uint32_t b = tid; b < nb; b += BLOCK) {
-            uint64_t excl = 0;
-            uint32_t tc = (uint32_t)(__hip_atomic_load(&my[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & LB_VAL);
-            if (tile > 0) {
-                excl = lb_column_sum<8>(lb + b, nb, 0, (int64_t)tile - 1);
-                lb_store(&my[b], LB_INC | (excl + tc));
-            }
-            s_gbase[b] = (int64_t)base[b] + (int64_t)excl - (int64_t)s_dstart[b];
         }
         __syncthreads();
         uint64_t vn = n - tbase < (uint64_t)PTILE ? n - tbase : (uint64_t)PTILE;
@@ -673,7 +709,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 // ----------------------------------------------------------------------------------
 template <class SRC>
 __device__ __forceinline__ void replay_tile(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids, int bits,
-                                            const uint64_t *__restrict__ base, const uint64_t *__restrict__ lbp,
+                                            const uint32_t *__restrict__ tpre,
                                             const uint8_t *__restrict__ res, uint32_t tile, uint8_t *s_res,
                                             uint32_t *s_cnt, uint32_t *s_tmp, int64_t *s_off, uint32_t *s_w)
 {
@@ -703,8 +739,8 @@ __device__ __forceinline__ void replay_tile(const uint32_t *__restrict__ src, ui
             s_cnt[q * MAX_BUCKETS + b] = tc;
             tc += c;
         }
-        uint64_t inc = lbp[(uint64_t)tile * nb + b] & LB_VAL;
-        s_off[b] = (int64_t)base[b] + (int64_t)inc - (int64_t)tc;
+        (void)tc;
+        s_off[b] = (int64_t)tpre[(uint64_t)tile * nb + b];
     }
     __syncthreads();
 #pragma unroll
@@ -722,8 +758,7 @@ __device__ __forceinline__ void replay_tile(const uint32_t *__restrict__ src, ui
 }
 
 __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restrict__ src, uint64_t n,
-                                                         uint32_t n_ids, int bits, const uint64_t *__restrict__ base,
-                                                         const uint64_t *__restrict__ lbp,
+                                                         uint32_t n_ids, int bits, const uint32_t *__restrict__ tpre,
                                                          const uint8_t *__restrict__ res, uint8_t *__restrict__ status,
                                                          uint32_t *__restrict__ viol, uint64_t *__restrict__ lbc,
                                                          uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
@@ -739,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restr
         const uint32_t tile = take_ticket(ticket, &s_tile);
         if (tile >= ntiles)
             break;
-        replay_tile<EventWords>(src, n, n_ids, bits, base, lbp, res, tile, s_res, s_cnt, nullptr, s_off, nullptr);
+        replay_tile<EventWords>(src, n, n_ids, bits, tpre, res, tile, s_res, s_cnt, nullptr, s_off, nullptr);
         const uint64_t tbase = (uint64_t)tile * PTILE;
         const uint64_t my0 = tbase + (uint64_t)tid * 16;
         // 16 consecutive status bytes per thread
@@ -823,11 +858,13 @@ static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
     };
     L.bits = bits;
     L.nb = (uint32_t)nb;
-    L.hist = (uint32_t *)take(HIST_COPIES * MAX_BUCKETS * 4);
+    L.hist = (uint32_t *)take(MAX_BUCKETS * 4);
+    L.gsum = (uint32_t *)take((size_t)MAX_RANGES * nb * 4);
+    L.gpre = (uint32_t *)take((size_t)MAX_RANGES * nb * 4);
     L.base = (uint64_t *)take((MAX_BUCKETS + 1) * 8);
     L.tbase = (uint32_t *)take((MAX_BUCKETS + 1) * 4);
     L.order = (uint32_t *)take(btiles * 4);
-    L.lbp = (uint64_t *)take(ptiles * nb * 8);
+    L.tpre = (uint32_t *)take(ptiles * nb * 4);
     L.lbv = (uint64_t *)take(btiles * LB_WORDS * 8);
     L.lbc = (uint64_t *)take(ptiles * 8);
     L.part = (uint32_t *)take((n ? n : 1) * 4);
@@ -860,27 +897,38 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
                                uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
                                hipStream_t s, int cu, uint32_t *chunk_sum = nullptr)
 {
-    launch_fill_u32(L.hist, 0, HIST_COPIES * MAX_BUCKETS, s);
     launch_fill_u64(L.lbv, 0, L.btiles_max * LB_WORDS, s);
-    launch_fill_u32(ctl->tickets[8], 0, 2 * TICKET_WORDS, s);
+    launch_fill_u32(ctl->tickets[9], 0, TICKET_WORDS, s);
+    // static tile ranges shared by the histogram and the partition: as many ranges as
+    // partition workgroups are resident at once
+    // (the histogram splits every range in HIST_SPLIT, for more workgroups in flight)
+    uint32_t gres = resident_grid((const void *)k_partition<SRC>, L.ptiles);
+    gres = gres < (uint32_t)(MAX_RANGES / HIST_SPLIT) ? gres : (uint32_t)(MAX_RANGES / HIST_SPLIT);
+    const uint32_t nranges = (uint32_t)(L.ptiles < gres ? L.ptiles : gres);
+    const uint32_t nrows = nranges * HIST_SPLIT;
     {
         ProfScope p(s, "bucket_hist");
-        const uint64_t hg = ceil_div(n ? n : 1, (uint64_t)BLOCK * 16);
-        k_bucket_hist<SRC><<<(unsigned)(hg < 2048 ? hg : 2048), BLOCK, 0, s>>>(src, n, n_ids, L.hist, ctl, chunk_sum);
+        k_bucket_hist<SRC><<<nrows, BLOCK, 0, s>>>(src, n, n_ids, L.nb, nrows, L.ptiles, L.gsum, ctl, chunk_sum);
+    }
+    {
+        ProfScope p(s, "bucket_colscan");
+        k_bucket_colscan<<<(unsigned)ceil_div(L.nb, BLOCK / WAVE), BLOCK, 0, s>>>(L.gsum, L.nb, nrows, L.gpre,
+                                                                                 L.hist);
     }
     {
         ProfScope p(s, "bucket_bases");
         k_bucket_bases<<<1, 1024, 0, s>>>(L.hist, L.nb, L.base, L.tbase);
+    }
+    {
+        ProfScope p(s, "bucket_order");
         k_bucket_order<<<(unsigned)ceil_div(L.btiles_max, BLOCK), BLOCK, 0, s>>>(L.tbase, L.nb, L.order);
     }
     const uint32_t *part = src;
     uint8_t *res = direct_out;
     if (L.nb > 1) {
-        launch_fill_u64(L.lbp, 0, L.ptiles * L.nb, s);
         ProfScope p(s, "partition");
-        const unsigned grid = resident_grid((const void *)k_partition<SRC>, L.ptiles);
-        k_partition<SRC><<<grid, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.part, L.lbp, ctl->tickets[8],
-                                                L.ptiles);
+        k_partition<SRC><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, L.part, L.tpre,
+                                                   L.ptiles);
         part = L.part;
         res = L.res;
     }
@@ -916,13 +964,12 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     launch_fill_u32(ctl->tickets[10], 0, TICKET_WORDS, s);
     ProfScope p(s, "replay_status");
     const unsigned grid = resident_grid((const void *)k_replay_status, L.ptiles);
-    k_replay_status<<<grid, BLOCK, 0, s>>>(events, n, n_ids, L.bits, L.base, L.lbp, L.res, status, viol, L.lbc,
+    k_replay_status<<<grid, BLOCK, 0, s>>>(events, n, n_ids, L.bits, L.tpre, L.res, status, viol, L.lbc,
                                            ctl->tickets[10], L.ptiles, ctl);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_replay_bytes(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
-                                                        int bits, const uint64_t *__restrict__ base,
-                                                        const uint64_t *__restrict__ lbp,
+                                                        int bits, const uint32_t *__restrict__ tpre,
                                                         const uint8_t *__restrict__ res, uint8_t *__restrict__ out,
                                                         uint64_t ntiles)
 {
@@ -933,7 +980,7 @@ __global__ __launch_bounds__(BLOCK) void k_replay_bytes(const uint32_t *__restri
     const uint32_t tid = threadIdx.x;
     // tiles are independent (no look-back): a plain grid-stride loop
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        replay_tile<DeclWords>(src, n, n_ids, bits, base, lbp, res, tile, s_res, s_cnt, s_tmp, s_off, nullptr);
+        replay_tile<DeclWords>(src, n, n_ids, bits, tpre, res, tile, s_res, s_cnt, s_tmp, s_off, nullptr);
         const uint64_t my0 = (uint64_t)tile * PTILE + (uint64_t)tid * 16;
         if (my0 + 16 <= n) {
             *reinterpret_cast<uint4 *>(out + my0) = *reinterpret_cast<const uint4 *>(s_res + tid * 16);
@@ -957,7 +1004,7 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
         return;
     ProfScope p(s, "replay_bytes");
     const unsigned grid = resident_grid((const void *)k_replay_bytes, L.ptiles);
-    k_replay_bytes<<<grid, BLOCK, 0, s>>>(decls, n_decl, n_vars, L.bits, L.base, L.lbp, L.res, pre, L.ptiles);
+    k_replay_bytes<<<grid, BLOCK, 0, s>>>(decls, n_decl, n_vars, L.bits, L.tpre, L.res, pre, L.ptiles);
 }
 
 } // namespace vc
