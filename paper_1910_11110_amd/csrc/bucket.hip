@@ -158,46 +158,47 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restric
                                                        uint32_t *__restrict__ chunk_sum)
 {
     __shared__ uint32_t s_h[MAX_BUCKETS];
-    __shared__ uint32_t s_ws[PTILE / HCHUNK][BLOCK / WAVE];
-    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    static_assert(HCHUNK % P_ITEMS == 0 && HCHUNK / P_ITEMS <= WAVE, "a chunk is whole lanes of one wave");
+    const uint32_t lane = lane_id();
     for (uint32_t i = threadIdx.x; i < nb; i += BLOCK)
         s_h[i] = 0;
     __syncthreads();
     uint64_t t0, t1;
     split_range(ntiles, nrows, blockIdx.x, t0, t1);
+    const bool vec = (reinterpret_cast<uintptr_t>(src) & 15u) == 0;
     for (uint64_t t = t0; t < t1; t++) {
-        // the tile's words, 16 loads in flight per thread (chunk c = items u / 4)
+        // 16 consecutive words per thread (four 16-byte loads when aligned); a chunk of
+        // HCHUNK words is HCHUNK / 16 consecutive lanes
+        const uint64_t i0 = t * PTILE + (uint64_t)threadIdx.x * P_ITEMS;
         uint32_t w[P_ITEMS];
+        if (vec && i0 + P_ITEMS <= n) {
 #pragma unroll
-        for (int u = 0; u < P_ITEMS; u++) {
-            const uint64_t i = t * PTILE + (uint64_t)u * BLOCK + threadIdx.x;
-            w[u] = i < n ? src[i] : 0u;
+            for (int q = 0; q < P_ITEMS / 4; q++) {
+                const uint4 v = reinterpret_cast<const uint4 *>(src + i0)[q];
+                w[4 * q] = v.x;
+                w[4 * q + 1] = v.y;
+                w[4 * q + 2] = v.z;
+                w[4 * q + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < P_ITEMS; u++)
+                w[u] = i0 + u < n ? src[i0 + u] : 0u;
         }
-        uint32_t a[PTILE / HCHUNK] = {};
+        uint32_t a = 0;
 #pragma unroll
         for (int u = 0; u < P_ITEMS; u++) {
-            const uint64_t i = t * PTILE + (uint64_t)u * BLOCK + threadIdx.x;
-            hist_word<SRC>(w[u], i, i < n, n_ids, s_h, ctl);
-            a[u / (HCHUNK / BLOCK)] += i < n ? SRC::arity(w[u], n_ids) : 0u;
+            hist_word<SRC>(w[u], i0 + u, i0 + u < n, n_ids, s_h, ctl);
+            a += i0 + u < n ? SRC::arity(w[u], n_ids) : 0u;
         }
         if (chunk_sum) {
+            constexpr int LANES = HCHUNK / P_ITEMS;
 #pragma unroll
-            for (int c = 0; c < PTILE / HCHUNK; c++) {
-                uint32_t v = a[c];
-#pragma unroll
-                for (int d = 1; d < WAVE; d <<= 1)
-                    v += __shfl_xor(v, d);
-                if (lane == 0)
-                    s_ws[c][wave] = v;
-            }
-            __syncthreads();
-            if (threadIdx.x < PTILE / HCHUNK) {
-                const uint64_t ch = t * (PTILE / HCHUNK) + threadIdx.x;
-                if (ch * HCHUNK < n)
-                    chunk_sum[ch] = s_ws[threadIdx.x][0] + s_ws[threadIdx.x][1] + s_ws[threadIdx.x][2] +
-                                    s_ws[threadIdx.x][3];
-            }
-            __syncthreads();
+            for (int d = 1; d < LANES; d <<= 1)
+                a += __shfl_xor(a, d);
+            const uint64_t ch = i0 / HCHUNK;
+            if ((lane & (LANES - 1)) == 0 && ch * HCHUNK < n)
+                chunk_sum[ch] = a;
         }
     }
     __syncthreads();

@@ -162,9 +162,6 @@ __global__ void k_translate_emit(const uint64_t *__restrict__ comp_off, uint64_t
 // applies to v#, so the two agree at every declaration from the common initial
 // (V,I)).  One workgroup writes 256 consecutive components.
 constexpr EffectTable TABLE = make_table();
-#ifndef VC_FUSED_WAVES
-#define VC_FUSED_WAVES 5
-#endif
 #ifndef VC_FUSED_COMPS
 #define VC_FUSED_COMPS 128
 #endif
@@ -583,146 +580,202 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
     add_flagged(nflag, n_flagged);
 }
 
-// what is loaded ahead, besides the tile's declarations, when the positions come from
-// per-chunk event counts: the prefix of the counts at the chunk holding the tile's first
-// declaration, and (per thread) the events of the declarations between that chunk's
-// start and the tile's first declaration
-struct ChunkPrefetch {
-    uint64_t cbase;
-    uint32_t part;
+// Positions found on the device, one wave per tile of WCOMPS components (no workgroup
+// barriers: every wave runs its tiles on its own).  The events before a tile are the
+// prefix of the per-chunk event counts (HCHUNK declarations a chunk, counted by the
+// histogram pass) at the chunk of the tile's first declaration plus the events of that
+// chunk's declarations before it; inside the tile, wave scans over the declarations and
+// the components.  The tile's events are staged in the wave's LDS and written out
+// contiguously; a tile whose declarations or events do not fit, or whose offsets are
+// malformed (reported with the component's index), is written in place, one component
+// per lane.
+constexpr int WCOMPS = 32;  // components per wave tile
+constexpr int WDCAP = 256;  // declarations staged per wave tile
+constexpr int WECAP = 768;  // events staged per wave tile
+
+struct WaveTile {
+    uint64_t coff[WCOMPS + 1];
+    uint32_t pos[WCOMPS + 1]; // events before each component, relative to the tile
+    uint32_t decl[WDCAP];
+    uint32_t scan[WDCAP + 1]; // exclusive prefix of (slot arity | body arity << 16)
+    uint32_t ev[WECAP];
+    uint8_t pre[WDCAP];
+    uint8_t st[WECAP];
 };
 
-__device__ __forceinline__ void fused_load_chunk(ChunkPrefetch &c, const FusedPrefetch &f, const uint32_t *decls,
-                                                 const uint64_t *chunk_prefix, uint64_t n_decl, uint32_t n_vars)
+__device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
 {
-    c.cbase = 0;
-    c.part = 0;
-    if (f.lo > n_decl)
-        return;
-    const uint64_t first = f.lo - f.lo % HCHUNK;
-    c.cbase = chunk_prefix[f.lo / HCHUNK];
-    const uint32_t np = (uint32_t)(f.lo - first);
-#pragma unroll
-    for (int k = 0; k < HCHUNK / BLOCK; k++) {
-        const uint32_t i = threadIdx.x + k * BLOCK;
-        if (i < np) {
-            const uint32_t wd = decls[first + i];
-            const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-            c.part += slot_arity(mode) + body_arity(mode);
-        }
-    }
+    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+    return slot_arity(mode) + body_arity(mode);
 }
 
-// Positions found on the device: the events before a tile are the prefix of the
-// per-chunk event counts (HCHUNK declarations a chunk, counted by the histogram pass)
-// at the chunk of the tile's first declaration plus the events of the declarations of
-// that chunk before it; inside the tile, a block scan.  Persistent and prefetching like
-// k_translate_emit_fused.  Malformed component offsets are reported with the
-// component's index (as the per-component count does on the other path).
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(VC_FUSED_WAVES))) void k_translate_emit_fused_dev(
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1)
+        v += __shfl_xor(v, d);
+    return v;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
     uint32_t n_vars, const uint8_t *__restrict__ pre_abs, const uint64_t *__restrict__ chunk_prefix,
     uint32_t *__restrict__ out, uint8_t *__restrict__ status, uint64_t ntiles, Control *ctl,
     unsigned long long *__restrict__ n_flagged, uint64_t cap)
 {
-    __shared__ uint32_t s_ev[FUSED_CAP];
-    __shared__ uint8_t s_st[FUSED_CAP];
-    __shared__ __align__(16) uint32_t s_decl[FUSED_DCAP];
-    __shared__ uint32_t s_scan[FUSED_DCAP + 1];
-    __shared__ __align__(16) uint8_t s_pre[FUSED_DCAP];
-    __shared__ uint64_t s_coff[FUSED_COMPS + 1], s_pos[FUSED_COMPS + 1];
-    __shared__ uint32_t s_wsum[BLOCK / WAVE], s_psum[BLOCK / WAVE];
-
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    __shared__ WaveTile s_tiles[BLOCK / WAVE];
+    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    WaveTile &L = s_tiles[wave];
     uint32_t nflag = 0;
-    uint64_t tile = blockIdx.x;
-    FusedPrefetch cur, nxt;
-    ChunkPrefetch ccur, cnxt;
-    if (tile < ntiles) {
-        fused_load_offsets(cur, comp_off, nullptr, n_comp, tile);
-        fused_load_decls(cur, decls, pre_abs, n_decl);
-        fused_load_chunk(ccur, cur, decls, chunk_prefix, n_decl, n_vars);
-    }
-    for (; tile < ntiles; tile += gridDim.x) {
-        const uint64_t tnext = tile + gridDim.x;
-        if (tnext < ntiles)
-            fused_load_offsets(nxt, comp_off, nullptr, n_comp, tnext);
-        const uint64_t c0 = tile * FUSED_COMPS;
-        const uint32_t nc = tile_comps(n_comp, tile);
-        const bool fits = decls_fit(cur, n_decl);
-        const uint32_t nd = fits ? (uint32_t)(cur.hi - cur.lo) : 0u;
-        stage_tile(cur, nc, nd, false, s_coff, s_pos, s_decl, s_pre);
-        __syncthreads();
+    const uint64_t nw = (uint64_t)gridDim.x * (BLOCK / WAVE);
+    for (uint64_t wt = (uint64_t)blockIdx.x * (BLOCK / WAVE) + wave; wt < ntiles; wt += nw) {
+        const uint64_t c0 = wt * WCOMPS;
+        const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)WCOMPS ? n_comp - c0 : (uint64_t)WCOMPS);
+        if (lane <= nc)
+            L.coff[lane] = comp_off[c0 + lane];
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t d_lo = L.coff[0], d_hi = L.coff[nc];
         // malformed offsets: reported; such a component has no events
-        bool bad = !fits;
-        for (uint32_t i = tid; i < nc; i += BLOCK) {
-            const uint64_t a = s_coff[i], b = s_coff[i + 1];
-            if (b < a || b > n_decl || (c0 + i == 0 && a != 0)) {
+        uint64_t a = 0, b = 0;
+        bool bad = false;
+        if (lane < nc) {
+            a = L.coff[lane];
+            b = L.coff[lane + 1];
+            if (b < a || b > n_decl || (c0 + lane == 0 && a != 0)) {
                 bad = true;
-                report_bad(ctl, c0 + i);
+                report_bad(ctl, c0 + lane);
             }
         }
-        const bool staged_scan = !__syncthreads_or(bad);
-        if (staged_scan)
-            scan_arities(nd, n_vars, s_decl, s_scan, s_wsum);
-        __syncthreads();
-        // events per component, exclusive block scan; the tile's base
-        uint32_t cnt = 0;
-        if (tid < nc) {
-            const uint64_t a = s_coff[tid], b = s_coff[tid + 1];
-            if (staged_scan) {
-                const uint32_t x = s_scan[b - s_coff[0]], y = s_scan[a - s_coff[0]];
-                cnt = ((x & 0xFFFFu) + (x >> 16)) - ((y & 0xFFFFu) + (y >> 16));
-            } else if (b >= a && b <= n_decl && !(c0 + tid == 0 && a != 0)) {
-                for (uint64_t d = a; d < b; d++) {
-                    const uint32_t wd = decls[d];
-                    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-                    cnt += slot_arity(mode) + body_arity(mode);
+        const bool any_bad = __ballot(bad) != 0;
+        const bool fits = !any_bad && d_hi - d_lo <= (uint64_t)WDCAP;
+        const uint32_t nd = fits ? (uint32_t)(d_hi - d_lo) : 0u;
+        // events before the tile: the chunk prefix plus the chunk's declarations before d_lo;
+        // and the tile's declarations (loads issued together)
+        uint64_t base = 0;
+        if (d_lo <= n_decl) {
+            const uint64_t first = d_lo - d_lo % HCHUNK;
+            uint32_t part = 0;
+            uint32_t pw[HCHUNK / WAVE], dw[WDCAP / WAVE], pr[WDCAP / WAVE];
+#pragma unroll
+            for (int k = 0; k < HCHUNK / WAVE; k++) {
+                const uint64_t i = first + k * WAVE + lane;
+                pw[k] = i < d_lo ? decls[i] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < WDCAP / WAVE; k++) {
+                const uint32_t i = k * WAVE + lane;
+                dw[k] = i < nd ? decls[d_lo + i] : 0u;
+                pr[k] = i < nd ? pre_abs[d_lo + i] : 0u;
+            }
+            const uint64_t cb = chunk_prefix[d_lo / HCHUNK];
+#pragma unroll
+            for (int k = 0; k < HCHUNK / WAVE; k++)
+                part += first + k * WAVE + lane < d_lo ? decl_arity(pw[k], n_vars) : 0u;
+            base = cb + wave_sum_u32(part);
+#pragma unroll
+            for (int k = 0; k < WDCAP / WAVE; k++) {
+                const uint32_t i = k * WAVE + lane;
+                if (i < nd) {
+                    L.decl[i] = dw[k];
+                    L.pre[i] = (uint8_t)pr[k];
                 }
             }
         }
-        const uint32_t inc = wave_scan_add(cnt, lane);
-        uint32_t part = ccur.part;
+        __builtin_amdgcn_wave_barrier();
+        // events per component (lane = component)
+        uint32_t cnt = 0;
+        if (fits) {
+            uint32_t carry = 0;
 #pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1)
-            part += __shfl_xor(part, d);
-        if (lane == WAVE - 1) {
-            s_wsum[wave] = inc;
-            s_psum[wave] = part;
+            for (int k = 0; k < WDCAP / WAVE; k++) {
+                const uint32_t i = k * WAVE + lane;
+                uint32_t m = 0;
+                if (i < nd) {
+                    const uint32_t wd = L.decl[i];
+                    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                    m = slot_arity(mode) | (body_arity(mode) << 16);
+                }
+                const uint32_t inc = wave_scan_add(m, lane);
+                if (i < nd)
+                    L.scan[i] = carry + inc - m;
+                carry += __shfl(inc, WAVE - 1);
+            }
+            if (lane == 0)
+                L.scan[nd] = carry;
+            __builtin_amdgcn_wave_barrier();
+            if (lane < nc) {
+                const uint32_t x = L.scan[b - d_lo], y = L.scan[a - d_lo];
+                cnt = ((x & 0xFFFFu) + (x >> 16)) - ((y & 0xFFFFu) + (y >> 16));
+            }
+        } else if (lane < nc && !bad) {
+            for (uint64_t d = a; d < b; d++)
+                cnt += decl_arity(decls[d], n_vars);
         }
-        __syncthreads();
-        uint32_t ex = inc - cnt, total = 0;
-        uint64_t base = ccur.cbase;
-        for (uint32_t w = 0; w < BLOCK / WAVE; w++) {
-            if (w < wave)
-                ex += s_wsum[w];
-            total += s_wsum[w];
-            base += s_psum[w];
+        const uint32_t incc = wave_scan_add(cnt, lane);
+        const uint32_t excl = incc - cnt, total = __shfl(incc, WAVE - 1);
+        const bool staged = fits && total <= (uint32_t)WECAP && base + total <= cap;
+        if (staged) {
+            if (lane <= nc)
+                L.pos[lane] = excl;
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < WDCAP / WAVE; k++) {
+                const uint32_t i = k * WAVE + lane;
+                if (i < nd) {
+                    uint32_t lo = 0, hi = nc; // largest j with coff[j] - d_lo <= i
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (L.coff[mid] - d_lo <= i)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    const uint32_t cs = (uint32_t)(L.coff[lo] - d_lo), ce = (uint32_t)(L.coff[lo + 1] - d_lo);
+                    const uint32_t base_c = L.scan[cs];
+                    const uint32_t pre = L.scan[i] - base_c, tot = L.scan[ce] - base_c;
+                    const uint32_t pe = L.pos[lo];
+                    emit_decl_lds(L.decl[i], n_vars, L.pre[i], pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16),
+                                  L.pos[lo + 1], L.ev, L.st, nflag);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t i = lane; i < total; i += WAVE)
+                out[base + i] = L.ev[i];
+            const uint32_t h0 = (uint32_t)((4u - (base & 3u)) & 3u);
+            const uint32_t head = h0 < total ? h0 : total;
+            const uint32_t nwords = (total - head) / 4;
+            if (lane < head)
+                status[base + lane] = L.st[lane];
+            uint32_t *sw = reinterpret_cast<uint32_t *>(status + base + head);
+            for (uint32_t k = lane; k < nwords; k += WAVE) {
+                const uint32_t q = head + 4 * k;
+                sw[k] = (uint32_t)L.st[q] | ((uint32_t)L.st[q + 1] << 8) | ((uint32_t)L.st[q + 2] << 16) |
+                        ((uint32_t)L.st[q + 3] << 24);
+            }
+            const uint32_t tail0 = head + 4 * nwords;
+            if (lane < total - tail0)
+                status[base + tail0 + lane] = L.st[tail0 + lane];
+        } else if (lane < nc && !bad) {
+            // in place, one component per lane; positions clamp to the output's capacity
+            // (only malformed offsets, reported, can make the events outnumber 5 per
+            // declaration)
+            const uint64_t p0 = base + excl < cap ? base + excl : cap;
+            const uint64_t end = base + excl + cnt < cap ? base + excl + cnt : cap;
+            uint64_t slot = p0;
+            for (uint64_t d = a; d < b; d++) {
+                const uint32_t wd = decls[d];
+                slot += slot_arity(decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u);
+            }
+            uint64_t sp = p0, bp = slot;
+            for (uint64_t d = a; d < b; d++) {
+                const uint32_t wd = decls[d];
+                const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, nflag);
+                sp += slot_arity(mode);
+                bp += body_arity(mode);
+            }
         }
-        // positions clamp to the output's capacity: only malformed offsets (reported)
-        // can make the events outnumber 5 per declaration
-        const uint64_t ebase = base < cap ? base : cap;
-        if (tid < nc)
-            s_pos[tid] = base + ex < cap ? base + ex : cap;
-        if (tid == 0)
-            s_pos[nc] = base + total < cap ? base + total : cap;
-        __syncthreads();
-        const bool staged = staged_scan && s_pos[nc] - ebase <= (uint64_t)FUSED_CAP;
-        if (staged)
-            emit_staged(nd, nc, s_coff[0], ebase, n_vars, s_coff, s_pos, s_scan, s_decl, s_pre, s_ev, s_st, nflag);
-        else
-            emit_in_place(nc, n_vars, n_decl, s_coff, s_pos, decls, pre_abs, out, status, nflag);
-        // the next tile's declarations are requested before this tile's output is written
-        if (tnext < ntiles) {
-            fused_load_decls(nxt, decls, pre_abs, n_decl);
-            fused_load_chunk(cnxt, nxt, decls, chunk_prefix, n_decl, n_vars);
-        }
-        __syncthreads();
-        if (staged)
-            write_staged((uint32_t)(s_pos[nc] - ebase), ebase, s_ev, s_st, out, status);
-        cur = nxt;
-        ccur = cnxt;
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
     }
     add_flagged(nflag, n_flagged);
 }
@@ -753,11 +806,11 @@ void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, 
 {
     if (!n_comp)
         return;
-    const uint64_t tiles = ceil_div(n_comp, FUSED_COMPS);
-    ProfScope prof_(s, "translate_emit_fused_dev");
-    k_translate_emit_fused_dev<<<resident_grid((const void *)k_translate_emit_fused_dev, tiles), BLOCK, 0, s>>>(
-        comp_off, n_comp, decls, n_decl, n_vars, pre_abs, chunk_prefix, out, status, tiles, tr_ctl, &ctl->n_flagged,
-        5 * n_decl);
+    const uint64_t tiles = ceil_div(n_comp, WCOMPS);
+    ProfScope prof_(s, "translate_emit_wave");
+    k_translate_emit_wave<<<resident_grid((const void *)k_translate_emit_wave, ceil_div(tiles, BLOCK / WAVE)), BLOCK, 0,
+                            s>>>(comp_off, n_comp, decls, n_decl, n_vars, pre_abs, chunk_prefix, out, status, tiles,
+                                 tr_ctl, &ctl->n_flagged, 5 * n_decl);
 }
 
 void launch_make_items_decls(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint64_t *items, Control *ctl,
