@@ -82,12 +82,18 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
         bool valid = (validmask >> j) & 1u;
-        uint64_t m = __ballot(valid);
+        const uint64_t vm = __ballot(valid);
+        // lanes whose digit equals this lane's: per bit, the ballot or its complement,
+        // chosen per lane (two 32-bit selects against the uniform ballot)
+        uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
         for (int b = 0; b < bits; b++) {
-            bool bit = (d[j] >> b) & 1u;
-            uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+            const bool bit = (d[j] >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            const uint32_t blo = (uint32_t)bb, bhi = (uint32_t)(bb >> 32);
+            mlo &= bit ? blo : ~blo;
+            mhi &= bit ? bhi : ~bhi;
         }
+        const uint64_t m = ((uint64_t)mhi << 32) | mlo;
         uint32_t r = mask_rank(m);
         uint32_t c = __builtin_popcountll(m);
         // the read and the leader's add are both LDS operations of this wave, executed
