@@ -12,7 +12,7 @@ constexpr int LOC = 1 << LBITS;
 constexpr int MAX_BUCKETS = 1024;         // ids up to 2^22
 constexpr int HIST_SPLIT = 4;             // histogram workgroups per partition tile range
 constexpr int MAX_RANGES = 4096;          // rows of per-range bucket counts (histogram workgroups)
-constexpr int HCHUNK = 256;               // declarations per arity chunk
+constexpr int HCHUNK = 64;                // declarations per arity chunk
 constexpr int P_ITEMS = 16;               // partition / replay: words per thread
 constexpr int PTILE = BLOCK * P_ITEMS;
 constexpr int B_ITEMS = 16;               // bucket scan: words per thread

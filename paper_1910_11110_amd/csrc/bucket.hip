@@ -154,8 +154,8 @@ __device__ __forceinline__ void hist_word(uint32_t w, uint64_t i, bool in, uint3
 }
 
 // Bucket histogram of a static range of tiles: workgroup r counts part r of nrows equal
-// parts of the tiles in LDS and stores its per-bucket counts as row r of gsum (a
-// partition range is HIST_SPLIT consecutive parts).  With chunk_sum, each chunk of
+// parts of the tiles in LDS and stores its per-bucket counts as row r of gsum
+// (column-major; a partition range is HIST_SPLIT consecutive parts).  With chunk_sum, each chunk of
 // HCHUNK words also gets its total arity (SRC::arity).
 template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
@@ -209,12 +209,13 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restric
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += BLOCK)
-        gsum[(uint64_t)blockIdx.x * nb + i] = s_h[i];
+        gsum[(uint64_t)i * nrows + blockIdx.x] = s_h[i]; // column-major: bucket i, row r
 }
 
-// Column scan of the per-range bucket counts: gpre[j][b] = counts of bucket b in rows
-// before j; tot[b] = all of bucket b.  One wave per bucket, each lane a run of rows
-// (at most 32), a wave scan over the lanes' sums.
+// Column scan of the per-range bucket counts (column-major, row r of bucket b at
+// b * nrows + r): gpre = counts of bucket b in rows before r; tot[b] = all of bucket b.
+// One wave per bucket, each lane a run of consecutive rows, a wave scan over the lanes'
+// sums.
 constexpr int COLSCAN_ROWS = MAX_RANGES / WAVE; // rows per lane
 __global__ __launch_bounds__(BLOCK) void k_bucket_colscan(const uint32_t *__restrict__ gsum, uint32_t nb,
                                                           uint32_t nrows, uint32_t *__restrict__ gpre,
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_colscan(const uint32_t *__rest
 #pragma unroll
     for (int k = 0; k < COLSCAN_ROWS; k++) {
         const uint32_t j = r0 + k;
-        v[k] = (k < (int)per && j < nrows) ? gsum[(uint64_t)j * nb + b] : 0u;
+        v[k] = (k < (int)per && j < nrows) ? gsum[(uint64_t)b * nrows + j] : 0u;
         sum += v[k];
     }
     const uint32_t inc = wave_scan_add(sum, lane);
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_colscan(const uint32_t *__rest
     for (int k = 0; k < COLSCAN_ROWS; k++) {
         const uint32_t j = r0 + k;
         if (k < (int)per && j < nrows)
-            gpre[(uint64_t)j * nb + b] = run;
+            gpre[(uint64_t)b * nrows + j] = run;
         run += v[k];
     }
     if (lane == WAVE - 1)
@@ -322,6 +323,7 @@ template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
                                                      int bits, const uint64_t *__restrict__ base,
                                                      const uint32_t *__restrict__ gpre, uint32_t nranges,
+                                                     uint32_t nrows,
                                                      uint32_t *__restrict__ dst, uint32_t *__restrict__ tpre,
                                                      uint64_t ntiles)
 {
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t nb = 1u << bits;
     for (uint32_t b = tid; b < nb; b += BLOCK)
-        s_run[b] = (uint32_t)base[b] + gpre[(uint64_t)blockIdx.x * HIST_SPLIT * nb + b];
+        s_run[b] = (uint32_t)base[b] + gpre[(uint64_t)b * nrows + (uint64_t)blockIdx.x * HIST_SPLIT];
     uint64_t t0, t1;
     split_range(ntiles, (uint64_t)nranges * HIST_SPLIT, (uint64_t)blockIdx.x * HIST_SPLIT, t0, t1);
     t1 = ((uint64_t)blockIdx.x + 1) * HIST_SPLIT * ntiles / ((uint64_t)nranges * HIST_SPLIT);
@@ -934,8 +936,8 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     uint8_t *res = direct_out;
     if (L.nb > 1) {
         ProfScope p(s, "partition");
-        k_partition<SRC><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, L.part, L.tpre,
-                                                   L.ptiles);
+        k_partition<SRC><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, nrows, L.part,
+                                                   L.tpre, L.ptiles);
         part = L.part;
         res = L.res;
     }

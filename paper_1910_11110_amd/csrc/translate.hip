@@ -655,9 +655,9 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         if (d_lo <= n_decl) {
             const uint64_t first = d_lo - d_lo % HCHUNK;
             uint32_t part = 0;
-            uint32_t pw[HCHUNK / WAVE], dw[WDCAP / WAVE], pr[WDCAP / WAVE];
+            uint32_t pw[(HCHUNK + WAVE - 1) / WAVE], dw[WDCAP / WAVE], pr[WDCAP / WAVE];
 #pragma unroll
-            for (int k = 0; k < HCHUNK / WAVE; k++) {
+            for (int k = 0; k < (HCHUNK + WAVE - 1) / WAVE; k++) {
                 const uint64_t i = first + k * WAVE + lane;
                 pw[k] = i < d_lo ? decls[i] : 0u;
             }
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             }
             const uint64_t cb = chunk_prefix[d_lo / HCHUNK];
 #pragma unroll
-            for (int k = 0; k < HCHUNK / WAVE; k++)
+            for (int k = 0; k < (HCHUNK + WAVE - 1) / WAVE; k++)
                 part += first + k * WAVE + lane < d_lo ? decl_arity(pw[k], n_vars) : 0u;
             base = cb + wave_sum_u32(part);
 #pragma unroll
