@@ -113,10 +113,20 @@ def wl_components(args, V, ctx, stream):
             times.append(time.perf_counter() - a)
         return n_ev / float(np.median(times)), f"oracle translate+check of the full workload, median of 3 runs"
 
+    nd = int(ct.decls.size)
+    # each kernel's own algorithmic traffic: its inputs read once, its outputs written once
+    # (unit: declarations for the declaration passes, translated events for the emitter)
+    kernel_bytes = {
+        "bucket_hist": (4 * nd + 4 * (nd // 64), nd, "declaration"),      # words; chunk event counts
+        "partition": (8 * nd, nd, "declaration"),                        # words in, words out
+        "bucket_scan": (5 * nd + n_vars, nd, "declaration"),             # words in, pre-status out, final
+        "replay_bytes": (6 * nd, nd, "declaration"),                     # words, gathered byte, byte out
+        "translate_emit_wave": (5 * nd + 8 * (n_comp + 1) + 5 * n_ev, n_ev, "translated event"),
+    }
     cfg = {"workload": f"components-2^{args.comp_log2}", "n_components": n_comp, "n_vars": n_vars,
-           "n_declarations": int(ct.decls.size), "n_events": int(n_ev), "violations": int(viol)}
+           "n_declarations": nd, "n_events": int(n_ev), "violations": int(viol)}
     return dict(step=step, units=n_ev, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, co, de),
-                per_unit=lambda: bytes_alg() / n_ev)
+                per_unit=lambda: bytes_alg() / n_ev, kernel_bytes=kernel_bytes)
 
 
 def wl_plain(args, V, ctx, stream, n=None, n_ids=64):
@@ -148,9 +158,16 @@ def wl_plain(args, V, ctx, stream, n=None, n_ids=64):
             times.append(time.perf_counter() - a)
         return m / float(np.median(times)), f"oracle check of the first {m} events, median of 3 runs"
 
+    kernel_bytes = {
+        "small_check": (5 * n + 4 * viol + n_ids, n, "event"),              # events in, status out, violations
+        "bucket_hist": (4 * n, n, "event"),
+        "partition": (8 * n, n, "event"),
+        "bucket_scan": (5 * n + n_ids, n, "event"),
+        "replay_status": (6 * n + 4 * viol, n, "event"),                    # words, gathered byte, status, violations
+    }
     cfg = {"workload": f"plain-{n}x{n_ids}", "n_events": n, "n_ids": n_ids, "violations": int(viol)}
     return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te),
-                per_unit=lambda: bytes_alg() / n)
+                per_unit=lambda: bytes_alg() / n, kernel_bytes=kernel_bytes)
 
 
 def wl_overlap(args, V, ctx, stream):
@@ -257,17 +274,24 @@ def main():
     kernels = {k: {"ms_per_launch": ms / max(n, 1), "launches_per_step": n / args.steps, "ms_per_step": ms / args.steps}
                for k, (ms, n) in prof.items()}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if kernels else None
-    per_unit = w["per_unit"]()
     alg_step = w["bytes_alg"]()
+    kb = w.get("kernel_bytes", {})
+    # per kernel: its own algorithmic bytes per launch / its average launch time
+    kroof = {}
+    for k, (b, units, unit) in kb.items():
+        if k in kernels and kernels[k]["ms_per_launch"] > 0:
+            gbs = b / (kernels[k]["ms_per_launch"] / 1e3) / 1e9
+            kroof[k] = {"bytes_per_launch": int(b), "units_per_launch": int(units), "unit": unit,
+                        "achieved_GBs": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     roof = None
     if dom:
         d = kernels[dom]
-        # method's algorithmic bytes per unit x units one launch processes / launch time
-        units_per_launch = w["units"] / d["launches_per_step"]
-        achieved = per_unit * units_per_launch / (d["ms_per_launch"] / 1e3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, args.workload),
-                "bytes_per_unit": round(per_unit, 3), "units_per_launch": units_per_launch,
+        r = kroof.get(dom)
+        achieved = r["achieved_GBs"] if r else None
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": r["frac"] if r else None, "traffic": traffic_for(dom, args.workload),
+                "bytes_per_unit": round(r["bytes_per_launch"] / r["units_per_launch"], 3) if r else None,
+                "units_per_launch": r["units_per_launch"] if r else None,
                 "ms_per_launch": round(d["ms_per_launch"], 4)}
     pipeline = {"algorithmic_bytes_per_step": int(alg_step),
                 "achieved_GBs": round(alg_step / (ms_step / 1e3) / 1e9, 2),
@@ -294,6 +318,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "pipeline_roofline": pipeline,
+        "kernel_rooflines": kroof,
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
         "source_digest": source_digest(),
     }
