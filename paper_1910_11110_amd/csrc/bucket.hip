@@ -69,7 +69,7 @@ struct DeclWords {
 };
 
 // predecessors read per look-back round
-constexpr int LB_WIN = 16;
+constexpr int LB_WIN = 4;
 
 // ----------------------------------------------------------------------------------
 // stable ranking of a tile's words by a digit (striped arrangement: item j of lane l
