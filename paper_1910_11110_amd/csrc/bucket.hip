@@ -73,25 +73,30 @@ constexpr int LB_WIN = 4;
 
 // ----------------------------------------------------------------------------------
 // stable ranking of a tile's words by a digit (striped arrangement: item j of lane l
-// in wave w is tile position w*64*ITEMS + j*64 + l); per-wave digit counters in LDS
+// in wave w is tile position w*64*ITEMS + j*64 + l); per-wave digit counters in LDS.
+// The lanes holding the same digit as this lane are found bit by bit: the lane's bit
+// sign-extended to a word (0 or all ones) XNOR the bit's ballot keeps the lanes that
+// agree on it (one three-input bit operation per mask half).  With PARTIAL, items whose
+// validmask bit is clear take no part: they get no rank and add to no counter.
 // ----------------------------------------------------------------------------------
-template <int ITEMS, int MAXD>
+template <int ITEMS, int MAXD, bool PARTIAL>
 __device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t validmask, int bits,
                                             uint32_t (&rank)[ITEMS], uint32_t *s_cnt /* [4][MAXD] */, uint32_t wave)
 {
 #pragma unroll
     for (int j = 0; j < ITEMS; j++) {
-        bool valid = (validmask >> j) & 1u;
-        const uint64_t vm = __ballot(valid);
-        // lanes whose digit equals this lane's: per bit, the ballot or its complement,
-        // chosen per lane (two 32-bit selects against the uniform ballot)
-        uint32_t mlo = (uint32_t)vm, mhi = (uint32_t)(vm >> 32);
+        const bool valid = PARTIAL ? ((validmask >> j) & 1u) != 0 : true;
+        uint32_t mlo = ~0u, mhi = ~0u;
+        if (PARTIAL) {
+            const uint64_t vm = __ballot(valid);
+            mlo = (uint32_t)vm;
+            mhi = (uint32_t)(vm >> 32);
+        }
         for (int b = 0; b < bits; b++) {
-            const bool bit = (d[j] >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            const uint32_t blo = (uint32_t)bb, bhi = (uint32_t)(bb >> 32);
-            mlo &= bit ? blo : ~blo;
-            mhi &= bit ? bhi : ~bhi;
+            const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d[j], b, 1);
+            const uint64_t bb = __ballot(sel != 0);
+            mlo &= ~(sel ^ (uint32_t)bb);
+            mhi &= ~(sel ^ (uint32_t)(bb >> 32));
         }
         const uint64_t m = ((uint64_t)mhi << 32) | mlo;
         uint32_t r = mask_rank(m);
@@ -352,11 +357,14 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
 #pragma unroll
         for (int j = 0; j < P_ITEMS; j++) {
             uint64_t g = wb + (uint64_t)j * WAVE + lane;
-            w[j] = g < n ? src[g] : 0u;
+            w[j] = src[g < n ? g : n - 1]; // clamped: a load for every lane, no branch
             valid |= (g < n ? 1u : 0u) << j;
             d[j] = SRC::key(w[j], n_ids) >> LBITS;
         }
-        rank_digits<P_ITEMS, MAX_BUCKETS>(d, valid, bits, rank, s_cnt, wave);
+        if (tbase + PTILE <= n)
+            rank_digits<P_ITEMS, MAX_BUCKETS, false>(d, valid, bits, rank, s_cnt, wave);
+        else
+            rank_digits<P_ITEMS, MAX_BUCKETS, true>(d, valid, bits, rank, s_cnt, wave);
         __syncthreads();
         // per bucket: wave offsets and the tile's count
         for (uint32_t b = tid; b < nb; b += BLOCK) {
@@ -412,6 +420,12 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
         __syncthreads();
     }
 }
+
+// bits 0, 8, 16 and 24 of v as bits 0..3 (the four partial products of the multiply
+// land on distinct bits: no carries)
+__device__ __forceinline__ uint32_t byte_lsbs(uint32_t v) { return (((v & 0x01010101u) * 0x00204081u) >> 21) & 0xFu; }
+// bits 0..3 of v as bits 0, 8, 16 and 24
+__device__ __forceinline__ uint32_t to_byte_lsbs(uint32_t v) { return ((v & 0xFu) * 0x00204081u) & 0x01010101u; }
 
 // ----------------------------------------------------------------------------------
 // 2. scan inside every bucket
@@ -473,16 +487,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         const uint32_t cnt = (uint32_t)(b1 - t0 < (uint64_t)BTILE ? b1 - t0 : (uint64_t)BTILE);
         const bool last_tile = t0 + cnt == b1;
 
-        // load packed items (striped arrangement)
+        // load packed items (striped arrangement).  Positions past the tile's count hold
+        // padding: local id LOC - 1 with the identity function, so every pass runs on full
+        // tiles; the stable passes leave the padding after all real items (it comes last
+        // in tile order and has the largest local id), where it changes no aggregate and
+        // its results are not written out.
         uint32_t it[B_ITEMS], d[B_ITEMS], rank[B_ITEMS];
-        uint32_t valid = 0;
 #pragma unroll
         for (int j = 0; j < B_ITEMS; j++) {
-            uint32_t pos = wave * WAVE * B_ITEMS + j * WAVE + lane;
-            uint32_t w = pos < cnt ? part[t0 + pos] : 0u;
-            uint32_t key = SRC::key(w, n_ids);
-            it[j] = (key & 0xFFFu) | (SRC::fc(w, n_ids) << 12) | (pos << 16);
-            valid |= (pos < cnt ? 1u : 0u) << j;
+            const uint32_t pos = wave * WAVE * B_ITEMS + j * WAVE + lane;
+            const uint32_t w = part[t0 + (pos < cnt ? pos : cnt - 1)];
+            const uint32_t key = SRC::key(w, n_ids);
+            const uint32_t real = (key & (LOC - 1)) | (SRC::fc(w, n_ids) << 12);
+            it[j] = (pos < cnt ? real : (LOC - 1) | (fcode(OP_NOOP, 0) << 12)) | (pos << 16);
         }
         for (uint32_t i = tid; i < LB_WORDS * 5; i += BLOCK)
             reinterpret_cast<uint32_t *>(s_agg)[i] = 0; // identity
@@ -494,15 +511,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             __syncthreads();
             if (pass == 1) {
 #pragma unroll
-                for (int j = 0; j < B_ITEMS; j++) {
-                    uint32_t pos = wave * WAVE * B_ITEMS + j * WAVE + lane;
-                    it[j] = pos < cnt ? s_a[pos] : 0u;
-                }
+                for (int j = 0; j < B_ITEMS; j++)
+                    it[j] = s_a[wave * WAVE * B_ITEMS + j * WAVE + lane];
             }
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++)
                 d[j] = (loc_of(it[j]) >> (6 * pass)) & 63u;
-            rank_digits<B_ITEMS, 64>(d, valid, 6, rank, s_cnt, wave);
+            rank_digits<B_ITEMS, 64, false>(d, 0u, 6, rank, s_cnt, wave);
             __syncthreads();
             if (tid < 64) {
                 uint32_t tc = 0;
@@ -523,10 +538,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             uint32_t *dstarr = pass == 0 ? s_a : s_b;
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++) {
-                const uint32_t dj = (loc_of(it[j]) >> (6 * pass)) & 63u;
-                uint32_t li = s_dst[dj] + s_cnt[wave * 64 + dj] + rank[j];
-                if (((valid >> j) & 1u) && li < BTILE)
-                    dstarr[li] = it[j];
+                const uint32_t dj = d[j];
+                // in range for consistent counts (the tile holds BTILE items); the mask
+                // keeps every store inside the array
+                const uint32_t li = (s_dst[dj] + s_cnt[wave * 64 + dj] + rank[j]) & (BTILE - 1);
+                dstarr[li] = it[j];
             }
             __syncthreads();
         }
@@ -534,22 +550,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         // segmented scan over the sorted items (blocked: thread t owns t*16 ..)
         const uint32_t first = tid * B_ITEMS;
         uint32_t acc = F_ID, headseen = 0;
-        uint32_t prevloc = first == 0 ? 0xFFFFu : (first - 1 < cnt ? loc_of(s_b[first - 1]) : 0xFFFFu);
+        uint32_t prevloc = first == 0 ? 0xFFFFu : loc_of(s_b[first - 1]);
         uint32_t x[B_ITEMS];
         uint32_t heads = 0;
 #pragma unroll
         for (int j = 0; j < B_ITEMS; j++) {
-            uint32_t p = first + j;
-            x[j] = p < cnt ? s_b[p] : 0xFFFFFFFFu;
-            uint32_t loc = p < cnt ? loc_of(x[j]) : 0xFFFEu;
-            if (loc != prevloc && p < cnt) {
+            x[j] = s_b[first + j];
+            const uint32_t loc = loc_of(x[j]);
+            if (loc != prevloc) {
                 heads |= 1u << j;
                 acc = F_ID;
                 headseen = 1;
             }
             prevloc = loc;
-            if (p < cnt)
-                acc = fcompose(s_f4[(x[j] >> 12) & 15u], acc);
+            acc = fcompose(s_f4[(x[j] >> 12) & 15u], acc);
         }
         // segmented scan of (flag, function) across threads: a segment restarts the
         // composition, so the carry into a thread is the composition since the last head
@@ -584,18 +598,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         // tile aggregate per local id: inclusive value at each segment's last item
         {
             uint32_t a = texc;
+            const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_b[first + B_ITEMS]) : 0xFFFFu;
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++) {
-                const uint32_t p = first + j;
-                if (p < cnt) {
-                    if ((heads >> j) & 1u)
-                        a = F_ID;
-                    a = fcompose(s_f4[(x[j] >> 12) & 15u], a);
-                    uint32_t nloc = (j + 1 < B_ITEMS) ? (p + 1 < cnt ? loc_of(x[j + 1]) : 0xFFFFu)
-                                                      : (p + 1 < cnt ? loc_of(s_b[p + 1]) : 0xFFFFu);
-                    if (nloc != loc_of(x[j]))
-                        s_agg[loc_of(x[j])] = (uint8_t)mon_code(a);
-                }
+                if ((heads >> j) & 1u)
+                    a = F_ID;
+                a = fcompose(s_f4[(x[j] >> 12) & 15u], a);
+                const uint32_t nloc = j + 1 < B_ITEMS ? loc_of(x[j + 1]) : after;
+                if (nloc != loc_of(x[j]))
+                    s_agg[loc_of(x[j])] = (uint8_t)mon_code(a);
             }
         }
         __syncthreads();
@@ -611,13 +622,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 #pragma unroll
             for (int q = 0; q < 5; q++) {
                 const uint32_t c4 = ag4[q];
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const uint32_t c = (c4 >> (8 * k)) & 7u, bit = 4 * q + k;
-                    agg.t |= ((c >> 2) & 1u) << bit;
-                    agg.x |= ((c >> 1) & 1u) << bit;
-                    agg.y |= (c & 1u) << bit;
-                }
+                agg.t |= byte_lsbs(c4 >> 2) << (4 * q);
+                agg.x |= byte_lsbs(c4 >> 1) << (4 * q);
+                agg.y |= byte_lsbs(c4) << (4 * q);
             }
             Planes st{PL_MASK, 0, 0}; // statuses entering the tile, as constants
             if (ti == 0) {
@@ -666,15 +673,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             lb_store(&tilew[wi], LB_INC | pl_pack(inc));
             uint32_t *st4 = reinterpret_cast<uint32_t *>(s_state) + wi * 5;
 #pragma unroll
-            for (int q = 0; q < 5; q++) {
-                uint32_t w4 = 0;
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    const int bit = 4 * q + k;
-                    w4 |= (((st.x >> bit) & 1u) | (((st.y >> bit) & 1u) << 1)) << (8 * k);
-                }
-                st4[q] = w4;
-            }
+            for (int q = 0; q < 5; q++)
+                st4[q] = to_byte_lsbs(st.x >> (4 * q)) | (to_byte_lsbs(st.y >> (4 * q)) << 1);
             if (last_tile && final_out) {
                 for (int k = 0; k < 20; k++) {
                     const uint32_t key = b * LOC + wi * 20 + k;
@@ -690,19 +690,17 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             uint32_t a = texc;
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++) {
-                const uint32_t p = first + j;
-                if (p < cnt) {
-                    if ((heads >> j) & 1u)
-                        a = F_ID;
-                    const uint32_t xj = s_b[p]; // re-read: keeps the items out of registers across the look-back
-                    uint32_t loc = loc_of(xj), fcj = (xj >> 12) & 15u;
-                    uint32_t pre = fapply(a, s_state[loc]);
-                    uint32_t post = fapply(s_f4[fcj], pre);
-                    uint32_t flag = (s_stuck[fcj] >> pre) & 1u;
-                    a = fcompose(s_f4[fcj], a);
-                    uint32_t r = MODE == BK_PRE ? pre : (post | (pre << 2) | (flag << 7));
-                    s_res[(xj >> 16) & (BTILE - 1)] = (uint8_t)r;
-                }
+                if ((heads >> j) & 1u)
+                    a = F_ID;
+                const uint32_t xj = s_b[first + j]; // re-read: keeps the items out of registers across the look-back
+                const uint32_t loc = loc_of(xj), fcj = (xj >> 12) & 15u;
+                const uint32_t fj = s_f4[fcj];
+                const uint32_t pre = fapply(a, s_state[loc]);
+                const uint32_t post = fapply(fj, pre);
+                const uint32_t flag = (s_stuck[fcj] >> pre) & 1u;
+                a = fcompose(fj, a);
+                const uint32_t r = MODE == BK_PRE ? pre : (post | (pre << 2) | (flag << 7));
+                s_res[(xj >> 16) & (BTILE - 1)] = (uint8_t)r;
             }
         }
         __syncthreads();
@@ -735,11 +733,14 @@ __device__ __forceinline__ void replay_tile(const uint32_t *__restrict__ src, ui
 #pragma unroll
     for (int j = 0; j < P_ITEMS; j++) {
         uint64_t g = wb + (uint64_t)j * WAVE + lane;
-        w[j] = g < n ? src[g] : 0u;
+        w[j] = src[g < n ? g : n - 1]; // clamped: a load for every lane, no branch
         valid |= (g < n ? 1u : 0u) << j;
         d[j] = SRC::key(w[j], n_ids) >> LBITS;
     }
-    rank_digits<P_ITEMS, MAX_BUCKETS>(d, valid, bits, rank, s_cnt, wave);
+    if (tbase + PTILE <= n)
+        rank_digits<P_ITEMS, MAX_BUCKETS, false>(d, valid, bits, rank, s_cnt, wave);
+    else
+        rank_digits<P_ITEMS, MAX_BUCKETS, true>(d, valid, bits, rank, s_cnt, wave);
     __syncthreads();
     for (uint32_t b = tid; b < nb; b += BLOCK) {
         uint32_t tc = 0;
