@@ -567,21 +567,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         }
         // segmented scan of (flag, function) across threads: a segment restarts the
         // composition, so the carry into a thread is the composition since the last head
+        // (DPP pattern of wave_scan_dpp on the pair; a lane without a source combines
+        // with (identity, no head))
         uint32_t f = acc, fl = headseen;
-#pragma unroll
-        for (int dd = 1; dd < WAVE; dd <<= 1) {
-            uint32_t g2 = __shfl_up(f, dd);
-            uint32_t fl2 = __shfl_up(fl, dd);
-            if (lane >= (uint32_t)dd && !fl) {
+        auto seg = [&](uint32_t g2, uint32_t fl2) {
+            if (!fl) {
                 f = fcompose(f, g2);
                 fl = fl2;
             }
-        }
-        uint32_t wexc = __shfl_up(f, 1), wexf = __shfl_up(fl, 1);
-        if (lane == 0) {
-            wexc = F_ID;
-            wexf = 0;
-        }
+        };
+        seg(dpp_move<DPP_ROW_SHR + 1>(F_ID, f), dpp_move<DPP_ROW_SHR + 1>(0u, fl));
+        seg(dpp_move<DPP_ROW_SHR + 2>(F_ID, f), dpp_move<DPP_ROW_SHR + 2>(0u, fl));
+        seg(dpp_move<DPP_ROW_SHR + 4>(F_ID, f), dpp_move<DPP_ROW_SHR + 4>(0u, fl));
+        seg(dpp_move<DPP_ROW_SHR + 8>(F_ID, f), dpp_move<DPP_ROW_SHR + 8>(0u, fl));
+        seg(dpp_move<DPP_ROW_BCAST15, 0xA>(F_ID, f), dpp_move<DPP_ROW_BCAST15, 0xA>(0u, fl));
+        seg(dpp_move<DPP_ROW_BCAST31, 0xC>(F_ID, f), dpp_move<DPP_ROW_BCAST31, 0xC>(0u, fl));
+        const uint32_t wexc = dpp_move<DPP_WAVE_SHR1>(F_ID, f), wexf = dpp_move<DPP_WAVE_SHR1>(0u, fl);
         if (lane == WAVE - 1) {
             s_wagg[wave] = f;
             s_wflag[wave] = fl;

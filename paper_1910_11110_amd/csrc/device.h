@@ -113,16 +113,38 @@ __device__ __forceinline__ uint32_t mask_rank(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// inclusive scan of transition functions across the wave (lane 0 earliest)
-__device__ __forceinline__ uint32_t wave_scan_compose(uint32_t f, uint32_t lane)
+// Lane moves by DPP (wave64): lane i of the result reads the source pattern's lane, or
+// keeps `old` where the pattern has no source lane or the row is masked off.  Scans are
+// called with the whole wave active.
+constexpr int DPP_ROW_SHR = 0x110;     // + n (1..15): lane i reads lane i - n of its row of 16
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane i reads lane i - 1
+constexpr int DPP_ROW_BCAST15 = 0x142; // lane 15 of each row to every lane of the next row
+constexpr int DPP_ROW_BCAST31 = 0x143; // lane 31 to every lane of rows 2 and 3
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t v)
 {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t g = __shfl_up(f, d);
-        if (lane >= (uint32_t)d)
-            f = fcompose(f, g);
-    }
-    return f;
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+// Inclusive scan of an associative operation across the wave (lane 0 first): shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes, then the last lane of row 0 (2) into row 1
+// (3), then lane 31 into rows 2 and 3.  op(earlier, later); `ident` is its identity.
+template <class OP>
+__device__ __forceinline__ uint32_t wave_scan_dpp(uint32_t v, uint32_t ident, OP op)
+{
+    v = op(dpp_move<DPP_ROW_SHR + 1>(ident, v), v);
+    v = op(dpp_move<DPP_ROW_SHR + 2>(ident, v), v);
+    v = op(dpp_move<DPP_ROW_SHR + 4>(ident, v), v);
+    v = op(dpp_move<DPP_ROW_SHR + 8>(ident, v), v);
+    v = op(dpp_move<DPP_ROW_BCAST15, 0xA>(ident, v), v);
+    v = op(dpp_move<DPP_ROW_BCAST31, 0xC>(ident, v), v);
+    return v;
+}
+
+// inclusive scan of transition functions across the wave (lane 0 earliest)
+__device__ __forceinline__ uint32_t wave_scan_compose(uint32_t f, uint32_t)
+{
+    return wave_scan_dpp(f, F_ID, [](uint32_t a, uint32_t b) { return fcompose(b, a); });
 }
 
 template <class T>
@@ -135,6 +157,18 @@ __device__ __forceinline__ T wave_scan_add(T v, uint32_t lane)
             v += g;
     }
     return v;
+}
+
+template <>
+__device__ __forceinline__ uint32_t wave_scan_add<uint32_t>(uint32_t v, uint32_t)
+{
+    return wave_scan_dpp(v, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
+// sum over the wave, in every lane
+__device__ __forceinline__ uint32_t wave_total_u32(uint32_t v)
+{
+    return __builtin_amdgcn_readlane(wave_scan_add<uint32_t>(v, 0u), WAVE - 1);
 }
 
 // ---------------------------------------------------------------------------------

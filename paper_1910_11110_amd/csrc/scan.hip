@@ -84,9 +84,7 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
 
     // exclusive scan of thread aggregates across the block
     uint32_t winc = wave_scan_compose(acc, lane);
-    uint32_t wexc = __shfl_up(winc, 1);
-    if (lane == 0)
-        wexc = F_ID;
+    const uint32_t wexc = dpp_move<DPP_WAVE_SHR1>(F_ID, winc); // lane 0: identity
     if (lane == WAVE - 1)
         s_wagg[wave] = winc;
     __syncthreads();

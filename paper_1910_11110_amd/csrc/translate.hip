@@ -285,10 +285,7 @@ __device__ __forceinline__ void emit_decl_lds(uint32_t wd, uint32_t n_vars, uint
 // adds the wave's flagged events to the global count (one atomic per wave that has any)
 __device__ __forceinline__ void add_flagged(uint32_t nflag, unsigned long long *n_flagged)
 {
-    uint32_t v = nflag;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1)
-        v += __shfl_xor(v, d);
+    const uint32_t v = wave_total_u32(nflag);
     if (lane_id() == 0 && v)
         atomicAdd(n_flagged, (unsigned long long)v);
 }
@@ -609,13 +606,6 @@ __device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
     return slot_arity(mode) + body_arity(mode);
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
-{
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1)
-        v += __shfl_xor(v, d);
-    return v;
-}
 
 __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
@@ -671,7 +661,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
 #pragma unroll
             for (int k = 0; k < (HCHUNK + WAVE - 1) / WAVE; k++)
                 part += first + k * WAVE + lane < d_lo ? decl_arity(pw[k], n_vars) : 0u;
-            base = cb + wave_sum_u32(part);
+            base = cb + wave_total_u32(part);
 #pragma unroll
             for (int k = 0; k < WDCAP / WAVE; k++) {
                 const uint32_t i = k * WAVE + lane;
@@ -698,7 +688,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 const uint32_t inc = wave_scan_add(m, lane);
                 if (i < nd)
                     L.scan[i] = carry + inc - m;
-                carry += __shfl(inc, WAVE - 1);
+                carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
             }
             if (lane == 0)
                 L.scan[nd] = carry;
@@ -712,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 cnt += decl_arity(decls[d], n_vars);
         }
         const uint32_t incc = wave_scan_add(cnt, lane);
-        const uint32_t excl = incc - cnt, total = __shfl(incc, WAVE - 1);
+        const uint32_t excl = incc - cnt, total = __builtin_amdgcn_readlane(incc, WAVE - 1);
         const bool staged = fits && total <= (uint32_t)WECAP && base + total <= cap;
         if (staged) {
             if (lane <= nc)
