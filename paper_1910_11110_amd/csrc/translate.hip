@@ -582,22 +582,29 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
 // prefix of the per-chunk event counts (HCHUNK declarations a chunk, counted by the
 // histogram pass) at the chunk of the tile's first declaration plus the events of that
 // chunk's declarations before it; inside the tile, wave scans over the declarations and
-// the components.  The tile's events are staged in the wave's LDS and written out
-// contiguously; a tile whose declarations or events do not fit, or whose offsets are
-// malformed (reported with the component's index), is written in place, one component
-// per lane.
+// the components.  Declaration i of the tile is held by lane i % 64 in round i / 64; its
+// component is found from a ballot of the component starts.  The tile's events are
+// staged in the wave's LDS and written out contiguously; a tile whose declarations or
+// events do not fit, or whose offsets are malformed (reported with the component's
+// index), is written in place, one component per lane.
 constexpr int WCOMPS = 32;  // components per wave tile
 constexpr int WDCAP = 256;  // declarations staged per wave tile
+constexpr int WROUNDS = WDCAP / WAVE;
 constexpr int WECAP = 768;  // events staged per wave tile
 
 struct WaveTile {
+    // staged events at index off + i, off = (first output index) mod 4: groups of four
+    // staged entries line up with 16-byte groups of the event output and 4-byte groups
+    // of the status output
+    __align__(16) uint32_t ev[WECAP + 4];
+    __align__(16) uint8_t st[WECAP + 4];
     uint64_t coff[WCOMPS + 1];
-    uint32_t pos[WCOMPS + 1]; // events before each component, relative to the tile
-    uint32_t decl[WDCAP];
+    // per non-empty component, by its rank among them: staged index of its first slot
+    // event minus the slot prefix at its first declaration (low word), and the same for
+    // its body events (high word)
+    uint64_t cab[WCOMPS];
     uint32_t scan[WDCAP + 1]; // exclusive prefix of (slot arity | body arity << 16)
-    uint32_t ev[WECAP];
-    uint8_t pre[WDCAP];
-    uint8_t st[WECAP];
+    __align__(4) uint8_t start[WDCAP]; // 1 where a non-empty component starts
 };
 
 __device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
@@ -605,7 +612,6 @@ __device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
     const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
     return slot_arity(mode) + body_arity(mode);
 }
-
 
 __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
@@ -617,12 +623,15 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
     WaveTile &L = s_tiles[wave];
     uint32_t nflag = 0;
+    // vector write-out needs 16-byte aligned events and 4-byte aligned statuses
+    const bool vec_out = (reinterpret_cast<uintptr_t>(out) & 15u) == 0 && (reinterpret_cast<uintptr_t>(status) & 3u) == 0;
     const uint64_t nw = (uint64_t)gridDim.x * (BLOCK / WAVE);
     for (uint64_t wt = (uint64_t)blockIdx.x * (BLOCK / WAVE) + wave; wt < ntiles; wt += nw) {
         const uint64_t c0 = wt * WCOMPS;
         const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)WCOMPS ? n_comp - c0 : (uint64_t)WCOMPS);
         if (lane <= nc)
             L.coff[lane] = comp_off[c0 + lane];
+        reinterpret_cast<uint32_t *>(L.start)[lane] = 0u;
         __builtin_amdgcn_wave_barrier();
         const uint64_t d_lo = L.coff[0], d_hi = L.coff[nc];
         // malformed offsets: reported; such a component has no events
@@ -639,55 +648,40 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         const bool any_bad = __ballot(bad) != 0;
         const bool fits = !any_bad && d_hi - d_lo <= (uint64_t)WDCAP;
         const uint32_t nd = fits ? (uint32_t)(d_hi - d_lo) : 0u;
-        // events before the tile: the chunk prefix plus the chunk's declarations before d_lo;
-        // and the tile's declarations (loads issued together)
+        // events before the tile: the chunk prefix plus the chunk's declarations before
+        // d_lo; and the tile's declarations with their pre-statuses (loads issued together)
         uint64_t base = 0;
+        uint32_t dw[WROUNDS], pr[WROUNDS], sx[WROUNDS];
         if (d_lo <= n_decl) {
             const uint64_t first = d_lo - d_lo % HCHUNK;
-            uint32_t part = 0;
-            uint32_t pw[(HCHUNK + WAVE - 1) / WAVE], dw[WDCAP / WAVE], pr[WDCAP / WAVE];
+            static_assert(HCHUNK <= WAVE, "one declaration of the chunk per lane");
+            const uint64_t pi = first + lane;
+            const uint32_t pw = pi < d_lo ? decls[pi] : 0u;
 #pragma unroll
-            for (int k = 0; k < (HCHUNK + WAVE - 1) / WAVE; k++) {
-                const uint64_t i = first + k * WAVE + lane;
-                pw[k] = i < d_lo ? decls[i] : 0u;
-            }
-#pragma unroll
-            for (int k = 0; k < WDCAP / WAVE; k++) {
+            for (int k = 0; k < WROUNDS; k++) {
                 const uint32_t i = k * WAVE + lane;
                 dw[k] = i < nd ? decls[d_lo + i] : 0u;
                 pr[k] = i < nd ? pre_abs[d_lo + i] : 0u;
             }
             const uint64_t cb = chunk_prefix[d_lo / HCHUNK];
-#pragma unroll
-            for (int k = 0; k < (HCHUNK + WAVE - 1) / WAVE; k++)
-                part += first + k * WAVE + lane < d_lo ? decl_arity(pw[k], n_vars) : 0u;
-            base = cb + wave_total_u32(part);
-#pragma unroll
-            for (int k = 0; k < WDCAP / WAVE; k++) {
-                const uint32_t i = k * WAVE + lane;
-                if (i < nd) {
-                    L.decl[i] = dw[k];
-                    L.pre[i] = (uint8_t)pr[k];
-                }
-            }
+            base = cb + wave_total_u32(pi < d_lo ? decl_arity(pw, n_vars) : 0u);
         }
-        __builtin_amdgcn_wave_barrier();
         // events per component (lane = component)
         uint32_t cnt = 0;
         if (fits) {
             uint32_t carry = 0;
 #pragma unroll
-            for (int k = 0; k < WDCAP / WAVE; k++) {
+            for (int k = 0; k < WROUNDS; k++) {
                 const uint32_t i = k * WAVE + lane;
                 uint32_t m = 0;
                 if (i < nd) {
-                    const uint32_t wd = L.decl[i];
-                    const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
+                    const uint32_t mode = decl_ok(dw[k], n_vars) ? (dw[k] >> 24) & 3u : 0u;
                     m = slot_arity(mode) | (body_arity(mode) << 16);
                 }
                 const uint32_t inc = wave_scan_add(m, lane);
+                sx[k] = carry + inc - m;
                 if (i < nd)
-                    L.scan[i] = carry + inc - m;
+                    L.scan[i] = sx[k];
                 carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
             }
             if (lane == 0)
@@ -705,46 +699,56 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         const uint32_t excl = incc - cnt, total = __builtin_amdgcn_readlane(incc, WAVE - 1);
         const bool staged = fits && total <= (uint32_t)WECAP && base + total <= cap;
         if (staged) {
-            if (lane <= nc)
-                L.pos[lane] = excl;
+            const uint32_t off = (uint32_t)(base & 3u), lim = off + total;
+            // non-empty components: start flag and staging bases, by rank
+            const bool nonempty = lane < nc && b > a;
+            const uint32_t rk = mask_rank(__ballot(nonempty));
+            if (nonempty) {
+                const uint32_t cs = (uint32_t)(a - d_lo), ce = (uint32_t)(b - d_lo);
+                const uint32_t y = L.scan[cs], x = L.scan[ce];
+                const uint32_t p0 = off + excl, slot_tot = (x & 0xFFFFu) - (y & 0xFFFFu);
+                const uint32_t sa = p0 - (y & 0xFFFFu), sb = p0 + slot_tot - (y >> 16);
+                L.cab[rk] = (uint64_t)sa | ((uint64_t)sb << 32);
+                L.start[cs] = 1;
+            }
             __builtin_amdgcn_wave_barrier();
+            uint32_t started = 0; // non-empty components started in earlier rounds
 #pragma unroll
-            for (int k = 0; k < WDCAP / WAVE; k++) {
+            for (int k = 0; k < WROUNDS; k++) {
+                if (k * WAVE >= nd)
+                    break;
                 const uint32_t i = k * WAVE + lane;
+                const uint32_t sf = i < nd ? L.start[i] : 0u;
+                const uint64_t sm = __ballot(sf != 0);
+                // the declaration's component: the last start at or before it
+                const uint32_t owner = started + mask_rank(sm) + sf - 1u;
+                started += (uint32_t)__builtin_popcountll(sm);
                 if (i < nd) {
-                    uint32_t lo = 0, hi = nc; // largest j with coff[j] - d_lo <= i
-                    while (hi - lo > 1) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (L.coff[mid] - d_lo <= i)
-                            lo = mid;
-                        else
-                            hi = mid;
-                    }
-                    const uint32_t cs = (uint32_t)(L.coff[lo] - d_lo), ce = (uint32_t)(L.coff[lo + 1] - d_lo);
-                    const uint32_t base_c = L.scan[cs];
-                    const uint32_t pre = L.scan[i] - base_c, tot = L.scan[ce] - base_c;
-                    const uint32_t pe = L.pos[lo];
-                    emit_decl_lds(L.decl[i], n_vars, L.pre[i], pe + (pre & 0xFFFFu), pe + (tot & 0xFFFFu) + (pre >> 16),
-                                  L.pos[lo + 1], L.ev, L.st, nflag);
+                    const uint64_t ab = L.cab[owner];
+                    emit_decl_lds(dw[k], n_vars, pr[k], (uint32_t)ab + (sx[k] & 0xFFFFu),
+                                  (uint32_t)(ab >> 32) + (sx[k] >> 16), lim, L.ev, L.st, nflag);
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            for (uint32_t i = lane; i < total; i += WAVE)
-                out[base + i] = L.ev[i];
-            const uint32_t h0 = (uint32_t)((4u - (base & 3u)) & 3u);
-            const uint32_t head = h0 < total ? h0 : total;
-            const uint32_t nwords = (total - head) / 4;
-            if (lane < head)
-                status[base + lane] = L.st[lane];
-            uint32_t *sw = reinterpret_cast<uint32_t *>(status + base + head);
-            for (uint32_t k = lane; k < nwords; k += WAVE) {
-                const uint32_t q = head + 4 * k;
-                sw[k] = (uint32_t)L.st[q] | ((uint32_t)L.st[q + 1] << 8) | ((uint32_t)L.st[q + 2] << 16) |
-                        ((uint32_t)L.st[q + 3] << 24);
+            // write-out by groups of four staged entries (output index base - off + j)
+            const uint64_t gb = base - off;
+            const uint32_t ngroups = (lim + 3u) / 4u;
+            for (uint32_t q = lane; q < ngroups; q += WAVE) {
+                const uint32_t j0 = 4u * q;
+                if (vec_out && j0 >= off && j0 + 4u <= lim) {
+                    *reinterpret_cast<uint4 *>(out + gb + j0) = *reinterpret_cast<const uint4 *>(&L.ev[j0]);
+                    *reinterpret_cast<uint32_t *>(status + gb + j0) = *reinterpret_cast<const uint32_t *>(&L.st[j0]);
+                } else {
+#pragma unroll
+                    for (uint32_t e = 0; e < 4; e++) {
+                        const uint32_t j = j0 + e;
+                        if (j >= off && j < lim) {
+                            out[gb + j] = L.ev[j];
+                            status[gb + j] = L.st[j];
+                        }
+                    }
+                }
             }
-            const uint32_t tail0 = head + 4 * nwords;
-            if (lane < total - tail0)
-                status[base + tail0 + lane] = L.st[tail0 + lane];
         } else if (lane < nc && !bad) {
             // in place, one component per lane; positions clamp to the output's capacity
             // (only malformed offsets, reported, can make the events outnumber 5 per
