@@ -72,14 +72,49 @@ struct DeclWords {
 constexpr int LB_WIN = 4;
 
 // ----------------------------------------------------------------------------------
-// stable ranking of a tile's words by a digit (striped arrangement: item j of lane l
+// Digit ranking
+// ----------------------------------------------------------------------------------
+// bit b of v as 0 or all ones.  An opaque v_bfe_i32: the ballot then tests this word
+// (one compare) instead of the compiler rederiving the bit from v (two more operations).
+__device__ __forceinline__ uint32_t sign_bit(uint32_t v, uint32_t b)
+{
+    uint32_t r;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(v), "s"(b));
+    return r;
+}
+template <int B>
+__device__ __forceinline__ uint32_t sign_bit(uint32_t v)
+{
+    uint32_t r;
+    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(v), "i"(B));
+    return r;
+}
+
+// keeps in (mlo, mhi) the lanes of the wave whose bit agrees with this lane's, given
+// as `sel` (0 or all ones); match_bits does so for bits [B, N) of d
+__device__ __forceinline__ void match_bit(uint32_t sel, uint32_t &mlo, uint32_t &mhi)
+{
+    const uint64_t bb = __ballot(sel != 0);
+    mlo &= ~(sel ^ (uint32_t)bb);
+    mhi &= ~(sel ^ (uint32_t)(bb >> 32));
+}
+template <int B, int N>
+__device__ __forceinline__ void match_bits(uint32_t d, uint32_t &mlo, uint32_t &mhi)
+{
+    if constexpr (B < N) {
+        match_bit(sign_bit<B>(d), mlo, mhi);
+        match_bits<B + 1, N>(d, mlo, mhi);
+    }
+}
+
+// Stable ranking of a tile's words by a digit (striped arrangement: item j of lane l
 // in wave w is tile position w*64*ITEMS + j*64 + l); per-wave digit counters in LDS.
 // The lanes holding the same digit as this lane are found bit by bit: the lane's bit
 // sign-extended to a word (0 or all ones) XNOR the bit's ballot keeps the lanes that
-// agree on it (one three-input bit operation per mask half).  With PARTIAL, items whose
-// validmask bit is clear take no part: they get no rank and add to no counter.
+// agree on it.  With PARTIAL, items whose validmask bit is clear take no part: they get
+// no rank and add to no counter.  CBITS > 0: the digit has CBITS bits (`bits` unused).
 // ----------------------------------------------------------------------------------
-template <int ITEMS, int MAXD, bool PARTIAL>
+template <int ITEMS, int MAXD, bool PARTIAL, int CBITS = 0>
 __device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t validmask, int bits,
                                             uint32_t (&rank)[ITEMS], uint32_t *s_cnt /* [4][MAXD] */, uint32_t wave)
 {
@@ -92,11 +127,11 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t
             mlo = (uint32_t)vm;
             mhi = (uint32_t)(vm >> 32);
         }
-        for (int b = 0; b < bits; b++) {
-            const uint32_t sel = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d[j], b, 1);
-            const uint64_t bb = __ballot(sel != 0);
-            mlo &= ~(sel ^ (uint32_t)bb);
-            mhi &= ~(sel ^ (uint32_t)(bb >> 32));
+        if constexpr (CBITS > 0) {
+            match_bits<0, CBITS>(d[j], mlo, mhi);
+        } else {
+            for (int b = 0; b < bits; b++)
+                match_bit(sign_bit(d[j], (uint32_t)b), mlo, mhi);
         }
         const uint64_t m = ((uint64_t)mhi << 32) | mlo;
         uint32_t r = mask_rank(m);
@@ -517,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++)
                 d[j] = (loc_of(it[j]) >> (6 * pass)) & 63u;
-            rank_digits<B_ITEMS, 64, false>(d, 0u, 6, rank, s_cnt, wave);
+            rank_digits<B_ITEMS, 64, false, 6>(d, 0u, 6, rank, s_cnt, wave);
             __syncthreads();
             if (tid < 64) {
                 uint32_t tc = 0;
