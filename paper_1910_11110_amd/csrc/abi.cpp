@@ -359,7 +359,7 @@ static bool use_small_path(const vc_trace *t)
 // path for larger id spaces: bucket partition, per-bucket scan, replay
 static bool use_bucket_path(const vc_trace *t)
 {
-    return !t->has_arrays && t->n_ids <= bucket_max_ids() && !getenv("VC_GENERAL_PATH");
+    return !t->has_arrays && t->n_ids <= bucket_max_ids() && t->n <= 0xFFFFFFFFull && !getenv("VC_GENERAL_PATH");
 }
 
 int enqueue_check(vc_trace *t, hipStream_t s)

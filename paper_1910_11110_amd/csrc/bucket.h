@@ -28,9 +28,9 @@ struct BucketLayout {
     uint32_t *tbase = nullptr;
     uint32_t *order = nullptr; // bucket tile (bucket-major index) taken by each ticket
     uint32_t *gsum = nullptr, *gpre = nullptr; // per tile range: bucket counts, their column prefix
-    uint32_t *tpre = nullptr;                  // per partition tile: start of each bucket's run
     uint64_t *lbv = nullptr, *lbc = nullptr;
     uint32_t *part = nullptr;
+    uint32_t *dstidx = nullptr; // per word: its position in the partitioned order
     uint8_t *res = nullptr;
     uint64_t ptiles = 0, btiles_max = 0;
 };

@@ -2,9 +2,10 @@
 // over 32-bit words (gfx950).
 //
 // 1. partition: one stable pass splits the words by bucket = id >> 12 (at most 1024
-//    buckets): each tile ranks its words by bucket with wave64 ballots, reorders them
-//    in LDS and writes every bucket's run contiguously; tile offsets come from a
-//    decoupled look-back whose final inclusive counts are kept for step 3.
+//    buckets).  A histogram per static range of tiles and a column scan give every
+//    range the start of each bucket's run; each range's workgroup then ranks the words
+//    of its tiles by bucket with wave64 ballots, reorders them in LDS, writes every
+//    bucket's run contiguously and stores each word's destination for step 3.
 // 2. bucket scan: every bucket (4096 ids) is scanned in its own tiles.  A tile sorts
 //    its words by the low 12 id bits in LDS (two stable 6-bit ballot passes), runs a
 //    segmented scan of the transition functions, and chains the dense per-id state of
@@ -12,10 +13,9 @@
 //    carry 20 ids each (3-bit codes: a transition function of the 7-element monoid,
 //    or a status) plus their own readiness flag.  The result byte of every word goes
 //    back to its position in the partitioned order.
-// 3. replay: each tile of the original order recomputes the partition ranks of its
-//    words (the same ballots), gathers their result bytes from the partitioned order,
-//    and hands them to the consumer in program order (status bytes and violation
-//    compaction for a trace; the translated events for declarations).
+// 3. replay: every word's result byte is gathered through its destination into
+//    program order and handed to the consumer (status bytes and violation compaction
+//    for a trace; the pre-statuses of the declarations for a translation).
 #include "bucket.h"
 #include "device.h"
 #include "internal.h"
@@ -357,14 +357,14 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restri
 // Workgroup j partitions the tiles of histogram parts [j * HIST_SPLIT, (j + 1) *
 // HIST_SPLIT) in order, keeping the running
 // global start of every bucket in LDS (from the column scan): no look-back, no tickets.
-// The start of each bucket's run in every tile is stored as row `tile` of tpre for the
-// replay.
+// Every word's position in the partitioned order is stored at its own index in dstidx
+// for the replay.
 template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
                                                      int bits, const uint64_t *__restrict__ base,
                                                      const uint32_t *__restrict__ gpre, uint32_t nranges,
                                                      uint32_t nrows,
-                                                     uint32_t *__restrict__ dst, uint32_t *__restrict__ tpre,
+                                                     uint32_t *__restrict__ dst, uint32_t *__restrict__ dstidx,
                                                      uint64_t ntiles)
 {
     __shared__ uint32_t s_words[PTILE];
@@ -429,7 +429,6 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
                 if (b < nb) {
                     s_dstart[b] = ex;
                     const uint32_t r = s_run[b];
-                    tpre[tile * nb + b] = r;
                     s_gbase[b] = (int64_t)r - (int64_t)ex;
                     s_run[b] = r + v[k];
                 }
@@ -440,8 +439,10 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
 #pragma unroll
         for (int j = 0; j < P_ITEMS; j++) {
             uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
-            if (((valid >> j) & 1u) && li < PTILE)
+            if (((valid >> j) & 1u) && li < PTILE) {
                 s_words[li] = w[j];
+                dstidx[wb + (uint64_t)j * WAVE + lane] = (uint32_t)(s_gbase[d[j]] + li);
+            }
         }
         __syncthreads();
         uint64_t vn = n - tbase < (uint64_t)PTILE ? n - tbase : (uint64_t)PTILE;
@@ -748,70 +749,57 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
 }
 
 // ----------------------------------------------------------------------------------
-// 3. replay: partition ranks again, gather result bytes into program order
+// 3. replay: result bytes gathered from the partitioned order into program order,
+// through the destination index the partition stored for every word
 // ----------------------------------------------------------------------------------
-template <class SRC>
-__device__ __forceinline__ void replay_tile(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids, int bits,
-                                            const uint32_t *__restrict__ tpre,
-                                            const uint8_t *__restrict__ res, uint32_t tile, uint8_t *s_res,
-                                            uint32_t *s_cnt, uint32_t *s_tmp, int64_t *s_off, uint32_t *s_w)
+// result bytes of words [i0, i0 + 16) (the part below n), packed 4 to a word; indices
+// past n - 1 (none for consistent counts) are clamped into the result array
+__device__ __forceinline__ void gather16(const uint32_t *__restrict__ dstidx, const uint8_t *__restrict__ res,
+                                         uint64_t n, uint64_t i0, uint32_t (&q)[4])
 {
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    const uint32_t nb = 1u << bits;
-    const uint64_t tbase = (uint64_t)tile * PTILE;
-    // per-wave counters live at [wave * MAX_BUCKETS + bucket]
-    for (uint32_t i = tid; i < 4 * nb; i += BLOCK)
-        s_cnt[(i / nb) * MAX_BUCKETS + (i % nb)] = 0;
-    __syncthreads();
-    uint32_t w[P_ITEMS], d[P_ITEMS], rank[P_ITEMS];
-    uint32_t valid = 0;
-    const uint64_t wb = tbase + (uint64_t)wave * WAVE * P_ITEMS;
+    uint32_t idx[16];
+    if (i0 + 16 <= n) {
+        const uint4 *v = reinterpret_cast<const uint4 *>(dstidx + i0);
 #pragma unroll
-    for (int j = 0; j < P_ITEMS; j++) {
-        uint64_t g = wb + (uint64_t)j * WAVE + lane;
-        w[j] = src[g < n ? g : n - 1]; // clamped: a load for every lane, no branch
-        valid |= (g < n ? 1u : 0u) << j;
-        d[j] = SRC::key(w[j], n_ids) >> LBITS;
-    }
-    if (tbase + PTILE <= n)
-        rank_digits<P_ITEMS, MAX_BUCKETS, false>(d, valid, bits, rank, s_cnt, wave);
-    else
-        rank_digits<P_ITEMS, MAX_BUCKETS, true>(d, valid, bits, rank, s_cnt, wave);
-    __syncthreads();
-    for (uint32_t b = tid; b < nb; b += BLOCK) {
-        uint32_t tc = 0;
-        for (uint32_t q = 0; q < 4; q++) {
-            uint32_t c = s_cnt[q * MAX_BUCKETS + b];
-            s_cnt[q * MAX_BUCKETS + b] = tc;
-            tc += c;
+        for (int k = 0; k < 4; k++) {
+            const uint4 x = v[k];
+            idx[4 * k] = x.x;
+            idx[4 * k + 1] = x.y;
+            idx[4 * k + 2] = x.z;
+            idx[4 * k + 3] = x.w;
         }
-        (void)tc;
-        s_off[b] = (int64_t)tpre[(uint64_t)tile * nb + b];
-    }
-    __syncthreads();
+    } else {
 #pragma unroll
-    for (int j = 0; j < P_ITEMS; j++) {
-        if ((valid >> j) & 1u) {
-            int64_t pos = s_off[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
-            uint32_t tp = wave * WAVE * P_ITEMS + j * WAVE + lane;
-            s_res[tp] = (pos >= 0 && (uint64_t)pos < n) ? res[pos] : (uint8_t)0;
-            if (s_w)
-                s_w[tp] = w[j];
-        }
+        for (int k = 0; k < 16; k++)
+            idx[k] = i0 + k < n ? dstidx[i0 + k] : 0u;
     }
-    __syncthreads();
-    (void)s_tmp;
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+        q[k] = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const uint64_t j = idx[k] < n ? idx[k] : n - 1;
+        const uint32_t byte = i0 + k < n ? (uint32_t)res[j] : 0u;
+        q[k >> 2] |= byte << (8 * (k & 3));
+    }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restrict__ src, uint64_t n,
-                                                         uint32_t n_ids, int bits, const uint32_t *__restrict__ tpre,
+__device__ __forceinline__ void store16(uint8_t *__restrict__ out, uint64_t n, uint64_t i0, const uint32_t (&q)[4])
+{
+    if (i0 + 16 <= n) {
+        *reinterpret_cast<uint4 *>(out + i0) = make_uint4(q[0], q[1], q[2], q[3]);
+    } else {
+        for (int k = 0; k < 16; k++)
+            if (i0 + k < n)
+                out[i0 + k] = (uint8_t)(q[k >> 2] >> (8 * (k & 3)));
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restrict__ dstidx, uint64_t n,
                                                          const uint8_t *__restrict__ res, uint8_t *__restrict__ status,
                                                          uint32_t *__restrict__ viol, uint64_t *__restrict__ lbc,
                                                          uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
 {
-    __shared__ __align__(16) uint8_t s_res[PTILE];
-    __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
-    __shared__ int64_t s_off[MAX_BUCKETS];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_excl;
@@ -820,27 +808,18 @@ __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restr
         const uint32_t tile = take_ticket(ticket, &s_tile);
         if (tile >= ntiles)
             break;
-        replay_tile<EventWords>(src, n, n_ids, bits, tpre, res, tile, s_res, s_cnt, nullptr, s_off, nullptr);
         const uint64_t tbase = (uint64_t)tile * PTILE;
         const uint64_t my0 = tbase + (uint64_t)tid * 16;
         // 16 consecutive status bytes per thread
         uint32_t q[4];
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-            q[k] = reinterpret_cast<const uint32_t *>(s_res)[tid * 4 + k];
+        gather16(dstidx, res, n, my0, q);
+        store16(status, n, my0, q);
         uint32_t flags = 0;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
             uint32_t byte = (q[k >> 2] >> (8 * (k & 3))) & 0xFFu;
             if (my0 + k < n)
                 flags |= ((byte >> 7) & 1u) << k;
-        }
-        if (my0 + 16 <= n) {
-            *reinterpret_cast<uint4 *>(status + my0) = make_uint4(q[0], q[1], q[2], q[3]);
-        } else {
-            for (int k = 0; k < 16; k++)
-                if (my0 + k < n)
-                    status[my0 + k] = s_res[tid * 16 + k];
         }
         uint32_t c = __builtin_popcount(flags);
         uint32_t inc = wave_scan_add(c, lane);
@@ -871,6 +850,17 @@ __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restr
             o++;
         }
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_replay_bytes(const uint32_t *__restrict__ dstidx, uint64_t n,
+                                                        const uint8_t *__restrict__ res, uint8_t *__restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * BLOCK * 16;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * BLOCK + threadIdx.x) * 16; i0 < n; i0 += stride) {
+        uint32_t q[4];
+        gather16(dstidx, res, n, i0, q);
+        store16(out, n, i0, q);
     }
 }
 
@@ -910,10 +900,10 @@ static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
     L.base = (uint64_t *)take((MAX_BUCKETS + 1) * 8);
     L.tbase = (uint32_t *)take((MAX_BUCKETS + 1) * 4);
     L.order = (uint32_t *)take(btiles * 4);
-    L.tpre = (uint32_t *)take(ptiles * nb * 4);
     L.lbv = (uint64_t *)take(btiles * LB_WORDS * 8);
     L.lbc = (uint64_t *)take(ptiles * 8);
     L.part = (uint32_t *)take((n ? n : 1) * 4);
+    L.dstidx = (uint32_t *)take((n ? n : 1) * 4);
     L.res = (uint8_t *)take(n ? n : 1);
     L.ptiles = ptiles;
     L.btiles_max = btiles;
@@ -974,7 +964,7 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     if (L.nb > 1) {
         ProfScope p(s, "partition");
         k_partition<SRC><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, nrows, L.part,
-                                                   L.tpre, L.ptiles);
+                                                   L.dstidx, L.ptiles);
         part = L.part;
         res = L.res;
     }
@@ -1010,33 +1000,8 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     launch_fill_u32(ctl->tickets[10], 0, TICKET_WORDS, s);
     ProfScope p(s, "replay_status");
     const unsigned grid = resident_grid((const void *)k_replay_status, L.ptiles);
-    k_replay_status<<<grid, BLOCK, 0, s>>>(events, n, n_ids, L.bits, L.tpre, L.res, status, viol, L.lbc,
-                                           ctl->tickets[10], L.ptiles, ctl);
-}
-
-__global__ __launch_bounds__(BLOCK) void k_replay_bytes(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
-                                                        int bits, const uint32_t *__restrict__ tpre,
-                                                        const uint8_t *__restrict__ res, uint8_t *__restrict__ out,
-                                                        uint64_t ntiles)
-{
-    __shared__ __align__(16) uint8_t s_res[PTILE];
-    __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
-    __shared__ int64_t s_off[MAX_BUCKETS];
-    __shared__ uint32_t s_tmp[BLOCK / WAVE];
-    const uint32_t tid = threadIdx.x;
-    // tiles are independent (no look-back): a plain grid-stride loop
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        replay_tile<DeclWords>(src, n, n_ids, bits, tpre, res, tile, s_res, s_cnt, s_tmp, s_off, nullptr);
-        const uint64_t my0 = (uint64_t)tile * PTILE + (uint64_t)tid * 16;
-        if (my0 + 16 <= n) {
-            *reinterpret_cast<uint4 *>(out + my0) = *reinterpret_cast<const uint4 *>(s_res + tid * 16);
-        } else {
-            for (int k = 0; k < 16; k++)
-                if (my0 + k < n)
-                    out[my0 + k] = s_res[tid * 16 + k];
-        }
-        __syncthreads();
-    }
+    k_replay_status<<<grid, BLOCK, 0, s>>>(L.dstidx, n, L.res, status, viol, L.lbc, ctl->tickets[10], L.ptiles,
+                                           ctl);
 }
 
 void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,
@@ -1049,8 +1014,8 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
     if (L.nb == 1)
         return;
     ProfScope p(s, "replay_bytes");
-    const unsigned grid = resident_grid((const void *)k_replay_bytes, L.ptiles);
-    k_replay_bytes<<<grid, BLOCK, 0, s>>>(decls, n_decl, n_vars, L.bits, L.tpre, L.res, pre, L.ptiles);
+    const unsigned grid = resident_grid((const void *)k_replay_bytes, ceil_div(n_decl, (uint64_t)BLOCK * 16));
+    k_replay_bytes<<<grid, BLOCK, 0, s>>>(L.dstidx, n_decl, L.res, pre);
 }
 
 } // namespace vc

@@ -65,7 +65,7 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
     TranslateState &tr = *t->tr;
     int r;
     uint64_t n_decl = tr.n_decl, n_comp = tr.n_comp;
-    const bool bucketed = tr.n_vars <= bucket_max_ids() && !getenv("VC_GENERAL_PATH");
+    const bool bucketed = tr.n_vars <= bucket_max_ids() && n_decl <= 0xFFFFFFFFull && !getenv("VC_GENERAL_PATH");
     // canonical bodies with the check requested: the check is fused into the emission
     tr.fused = tr.check && !tr.body_off && bucketed && !getenv("VC_UNFUSED");
     // ... and the positions are found by the emission itself when the largest possible
