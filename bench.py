@@ -118,10 +118,10 @@ def wl_components(args, V, ctx, stream):
     # (unit: declarations for the declaration passes, translated events for the emitter)
     kernel_bytes = {
         "bucket_hist": (4 * nd + 4 * (nd // 64), nd, "declaration"),      # words; chunk event counts
-        "partition": (8 * nd, nd, "declaration"),                        # words in, words out
+        "partition": (12 * nd, nd, "declaration"),                       # words in; words, destinations out
         "bucket_scan": (5 * nd + n_vars, nd, "declaration"),             # words in, pre-status out, final
-        "replay_bytes": (6 * nd, nd, "declaration"),                     # words, gathered byte, byte out
-        "translate_emit_wave": (5 * nd + 8 * (n_comp + 1) + 5 * n_ev, n_ev, "translated event"),
+        # declarations, their destinations and gathered pre-statuses, offsets; events and status bytes out
+        "translate_emit_wave": (9 * nd + 8 * (n_comp + 1) + 5 * n_ev, n_ev, "translated event"),
     }
     cfg = {"workload": f"components-2^{args.comp_log2}", "n_components": n_comp, "n_vars": n_vars,
            "n_declarations": nd, "n_events": int(n_ev), "violations": int(viol)}
@@ -161,9 +161,9 @@ def wl_plain(args, V, ctx, stream, n=None, n_ids=64):
     kernel_bytes = {
         "small_check": (5 * n + 4 * viol + n_ids, n, "event"),              # events in, status out, violations
         "bucket_hist": (4 * n, n, "event"),
-        "partition": (8 * n, n, "event"),
+        "partition": (12 * n, n, "event"),                                  # words in; words, destinations out
         "bucket_scan": (5 * n + n_ids, n, "event"),
-        "replay_status": (6 * n + 4 * viol, n, "event"),                    # words, gathered byte, status, violations
+        "replay_status": (6 * n + 4 * viol, n, "event"),                    # destinations, gathered byte, status, violations
     }
     cfg = {"workload": f"plain-{n}x{n_ids}", "n_events": n, "n_ids": n_ids, "violations": int(viol)}
     return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te),

@@ -53,4 +53,15 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
 void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,
                             void *scratch, Control *ctl, hipStream_t s, int cu, uint32_t *chunk_sum = nullptr);
 
+// the same without the replay into program order: the pre-status of declaration d is
+// res[dstidx[d]], or pre[d] (res = pre, dstidx = null) when the variables form one
+// bucket.  res and dstidx point into `scratch`.
+struct DeclPre {
+    const uint8_t *res;
+    const uint32_t *dstidx;
+};
+DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre,
+                                           uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
+                                           uint32_t *chunk_sum);
+
 } // namespace vc

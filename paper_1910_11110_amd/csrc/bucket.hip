@@ -1018,4 +1018,17 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
     k_replay_bytes<<<grid, BLOCK, 0, s>>>(L.dstidx, n_decl, L.res, pre);
 }
 
+DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre,
+                                           uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
+                                           uint32_t *chunk_sum)
+{
+    if (n_decl == 0)
+        return DeclPre{pre, nullptr};
+    BucketLayout L = bucket_layout(scratch, n_decl, n_vars);
+    partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu, chunk_sum);
+    if (L.nb == 1)
+        return DeclPre{pre, nullptr};
+    return DeclPre{L.res, L.dstidx};
+}
+
 } // namespace vc

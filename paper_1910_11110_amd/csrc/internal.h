@@ -129,10 +129,12 @@ void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, cons
 // the same with the positions found on the device (no per-component counts): the events
 // before a tile come from chunk_prefix, the exclusive prefix of the per-chunk event counts
 // (HCHUNK declarations a chunk); malformed component offsets go to tr_ctl's error index.
+// The pre-status of declaration d is res[dstidx[d]] (res[d] when dstidx is null).
 // `out` and `status` must hold 5 * n_decl entries (the largest possible length).
 void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
-                                     uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *chunk_prefix,
-                                     uint32_t *out, uint8_t *status, Control *tr_ctl, Control *ctl, hipStream_t s);
+                                     uint32_t n_vars, const uint8_t *res, const uint32_t *dstidx,
+                                     const uint64_t *chunk_prefix, uint32_t *out, uint8_t *status, Control *tr_ctl,
+                                     Control *ctl, hipStream_t s);
 
 // ------------------------------- overlap ------------------------------------------
 struct OverlapSets {

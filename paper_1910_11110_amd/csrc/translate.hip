@@ -607,6 +607,18 @@ struct WaveTile {
     __align__(4) uint8_t start[WDCAP]; // 1 where a non-empty component starts
 };
 
+// pre-status of declaration d: its result byte in the partitioned order, through its
+// destination (clamped; in range for consistent counts), or in program order when
+// there is no destination array (one bucket)
+__device__ __forceinline__ uint32_t pre_status(const uint8_t *__restrict__ res, const uint32_t *__restrict__ dstidx,
+                                               uint64_t n_decl, uint64_t d)
+{
+    if (!dstidx)
+        return res[d];
+    const uint32_t j = dstidx[d];
+    return res[j < n_decl ? j : n_decl - 1];
+}
+
 __device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
 {
     const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
@@ -615,9 +627,9 @@ __device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
 
 __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
-    uint32_t n_vars, const uint8_t *__restrict__ pre_abs, const uint64_t *__restrict__ chunk_prefix,
-    uint32_t *__restrict__ out, uint8_t *__restrict__ status, uint64_t ntiles, Control *ctl,
-    unsigned long long *__restrict__ n_flagged, uint64_t cap)
+    uint32_t n_vars, const uint8_t *__restrict__ res, const uint32_t *__restrict__ dstidx,
+    const uint64_t *__restrict__ chunk_prefix, uint32_t *__restrict__ out, uint8_t *__restrict__ status,
+    uint64_t ntiles, Control *ctl, unsigned long long *__restrict__ n_flagged, uint64_t cap)
 {
     __shared__ WaveTile s_tiles[BLOCK / WAVE];
     const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
@@ -651,7 +663,9 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         // events before the tile: the chunk prefix plus the chunk's declarations before
         // d_lo; and the tile's declarations with their pre-statuses (loads issued together)
         uint64_t base = 0;
-        uint32_t dw[WROUNDS], pr[WROUNDS], sx[WROUNDS];
+        // (the pre-statuses are gathered through the destinations after the arity scan,
+        // which hides the destinations' latency)
+        uint32_t dw[WROUNDS], pr[WROUNDS], sx[WROUNDS], ix[WROUNDS];
         if (d_lo <= n_decl) {
             const uint64_t first = d_lo - d_lo % HCHUNK;
             static_assert(HCHUNK <= WAVE, "one declaration of the chunk per lane");
@@ -661,7 +675,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             for (int k = 0; k < WROUNDS; k++) {
                 const uint32_t i = k * WAVE + lane;
                 dw[k] = i < nd ? decls[d_lo + i] : 0u;
-                pr[k] = i < nd ? pre_abs[d_lo + i] : 0u;
+                ix[k] = i < nd ? (dstidx ? dstidx[d_lo + i] : (uint32_t)(d_lo + i)) : 0u;
             }
             const uint64_t cb = chunk_prefix[d_lo / HCHUNK];
             base = cb + wave_total_u32(pi < d_lo ? decl_arity(pw, n_vars) : 0u);
@@ -686,6 +700,9 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             }
             if (lane == 0)
                 L.scan[nd] = carry;
+#pragma unroll
+            for (int k = 0; k < WROUNDS; k++)
+                pr[k] = k * WAVE + lane < nd ? (uint32_t)res[ix[k] < n_decl ? ix[k] : n_decl - 1] : 0u;
             __builtin_amdgcn_wave_barrier();
             if (lane < nc) {
                 const uint32_t x = L.scan[b - d_lo], y = L.scan[a - d_lo];
@@ -764,7 +781,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             for (uint64_t d = a; d < b; d++) {
                 const uint32_t wd = decls[d];
                 const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
-                emit_decl(wd, n_vars, pre_abs[d], sp, bp, end, out, status, nflag);
+                emit_decl(wd, n_vars, pre_status(res, dstidx, n_decl, d), sp, bp, end, out, status, nflag);
                 sp += slot_arity(mode);
                 bp += body_arity(mode);
             }
@@ -795,15 +812,16 @@ void launch_translate_emit_fused(const uint64_t *comp_off, uint64_t n_comp, cons
 }
 
 void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
-                                     uint32_t n_vars, const uint8_t *pre_abs, const uint64_t *chunk_prefix,
-                                     uint32_t *out, uint8_t *status, Control *tr_ctl, Control *ctl, hipStream_t s)
+                                     uint32_t n_vars, const uint8_t *res, const uint32_t *dstidx,
+                                     const uint64_t *chunk_prefix, uint32_t *out, uint8_t *status, Control *tr_ctl,
+                                     Control *ctl, hipStream_t s)
 {
     if (!n_comp)
         return;
     const uint64_t tiles = ceil_div(n_comp, WCOMPS);
     ProfScope prof_(s, "translate_emit_wave");
     k_translate_emit_wave<<<resident_grid((const void *)k_translate_emit_wave, ceil_div(tiles, BLOCK / WAVE)), BLOCK, 0,
-                            s>>>(comp_off, n_comp, decls, n_decl, n_vars, pre_abs, chunk_prefix, out, status, tiles,
+                            s>>>(comp_off, n_comp, decls, n_decl, n_vars, res, dstidx, chunk_prefix, out, status, tiles,
                                  tr_ctl, &ctl->n_flagged, 5 * n_decl);
 }
 

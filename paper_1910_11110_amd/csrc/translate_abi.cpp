@@ -74,6 +74,9 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
     if (tr.device_sized) {
         const uint64_t cap = 5 * n_decl ? 5 * n_decl : 1;
         const uint64_t nchunks = ceil_div(n_decl, (uint64_t)HCHUNK);
+        // the bucket scan's partitioned results stay in its part of the scratch until the
+        // emission has read them: the chunk scan works behind it
+        const size_t bucket_bytes = (bucket_scratch_bytes(n_decl, tr.n_vars) + 255) / 256 * 256;
         hipError_t e;
         // per-chunk event counts and their exclusive prefix (in the count and position
         // buffers, which this way of placing the events does not otherwise use)
@@ -81,8 +84,7 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
             (r = devbuf_reserve(tr.pos, (nchunks + 1) * 8)) != VC_OK ||
             (r = devbuf_reserve(tr.pre_abs, n_decl ? n_decl : 1)) != VC_OK ||
             (r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK ||
-            (r = devbuf_reserve(tr.scratch, std::max(bucket_scratch_bytes(n_decl, tr.n_vars),
-                                                     excl_scan_scratch_bytes(nchunks)))) != VC_OK ||
+            (r = devbuf_reserve(tr.scratch, bucket_bytes + excl_scan_scratch_bytes(nchunks))) != VC_OK ||
             (r = devbuf_reserve(t->status, cap)) != VC_OK || (r = devbuf_reserve(t->fin, 2 * (size_t)tr.n_vars)) != VC_OK ||
             (r = devbuf_reserve(t->viol, cap * 4)) != VC_OK ||
             (r = devbuf_reserve(t->scratch, compact_scratch_bytes(cap))) != VC_OK)
@@ -100,12 +102,15 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         launch_reset_control(tr.ctl, s);
         launch_reset_control(t->ctl, s);
         launch_fill_u8((uint8_t *)tr.final_abs.p, 1, tr.n_vars, s);
-        launch_bucket_decl_pre(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, (uint8_t *)tr.final_abs.p,
-                               tr.scratch.p, tr.ctl, s, t->ctx->cu_count, (uint32_t *)tr.cnt.p);
+        const DeclPre pre =
+            launch_bucket_decl_pre_partitioned(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
+                                               (uint8_t *)tr.final_abs.p, tr.scratch.p, tr.ctl, s, t->ctx->cu_count,
+                                               (uint32_t *)tr.cnt.p);
         // the translated length lands in tr.ctl->n_out
         launch_excl_scan((uint32_t *)tr.cnt.p, nchunks, (uint64_t *)tr.pos.p,
-                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), tr.scratch.p, tr.ctl->tickets[4], s);
-        launch_translate_emit_fused_dev(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
+                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), (char *)tr.scratch.p + bucket_bytes,
+                         tr.ctl->tickets[4], s);
+        launch_translate_emit_fused_dev(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, pre.res, pre.dstidx,
                                         (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, tr.ctl, t->ctl, s);
         // final store: each real variable ends where its abstract variable ends
         uint8_t *fin = (uint8_t *)t->fin.p;
