@@ -55,7 +55,8 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
 
 // the same without the replay into program order: the pre-status of declaration d is
 // res[dstidx[d]], or pre[d] (res = pre, dstidx = null) when the variables form one
-// bucket.  res and dstidx point into `scratch`.
+// bucket.  res and dstidx point into `scratch`.  final_out (2 * n_vars bytes,
+// pre-filled) receives the final statuses twice: at [0, n_vars) and [n_vars, 2 n_vars).
 struct DeclPre {
     const uint8_t *res;
     const uint32_t *dstidx;

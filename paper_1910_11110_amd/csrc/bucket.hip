@@ -380,6 +380,19 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
     uint64_t t0, t1;
     split_range(ntiles, (uint64_t)nranges * HIST_SPLIT, (uint64_t)blockIdx.x * HIST_SPLIT, t0, t1);
     t1 = ((uint64_t)blockIdx.x + 1) * HIST_SPLIT * ntiles / ((uint64_t)nranges * HIST_SPLIT);
+    // the words of the next tile are loaded while this one is ranked and written
+    // (clamped indices: a load for every lane, no branch)
+    uint32_t nxt[P_ITEMS];
+    auto load_tile = [&](uint64_t tile) {
+        const uint64_t wb = tile * PTILE + (uint64_t)wave * WAVE * P_ITEMS;
+#pragma unroll
+        for (int j = 0; j < P_ITEMS; j++) {
+            const uint64_t g = wb + (uint64_t)j * WAVE + lane;
+            nxt[j] = src[g < n ? g : n - 1];
+        }
+    };
+    if (t0 < t1)
+        load_tile(t0);
     for (uint64_t tile = t0; tile < t1; tile++) {
         const uint64_t tbase = tile * PTILE;
         // per-wave counters live at [wave * MAX_BUCKETS + bucket]
@@ -392,10 +405,12 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
 #pragma unroll
         for (int j = 0; j < P_ITEMS; j++) {
             uint64_t g = wb + (uint64_t)j * WAVE + lane;
-            w[j] = src[g < n ? g : n - 1]; // clamped: a load for every lane, no branch
+            w[j] = nxt[j];
             valid |= (g < n ? 1u : 0u) << j;
             d[j] = SRC::key(w[j], n_ids) >> LBITS;
         }
+        if (tile + 1 < t1)
+            load_tile(tile + 1);
         if (tbase + PTILE <= n)
             rank_digits<P_ITEMS, MAX_BUCKETS, false>(d, valid, bits, rank, s_cnt, wave);
         else
@@ -475,7 +490,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                                                        uint32_t nb, const uint64_t *__restrict__ base,
                                                        const uint32_t *__restrict__ tbase,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ out,
-                                                       uint8_t *__restrict__ final_out, uint64_t *__restrict__ lbv,
+                                                       uint8_t *__restrict__ final_out, uint32_t final_dup,
+                                                       uint64_t *__restrict__ lbv,
                                                        uint32_t *__restrict__ ticket,
                                                        const uint32_t *__restrict__ order)
 {
@@ -715,8 +731,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             if (last_tile && final_out) {
                 for (int k = 0; k < 20; k++) {
                     const uint32_t key = b * LOC + wi * 20 + k;
-                    if (wi * 20 + k < LOC && key < n_ids)
-                        final_out[key] = (uint8_t)(((inc.x >> k) & 1u) | (((inc.y >> k) & 1u) << 1));
+                    if (wi * 20 + k < LOC && key < n_ids) {
+                        const uint8_t fv = (uint8_t)(((inc.x >> k) & 1u) | (((inc.y >> k) & 1u) << 1));
+                        final_out[key] = fv;
+                        if (final_dup)
+                            final_out[final_dup + key] = fv;
+                    }
                 }
             }
         }
@@ -927,14 +947,14 @@ BucketLayout bucket_layout(void *scratch, uint64_t n, uint32_t n_ids)
 uint32_t bucket_max_ids() { return (uint32_t)MAX_BUCKETS * LOC; }
 
 // histogram, partition and per-bucket scan; result bytes land in L.res (partitioned
-// order), or in `direct_out` (program order) when everything is one bucket
+// order), or in `direct_out` (program order) when everything is one bucket.  The final
+// statuses go to final_out, and also to final_out + final_dup when final_dup > 0.
 template <class SRC>
 static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, const uint8_t *init, int mode,
                                uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
-                               hipStream_t s, int cu, uint32_t *chunk_sum = nullptr)
+                               hipStream_t s, int cu, uint32_t *chunk_sum = nullptr, uint32_t final_dup = 0)
 {
-    launch_fill_u64(L.lbv, 0, L.btiles_max * LB_WORDS, s);
-    launch_fill_u32(ctl->tickets[9], 0, TICKET_WORDS, s);
+    launch_clear_lookback(L.lbv, L.btiles_max * LB_WORDS, ctl->tickets[9], s);
     // static tile ranges shared by the histogram and the partition: as many ranges as
     // partition workgroups are resident at once
     // (the histogram splits every range in HIST_SPLIT, for more workgroups in flight)
@@ -978,10 +998,10 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
                                             btiles);
         if (mode == BK_PRE)
             k_bucket_scan<BK_PRE, SRC><<<grid, BLOCK, 0, s>>>(part, n_ids, L.nb, L.base, L.tbase, init, res,
-                                                              final_out, L.lbv, ctl->tickets[9], L.order);
+                                                              final_out, final_dup, L.lbv, ctl->tickets[9], L.order);
         else
             k_bucket_scan<BK_STATUS, SRC><<<grid, BLOCK, 0, s>>>(part, n_ids, L.nb, L.base, L.tbase, init, res,
-                                                                 final_out, L.lbv, ctl->tickets[9], L.order);
+                                                                 final_out, final_dup, L.lbv, ctl->tickets[9], L.order);
     }
 }
 
@@ -996,8 +1016,7 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
         launch_compact(status, n, viol, L.lbc, ctl, s);
         return;
     }
-    launch_fill_u64(L.lbc, 0, L.ptiles, s);
-    launch_fill_u32(ctl->tickets[10], 0, TICKET_WORDS, s);
+    launch_clear_lookback(L.lbc, L.ptiles, ctl->tickets[10], s);
     ProfScope p(s, "replay_status");
     const unsigned grid = resident_grid((const void *)k_replay_status, L.ptiles);
     k_replay_status<<<grid, BLOCK, 0, s>>>(L.dstidx, n, L.res, status, viol, L.lbc, ctl->tickets[10], L.ptiles,
@@ -1025,7 +1044,8 @@ DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_dec
     if (n_decl == 0)
         return DeclPre{pre, nullptr};
     BucketLayout L = bucket_layout(scratch, n_decl, n_vars);
-    partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu, chunk_sum);
+    partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu, chunk_sum,
+                                  n_vars);
     if (L.nb == 1)
         return DeclPre{pre, nullptr};
     return DeclPre{L.res, L.dstidx};

@@ -100,8 +100,7 @@ void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scr
         return;
     uint64_t tiles = ceil_div(n, CTILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
-    launch_fill_u64(lb, 0, tiles, s);
-    launch_fill_u32(ctl->tickets[2], 0, TICKET_WORDS, s);
+    launch_clear_lookback(lb, tiles, ctl->tickets[2], s);
     {
         ProfScope prof_(s, "compact");
         k_compact<<<resident_grid((const void *)k_compact, tiles), BLOCK, 0, s>>>(status, n, viol, lb, ctl->tickets[2],

@@ -49,7 +49,10 @@ constexpr size_t CONTROL_BYTES = (sizeof(Control) + 255) / 256 * 256;
 void launch_fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t s);
 void launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s);
 void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
-void launch_reset_control(Control *c, hipStream_t s);
+// resets c (and c2 when given) to the start-of-run state
+void launch_reset_control(Control *c, hipStream_t s, Control *c2 = nullptr);
+// zeroes n look-back words and the ticket counters of one kernel (one launch)
+void launch_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket, hipStream_t s);
 
 // exclusive scan of n uint32 counts into n+1 uint64 offsets (out[n] = total, also
 // stored to *total when non-null); scratch of excl_scan_scratch_bytes(n)

@@ -143,8 +143,7 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
         return;
     uint64_t tiles = ceil_div(n, SCAN_TILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
-    launch_fill_u64(lb, 0, tiles, s);
-    launch_fill_u32(ctl->tickets[1], 0, TICKET_WORDS, s);
+    launch_clear_lookback(lb, tiles, ctl->tickets[1], s);
     const unsigned grid = resident_grid(mode == SCAN_STATUS ? (const void *)k_segscan<SCAN_STATUS>
                                                             : (const void *)k_segscan<SCAN_PRE>,
                                         tiles, grid_cap);

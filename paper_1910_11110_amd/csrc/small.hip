@@ -260,8 +260,7 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
     uint64_t tiles = ceil_div(n, STILE);
     uint64_t *lbv = reinterpret_cast<uint64_t *>(scratch);
     uint64_t *lbc = lbv + tiles * SPW;
-    launch_fill_u64(lbv, 0, tiles * (SPW + 1), s);
-    launch_fill_u32(ctl->tickets[7], 0, TICKET_WORDS, s);
+    launch_clear_lookback(lbv, tiles * (SPW + 1), ctl->tickets[7], s);
     const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap);
     ProfScope prof_(s, "small_check");
     k_small_check<<<grid, BLOCK, 0, s>>>(events, n, n_ids, init, status, final_out, viol, lbv, lbc, ctl->tickets[7],

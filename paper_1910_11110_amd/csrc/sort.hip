@@ -45,8 +45,23 @@ __global__ void k_fill_u8(uint8_t *p, uint8_t v, size_t n)
         p[i] = v;
 }
 
-__global__ void k_reset_control(Control *c)
+// zeroes a look-back array and one set of tile ticket counters
+__global__ void k_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket)
 {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        lb[i] = 0;
+    if (blockIdx.x == 0)
+        for (uint32_t t = threadIdx.x; t < TICKET_WORDS; t += blockDim.x)
+            ticket[t] = 0;
+}
+
+// workgroup k resets control block k (c, then c2)
+__global__ void k_reset_control(Control *c, Control *c2)
+{
+    if (blockIdx.x == 1)
+        c = c2;
     uint32_t *w = reinterpret_cast<uint32_t *>(c);
     for (uint32_t t = threadIdx.x; t < sizeof(Control) / 4; t += blockDim.x)
         w[t] = 0;
@@ -260,7 +275,15 @@ void launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s)
         k_fill_u8<<<grid_for(n, 16), BLOCK, 0, s>>>(p, v, n);
 }
 
-void launch_reset_control(Control *c, hipStream_t s) { k_reset_control<<<1, 256, 0, s>>>(c); }
+void launch_reset_control(Control *c, hipStream_t s, Control *c2)
+{
+    k_reset_control<<<c2 ? 2 : 1, 256, 0, s>>>(c, c2);
+}
+
+void launch_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket, hipStream_t s)
+{
+    k_clear_lookback<<<grid_for(n ? n : 1, 4), BLOCK, 0, s>>>(lb, n, ticket);
+}
 
 void launch_make_items_events(const uint32_t *events, uint64_t n, uint32_t n_ids, uint64_t *items, Control *ctl,
                               hipStream_t s, uint32_t key_base, uint64_t payload_base)
@@ -297,9 +320,8 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
     }
     uint64_t *src = a, *dst = b;
     for (int p = 0; p < passes; p++) {
-        launch_fill_u64(lb, 0, tiles * RADIX, s);
         uint32_t *ticket = ctl->tickets[0];
-        launch_fill_u32(ticket, 0, TICKET_WORDS, s);
+        launch_clear_lookback(lb, tiles * RADIX, ticket, s);
         unsigned grid = resident_grid((const void *)k_sort_pass, tiles, grid_cap);
         {
             ProfScope prof_(s, "sort_pass");

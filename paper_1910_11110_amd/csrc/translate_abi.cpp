@@ -83,7 +83,6 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         if ((r = devbuf_reserve(tr.cnt, (nchunks ? nchunks : 1) * 4)) != VC_OK ||
             (r = devbuf_reserve(tr.pos, (nchunks + 1) * 8)) != VC_OK ||
             (r = devbuf_reserve(tr.pre_abs, n_decl ? n_decl : 1)) != VC_OK ||
-            (r = devbuf_reserve(tr.final_abs, tr.n_vars)) != VC_OK ||
             (r = devbuf_reserve(tr.scratch, bucket_bytes + excl_scan_scratch_bytes(nchunks))) != VC_OK ||
             (r = devbuf_reserve(t->status, cap)) != VC_OK || (r = devbuf_reserve(t->fin, 2 * (size_t)tr.n_vars)) != VC_OK ||
             (r = devbuf_reserve(t->viol, cap * 4)) != VC_OK ||
@@ -99,23 +98,20 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
             t->own_events = true;
         }
         t->n = 0; // set from the device when the work is collected
-        launch_reset_control(tr.ctl, s);
-        launch_reset_control(t->ctl, s);
-        launch_fill_u8((uint8_t *)tr.final_abs.p, 1, tr.n_vars, s);
+        launch_reset_control(tr.ctl, s, t->ctl);
+        // final store: each real variable ends where its abstract variable ends (both
+        // halves written by the scan; variables it never touches keep (V,I))
+        uint8_t *fin = (uint8_t *)t->fin.p;
+        launch_fill_u8(fin, 1, 2 * (size_t)tr.n_vars, s);
         const DeclPre pre =
-            launch_bucket_decl_pre_partitioned(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p,
-                                               (uint8_t *)tr.final_abs.p, tr.scratch.p, tr.ctl, s, t->ctx->cu_count,
-                                               (uint32_t *)tr.cnt.p);
+            launch_bucket_decl_pre_partitioned(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, fin, tr.scratch.p,
+                                               tr.ctl, s, t->ctx->cu_count, (uint32_t *)tr.cnt.p);
         // the translated length lands in tr.ctl->n_out
         launch_excl_scan((uint32_t *)tr.cnt.p, nchunks, (uint64_t *)tr.pos.p,
                          reinterpret_cast<uint64_t *>(&tr.ctl->n_out), (char *)tr.scratch.p + bucket_bytes,
                          tr.ctl->tickets[4], s);
         launch_translate_emit_fused_dev(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, pre.res, pre.dstidx,
                                         (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, tr.ctl, t->ctl, s);
-        // final store: each real variable ends where its abstract variable ends
-        uint8_t *fin = (uint8_t *)t->fin.p;
-        (void)hipMemcpyAsync(fin, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
-        (void)hipMemcpyAsync(fin + tr.n_vars, tr.final_abs.p, tr.n_vars, hipMemcpyDeviceToDevice, s);
         launch_compact((uint8_t *)t->status.p, cap, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s,
                        &t->ctl->n_flagged, &tr.ctl->n_out);
         return VC_OK;

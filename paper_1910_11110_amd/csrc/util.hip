@@ -121,8 +121,7 @@ void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *t
     }
     uint64_t tiles = ceil_div(n, XTILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
-    launch_fill_u64(lb, 0, tiles, s);
-    launch_fill_u32(ticket, 0, TICKET_WORDS, s);
+    launch_clear_lookback(lb, tiles, ticket, s);
     {
         ProfScope prof_(s, "excl_scan");
         k_excl_scan<<<resident_grid((const void *)k_excl_scan, tiles), BLOCK, 0, s>>>(in, n, out, total, lb, ticket,
