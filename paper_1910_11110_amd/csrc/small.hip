@@ -1,16 +1,21 @@
 // small.hip -- single-pass check of a trace over at most 64 variables (gfx950).
 //
-// No sort: the trace is cut into tiles of 4096 events in program order; each thread
-// owns 16 consecutive events of a tile and keeps, per variable, the composition of
-// its own events (a private 64-entry table of transition functions in LDS).  A
-// per-variable scan across the 256 threads of the tile (64 lanes = 64 variables)
-// turns the tables into exclusive prefixes and yields the tile's aggregate per
-// variable.  Tiles chain their per-variable states with a decoupled look-back: four
-// self-flagged 64-bit words of 20 variables each, the functions as bit planes, one wave
-// per word folding 64 predecessors a round.  Each thread then replays its 16
-// events from its entering statuses and writes its 16 status bytes as one 16-byte
-// store; flagged events are compacted in the same kernel (a second look-back on the
-// count), and the last tile writes the final statuses.
+// No sort.  The trace is cut into tiles of 4096 events in program order; thread t of
+// a tile owns events [16t, 16t + 16).  The state of all 64 variables is held as 64-bit
+// bit planes (bit v = variable v): a transition function of the 7-element monoid per
+// variable as three planes (T, X, Y), a status as two planes (C = CPU copy valid,
+// G = GPU copy valid).
+//   1. Each thread composes its 16 events into its own function planes (an event
+//      changes one bit of each plane).
+//   2. A wave scan of the function planes (DPP row shifts and row broadcasts) and the
+//      wave totals give every thread the composition of the tile's events before it.
+//   3. The tiles chain their statuses with a decoupled look-back on the tile's
+//      function: four self-flagged 64-bit words of 20 variables each (one wave per
+//      word).
+//   4. Each thread applies its prefix to the statuses entering the tile and replays its
+//      16 events on status planes: status bytes (one 16-byte store per thread), the
+//      flagged events compacted in the same kernel (a second look-back on the count),
+//      and the final statuses from the last tile.
 #include "device.h"
 #include "internal.h"
 #include "prof.h"
@@ -23,10 +28,77 @@ constexpr EffectTable TABLE = make_table();
 constexpr int SK = 64;               // variables
 constexpr int SE = 16;               // events per thread
 constexpr int STILE = BLOCK * SE;    // events per tile
-constexpr int SROW = SK + 1;         // padded table row (words)
 constexpr int SPW = (SK + 19) / 20;  // look-back words per tile (20 variables each)
 static_assert(SPW == BLOCK / WAVE, "one wave per look-back word");
+static_assert(BLOCK == 256, "one thread per entry of the event-byte table");
 
+// status after a monoid element (3-bit code) from a status: 2 bits at 2 * (code * 4 + s)
+constexpr uint64_t make_apply_table()
+{
+    uint64_t t = 0;
+    for (uint32_t c = 0; c < 8; c++)
+        for (uint32_t s = 0; s < 4; s++) {
+            const uint32_t T = (c >> 2) & 1u, X = (c >> 1) & 1u, Y = c & 1u;
+            const uint32_t cb = s & 1u, gb = (s >> 1) & 1u;
+            const uint32_t r = T ? (X | (Y << 1)) : ((cb | (X & gb)) | ((gb | (Y & cb)) << 1));
+            t |= (uint64_t)r << (2 * (c * 4 + s));
+        }
+    return t;
+}
+constexpr uint64_t APPLY = make_apply_table();
+
+// one 32-bit half of the function planes of up to 64 variables
+struct Fn32 {
+    uint32_t t, x, y;
+};
+
+// h o f (f first) on one half of the planes
+__device__ __forceinline__ Fn32 fn_compose(Fn32 h, Fn32 f)
+{
+    const uint32_t ex = f.x | (h.x & (~f.t | f.y));
+    const uint32_t ey = f.y | (h.y & (~f.t | f.x));
+    return Fn32{h.t | f.t, (h.t & h.x) | (~h.t & ex), (h.t & h.y) | (~h.t & ey)};
+}
+
+// statuses (c, g) after f, on one half of the planes
+__device__ __forceinline__ void fn_apply(Fn32 f, uint32_t &c, uint32_t &g)
+{
+    const uint32_t nc = (f.t & f.x) | (~f.t & (c | (f.x & g)));
+    const uint32_t ng = (f.t & f.y) | (~f.t & (g | (f.y & c)));
+    c = nc;
+    g = ng;
+}
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ Fn32 fn_move(Fn32 f)
+{
+    return Fn32{dpp_move<CTRL, ROWS>(0u, f.t), dpp_move<CTRL, ROWS>(0u, f.x), dpp_move<CTRL, ROWS>(0u, f.y)};
+}
+
+// inclusive scan of the function planes across the wave (lane 0 first); a lane
+// without a source combines with the identity (all planes zero)
+__device__ __forceinline__ void fn_wave_scan(Fn32 &lo, Fn32 &hi)
+{
+#define VC_FN_STEP(CTRL, ROWS)                                                                                         \
+    {                                                                                                                  \
+        const Fn32 gl = fn_move<CTRL, ROWS>(lo), gh = fn_move<CTRL, ROWS>(hi);                                         \
+        lo = fn_compose(lo, gl);                                                                                       \
+        hi = fn_compose(hi, gh);                                                                                       \
+    }
+    VC_FN_STEP(DPP_ROW_SHR + 1, 0xF)
+    VC_FN_STEP(DPP_ROW_SHR + 2, 0xF)
+    VC_FN_STEP(DPP_ROW_SHR + 4, 0xF)
+    VC_FN_STEP(DPP_ROW_SHR + 8, 0xF)
+    VC_FN_STEP(DPP_ROW_BCAST15, 0xA)
+    VC_FN_STEP(DPP_ROW_BCAST31, 0xC)
+#undef VC_FN_STEP
+}
+
+__device__ __forceinline__ uint32_t bits20(uint32_t lo, uint32_t hi, uint32_t k)
+{
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    return (uint32_t)(v >> (20 * k)) & PL_MASK;
+}
 
 __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ status,
@@ -34,21 +106,26 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
                                                        uint64_t *__restrict__ lbv, uint64_t *__restrict__ lbc,
                                                        uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
 {
-    __shared__ uint32_t s_tab[BLOCK * SROW];
-    __shared__ uint32_t s_q[4][SK];      // per quarter: composition of its 64 threads' tables
-    __shared__ uint8_t s_agg[SK + 8];    // tile aggregate function per variable (packed)
-    __shared__ uint8_t s_carry[SK + 8];  // status per variable entering the tile
-    __shared__ uint8_t s_qin[4][SK];     // status per variable entering each quarter
-    __shared__ uint32_t s_f4[16], s_stuck[16];
+    // per top byte of an event word (op | side << 3 | reserved << 4): the effect's monoid
+    // code (bits 0-2), its stuck mask (bits 3-6), malformed (bit 7: reserved bits set or
+    // op past Noop)
+    __shared__ uint8_t s_info[256];
+    __shared__ Fn32 s_wtot[BLOCK / WAVE][2]; // per wave: composition of its threads
+    __shared__ uint32_t s_in[SPW][2];        // statuses entering the tile, 20 variables a word
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
     __shared__ unsigned long long s_vexcl;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    if (tid < 16) {
-        s_f4[tid] = TABLE.f4[tid];
-        s_stuck[tid] = TABLE.stuck[tid];
+    {
+        const uint32_t op = tid & 7u, side = (tid >> 3) & 1u;
+        const bool bad = (tid >> 4) != 0 || op > OP_NOOP;
+        const uint32_t fc = bad ? fcode(OP_NOOP, 0) : fcode(op, side);
+        s_info[tid] = (uint8_t)(mon_code(TABLE.f4[fc]) | (TABLE.stuck[fc] << 3) | ((bad ? 1u : 0u) << 7));
     }
+    __syncthreads();
+    constexpr uint32_t NOOP_INFO = 0; // identity, never stuck
+
     for (;;) {
         const uint32_t tile = take_ticket(ticket, &s_tile);
         if (tile >= ntiles)
@@ -56,149 +133,138 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
         const uint64_t base = (uint64_t)tile * STILE;
         const uint64_t my0 = base + (uint64_t)tid * SE;
 
-        // ---- load 16 consecutive events, decode ------------------------------------
-        uint32_t key[SE], fc[SE];
-        uint32_t valid = 0;
+        // ---- load and decode 16 consecutive events: id (6 bits) | info << 8 -----------
+        uint32_t w[SE];
+        uint32_t valid = 0xFFFFu;
         if (my0 + SE <= n) {
             const uint4 *p = reinterpret_cast<const uint4 *>(ev + my0);
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                uint4 v = p[q];
-                uint32_t w[4] = { v.x, v.y, v.z, v.w };
-#pragma unroll
-                for (int b = 0; b < 4; b++) {
-                    key[4 * q + b] = w[b];
-                }
+                const uint4 v = p[q];
+                w[4 * q] = v.x;
+                w[4 * q + 1] = v.y;
+                w[4 * q + 2] = v.z;
+                w[4 * q + 3] = v.w;
             }
-            valid = 0xFFFFu;
         } else {
+            valid = 0;
 #pragma unroll
             for (int j = 0; j < SE; j++) {
-                key[j] = my0 + j < n ? ev[my0 + j] : 0u;
-                valid |= (my0 + j < n ? 1u : 0u) << j;
+                const bool in = my0 + j < n;
+                w[j] = in ? ev[my0 + j] : (OP_NOOP << 24);
+                valid |= (in ? 1u : 0u) << j;
             }
         }
+        uint32_t iv[SE];
+        uint32_t badm = 0;
 #pragma unroll
         for (int j = 0; j < SE; j++) {
-            uint32_t w = key[j];
-            uint32_t id = w & 0xFFFFFFu, op = (w >> 24) & 7u, side = (w >> 27) & 1u;
-            if (((valid >> j) & 1u) && ((w >> 28) != 0 || op > OP_NOOP || id >= n_ids)) {
-                unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
-                atomicMin(e, (unsigned long long)(my0 + j));
-                id = 0;
-                op = OP_NOOP;
+            const uint32_t info = s_info[w[j] >> 24];
+            const uint32_t id = w[j] & 0xFFFFFFu;
+            const bool bad = (info >> 7) != 0 || id >= n_ids;
+            badm |= (bad ? 1u : 0u) << j;
+            iv[j] = (id & 63u) | (info << 8);
+        }
+        if (__ballot(badm != 0)) {
+            // malformed words count as Noop on variable 0; the first index is reported
+#pragma unroll
+            for (int j = 0; j < SE; j++) {
+                if ((badm >> j) & 1u) {
+                    if ((valid >> j) & 1u) {
+                        unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
+                        atomicMin(e, (unsigned long long)(my0 + j));
+                    }
+                    iv[j] = NOOP_INFO << 8;
+                }
             }
-            key[j] = id;
-            fc[j] = (valid >> j) & 1u ? fcode(op, side) : fcode(OP_NOOP, 0);
         }
 
-        // ---- phase 1: each thread's composition per variable, in registers -------------
-        // before[j]: composition of this thread's earlier events on key[j] (identity if
-        // none); the last event of each key writes the thread's aggregate for that key
-        uint32_t before[SE];
-        uint32_t agg[SE];
+        // ---- 1. this thread's function planes --------------------------------------
+        Fn32 lo{0, 0, 0}, hi{0, 0, 0};
 #pragma unroll
         for (int j = 0; j < SE; j++) {
-            uint32_t acc = F_ID;
-#pragma unroll
-            for (int i = 0; i < j; i++)
-                acc = key[i] == key[j] ? agg[i] : acc;
-            before[j] = acc;
-            agg[j] = fcompose(s_f4[fc[j]], acc);
+            const uint32_t id = iv[j] & 63u, code = (iv[j] >> 8) & 7u;
+            const uint32_t ct = (uint32_t)-(int32_t)((code >> 2) & 1u), cx = (uint32_t)-(int32_t)((code >> 1) & 1u),
+                           cy = (uint32_t)-(int32_t)(code & 1u);
+            const uint32_t m = 1u << (id & 31u);
+            const uint32_t mlo = id < 32 ? m : 0u, mhi = id < 32 ? 0u : m;
+            lo = fn_compose(Fn32{mlo & ct, mlo & cx, mlo & cy}, lo);
+            hi = fn_compose(Fn32{mhi & ct, mhi & cx, mhi & cy}, hi);
         }
-        uint32_t *row = s_tab + tid * SROW;
-#pragma unroll
-        for (int k = 0; k < SK; k++)
-            row[k] = F_ID;
-#pragma unroll
-        for (int j = 0; j < SE; j++) {
-            bool last = true;
-#pragma unroll
-            for (int i = j + 1; i < SE; i++)
-                last = last && key[i] != key[j];
-            if (last)
-                row[key[j]] = agg[j];
+
+        // ---- 2. composition of the tile's events before this thread ------------------
+        const Fn32 own_lo = lo, own_hi = hi;
+        fn_wave_scan(lo, hi);
+        if (lane == WAVE - 1) {
+            s_wtot[wave][0] = lo;
+            s_wtot[wave][1] = hi;
         }
+        // exclusive: the inclusive prefix of the lane before (lane 0: identity)
+        const Fn32 xlo = fn_move<DPP_WAVE_SHR1>(lo), xhi = fn_move<DPP_WAVE_SHR1>(hi);
+        (void)own_lo;
+        (void)own_hi;
         __syncthreads();
+        // earlier waves, then the wave's own prefix
+        Fn32 plo{0, 0, 0}, phi{0, 0, 0}, alo{0, 0, 0}, ahi{0, 0, 0};
+#pragma unroll
+        for (uint32_t w2 = 0; w2 < BLOCK / WAVE; w2++) {
+            if (w2 == wave) {
+                plo = alo;
+                phi = ahi;
+            }
+            alo = fn_compose(s_wtot[w2][0], alo);
+            ahi = fn_compose(s_wtot[w2][1], ahi);
+        }
+        plo = fn_compose(xlo, plo);
+        phi = fn_compose(xhi, phi);
 
-        // ---- phase 2: per-variable exclusive scan over the threads --------------------
-        // wave q scans threads 64q .. 64q+63 for variable `lane`: all reads first, the
-        // composition chain in registers, then all writes
+        // ---- 3. statuses entering the tile: look-back, one wave per word of 20 --------
         {
-            const uint32_t q = wave;
-            uint32_t v[WAVE];
-#pragma unroll
-            for (int i = 0; i < WAVE; i++)
-                v[i] = s_tab[(q * WAVE + i) * SROW + lane];
-            uint32_t acc = F_ID;
-#pragma unroll
-            for (int i = 0; i < WAVE; i++) {
-                uint32_t f = v[i];
-                v[i] = acc; // exclusive within the quarter
-                acc = fcompose(f, acc);
-            }
-#pragma unroll
-            for (int i = 0; i < WAVE; i++)
-                s_tab[(q * WAVE + i) * SROW + lane] = v[i];
-            s_q[q][lane] = acc;
-        }
-        __syncthreads();
-        if (tid < SK) {
-            uint32_t a = F_ID;
-            for (int q = 0; q < 4; q++)
-                a = fcompose(s_q[q][tid], a);
-            s_agg[tid] = (uint8_t)fpack(a);
-        }
-        __syncthreads();
-
-        // ---- look-back: status per variable entering the tile.  Four words of 20
-        // variables as bit planes, one wave per word, 64 predecessors per round ----------
-        {
-            const uint32_t k = wave * 20 + lane; // this lane's variable (lanes < 20)
-            const bool mine = lane < 20 && k < SK;
-            const uint32_t code = mine ? mon_code_packed(s_agg[k]) : 0u;
-            const Planes agg{(uint32_t)__ballot((code >> 2) & 1u) & PL_MASK,
-                             (uint32_t)__ballot((code >> 1) & 1u) & PL_MASK, (uint32_t)__ballot(code & 1u) & PL_MASK};
+            const uint32_t k = wave;
+            const Planes agg{bits20(alo.t, ahi.t, k), bits20(alo.x, ahi.x, k), bits20(alo.y, ahi.y, k)};
             Planes first{PL_MASK, 0, 0};
             if (tile == 0) {
-                const uint32_t s0 = (init && mine && k < n_ids) ? init[k] : 1u;
+                const uint32_t v = k * 20 + lane;
+                const uint32_t s0 = (init && lane < 20 && v < n_ids) ? init[v] : 1u;
                 first.x = (uint32_t)__ballot(s0 & 1u) & PL_MASK;
                 first.y = (uint32_t)__ballot((s0 >> 1) & 1u) & PL_MASK;
             }
-            const Planes st = lb_planes_exclusive(lbv, SPW, tile, wave, agg, first);
-            if (mine) {
-                s_carry[k] = (uint8_t)(((st.x >> lane) & 1u) | (((st.y >> lane) & 1u) << 1));
-                if (tile + 1 == ntiles && final_out && k < n_ids) {
-                    const Planes inc = pl_compose(agg, st);
-                    final_out[k] = (uint8_t)(((inc.x >> lane) & 1u) | (((inc.y >> lane) & 1u) << 1));
-                }
+            const Planes st = lb_planes_exclusive(lbv, SPW, tile, k, agg, first);
+            if (lane == 0) {
+                s_in[k][0] = st.x;
+                s_in[k][1] = st.y;
+            }
+            if (tile + 1 == ntiles && final_out && lane < 20) {
+                const uint32_t v = k * 20 + lane;
+                const Planes inc = pl_compose(agg, st);
+                if (v < n_ids)
+                    final_out[v] = (uint8_t)(((inc.x >> lane) & 1u) | (((inc.y >> lane) & 1u) << 1));
             }
         }
         __syncthreads();
-        // status per variable entering each quarter
-        {
-            uint32_t q = wave;
-            uint32_t s = s_carry[lane];
-            for (uint32_t r = 0; r < q; r++)
-                s = fapply(s_q[r][lane], s);
-            s_qin[q][lane] = (uint8_t)s;
-        }
-        __syncthreads();
-
-        // ---- phase 3: replay each thread's events ------------------------------------
-        // status of key[j] entering this thread = (thread's exclusive prefix)(status
-        // entering the quarter); then the thread's own earlier events on that key
-        uint32_t out[4] = { 0, 0, 0, 0 };
-        uint32_t flags = 0;
-        uint32_t enter[SE];
+        uint64_t c64 = 0, g64 = 0;
 #pragma unroll
-        for (int j = 0; j < SE; j++)
-            enter[j] = fapply(row[key[j]], s_qin[wave][key[j]]);
+        for (int k = 0; k < SPW; k++) {
+            c64 |= (uint64_t)s_in[k][0] << (20 * k);
+            g64 |= (uint64_t)s_in[k][1] << (20 * k);
+        }
+        uint32_t clo = (uint32_t)c64, chi = (uint32_t)(c64 >> 32), glo = (uint32_t)g64, ghi = (uint32_t)(g64 >> 32);
+        fn_apply(plo, clo, glo);
+        fn_apply(phi, chi, ghi);
+
+        // ---- 4. replay this thread's events ------------------------------------------
+        uint64_t C = ((uint64_t)chi << 32) | clo, G = ((uint64_t)ghi << 32) | glo;
+        uint32_t out[4] = {0, 0, 0, 0};
+        uint32_t flags = 0;
 #pragma unroll
         for (int j = 0; j < SE; j++) {
-            uint32_t pre = fapply(before[j], enter[j]);
-            uint32_t post = fapply(s_f4[fc[j]], pre);
-            uint32_t flag = (s_stuck[fc[j]] >> pre) & 1u & ((valid >> j) & 1u);
+            const uint32_t id = iv[j] & 63u, info = iv[j] >> 8, code = info & 7u;
+            const uint32_t pre = (uint32_t)((C >> id) & 1u) | ((uint32_t)((G >> id) & 1u) << 1);
+            const uint32_t post = (uint32_t)(APPLY >> (2u * (code * 4u + pre))) & 3u;
+            const uint32_t flag = (info >> (3u + pre)) & 1u & ((valid >> j) & 1u);
+            const uint32_t d = post ^ pre;
+            C ^= (uint64_t)(d & 1u) << id;
+            G ^= (uint64_t)(d >> 1) << id;
             out[j >> 2] |= (post | (pre << 2) | (flag << 7)) << (8 * (j & 3));
             flags |= flag << j;
         }
@@ -217,10 +283,10 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
             s_wsum[wave] = inc;
         __syncthreads();
         uint32_t woff = 0, total = 0;
-        for (uint32_t w = 0; w < BLOCK / WAVE; w++) {
-            if (w < wave)
-                woff += s_wsum[w];
-            total += s_wsum[w];
+        for (uint32_t w2 = 0; w2 < BLOCK / WAVE; w2++) {
+            if (w2 < wave)
+                woff += s_wsum[w2];
+            total += s_wsum[w2];
         }
         if (wave == 0) {
             const uint64_t excl = lb_count_exclusive(lbc, tile, total);
