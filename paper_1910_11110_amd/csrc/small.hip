@@ -13,9 +13,11 @@
 //      function: four self-flagged 64-bit words of 20 variables each (one wave per
 //      word).
 //   4. Each thread applies its prefix to the statuses entering the tile and replays its
-//      16 events on status planes: status bytes (one 16-byte store per thread), the
-//      flagged events compacted in the same kernel (a second look-back on the count),
-//      and the final statuses from the last tile.
+//      16 events on status planes: status bytes (one 16-byte store per thread) and the
+//      final statuses from the last tile.  The tile's count of flagged events and, per
+//      thread, its flag mask and offset inside the tile are stored; a scan of the tile
+//      counts and a scatter pass then write the ascending violation indices (no second
+//      chain of tiles).
 #include "device.h"
 #include "internal.h"
 #include "prof.h"
@@ -102,9 +104,10 @@ __device__ __forceinline__ uint32_t bits20(uint32_t lo, uint32_t hi, uint32_t k)
 
 __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ status,
-                                                       uint8_t *__restrict__ final_out, uint32_t *__restrict__ viol,
-                                                       uint64_t *__restrict__ lbv, uint64_t *__restrict__ lbc,
-                                                       uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
+                                                       uint8_t *__restrict__ final_out,
+                                                       uint64_t *__restrict__ lbv, uint32_t *__restrict__ tcnt,
+                                                       uint32_t *__restrict__ fw, uint32_t *__restrict__ ticket,
+                                                       uint64_t ntiles, Control *ctl)
 {
     // per top byte of an event word (op | side << 3 | reserved << 4): the effect's monoid
     // code (bits 0-2), its stuck mask (bits 3-6), malformed (bit 7: reserved bits set or
@@ -114,7 +117,6 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
     __shared__ uint32_t s_in[SPW][2];        // statuses entering the tile, 20 variables a word
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_vexcl;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     {
@@ -276,9 +278,10 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
                     status[my0 + j] = (uint8_t)(out[j >> 2] >> (8 * (j & 3)));
         }
 
-        // ---- violations: tile count, look-back for the offset, ascending indices -------
-        uint32_t cnt = __builtin_popcount(flags);
-        uint32_t inc = wave_scan_add(cnt, lane);
+        // ---- flagged events: per thread its mask and offset inside the tile, per tile
+        // the count
+        const uint32_t cnt = __builtin_popcount(flags);
+        const uint32_t inc = wave_scan_add(cnt, lane);
         if (lane == WAVE - 1)
             s_wsum[wave] = inc;
         __syncthreads();
@@ -288,32 +291,63 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
                 woff += s_wsum[w2];
             total += s_wsum[w2];
         }
-        if (wave == 0) {
-            const uint64_t excl = lb_count_exclusive(lbc, tile, total);
-            if (lane == 0) {
-                s_vexcl = excl;
-                if (tile + 1 == ntiles)
-                    ctl->n_viol = excl + total;
-            }
-        }
-        __syncthreads();
-        uint64_t o = s_vexcl + woff + inc - cnt;
+        fw[(uint64_t)tile * BLOCK + tid] = flags | ((woff + inc - cnt) << 16);
+        if (tid == 0)
+            tcnt[tile] = total;
+    }
+}
+
+// violation indices of every tile at its offset among all flagged events
+__global__ __launch_bounds__(BLOCK) void k_small_viol(const uint32_t *__restrict__ fw, const uint64_t *__restrict__ offs,
+                                                      uint64_t ntiles, uint32_t *__restrict__ viol)
+{
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t word = fw[tile * BLOCK + threadIdx.x];
+        uint32_t flags = word & 0xFFFFu;
+        uint64_t o = offs[tile] + (word >> 16);
+        const uint64_t my0 = tile * STILE + (uint64_t)threadIdx.x * SE;
         while (flags) {
-            uint32_t b = __builtin_ctz(flags);
+            const uint32_t b = __builtin_ctz(flags);
             flags &= flags - 1;
             viol[o++] = (uint32_t)(my0 + b);
         }
-        __syncthreads();
     }
 }
 
 } // namespace
 
-size_t small_scratch_bytes(uint64_t n)
+// scratch: look-back words, tile counts, their offsets, the chunk scan's scratch, the
+// per-thread flag words
+struct SmallLayout {
+    uint64_t *lbv;
+    uint32_t *tcnt;
+    uint64_t *offs;
+    void *xscan;
+    uint32_t *fw;
+    size_t bytes;
+};
+
+static SmallLayout small_layout(void *scratch, uint64_t n)
 {
-    uint64_t tiles = ceil_div(n ? n : 1, STILE);
-    return tiles * (SPW + 1) * sizeof(uint64_t);
+    const uint64_t tiles = ceil_div(n ? n : 1, STILE);
+    char *p = reinterpret_cast<char *>(scratch);
+    size_t off = 0;
+    auto take = [&](size_t sz) {
+        char *r = p ? p + off : nullptr;
+        off += (sz + 255) & ~size_t(255);
+        return r;
+    };
+    SmallLayout L;
+    L.lbv = reinterpret_cast<uint64_t *>(take(tiles * SPW * sizeof(uint64_t)));
+    L.tcnt = reinterpret_cast<uint32_t *>(take(tiles * 4));
+    L.offs = reinterpret_cast<uint64_t *>(take((tiles + 1) * 8));
+    L.xscan = take(excl_scan_scratch_bytes(tiles));
+    L.fw = reinterpret_cast<uint32_t *>(take(tiles * BLOCK * 4));
+    L.bytes = off;
+    return L;
 }
+
+size_t small_scratch_bytes(uint64_t n) { return small_layout(nullptr, n).bytes; }
 
 uint32_t small_max_ids() { return SK; }
 
@@ -323,14 +357,22 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
 {
     if (n == 0)
         return;
-    uint64_t tiles = ceil_div(n, STILE);
-    uint64_t *lbv = reinterpret_cast<uint64_t *>(scratch);
-    uint64_t *lbc = lbv + tiles * SPW;
-    launch_clear_lookback(lbv, tiles * (SPW + 1), ctl->tickets[7], s);
-    const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap);
-    ProfScope prof_(s, "small_check");
-    k_small_check<<<grid, BLOCK, 0, s>>>(events, n, n_ids, init, status, final_out, viol, lbv, lbc, ctl->tickets[7],
-                                         tiles, ctl);
+    const uint64_t tiles = ceil_div(n, STILE);
+    const SmallLayout L = small_layout(scratch, n);
+    launch_clear_lookback(L.lbv, tiles * SPW, ctl->tickets[7], s);
+    {
+        const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap);
+        ProfScope prof_(s, "small_check");
+        k_small_check<<<grid, BLOCK, 0, s>>>(events, n, n_ids, init, status, final_out, L.lbv, L.tcnt, L.fw,
+                                             ctl->tickets[7], tiles, ctl);
+    }
+    // the violation count lands in ctl->n_viol
+    launch_excl_scan(L.tcnt, tiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan, ctl->tickets[8], s);
+    {
+        ProfScope prof_(s, "small_viol");
+        const unsigned grid = (unsigned)(tiles < 8192 ? tiles : 8192);
+        k_small_viol<<<grid, BLOCK, 0, s>>>(L.fw, L.offs, tiles, viol);
+    }
 }
 
 } // namespace vc
