@@ -23,10 +23,10 @@ constexpr uint32_t TICKET_STRIDE = 32;
 constexpr uint32_t TICKET_WORDS = TICKET_GROUPS * TICKET_STRIDE;
 
 // Grid of a kernel that takes tile tickets: at most what is resident on the device at
-// once (occupancy of `kernel` at BLOCK threads x compute units), at most `cap` when
+// once (occupancy of `kernel` at `block` threads x compute units), at most `cap` when
 // non-zero, and a multiple of TICKET_GROUPS no smaller than TICKET_GROUPS; tiles beyond
 // the grid are taken in turn by the resident workgroups.
-unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap = 0);
+unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap = 0, int block = BLOCK);
 
 struct Control {
     uint32_t err_index_lo;        // first malformed input index (low/high), 0xFFFFFFFF.. if none

@@ -1,7 +1,7 @@
 // small.hip -- single-pass check of a trace over at most 64 variables (gfx950).
 //
-// No sort.  The trace is cut into tiles of 4096 events in program order; thread t of
-// a tile owns events [16t, 16t + 16).  The state of all 64 variables is held as 64-bit
+// No sort.  The trace is cut into tiles of 8192 events in program order (512 threads,
+// eight waves); thread t of a tile owns events [16t, 16t + 16).  The state of all 64 variables is held as 64-bit
 // bit planes (bit v = variable v): a transition function of the 7-element monoid per
 // variable as three planes (T, X, Y), a status as two planes (C = CPU copy valid,
 // G = GPU copy valid).
@@ -28,11 +28,13 @@ namespace {
 
 constexpr EffectTable TABLE = make_table();
 constexpr int SK = 64;               // variables
+constexpr int SB = 512;              // threads per tile
+constexpr int SW = SB / WAVE;        // waves per tile
 constexpr int SE = 16;               // events per thread
-constexpr int STILE = BLOCK * SE;    // events per tile
+constexpr int STILE = SB * SE;       // events per tile
 constexpr int SPW = (SK + 19) / 20;  // look-back words per tile (20 variables each)
-static_assert(SPW == BLOCK / WAVE, "one wave per look-back word");
-static_assert(BLOCK == 256, "one thread per entry of the event-byte table");
+static_assert(SPW <= SW, "one wave per look-back word");
+static_assert(SB >= 256, "one thread per entry of the event-byte table");
 
 // status after a monoid element (3-bit code) from a status: 2 bits at 2 * (code * 4 + s)
 constexpr uint64_t make_apply_table()
@@ -102,7 +104,7 @@ __device__ __forceinline__ uint32_t bits20(uint32_t lo, uint32_t hi, uint32_t k)
     return (uint32_t)(v >> (20 * k)) & PL_MASK;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
+__global__ __launch_bounds__(SB) void k_small_check(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ status,
                                                        uint8_t *__restrict__ final_out,
                                                        uint64_t *__restrict__ lbv, uint32_t *__restrict__ tcnt,
@@ -113,13 +115,13 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
     // code (bits 0-2), its stuck mask (bits 3-6), malformed (bit 7: reserved bits set or
     // op past Noop)
     __shared__ uint8_t s_info[256];
-    __shared__ Fn32 s_wtot[BLOCK / WAVE][2]; // per wave: composition of its threads
+    __shared__ Fn32 s_wtot[SW][2];           // per wave: composition of its threads
     __shared__ uint32_t s_in[SPW][2];        // statuses entering the tile, 20 variables a word
-    __shared__ uint32_t s_wsum[BLOCK / WAVE];
+    __shared__ uint32_t s_wsum[SW];
     __shared__ uint32_t s_tile;
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    {
+    if (tid < 256) {
         const uint32_t op = tid & 7u, side = (tid >> 3) & 1u;
         const bool bad = (tid >> 4) != 0 || op > OP_NOOP;
         const uint32_t fc = bad ? fcode(OP_NOOP, 0) : fcode(op, side);
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
         // earlier waves, then the wave's own prefix
         Fn32 plo{0, 0, 0}, phi{0, 0, 0}, alo{0, 0, 0}, ahi{0, 0, 0};
 #pragma unroll
-        for (uint32_t w2 = 0; w2 < BLOCK / WAVE; w2++) {
+        for (uint32_t w2 = 0; w2 < SW; w2++) {
             if (w2 == wave) {
                 plo = alo;
                 phi = ahi;
@@ -221,7 +223,7 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
         phi = fn_compose(xhi, phi);
 
         // ---- 3. statuses entering the tile: look-back, one wave per word of 20 --------
-        {
+        if (wave < SPW) {
             const uint32_t k = wave;
             const Planes agg{bits20(alo.t, ahi.t, k), bits20(alo.x, ahi.x, k), bits20(alo.y, ahi.y, k)};
             Planes first{PL_MASK, 0, 0};
@@ -286,23 +288,23 @@ __global__ __launch_bounds__(BLOCK) void k_small_check(const uint32_t *__restric
             s_wsum[wave] = inc;
         __syncthreads();
         uint32_t woff = 0, total = 0;
-        for (uint32_t w2 = 0; w2 < BLOCK / WAVE; w2++) {
+        for (uint32_t w2 = 0; w2 < SW; w2++) {
             if (w2 < wave)
                 woff += s_wsum[w2];
             total += s_wsum[w2];
         }
-        fw[(uint64_t)tile * BLOCK + tid] = flags | ((woff + inc - cnt) << 16);
+        fw[(uint64_t)tile * SB + tid] = flags | ((woff + inc - cnt) << 16);
         if (tid == 0)
             tcnt[tile] = total;
     }
 }
 
 // violation indices of every tile at its offset among all flagged events
-__global__ __launch_bounds__(BLOCK) void k_small_viol(const uint32_t *__restrict__ fw, const uint64_t *__restrict__ offs,
+__global__ __launch_bounds__(SB) void k_small_viol(const uint32_t *__restrict__ fw, const uint64_t *__restrict__ offs,
                                                       uint64_t ntiles, uint32_t *__restrict__ viol)
 {
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t word = fw[tile * BLOCK + threadIdx.x];
+        const uint32_t word = fw[tile * SB + threadIdx.x];
         uint32_t flags = word & 0xFFFFu;
         uint64_t o = offs[tile] + (word >> 16);
         const uint64_t my0 = tile * STILE + (uint64_t)threadIdx.x * SE;
@@ -342,7 +344,7 @@ static SmallLayout small_layout(void *scratch, uint64_t n)
     L.tcnt = reinterpret_cast<uint32_t *>(take(tiles * 4));
     L.offs = reinterpret_cast<uint64_t *>(take((tiles + 1) * 8));
     L.xscan = take(excl_scan_scratch_bytes(tiles));
-    L.fw = reinterpret_cast<uint32_t *>(take(tiles * BLOCK * 4));
+    L.fw = reinterpret_cast<uint32_t *>(take(tiles * SB * 4));
     L.bytes = off;
     return L;
 }
@@ -361,9 +363,9 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
     const SmallLayout L = small_layout(scratch, n);
     launch_clear_lookback(L.lbv, tiles * SPW, ctl->tickets[7], s);
     {
-        const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap);
+        const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap, SB);
         ProfScope prof_(s, "small_check");
-        k_small_check<<<grid, BLOCK, 0, s>>>(events, n, n_ids, init, status, final_out, L.lbv, L.tcnt, L.fw,
+        k_small_check<<<grid, SB, 0, s>>>(events, n, n_ids, init, status, final_out, L.lbv, L.tcnt, L.fw,
                                              ctl->tickets[7], tiles, ctl);
     }
     // the violation count lands in ctl->n_viol
@@ -371,7 +373,7 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
     {
         ProfScope prof_(s, "small_viol");
         const unsigned grid = (unsigned)(tiles < 8192 ? tiles : 8192);
-        k_small_viol<<<grid, BLOCK, 0, s>>>(L.fw, L.offs, tiles, viol);
+        k_small_viol<<<grid, SB, 0, s>>>(L.fw, L.offs, tiles, viol);
     }
 }
 

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(BLOCK) void k_excl_scan(const uint32_t *__restrict_
 
 } // namespace
 
-unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap)
+unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap, int block)
 {
     static std::mutex mu;
     static std::unordered_map<const void *, int> per_cu_cache;
@@ -90,7 +90,7 @@ unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap)
         auto it = per_cu_cache.find(kernel);
         if (it == per_cu_cache.end()) {
             int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, BLOCK, 0) != hipSuccess || nb < 1)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1)
                 nb = 1;
             it = per_cu_cache.emplace(kernel, nb).first;
         }
