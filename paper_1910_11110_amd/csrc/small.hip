@@ -299,20 +299,32 @@ __global__ __launch_bounds__(SB) void k_small_check(const uint32_t *__restrict__
     }
 }
 
-// violation indices of every tile at its offset among all flagged events
+// violation indices of every tile at its offset among all flagged events: each thread
+// lists its flagged indices in LDS at its offset inside the tile, then the tile's run is
+// written out contiguously
 __global__ __launch_bounds__(SB) void k_small_viol(const uint32_t *__restrict__ fw, const uint64_t *__restrict__ offs,
-                                                      uint64_t ntiles, uint32_t *__restrict__ viol)
+                                                   uint64_t ntiles, uint32_t *__restrict__ viol)
 {
+    __shared__ uint32_t s_idx[STILE];
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t o0 = offs[tile], total = offs[tile + 1] - o0;
+        if (total == 0)
+            continue; // uniform: no flagged event in the tile
         const uint32_t word = fw[tile * SB + threadIdx.x];
-        uint32_t flags = word & 0xFFFFu;
-        uint64_t o = offs[tile] + (word >> 16);
-        const uint64_t my0 = tile * STILE + (uint64_t)threadIdx.x * SE;
+        uint32_t flags = word & 0xFFFFu, o = word >> 16;
+        const uint32_t my0 = (uint32_t)(tile * STILE) + threadIdx.x * SE;
         while (flags) {
             const uint32_t b = __builtin_ctz(flags);
             flags &= flags - 1;
-            viol[o++] = (uint32_t)(my0 + b);
+            if (o < STILE)
+                s_idx[o] = my0 + b;
+            o++;
         }
+        __syncthreads();
+        const uint32_t cnt = total < (uint64_t)STILE ? (uint32_t)total : (uint32_t)STILE;
+        for (uint32_t i = threadIdx.x; i < cnt; i += SB)
+            viol[o0 + i] = s_idx[i];
+        __syncthreads();
     }
 }
 
