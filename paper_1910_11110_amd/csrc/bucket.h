@@ -28,7 +28,12 @@ struct BucketLayout {
     uint32_t *tbase = nullptr;
     uint32_t *order = nullptr; // bucket tile (bucket-major index) taken by each ticket
     uint32_t *gsum = nullptr, *gpre = nullptr; // per tile range: bucket counts, their column prefix
-    uint64_t *lbv = nullptr, *lbc = nullptr;
+    uint64_t *lbv = nullptr;
+    // trace check: per partition tile the count of flagged events and its offset among
+    // all of them; per thread of a tile its flag word (mask | offset inside the tile << 16)
+    uint32_t *tcnt = nullptr, *fw = nullptr;
+    uint64_t *offs = nullptr;
+    void *xscan = nullptr; // scratch of the scan of the tile counts
     uint32_t *part = nullptr;
     uint32_t *dstidx = nullptr; // per word: its position in the partitioned order
     uint8_t *res = nullptr;

@@ -815,21 +815,19 @@ __device__ __forceinline__ void store16(uint8_t *__restrict__ out, uint64_t n, u
     }
 }
 
+// status bytes in program order; per thread its flag mask and offset among the flagged
+// events of its tile, per tile the count (placed by a scan and a scatter pass)
 __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restrict__ dstidx, uint64_t n,
                                                          const uint8_t *__restrict__ res, uint8_t *__restrict__ status,
-                                                         uint32_t *__restrict__ viol, uint64_t *__restrict__ lbc,
-                                                         uint32_t *__restrict__ ticket, uint64_t ntiles, Control *ctl)
+                                                         uint32_t *__restrict__ fw, uint32_t *__restrict__ tcnt,
+                                                         uint64_t ntiles)
 {
+    static_assert(P_ITEMS == FLAG_EVENTS, "one flag word per thread");
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
-    __shared__ uint32_t s_tile;
-    __shared__ unsigned long long s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
-    for (;;) {
-        const uint32_t tile = take_ticket(ticket, &s_tile);
-        if (tile >= ntiles)
-            break;
-        const uint64_t tbase = (uint64_t)tile * PTILE;
-        const uint64_t my0 = tbase + (uint64_t)tid * 16;
+    // tiles are independent: a plain grid-stride loop
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t my0 = tile * PTILE + (uint64_t)tid * 16;
         // 16 consecutive status bytes per thread
         uint32_t q[4];
         gather16(dstidx, res, n, my0, q);
@@ -837,12 +835,12 @@ __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restr
         uint32_t flags = 0;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
-            uint32_t byte = (q[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+            const uint32_t byte = (q[k >> 2] >> (8 * (k & 3))) & 0xFFu;
             if (my0 + k < n)
                 flags |= ((byte >> 7) & 1u) << k;
         }
-        uint32_t c = __builtin_popcount(flags);
-        uint32_t inc = wave_scan_add(c, lane);
+        const uint32_t c = __builtin_popcount(flags);
+        const uint32_t inc = wave_scan_add(c, lane);
         if (lane == WAVE - 1)
             s_wsum[wave] = inc;
         __syncthreads();
@@ -852,23 +850,9 @@ __global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restr
                 woff += s_wsum[w2];
             total += s_wsum[w2];
         }
-        if (wave == 0) {
-            const uint64_t excl = lb_count_exclusive(lbc, tile, total);
-            if (lane == 0) {
-                s_excl = excl;
-                if (tile + 1 == ntiles)
-                    ctl->n_viol = excl + total;
-            }
-        }
-        __syncthreads();
-        uint64_t o = s_excl + woff + inc - c;
-        while (flags) {
-            uint32_t bb = __builtin_ctz(flags);
-            flags &= flags - 1;
-            if (o < n)
-                viol[o] = (uint32_t)(my0 + bb);
-            o++;
-        }
+        fw[tile * BLOCK + tid] = flags | ((woff + inc - c) << 16);
+        if (tid == 0)
+            tcnt[tile] = total;
         __syncthreads();
     }
 }
@@ -921,7 +905,10 @@ static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
     L.tbase = (uint32_t *)take((MAX_BUCKETS + 1) * 4);
     L.order = (uint32_t *)take(btiles * 4);
     L.lbv = (uint64_t *)take(btiles * LB_WORDS * 8);
-    L.lbc = (uint64_t *)take(ptiles * 8);
+    L.tcnt = (uint32_t *)take(ptiles * 4);
+    L.offs = (uint64_t *)take((ptiles + 1) * 8);
+    L.xscan = take(excl_scan_scratch_bytes(ptiles));
+    L.fw = (uint32_t *)take(ptiles * BLOCK * 4);
     L.part = (uint32_t *)take((n ? n : 1) * 4);
     L.dstidx = (uint32_t *)take((n ? n : 1) * 4);
     L.res = (uint8_t *)take(n ? n : 1);
@@ -1013,14 +1000,19 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     BucketLayout L = bucket_layout(scratch, n, n_ids);
     partition_and_scan<EventWords>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu);
     if (L.nb == 1) {
-        launch_compact(status, n, viol, L.lbc, ctl, s);
+        // (the flag words' area, 1 KiB per tile, holds the compaction's 8 bytes per tile)
+        launch_compact(status, n, viol, L.fw, ctl, s);
         return;
     }
-    launch_clear_lookback(L.lbc, L.ptiles, ctl->tickets[10], s);
-    ProfScope p(s, "replay_status");
-    const unsigned grid = resident_grid((const void *)k_replay_status, L.ptiles);
-    k_replay_status<<<grid, BLOCK, 0, s>>>(L.dstidx, n, L.res, status, viol, L.lbc, ctl->tickets[10], L.ptiles,
-                                           ctl);
+    {
+        ProfScope p(s, "replay_status");
+        const unsigned grid = resident_grid((const void *)k_replay_status, L.ptiles);
+        k_replay_status<<<grid, BLOCK, 0, s>>>(L.dstidx, n, L.res, status, L.fw, L.tcnt, L.ptiles);
+    }
+    // the violation count lands in ctl->n_viol
+    launch_excl_scan(L.tcnt, L.ptiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan,
+                     ctl->tickets[10], s);
+    launch_flag_scatter(L.fw, L.offs, L.ptiles, BLOCK, viol, s);
 }
 
 void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,

@@ -89,7 +89,52 @@ __global__ __launch_bounds__(BLOCK) void k_compact(const uint8_t *__restrict__ s
     }
 }
 
+// Violation indices from per-thread flag words of 16 consecutive events (flag mask |
+// the thread's offset among its tile's flagged events << 16) and the tiles' offsets
+// among all flagged events (ntiles + 1 entries).  Each thread lists its flagged indices
+// in LDS at its offset, then the tile's run is written out contiguously.
+template <int TB>
+__global__ __launch_bounds__(TB) void k_flag_scatter(const uint32_t *__restrict__ fw, const uint64_t *__restrict__ offs,
+                                                     uint64_t ntiles, uint32_t *__restrict__ viol)
+{
+    constexpr uint32_t TE = TB * FLAG_EVENTS; // events per tile
+    __shared__ uint32_t s_idx[TE];
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t o0 = offs[tile], total = offs[tile + 1] - o0;
+        if (total == 0)
+            continue; // uniform: no flagged event in the tile
+        const uint32_t word = fw[tile * TB + threadIdx.x];
+        uint32_t flags = word & 0xFFFFu, o = word >> 16;
+        const uint32_t my0 = (uint32_t)(tile * TE) + threadIdx.x * FLAG_EVENTS;
+        while (flags) {
+            const uint32_t b = __builtin_ctz(flags);
+            flags &= flags - 1;
+            if (o < TE)
+                s_idx[o] = my0 + b;
+            o++;
+        }
+        __syncthreads();
+        const uint32_t cnt = total < (uint64_t)TE ? (uint32_t)total : TE;
+        for (uint32_t i = threadIdx.x; i < cnt; i += TB)
+            viol[o0 + i] = s_idx[i];
+        __syncthreads();
+    }
+}
+
 } // namespace
+
+void launch_flag_scatter(const uint32_t *fw, const uint64_t *offs, uint64_t ntiles, int tb, uint32_t *viol,
+                         hipStream_t s)
+{
+    if (!ntiles)
+        return;
+    ProfScope prof_(s, "flag_scatter");
+    const unsigned grid = (unsigned)(ntiles < 8192 ? ntiles : 8192);
+    if (tb == 512)
+        k_flag_scatter<512><<<grid, 512, 0, s>>>(fw, offs, ntiles, viol);
+    else
+        k_flag_scatter<256><<<grid, 256, 0, s>>>(fw, offs, ntiles, viol);
+}
 
 size_t compact_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, CTILE) * sizeof(uint64_t); }
 

@@ -108,6 +108,14 @@ size_t compact_scratch_bytes(uint64_t n);
 void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
                     const unsigned long long *flagged = nullptr, const unsigned long long *n_dev = nullptr);
 
+// violation indices from per-thread flag words over FLAG_EVENTS consecutive events each
+// (flag mask | the thread's offset among the flagged events of its tile << 16; tb = 256
+// or 512 threads per tile, fw[tile * tb + thread]) and the tiles' offsets among all
+// flagged events (offs: ntiles + 1 entries, the exclusive scan of the tile counts)
+constexpr int FLAG_EVENTS = 16;
+void launch_flag_scatter(const uint32_t *fw, const uint64_t *offs, uint64_t ntiles, int tb, uint32_t *viol,
+                         hipStream_t s);
+
 // ------------------------------- translation --------------------------------------
 // sort items of the declarations: key = variable, fcode = the declaration's effect
 // on the abstract variable, payload = declaration index

@@ -30,7 +30,7 @@ constexpr EffectTable TABLE = make_table();
 constexpr int SK = 64;               // variables
 constexpr int SB = 512;              // threads per tile
 constexpr int SW = SB / WAVE;        // waves per tile
-constexpr int SE = 16;               // events per thread
+constexpr int SE = FLAG_EVENTS;      // events per thread
 constexpr int STILE = SB * SE;       // events per tile
 constexpr int SPW = (SK + 19) / 20;  // look-back words per tile (20 variables each)
 static_assert(SPW <= SW, "one wave per look-back word");
@@ -299,35 +299,6 @@ __global__ __launch_bounds__(SB) void k_small_check(const uint32_t *__restrict__
     }
 }
 
-// violation indices of every tile at its offset among all flagged events: each thread
-// lists its flagged indices in LDS at its offset inside the tile, then the tile's run is
-// written out contiguously
-__global__ __launch_bounds__(SB) void k_small_viol(const uint32_t *__restrict__ fw, const uint64_t *__restrict__ offs,
-                                                   uint64_t ntiles, uint32_t *__restrict__ viol)
-{
-    __shared__ uint32_t s_idx[STILE];
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t o0 = offs[tile], total = offs[tile + 1] - o0;
-        if (total == 0)
-            continue; // uniform: no flagged event in the tile
-        const uint32_t word = fw[tile * SB + threadIdx.x];
-        uint32_t flags = word & 0xFFFFu, o = word >> 16;
-        const uint32_t my0 = (uint32_t)(tile * STILE) + threadIdx.x * SE;
-        while (flags) {
-            const uint32_t b = __builtin_ctz(flags);
-            flags &= flags - 1;
-            if (o < STILE)
-                s_idx[o] = my0 + b;
-            o++;
-        }
-        __syncthreads();
-        const uint32_t cnt = total < (uint64_t)STILE ? (uint32_t)total : (uint32_t)STILE;
-        for (uint32_t i = threadIdx.x; i < cnt; i += SB)
-            viol[o0 + i] = s_idx[i];
-        __syncthreads();
-    }
-}
-
 } // namespace
 
 // scratch: look-back words, tile counts, their offsets, the chunk scan's scratch, the
@@ -382,11 +353,7 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
     }
     // the violation count lands in ctl->n_viol
     launch_excl_scan(L.tcnt, tiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan, ctl->tickets[8], s);
-    {
-        ProfScope prof_(s, "small_viol");
-        const unsigned grid = (unsigned)(tiles < 8192 ? tiles : 8192);
-        k_small_viol<<<grid, SB, 0, s>>>(L.fw, L.offs, tiles, viol);
-    }
+    launch_flag_scatter(L.fw, L.offs, tiles, SB, viol, s);
 }
 
 } // namespace vc
