@@ -36,6 +36,8 @@ struct BucketLayout {
     void *xscan = nullptr; // scratch of the scan of the tile counts
     uint32_t *part = nullptr;
     uint32_t *dstidx = nullptr; // per word: its position in the partitioned order
+    uint16_t *li16 = nullptr;   // per word: its position in its tile's bucket-sorted order
+    uint32_t *tpre = nullptr;   // per partition tile: start of every bucket's run
     uint8_t *res = nullptr;
     uint64_t ptiles = 0, btiles_max = 0;
 };

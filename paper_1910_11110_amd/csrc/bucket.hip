@@ -357,14 +357,16 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restri
 // Workgroup j partitions the tiles of histogram parts [j * HIST_SPLIT, (j + 1) *
 // HIST_SPLIT) in order, keeping the running
 // global start of every bucket in LDS (from the column scan): no look-back, no tickets.
-// Every word's position in the partitioned order is stored at its own index in dstidx
-// for the replay.
+// For the replay, either every word's position in the partitioned order is stored at its
+// own index in dstidx, or (li16, tpre) its position inside its tile's bucket-sorted order
+// and, per tile, the start of every bucket's run (row `tile` of tpre).
 template <class SRC>
 __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
                                                      int bits, const uint64_t *__restrict__ base,
                                                      const uint32_t *__restrict__ gpre, uint32_t nranges,
                                                      uint32_t nrows,
                                                      uint32_t *__restrict__ dst, uint32_t *__restrict__ dstidx,
+                                                     uint16_t *__restrict__ li16, uint32_t *__restrict__ tpre,
                                                      uint64_t ntiles)
 {
     __shared__ uint32_t s_words[PTILE];
@@ -444,6 +446,8 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
                 if (b < nb) {
                     s_dstart[b] = ex;
                     const uint32_t r = s_run[b];
+                    if (tpre)
+                        tpre[tile * nb + b] = r;
                     s_gbase[b] = (int64_t)r - (int64_t)ex;
                     s_run[b] = r + v[k];
                 }
@@ -456,7 +460,10 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
             uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
             if (((valid >> j) & 1u) && li < PTILE) {
                 s_words[li] = w[j];
-                dstidx[wb + (uint64_t)j * WAVE + lane] = (uint32_t)(s_gbase[d[j]] + li);
+                if (li16)
+                    li16[wb + (uint64_t)j * WAVE + lane] = (uint16_t)li;
+                else
+                    dstidx[wb + (uint64_t)j * WAVE + lane] = (uint32_t)(s_gbase[d[j]] + li);
             }
         }
         __syncthreads();
@@ -816,28 +823,104 @@ __device__ __forceinline__ void store16(uint8_t *__restrict__ out, uint64_t n, u
 }
 
 // status bytes in program order; per thread its flag mask and offset among the flagged
-// events of its tile, per tile the count (placed by a scan and a scatter pass)
-__global__ __launch_bounds__(BLOCK) void k_replay_status(const uint32_t *__restrict__ dstidx, uint64_t n,
+// events of its tile, per tile the count (placed by a scan and a scatter pass).  A tile's
+// result bytes are the runs res[tpre[tile][b] .. tpre[tile + 1][b]) of its buckets, in
+// the tile's bucket-sorted order: they are copied run by run into LDS, and every word
+// takes its byte at its position li16 in that order.
+__global__ __launch_bounds__(BLOCK) void k_replay_status(const uint16_t *__restrict__ li16,
+                                                         const uint32_t *__restrict__ tpre,
+                                                         const uint64_t *__restrict__ base, uint32_t nb, uint64_t n,
                                                          const uint8_t *__restrict__ res, uint8_t *__restrict__ status,
                                                          uint32_t *__restrict__ fw, uint32_t *__restrict__ tcnt,
                                                          uint64_t ntiles)
 {
     static_assert(P_ITEMS == FLAG_EVENTS, "one flag word per thread");
+    constexpr int BPT = MAX_BUCKETS / BLOCK; // buckets per thread
+    __shared__ __align__(16) uint8_t s_res[PTILE];
+    __shared__ uint32_t s_start[MAX_BUCKETS + 1]; // run starts in the tile's sorted order
+    __shared__ uint32_t s_src[MAX_BUCKETS];       // run starts in res
+    __shared__ uint16_t s_bkt[PTILE];             // bucket of every sorted position
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     // tiles are independent: a plain grid-stride loop
     for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t my0 = tile * PTILE + (uint64_t)tid * 16;
-        // 16 consecutive status bytes per thread
-        uint32_t q[4];
-        gather16(dstidx, res, n, my0, q);
-        store16(status, n, my0, q);
-        uint32_t flags = 0;
+        const uint64_t t0 = tile * PTILE;
+        const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)PTILE ? n - t0 : (uint64_t)PTILE);
+        // run lengths (the next tile's run starts where this one's ends), their scan
+        uint32_t len[BPT], sum = 0;
 #pragma unroll
-        for (int k = 0; k < 16; k++) {
-            const uint32_t byte = (q[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-            if (my0 + k < n)
-                flags |= ((byte >> 7) & 1u) << k;
+        for (int k = 0; k < BPT; k++) {
+            const uint32_t b = tid * BPT + k;
+            uint32_t l = 0;
+            if (b < nb) {
+                const uint32_t r0 = tpre[tile * nb + b];
+                const uint32_t r1 = tile + 1 < ntiles ? tpre[(tile + 1) * nb + b] : (uint32_t)base[b + 1];
+                s_src[b] = r0;
+                l = r1 - r0;
+            }
+            len[k] = l;
+            sum += l;
+        }
+        uint32_t ex = block_excl_scan_u32(sum, s_tmp);
+#pragma unroll
+        for (int k = 0; k < BPT; k++) {
+            const uint32_t b = tid * BPT + k;
+            if (b < nb)
+                s_start[b] = ex;
+            ex += len[k];
+        }
+        if (tid == 0)
+            s_start[nb] = tn;
+        __syncthreads();
+        // bucket of every sorted position, then the runs copied with consecutive lanes on
+        // consecutive positions (a few runs, a few cache lines per wave load)
+#pragma unroll
+        for (int k = 0; k < BPT; k++) {
+            const uint32_t b = tid * BPT + k;
+            if (b < nb)
+                for (uint32_t p = s_start[b]; p < s_start[b + 1]; p++)
+                    s_bkt[p] = (uint16_t)b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < P_ITEMS; k++) {
+            const uint32_t p = k * BLOCK + tid;
+            if (p < tn) {
+                const uint32_t b = s_bkt[p];
+                const uint64_t j = (uint64_t)s_src[b] + (p - s_start[b]);
+                s_res[p] = res[j < n ? j : n - 1];
+            }
+        }
+        __syncthreads();
+        // 16 consecutive words per thread
+        const uint64_t my0 = t0 + (uint64_t)tid * 16;
+        uint32_t q[4] = {0, 0, 0, 0};
+        uint32_t flags = 0;
+        if (my0 + 16 <= n) {
+            const uint4 *lv = reinterpret_cast<const uint4 *>(li16 + my0);
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const uint4 v = lv[h];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    const uint32_t li = (w[k >> 1] >> (16 * (k & 1))) & (PTILE - 1);
+                    const uint32_t byte = s_res[li];
+                    const int e = h * 8 + k;
+                    q[e >> 2] |= byte << (8 * (e & 3));
+                    flags |= ((byte >> 7) & 1u) << e;
+                }
+            }
+            *reinterpret_cast<uint4 *>(status + my0) = make_uint4(q[0], q[1], q[2], q[3]);
+        } else {
+            for (int e = 0; e < 16; e++) {
+                if (my0 + e < n) {
+                    const uint32_t byte = s_res[li16[my0 + e] & (PTILE - 1)];
+                    status[my0 + e] = (uint8_t)byte;
+                    flags |= ((byte >> 7) & 1u) << e;
+                }
+            }
         }
         const uint32_t c = __builtin_popcount(flags);
         const uint32_t inc = wave_scan_add(c, lane);
@@ -911,6 +994,8 @@ static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
     L.fw = (uint32_t *)take(ptiles * BLOCK * 4);
     L.part = (uint32_t *)take((n ? n : 1) * 4);
     L.dstidx = (uint32_t *)take((n ? n : 1) * 4);
+    L.li16 = (uint16_t *)take((n ? n : 1) * 2);
+    L.tpre = (uint32_t *)take(ptiles * nb * 4);
     L.res = (uint8_t *)take(n ? n : 1);
     L.ptiles = ptiles;
     L.btiles_max = btiles;
@@ -970,8 +1055,11 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     uint8_t *res = direct_out;
     if (L.nb > 1) {
         ProfScope p(s, "partition");
+        // the trace check replays by tile runs, the translation by destinations
+        const bool runs = mode == BK_STATUS;
         k_partition<SRC><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, nrows, L.part,
-                                                   L.dstidx, L.ptiles);
+                                                   runs ? nullptr : L.dstidx, runs ? L.li16 : nullptr,
+                                                   runs ? L.tpre : nullptr, L.ptiles);
         part = L.part;
         res = L.res;
     }
@@ -1007,7 +1095,8 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     {
         ProfScope p(s, "replay_status");
         const unsigned grid = resident_grid((const void *)k_replay_status, L.ptiles);
-        k_replay_status<<<grid, BLOCK, 0, s>>>(L.dstidx, n, L.res, status, L.fw, L.tcnt, L.ptiles);
+        k_replay_status<<<grid, BLOCK, 0, s>>>(L.li16, L.tpre, L.base, L.nb, n, L.res, status, L.fw, L.tcnt,
+                                               L.ptiles);
     }
     // the violation count lands in ctl->n_viol
     launch_excl_scan(L.tcnt, L.ptiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan,
