@@ -190,10 +190,19 @@ __global__ __launch_bounds__(SB) void k_small_check(const uint32_t *__restrict__
             const uint32_t id = iv[j] & 63u, code = (iv[j] >> 8) & 7u;
             const uint32_t ct = (uint32_t)-(int32_t)((code >> 2) & 1u), cx = (uint32_t)-(int32_t)((code >> 1) & 1u),
                            cy = (uint32_t)-(int32_t)(code & 1u);
-            const uint32_t m = 1u << (id & 31u);
-            const uint32_t mlo = id < 32 ? m : 0u, mhi = id < 32 ? 0u : m;
-            lo = fn_compose(Fn32{mlo & ct, mlo & cx, mlo & cy}, lo);
-            hi = fn_compose(Fn32{mhi & ct, mhi & cx, mhi & cy}, hi);
+            // the event's variable lives in one half: its new bits are computed from that
+            // half and inserted under the variable's mask
+            const bool up = id >= 32;
+            const uint32_t m = 1u << (id & 31u), mlo = up ? 0u : m, mhi = up ? m : 0u;
+            const uint32_t ft = up ? hi.t : lo.t, fx = up ? hi.x : lo.x, fy = up ? hi.y : lo.y;
+            const uint32_t nx = (ct & cx) | (~ct & (fx | (cx & (~ft | fy))));
+            const uint32_t ny = (ct & cy) | (~ct & (fy | (cy & (~ft | fx))));
+            lo.t |= mlo & ct;
+            hi.t |= mhi & ct;
+            lo.x = (mlo & nx) | (~mlo & lo.x);
+            hi.x = (mhi & nx) | (~mhi & hi.x);
+            lo.y = (mlo & ny) | (~mlo & lo.y);
+            hi.y = (mhi & ny) | (~mhi & hi.y);
         }
 
         // ---- 2. composition of the tile's events before this thread ------------------
