@@ -282,6 +282,63 @@ __device__ __forceinline__ void emit_decl_lds(uint32_t wd, uint32_t n_vars, uint
     nflag += reads ? 2u * gflag + rflag : 0u;
 }
 
+// The same from a table: everything a declaration emits, apart from its variable and
+// positions, depends only on its mode, its side and the pre-status.  Entry
+// mode << 3 | side << 2 | pre-status: bits 0-3 the guard's op and side (event word bits
+// 24-27), 4-11 the guard's status byte, 12-19 the status byte of w (on v# and in the
+// body), 20-27 that of the body's r, 28-29 the number of flagged events among them.
+__device__ __forceinline__ uint32_t decl_table_entry(uint32_t idx)
+{
+    const uint32_t mode = (idx >> 3) & 3u, side = (idx >> 2) & 1u, st = idx & 3u;
+    if (mode > 2)
+        return 0;
+    const bool reads = mode != 1u;
+    const bool valid = (st >> side) & 1u;
+    const uint32_t gop = valid ? OP_NOOP : (side ? OP_PUSH : OP_PULL);
+    const uint32_t gf4 = valid ? TABLE.f4[fcode(OP_NOOP, 0)]
+                               : (side ? TABLE.f4[fcode(OP_PUSH, 0)] : TABLE.f4[fcode(OP_PULL, 0)]);
+    const uint32_t gstk = valid ? 0u : (side ? TABLE.stuck[fcode(OP_PUSH, 0)] : TABLE.stuck[fcode(OP_PULL, 0)]);
+    const uint32_t gpost = fapply(gf4, st), gflag = (gstk >> st) & 1u;
+    const uint32_t gbits = gop | ((valid ? side : 0u) << 3);
+    const uint32_t gbyte = gpost | (st << 2) | (gflag << 7);
+    const uint32_t s1 = reads ? gpost : st;
+    const uint32_t wbyte = fapply(side ? TABLE.f4[fcode(OP_W, 1)] : TABLE.f4[fcode(OP_W, 0)], s1) | (s1 << 2);
+    const uint32_t rstk = side ? TABLE.stuck[fcode(OP_R, 1)] : TABLE.stuck[fcode(OP_R, 0)];
+    const uint32_t rflag = (rstk >> s1) & 1u;
+    const uint32_t rf4 = side ? TABLE.f4[fcode(OP_R, 1)] : TABLE.f4[fcode(OP_R, 0)];
+    const uint32_t rbyte = fapply(rf4, s1) | (s1 << 2) | (rflag << 7);
+    const uint32_t nfl = reads ? 2u * gflag + rflag : 0u;
+    return gbits | (gbyte << 4) | (wbyte << 12) | (rbyte << 20) | (nfl << 28);
+}
+
+// Stores without branches: an event that the declaration does not have (or whose
+// position is not below `end`, which consistent counts never give) goes to the lane's own
+// spare slot `spare`, which the write-out never reads.
+__device__ __forceinline__ void emit_decl_tab(uint32_t wd, uint32_t n_vars, uint32_t st, uint32_t slot_p,
+                                              uint32_t body_p, uint32_t end, uint32_t spare, uint32_t *ev,
+                                              uint8_t *stat, uint32_t &nflag, const uint32_t *tab)
+{
+    const bool ok = decl_ok(wd, n_vars);
+    const uint32_t v = ok ? wd & 0xFFFFFFu : 0u, mode = ok ? (wd >> 24) & 3u : 0u, side = (wd >> 27) & 1u;
+    const uint32_t e = tab[(mode << 3) | (side << 2) | st];
+    const bool reads = mode != 1u, writes = mode != 0u;
+    const uint32_t sbit = side << 27, vabs = n_vars + v;
+    const uint32_t gword = (e & 15u) << 24;
+    const uint8_t gbyte = (uint8_t)(e >> 4), wbyte = (uint8_t)(e >> 12), rbyte = (uint8_t)(e >> 20);
+    const uint32_t pw = slot_p + (reads ? 2u : 0u), pbw = body_p + (reads ? 1u : 0u);
+    auto put = [&](bool has, uint32_t p, uint32_t word, uint8_t byte) {
+        const uint32_t q = has && p < end ? p : spare;
+        ev[q] = word;
+        stat[q] = byte;
+    };
+    put(reads, slot_p, v | gword, gbyte);
+    put(reads, slot_p + 1, vabs | gword, gbyte);
+    put(writes, pw, vabs | (OP_W << 24) | sbit, wbyte);
+    put(reads, body_p, v | (OP_R << 24) | sbit, rbyte);
+    put(writes, pbw, v | (OP_W << 24) | sbit, wbyte);
+    nflag += e >> 28;
+}
+
 // adds the wave's flagged events to the global count (one atomic per wave that has any)
 __device__ __forceinline__ void add_flagged(uint32_t nflag, unsigned long long *n_flagged)
 {
@@ -596,8 +653,8 @@ struct WaveTile {
     // staged events at index off + i, off = (first output index) mod 4: groups of four
     // staged entries line up with 16-byte groups of the event output and 4-byte groups
     // of the status output
-    __align__(16) uint32_t ev[WECAP + 4];
-    __align__(16) uint8_t st[WECAP + 4];
+    __align__(16) uint32_t ev[WECAP + 4 + WAVE]; // + one spare slot per lane
+    __align__(16) uint8_t st[WECAP + 4 + WAVE];
     uint64_t coff[WCOMPS + 1];
     // per non-empty component, by its rank among them: staged index of its first slot
     // event minus the slot prefix at its first declaration (low word), and the same for
@@ -632,7 +689,11 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     uint64_t ntiles, Control *ctl, unsigned long long *__restrict__ n_flagged, uint64_t cap)
 {
     __shared__ WaveTile s_tiles[BLOCK / WAVE];
+    __shared__ uint32_t s_decl_tab[32];
     const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    if (threadIdx.x < 32)
+        s_decl_tab[threadIdx.x] = decl_table_entry(threadIdx.x);
+    __syncthreads();
     WaveTile &L = s_tiles[wave];
     uint32_t nflag = 0;
     // vector write-out needs 16-byte aligned events and 4-byte aligned statuses
@@ -742,8 +803,9 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 started += (uint32_t)__builtin_popcountll(sm);
                 if (i < nd) {
                     const uint64_t ab = L.cab[owner];
-                    emit_decl_lds(dw[k], n_vars, pr[k], (uint32_t)ab + (sx[k] & 0xFFFFu),
-                                  (uint32_t)(ab >> 32) + (sx[k] >> 16), lim, L.ev, L.st, nflag);
+                    emit_decl_tab(dw[k], n_vars, pr[k], (uint32_t)ab + (sx[k] & 0xFFFFu),
+                                  (uint32_t)(ab >> 32) + (sx[k] >> 16), lim, WECAP + 4 + lane, L.ev, L.st, nflag,
+                                  s_decl_tab);
                 }
             }
             __builtin_amdgcn_wave_barrier();
