@@ -644,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_fused(const uint64_t *
 // staged in the wave's LDS and written out contiguously; a tile whose declarations or
 // events do not fit, or whose offsets are malformed (reported with the component's
 // index), is written in place, one component per lane.
-constexpr int WCOMPS = 32;  // components per wave tile
+constexpr int WCOMPS = 40;  // components per wave tile
 constexpr int WDCAP = 256;  // declarations staged per wave tile
 constexpr int WROUNDS = WDCAP / WAVE;
 constexpr int WECAP = 768;  // events staged per wave tile
@@ -747,6 +747,9 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             uint32_t carry = 0;
 #pragma unroll
             for (int k = 0; k < WROUNDS; k++) {
+                sx[k] = 0;
+                if (k * WAVE >= nd)
+                    continue; // uniform: no declaration in this round
                 const uint32_t i = k * WAVE + lane;
                 uint32_t m = 0;
                 if (i < nd) {
