@@ -606,15 +606,23 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             __syncthreads();
         }
 
-        // segmented scan over the sorted items (blocked: thread t owns t*16 ..)
+        // segmented scan over the sorted items (blocked: thread t owns t*16 ..).  A
+        // segment that starts and ends in this thread stores its aggregate (the tile's
+        // function for its local id) at its last item; the thread's first segment, when
+        // it started earlier, gets the carry from the scan below first.
         const uint32_t first = tid * B_ITEMS;
         uint32_t acc = F_ID, headseen = 0;
         uint32_t prevloc = first == 0 ? 0xFFFFu : loc_of(s_b[first - 1]);
+        const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_b[first + B_ITEMS]) : 0xFFFFu;
         uint32_t x[B_ITEMS];
         uint32_t heads = 0;
 #pragma unroll
-        for (int j = 0; j < B_ITEMS; j++) {
+        for (int j = 0; j < B_ITEMS; j++)
             x[j] = s_b[first + j];
+        uint32_t lead = F_ID;  // composition of the items before the thread's first head
+        bool lead_ends = false; // ... and that run ends inside this thread
+#pragma unroll
+        for (int j = 0; j < B_ITEMS; j++) {
             const uint32_t loc = loc_of(x[j]);
             if (loc != prevloc) {
                 heads |= 1u << j;
@@ -623,6 +631,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
             }
             prevloc = loc;
             acc = fcompose(s_f4[(x[j] >> 12) & 15u], acc);
+            const uint32_t nloc = j + 1 < B_ITEMS ? loc_of(x[j + 1]) : after;
+            if (nloc != loc) {
+                if (headseen)
+                    s_agg[loc] = (uint8_t)mon_code(acc);
+                else
+                    lead_ends = true;
+            }
+            if (!headseen)
+                lead = acc;
         }
         // segmented scan of (flag, function) across threads: a segment restarts the
         // composition, so the carry into a thread is the composition since the last head
@@ -655,20 +672,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
                 break;
         }
         uint32_t texc = wexf ? wexc : fcompose(wexc, cw);
-        // tile aggregate per local id: inclusive value at each segment's last item
-        {
-            uint32_t a = texc;
-            const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_b[first + B_ITEMS]) : 0xFFFFu;
-#pragma unroll
-            for (int j = 0; j < B_ITEMS; j++) {
-                if ((heads >> j) & 1u)
-                    a = F_ID;
-                a = fcompose(s_f4[(x[j] >> 12) & 15u], a);
-                const uint32_t nloc = j + 1 < B_ITEMS ? loc_of(x[j + 1]) : after;
-                if (nloc != loc_of(x[j]))
-                    s_agg[loc_of(x[j])] = (uint8_t)mon_code(a);
-            }
-        }
+        // the thread's first segment, begun before it, ending inside it
+        if (lead_ends && !(heads & 1u))
+            s_agg[loc_of(x[0])] = (uint8_t)mon_code(fcompose(lead, texc));
         __syncthreads();
 
         // look-back on the dense per-id state of the bucket: 20 ids per 64-bit word as bit
