@@ -26,7 +26,7 @@ struct BucketLayout {
     uint32_t *hist = nullptr;
     uint64_t *base = nullptr;
     uint32_t *tbase = nullptr;
-    uint32_t *order = nullptr; // bucket tile (bucket-major index) taken by each ticket
+    uint2 *order = nullptr; // per ticket: bucket tile (bucket-major index), (index in bucket | bucket << 22)
     uint32_t *gsum = nullptr, *gpre = nullptr; // per tile range: bucket counts, their column prefix
     uint64_t *lbv = nullptr;
     // trace check: per partition tile the count of flagged events and its offset among

@@ -321,9 +321,10 @@ __global__ __launch_bounds__(1024) void k_bucket_bases(const uint32_t *__restric
 // has more than r tiles, in bucket order.  A tile's look-back only waits on earlier
 // tiles of its own bucket, which come in earlier rounds; interleaving the buckets keeps
 // few tiles of one bucket in flight at once, so its walks stay short.  Tile (b, r) goes
-// to position sum_b' min(T_b', r) + #{b' < b : T_b' > r}.
+// to position sum_b' min(T_b', r) + #{b' < b : T_b' > r}; the entry holds the tile's
+// bucket-major index, its index r in its bucket and the bucket.
 __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restrict__ tbase, uint32_t nb,
-                                                        uint32_t *__restrict__ order)
+                                                        uint2 *__restrict__ order)
 {
     __shared__ uint32_t s_t[MAX_BUCKETS + 1];
     for (uint32_t i = threadIdx.x; i <= nb; i += BLOCK)
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restri
         k += t2 < r ? t2 : r;
         k += (b2 < b && t2 > r) ? 1u : 0u;
     }
-    order[k] = G;
+    order[k] = make_uint2(G, r | (b << 22)); // tile, its index in the bucket | bucket
 }
 
 // ----------------------------------------------------------------------------------
@@ -493,26 +494,27 @@ __device__ __forceinline__ uint32_t to_byte_lsbs(uint32_t v) { return ((v & 0xFu
 __device__ __forceinline__ uint32_t loc_of(uint32_t p) { return p & 0xFFFu; }
 
 template <int MODE, class SRC>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void k_bucket_scan(const uint32_t *__restrict__ part, uint32_t n_ids,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_bucket_scan(const uint32_t *__restrict__ part, uint32_t n_ids,
                                                        uint32_t nb, const uint64_t *__restrict__ base,
                                                        const uint32_t *__restrict__ tbase,
                                                        const uint8_t *__restrict__ init, uint8_t *__restrict__ out,
                                                        uint8_t *__restrict__ final_out, uint32_t final_dup,
                                                        uint64_t *__restrict__ lbv,
                                                        uint32_t *__restrict__ ticket,
-                                                       const uint32_t *__restrict__ order)
+                                                       const uint2 *__restrict__ order)
 {
     __shared__ uint32_t s_a[BTILE];
     __shared__ uint32_t s_b[BTILE];
     __shared__ uint32_t s_cnt[4 * 64];
     __shared__ uint32_t s_dst[64];
     // per local id (padded to whole look-back words): 3-bit monoid code of the tile's
-    // function, status entering the tile
+    // function; the same bytes then hold the status entering the tile (each look-back
+    // thread reads its codes before it writes its statuses)
     __shared__ __align__(16) uint8_t s_agg[LB_WORDS * 20];
-    __shared__ __align__(16) uint8_t s_state[LB_WORDS * 20];
-    __shared__ uint8_t s_res[BTILE];
+    uint8_t *const s_state = s_agg;
+    // result bytes by tile position, in s_a once the sort no longer needs it
+    uint8_t *const s_res = reinterpret_cast<uint8_t *>(s_a);
     __shared__ uint32_t s_f4[16], s_stuck[16];
-    __shared__ uint32_t s_tbase[MAX_BUCKETS + 1];
     __shared__ uint32_t s_wagg[BLOCK / WAVE], s_wflag[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
 
@@ -521,26 +523,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(3))) void
         s_f4[tid] = TABLE.f4[tid];
         s_stuck[tid] = TABLE.stuck[tid];
     }
-    for (uint32_t i = tid; i <= nb; i += BLOCK)
-        s_tbase[i] = tbase[i];
     __syncthreads();
-    const uint32_t ntiles = s_tbase[nb];
+    const uint32_t ntiles = tbase[nb];
     for (;;) {
         const uint32_t k = take_ticket(ticket, &s_tile);
         if (k >= ntiles)
             break;
-        const uint32_t g = order[k]; // bucket-major index of the tile
-        // bucket of this tile: largest b with tbase[b] <= g
-        uint32_t lo = 0, hi = nb;
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (s_tbase[mid] <= g)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        const uint32_t b = lo;
-        const uint32_t ti = g - s_tbase[b];        // tile within the bucket
+        const uint2 o = order[k];
+        const uint32_t g = o.x;                 // bucket-major index of the tile
+        const uint32_t b = o.y >> 22;           // its bucket
+        const uint32_t ti = o.y & ((1u << 22) - 1); // tile within the bucket
         const uint64_t b0 = base[b], b1 = base[b + 1];
         const uint64_t t0 = b0 + (uint64_t)ti * BTILE;
         const uint32_t cnt = (uint32_t)(b1 - t0 < (uint64_t)BTILE ? b1 - t0 : (uint64_t)BTILE);
@@ -992,7 +984,7 @@ static BucketLayout carve(char *p0, uint64_t n, uint32_t n_ids, size_t *bytes)
     L.gpre = (uint32_t *)take((size_t)MAX_RANGES * nb * 4);
     L.base = (uint64_t *)take((MAX_BUCKETS + 1) * 8);
     L.tbase = (uint32_t *)take((MAX_BUCKETS + 1) * 4);
-    L.order = (uint32_t *)take(btiles * 4);
+    L.order = (uint2 *)take(btiles * 8);
     L.lbv = (uint64_t *)take(btiles * LB_WORDS * 8);
     L.tcnt = (uint32_t *)take(ptiles * 4);
     L.offs = (uint64_t *)take((ptiles + 1) * 8);
