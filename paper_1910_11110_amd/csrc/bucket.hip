@@ -360,9 +360,11 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restri
 // global start of every bucket in LDS (from the column scan): no look-back, no tickets.
 // For the replay, either every word's position in the partitioned order is stored at its
 // own index in dstidx, or (li16, tpre) its position inside its tile's bucket-sorted order
-// and, per tile, the start of every bucket's run (row `tile` of tpre).
-template <class SRC>
-__global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
+// and, per tile, the start of every bucket's run (row `tile` of tpre).  MAXB bounds the
+// number of buckets (LDS tables sized for it); global positions are kept modulo 2^32
+// (they are below 2^32).
+template <class SRC, int MAXB>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 256 ? 4 : 3))) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
                                                      int bits, const uint64_t *__restrict__ base,
                                                      const uint32_t *__restrict__ gpre, uint32_t nranges,
                                                      uint32_t nrows,
@@ -370,11 +372,13 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
                                                      uint16_t *__restrict__ li16, uint32_t *__restrict__ tpre,
                                                      uint64_t ntiles)
 {
+    static_assert(MAXB % BLOCK == 0, "whole buckets per thread in the scan");
+    constexpr int BPT = MAXB / BLOCK;
     __shared__ uint32_t s_words[PTILE];
-    __shared__ uint32_t s_cnt[4 * MAX_BUCKETS];
-    __shared__ uint32_t s_dstart[MAX_BUCKETS];
-    __shared__ uint32_t s_run[MAX_BUCKETS];
-    __shared__ int64_t s_gbase[MAX_BUCKETS];
+    __shared__ uint32_t s_cnt[4 * MAXB];
+    __shared__ uint32_t s_dstart[MAXB];
+    __shared__ uint32_t s_run[MAXB];
+    __shared__ uint32_t s_gbase[MAXB]; // global position of the tile's sorted position 0 (mod 2^32)
     __shared__ uint32_t s_tmp[BLOCK / WAVE];
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t nb = 1u << bits;
@@ -398,9 +402,9 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
         load_tile(t0);
     for (uint64_t tile = t0; tile < t1; tile++) {
         const uint64_t tbase = tile * PTILE;
-        // per-wave counters live at [wave * MAX_BUCKETS + bucket]
+        // per-wave counters live at [wave * MAXB + bucket]
         for (uint32_t i = tid; i < 4 * nb; i += BLOCK)
-            s_cnt[(i / nb) * MAX_BUCKETS + (i % nb)] = 0;
+            s_cnt[(i / nb) * MAXB + (i % nb)] = 0;
         __syncthreads();
         uint32_t w[P_ITEMS], d[P_ITEMS], rank[P_ITEMS];
         uint32_t valid = 0;
@@ -415,41 +419,41 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
         if (tile + 1 < t1)
             load_tile(tile + 1);
         if (tbase + PTILE <= n)
-            rank_digits<P_ITEMS, MAX_BUCKETS, false>(d, valid, bits, rank, s_cnt, wave);
+            rank_digits<P_ITEMS, MAXB, false>(d, valid, bits, rank, s_cnt, wave);
         else
-            rank_digits<P_ITEMS, MAX_BUCKETS, true>(d, valid, bits, rank, s_cnt, wave);
+            rank_digits<P_ITEMS, MAXB, true>(d, valid, bits, rank, s_cnt, wave);
         __syncthreads();
         // per bucket: wave offsets and the tile's count
         for (uint32_t b = tid; b < nb; b += BLOCK) {
             uint32_t tc = 0;
             for (uint32_t q = 0; q < 4; q++) {
-                uint32_t c = s_cnt[q * MAX_BUCKETS + b];
-                s_cnt[q * MAX_BUCKETS + b] = tc;
+                uint32_t c = s_cnt[q * MAXB + b];
+                s_cnt[q * MAXB + b] = tc;
                 tc += c;
             }
             s_dstart[b] = tc; // tile count, turned into starts below
         }
         __syncthreads();
-        // exclusive scan of the tile counts over buckets (nb <= 1024, 4 per thread); the
-        // tile's runs start at s_run (stored for the replay), which then advances
+        // exclusive scan of the tile counts over buckets (BPT per thread); the tile's runs
+        // start at s_run (stored for the replay), which then advances
         {
-            uint32_t v[4], sum = 0;
+            uint32_t v[BPT], sum = 0;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                uint32_t b = tid * 4 + k;
+            for (int k = 0; k < BPT; k++) {
+                uint32_t b = tid * BPT + k;
                 v[k] = b < nb ? s_dstart[b] : 0;
                 sum += v[k];
             }
             uint32_t ex = block_excl_scan_u32(sum, s_tmp);
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                uint32_t b = tid * 4 + k;
+            for (int k = 0; k < BPT; k++) {
+                uint32_t b = tid * BPT + k;
                 if (b < nb) {
                     s_dstart[b] = ex;
                     const uint32_t r = s_run[b];
                     if (tpre)
                         tpre[tile * nb + b] = r;
-                    s_gbase[b] = (int64_t)r - (int64_t)ex;
+                    s_gbase[b] = r - ex;
                     s_run[b] = r + v[k];
                 }
                 ex += v[k];
@@ -458,13 +462,13 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < P_ITEMS; j++) {
-            uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAX_BUCKETS + d[j]] + rank[j];
+            uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAXB + d[j]] + rank[j];
             if (((valid >> j) & 1u) && li < PTILE) {
                 s_words[li] = w[j];
                 if (li16)
                     li16[wb + (uint64_t)j * WAVE + lane] = (uint16_t)li;
                 else
-                    dstidx[wb + (uint64_t)j * WAVE + lane] = (uint32_t)(s_gbase[d[j]] + li);
+                    dstidx[wb + (uint64_t)j * WAVE + lane] = s_gbase[d[j]] + li;
             }
         }
         __syncthreads();
@@ -472,9 +476,9 @@ __global__ __launch_bounds__(BLOCK) void k_partition(const uint32_t *__restrict_
         for (uint32_t pos = tid; pos < vn; pos += BLOCK) {
             uint32_t x = s_words[pos];
             uint32_t b = SRC::key(x, n_ids) >> LBITS;
-            int64_t gi = s_gbase[b] + pos;
-            if (gi >= 0 && (uint64_t)gi < n) // always true for consistent counts; never write outside
-                dst[(uint64_t)gi] = x;
+            const uint32_t gi = s_gbase[b] + pos;
+            if (gi < n) // always true for consistent counts; never write outside
+                dst[gi] = x;
         }
         __syncthreads();
     }
@@ -1028,7 +1032,9 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     // static tile ranges shared by the histogram and the partition: as many ranges as
     // partition workgroups are resident at once
     // (the histogram splits every range in HIST_SPLIT, for more workgroups in flight)
-    uint32_t gres = resident_grid((const void *)k_partition<SRC>, L.ptiles);
+    const bool small_nb = L.nb <= 256;
+    const void *part_k = small_nb ? (const void *)k_partition<SRC, 256> : (const void *)k_partition<SRC, MAX_BUCKETS>;
+    uint32_t gres = resident_grid(part_k, L.ptiles);
     gres = gres < (uint32_t)(MAX_RANGES / HIST_SPLIT) ? gres : (uint32_t)(MAX_RANGES / HIST_SPLIT);
     const uint32_t nranges = (uint32_t)(L.ptiles < gres ? L.ptiles : gres);
     const uint32_t nrows = nranges * HIST_SPLIT;
@@ -1055,9 +1061,15 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
         ProfScope p(s, "partition");
         // the trace check replays by tile runs, the translation by destinations
         const bool runs = mode == BK_STATUS;
-        k_partition<SRC><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, nrows, L.part,
-                                                   runs ? nullptr : L.dstidx, runs ? L.li16 : nullptr,
-                                                   runs ? L.tpre : nullptr, L.ptiles);
+        if (small_nb)
+            k_partition<SRC, 256><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, nrows,
+                                                            L.part, runs ? nullptr : L.dstidx,
+                                                            runs ? L.li16 : nullptr, runs ? L.tpre : nullptr, L.ptiles);
+        else
+            k_partition<SRC, MAX_BUCKETS><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges,
+                                                                    nrows, L.part, runs ? nullptr : L.dstidx,
+                                                                    runs ? L.li16 : nullptr, runs ? L.tpre : nullptr,
+                                                                    L.ptiles);
         part = L.part;
         res = L.res;
     }
