@@ -110,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
     for (int j = 0; j < SCAN_ITEMS; j++) {
         uint64_t g = base + first + j;
         if (g >= n)
-            break;
+            continue; // (the items past n are the tile's last: nothing follows them)
         uint32_t pre = (heads >> j) & 1u ? head_state[j] : state;
         uint32_t post = fapply(s_f4[fc[j]], pre);
         uint32_t flag = (s_stuck[fc[j]] >> pre) & 1u;

@@ -311,15 +311,15 @@ __device__ __forceinline__ uint32_t decl_table_entry(uint32_t idx)
     return gbits | (gbyte << 4) | (wbyte << 12) | (rbyte << 20) | (nfl << 28);
 }
 
-// Stores without branches: an event that the declaration does not have (or whose
-// position is not below `end`, which consistent counts never give) goes to the lane's own
-// spare slot `spare`, which the write-out never reads.
+// For a well-formed word (malformed ones are rewritten before), with positions exact by
+// construction (they come from the tile's own arity scan).  Stores without branches: an
+// event the declaration does not have goes to the lane's own spare slot `spare`, which
+// the write-out never reads.
 __device__ __forceinline__ void emit_decl_tab(uint32_t wd, uint32_t n_vars, uint32_t st, uint32_t slot_p,
-                                              uint32_t body_p, uint32_t end, uint32_t spare, uint32_t *ev,
-                                              uint8_t *stat, uint32_t &nflag, const uint32_t *tab)
+                                              uint32_t body_p, uint32_t spare, uint32_t *ev, uint8_t *stat,
+                                              uint32_t &nflag, const uint32_t *tab)
 {
-    const bool ok = decl_ok(wd, n_vars);
-    const uint32_t v = ok ? wd & 0xFFFFFFu : 0u, mode = ok ? (wd >> 24) & 3u : 0u, side = (wd >> 27) & 1u;
+    const uint32_t v = wd & 0xFFFFFFu, mode = (wd >> 24) & 3u, side = (wd >> 27) & 1u;
     const uint32_t e = tab[(mode << 3) | (side << 2) | st];
     const bool reads = mode != 1u, writes = mode != 0u;
     const uint32_t sbit = side << 27, vabs = n_vars + v;
@@ -327,7 +327,7 @@ __device__ __forceinline__ void emit_decl_tab(uint32_t wd, uint32_t n_vars, uint
     const uint8_t gbyte = (uint8_t)(e >> 4), wbyte = (uint8_t)(e >> 12), rbyte = (uint8_t)(e >> 20);
     const uint32_t pw = slot_p + (reads ? 2u : 0u), pbw = body_p + (reads ? 1u : 0u);
     auto put = [&](bool has, uint32_t p, uint32_t word, uint8_t byte) {
-        const uint32_t q = has && p < end ? p : spare;
+        const uint32_t q = has ? p : spare;
         ev[q] = word;
         stat[q] = byte;
     };
@@ -753,7 +753,11 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 const uint32_t i = k * WAVE + lane;
                 uint32_t m = 0;
                 if (i < nd) {
-                    const uint32_t mode = decl_ok(dw[k], n_vars) ? (dw[k] >> 24) & 3u : 0u;
+                    // a malformed declaration becomes R on variable 0 on its side (from
+                    // here on the word is well formed)
+                    if (!decl_ok(dw[k], n_vars))
+                        dw[k] &= 1u << 27;
+                    const uint32_t mode = (dw[k] >> 24) & 3u;
                     m = slot_arity(mode) | (body_arity(mode) << 16);
                 }
                 const uint32_t inc = wave_scan_add(m, lane);
@@ -807,7 +811,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 if (i < nd) {
                     const uint64_t ab = L.cab[owner];
                     emit_decl_tab(dw[k], n_vars, pr[k], (uint32_t)ab + (sx[k] & 0xFFFFu),
-                                  (uint32_t)(ab >> 32) + (sx[k] >> 16), lim, WECAP + 4 + lane, L.ev, L.st, nflag,
+                                  (uint32_t)(ab >> 32) + (sx[k] >> 16), WECAP + 4 + lane, L.ev, L.st, nflag,
                                   s_decl_tab);
                 }
             }
