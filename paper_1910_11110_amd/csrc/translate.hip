@@ -699,11 +699,18 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     // vector write-out needs 16-byte aligned events and 4-byte aligned statuses
     const bool vec_out = (reinterpret_cast<uintptr_t>(out) & 15u) == 0 && (reinterpret_cast<uintptr_t>(status) & 3u) == 0;
     const uint64_t nw = (uint64_t)gridDim.x * (BLOCK / WAVE);
+    // the next tile's component offsets are loaded while this tile is processed
+    auto load_coff = [&](uint64_t t) -> uint64_t {
+        const uint64_t c = t * WCOMPS + lane;
+        return t < ntiles && c <= n_comp && lane <= WCOMPS ? comp_off[c] : 0ull;
+    };
+    uint64_t coff_next = load_coff((uint64_t)blockIdx.x * (BLOCK / WAVE) + wave);
     for (uint64_t wt = (uint64_t)blockIdx.x * (BLOCK / WAVE) + wave; wt < ntiles; wt += nw) {
         const uint64_t c0 = wt * WCOMPS;
         const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)WCOMPS ? n_comp - c0 : (uint64_t)WCOMPS);
         if (lane <= nc)
-            L.coff[lane] = comp_off[c0 + lane];
+            L.coff[lane] = coff_next;
+        coff_next = load_coff(wt + nw);
         reinterpret_cast<uint32_t *>(L.start)[lane] = 0u;
         __builtin_amdgcn_wave_barrier();
         const uint64_t d_lo = L.coff[0], d_hi = L.coff[nc];
