@@ -574,20 +574,15 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                 d[j] = (loc_of(it[j]) >> (6 * pass)) & 63u;
             rank_digits<B_ITEMS, 64, false, 6>(d, 0u, 6, rank, s_cnt, wave);
             __syncthreads();
-            if (tid < 64) {
+            if (tid < 64) { // wave 0, lane = digit: wave offsets, then the digit starts
                 uint32_t tc = 0;
-                for (uint32_t q = 0; q < 4; q++) {
+                for (uint32_t q = 0; q < BLOCK / WAVE; q++) {
                     uint32_t c = s_cnt[q * 64 + tid];
                     s_cnt[q * 64 + tid] = tc;
                     tc += c;
                 }
-                s_dst[tid] = tc;
-            }
-            __syncthreads();
-            if (tid < WAVE) {
-                uint32_t v = s_dst[tid];
-                uint32_t inc = wave_scan_add(v, lane);
-                s_dst[tid] = inc - v;
+                const uint32_t inc = wave_scan_add(tc, lane);
+                s_dst[tid] = inc - tc;
             }
             __syncthreads();
             uint32_t *dstarr = pass == 0 ? s_a : s_b;
