@@ -494,8 +494,12 @@ __device__ __forceinline__ uint32_t to_byte_lsbs(uint32_t v) { return ((v & 0xFu
 // 2. scan inside every bucket
 // ----------------------------------------------------------------------------------
 // in-LDS stable sort of a tile's packed items (local id 12 bits | fcode 4 | pos 12 |
-// 4 spare) by the local id: two 6-bit passes
+// 4 spare) by the local id
 __device__ __forceinline__ uint32_t loc_of(uint32_t p) { return p & 0xFFFu; }
+// in-tile sort of the bucket scan: 4-bit digits, three passes over the 12-bit local id
+constexpr int SORT_BITS = 4;
+constexpr int SORT_DIGITS = 1 << SORT_BITS;
+static_assert(3 * SORT_BITS == LBITS, "three passes cover the local id");
 
 template <int MODE, class SRC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_bucket_scan(const uint32_t *__restrict__ part, uint32_t n_ids,
@@ -507,17 +511,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                        uint32_t *__restrict__ ticket,
                                                        const uint2 *__restrict__ order)
 {
-    __shared__ uint32_t s_a[BTILE];
-    __shared__ uint32_t s_b[BTILE];
-    __shared__ uint32_t s_cnt[4 * 64];
-    __shared__ uint32_t s_dst[64];
+    // the tile's items: tile order, then sorted by local id
+    __shared__ __align__(16) uint32_t s_a[BTILE];
+    // sort counters, digit-major: s_cnt[digit * BLOCK + thread]
+    __shared__ __align__(16) uint32_t s_cnt[SORT_DIGITS * BLOCK];
+    __shared__ uint32_t s_wsum[BLOCK / WAVE];
     // per local id (padded to whole look-back words): 3-bit monoid code of the tile's
     // function; the same bytes then hold the status entering the tile (each look-back
     // thread reads its codes before it writes its statuses)
     __shared__ __align__(16) uint8_t s_agg[LB_WORDS * 20];
     uint8_t *const s_state = s_agg;
-    // result bytes by tile position, in s_a once the sort no longer needs it
-    uint8_t *const s_res = reinterpret_cast<uint8_t *>(s_a);
+    // result bytes by tile position, in the counters once the sort no longer needs them
+    uint8_t *const s_res = reinterpret_cast<uint8_t *>(s_cnt);
     __shared__ uint32_t s_f4[16], s_stuck[16];
     __shared__ uint32_t s_wagg[BLOCK / WAVE], s_wflag[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
@@ -547,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         // tiles; the stable passes leave the padding after all real items (it comes last
         // in tile order and has the largest local id), where it changes no aggregate and
         // its results are not written out.
-        uint32_t it[B_ITEMS], d[B_ITEMS], rank[B_ITEMS];
+        uint32_t it[B_ITEMS];
 #pragma unroll
         for (int j = 0; j < B_ITEMS; j++) {
             const uint32_t pos = wave * WAVE * B_ITEMS + j * WAVE + lane;
@@ -558,42 +563,81 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         }
         for (uint32_t i = tid; i < LB_WORDS * 5; i += BLOCK)
             reinterpret_cast<uint32_t *>(s_agg)[i] = 0; // identity
-        // two stable 6-bit passes: low bits into s_a, then high bits into s_b
+        // tile order into LDS; each thread then takes 16 consecutive positions (blocked)
 #pragma unroll
-        for (int pass = 0; pass < 2; pass++) {
-            for (uint32_t i = tid; i < 4 * 64; i += BLOCK)
-                s_cnt[i] = 0;
-            __syncthreads();
-            if (pass == 1) {
+        for (int j = 0; j < B_ITEMS; j++)
+            s_a[wave * WAVE * B_ITEMS + j * WAVE + lane] = it[j];
 #pragma unroll
-                for (int j = 0; j < B_ITEMS; j++)
-                    it[j] = s_a[wave * WAVE * B_ITEMS + j * WAVE + lane];
+        for (int q = 0; q < SORT_DIGITS; q++)
+            s_cnt[q * BLOCK + tid] = 0;
+        __syncthreads();
+        const uint32_t first = tid * B_ITEMS;
+        // three stable 4-bit counting passes.  Thread t counts its items' digits in its own
+        // counter column; a digit-major scan of all counters gives, for digit q and thread
+        // t, the items of smaller digits plus those of digit q in threads before t; the
+        // thread's items then take their places by a returning add on the same counters,
+        // in item order (the adds of one thread to one address execute in program order).
+#pragma unroll
+        for (int pass = 0; pass < 3; pass++) {
+            uint32_t x[B_ITEMS], ad[B_ITEMS];
+#pragma unroll
+            for (int j4 = 0; j4 < B_ITEMS / 4; j4++) {
+                const uint4 v = reinterpret_cast<const uint4 *>(s_a + first)[j4];
+                x[4 * j4] = v.x;
+                x[4 * j4 + 1] = v.y;
+                x[4 * j4 + 2] = v.z;
+                x[4 * j4 + 3] = v.w;
             }
-#pragma unroll
-            for (int j = 0; j < B_ITEMS; j++)
-                d[j] = (loc_of(it[j]) >> (6 * pass)) & 63u;
-            rank_digits<B_ITEMS, 64, false, 6>(d, 0u, 6, rank, s_cnt, wave);
-            __syncthreads();
-            if (tid < 64) { // wave 0, lane = digit: wave offsets, then the digit starts
-                uint32_t tc = 0;
-                for (uint32_t q = 0; q < BLOCK / WAVE; q++) {
-                    uint32_t c = s_cnt[q * 64 + tid];
-                    s_cnt[q * 64 + tid] = tc;
-                    tc += c;
-                }
-                const uint32_t inc = wave_scan_add(tc, lane);
-                s_dst[tid] = inc - tc;
-            }
-            __syncthreads();
-            uint32_t *dstarr = pass == 0 ? s_a : s_b;
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++) {
-                const uint32_t dj = d[j];
-                // in range for consistent counts (the tile holds BTILE items); the mask
-                // keeps every store inside the array
-                const uint32_t li = (s_dst[dj] + s_cnt[wave * 64 + dj] + rank[j]) & (BTILE - 1);
-                dstarr[li] = it[j];
+                ad[j] = ((loc_of(x[j]) >> (SORT_BITS * pass)) & (SORT_DIGITS - 1)) * BLOCK + tid;
+                atomicAdd(&s_cnt[ad[j]], 1u);
             }
+            __syncthreads();
+            {
+                // thread t scans counters [16 t, 16 t + 16)
+                static_assert(SORT_DIGITS * BLOCK == 16 * BLOCK, "one row of 16 counters per thread");
+                uint4 *c4 = reinterpret_cast<uint4 *>(s_cnt) + tid * 4;
+                uint32_t c[16];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const uint4 v = c4[q];
+                    c[4 * q] = v.x;
+                    c[4 * q + 1] = v.y;
+                    c[4 * q + 2] = v.z;
+                    c[4 * q + 3] = v.w;
+                }
+                uint32_t run = 0;
+#pragma unroll
+                for (int q = 0; q < 16; q++) {
+                    const uint32_t t = c[q];
+                    c[q] = run;
+                    run += t;
+                }
+                const uint32_t inc = wave_scan_add(run, lane);
+                if (lane == WAVE - 1)
+                    s_wsum[wave] = inc;
+                __syncthreads();
+                uint32_t base = inc - run;
+                for (uint32_t w2 = 0; w2 < wave; w2++)
+                    base += s_wsum[w2];
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    c4[q] = make_uint4(c[4 * q] + base, c[4 * q + 1] + base, c[4 * q + 2] + base,
+                                       c[4 * q + 3] + base);
+            }
+            __syncthreads();
+            // the tile's items were all read above; the mask keeps every store inside the
+            // array (consistent counts give positions below BTILE)
+#pragma unroll
+            for (int j = 0; j < B_ITEMS; j++) {
+                const uint32_t r = atomicAdd(&s_cnt[ad[j]], 1u);
+                s_a[r & (BTILE - 1)] = x[j];
+            }
+            // this thread's counter column is touched by no other thread until the barrier
+#pragma unroll
+            for (int q = 0; q < SORT_DIGITS; q++)
+                s_cnt[q * BLOCK + tid] = 0;
             __syncthreads();
         }
 
@@ -601,15 +645,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         // segment that starts and ends in this thread stores its aggregate (the tile's
         // function for its local id) at its last item; the thread's first segment, when
         // it started earlier, gets the carry from the scan below first.
-        const uint32_t first = tid * B_ITEMS;
         uint32_t acc = F_ID, headseen = 0;
-        uint32_t prevloc = first == 0 ? 0xFFFFu : loc_of(s_b[first - 1]);
-        const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_b[first + B_ITEMS]) : 0xFFFFu;
+        uint32_t prevloc = first == 0 ? 0xFFFFu : loc_of(s_a[first - 1]);
+        const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_a[first + B_ITEMS]) : 0xFFFFu;
         uint32_t x[B_ITEMS];
         uint32_t heads = 0;
 #pragma unroll
         for (int j = 0; j < B_ITEMS; j++)
-            x[j] = s_b[first + j];
+            x[j] = s_a[first + j];
         uint32_t lead = F_ID;  // composition of the items before the thread's first head
         bool lead_ends = false; // ... and that run ends inside this thread
 #pragma unroll
@@ -753,7 +796,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             for (int j = 0; j < B_ITEMS; j++) {
                 if ((heads >> j) & 1u)
                     a = F_ID;
-                const uint32_t xj = s_b[first + j]; // re-read: keeps the items out of registers across the look-back
+                const uint32_t xj = s_a[first + j]; // re-read: keeps the items out of registers across the look-back
                 const uint32_t loc = loc_of(xj), fcj = (xj >> 12) & 15u;
                 const uint32_t fj = s_f4[fcj];
                 const uint32_t pre = fapply(a, s_state[loc]);
