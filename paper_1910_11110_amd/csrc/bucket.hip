@@ -253,39 +253,52 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restric
 }
 
 // Column scan of the per-range bucket counts (column-major, row r of bucket b at
-// b * nrows + r): gpre = counts of bucket b in rows before r; tot[b] = all of bucket b.
-// One wave per bucket, each lane a run of consecutive rows, a wave scan over the lanes'
-// sums.
-constexpr int COLSCAN_ROWS = MAX_RANGES / WAVE; // rows per lane
+// b * nrows + r).  The partition needs the counts of bucket b in the rows before each
+// range's first row (every HIST_SPLIT-th row): gpre[b * (nrows / HIST_SPLIT) + range];
+// tot[b] = all of bucket b.  One workgroup per bucket, each thread 16 consecutive rows
+// (four 16-byte loads), a block scan over the threads' sums.
+constexpr int COLSCAN_ROWS = MAX_RANGES / BLOCK; // rows per thread
+static_assert(COLSCAN_ROWS == 16 && HIST_SPLIT == 4, "four 16-byte groups of rows, one range start each");
 __global__ __launch_bounds__(BLOCK) void k_bucket_colscan(const uint32_t *__restrict__ gsum, uint32_t nb,
                                                           uint32_t nrows, uint32_t *__restrict__ gpre,
                                                           uint32_t *__restrict__ tot)
 {
-    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
-    const uint32_t b = blockIdx.x * (BLOCK / WAVE) + wave;
-    if (b >= nb)
-        return;
-    const uint32_t per = (nrows + WAVE - 1) / WAVE;
-    const uint32_t r0 = lane * per;
-    uint32_t v[COLSCAN_ROWS];
+    __shared__ uint32_t s_w[BLOCK / WAVE];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
+    const uint32_t b = blockIdx.x;
+    // nrows is a whole number of ranges (HIST_SPLIT rows each), so a 16-byte group of
+    // rows is entirely in or entirely out, and the column starts 16-byte aligned
+    const uint4 *col = reinterpret_cast<const uint4 *>(gsum + (uint64_t)b * nrows);
+    uint4 v[4];
     uint32_t sum = 0;
 #pragma unroll
-    for (int k = 0; k < COLSCAN_ROWS; k++) {
-        const uint32_t j = r0 + k;
-        v[k] = (k < (int)per && j < nrows) ? gsum[(uint64_t)b * nrows + j] : 0u;
-        sum += v[k];
+    for (int q = 0; q < 4; q++) {
+        const uint32_t r = tid * COLSCAN_ROWS + 4u * q;
+        v[q] = r < nrows ? col[r / 4] : make_uint4(0, 0, 0, 0);
+        sum += v[q].x + v[q].y + v[q].z + v[q].w;
     }
     const uint32_t inc = wave_scan_add(sum, lane);
-    uint32_t run = inc - sum;
-#pragma unroll
-    for (int k = 0; k < COLSCAN_ROWS; k++) {
-        const uint32_t j = r0 + k;
-        if (k < (int)per && j < nrows)
-            gpre[(uint64_t)b * nrows + j] = run;
-        run += v[k];
-    }
     if (lane == WAVE - 1)
-        tot[b] = inc;
+        s_w[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (uint32_t w2 = 0; w2 < wave; w2++)
+        run += s_w[w2];
+    const uint32_t nranges = nrows / HIST_SPLIT;
+    uint32_t pre[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        pre[q] = run;
+        run += v[q].x + v[q].y + v[q].z + v[q].w;
+    }
+    const uint32_t r0 = tid * (COLSCAN_ROWS / HIST_SPLIT); // first range of this thread
+    uint32_t *out = gpre + (uint64_t)b * nranges;
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        if (r0 + q < nranges)
+            out[r0 + q] = pre[q];
+    if (tid == BLOCK - 1)
+        tot[b] = run;
 }
 
 // bucket bases (exclusive scan of the histogram) and first tile of every bucket
@@ -323,33 +336,38 @@ __global__ __launch_bounds__(1024) void k_bucket_bases(const uint32_t *__restric
 // few tiles of one bucket in flight at once, so its walks stay short.  Tile (b, r) goes
 // to position sum_b' min(T_b', r) + #{b' < b : T_b' > r}; the entry holds the tile's
 // bucket-major index, its index r in its bucket and the bucket.
+// One wave per tile G (bucket-major index); the lanes take the buckets in turn.
 __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restrict__ tbase, uint32_t nb,
                                                         uint2 *__restrict__ order)
 {
-    __shared__ uint32_t s_t[MAX_BUCKETS + 1];
-    for (uint32_t i = threadIdx.x; i <= nb; i += BLOCK)
-        s_t[i] = tbase[i];
-    __syncthreads();
-    const uint32_t ntiles = s_t[nb];
-    const uint32_t G = blockIdx.x * BLOCK + threadIdx.x;
+    const uint32_t lane = lane_id();
+    const uint32_t G = blockIdx.x * (BLOCK / WAVE) + threadIdx.x / WAVE;
+    const uint32_t ntiles = tbase[nb];
     if (G >= ntiles)
         return;
-    uint32_t lo = 0, hi = nb; // bucket of G: largest b with tbase[b] <= G
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_t[mid] <= G)
-            lo = mid;
-        else
-            hi = mid;
+    // G's bucket b is the largest with tbase[b] <= G (tbase does not decrease), and its
+    // index r in b is G - tbase[b]
+    uint32_t nle = 0, start = 0;
+    for (uint32_t b2 = lane; b2 < nb; b2 += WAVE) {
+        const uint32_t t = tbase[b2];
+        if (b2 > 0 && t <= G)
+            nle++;
+        if (t <= G && t > start)
+            start = t;
     }
-    const uint32_t b = lo, r = G - s_t[b];
+    const uint32_t b = wave_total_u32(nle);
+    start = __builtin_amdgcn_readlane(wave_scan_dpp(start, 0u, [](uint32_t x, uint32_t y) { return x > y ? x : y; }),
+                                      WAVE - 1);
+    const uint32_t r = G - start;
     uint32_t k = 0;
-    for (uint32_t b2 = 0; b2 < nb; b2++) {
-        const uint32_t t2 = s_t[b2 + 1] - s_t[b2];
+    for (uint32_t b2 = lane; b2 < nb; b2 += WAVE) {
+        const uint32_t t2 = tbase[b2 + 1] - tbase[b2];
         k += t2 < r ? t2 : r;
         k += (b2 < b && t2 > r) ? 1u : 0u;
     }
-    order[k] = make_uint2(G, r | (b << 22)); // tile, its index in the bucket | bucket
+    k = wave_total_u32(k);
+    if (lane == 0)
+        order[k] = make_uint2(G, r | (b << 22)); // tile, its index in the bucket | bucket
 }
 
 // ----------------------------------------------------------------------------------
@@ -367,7 +385,6 @@ template <class SRC, int MAXB>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 256 ? 4 : 3))) void k_partition(const uint32_t *__restrict__ src, uint64_t n, uint32_t n_ids,
                                                      int bits, const uint64_t *__restrict__ base,
                                                      const uint32_t *__restrict__ gpre, uint32_t nranges,
-                                                     uint32_t nrows,
                                                      uint32_t *__restrict__ dst, uint32_t *__restrict__ dstidx,
                                                      uint16_t *__restrict__ li16, uint32_t *__restrict__ tpre,
                                                      uint64_t ntiles)
@@ -383,7 +400,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 2
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t nb = 1u << bits;
     for (uint32_t b = tid; b < nb; b += BLOCK)
-        s_run[b] = (uint32_t)base[b] + gpre[(uint64_t)b * nrows + (uint64_t)blockIdx.x * HIST_SPLIT];
+        s_run[b] = (uint32_t)base[b] + gpre[(uint64_t)b * nranges + blockIdx.x];
     uint64_t t0, t1;
     split_range(ntiles, (uint64_t)nranges * HIST_SPLIT, (uint64_t)blockIdx.x * HIST_SPLIT, t0, t1);
     t1 = ((uint64_t)blockIdx.x + 1) * HIST_SPLIT * ntiles / ((uint64_t)nranges * HIST_SPLIT);
@@ -1058,15 +1075,23 @@ BucketLayout bucket_layout(void *scratch, uint64_t n, uint32_t n_ids)
 
 uint32_t bucket_max_ids() { return (uint32_t)MAX_BUCKETS * LOC; }
 
+FillJob bucket_lookback(void *scratch, uint64_t n, uint32_t n_ids)
+{
+    const BucketLayout L = bucket_layout(scratch, n, n_ids);
+    return FillJob{L.lbv, (size_t)L.btiles_max * LB_WORDS * sizeof(uint64_t), 0};
+}
+
 // histogram, partition and per-bucket scan; result bytes land in L.res (partitioned
 // order), or in `direct_out` (program order) when everything is one bucket.  The final
 // statuses go to final_out, and also to final_out + final_dup when final_dup > 0.
 template <class SRC>
 static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, const uint8_t *init, int mode,
                                uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
-                               hipStream_t s, int cu, uint32_t *chunk_sum = nullptr, uint32_t final_dup = 0)
+                               hipStream_t s, int cu, uint32_t *chunk_sum = nullptr, uint32_t final_dup = 0,
+                               bool lookback_cleared = false)
 {
-    launch_clear_lookback(L.lbv, L.btiles_max * LB_WORDS, ctl->tickets[9], s);
+    if (!lookback_cleared)
+        launch_clear_lookback(L.lbv, L.btiles_max * LB_WORDS, ctl->tickets[9], s);
     // static tile ranges shared by the histogram and the partition: as many ranges as
     // partition workgroups are resident at once
     // (the histogram splits every range in HIST_SPLIT, for more workgroups in flight)
@@ -1082,8 +1107,7 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     }
     {
         ProfScope p(s, "bucket_colscan");
-        k_bucket_colscan<<<(unsigned)ceil_div(L.nb, BLOCK / WAVE), BLOCK, 0, s>>>(L.gsum, L.nb, nrows, L.gpre,
-                                                                                 L.hist);
+        k_bucket_colscan<<<L.nb, BLOCK, 0, s>>>(L.gsum, L.nb, nrows, L.gpre, L.hist);
     }
     {
         ProfScope p(s, "bucket_bases");
@@ -1091,7 +1115,7 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     }
     {
         ProfScope p(s, "bucket_order");
-        k_bucket_order<<<(unsigned)ceil_div(L.btiles_max, BLOCK), BLOCK, 0, s>>>(L.tbase, L.nb, L.order);
+        k_bucket_order<<<(unsigned)ceil_div(L.btiles_max, BLOCK / WAVE), BLOCK, 0, s>>>(L.tbase, L.nb, L.order);
     }
     const uint32_t *part = src;
     uint8_t *res = direct_out;
@@ -1100,12 +1124,12 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
         // the trace check replays by tile runs, the translation by destinations
         const bool runs = mode == BK_STATUS;
         if (small_nb)
-            k_partition<SRC, 256><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges, nrows,
+            k_partition<SRC, 256><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges,
                                                             L.part, runs ? nullptr : L.dstidx,
                                                             runs ? L.li16 : nullptr, runs ? L.tpre : nullptr, L.ptiles);
         else
             k_partition<SRC, MAX_BUCKETS><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges,
-                                                                    nrows, L.part, runs ? nullptr : L.dstidx,
+                                                                    L.part, runs ? nullptr : L.dstidx,
                                                                     runs ? L.li16 : nullptr, runs ? L.tpre : nullptr,
                                                                     L.ptiles);
         part = L.part;
@@ -1168,13 +1192,13 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
 
 DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre,
                                            uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
-                                           uint32_t *chunk_sum)
+                                           uint32_t *chunk_sum, bool lookback_cleared)
 {
     if (n_decl == 0)
         return DeclPre{pre, nullptr};
     BucketLayout L = bucket_layout(scratch, n_decl, n_vars);
     partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu, chunk_sum,
-                                  n_vars);
+                                  n_vars, lookback_cleared);
     if (L.nb == 1)
         return DeclPre{pre, nullptr};
     return DeclPre{L.res, L.dstidx};

@@ -139,13 +139,14 @@ void launch_flag_scatter(const uint32_t *fw, const uint64_t *offs, uint64_t ntil
 size_t compact_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, CTILE) * sizeof(uint64_t); }
 
 void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
-                    const unsigned long long *flagged, const unsigned long long *n_dev)
+                    const unsigned long long *flagged, const unsigned long long *n_dev, bool lookback_cleared)
 {
     if (n == 0)
         return;
     uint64_t tiles = ceil_div(n, CTILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
-    launch_clear_lookback(lb, tiles, ctl->tickets[2], s);
+    if (!lookback_cleared)
+        launch_clear_lookback(lb, tiles, ctl->tickets[2], s);
     {
         ProfScope prof_(s, "compact");
         k_compact<<<resident_grid((const void *)k_compact, tiles), BLOCK, 0, s>>>(status, n, viol, lb, ctl->tickets[2],

@@ -53,12 +53,22 @@ void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 void launch_reset_control(Control *c, hipStream_t s, Control *c2 = nullptr);
 // zeroes n look-back words and the ticket counters of one kernel (one launch)
 void launch_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket, hipStream_t s);
+// one launch for the set-up of a pipeline: resets c and c2 (either may be null; their
+// ticket counters included) and fills every job's bytes with its value
+struct FillJob {
+    void *p;
+    size_t bytes;
+    uint8_t value;
+};
+constexpr int MAX_FILL_JOBS = 4;
+void launch_prep(Control *c, Control *c2, const FillJob *jobs, int njobs, hipStream_t s);
 
 // exclusive scan of n uint32 counts into n+1 uint64 offsets (out[n] = total, also
 // stored to *total when non-null); scratch of excl_scan_scratch_bytes(n)
 size_t excl_scan_scratch_bytes(uint64_t n);
+// (lookback_cleared: the caller has zeroed the scratch and the ticket counters)
 void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total, void *scratch, uint32_t *ticket,
-                      hipStream_t s);
+                      hipStream_t s, bool lookback_cleared = false);
 
 // ------------------------------- radix sort ---------------------------------------
 // Stable LSD sort of 64-bit items by their 28-bit key (see device.h), key_bits
@@ -105,8 +115,10 @@ size_t compact_scratch_bytes(uint64_t n);
 // it is zero, the list is empty and the status bytes are not read.  When `n_dev` is
 // given, the bytes are the first min(n, *n_dev) (a length known only on the device; n
 // bounds it and sizes the launch).
+// (lookback_cleared: the caller has zeroed the scratch and ctl's ticket counters)
 void launch_compact(const uint8_t *status, uint64_t n, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
-                    const unsigned long long *flagged = nullptr, const unsigned long long *n_dev = nullptr);
+                    const unsigned long long *flagged = nullptr, const unsigned long long *n_dev = nullptr,
+                    bool lookback_cleared = false);
 
 // violation indices from per-thread flag words over FLAG_EVENTS consecutive events each
 // (flag mask | the thread's offset among the flagged events of its tile << 16; tb = 256

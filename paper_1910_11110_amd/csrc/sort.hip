@@ -72,6 +72,49 @@ __global__ void k_reset_control(Control *c, Control *c2)
     }
 }
 
+struct PrepArgs {
+    Control *c[2];
+    uint8_t *p[MAX_FILL_JOBS];
+    uint64_t n[MAX_FILL_JOBS];
+    uint32_t v[MAX_FILL_JOBS];
+    uint32_t njobs;
+};
+
+// workgroups 0 and 1 reset the control blocks; every thread fills its share of each job
+// (bytes up to 16-byte alignment, 16-byte stores, the bytes after the last full store)
+__global__ __launch_bounds__(BLOCK) void k_prep(PrepArgs a)
+{
+    if (blockIdx.x < 2 && a.c[blockIdx.x]) {
+        Control *c = a.c[blockIdx.x];
+        uint32_t *w = reinterpret_cast<uint32_t *>(c);
+        for (uint32_t t = threadIdx.x; t < sizeof(Control) / 4; t += blockDim.x)
+            w[t] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            c->err_index_lo = 0xFFFFFFFFu;
+            c->err_index_hi = 0xFFFFFFFFu;
+        }
+    }
+    const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x, stride = (uint64_t)gridDim.x * BLOCK;
+    for (uint32_t j = 0; j < a.njobs; j++) {
+        uint8_t *p = a.p[j];
+        const uint64_t n = a.n[j];
+        const uint8_t v = (uint8_t)a.v[j];
+        const uint32_t v4 = a.v[j] * 0x01010101u;
+        const uint64_t mis = (16u - (uint32_t)(reinterpret_cast<uintptr_t>(p) & 15u)) & 15u;
+        const uint64_t head = mis < n ? mis : n;
+        const uint64_t body = (n - head) / 16;
+        if (tid < head)
+            p[tid] = v;
+        uint4 *q = reinterpret_cast<uint4 *>(p + head);
+        for (uint64_t i = tid; i < body; i += stride)
+            q[i] = make_uint4(v4, v4, v4, v4);
+        const uint64_t t0 = head + body * 16;
+        if (tid < n - t0)
+            p[t0 + tid] = v;
+    }
+}
+
 // histograms of every pass's digit, over all items
 __global__ __launch_bounds__(BLOCK) void k_hist(const uint64_t *__restrict__ items, uint64_t n, int passes,
                                                 int bits, uint32_t *__restrict__ hist)
@@ -278,6 +321,25 @@ void launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s)
 void launch_reset_control(Control *c, hipStream_t s, Control *c2)
 {
     k_reset_control<<<c2 ? 2 : 1, 256, 0, s>>>(c, c2);
+}
+
+void launch_prep(Control *c, Control *c2, const FillJob *jobs, int njobs, hipStream_t s)
+{
+    PrepArgs a{};
+    a.c[0] = c;
+    a.c[1] = c2;
+    uint64_t most = 0;
+    for (int j = 0; j < njobs && j < MAX_FILL_JOBS; j++) {
+        a.p[a.njobs] = (uint8_t *)jobs[j].p;
+        a.n[a.njobs] = jobs[j].p ? jobs[j].bytes : 0;
+        a.v[a.njobs] = jobs[j].value;
+        most = a.n[a.njobs] / 16 > most ? a.n[a.njobs] / 16 : most;
+        a.njobs++;
+    }
+    unsigned grid = grid_for(most ? most : 1, 4);
+    if (grid < 2)
+        grid = 2;
+    k_prep<<<grid, BLOCK, 0, s>>>(a);
 }
 
 void launch_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket, hipStream_t s)

@@ -98,22 +98,27 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
             t->own_events = true;
         }
         t->n = 0; // set from the device when the work is collected
-        launch_reset_control(tr.ctl, s, t->ctl);
-        // final store: each real variable ends where its abstract variable ends (both
-        // halves written by the scan; variables it never touches keep (V,I))
+        // one set-up launch: both control blocks (with their ticket counters), the look-back
+        // words of the bucket scan, of the chunk scan and of the compaction, and the final
+        // store: each real variable ends where its abstract variable ends (both halves
+        // written by the scan; variables it never touches keep (V,I))
         uint8_t *fin = (uint8_t *)t->fin.p;
-        launch_fill_u8(fin, 1, 2 * (size_t)tr.n_vars, s);
+        char *xscan = (char *)tr.scratch.p + bucket_bytes;
+        const FillJob jobs[4] = {bucket_lookback(tr.scratch.p, n_decl, tr.n_vars),
+                                 FillJob{xscan, excl_scan_scratch_bytes(nchunks), 0},
+                                 FillJob{t->scratch.p, compact_scratch_bytes(cap), 0},
+                                 FillJob{fin, 2 * (size_t)tr.n_vars, 1}};
+        launch_prep(tr.ctl, t->ctl, jobs, 4, s);
         const DeclPre pre =
             launch_bucket_decl_pre_partitioned(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, fin, tr.scratch.p,
-                                               tr.ctl, s, t->ctx->cu_count, (uint32_t *)tr.cnt.p);
+                                               tr.ctl, s, t->ctx->cu_count, (uint32_t *)tr.cnt.p, true);
         // the translated length lands in tr.ctl->n_out
         launch_excl_scan((uint32_t *)tr.cnt.p, nchunks, (uint64_t *)tr.pos.p,
-                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), (char *)tr.scratch.p + bucket_bytes,
-                         tr.ctl->tickets[4], s);
+                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), xscan, tr.ctl->tickets[4], s, true);
         launch_translate_emit_fused_dev(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, pre.res, pre.dstidx,
                                         (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, tr.ctl, t->ctl, s);
         launch_compact((uint8_t *)t->status.p, cap, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s,
-                       &t->ctl->n_flagged, &tr.ctl->n_out);
+                       &t->ctl->n_flagged, &tr.ctl->n_out, true);
         return VC_OK;
     }
     // counts and positions of each component's translated events

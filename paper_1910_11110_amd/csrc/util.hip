@@ -111,7 +111,7 @@ unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap, int blo
 size_t excl_scan_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, XTILE) * sizeof(uint64_t); }
 
 void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total, void *scratch, uint32_t *ticket,
-                      hipStream_t s)
+                      hipStream_t s, bool lookback_cleared)
 {
     if (n == 0) {
         launch_fill_u64(out, 0, 1, s);
@@ -121,7 +121,8 @@ void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *t
     }
     uint64_t tiles = ceil_div(n, XTILE);
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
-    launch_clear_lookback(lb, tiles, ticket, s);
+    if (!lookback_cleared)
+        launch_clear_lookback(lb, tiles, ticket, s);
     {
         ProfScope prof_(s, "excl_scan");
         k_excl_scan<<<resident_grid((const void *)k_excl_scan, tiles), BLOCK, 0, s>>>(in, n, out, total, lb, ticket,
