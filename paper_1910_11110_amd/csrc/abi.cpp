@@ -371,14 +371,13 @@ int enqueue_check(vc_trace *t, hipStream_t s)
             (r = devbuf_reserve(t->viol, (t->n ? t->n : 1) * 4)) != VC_OK ||
             (r = devbuf_reserve(t->scratch, small_scratch_bytes(t->n))) != VC_OK)
             return r;
-        launch_reset_control(t->ctl, s);
+        // the initial statuses are copied, or written as (V,I) by the set-up launch
         uint8_t *fin = (uint8_t *)t->fin.p;
+        const FillJob fill{fin, t->n_ids, 1};
         if (t->init)
             (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
-        else
-            launch_fill_u8(fin, 1, t->n_ids, s);
         launch_small_check(t->events, t->n, t->n_ids, t->init, (uint8_t *)t->status.p, fin, (uint32_t *)t->viol.p,
-                           t->scratch.p, t->ctl, s, 8u * (unsigned)t->ctx->cu_count);
+                           t->scratch.p, t->ctl, s, 8u * (unsigned)t->ctx->cu_count, t->init ? nullptr : &fill);
         return VC_OK;
     }
     if (use_bucket_path(t)) {
@@ -387,14 +386,12 @@ int enqueue_check(vc_trace *t, hipStream_t s)
             (r = devbuf_reserve(t->viol, (t->n ? t->n : 1) * 4)) != VC_OK ||
             (r = devbuf_reserve(t->scratch, bucket_scratch_bytes(t->n, t->n_ids))) != VC_OK)
             return r;
-        launch_reset_control(t->ctl, s);
         uint8_t *fin = (uint8_t *)t->fin.p;
+        const FillJob fill{fin, t->n_ids, 1};
         if (t->init)
             (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
-        else
-            launch_fill_u8(fin, 1, t->n_ids, s);
         launch_bucket_check(t->events, t->n, t->n_ids, t->init, (uint8_t *)t->status.p, fin, (uint32_t *)t->viol.p,
-                            t->scratch.p, t->ctl, s, t->ctx->cu_count);
+                            t->scratch.p, t->ctl, s, t->ctx->cu_count, t->init ? nullptr : &fill);
         return VC_OK;
     }
     uint64_t m = t->n;

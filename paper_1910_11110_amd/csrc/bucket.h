@@ -48,10 +48,11 @@ size_t bucket_scratch_bytes(uint64_t n, uint32_t n_ids);
 BucketLayout bucket_layout(void *scratch, uint64_t n, uint32_t n_ids);
 
 // plain check of n events over n_ids <= bucket_max_ids() ids: status bytes in program
-// order, final table (pre-filled with the initial statuses by the caller), violations
-// (count into ctl->n_viol)
+// order, final table (holding the initial statuses, or filled by fin_fill in the set-up
+// launch), violations (count into ctl->n_viol).  Resets ctl first.
 void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
-                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu);
+                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu,
+                         const FillJob *fin_fill);
 
 // status of each declaration's abstract variable before it, in program order, and the
 // final status of every abstract variable (final_out pre-filled by the caller; may be

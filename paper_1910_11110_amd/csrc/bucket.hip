@@ -1153,15 +1153,29 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
 }
 
 void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
-                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu)
+                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu,
+                         const FillJob *fin_fill)
 {
+    BucketLayout L = bucket_layout(scratch, n, n_ids);
+    // one set-up launch: the control block, the look-back words of the bucket scan and of
+    // the scan after it (or of the compaction, which the flag words' area holds: 1 KiB
+    // per tile against its 8 bytes per tile), and the caller's fill of the final table
+    FillJob jobs[3];
+    int nj = 0;
+    jobs[nj++] = FillJob{L.lbv, (size_t)L.btiles_max * LB_WORDS * sizeof(uint64_t), 0};
+    if (L.nb == 1)
+        jobs[nj++] = FillJob{L.fw, compact_scratch_bytes(n), 0};
+    else
+        jobs[nj++] = FillJob{L.xscan, excl_scan_scratch_bytes(L.ptiles), 0};
+    if (fin_fill)
+        jobs[nj++] = *fin_fill;
+    launch_prep(ctl, nullptr, jobs, nj, s);
     if (n == 0)
         return;
-    BucketLayout L = bucket_layout(scratch, n, n_ids);
-    partition_and_scan<EventWords>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu);
+    partition_and_scan<EventWords>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu, nullptr, 0,
+                                   true);
     if (L.nb == 1) {
-        // (the flag words' area, 1 KiB per tile, holds the compaction's 8 bytes per tile)
-        launch_compact(status, n, viol, L.fw, ctl, s);
+        launch_compact(status, n, viol, L.fw, ctl, s, nullptr, nullptr, true);
         return;
     }
     {
@@ -1172,7 +1186,7 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     }
     // the violation count lands in ctl->n_viol
     launch_excl_scan(L.tcnt, L.ptiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan,
-                     ctl->tickets[10], s);
+                     ctl->tickets[10], s, true);
     launch_flag_scatter(L.fw, L.offs, L.ptiles, BLOCK, viol, s);
 }
 

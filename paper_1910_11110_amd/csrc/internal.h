@@ -101,12 +101,13 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
 
 // ------------------------------- small id spaces ----------------------------------
 // single-kernel check of a trace over at most small_max_ids() ids (events 16-byte
-// aligned): statuses, final table, violations (count into ctl->n_viol)
+// aligned): statuses, final table (holding the initial statuses, or filled by fin_fill
+// in the set-up launch), violations (count into ctl->n_viol).  Resets ctl first.
 uint32_t small_max_ids();
 size_t small_scratch_bytes(uint64_t n);
 void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
-                        unsigned grid_cap = 1u << 30);
+                        unsigned grid_cap, const FillJob *fin_fill);
 
 // ------------------------------- compaction ---------------------------------------
 size_t compact_scratch_bytes(uint64_t n);

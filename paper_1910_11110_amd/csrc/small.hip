@@ -347,13 +347,18 @@ uint32_t small_max_ids() { return SK; }
 
 void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
-                        unsigned grid_cap)
+                        unsigned grid_cap, const FillJob *fin_fill)
 {
-    if (n == 0)
-        return;
     const uint64_t tiles = ceil_div(n, STILE);
     const SmallLayout L = small_layout(scratch, n);
-    launch_clear_lookback(L.lbv, tiles * SPW, ctl->tickets[7], s);
+    // one set-up launch: the control block, both look-back arrays, the caller's fill
+    FillJob jobs[3] = {FillJob{L.lbv, (size_t)tiles * SPW * sizeof(uint64_t), 0},
+                       FillJob{L.xscan, excl_scan_scratch_bytes(tiles), 0}, FillJob{nullptr, 0, 0}};
+    if (fin_fill)
+        jobs[2] = *fin_fill;
+    launch_prep(ctl, nullptr, jobs, 3, s);
+    if (n == 0)
+        return;
     {
         const unsigned grid = resident_grid((const void *)k_small_check, tiles, grid_cap, SB);
         ProfScope prof_(s, "small_check");
@@ -361,7 +366,8 @@ void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, cons
                                              ctl->tickets[7], tiles, ctl);
     }
     // the violation count lands in ctl->n_viol
-    launch_excl_scan(L.tcnt, tiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan, ctl->tickets[8], s);
+    launch_excl_scan(L.tcnt, tiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan, ctl->tickets[8], s,
+                     true);
     launch_flag_scatter(L.fw, L.offs, tiles, SB, viol, s);
 }
 
