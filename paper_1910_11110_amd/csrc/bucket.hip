@@ -517,6 +517,13 @@ __device__ __forceinline__ uint32_t loc_of(uint32_t p) { return p & 0xFFFu; }
 constexpr int SORT_BITS = 4;
 constexpr int SORT_DIGITS = 1 << SORT_BITS;
 static_assert(3 * SORT_BITS == LBITS, "three passes cover the local id");
+// LDS index of word i of a padded array: 4 spare words after every 64, so that 16 lanes
+// reading 16 consecutive words each (16-byte accesses) fall on distinct banks
+__device__ __forceinline__ uint32_t padw(uint32_t i) { return i + ((i >> 6) << 2); }
+constexpr int PAD_TILE_WORDS = BTILE + BTILE / 16;
+constexpr int PAD_CNT_WORDS = SORT_DIGITS * BLOCK + SORT_DIGITS * BLOCK / 16;
+// counter (digit q, thread t) at padw(q * BLOCK + t) = q * PAD_ROW + padw(t)
+constexpr uint32_t PAD_ROW = BLOCK + BLOCK / 16;
 
 template <int MODE, class SRC>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_bucket_scan(const uint32_t *__restrict__ part, uint32_t n_ids,
@@ -529,9 +536,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                        const uint2 *__restrict__ order)
 {
     // the tile's items: tile order, then sorted by local id
-    __shared__ __align__(16) uint32_t s_a[BTILE];
-    // sort counters, digit-major: s_cnt[digit * BLOCK + thread]
-    __shared__ __align__(16) uint32_t s_cnt[SORT_DIGITS * BLOCK];
+    __shared__ __align__(16) uint32_t s_a[PAD_TILE_WORDS];
+    // sort counters, digit-major: s_cnt[padw(digit * BLOCK + thread)]
+    __shared__ __align__(16) uint32_t s_cnt[PAD_CNT_WORDS];
     __shared__ uint32_t s_wsum[BLOCK / WAVE];
     // per local id (padded to whole look-back words): 3-bit monoid code of the tile's
     // function; the same bytes then hold the status entering the tile (each look-back
@@ -583,12 +590,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         // tile order into LDS; each thread then takes 16 consecutive positions (blocked)
 #pragma unroll
         for (int j = 0; j < B_ITEMS; j++)
-            s_a[wave * WAVE * B_ITEMS + j * WAVE + lane] = it[j];
+            s_a[padw(wave * WAVE * B_ITEMS + j * WAVE + lane)] = it[j];
 #pragma unroll
         for (int q = 0; q < SORT_DIGITS; q++)
-            s_cnt[q * BLOCK + tid] = 0;
+            s_cnt[q * PAD_ROW + padw(tid)] = 0;
         __syncthreads();
-        const uint32_t first = tid * B_ITEMS;
+        // a thread's 16 consecutive words never cross a padding gap
+        static_assert(64 % B_ITEMS == 0, "blocked runs inside one padded row");
+        const uint32_t first = tid * B_ITEMS, pfirst = padw(first), ptid = padw(tid);
         // three stable 4-bit counting passes.  Thread t counts its items' digits in its own
         // counter column; a digit-major scan of all counters gives, for digit q and thread
         // t, the items of smaller digits plus those of digit q in threads before t; the
@@ -596,25 +605,26 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         // in item order (the adds of one thread to one address execute in program order).
 #pragma unroll
         for (int pass = 0; pass < 3; pass++) {
-            uint32_t x[B_ITEMS], ad[B_ITEMS];
+            uint32_t x[B_ITEMS];
+            auto counter = [&](uint32_t xj) {
+                return ((loc_of(xj) >> (SORT_BITS * pass)) & (SORT_DIGITS - 1)) * PAD_ROW + ptid;
+            };
 #pragma unroll
             for (int j4 = 0; j4 < B_ITEMS / 4; j4++) {
-                const uint4 v = reinterpret_cast<const uint4 *>(s_a + first)[j4];
+                const uint4 v = reinterpret_cast<const uint4 *>(s_a + pfirst)[j4];
                 x[4 * j4] = v.x;
                 x[4 * j4 + 1] = v.y;
                 x[4 * j4 + 2] = v.z;
                 x[4 * j4 + 3] = v.w;
             }
 #pragma unroll
-            for (int j = 0; j < B_ITEMS; j++) {
-                ad[j] = ((loc_of(x[j]) >> (SORT_BITS * pass)) & (SORT_DIGITS - 1)) * BLOCK + tid;
-                atomicAdd(&s_cnt[ad[j]], 1u);
-            }
+            for (int j = 0; j < B_ITEMS; j++)
+                atomicAdd(&s_cnt[counter(x[j])], 1u);
             __syncthreads();
             {
                 // thread t scans counters [16 t, 16 t + 16)
                 static_assert(SORT_DIGITS * BLOCK == 16 * BLOCK, "one row of 16 counters per thread");
-                uint4 *c4 = reinterpret_cast<uint4 *>(s_cnt) + tid * 4;
+                uint4 *c4 = reinterpret_cast<uint4 *>(s_cnt + padw(tid * 16));
                 uint32_t c[16];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
@@ -648,13 +658,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             // array (consistent counts give positions below BTILE)
 #pragma unroll
             for (int j = 0; j < B_ITEMS; j++) {
-                const uint32_t r = atomicAdd(&s_cnt[ad[j]], 1u);
-                s_a[r & (BTILE - 1)] = x[j];
+                const uint32_t r = atomicAdd(&s_cnt[counter(x[j])], 1u);
+                s_a[padw(r & (BTILE - 1))] = x[j];
             }
             // this thread's counter column is touched by no other thread until the barrier
 #pragma unroll
             for (int q = 0; q < SORT_DIGITS; q++)
-                s_cnt[q * BLOCK + tid] = 0;
+                s_cnt[q * PAD_ROW + ptid] = 0;
             __syncthreads();
         }
 
@@ -663,13 +673,13 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         // function for its local id) at its last item; the thread's first segment, when
         // it started earlier, gets the carry from the scan below first.
         uint32_t acc = F_ID, headseen = 0;
-        uint32_t prevloc = first == 0 ? 0xFFFFu : loc_of(s_a[first - 1]);
-        const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_a[first + B_ITEMS]) : 0xFFFFu;
+        uint32_t prevloc = first == 0 ? 0xFFFFu : loc_of(s_a[padw(first - 1)]);
+        const uint32_t after = first + B_ITEMS < BTILE ? loc_of(s_a[padw(first + B_ITEMS)]) : 0xFFFFu;
         uint32_t x[B_ITEMS];
         uint32_t heads = 0;
 #pragma unroll
         for (int j = 0; j < B_ITEMS; j++)
-            x[j] = s_a[first + j];
+            x[j] = s_a[pfirst + j];
         uint32_t lead = F_ID;  // composition of the items before the thread's first head
         bool lead_ends = false; // ... and that run ends inside this thread
 #pragma unroll
@@ -813,7 +823,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
             for (int j = 0; j < B_ITEMS; j++) {
                 if ((heads >> j) & 1u)
                     a = F_ID;
-                const uint32_t xj = s_a[first + j]; // re-read: keeps the items out of registers across the look-back
+                const uint32_t xj = s_a[pfirst + j]; // re-read: keeps the items out of registers across the look-back
                 const uint32_t loc = loc_of(xj), fcj = (xj >> 12) & 15u;
                 const uint32_t fj = s_f4[fcj];
                 const uint32_t pre = fapply(a, s_state[loc]);
