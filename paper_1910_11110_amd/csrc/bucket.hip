@@ -172,27 +172,6 @@ __host__ __device__ inline void split_range(uint64_t ntiles, uint64_t parts, uin
     hi = (part + 1) * ntiles / parts;
 }
 
-template <class SRC>
-__device__ __forceinline__ void hist_word(uint32_t w, uint64_t i, bool in, uint32_t n_ids, uint32_t *s_h, Control *ctl)
-{
-    if (in && !SRC::ok(w, n_ids)) {
-        unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
-        atomicMin(e, (unsigned long long)i);
-    }
-    // lanes agreeing with the first active lane add once; the others add alone
-    const uint32_t b = SRC::key(w, n_ids) >> LBITS;
-    const uint32_t b0 = __builtin_amdgcn_readfirstlane(in ? b : 0xFFFFFFFFu);
-    const uint64_t same = __ballot(in && b == b0);
-    if (in) {
-        if (b == b0) {
-            if (mask_rank(same) == 0)
-                atomicAdd(&s_h[b0], (uint32_t)__builtin_popcountll(same));
-        } else {
-            atomicAdd(&s_h[b], 1u);
-        }
-    }
-}
-
 // Bucket histogram of a static range of tiles: workgroup r counts part r of nrows equal
 // parts of the tiles in LDS and stores its per-bucket counts as row r of gsum
 // (column-major; a partition range is HIST_SPLIT consecutive parts).  With chunk_sum, each chunk of
@@ -232,11 +211,28 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_hist(const uint32_t *__restric
                 w[u] = i0 + u < n ? src[i0 + u] : 0u;
         }
         uint32_t a = 0;
+        // a run of one bucket among the thread's consecutive words adds once (a skewed id
+        // distribution makes long runs; one LDS add per word would pile onto one address)
+        uint32_t cur = 0xFFFFFFFFu, run = 0;
 #pragma unroll
         for (int u = 0; u < P_ITEMS; u++) {
-            hist_word<SRC>(w[u], i0 + u, i0 + u < n, n_ids, s_h, ctl);
-            a += i0 + u < n ? SRC::arity(w[u], n_ids) : 0u;
+            const bool in = i0 + u < n;
+            if (in && !SRC::ok(w[u], n_ids)) {
+                unsigned long long *e = reinterpret_cast<unsigned long long *>(&ctl->err_index_lo);
+                atomicMin(e, (unsigned long long)(i0 + u));
+            }
+            const uint32_t b = in ? SRC::key(w[u], n_ids) >> LBITS : 0xFFFFFFFFu;
+            if (b != cur) {
+                if (run)
+                    atomicAdd(&s_h[cur], run);
+                cur = b;
+                run = 0;
+            }
+            run += in ? 1u : 0u;
+            a += in ? SRC::arity(w[u], n_ids) : 0u;
         }
+        if (run)
+            atomicAdd(&s_h[cur], run);
         if (chunk_sum) {
             constexpr int LANES = HCHUNK / P_ITEMS;
 #pragma unroll
