@@ -74,14 +74,8 @@ constexpr int LB_WIN = 4;
 // ----------------------------------------------------------------------------------
 // Digit ranking
 // ----------------------------------------------------------------------------------
-// bit b of v as 0 or all ones.  An opaque v_bfe_i32: the ballot then tests this word
+// bit B of v as 0 or all ones.  An opaque v_bfe_i32: the ballot then tests this word
 // (one compare) instead of the compiler rederiving the bit from v (two more operations).
-__device__ __forceinline__ uint32_t sign_bit(uint32_t v, uint32_t b)
-{
-    uint32_t r;
-    asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(r) : "v"(v), "s"(b));
-    return r;
-}
 template <int B>
 __device__ __forceinline__ uint32_t sign_bit(uint32_t v)
 {
@@ -112,10 +106,10 @@ __device__ __forceinline__ void match_bits(uint32_t d, uint32_t &mlo, uint32_t &
 // The lanes holding the same digit as this lane are found bit by bit: the lane's bit
 // sign-extended to a word (0 or all ones) XNOR the bit's ballot keeps the lanes that
 // agree on it.  With PARTIAL, items whose validmask bit is clear take no part: they get
-// no rank and add to no counter.  CBITS > 0: the digit has CBITS bits (`bits` unused).
+// no rank and add to no counter.  The digit has CBITS bits.
 // ----------------------------------------------------------------------------------
-template <int ITEMS, int MAXD, bool PARTIAL, int CBITS = 0>
-__device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t validmask, int bits,
+template <int ITEMS, int MAXD, bool PARTIAL, int CBITS>
+__device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t validmask,
                                             uint32_t (&rank)[ITEMS], uint32_t *s_cnt /* [4][MAXD] */, uint32_t wave)
 {
 #pragma unroll
@@ -127,12 +121,7 @@ __device__ __forceinline__ void rank_digits(const uint32_t (&d)[ITEMS], uint32_t
             mlo = (uint32_t)vm;
             mhi = (uint32_t)(vm >> 32);
         }
-        if constexpr (CBITS > 0) {
-            match_bits<0, CBITS>(d[j], mlo, mhi);
-        } else {
-            for (int b = 0; b < bits; b++)
-                match_bit(sign_bit(d[j], (uint32_t)b), mlo, mhi);
-        }
+        match_bits<0, CBITS>(d[j], mlo, mhi);
         const uint64_t m = ((uint64_t)mhi << 32) | mlo;
         uint32_t r = mask_rank(m);
         uint32_t c = __builtin_popcountll(m);
@@ -431,10 +420,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 2
         }
         if (tile + 1 < t1)
             load_tile(tile + 1);
+        // ranked on all the bits MAXB buckets take (a bucket index has none above
+        // `bits`), so that the per-bit steps unroll
+        constexpr int RBITS = MAXB <= 256 ? 8 : 10;
+        static_assert((1 << RBITS) == MAXB, "MAXB is 256 or 1024");
         if (tbase + PTILE <= n)
-            rank_digits<P_ITEMS, MAXB, false>(d, valid, bits, rank, s_cnt, wave);
+            rank_digits<P_ITEMS, MAXB, false, RBITS>(d, valid, rank, s_cnt, wave);
         else
-            rank_digits<P_ITEMS, MAXB, true>(d, valid, bits, rank, s_cnt, wave);
+            rank_digits<P_ITEMS, MAXB, true, RBITS>(d, valid, rank, s_cnt, wave);
         __syncthreads();
         // per bucket: wave offsets and the tile's count
         for (uint32_t b = tid; b < nb; b += BLOCK) {
