@@ -97,6 +97,18 @@ extern "C" int vc_ctx_create(int hip_device, void *hip_stream, vc_ctx **out)
         }
         c->own_stream = true;
     }
+    if ((e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess) {
+        if (c->ev_fork)
+            (void)hipEventDestroy(c->ev_fork);
+        if (c->side)
+            (void)hipStreamDestroy(c->side);
+        if (c->own_stream)
+            (void)hipStreamDestroy(c->stream);
+        delete c;
+        return vc_hip_fail(e, "side stream / events");
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
         c->cu_count = prop.multiProcessorCount;
@@ -110,6 +122,7 @@ extern "C" int vc_ctx_destroy(vc_ctx *c)
         return VC_OK;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->side);
     // traces outlive their context only to be freed: detach them
     for (vc_trace *t : c->traces) {
         t->ctx = nullptr;
@@ -117,6 +130,9 @@ extern "C" int vc_ctx_destroy(vc_ctx *c)
     }
     batch_release(c);
     prof_destroy(c);
+    (void)hipEventDestroy(c->ev_join);
+    (void)hipEventDestroy(c->ev_fork);
+    (void)hipStreamDestroy(c->side);
     if (c->own_stream)
         (void)hipStreamDestroy(c->stream);
     delete c;

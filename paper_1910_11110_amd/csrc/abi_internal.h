@@ -40,6 +40,10 @@ struct vc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // a second stream for work that overlaps the main stream's (default priority), with
+    // the events that fork it from and join it back to the main stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int cu_count = 256;
     std::vector<vc_trace *> pending; // traces with enqueued work not yet collected
     std::vector<vc_trace *> traces;  // live traces (detached when the context goes)

@@ -70,10 +70,12 @@ struct DeclPre {
     const uint32_t *dstidx;
 };
 // (lookback_cleared: the caller has zeroed the look-back words, bucket_lookback(), and
-// ctl's ticket counters)
+// ctl's ticket counters; after_hist, when given, is recorded on s once the histogram pass,
+// which writes chunk_sum, is enqueued)
 DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre,
                                            uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
-                                           uint32_t *chunk_sum, bool lookback_cleared = false);
+                                           uint32_t *chunk_sum, bool lookback_cleared = false,
+                                           hipEvent_t after_hist = nullptr);
 // the look-back words of the bucket scan inside `scratch` (as a job that zeroes them)
 FillJob bucket_lookback(void *scratch, uint64_t n, uint32_t n_ids);
 

@@ -1087,7 +1087,7 @@ template <class SRC>
 static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, const uint8_t *init, int mode,
                                uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
                                hipStream_t s, int cu, uint32_t *chunk_sum = nullptr, uint32_t final_dup = 0,
-                               bool lookback_cleared = false)
+                               bool lookback_cleared = false, hipEvent_t after_hist = nullptr)
 {
     if (!lookback_cleared)
         launch_clear_lookback(L.lbv, L.btiles_max * LB_WORDS, ctl->tickets[9], s);
@@ -1104,6 +1104,8 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
         ProfScope p(s, "bucket_hist");
         k_bucket_hist<SRC><<<nrows, BLOCK, 0, s>>>(src, n, n_ids, L.nb, nrows, L.ptiles, L.gsum, ctl, chunk_sum);
     }
+    if (after_hist)
+        (void)hipEventRecord(after_hist, s);
     {
         ProfScope p(s, "bucket_colscan");
         k_bucket_colscan<<<L.nb, BLOCK, 0, s>>>(L.gsum, L.nb, nrows, L.gpre, L.hist);
@@ -1205,13 +1207,13 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
 
 DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre,
                                            uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
-                                           uint32_t *chunk_sum, bool lookback_cleared)
+                                           uint32_t *chunk_sum, bool lookback_cleared, hipEvent_t after_hist)
 {
     if (n_decl == 0)
         return DeclPre{pre, nullptr};
     BucketLayout L = bucket_layout(scratch, n_decl, n_vars);
     partition_and_scan<DeclWords>(decls, n_decl, n_vars, nullptr, BK_PRE, final_out, L, pre, ctl, s, cu, chunk_sum,
-                                  n_vars, lookback_cleared);
+                                  n_vars, lookback_cleared, after_hist);
     if (L.nb == 1)
         return DeclPre{pre, nullptr};
     return DeclPre{L.res, L.dstidx};

@@ -109,12 +109,28 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
                                  FillJob{t->scratch.p, compact_scratch_bytes(cap), 0},
                                  FillJob{fin, 2 * (size_t)tr.n_vars, 1}};
         launch_prep(tr.ctl, t->ctl, jobs, 4, s);
+        // the scan of the chunk counts needs only the histogram pass: it runs on the side
+        // stream while the partition and the bucket scan run, and the emitter waits for it
+        vc_ctx *c = t->ctx;
+        const bool fork = n_decl > 0;
         const DeclPre pre =
             launch_bucket_decl_pre_partitioned(tr.decls, n_decl, tr.n_vars, (uint8_t *)tr.pre_abs.p, fin, tr.scratch.p,
-                                               tr.ctl, s, t->ctx->cu_count, (uint32_t *)tr.cnt.p, true);
+                                               tr.ctl, s, c->cu_count, (uint32_t *)tr.cnt.p, true,
+                                               fork ? c->ev_fork : nullptr);
+        hipStream_t sx = s;
+        if (fork) {
+            if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess)
+                return vc_hip_fail(e, "hipStreamWaitEvent(side)");
+            sx = c->side;
+        }
         // the translated length lands in tr.ctl->n_out
         launch_excl_scan((uint32_t *)tr.cnt.p, nchunks, (uint64_t *)tr.pos.p,
-                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), xscan, tr.ctl->tickets[4], s, true);
+                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), xscan, tr.ctl->tickets[4], sx, true);
+        if (fork) {
+            if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess ||
+                (e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess)
+                return vc_hip_fail(e, "join of the side stream");
+        }
         launch_translate_emit_fused_dev(tr.comp_off, n_comp, tr.decls, n_decl, tr.n_vars, pre.res, pre.dstidx,
                                         (uint64_t *)tr.pos.p, t->events, (uint8_t *)t->status.p, tr.ctl, t->ctl, s);
         launch_compact((uint8_t *)t->status.p, cap, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s,
