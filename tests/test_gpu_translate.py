@@ -129,6 +129,33 @@ def test_translation_device_input_and_rerun(ctx):
     t.free()
 
 
+def test_translation_back_to_back_on_one_context(ctx):
+    """Translations enqueued one after another on one context with a single wait at the
+    end, then one of them run twice more without a wait between: the scan of the chunk
+    counts runs on the context's second stream, forked after each translation's
+    histogram pass and joined before its emitter, so no run may see another's counts."""
+    import torch
+    from paper_1910_11110_amd import vcheck as V
+    cts = [gen.component_trace(300_000, 1 << 16, 11), gen.component_trace(120_000, 1 << 20, 12)]
+    dev = [(torch.from_numpy(c.comp_off.view(np.int64)).cuda(), torch.from_numpy(c.decls.view(np.int32)).cuda())
+           for c in cts]
+    torch.cuda.synchronize()
+    say("[translate] two translations, one wait")
+    ts = [V.translate(ctx, co, de, c.n_vars, check=True) for (co, de), c in zip(dev, cts)]
+    V._check(V.lib().vc_translate_run(ts[0].h))
+    V._check(V.lib().vc_translate_run(ts[0].h))
+    ctx.sync()
+    for t, c in zip(ts, cts):
+        ref_tr = O.translate(c.comp_off, c.decls, c.n_vars)
+        ref = O.check(ref_tr, 2 * c.n_vars)
+        assert np.array_equal(t.events(), ref_tr)
+        assert np.array_equal(t.status(), ref.status)
+        assert np.array_equal(t.final(), ref.final)
+        v = t.violations()
+        assert v.total == ref.violations.size and np.array_equal(v.indices, ref.violations)
+        t.free()
+
+
 def test_translation_malformed_declaration(ctx):
     from paper_1910_11110_amd import vcheck as V
     co = np.array([0, 2], np.uint64)
