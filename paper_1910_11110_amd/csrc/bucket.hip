@@ -315,11 +315,14 @@ __global__ __launch_bounds__(1024) void k_bucket_bases(const uint32_t *__restric
     }
 }
 
-// Order in which the bucket tiles are taken: round r holds tile r of every bucket that
-// has more than r tiles, in bucket order.  A tile's look-back only waits on earlier
-// tiles of its own bucket, which come in earlier rounds; interleaving the buckets keeps
-// few tiles of one bucket in flight at once, so its walks stay short.  Tile (b, r) goes
-// to position sum_b' min(T_b', r) + #{b' < b : T_b' > r}; the entry holds the tile's
+// Order in which the bucket tiles are taken: tile r of bucket b (T_b tiles) at the key
+// (2r + 1) / (2 T_b), its relative place in its bucket, ties in bucket order.  Every
+// bucket's tiles come in their own order, so a tile's look-back only waits on tiles
+// taken before it; and the tiles of small buckets, whose chains are short, are spread
+// over the whole run instead of coming first, so that they keep the CUs busy while a
+// large bucket's chain advances (a skewed id distribution puts most tiles in one
+// bucket).  Tile (b, r) goes to the number of tiles (b', r') with (2r' + 1) T_b <
+// (2r + 1) T_b', plus the ties in buckets b' < b; the entry holds the tile's
 // bucket-major index, its index r in its bucket and the bucket.
 // One wave per tile G (bucket-major index); the lanes take the buckets in turn.
 __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restrict__ tbase, uint32_t nb,
@@ -344,11 +347,24 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_order(const uint32_t *__restri
     start = __builtin_amdgcn_readlane(wave_scan_dpp(start, 0u, [](uint32_t x, uint32_t y) { return x > y ? x : y; }),
                                       WAVE - 1);
     const uint32_t r = G - start;
+    const uint64_t Tb = tbase[b + 1] - tbase[b]; // > 0: bucket b holds tile r
+    const uint64_t q = 2ull * r + 1;
     uint32_t k = 0;
     for (uint32_t b2 = lane; b2 < nb; b2 += WAVE) {
-        const uint32_t t2 = tbase[b2 + 1] - tbase[b2];
-        k += t2 < r ? t2 : r;
-        k += (b2 < b && t2 > r) ? 1u : 0u;
+        const uint64_t T2 = tbase[b2 + 1] - tbase[b2];
+        if (T2 == 0)
+            continue;
+        // tiles r' of b2 with a smaller key: 2r' + 1 <= M
+        const uint64_t qt = q * T2;
+        const uint64_t M = (qt - 1) / Tb;
+        const uint64_t lt = (M + 1) / 2;
+        k += (uint32_t)(lt < T2 ? lt : T2);
+        // a tile of an earlier bucket with the same key
+        if (b2 < b && qt % Tb == 0) {
+            const uint64_t m = qt / Tb;
+            if ((m & 1u) && (m - 1) / 2 < T2)
+                k++;
+        }
     }
     k = wave_total_u32(k);
     if (lane == 0)
