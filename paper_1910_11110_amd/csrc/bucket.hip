@@ -7,7 +7,7 @@
 //    of its tiles by bucket with wave64 ballots, reorders them in LDS, writes every
 //    bucket's run contiguously and stores each word's destination for step 3.
 // 2. bucket scan: every bucket (4096 ids) is scanned in its own tiles.  A tile sorts
-//    its words by the low 12 id bits in LDS (two stable 6-bit ballot passes), runs a
+//    its words by the low 12 id bits in LDS (three stable 4-bit counting passes), runs a
 //    segmented scan of the transition functions, and chains the dense per-id state of
 //    its bucket with the previous tile by a decoupled look-back whose 64-bit words
 //    carry 20 ids each (3-bit codes: a transition function of the 7-element monoid,
