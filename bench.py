@@ -208,6 +208,128 @@ def wl_overlap(args, V, ctx, stream):
                 per_unit=lambda: bytes_alg() / n)
 
 
+def _oracle_sample(inputs, budget_events):
+    """events/s of the oracle over the first traces of `inputs` ((events, n_ids, lo, hi))
+    up to about budget_events events; and how many traces and events that was"""
+    from oracle import oracle as O
+    take, m = [], 0
+    for inp in inputs:
+        if m >= budget_events:
+            break
+        take.append(inp)
+        m += inp[0].size
+    a = time.perf_counter()
+    for ev, nv, lo, hi in take:
+        if lo is None:
+            O.check(ev, nv)
+        else:
+            O.check_overlap(ev, lo, hi)
+    return m / (time.perf_counter() - a), len(take), m
+
+
+def wl_batched(args, V, ctx, stream):
+    """4,096 independent traces (lengths log-uniform in [100, 10^6], variables log-uniform
+    in [8, 65,536], 20 % with array intervals), loaded once; a step is one batched check
+    of all of them (one pipeline, replayed as a HIP graph)."""
+    from paper_1910_11110_amd import gen
+    n_tr = 4096
+    log(f"[bench] generating {n_tr} traces")
+    shapes = gen.trace_shapes(n_tr, args.seed)
+    traces, inputs = [], []
+    for sh in shapes:
+        ev, lo, hi = gen.trace_inputs(sh)
+        t = V.Trace.load(ctx, ev, sh.n_vars)
+        if lo is not None:
+            t.set_arrays(lo, hi)
+        traces.append(t)
+        inputs.append((ev, sh.n_vars, lo, hi))
+    n = sum(sh.length for sh in shapes)
+    log(f"[bench] {n} events; first batched check")
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    viol = sum(t.violations().total for t in traces)
+    ids = sum(sh.n_vars for sh in shapes)
+
+    def step():
+        V.batch_check(ctx, traces)
+
+    def bytes_alg():
+        return 4 * n + n + 4 * viol + ids
+
+    def cpu_sample():
+        v, k, m = _oracle_sample(inputs, 1 << 24)
+        return v, f"oracle check of the first {k} traces ({m} events), one run"
+
+    cfg = {"workload": "batched-4096-traces", "n_traces": n_tr, "n_events": n,
+           "with_arrays": sum(1 for sh in shapes if sh.has_arrays), "violations": int(viol)}
+    return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(traces, inputs),
+                per_unit=lambda: bytes_alg() / n)
+
+
+def wl_served(args, V, ctx, stream):
+    """Served streams: 256 streams (trace lengths log-uniform in [2^16, 2^20], variables
+    log-uniform in [8, 65,536], 20 % with array intervals), each submitting its trace in
+    2^16-event chunks from host memory, all interleaved; the server admits, batches and
+    checks them with the streams' status tables resident on the device.  A step opens
+    the streams, submits every chunk, waits for every completion and closes the streams;
+    it is timed on the host clock and includes the chunks' copies to the device."""
+    from paper_1910_11110_amd import gen
+    n_str, chunk = 256, 1 << 16
+    log(f"[bench] generating {n_str} streams")
+    shapes = gen.trace_shapes(n_str, args.seed, len_range=(1 << 16, 1 << 20))
+    inputs = []
+    for sh in shapes:
+        ev, lo, hi = gen.trace_inputs(sh)
+        inputs.append((ev, sh.n_vars, lo, hi))
+    outs = [np.empty(ev.size, np.uint8) for ev, *_ in inputs]
+    n = sum(ev.size for ev, *_ in inputs)
+    srv = V.Server(ctx, 64 << 30)
+    state = {"lat": [], "viol": 0}
+
+    def step():
+        sids = [srv.open(nv, lo, hi) for _ev, nv, lo, hi in inputs]
+        maxc = max((ev.size + chunk - 1) // chunk for ev, *_ in inputs)
+        want = 0
+        for k in range(maxc):
+            for i, (ev, *_r) in enumerate(inputs):
+                a = k * chunk
+                if a < ev.size:
+                    srv.submit(sids[i], ev[a:a + chunk], outs[i][a:a + chunk])
+                    want += 1
+        lat, viol, got = [], 0, 0
+        while got < want:
+            cs = srv.poll()
+            for c in cs:
+                if c.status != 0:
+                    raise RuntimeError(f"chunk {c.chunk} failed with {c.status}")
+                lat.append(c.t_done - c.t_submit)
+                viol += c.n_violations
+            got += len(cs)
+            if not cs:
+                time.sleep(0.0002)
+        for i, s_ in enumerate(sids):
+            srv.close_stream(s_, inputs[i][1])
+        state["lat"], state["viol"] = lat, viol
+
+    def bytes_alg():
+        return 4 * n + n + 4 * state["viol"] + sum(nv for _e, nv, *_r in inputs)
+
+    def cpu_sample():
+        v, k, m = _oracle_sample(inputs, 1 << 24)
+        return v, f"oracle check of the first {k} streams' traces ({m} events), one run"
+
+    def extra():
+        lat = np.sort(np.asarray(state["lat"], np.float64)) * 1e3
+        return {"serving": {"chunks_per_step": int(lat.size), "chunk_events": chunk,
+                            "latency_ms_p50": round(float(lat[lat.size // 2]), 3),
+                            "latency_ms_p99": round(float(lat[min(lat.size - 1, (lat.size * 99) // 100)]), 3),
+                            "note": "submit-to-done per chunk; the step includes host-to-device copies"}}
+
+    cfg = {"workload": "served-256-streams-2^16-chunks", "n_streams": n_str, "n_events": n}
+    return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(srv, inputs, outs),
+                per_unit=lambda: bytes_alg() / n, host_timed=True, extra=extra)
+
+
 def copy_probe(torch, n_words=1 << 28):
     """One plain elementwise kernel of known traffic (reads and writes 4 * n_words bytes),
     launched before the workload so that a hardware-counter run of this script also
@@ -223,7 +345,8 @@ def copy_probe(torch, n_words=1 << 28):
 
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
              "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
-             "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap}
+             "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap,
+             "batched": wl_batched, "served": wl_served}
 
 
 def main():
@@ -256,12 +379,20 @@ def main():
         w["step"]()
     ctx.sync()
     torch.cuda.synchronize()
-    # timed region: exactly `steps` steps, synchronized on both sides
-    with Timer(stream) as tm:
+    # timed region: exactly `steps` steps, synchronized on both sides (a served step
+    # waits for its own completions and runs on the server's streams: host clock)
+    if w.get("host_timed"):
+        a = time.perf_counter()
         for _ in range(args.steps):
             w["step"]()
-    ctx.sync()
-    ms_step = tm.ms / args.steps
+        ctx.sync()
+        ms_step = (time.perf_counter() - a) * 1e3 / args.steps
+    else:
+        with Timer(stream) as tm:
+            for _ in range(args.steps):
+                w["step"]()
+        ctx.sync()
+        ms_step = tm.ms / args.steps
     value = w["units"] / (ms_step / 1e3)
 
     # per-kernel durations: the same steps again with event pairs around each kernel
@@ -322,6 +453,8 @@ def main():
         "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
         "source_digest": source_digest(),
     }
+    if "extra" in w:
+        out.update(w["extra"]())
     print(json.dumps(out), flush=True)
 
 

@@ -130,6 +130,8 @@ extern "C" int vc_ctx_destroy(vc_ctx *c)
     }
     batch_release(c);
     prof_destroy(c);
+    devbuf_free(c->gather_ptrs);
+    devbuf_free(c->gather_out);
     (void)hipEventDestroy(c->ev_join);
     (void)hipEventDestroy(c->ev_fork);
     (void)hipStreamDestroy(c->side);
@@ -148,9 +150,49 @@ extern "C" int vc_sync(vc_ctx *c)
     if (e != hipSuccess)
         return vc_hip_fail(e, "hipStreamSynchronize");
     prof_collect(c);
+    // finished checks (not translations) are collected together: one gather launch and
+    // one copy instead of one or two small copies per trace
+    std::vector<vc_trace *> many;
+    for (vc_trace *t : c->pending)
+        if (t->check_pending && !t->translate_pending)
+            many.push_back(t);
+    std::vector<uint32_t> hdr;
+    if (many.size() >= 8) {
+        const size_t m = many.size();
+        std::vector<const void *> ptrs(2 * m);
+        for (size_t i = 0; i < m; i++) {
+            ptrs[i] = many[i]->ctl;
+            ptrs[m + i] = many[i]->viol.p;
+        }
+        hdr.resize(m * GATHER_WORDS);
+        int r;
+        if ((r = devbuf_reserve(c->gather_ptrs, 2 * m * sizeof(void *))) != VC_OK ||
+            (r = devbuf_reserve(c->gather_out, hdr.size() * 4)) != VC_OK)
+            return r;
+        const void **dp = (const void **)c->gather_ptrs.p;
+        if ((e = hipMemcpyAsync(dp, ptrs.data(), 2 * m * sizeof(void *), hipMemcpyHostToDevice, c->stream)) !=
+            hipSuccess)
+            return vc_hip_fail(e, "hipMemcpyAsync(control pointers)");
+        launch_gather_headers((const Control *const *)dp, (const uint32_t *const *)(dp + m), (uint32_t)m,
+                              (uint32_t *)c->gather_out.p, c->stream);
+        if ((e = hipMemcpyAsync(hdr.data(), c->gather_out.p, hdr.size() * 4, hipMemcpyDeviceToHost, c->stream)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+            return vc_hip_fail(e, "gather of control headers");
+    }
     int rc = VC_OK;
+    size_t k = 0;
     for (vc_trace *t : c->pending) {
-        int r = trace_collect(t);
+        int r;
+        if (!hdr.empty() && k < many.size() && many[k] == t) {
+            Control h;
+            memcpy(&h, &hdr[k * GATHER_WORDS], CONTROL_HEADER);
+            t->pending = false;
+            r = trace_collect_check(t, h, hdr[k * GATHER_WORDS + CONTROL_HEADER / 4]);
+            k++;
+        } else {
+            r = trace_collect(t);
+        }
         if (r != VC_OK && rc == VC_OK)
             rc = r;
     }
@@ -187,6 +229,15 @@ int trace_collect(vc_trace *t)
     e = hipMemcpy(&h, t->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return vc_hip_fail(e, "hipMemcpy(control)");
+    uint32_t f = 0;
+    if (h.n_viol && (e = hipMemcpy(&f, t->viol.p, sizeof f, hipMemcpyDeviceToHost)) != hipSuccess)
+        return vc_hip_fail(e, "hipMemcpy(first violation)");
+    return trace_collect_check(t, h, f);
+}
+
+// a finished check's counters from its control header and first violation word
+int trace_collect_check(vc_trace *t, const Control &h, uint32_t first_viol)
+{
     uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
     if (bad != ~0ull) {
         t->checked = false;
@@ -198,14 +249,7 @@ int trace_collect(vc_trace *t)
         t->check_pending = false;
         t->n_viol = h.n_viol;
         t->n_induced_stuck = h.n_induced_stuck;
-        t->first = t->n;
-        if (t->n_viol) {
-            uint32_t f = 0;
-            e = hipMemcpy(&f, t->viol.p, sizeof f, hipMemcpyDeviceToHost);
-            if (e != hipSuccess)
-                return vc_hip_fail(e, "hipMemcpy(first violation)");
-            t->first = f;
-        }
+        t->first = t->n_viol ? first_viol : t->n;
         t->checked = true;
         t->error = VC_OK;
     }

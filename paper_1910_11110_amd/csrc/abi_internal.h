@@ -44,6 +44,9 @@ struct vc_ctx {
     // the events that fork it from and join it back to the main stream
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // collection of many finished checks at once: their control-block and violation
+    // pointers, and the gathered headers
+    DevBuf gather_ptrs, gather_out;
     int cu_count = 256;
     std::vector<vc_trace *> pending; // traces with enqueued work not yet collected
     std::vector<vc_trace *> traces;  // live traces (detached when the context goes)
@@ -58,6 +61,7 @@ struct ProfGuard {
     ~ProfGuard();
 };
 void prof_collect(vc_ctx *c);
+int trace_collect_check(vc_trace *t, const vc::Control &h, uint32_t first_viol);
 // VC_OK for a trace whose context is alive; else the error (NULL trace, or a context
 // already destroyed), recorded for vc_last_error under `fn`
 int trace_usable(vc_trace *t, const char *fn);

@@ -340,13 +340,20 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
     std::vector<TraceDesc> desc(n);
     std::vector<uint64_t> ev_off(n + 1), key_off(n + 1), sig;
     uint64_t N = 0, K = 0, M = 0;
+    {
+        // each trace at most once (sorted handles: neighbours)
+        std::vector<std::pair<vc_trace *, uint32_t>> seen(n);
+        for (uint32_t i = 0; i < n; i++)
+            seen[i] = {traces[i], i};
+        std::sort(seen.begin(), seen.end());
+        for (uint32_t i = 1; i < n; i++)
+            if (seen[i].first && seen[i].first == seen[i - 1].first)
+                return vc_fail(VC_EINVAL, "vc_batch_check: trace %u appears twice", seen[i].second);
+    }
     for (uint32_t i = 0; i < n; i++) {
         vc_trace *t = traces[i];
         if (!t || t->ctx != c)
             return vc_fail(VC_EINVAL, "vc_batch_check: trace %u is NULL or belongs to another context", i);
-        for (uint32_t j = 0; j < i; j++)
-            if (traces[j] == t)
-                return vc_fail(VC_EINVAL, "vc_batch_check: trace %u appears twice", i);
         if (t->pending) {
             int r = vc_sync(c);
             if (r != VC_OK)

@@ -53,6 +53,11 @@ void launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 void launch_reset_control(Control *c, hipStream_t s, Control *c2 = nullptr);
 // zeroes n look-back words and the ticket counters of one kernel (one launch)
 void launch_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket, hipStream_t s);
+// the host-read headers of n control blocks and the first violation word of each (read
+// only when its block counts violations), GATHER_WORDS words per block into out
+constexpr uint32_t GATHER_WORDS = CONTROL_HEADER / 4 + 1;
+void launch_gather_headers(const Control *const *ctl, const uint32_t *const *viol, uint32_t n, uint32_t *out,
+                           hipStream_t s);
 // one launch for the set-up of a pipeline: resets c and c2 (either may be null; their
 // ticket counters included) and fills every job's bytes with its value
 struct FillJob {

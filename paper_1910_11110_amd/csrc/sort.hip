@@ -57,6 +57,20 @@ __global__ void k_clear_lookback(uint64_t *lb, size_t n, uint32_t *ticket)
             ticket[t] = 0;
 }
 
+// thread i copies the host-read header of control block ctl[i] to out[i * GATHER_WORDS]
+// and, when that block counts violations, the first word of viol[i] after it
+__global__ void k_gather_headers(const Control *const *ctl, const uint32_t *const *viol, uint32_t n, uint32_t *out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint32_t *h = reinterpret_cast<const uint32_t *>(ctl[i]);
+    uint32_t *o = out + (size_t)i * GATHER_WORDS;
+    for (uint32_t k = 0; k < CONTROL_HEADER / 4; k++)
+        o[k] = h[k];
+    o[CONTROL_HEADER / 4] = ctl[i]->n_viol ? viol[i][0] : 0u;
+}
+
 // workgroup k resets control block k (c, then c2)
 __global__ void k_reset_control(Control *c, Control *c2)
 {
@@ -321,6 +335,13 @@ void launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t s)
 void launch_reset_control(Control *c, hipStream_t s, Control *c2)
 {
     k_reset_control<<<c2 ? 2 : 1, 256, 0, s>>>(c, c2);
+}
+
+void launch_gather_headers(const Control *const *ctl, const uint32_t *const *viol, uint32_t n, uint32_t *out,
+                           hipStream_t s)
+{
+    if (n)
+        k_gather_headers<<<(n + BLOCK - 1) / BLOCK, BLOCK, 0, s>>>(ctl, viol, n, out);
 }
 
 void launch_prep(Control *c, Control *c2, const FillJob *jobs, int njobs, hipStream_t s)
