@@ -9,6 +9,7 @@ arithmetic of the checked method is done in Python.
 from __future__ import annotations
 
 import ctypes as C
+import hashlib
 import os
 import subprocess
 from dataclasses import dataclass
@@ -18,16 +19,33 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "vc_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+STAMP = LIB + ".src"   # digest of the source the library was built from
 
 _lib = None
 
 
+def _digest() -> str:
+    with open(SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _fresh() -> bool:
+    if not (os.path.exists(LIB) and os.path.exists(STAMP)):
+        return False
+    with open(STAMP) as f:
+        return f.read().strip() == _digest()
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no vectorisation flags needed)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    """Compile the oracle with gcc (plain -O2, no vectorisation flags needed).  Called by
+    the build entry point and by the test session's start-up, before any GPU work: a
+    process that holds a GPU never starts a compiler."""
+    if force or not _fresh():
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", SRC, "-o", tmp])
         os.replace(tmp, LIB)
+        with open(STAMP, "w") as f:
+            f.write(_digest() + "\n")
     return LIB
 
 
@@ -53,10 +71,12 @@ def load(path: str):
 
 
 def lib():
+    """The built oracle.  It is never compiled here: a stale or missing library is an
+    error (build it with build(), which the build entry point and the test session run)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build(force=True)
+        if not _fresh():
+            raise RuntimeError(f"{LIB} is missing or older than {SRC}; run oracle.oracle.build() first")
         _lib = load(LIB)
     return _lib
 

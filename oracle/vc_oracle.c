@@ -220,6 +220,8 @@ uint64_t oracle_check_count(const uint32_t *events, uint64_t n, uint32_t n_ids, 
  * Bodies: body_off == NULL gives the canonical body of each declaration in order
  * (R: r x, W: w x, RW: r x; w x, on the component's side); otherwise component c's
  * body is body[body_off[c] .. body_off[c+1]) verbatim (ids < n_vars).
+ * A variable declared twice in one component is malformed (index of the second
+ * declaration in *bad).
  * Returns 0, -1 on a malformed input (index in *bad), -5 if out_cap is too small
  * (then *n_out is the required size and nothing beyond out_cap is written).
  * ------------------------------------------------------------------------------ */
@@ -268,6 +270,16 @@ int oracle_translate(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *
                 if (bad) *bad = d;
                 free(em.sigma);
                 return -1;
+            }
+            /* the declarations joined by a conjunction name distinct variables (syntax
+             * of access modes, Section 3.3): a variable declared a second time in the
+             * same component is malformed input */
+            for (uint64_t e = a; e < d; e++) {
+                if ((decls[e] & 0xFFFFFFu) == v) {
+                    if (bad) *bad = d;
+                    free(em.sigma);
+                    return -1;
+                }
             }
             uint32_t abs_v = n_vars + v;
             if (mode == 0 || mode == 2) { /* R or RW: guarded transfer */

@@ -30,6 +30,7 @@ MUTANTS = {
     "overlap-rule3-ignores-premise": ("if (!(j >= 0 && ((m[j] >> 24) & 3u) == 1))", "if (1)"),
     "overlap-rw-not-inferred": ("if (mode == 2) /* RW x# */\n                    need_rw = 1;", "\n"),
     "induced-rw-wrong-side": ("cur = apply_effect(OP_W, side, cur, &st2);", "cur = apply_effect(OP_W, !side, cur, &st2);"),
+    "repeated-variable-accepted": ("if ((decls[e] & 0xFFFFFFu) == v) {", "if (0) {"),
     "overlap-inclusive-upper": ("return x != y && lo[x] < hi[y] && lo[y] < hi[x];",
                                 "return x != y && lo[x] <= hi[y] && lo[y] <= hi[x];"),
 }
@@ -49,6 +50,7 @@ def _pins():
     T.test_overlap_write_makes_overlapping_arrays_valid_on_side_only()
     T.test_overlap_rules_keep_element_model_consistent_pvector()
     T.test_overlap_sets_brute_force_small()
+    T.test_repeated_variable_in_a_component_is_rejected()
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -65,7 +67,7 @@ def test_planted_mistake_fails_a_pin(name):
         saved = O._lib
         O._lib = O.load(so)
         try:
-            with pytest.raises((AssertionError, O.OracleError)):
+            with pytest.raises((AssertionError, O.OracleError, pytest.fail.Exception)):
                 _pins()
         finally:
             O._lib = saved

@@ -247,6 +247,27 @@ def test_translation_fixed_arity():
     assert tr.size == int(np.where(mode == 0, 3, np.where(mode == 1, 2, 5)).sum())
 
 
+def test_repeated_variable_in_a_component_is_rejected():
+    """The declarations of one component are joined by a conjunction over distinct
+    variables (syntax of access modes, Section 3.3, footnote to M ^ M'): a second
+    declaration of the same variable in a component is malformed, on the same side or
+    on the other one, and is reported at its own index.  The same declarations split
+    over two components are a well-formed program."""
+    for second in (("R", "GPU"), ("W", "CPU"), ("RW", "GPU")):
+        co = np.array([0, 1, 3], np.uint64)
+        de = np.array([decl("R", "CPU", 1), decl("W", "CPU", 0), decl(*second, 0)], np.uint32)
+        with pytest.raises(O.OracleError, match="index 2"):
+            O.translate(co, de, 2)
+    co = np.array([0, 1, 2], np.uint64)
+    de = np.array([decl("W", "CPU", 0), decl("R", "GPU", 0)], np.uint32)
+    tr = O.translate(co, de, 1)
+    # W CPU x: w x#, body w x; R GPU x: x# is (V,I), not valid on the GPU, so Push x; Push x#
+    assert list(tr) == [ev("w", "CPU", 1), ev("w", "CPU", 0), ev("Push", "CPU", 0), ev("Push", "CPU", 1),
+                        ev("r", "GPU", 0)]
+    r = O.check(tr, 2)
+    assert r.violations.size == 0
+
+
 def test_ill_declared_body_is_caught():
     """A component that writes x on the GPU under an R declaration is not well-declared;
     a later CPU read of x through R x# finds x# valid and gets stuck (the check sees the
