@@ -118,7 +118,11 @@ int vc_read_overlap_sets(vc_trace *t, uint64_t *off, uint32_t *nbr, uint64_t cap
  *   with remIsValid and local Push.
  * comp_off : n_comp + 1 CSR offsets (uint64, non-decreasing, comp_off[0] = 0) of each
  *            component's declarations in decls.
- * decls    : comp_off[n_comp] decl words; a variable appears at most once per component.
+ * decls    : comp_off[n_comp] decl words.  The declarations of a component are a
+ *            conjunction over distinct variables (syntax of access modes, Section 3.3):
+ *            a variable declared twice in one component is malformed (VC_EINVAL, at the
+ *            second declaration's index; from vc_translate for host input, from vc_sync
+ *            for device input).
  * n_vars   : real variables are ids [0, n_vars); the abstract variable of v is n_vars + v
  *            (2 * n_vars <= 2^24).  Real and abstract variables start at (V,I).
  * body_off / body : NULL for the canonical body of each declaration in order

@@ -148,10 +148,13 @@ def overlap_sets(lo: np.ndarray, hi: np.ndarray):
     hi = np.ascontiguousarray(hi, dtype=np.uint32)
     n = lo.size
     off = np.empty(n + 1, dtype=np.uint64)
-    k = int(lib().oracle_overlap_sets(_p(lo), _p(hi), n, None, None, 0))
-    nbr = np.empty(max(k, 1), dtype=np.uint32)
-    lib().oracle_overlap_sets(_p(lo), _p(hi), n, _p(off), _p(nbr), nbr.size)
-    return off, nbr[:k]
+    # one pass when the neighbours fit a generous first guess, a second one otherwise
+    nbr = np.empty(max(16 * n, 1), dtype=np.uint32)
+    k = int(lib().oracle_overlap_sets(_p(lo), _p(hi), n, _p(off), _p(nbr), nbr.size))
+    if k > nbr.size:
+        nbr = np.empty(k, dtype=np.uint32)
+        lib().oracle_overlap_sets(_p(lo), _p(hi), n, _p(off), _p(nbr), nbr.size)
+    return off, nbr[:k].copy()
 
 
 def check_overlap(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, init: np.ndarray | None = None,

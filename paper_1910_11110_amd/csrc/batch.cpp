@@ -14,6 +14,8 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
+#include <sys/types.h>
 
 #include <algorithm>
 #include <chrono>
@@ -120,9 +122,13 @@ void tune_store(const std::string &key, const SortTuning &t, unsigned scan_grid)
     char line[160];
     snprintf(line, sizeof line, "\"%s\": [%d, %u, %u]", key.c_str(), t.max_bits, t.grid_cap, scan_grid);
     entries.push_back(line);
-    std::string dir = path.substr(0, path.rfind('/'));
-    std::string cmd = "mkdir -p '" + dir + "'";
-    if (system(cmd.c_str()) != 0) {
+    // create the cache's directory, one path component at a time (no process is spawned)
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        const std::string dir = path.substr(0, slash);
+        for (size_t p = 1; p <= dir.size(); p++)
+            if (p == dir.size() || dir[p] == '/')
+                (void)mkdir(dir.substr(0, p).c_str(), 0755); // EEXIST is fine
     }
     if (FILE *f = fopen(path.c_str(), "w")) {
         fprintf(f, "{\n");

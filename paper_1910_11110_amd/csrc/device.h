@@ -420,11 +420,19 @@ __device__ __forceinline__ uint64_t lb_column_sum(const uint64_t *lb, uint64_t s
 // done; so the lowest unfinished tile is either running (all it waits on is finished)
 // or not yet handed out, in which case every workgroup of its group is idle and one of
 // them takes it: every wait ends.
-__device__ __forceinline__ uint32_t take_ticket(uint32_t *counters, uint32_t *s_slot)
+// That argument needs every workgroup of the grid resident, which holds while no other
+// grouped-ticket grid runs beside it.  Work that runs beside another pipeline (a side
+// stream) takes tickets from one counter (groups = 1): a ticket is then only ever
+// handed to a running workgroup, in order, so the lowest unfinished tile always runs,
+// whatever else occupies the device, and that grid always finishes.  Of two grids that
+// run together at most one is grouped, so one of them always finishes and frees its
+// slots for the other.
+__device__ __forceinline__ uint32_t take_ticket(uint32_t *counters, uint32_t *s_slot,
+                                                uint32_t groups = TICKET_GROUPS)
 {
     if (threadIdx.x == 0) {
-        const uint32_t g = blockIdx.x % TICKET_GROUPS;
-        *s_slot = atomicAdd(&counters[g * TICKET_STRIDE], 1u) * TICKET_GROUPS + g;
+        const uint32_t g = blockIdx.x % groups;
+        *s_slot = atomicAdd(&counters[g * TICKET_STRIDE], 1u) * groups + g;
     }
     __syncthreads();
     return *s_slot;

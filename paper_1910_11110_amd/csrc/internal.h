@@ -71,9 +71,11 @@ void launch_prep(Control *c, Control *c2, const FillJob *jobs, int njobs, hipStr
 // exclusive scan of n uint32 counts into n+1 uint64 offsets (out[n] = total, also
 // stored to *total when non-null); scratch of excl_scan_scratch_bytes(n)
 size_t excl_scan_scratch_bytes(uint64_t n);
-// (lookback_cleared: the caller has zeroed the scratch and the ticket counters)
+// (lookback_cleared: the caller has zeroed the scratch and the ticket counters;
+// beside: the scan runs on a stream beside another pipeline, so its tiles are handed out
+// from one ticket counter, which keeps both grids free of waits on absent workgroups)
 void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total, void *scratch, uint32_t *ticket,
-                      hipStream_t s, bool lookback_cleared = false);
+                      hipStream_t s, bool lookback_cleared = false, bool beside = false);
 
 // ------------------------------- radix sort ---------------------------------------
 // Stable LSD sort of 64-bit items by their 28-bit key (see device.h), key_bits

@@ -6,13 +6,19 @@
 // scan, so a chunk's descriptor can read and write the same table.  A server thread
 // admits queued chunks while the device bytes they need fit the budget, packs the
 // ready ones (at most one per stream, in order) into one batched launch, and keeps
-// two launch slots on two HIP streams so that a batch is staged and launched while
-// the previous one still runs.  Finished chunks are copied back and reported through
-// vc_poll with their submission, launch and completion times.
+// two launch slots so that a batch is staged and launched while the previous one
+// still runs.  Each slot copies on its own HIP stream; the kernels of both slots go to
+// one compute stream, so two batched pipelines (whose tiles wait on one another through
+// grouped tickets) never run at the same time.  Finished chunks are copied back and
+// reported through vc_poll with their submission, launch and completion times.  A
+// batch that cannot be launched (device memory, batch limits) completes every chunk
+// with the error, and the chunks' streams then fail their later chunks too (their
+// resident tables no longer follow the stream).
 #include <hip/hip_runtime.h>
 
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -64,6 +70,7 @@ struct Stream {
     std::deque<Chunk *> queue;
     bool in_flight = false;
     bool closing = false;
+    int failed = VC_OK; // error of a chunk that could not run; later chunks report it too
 };
 
 // device buffers of chunks come from power-of-two size classes and are recycled, so
@@ -104,8 +111,10 @@ struct Pool {
 };
 
 struct Slot {
-    hipStream_t s = nullptr;
-    hipEvent_t done = nullptr;
+    hipStream_t s = nullptr;        // copies of this slot's batch
+    hipEvent_t done = nullptr;      // results copied back
+    hipEvent_t staged = nullptr;    // inputs and descriptors on the device
+    hipEvent_t computed = nullptr;  // kernels done (on the compute stream)
     std::vector<Chunk *> chunks;
     BatchState *b = nullptr;
     bool busy = false;
@@ -126,6 +135,7 @@ struct vc_server {
     std::thread worker;
     std::atomic<bool> stop{ false };
     Slot slots[2];
+    hipStream_t compute = nullptr; // kernels of both slots, in launch order
     std::string error;
     Pool *pool = nullptr;
 
@@ -139,6 +149,10 @@ void batch_free(BatchState *b);
 BatchState *batch_new();
 
 namespace {
+
+// limits of one batched launch (the batched pipeline's key and index spaces)
+constexpr uint64_t MAX_BATCH_IDS = 1ull << 28;
+constexpr uint32_t MAX_BATCH_EVENTS = 1u << 30;
 
 int alloc_chunk(Pool &pool, Chunk *c)
 {
@@ -224,8 +238,51 @@ static void finish_slot(vc_server *S, Slot &sl)
     S->cv_done.notify_all();
 }
 
-static void launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
+// completes a chunk that did not run (caller holds S->mu); its stream fails from here on
+static void fail_chunk_locked(vc_server *S, Chunk *c, int code, double t)
 {
+    vc_completion comp{};
+    comp.stream = c->stream;
+    comp.chunk = c->id;
+    comp.first_event = c->first_event;
+    comp.n_events = c->events.size();
+    comp.first_violation = c->first_event + c->events.size();
+    comp.t_submit = c->t_submit;
+    comp.t_start = t;
+    comp.t_done = t;
+    comp.status = code;
+    S->completions.push_back(comp);
+    auto it = S->streams.find(c->stream);
+    if (it != S->streams.end()) {
+        it->second->in_flight = false;
+        if (it->second->failed == VC_OK)
+            it->second->failed = code;
+    }
+    S->used -= c->bytes;
+    free_chunk(*S->pool, c);
+}
+
+static void fail_batch(vc_server *S, std::vector<Chunk *> &batch, int code, const char *why)
+{
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->error = why;
+    const double t = S->now();
+    for (Chunk *c : batch)
+        fail_chunk_locked(S, c, code, t);
+    batch.clear();
+    S->cv.notify_all();
+    S->cv_done.notify_all();
+}
+
+// stages the batch on the slot's stream and enqueues its pipeline on the compute
+// stream; returns false (every chunk completed with the error) if it cannot run
+static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
+{
+    for (Chunk *c : batch)
+        if (alloc_chunk(*S->pool, c) != VC_OK) {
+            fail_batch(S, batch, VC_ENOMEM, vc_last_error());
+            return false;
+        }
     std::vector<TraceDesc> desc(batch.size());
     uint64_t M = 0;
     for (size_t i = 0; i < batch.size(); i++) {
@@ -261,11 +318,28 @@ static void launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
     double t = S->now();
     for (Chunk *c : batch)
         c->t_start = t;
-    if (batch_prepare(*sl.b, desc, M, sl.s) == VC_OK)
-        batch_enqueue(*sl.b, sl.s);
+    const int r = batch_prepare(*sl.b, desc, M, sl.s);
+    if (r != VC_OK) {
+        // nothing was enqueued that reads the chunks' buffers on the compute stream; the
+        // copies already issued finish before the buffers are reused (same stream)
+        (void)hipStreamSynchronize(sl.s);
+        fail_batch(S, batch, r, vc_last_error());
+        return false;
+    }
+    hipError_t e;
+    if ((e = hipEventRecord(sl.staged, sl.s)) != hipSuccess ||
+        (e = hipStreamWaitEvent(S->compute, sl.staged, 0)) != hipSuccess) {
+        (void)hipStreamSynchronize(sl.s);
+        fail_batch(S, batch, VC_EDEVICE, hipGetErrorString(e));
+        return false;
+    }
+    batch_enqueue(*sl.b, S->compute);
+    (void)hipEventRecord(sl.computed, S->compute);
+    (void)hipStreamWaitEvent(sl.s, sl.computed, 0);
     (void)hipEventRecord(sl.done, sl.s);
     sl.chunks = batch;
     sl.busy = true;
+    return true;
 }
 
 static void server_loop(vc_server *S)
@@ -286,36 +360,43 @@ static void server_loop(vc_server *S)
             }
         }
         std::vector<Chunk *> batch;
+        bool failed_any = false;
         if (free_slot) {
             std::unique_lock<std::mutex> lk(S->mu);
-            uint64_t events = 0;
+            uint64_t events = 0, ids = 0;
             for (auto &kv : S->streams) {
                 Stream *st = kv.second;
                 if (st->in_flight || st->queue.empty())
                     continue;
                 Chunk *c = st->queue.front();
+                if (st->failed != VC_OK) { // the stream's table no longer follows it
+                    st->queue.pop_front();
+                    S->used += c->bytes;
+                    fail_chunk_locked(S, c, st->failed, S->now());
+                    failed_any = true;
+                    continue;
+                }
                 if (S->used + c->bytes > S->budget) // admission: wait for memory to free up
                     continue;
-                if (!batch.empty() && events + c->events.size() > S->max_batch)
+                // one launch holds at most MAX_BATCH_IDS ids and max_batch events; a
+                // stream alone always fits (n_ids <= 2^24, chunks < 2^32 events)
+                if (!batch.empty() && (events + c->events.size() > S->max_batch || ids + st->n_ids > MAX_BATCH_IDS))
                     continue;
                 st->queue.pop_front();
                 st->in_flight = true;
                 S->used += c->bytes;
                 events += c->events.size();
+                ids += st->n_ids;
                 batch.push_back(c);
+            }
+            if (failed_any) {
+                S->cv.notify_all();
+                S->cv_done.notify_all();
             }
         }
         if (!batch.empty()) {
-            bool ok = true;
-            for (Chunk *c : batch)
-                if (alloc_chunk(*S->pool, c) != VC_OK)
-                    ok = false;
-            if (!ok) {
-                std::lock_guard<std::mutex> lk(S->mu);
-                S->error = vc_last_error();
-            }
-            launch_slot(S, *free_slot, batch);
-            turn ^= 1;
+            if (launch_slot(S, *free_slot, batch))
+                turn ^= 1;
             continue;
         }
         bool any_busy = S->slots[0].busy || S->slots[1].busy;
@@ -344,13 +425,29 @@ extern "C" int vc_server_create(vc_ctx *c, uint64_t budget, uint32_t max_batch_e
     vc_server *S = new vc_server();
     S->ctx = c;
     S->budget = budget;
-    S->max_batch = max_batch_events ? max_batch_events : (1u << 22);
+    S->max_batch = max_batch_events ? std::min(max_batch_events, MAX_BATCH_EVENTS) : (1u << 22);
     S->t0 = Clock::now();
     S->pool = new Pool();
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&S->compute, hipStreamNonBlocking)) != hipSuccess) {
+        delete S->pool;
+        delete S;
+        return vc_hip_fail(e, "server stream");
+    }
     for (Slot &sl : S->slots) {
-        hipError_t e;
         if ((e = hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess) {
+            (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.staged, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&sl.computed, hipEventDisableTiming)) != hipSuccess) {
+            for (Slot &x : S->slots) {
+                if (x.computed) (void)hipEventDestroy(x.computed);
+                if (x.staged) (void)hipEventDestroy(x.staged);
+                if (x.done) (void)hipEventDestroy(x.done);
+                if (x.s) (void)hipStreamDestroy(x.s);
+                if (x.b) batch_free(x.b);
+            }
+            (void)hipStreamDestroy(S->compute);
+            delete S->pool;
             delete S;
             return vc_hip_fail(e, "server stream");
         }
@@ -381,9 +478,12 @@ extern "C" int vc_server_destroy(vc_server *S)
     }
     for (Slot &sl : S->slots) {
         batch_free(sl.b);
+        (void)hipEventDestroy(sl.computed);
+        (void)hipEventDestroy(sl.staged);
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.s);
     }
+    (void)hipStreamDestroy(S->compute);
     delete S->pool;
     {
         std::lock_guard<std::mutex> lk(g_deg_mu);

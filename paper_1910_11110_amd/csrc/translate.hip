@@ -74,9 +74,17 @@ __global__ void k_translate_count(const uint64_t *__restrict__ comp_off, uint64_
         }
         uint32_t k = 0;
         for (uint64_t d = a; d < b; d++) {
-            uint32_t mode = (decls[d] >> 24) & 3u;
+            const uint32_t w = decls[d];
+            uint32_t mode = (w >> 24) & 3u;
             mode = mode > 2 ? 0 : mode;
             k += slot_arity(mode) + (body_off ? 0u : body_arity(mode));
+            // a component declares each variable once (conjunction over distinct
+            // variables): a repeat is reported at its own index
+            for (uint64_t e = a; e < d; e++)
+                if (((decls[e] ^ w) & 0xFFFFFFu) == 0u) {
+                    report_bad(ctl, d);
+                    break;
+                }
         }
         if (body_off) {
             uint64_t ba = body_off[c], bb = body_off[c + 1];
@@ -751,6 +759,9 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         // events per component (lane = component)
         uint32_t cnt = 0;
         if (fits) {
+            // first declaration of every non-empty component
+            if (lane < nc && b > a)
+                L.start[a - d_lo] = 1;
             uint32_t carry = 0;
 #pragma unroll
             for (int k = 0; k < WROUNDS; k++) {
@@ -769,8 +780,10 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 }
                 const uint32_t inc = wave_scan_add(m, lane);
                 sx[k] = carry + inc - m;
-                if (i < nd)
+                if (i < nd) {
                     L.scan[i] = sx[k];
+                    L.ev[i] = dw[k] & 0xFFFFFFu; // variables, for the repeat check below
+                }
                 carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
             }
             if (lane == 0)
@@ -779,13 +792,41 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             for (int k = 0; k < WROUNDS; k++)
                 pr[k] = k * WAVE + lane < nd ? (uint32_t)res[ix[k] < n_decl ? ix[k] : n_decl - 1] : 0u;
             __builtin_amdgcn_wave_barrier();
+            // a component declares each variable once: every declaration that does not
+            // start its component looks back over the earlier ones of its component
+            // (their statuses would otherwise be evaluated as if only one existed)
+#pragma unroll
+            for (int k = 0; k < WROUNDS; k++) {
+                const uint32_t i = k * WAVE + lane;
+                if (i < nd && !L.start[i]) {
+                    const uint32_t v = L.ev[i];
+                    for (uint32_t j = i; j-- > 0;) {
+                        if (L.ev[j] == v) {
+                            report_bad(ctl, d_lo + i);
+                            break;
+                        }
+                        if (L.start[j])
+                            break;
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
             if (lane < nc) {
                 const uint32_t x = L.scan[b - d_lo], y = L.scan[a - d_lo];
                 cnt = ((x & 0xFFFFu) + (x >> 16)) - ((y & 0xFFFFu) + (y >> 16));
             }
         } else if (lane < nc && !bad) {
-            for (uint64_t d = a; d < b; d++)
-                cnt += decl_arity(decls[d], n_vars);
+            // a component too large to stage: counted serially by its lane, with the
+            // repeat check by pairs (quadratic in the component's size)
+            for (uint64_t d = a; d < b; d++) {
+                const uint32_t w = decls[d];
+                cnt += decl_arity(w, n_vars);
+                for (uint64_t e = a; e < d; e++)
+                    if (((decls[e] ^ w) & 0xFFFFFFu) == 0u) {
+                        report_bad(ctl, d);
+                        break;
+                    }
+            }
         }
         const uint32_t incc = wave_scan_add(cnt, lane);
         const uint32_t excl = incc - cnt, total = __builtin_amdgcn_readlane(incc, WAVE - 1);

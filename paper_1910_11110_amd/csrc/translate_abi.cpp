@@ -5,6 +5,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
+#include <vector>
 
 #include "abi_internal.h"
 #include "bucket.h"
@@ -38,6 +40,32 @@ int validate_host(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *dec
         if ((w & 0xF4000000u) != 0 || ((w >> 24) & 3u) > 2u || (w & 0xFFFFFFu) >= n_vars)
             return vc_fail(VC_EINVAL, "vc_translate: malformed declaration 0x%08x at index %llu", w,
                            (unsigned long long)d);
+    }
+    // the declarations of a component are a conjunction over distinct variables (syntax
+    // of access modes, Section 3.3): the first repeat is reported at its own index
+    std::vector<std::pair<uint32_t, uint64_t>> big;
+    for (uint64_t c = 0; c < n_comp; c++) {
+        const uint64_t a = comp_off[c], b = comp_off[c + 1];
+        uint64_t rep = ~0ull;
+        if (b - a <= 32) {
+            for (uint64_t d = a + 1; d < b && rep == ~0ull; d++)
+                for (uint64_t e = a; e < d; e++)
+                    if (((decls[e] ^ decls[d]) & 0xFFFFFFu) == 0u) {
+                        rep = d;
+                        break;
+                    }
+        } else {
+            big.clear();
+            for (uint64_t d = a; d < b; d++)
+                big.emplace_back(decls[d] & 0xFFFFFFu, d);
+            std::sort(big.begin(), big.end());
+            for (size_t k = 1; k < big.size(); k++)
+                if (big[k].first == big[k - 1].first)
+                    rep = std::min(rep, big[k].second); // the later one of an equal pair
+        }
+        if (rep != ~0ull)
+            return vc_fail(VC_EINVAL, "vc_translate: variable %u declared twice in component %llu, at index %llu",
+                           decls[rep] & 0xFFFFFFu, (unsigned long long)c, (unsigned long long)rep);
     }
     if (body_off) {
         if (body_off[0] != 0)
@@ -125,7 +153,7 @@ int translate_enqueue(vc_trace *t, hipStream_t s)
         }
         // the translated length lands in tr.ctl->n_out
         launch_excl_scan((uint32_t *)tr.cnt.p, nchunks, (uint64_t *)tr.pos.p,
-                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), xscan, tr.ctl->tickets[4], sx, true);
+                         reinterpret_cast<uint64_t *>(&tr.ctl->n_out), xscan, tr.ctl->tickets[4], sx, true, fork);
         if (fork) {
             if ((e = hipEventRecord(c->ev_join, c->side)) != hipSuccess ||
                 (e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess)

@@ -20,14 +20,14 @@ constexpr int XTILE = BLOCK * XITEMS;
 __global__ __launch_bounds__(BLOCK) void k_excl_scan(const uint32_t *__restrict__ in, uint64_t n,
                                                      uint64_t *__restrict__ out, uint64_t *__restrict__ total,
                                                      uint64_t *__restrict__ lb, uint32_t *__restrict__ ticket,
-                                                     uint64_t ntiles)
+                                                     uint64_t ntiles, uint32_t groups)
 {
     __shared__ uint64_t s_wsum[BLOCK / WAVE];
     __shared__ uint32_t s_tile;
     __shared__ uint64_t s_excl;
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     for (;;) {
-        const uint32_t tile = take_ticket(ticket, &s_tile);
+        const uint32_t tile = take_ticket(ticket, &s_tile, groups);
         if (tile >= ntiles)
             break;
         const uint64_t my0 = (uint64_t)tile * XTILE + (uint64_t)tid * XITEMS;
@@ -111,7 +111,7 @@ unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap, int blo
 size_t excl_scan_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, XTILE) * sizeof(uint64_t); }
 
 void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *total, void *scratch, uint32_t *ticket,
-                      hipStream_t s, bool lookback_cleared)
+                      hipStream_t s, bool lookback_cleared, bool beside)
 {
     if (n == 0) {
         launch_fill_u64(out, 0, 1, s);
@@ -125,8 +125,11 @@ void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *t
         launch_clear_lookback(lb, tiles, ticket, s);
     {
         ProfScope prof_(s, "excl_scan");
+        // beside another pipeline: tickets from one counter (they then never wait on a
+        // workgroup that is not running)
+        const uint32_t groups = beside ? 1u : TICKET_GROUPS;
         k_excl_scan<<<resident_grid((const void *)k_excl_scan, tiles), BLOCK, 0, s>>>(in, n, out, total, lb, ticket,
-                                                                                   tiles);
+                                                                                   tiles, groups);
     }
 }
 

@@ -213,3 +213,21 @@ def test_trace_outlives_context():
     with pytest.raises(V.VCError):
         t.check()
     t.free()
+
+
+@pytest.mark.timeout(600)
+def test_small_path_full_size_persistent(ctx):
+    """The plain law at 2^28 events over 64 ids (the single-trace measurement workload):
+    32,768 tiles of 8,192 events, far more than the resident grid, so every workgroup of
+    the <= 64-id kernel takes many tiles in turn."""
+    say("[plain] generating 2^28 events over 64 ids")
+    e = gen.plain_events(1 << 28, 64, 0)
+    assert_parity(ctx, e, 64, label="plain 2^28 x 64")
+
+
+@pytest.mark.timeout(600)
+def test_bucket_path_full_size(ctx):
+    """The plain law at 2^26 events over 2^20 ids (bucket path at its measured size)."""
+    say("[plain] generating 2^26 events over 2^20 ids")
+    e = gen.plain_events(1 << 26, 1 << 20, 0)
+    assert_parity(ctx, e, 1 << 20, label="plain 2^26 x 2^20")

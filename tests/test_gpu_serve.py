@@ -27,9 +27,10 @@ def ctx():
     c.close()
 
 
-def run_streams(srv, specs, timeout=120.0):
+def run_streams(srv, specs, timeout=120.0, chunk=None):
     """specs: list of (events, n_ids, lo, hi, init).  Submits every chunk of every stream,
     interleaved, and returns per stream (status bytes, completions, final table)."""
+    CHUNK = chunk or globals()["CHUNK"]
     sids, bufs, comps = [], [], {}
     for ev, n_ids, lo, hi, init in specs:
         sids.append(srv.open(n_ids, lo, hi, init))
@@ -140,3 +141,55 @@ def test_served_malformed_chunk_rejected(ctx):
     assert ex.value.code == V.VC_EINVAL and "index 10" in str(ex.value)
     srv.close_stream(s, 16)
     srv.close()
+
+
+@pytest.mark.timeout(600)
+def test_served_workload_shapes_full_chunks(ctx):
+    """Streams with the batched workload's shapes (lengths log-uniform in [100, 10^6],
+    variables log-uniform in [8, 65,536], 20 % with intervals) submitted in chunks of
+    2^16 events: every stream equals the oracle on its whole trace, and streams served
+    alone give the same bytes as in the mix."""
+    from paper_1910_11110_amd import vcheck as V
+    shapes = gen.trace_shapes(40, 11)
+    specs = []
+    for i, sh in enumerate(shapes):
+        ev, lo, hi = gen.trace_inputs(sh)
+        specs.append((ev, sh.n_vars, lo, hi, None))
+    n = sum(sp[0].size for sp in specs)
+    say(f"[serve] 40 streams, {n} events, 2^16-event chunks")
+    srv = V.Server(ctx, 64 << 30)
+    bufs, comps, finals, got = run_streams(srv, specs, timeout=300.0, chunk=1 << 16)
+    srv.close()
+    starts = {}
+    for c in got:
+        starts.setdefault(c.t_start, set()).add(c.stream)
+    assert max(len(v) for v in starts.values()) > 1
+    for i, spec in enumerate(specs):
+        ref = oracle_of(*spec)
+        assert np.array_equal(bufs[i], ref.status), f"stream {i} status"
+        assert np.array_equal(finals[i], ref.final), f"stream {i} final"
+        assert sum(c.n_violations for c in comps.get(i, [])) == ref.violations.size, f"stream {i} violations"
+    longest = sorted(range(len(specs)), key=lambda i: -specs[i][0].size)[:4]
+    for i in longest:
+        srv = V.Server(ctx, 64 << 30)
+        alone, _, fin, _ = run_streams(srv, [specs[i]], timeout=300.0, chunk=1 << 16)
+        srv.close()
+        assert np.array_equal(alone[0], bufs[i]) and np.array_equal(fin[0], finals[i]), f"alone {i}"
+
+
+def test_served_batches_split_at_the_id_limit(ctx):
+    """Seventeen streams of 2^24 ids each hold more ids together than one batched launch
+    takes (2^28): admission splits them over several launches, and every chunk completes
+    with the oracle's results."""
+    from paper_1910_11110_amd import vcheck as V
+    specs = [(gen.plain_events(3000, 1 << 24, 900 + i), 1 << 24, None, None, None) for i in range(17)]
+    srv = V.Server(ctx, 64 << 30)
+    bufs, comps, finals, got = run_streams(srv, specs, chunk=1000)
+    srv.close()
+    starts = {}
+    for c in got:
+        starts.setdefault(c.t_start, set()).add(c.stream)
+    assert max(len(v) for v in starts.values()) <= 16
+    for i, spec in enumerate(specs):
+        ref = oracle_of(*spec)
+        assert np.array_equal(bufs[i], ref.status) and np.array_equal(finals[i], ref.final), f"stream {i}"

@@ -243,3 +243,72 @@ def test_translation_malformed_offsets_device(ctx, host_sized):
     finally:
         os.environ.pop("VC_HOST_SIZED", None)
     assert "index 1" in str(ex.value)
+
+
+def _with_repeat(n_comp, n_vars, seed, big=False):
+    """A component program with one variable declared twice in one component (the
+    declarations of a component must name distinct variables, Section 3.3); returns the
+    inputs and the index the oracle reports."""
+    ct = gen.component_trace(n_comp, n_vars, seed)
+    co, de = ct.comp_off.copy(), ct.decls.copy()
+    if big:
+        # one component of 300 declarations (more than a wave tile stages) in the middle
+        mid = n_comp // 2
+        a = int(co[mid])
+        extra = gen.pack_decls(np.arange(300) + 5, np.zeros(300, np.int64), np.zeros(300, np.int64))
+        extra[290] = (extra[290] & ~np.uint32(0xFFFFFF)) | (extra[7] & np.uint32(0xFFFFFF))
+        de = np.concatenate([de[:a], extra, de[a:]]).astype(np.uint32)
+        co = np.concatenate([co[:mid + 1], co[mid + 1:] + np.uint64(300)]).astype(np.uint64)
+        co = np.concatenate([co[:mid + 1], [co[mid] + np.uint64(300)], co[mid + 1:]]).astype(np.uint64)
+    else:
+        k = np.diff(co)
+        c = int(np.nonzero(k >= 3)[0][len(np.nonzero(k >= 3)[0]) // 3])
+        a = int(co[c])
+        de[a + 2] = (de[a + 2] & ~np.uint32(0xFFFFFF)) | (de[a] & np.uint32(0xFFFFFF))
+    with pytest.raises(O.OracleError) as ex:
+        O.translate(co, de, n_vars)
+    idx = int(str(ex.value).split("index ")[1])
+    return co, de, idx
+
+
+@pytest.mark.parametrize("where", ["host", "device", "device-host-sized", "device-unfused"])
+@pytest.mark.parametrize("big", [False, True])
+def test_translation_repeated_variable_rejected(ctx, where, big):
+    """A variable declared twice in one component is malformed input: VC_EINVAL with the
+    index of the second declaration, the oracle's, on every path (host validation, the
+    wave emitter's look-back over the component, the serial pass of components too large
+    to stage, and the per-component count kernel)."""
+    import os
+    import torch
+    from paper_1910_11110_amd import vcheck as V
+    co, de, idx = _with_repeat(20_000, 1 << 12, 5, big)
+    say(f"[translate] repeated variable at {idx} ({where}, big={big})")
+    env = {"device-host-sized": "VC_HOST_SIZED", "device-unfused": "VC_UNFUSED"}.get(where)
+    if env:
+        os.environ[env] = "1"
+    try:
+        with pytest.raises(V.VCError) as ex:
+            if where == "host":
+                V.translate(ctx, co, de, 1 << 12, check=True)
+            else:
+                tco = torch.from_numpy(co.view(np.int64)).cuda()
+                tde = torch.from_numpy(de.view(np.int32)).cuda()
+                torch.cuda.synchronize()
+                t = V.translate(ctx, tco, tde, 1 << 12, check=True)
+                ctx.sync()
+                t.free()
+    finally:
+        if env:
+            del os.environ[env]
+    assert ex.value.code == V.VC_EINVAL and f"index {idx}" in str(ex.value), str(ex.value)
+
+
+def test_translation_repeated_variable_minimal(ctx):
+    """[W CPU x, R GPU x] in one component is rejected; the same declarations in two
+    components translate and check as the oracle does."""
+    from paper_1910_11110_amd import vcheck as V
+    de = np.array([decl("W", "CPU", 0), decl("R", "GPU", 0)], np.uint32)
+    with pytest.raises(V.VCError) as ex:
+        V.translate(ctx, np.array([0, 2], np.uint64), de, 1, check=True)
+    assert ex.value.code == V.VC_EINVAL and "index 1" in str(ex.value)
+    assert_translation(ctx, np.array([0, 1, 2], np.uint64), de, 1, label="split over two components")
