@@ -237,6 +237,35 @@ int vc_stream_close(vc_server *srv, uint64_t stream, uint8_t *final_out);
 /* seconds on the server clock */
 double vc_server_now(vc_server *srv);
 
+/* ---------------------------------------------------------------------------------
+ * Plain check without allocation.  For callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It computes what vc_trace_load + vc_check compute for a trace over at most 64 ids
+ * (the same single-kernel path), writing into the caller's device buffers.  Its work
+ * space (control block, look-back words, tile counts, flag words) is one static device
+ * array of VC_NOALLOC_SCRATCH_BYTES per GPU, held from the first vc_ctx_create on that
+ * GPU until the process ends; the call allocates nothing and does not wait.  Work is
+ * enqueued on the context's stream.
+ *   events       : n event words (device, 16-byte aligned), n <= VC_NOALLOC_MAX_EVENTS
+ *   n_ids        : 1..64; every id must be < n_ids
+ *   init         : n_ids status codes (device), or NULL for (V,I)
+ *   status       : n bytes (device): post | pre << 2 | stuck << 7
+ *   final_status : n_ids bytes (device)
+ *   violations   : room for n uint32 (device); the first counts[0] are the ascending
+ *                  indices of the stuck events
+ *   counts       : 3 uint64 (device): [0] number of violations, [1] first violation (n
+ *                  if none), [2] index of the first malformed event word (UINT64_MAX if
+ *                  none; the other outputs are then undefined)
+ * Every call on one GPU uses that GPU's one array: calls that overlap in time on one
+ * GPU (different streams or host threads) race and must be serialized by the caller;
+ * calls on one stream are ordered.  Sizes beyond the limits, NULL buffers and
+ * misaligned events return VC_EINVAL before anything is enqueued.
+ * --------------------------------------------------------------------------------- */
+#define VC_NOALLOC_MAX_EVENTS (1ull << 24)
+#define VC_NOALLOC_SCRATCH_BYTES (4608u * 1024u)
+int vc_check_small_noalloc(vc_ctx *ctx, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
+                           uint8_t *status, uint8_t *final_status, uint32_t *violations, uint64_t *counts);
+
 #ifdef __cplusplus
 }
 #endif

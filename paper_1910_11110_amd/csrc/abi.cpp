@@ -112,6 +112,11 @@ extern "C" int vc_ctx_create(int hip_device, void *hip_stream, vc_ctx **out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess)
         c->cu_count = prop.multiProcessorCount;
+    int r = noalloc_setup(hip_device, &c->noalloc_scratch);
+    if (r != VC_OK) {
+        vc_ctx_destroy(c);
+        return r;
+    }
     *out = c;
     return VC_OK;
 }

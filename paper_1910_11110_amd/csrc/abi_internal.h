@@ -52,6 +52,8 @@ struct vc_ctx {
     std::vector<vc_trace *> traces;  // live traces (detached when the context goes)
     BatchState *batch = nullptr;
     vc::Profiler *prof = nullptr;
+    // device address of the static work space of vc_check_small_noalloc on this device
+    void *noalloc_scratch = nullptr;
 };
 
 // makes a context's profiler the active one for launches issued by this thread
@@ -123,3 +125,9 @@ void translate_release(vc_trace *t);
 
 // batch (batch.cpp)
 void batch_release(vc_ctx *c);
+
+// no-alloc check (noalloc.hip): the device address of the static work space of the
+// current device, taken once per device
+namespace vc {
+int noalloc_setup(int device, void **out);
+}

@@ -345,6 +345,16 @@ size_t small_scratch_bytes(uint64_t n) { return small_layout(nullptr, n).bytes; 
 
 uint32_t small_max_ids() { return SK; }
 
+void excl_scan_warm_launch_shape();
+
+// computes the persistent grids of the small check once, so that later launches make
+// no host-side allocation
+void small_warm_launch_shapes()
+{
+    (void)resident_grid((const void *)k_small_check, 1, 0, SB);
+    excl_scan_warm_launch_shape();
+}
+
 void launch_small_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s,
                         unsigned grid_cap, const FillJob *fin_fill)

@@ -79,6 +79,7 @@ def lib():
             "vc_profile_enable": ([P, i32], i32),
             "vc_profile_reset": ([P], i32),
             "vc_profile_read": ([P, C.c_char_p, u32, P, P, u32, pu32], i32),
+            "vc_check_small_noalloc": ([P, P, u64, u32, P, P, P, P, P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -269,6 +270,18 @@ def translate(ctx: Context, comp_off, decls, n_vars: int, body_off=None, body=No
     h = C.c_void_p()
     _check(lib().vc_translate(ctx.h, cp, n_comp, dp, n_vars, bp, yp, flags, C.byref(h)))
     return Trace(ctx, h, (ck, dk, bk, yk) if dev else ())
+
+
+def check_small_noalloc(ctx: Context, events, n_ids: int, init, status, final, violations, counts):
+    """vc_check_small_noalloc on torch CUDA tensors (events uint32/int32, 16-byte aligned;
+    init uint8 or None; status uint8[n]; final uint8[n_ids]; violations int32[n];
+    counts int64[3]).  Enqueued on the context's stream; nothing is allocated."""
+    for a in (events, status, final, violations, counts) + ((init,) if init is not None else ()):
+        assert _is_torch_cuda(a) and a.is_contiguous(), "device tensors expected"
+    ip = None if init is None else C.c_void_p(init.data_ptr())
+    _check(lib().vc_check_small_noalloc(ctx.h, C.c_void_p(events.data_ptr()), events.numel(), n_ids, ip,
+                                        C.c_void_p(status.data_ptr()), C.c_void_p(final.data_ptr()),
+                                        C.c_void_p(violations.data_ptr()), C.c_void_p(counts.data_ptr())))
 
 
 def batch_check(ctx: Context, traces):
