@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the validity-status checker on one MI355X.
 
-A step is one pass of the hot path over one batch of synthetic input.  The default
-workload is the VectorPU-style component trace (2^23 components over 2^20
-variables, Zipf(1.1) variables, R/W/RW = 0.5/0.3/0.2): declarations are
-translated into core effects and the translated trace (~1.17e8 events) is checked
-in the same enqueue.  Inputs are generated on the host, copied to HBM once, and
-stay resident; the timed region covers only device work (plus the one host-visible
-size read-back the translation does).
+A step is one pass of the hot path over one batch of synthetic input.  The headline
+workload is the VectorPU-style component trace (2^23 components over 2^20 variables,
+Zipf(1.1) variables, R/W/RW = 0.5/0.3/0.2): declarations are translated into core
+effects and the translated trace (~1.17e8 events) is checked in the same enqueue.
+Inputs are generated on the host, copied to HBM once, and stay resident; the timed
+region covers only device work.
 
-Prints one JSON line.  Extra workloads (--workload) report the same schema.
+Prints one JSON line.  By default the line also carries, under "also", the plain
+single-trace workload at 2^28 events over 64 ids, the batched workload (4,096 traces)
+and the served workload (an open-loop Poisson replay), each with its own roofline,
+oracle baseline and, for batched and served, the same traces checked one after
+another by the per-trace path on the same GPU.
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import hashlib
 import json
 import os
@@ -58,6 +62,30 @@ def traffic_for(kernel: str, workload: str):
     return None
 
 
+def host_info() -> dict:
+    """The host the oracle is timed on: CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
+def pool_threads() -> int:
+    """Threads for the all-core oracle timing: every usable core, at most 16 (the GPU
+    box's CPU share for one GPU)."""
+    return max(1, min(16, host_info()["nproc"] or 1))
+
+
 class Timer:
     """HIP events on the stream the library launches on."""
 
@@ -78,14 +106,24 @@ class Timer:
         self.ms = self.a.elapsed_time(self.b)
 
 
+def _median_rate(units, fn, runs=3):
+    times = []
+    for _ in range(runs):
+        a = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - a)
+    return units / float(np.median(times))
+
+
 # ------------------------------------------------------------------------------------------
-# workloads
+# workloads: each returns step(), the units of a step, the algorithmic bytes of a step
+# (the method's inputs read once and outputs written once), the oracle timing and config
 # ------------------------------------------------------------------------------------------
 def wl_components(args, V, ctx, stream):
     import torch
     from paper_1910_11110_amd import gen
     n_comp, n_vars = 1 << args.comp_log2, 1 << 20
-    log(f"[bench] generating {n_comp} components over {n_vars} variables")
+    log(f"[bench] components: generating {n_comp} components over {n_vars} variables")
     ct = gen.component_trace(n_comp, n_vars, args.seed)
     co = torch.from_numpy(ct.comp_off.view(np.int64)).cuda()
     de = torch.from_numpy(ct.decls.view(np.int32)).cuda()
@@ -99,41 +137,38 @@ def wl_components(args, V, ctx, stream):
         t.rerun()
 
     def bytes_alg():
-        # read declarations and offsets once; write the translated trace, one status
-        # byte per event, the violation indices and the final statuses
+        # declarations (4 B) and component offsets (8 B) read once; the translated trace
+        # (4 B), one status byte per event, the violation indices and the final statuses
+        # of real and abstract variables written once
         return 4 * ct.decls.size + 8 * (n_comp + 1) + 4 * n_ev + n_ev + 4 * viol + 2 * n_vars
 
     def cpu_sample():
         from oracle import oracle as O
-        times = []
-        for _ in range(3):
-            a = time.perf_counter()
+
+        def run():
             tr = O.translate(ct.comp_off, ct.decls, n_vars)
             O.check(tr, 2 * n_vars)
-            times.append(time.perf_counter() - a)
-        return n_ev / float(np.median(times)), f"oracle translate+check of the full workload, median of 3 runs"
+        return _median_rate(n_ev, run), "oracle translate + check of the full workload, median of 3 runs", None
 
     nd = int(ct.decls.size)
-    # each kernel's own algorithmic traffic: its inputs read once, its outputs written once
-    # (unit: declarations for the declaration passes, translated events for the emitter)
-    kernel_bytes = {
+    # each kernel's own minimum traffic: its inputs read once, its outputs written once
+    own_io = {
         "bucket_hist": (4 * nd + 4 * (nd // 64), nd, "declaration"),      # words; chunk event counts
         "partition": (12 * nd, nd, "declaration"),                       # words in; words, destinations out
         "bucket_scan": (5 * nd + n_vars, nd, "declaration"),             # words in, pre-status out, final
-        # declarations, their destinations and gathered pre-statuses, offsets; events and status bytes out
         "translate_emit_wave": (9 * nd + 8 * (n_comp + 1) + 5 * n_ev, n_ev, "translated event"),
     }
     cfg = {"workload": f"components-2^{args.comp_log2}", "n_components": n_comp, "n_vars": n_vars,
            "n_declarations": nd, "n_events": int(n_ev), "violations": int(viol)}
-    return dict(step=step, units=n_ev, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, co, de),
-                per_unit=lambda: bytes_alg() / n_ev, kernel_bytes=kernel_bytes)
+    return dict(step=step, units=n_ev, unit="translated event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg,
+                keep=(t, co, de), own_io=own_io)
 
 
 def wl_plain(args, V, ctx, stream, n=None, n_ids=64):
     import torch
     from paper_1910_11110_amd import gen
     n = n or (1 << args.plain_log2)
-    log(f"[bench] generating {n} plain events over {n_ids} ids")
+    log(f"[bench] plain: generating {n} events over {n_ids} ids")
     e = gen.plain_events(n, n_ids, args.seed)
     te = torch.from_numpy(e.view(np.int32)).cuda()
     torch.cuda.synchronize()
@@ -146,28 +181,25 @@ def wl_plain(args, V, ctx, stream, n=None, n_ids=64):
         t.check()
 
     def bytes_alg():
+        # events in (4 B), status bytes out (1 B), violation indices, final table
         return 4 * n + n + 4 * viol + n_ids
 
     def cpu_sample():
         from oracle import oracle as O
         m = min(n, 1 << 27)
-        times = []
-        for _ in range(3):
-            a = time.perf_counter()
-            O.check(e[:m], n_ids)
-            times.append(time.perf_counter() - a)
-        return m / float(np.median(times)), f"oracle check of the first {m} events, median of 3 runs"
+        return (_median_rate(m, lambda: O.check(e[:m], n_ids)),
+                f"oracle check of the first {m} events, median of 3 runs", None)
 
-    kernel_bytes = {
-        "small_check": (5 * n + 4 * viol + n_ids, n, "event"),              # events in, status out, violations
+    own_io = {
+        "small_check": (5 * n + 4 * viol + n_ids, n, "event"),
         "bucket_hist": (4 * n, n, "event"),
-        "partition": (12 * n, n, "event"),                                  # words in; words, destinations out
+        "partition": (12 * n, n, "event"),
         "bucket_scan": (5 * n + n_ids, n, "event"),
-        "replay_status": (6 * n + 4 * viol, n, "event"),                    # destinations, gathered byte, status, violations
+        "replay_status": (6 * n + 4 * viol, n, "event"),
     }
     cfg = {"workload": f"plain-{n}x{n_ids}", "n_events": n, "n_ids": n_ids, "violations": int(viol)}
-    return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te),
-                per_unit=lambda: bytes_alg() / n, kernel_bytes=kernel_bytes)
+    return dict(step=step, units=n, unit="event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te),
+                own_io=own_io)
 
 
 def wl_overlap(args, V, ctx, stream):
@@ -190,27 +222,32 @@ def wl_overlap(args, V, ctx, stream):
         t.check()
 
     def bytes_alg():
-        return 4 * n + n + 4 * viol + n_arr
+        return 4 * n + n + 4 * viol + n_arr + 8 * n_arr
 
     def cpu_sample():
         from oracle import oracle as O
         sets = O.overlap_sets(lo, hi)
-        times = []
-        for _ in range(3):
-            a = time.perf_counter()
-            O.check_overlap(e, lo, hi, sets=sets)
-            times.append(time.perf_counter() - a)
-        return n / float(np.median(times)), "oracle overlap check of the full workload (sets precomputed), median of 3"
+        return (_median_rate(n, lambda: O.check_overlap(e, lo, hi, sets=sets)),
+                "oracle overlap check of the full workload (overlap sets precomputed), median of 3", None)
 
     cfg = {"workload": "overlap-2^16-arrays-2^24-events", "n_events": n, "n_arrays": n_arr, "violations": int(viol),
            "interval_sweep_ms_incl_host": round(sweep_s * 1e3, 3)}
-    return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te),
-                per_unit=lambda: bytes_alg() / n)
+    return dict(step=step, units=n, unit="event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te))
 
 
-def _oracle_sample(inputs, budget_events):
-    """events/s of the oracle over the first traces of `inputs` ((events, n_ids, lo, hi))
-    up to about budget_events events; and how many traces and events that was"""
+def _oracle_job(inp, sets):
+    from oracle import oracle as O
+    ev, nv, lo, hi = inp
+    if lo is None:
+        O.check(ev, nv)
+    else:
+        O.check_overlap(ev, lo, hi, sets=sets)
+
+
+def _oracle_traces(inputs, budget_events):
+    """The oracle over the first traces of `inputs` ((events, n_ids, lo, hi)) up to about
+    budget_events events, on one host core and then trace-parallel on every usable core.
+    Overlap sets are computed before the clock starts: only the evaluation is timed."""
     from oracle import oracle as O
     take, m = [], 0
     for inp in inputs:
@@ -218,13 +255,33 @@ def _oracle_sample(inputs, budget_events):
             break
         take.append(inp)
         m += inp[0].size
+    sets = [None if lo is None else O.overlap_sets(lo, hi) for _e, _n, lo, hi in take]
     a = time.perf_counter()
-    for ev, nv, lo, hi in take:
-        if lo is None:
-            O.check(ev, nv)
-        else:
-            O.check_overlap(ev, lo, hi)
-    return m / (time.perf_counter() - a), len(take), m
+    for inp, s in zip(take, sets):
+        _oracle_job(inp, s)
+    one = m / (time.perf_counter() - a)
+    k = pool_threads()
+    a = time.perf_counter()
+    with cf.ThreadPoolExecutor(k) as ex:
+        list(ex.map(lambda js: _oracle_job(*js), zip(take, sets)))
+    allc = m / (time.perf_counter() - a)
+    return one, allc, k, len(take), m
+
+
+def _sequential_per_trace(V, ctx, traces, units):
+    """The same traces checked one after another by the per-trace path (vc_check on each
+    resident trace, all enqueued on the context's stream, one wait at the end)."""
+    best = None
+    for _ in range(3):
+        ctx.sync()
+        a = time.perf_counter()
+        for t in traces:
+            t.check()
+        ctx.sync()
+        s = time.perf_counter() - a
+        best = s if best is None else min(best, s)
+    return {"value": round(units / best, 1), "unit": "events/s", "ms": round(best * 1e3, 3),
+            "how": "vc_check on every trace in turn (inputs resident), one sync at the end; best of 3"}
 
 
 def wl_batched(args, V, ctx, stream):
@@ -233,7 +290,7 @@ def wl_batched(args, V, ctx, stream):
     of all of them (one pipeline, replayed as a HIP graph)."""
     from paper_1910_11110_amd import gen
     n_tr = 4096
-    log(f"[bench] generating {n_tr} traces")
+    log(f"[bench] batched: generating {n_tr} traces")
     shapes = gen.trace_shapes(n_tr, args.seed)
     traces, inputs = [], []
     for sh in shapes:
@@ -244,7 +301,7 @@ def wl_batched(args, V, ctx, stream):
         traces.append(t)
         inputs.append((ev, sh.n_vars, lo, hi))
     n = sum(sh.length for sh in shapes)
-    log(f"[bench] {n} events; first batched check")
+    log(f"[bench] batched: {n} events; first batched check")
     V.batch_check(ctx, traces)
     ctx.sync()
     viol = sum(t.violations().total for t in traces)
@@ -257,77 +314,144 @@ def wl_batched(args, V, ctx, stream):
         return 4 * n + n + 4 * viol + ids
 
     def cpu_sample():
-        v, k, m = _oracle_sample(inputs, 1 << 24)
-        return v, f"oracle check of the first {k} traces ({m} events), one run"
+        one, allc, k, nt, m = _oracle_traces(inputs, 1 << 25)
+        return one, f"oracle check of the first {nt} traces ({m} events), one run, overlap sets precomputed", \
+            {"value": round(allc, 1), "threads": k}
+
+    def extra():
+        log("[bench] batched: the same traces through the per-trace path, one after another")
+        return {"sequential_per_trace": _sequential_per_trace(V, ctx, traces, n)}
 
     cfg = {"workload": "batched-4096-traces", "n_traces": n_tr, "n_events": n,
            "with_arrays": sum(1 for sh in shapes if sh.has_arrays), "violations": int(viol)}
-    return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(traces, inputs),
-                per_unit=lambda: bytes_alg() / n)
+    return dict(step=step, units=n, unit="event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg,
+                keep=(traces, inputs), extra=extra, multi_pass=("sort_pass", "hist"))
 
 
-def wl_served(args, V, ctx, stream):
-    """Served streams: 256 streams (trace lengths log-uniform in [2^16, 2^20], variables
-    log-uniform in [8, 65,536], 20 % with array intervals), each submitting its trace in
-    2^16-event chunks from host memory, all interleaved; the server admits, batches and
-    checks them with the streams' status tables resident on the device.  A step opens
-    the streams, submits every chunk, waits for every completion and closes the streams;
-    it is timed on the host clock and includes the chunks' copies to the device."""
+# ------------------------------------------------------------------------------------------
+# served: open-loop Poisson replay
+# ------------------------------------------------------------------------------------------
+def _served_pool(seed, n_pool):
     from paper_1910_11110_amd import gen
-    n_str, chunk = 256, 1 << 16
-    log(f"[bench] generating {n_str} streams")
-    shapes = gen.trace_shapes(n_str, args.seed, len_range=(1 << 16, 1 << 20))
-    inputs = []
+    shapes = gen.trace_shapes(n_pool, seed + 100)
+    pool = []
     for sh in shapes:
         ev, lo, hi = gen.trace_inputs(sh)
-        inputs.append((ev, sh.n_vars, lo, hi))
-    outs = [np.empty(ev.size, np.uint8) for ev, *_ in inputs]
-    n = sum(ev.size for ev, *_ in inputs)
-    srv = V.Server(ctx, 64 << 30)
-    state = {"lat": [], "viol": 0}
+        pool.append((ev, sh.n_vars, lo, hi, np.empty(ev.size, np.uint8)))
+    return pool
 
-    def step():
-        sids = [srv.open(nv, lo, hi) for _ev, nv, lo, hi in inputs]
-        maxc = max((ev.size + chunk - 1) // chunk for ev, *_ in inputs)
-        want = 0
-        for k in range(maxc):
-            for i, (ev, *_r) in enumerate(inputs):
-                a = k * chunk
-                if a < ev.size:
-                    srv.submit(sids[i], ev[a:a + chunk], outs[i][a:a + chunk])
-                    want += 1
-        lat, viol, got = [], 0, 0
-        while got < want:
-            cs = srv.poll()
-            for c in cs:
-                if c.status != 0:
-                    raise RuntimeError(f"chunk {c.chunk} failed with {c.status}")
-                lat.append(c.t_done - c.t_submit)
-                viol += c.n_violations
-            got += len(cs)
-            if not cs:
-                time.sleep(0.0002)
-        for i, s_ in enumerate(sids):
-            srv.close_stream(s_, inputs[i][1])
-        state["lat"], state["viol"] = lat, viol
 
-    def bytes_alg():
-        return 4 * n + n + 4 * state["viol"] + sum(nv for _e, nv, *_r in inputs)
+def _replay(V, ctx, pool, arrivals, budget, chunk, label):
+    """Opens one stream per arrival (pool trace i % len(pool)) at its arrival time, submits
+    all its chunks then (a stream's chunks run in order, one at a time), and closes it
+    when its last chunk has completed.  Returns latencies and throughput."""
+    srv = V.Server(ctx, budget)
+    n_arr = arrivals.size
+    open_ = {}   # stream -> [pool index, chunks left, arrival (server clock), last done]
+    chunk_lat, trace_lat = [], []
+    done_events, i, viol = 0, 0, 0
+    t0 = srv.now()
+    last_done = t0
+    deadline = t0 + float(arrivals[-1] if n_arr else 0.0) + 120.0
+    while i < n_arr or open_:
+        now = srv.now()
+        while i < n_arr and t0 + arrivals[i] <= now:
+            ev, nv, lo, hi, out = pool[i % len(pool)]
+            s = srv.open(nv, lo, hi)
+            k = 0
+            for a in range(0, ev.size, chunk):
+                srv.submit(s, ev[a:a + chunk], out[a:a + chunk])
+                k += 1
+            open_[s] = [i % len(pool), k, t0 + float(arrivals[i]), 0.0]
+            i += 1
+        cs = srv.poll()
+        for c in cs:
+            if c.status != 0:
+                raise RuntimeError(f"{label}: chunk {c.chunk} failed with {c.status}")
+            chunk_lat.append(c.t_done - c.t_submit)
+            done_events += c.n_events
+            viol += c.n_violations
+            st = open_[c.stream]
+            st[1] -= 1
+            st[3] = max(st[3], c.t_done)
+            last_done = max(last_done, c.t_done)
+        for s in [s for s, st in open_.items() if st[1] == 0]:
+            st = open_.pop(s)
+            trace_lat.append(st[3] - st[2])
+            srv.close_stream(s, pool[st[0]][1])
+        if not cs:
+            if srv.now() > deadline:
+                raise RuntimeError(f"{label}: completions stalled")
+            time.sleep(0.0002)
+    srv.close()
+    span = last_done - t0
+    cl = np.sort(np.asarray(chunk_lat)) * 1e3
+    tl = np.sort(np.asarray(trace_lat)) * 1e3
 
-    def cpu_sample():
-        v, k, m = _oracle_sample(inputs, 1 << 24)
-        return v, f"oracle check of the first {k} streams' traces ({m} events), one run"
+    def pct(a, q):
+        return round(float(a[min(a.size - 1, (a.size * q) // 100)]), 3) if a.size else None
+    return {"traces": int(n_arr), "chunks": int(cl.size), "events": int(done_events), "violations": int(viol),
+            "span_s": round(span, 3), "sustained_events_per_s": round(done_events / span, 1) if span > 0 else None,
+            "chunk_latency_ms": {"p50": pct(cl, 50), "p99": pct(cl, 99), "max": round(float(cl[-1]), 3)},
+            "trace_latency_ms": {"p50": pct(tl, 50), "p99": pct(tl, 99), "max": round(float(tl[-1]), 3)}}
 
-    def extra():
-        lat = np.sort(np.asarray(state["lat"], np.float64)) * 1e3
-        return {"serving": {"chunks_per_step": int(lat.size), "chunk_events": chunk,
-                            "latency_ms_p50": round(float(lat[lat.size // 2]), 3),
-                            "latency_ms_p99": round(float(lat[min(lat.size - 1, (lat.size * 99) // 100)]), 3),
-                            "note": "submit-to-done per chunk; the step includes host-to-device copies"}}
 
-    cfg = {"workload": "served-256-streams-2^16-chunks", "n_streams": n_str, "n_events": n}
-    return dict(step=step, units=n, bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(srv, inputs, outs),
-                per_unit=lambda: bytes_alg() / n, host_timed=True, extra=extra)
+def served_report(args, V, ctx):
+    """Served workload: Poisson arrivals of traces with the batched workload's shapes, each
+    split into 2^16-event chunks, its status table resident on the device between chunks;
+    admission by a 64 GB budget (and, in a second replay, by a 64 MB budget that binds)."""
+    from paper_1910_11110_amd import gen
+    chunk = 1 << 16
+    log(f"[bench] served: generating a pool of {args.served_pool} traces")
+    pool = _served_pool(args.seed, args.served_pool)
+    pool_events = sum(p[0].size for p in pool)
+    arrivals = gen.poisson_arrivals(args.served_rate, args.served_seconds, args.seed)
+    offered = float(np.mean([p[0].size for p in pool])) * args.served_rate
+    log(f"[bench] served: replay of {arrivals.size} arrivals over {args.served_seconds} s at 64 GB")
+    main = _replay(V, ctx, pool, arrivals, 64 << 30, chunk, "64 GB replay")
+    log("[bench] served: capacity (the whole pool arriving at once)")
+    cap = _replay(V, ctx, pool, np.zeros(len(pool)), 64 << 30, chunk, "capacity")
+    small_s = min(5.0, args.served_seconds)
+    arr2 = arrivals[arrivals < small_s]
+    log(f"[bench] served: replay of {arr2.size} arrivals over {small_s} s at 64 MB")
+    tight = _replay(V, ctx, pool, arr2, 64 << 20, chunk, "64 MB replay")
+    log("[bench] served: the pool through the per-trace path, one after another")
+    seq = None
+    for _ in range(2):
+        a = time.perf_counter()
+        for ev, nv, lo, hi, out in pool:
+            t = V.Trace.load(ctx, ev, nv)
+            if lo is not None:
+                t.set_arrays(lo, hi)
+            t.check()
+            ctx.sync()
+            t.status()
+            t.free()
+        s = time.perf_counter() - a
+        seq = s if seq is None else min(seq, s)
+    one, allc, k, nt, m = _oracle_traces([p[:4] for p in pool], 1 << 25)
+    rec = {
+        "config": {"workload": "served-poisson", "rate_traces_per_s": args.served_rate,
+                   "duration_s": args.served_seconds, "chunk_events": chunk, "budget_bytes": 64 << 30,
+                   "trace_pool": len(pool), "pool_events": int(pool_events),
+                   "shapes": "lengths log-uniform [100, 1e6], variables log-uniform [8, 65536], 20% with arrays",
+                   "offered_events_per_s": round(offered, 1)},
+        "value": main["sustained_events_per_s"], "unit": "events/s",
+        "replay": main,
+        "capacity": cap,
+        "tight_budget_64MB": tight,
+        "sequential_per_trace": {"value": round(pool_events / seq, 1), "unit": "events/s", "ms": round(seq * 1e3, 3),
+                                 "how": "per pool trace: load from host, set arrays, vc_check, sync, read the "
+                                        "status bytes, free; best of 2"},
+        "cpu_baseline": {"value": round(one, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+                         "sample": f"oracle check of the first {nt} pool traces ({m} events), overlap sets "
+                                   f"precomputed", "host": host_info(),
+                         "all_cores": {"value": round(allc, 1), "threads": k}},
+        "note": "latencies are submit-to-completion on the server clock, queueing included; a trace's latency "
+                "runs from its arrival to its last chunk's completion; the replay includes the chunks' copies "
+                "from host memory and the status bytes' copies back",
+    }
+    return rec
 
 
 def copy_probe(torch, n_words=1 << 28):
@@ -346,7 +470,82 @@ def copy_probe(torch, n_words=1 << 28):
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
              "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
              "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap,
-             "batched": wl_batched, "served": wl_served}
+             "batched": wl_batched}
+
+
+def measure(name, args, V, ctx, stream, steps, warmup, cpu=True):
+    """Runs `steps` timed steps of a workload after `warmup` untimed ones and returns its
+    record: throughput, the roofline of its dominant kernel, the whole step's fraction of
+    peak, per-kernel times and the oracle baseline."""
+    import torch
+    w = WORKLOADS[name](args, V, ctx, stream)
+    for _ in range(warmup):
+        w["step"]()
+    ctx.sync()
+    torch.cuda.synchronize()
+    # timed region: exactly `steps` steps, synchronized on both sides
+    with Timer(stream) as tm:
+        for _ in range(steps):
+            w["step"]()
+    ctx.sync()
+    ms_step = tm.ms / steps
+    value = w["units"] / (ms_step / 1e3)
+
+    # per-kernel durations: the same steps again with event pairs around each kernel
+    ctx.profile(True)
+    ctx.profile_reset()
+    for _ in range(steps):
+        w["step"]()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    kernels = {k: {"ms_per_launch": ms / max(n, 1), "launches_per_step": n / steps, "ms_per_step": ms / steps}
+               for k, (ms, n) in prof.items()}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if kernels else None
+    alg_step = w["bytes_alg"]()
+    per_unit = alg_step / w["units"]
+    roof = None
+    if dom:
+        d = kernels[dom]
+        # units one launch of the dominant kernel processes: every unit for a kernel that
+        # passes over the whole input on each launch (sort passes), else the step's units
+        # spread over its launches
+        multi = any(dom.startswith(p) for p in w.get("multi_pass", ()))
+        upl = w["units"] if multi or d["launches_per_step"] <= 1 else w["units"] / d["launches_per_step"]
+        achieved = per_unit * upl / (d["ms_per_launch"] / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, name),
+                "bytes_per_unit": round(per_unit, 4), "unit_of_work": w["unit"], "units_per_launch": int(upl),
+                "ms_per_launch": round(d["ms_per_launch"], 4),
+                "basis": "the path's algorithmic bytes per unit (inputs read once, outputs written once) x the "
+                         "units one launch processes / the kernel's mean launch time (HIP events)"}
+    # each kernel's own minimum I/O (intermediates of the sort included), for comparison
+    own = {}
+    for k, (b, units, unit) in w.get("own_io", {}).items():
+        if k in kernels and kernels[k]["ms_per_launch"] > 0:
+            gbs = b / (kernels[k]["ms_per_launch"] / 1e3) / 1e9
+            own[k] = {"bytes_per_launch": int(b), "units_per_launch": int(units), "unit": unit,
+                      "achieved_GBs": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    pipeline = {"algorithmic_bytes_per_step": int(alg_step), "bytes_per_unit": round(per_unit, 4),
+                "achieved_GBs": round(alg_step / (ms_step / 1e3) / 1e9, 2),
+                "frac": round(alg_step / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    cpu_rec = None
+    if cpu:
+        log(f"[bench] {name}: timing the oracle on the host")
+        v, sample, allc = w["cpu"]()
+        cpu_rec = {"value": round(v, 1), "unit": "events/s", "cores": 1, "kind": "oracle", "sample": sample,
+                   "host": host_info()}
+        if allc:
+            cpu_rec["all_cores"] = allc
+    rec = {"config": w["config"], "value": round(value, 1), "unit": "events/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": round(ms_step, 4), "roofline": roof, "pipeline_roofline": pipeline, "cpu_baseline": cpu_rec,
+           "kernel_own_io": own,
+           "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()}}
+    if "extra" in w:
+        rec.update(w["extra"]())
+    del w
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return rec
 
 
 def main():
@@ -354,10 +553,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="components", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="components", choices=sorted(WORKLOADS) + ["served"])
+    ap.add_argument("--also", default="plain-large,batched,served",
+                    help="workloads reported beside the headline one (comma separated; empty for none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--comp-log2", type=int, default=23)
     ap.add_argument("--plain-log2", type=int, default=28)
+    ap.add_argument("--served-rate", type=float, default=2000.0)
+    ap.add_argument("--served-seconds", type=float, default=15.0)
+    ap.add_argument("--served-pool", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="launch one 1 GiB elementwise kernel first (calibrates hardware traffic counters)")
@@ -373,88 +577,40 @@ def main():
     ctx = V.Context(0, stream)
     if args.copy_probe:
         log(f"[bench] copy probe: {copy_probe(torch)} bytes read and written")
-    w = WORKLOADS[args.workload](args, V, ctx, stream)
-
-    for _ in range(args.warmup):
-        w["step"]()
-    ctx.sync()
-    torch.cuda.synchronize()
-    # timed region: exactly `steps` steps, synchronized on both sides (a served step
-    # waits for its own completions and runs on the server's streams: host clock)
-    if w.get("host_timed"):
-        a = time.perf_counter()
-        for _ in range(args.steps):
-            w["step"]()
-        ctx.sync()
-        ms_step = (time.perf_counter() - a) * 1e3 / args.steps
+    cpu = not args.no_cpu_baseline
+    if args.workload == "served":
+        head = served_report(args, V, ctx)
+        head.update(steps=1, warmup=0, ms_per_step=None, roofline=None)
     else:
-        with Timer(stream) as tm:
-            for _ in range(args.steps):
-                w["step"]()
-        ctx.sync()
-        ms_step = tm.ms / args.steps
-    value = w["units"] / (ms_step / 1e3)
-
-    # per-kernel durations: the same steps again with event pairs around each kernel
-    ctx.profile(True)
-    ctx.profile_reset()
-    for _ in range(args.steps):
-        w["step"]()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    kernels = {k: {"ms_per_launch": ms / max(n, 1), "launches_per_step": n / args.steps, "ms_per_step": ms / args.steps}
-               for k, (ms, n) in prof.items()}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if kernels else None
-    alg_step = w["bytes_alg"]()
-    kb = w.get("kernel_bytes", {})
-    # per kernel: its own algorithmic bytes per launch / its average launch time
-    kroof = {}
-    for k, (b, units, unit) in kb.items():
-        if k in kernels and kernels[k]["ms_per_launch"] > 0:
-            gbs = b / (kernels[k]["ms_per_launch"] / 1e3) / 1e9
-            kroof[k] = {"bytes_per_launch": int(b), "units_per_launch": int(units), "unit": unit,
-                        "achieved_GBs": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    roof = None
-    if dom:
-        d = kernels[dom]
-        r = kroof.get(dom)
-        achieved = r["achieved_GBs"] if r else None
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": r["frac"] if r else None, "traffic": traffic_for(dom, args.workload),
-                "bytes_per_unit": round(r["bytes_per_launch"] / r["units_per_launch"], 3) if r else None,
-                "units_per_launch": r["units_per_launch"] if r else None,
-                "ms_per_launch": round(d["ms_per_launch"], 4)}
-    pipeline = {"algorithmic_bytes_per_step": int(alg_step),
-                "achieved_GBs": round(alg_step / (ms_step / 1e3) / 1e9, 2),
-                "frac": round(alg_step / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on the host")
-        v, sample = w["cpu"]()
-        cpu = {"value": round(v, 1), "unit": "events/s", "cores": 1, "kind": "oracle", "sample": sample}
+        head = measure(args.workload, args, V, ctx, stream, args.steps, args.warmup, cpu)
+    also = {}
+    for name in [x for x in args.also.split(",") if x and x != args.workload]:
+        if name == "served":
+            also[name] = served_report(args, V, ctx)
+        else:
+            also[name] = measure(name, args, V, ctx, stream, args.steps, args.warmup, cpu)
     out = {
         "metric": "trace events checked/sec (bit-exact)",
-        "value": round(value, 1),
+        "value": head["value"],
         "unit": "events/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "steps": head["steps"],
+        "warmup": head["warmup"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": w["config"],
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "pipeline_roofline": pipeline,
-        "kernel_rooflines": kroof,
-        "kernels": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in kernels.items()},
-        "source_digest": source_digest(),
+        "config": head["config"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head["cpu_baseline"],
     }
-    if "extra" in w:
-        out.update(w["extra"]())
+    for k, v in head.items():
+        if k not in out and k not in ("unit",):
+            out[k] = v
+    out["also"] = also
+    out["source_digest"] = source_digest()
     print(json.dumps(out), flush=True)
 
 

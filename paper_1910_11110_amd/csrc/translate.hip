@@ -656,6 +656,7 @@ constexpr int WCOMPS = 40;  // components per wave tile
 constexpr int WDCAP = 256;  // declarations staged per wave tile
 constexpr int WROUNDS = WDCAP / WAVE;
 constexpr int WECAP = 768;  // events staged per wave tile
+constexpr uint32_t REPEAT_REG = 8; // declarations per component compared in registers
 
 struct WaveTile {
     // staged events at index off + i, off = (first output index) mod 4: groups of four
@@ -759,9 +760,6 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         // events per component (lane = component)
         uint32_t cnt = 0;
         if (fits) {
-            // first declaration of every non-empty component
-            if (lane < nc && b > a)
-                L.start[a - d_lo] = 1;
             uint32_t carry = 0;
 #pragma unroll
             for (int k = 0; k < WROUNDS; k++) {
@@ -792,25 +790,40 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             for (int k = 0; k < WROUNDS; k++)
                 pr[k] = k * WAVE + lane < nd ? (uint32_t)res[ix[k] < n_decl ? ix[k] : n_decl - 1] : 0u;
             __builtin_amdgcn_wave_barrier();
-            // a component declares each variable once: every declaration that does not
-            // start its component looks back over the earlier ones of its component
-            // (their statuses would otherwise be evaluated as if only one existed)
+            // a component declares each variable once (their statuses would otherwise be
+            // evaluated as if only one existed): the lane of each component compares its
+            // variables pairwise, in registers for up to REPEAT_REG declarations
+            if (lane < nc && b - a > 1) {
+                const uint32_t cs = (uint32_t)(a - d_lo), len = (uint32_t)(b - a);
+                if (len <= REPEAT_REG) {
+                    uint32_t v[REPEAT_REG];
 #pragma unroll
-            for (int k = 0; k < WROUNDS; k++) {
-                const uint32_t i = k * WAVE + lane;
-                if (i < nd && !L.start[i]) {
-                    const uint32_t v = L.ev[i];
-                    for (uint32_t j = i; j-- > 0;) {
-                        if (L.ev[j] == v) {
-                            report_bad(ctl, d_lo + i);
+                    for (uint32_t q = 0; q < REPEAT_REG; q++)
+                        v[q] = q < len ? L.ev[cs + q] : (0x80000000u | q); // distinct past the end
+                    uint32_t rep = 0; // bit q: declaration q repeats an earlier one
+#pragma unroll
+                    for (uint32_t q = 1; q < REPEAT_REG; q++) {
+                        bool hit = false;
+#pragma unroll
+                        for (uint32_t r = 0; r < q; r++)
+                            hit |= v[q] == v[r];
+                        rep |= (hit ? 1u : 0u) << q;
+                    }
+                    if (rep)
+                        report_bad(ctl, a + (uint32_t)__builtin_ctz(rep));
+                } else {
+                    for (uint32_t q = 1; q < len; q++) {
+                        const uint32_t vq = L.ev[cs + q];
+                        bool hit = false;
+                        for (uint32_t r = 0; r < q && !hit; r++)
+                            hit = L.ev[cs + r] == vq;
+                        if (hit) {
+                            report_bad(ctl, a + q);
                             break;
                         }
-                        if (L.start[j])
-                            break;
                     }
                 }
             }
-            __builtin_amdgcn_wave_barrier();
             if (lane < nc) {
                 const uint32_t x = L.scan[b - d_lo], y = L.scan[a - d_lo];
                 cnt = ((x & 0xFFFFu) + (x >> 16)) - ((y & 0xFFFFu) + (y >> 16));
