@@ -207,6 +207,14 @@ extern "C" int vc_sync(vc_ctx *c)
     return VC_OK;
 }
 
+// a kernel found its own bookkeeping inconsistent (it skipped the writes concerned)
+static int internal_failure(uint32_t code)
+{
+    return vc_fail(VC_EDEVICE, "internal error 0x%x: %s", code,
+                   (code & ERR_PARTITION_RANGE) ? "a partition destination fell outside the output"
+                                                : "unknown");
+}
+
 // gathers the device-side counters of a finished check into the handle
 int trace_collect(vc_trace *t)
 {
@@ -218,6 +226,12 @@ int trace_collect(vc_trace *t)
         if ((e = hipMemcpy(&h, t->tr->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost)) != hipSuccess)
             return vc_hip_fail(e, "hipMemcpy(control)");
         uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
+        if (h.err_code) {
+            t->checked = false;
+            t->check_pending = false;
+            t->error = VC_EDEVICE;
+            return internal_failure(h.err_code);
+        }
         if (bad != ~0ull) {
             t->checked = false;
             t->check_pending = false;
@@ -244,6 +258,12 @@ int trace_collect(vc_trace *t)
 int trace_collect_check(vc_trace *t, const Control &h, uint32_t first_viol)
 {
     uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
+    if (h.err_code) {
+        t->checked = false;
+        t->check_pending = false;
+        t->error = VC_EDEVICE;
+        return internal_failure(h.err_code);
+    }
     if (bad != ~0ull) {
         t->checked = false;
         t->check_pending = false;

@@ -388,7 +388,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 2
                                                      const uint32_t *__restrict__ gpre, uint32_t nranges,
                                                      uint32_t *__restrict__ dst, uint32_t *__restrict__ dstidx,
                                                      uint16_t *__restrict__ li16, uint32_t *__restrict__ tpre,
-                                                     uint64_t ntiles)
+                                                     uint64_t ntiles, Control *ctl)
 {
     static_assert(MAXB % BLOCK == 0, "whole buckets per thread in the scan");
     constexpr int BPT = MAXB / BLOCK;
@@ -487,10 +487,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 2
             uint32_t li = s_dstart[d[j]] + s_cnt[wave * MAXB + d[j]] + rank[j];
             if (((valid >> j) & 1u) && li < PTILE) {
                 s_words[li] = w[j];
-                if (li16)
+                if (li16) {
                     li16[wb + (uint64_t)j * WAVE + lane] = (uint16_t)li;
-                else
-                    dstidx[wb + (uint64_t)j * WAVE + lane] = s_gbase[d[j]] + li;
+                } else {
+                    const uint32_t di = s_gbase[d[j]] + li;
+                    dstidx[wb + (uint64_t)j * WAVE + lane] = di;
+                    if (di >= n) // readers clamp it; reported
+                        atomicOr(&ctl->err_code, ERR_PARTITION_RANGE);
+                }
             }
         }
         __syncthreads();
@@ -501,6 +505,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MAXB <= 2
             const uint32_t gi = s_gbase[b] + pos;
             if (gi < n) // always true for consistent counts; never write outside
                 dst[gi] = x;
+            else
+                atomicOr(&ctl->err_code, ERR_PARTITION_RANGE);
         }
         __syncthreads();
     }
@@ -1143,12 +1149,13 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
         if (small_nb)
             k_partition<SRC, 256><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges,
                                                             L.part, runs ? nullptr : L.dstidx,
-                                                            runs ? L.li16 : nullptr, runs ? L.tpre : nullptr, L.ptiles);
+                                                            runs ? L.li16 : nullptr, runs ? L.tpre : nullptr, L.ptiles,
+                                                            ctl);
         else
             k_partition<SRC, MAX_BUCKETS><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges,
                                                                     L.part, runs ? nullptr : L.dstidx,
                                                                     runs ? L.li16 : nullptr, runs ? L.tpre : nullptr,
-                                                                    L.ptiles);
+                                                                    L.ptiles, ctl);
         part = L.part;
         res = L.res;
     }

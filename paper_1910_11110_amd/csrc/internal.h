@@ -31,7 +31,7 @@ unsigned resident_grid(const void *kernel, uint64_t tiles, unsigned cap = 0, int
 struct Control {
     uint32_t err_index_lo;        // first malformed input index (low/high), 0xFFFFFFFF.. if none
     uint32_t err_index_hi;
-    uint32_t err_code;
+    uint32_t err_code;            // internal consistency failures (ERR_* bits), 0 if none
     uint32_t pad0;
     unsigned long long n_viol;    // violations found
     unsigned long long n_induced_stuck;
@@ -40,6 +40,9 @@ struct Control {
     unsigned long long pad[2];
     uint32_t tickets[16][TICKET_WORDS]; // tile ticket counters, one set per kernel of the pipeline
 };
+// err_code bits: a partition destination outside the output (the bucket counts of the
+// histogram pass and the partition disagree; the write is skipped)
+constexpr uint32_t ERR_PARTITION_RANGE = 1u;
 // the part of Control the host reads back (everything before the ticket counters)
 constexpr size_t CONTROL_HEADER = offsetof(Control, tickets);
 // device bytes reserved for a Control inside a larger allocation

@@ -219,7 +219,7 @@ static void finish_slot(vc_server *S, Slot &sl)
         comp.first_event = c->first_event;
         comp.n_events = c->events.size();
         uint64_t bad = ((uint64_t)h[i].err_index_hi << 32) | h[i].err_index_lo;
-        comp.status = e != hipSuccess ? VC_EDEVICE : (bad != ~0ull ? VC_EINVAL : VC_OK);
+        comp.status = e != hipSuccess || h[i].err_code ? VC_EDEVICE : (bad != ~0ull ? VC_EINVAL : VC_OK);
         comp.n_violations = h[i].n_viol;
         comp.first_violation = h[i].n_viol ? c->first_event + first[i] : c->first_event + c->events.size();
         comp.t_submit = c->t_submit;
