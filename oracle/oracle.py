@@ -65,6 +65,8 @@ def load(path: str):
     L.oracle_overlap_sets.restype = u64
     L.oracle_check_overlap.argtypes = [P, u64, u32, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
     L.oracle_check_overlap.restype = i32
+    L.oracle_check_dynamic.argtypes = [P, u64, u32, P, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
+    L.oracle_check_dynamic.restype = i32
     L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
     L.oracle_overlap_extend.restype = i32
     return L
@@ -180,6 +182,38 @@ def check_overlap(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, init: np.n
     if rc != 0:
         raise OracleError(f"oracle_check_overlap failed: {rc}")
     return CheckResult(st, fin[:n_arrays], viol[:nv.value].copy(), first.value, ni.value, nis.value)
+
+
+NO_MOTHER = 0xFFFFFFFF
+OP_CREATE, OP_DESTROY = 6, 7
+
+
+def check_dynamic(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, mother: np.ndarray,
+                  init: np.ndarray | None = None) -> CheckResult:
+    """Check with partial vectors created (op 6) and destroyed (op 7) during the trace:
+    a created partial vector inherits its mother's status; a write induces RW on the
+    arrays live at that point that overlap it."""
+    ev = np.ascontiguousarray(events, dtype=np.uint32)
+    lo = np.ascontiguousarray(lo, dtype=np.uint32)
+    hi = np.ascontiguousarray(hi, dtype=np.uint32)
+    mo = np.ascontiguousarray(mother, dtype=np.uint32)
+    n_arrays = int(lo.size)
+    ini = None if init is None else np.ascontiguousarray(init, dtype=np.uint8)
+    n = ev.size
+    st = np.empty(max(n, 1), dtype=np.uint8)
+    fin = np.empty(max(n_arrays, 1), dtype=np.uint8)
+    viol = np.empty(max(n, 1), dtype=np.uint32)
+    nv, first, ni, nis, bad = (C.c_uint64() for _ in range(5))
+    rc = lib().oracle_check_dynamic(_p(ev), n, n_arrays, _p(lo), _p(hi), _p(mo), _p(ini), _p(st), _p(fin),
+                                    _p(viol), viol.size, C.byref(nv), C.byref(first), C.byref(ni), C.byref(nis),
+                                    C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed event at index {bad.value}")
+    if rc == -3:
+        raise OracleError(f"array {bad.value} breaks the layout rules")
+    if rc != 0:
+        raise OracleError(f"oracle_check_dynamic failed: {rc}")
+    return CheckResult(st[:n], fin[:n_arrays], viol[:nv.value].copy(), first.value, ni.value, nis.value)
 
 
 def overlap_extend(m: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:

@@ -473,3 +473,143 @@ int oracle_overlap_extend(const uint32_t *m, int n_m, const uint32_t *lo, const 
     }
     return n;
 }
+
+/* ------------------------------------------------------------------------------
+ * Partial vectors created and destroyed during the trace (Section "Towards an
+ * implementation in VectorPU": a registry r_v of the live pvectors of a vector,
+ * updated at creations and deletions and queried at every call with W or RW
+ * operands; appendix "Partial Vectors": a new pvector inherits the coherence state
+ * of its mother vector).
+ *   arrays    : [lo, hi) intervals; mother[x] is the vector a partial vector x lies
+ *               in, or NO_MOTHER for a vector.  A partial vector lies inside its
+ *               mother, and a mother is a vector.
+ *   events    : op 0-4 as in the plain method, op 6 = create x, op 7 = destroy x
+ *               (side bit 0).  An array without a create event is live from the
+ *               start; each array is created at most once and destroyed at most once.
+ *   creation  : a partial vector takes its mother's status at that point, a vector
+ *               its initial status.
+ *   writes    : w_s x is followed by the induced RW_s y for every array y != x that
+ *               is live at that point and overlaps x (the registry is a plain list of
+ *               the live arrays, searched in full: the "unordered list" the paper
+ *               names for few pvectors).
+ *   outputs   : as in the plain method; the byte of a create or destroy event holds
+ *               the array's status after it as both post and pre, never stuck.
+ * Returns -1 (with *bad = event index) for a malformed word, an access to an array
+ * that is not live, a second create, a create of a live array, a destroy of an array
+ * that is not live, or the create of a partial vector whose mother is not live;
+ * -3 (with *bad = array) for arrays that break the layout rules above.
+ * ------------------------------------------------------------------------------ */
+#define NO_MOTHER 0xFFFFFFFFu
+enum { OP_CREATE = 6, OP_DESTROY = 7 };
+
+int oracle_check_dynamic(const uint32_t *events, uint64_t n, uint32_t n_arrays, const uint32_t *lo,
+                         const uint32_t *hi, const uint32_t *mother, const uint8_t *init, uint8_t *status_out,
+                         uint8_t *final_out, uint32_t *viol_out, uint64_t viol_cap, uint64_t *n_viol,
+                         uint64_t *first_viol, uint64_t *n_induced, uint64_t *n_induced_stuck, uint64_t *bad)
+{
+    for (uint32_t x = 0; x < n_arrays; x++) {
+        uint32_t m = mother[x];
+        int ok = lo[x] < hi[x];
+        if (m != NO_MOTHER)
+            ok = ok && m < n_arrays && m != x && mother[m] == NO_MOTHER && lo[m] <= lo[x] && hi[x] <= hi[m];
+        if (!ok) {
+            if (bad) *bad = x;
+            return -3;
+        }
+    }
+    uint8_t *sigma = (uint8_t *)malloc(n_arrays ? n_arrays : 1);
+    uint8_t *live = (uint8_t *)malloc(n_arrays ? n_arrays : 1);
+    uint8_t *created = (uint8_t *)calloc(n_arrays ? n_arrays : 1, 1);
+    uint32_t *list = (uint32_t *)malloc((n_arrays ? n_arrays : 1) * sizeof(uint32_t)); /* the registry */
+    uint32_t *where = (uint32_t *)malloc((n_arrays ? n_arrays : 1) * sizeof(uint32_t));
+    if (!sigma || !live || !created || !list || !where) {
+        free(sigma); free(live); free(created); free(list); free(where);
+        return -2;
+    }
+    /* arrays without a create event are live from the start */
+    for (uint32_t x = 0; x < n_arrays; x++)
+        live[x] = 1;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t x = events[i] & 0xFFFFFFu, op = (events[i] >> 24) & 7u;
+        if (op == OP_CREATE && x < n_arrays)
+            live[x] = 0;
+    }
+    uint32_t n_live = 0;
+    for (uint32_t x = 0; x < n_arrays; x++) {
+        sigma[x] = init ? init[x] : 1;
+        if (live[x]) {
+            where[x] = n_live;
+            list[n_live++] = x;
+        }
+    }
+    uint64_t nv = 0, first = n, ni = 0, nis = 0;
+    int rc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t e = events[i];
+        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+        int malformed = (e >> 28) != 0 || op == 5 || x >= n_arrays || (op >= OP_CREATE && side);
+        if (!malformed) {
+            if (op == OP_CREATE)
+                malformed = live[x] || created[x] || (mother[x] != NO_MOTHER && !live[mother[x]]);
+            else
+                malformed = !live[x];
+        }
+        if (malformed) {
+            if (bad) *bad = i;
+            rc = -1;
+            break;
+        }
+        if (op == OP_CREATE) {
+            sigma[x] = mother[x] != NO_MOTHER ? sigma[mother[x]] : (init ? init[x] : 1);
+            live[x] = 1;
+            created[x] = 1;
+            where[x] = n_live;
+            list[n_live++] = x;
+            if (status_out)
+                status_out[i] = (uint8_t)(sigma[x] | (sigma[x] << 2));
+            continue;
+        }
+        if (op == OP_DESTROY) {
+            live[x] = 0;
+            uint32_t last = list[--n_live]; /* remove x from the registry */
+            list[where[x]] = last;
+            where[last] = where[x];
+            if (status_out)
+                status_out[i] = (uint8_t)(sigma[x] | (sigma[x] << 2));
+            continue;
+        }
+        int pre = sigma[x], stuck = 0;
+        int post = apply_effect((int)op, (int)side, pre, &stuck);
+        sigma[x] = (uint8_t)post;
+        if (status_out)
+            status_out[i] = (uint8_t)(post | (pre << 2) | (stuck << 7));
+        if (stuck) {
+            if (viol_out && nv < viol_cap)
+                viol_out[nv] = (uint32_t)i;
+            else if (viol_out)
+                rc = -5;
+            if (first == n)
+                first = i;
+            nv++;
+        }
+        if (op == OP_W) {
+            for (uint32_t k = 0; k < n_live; k++) {
+                uint32_t y = list[k];
+                if (!overlaps(lo, hi, x, y))
+                    continue;
+                int st = 0;
+                sigma[y] = (uint8_t)apply_induced_rw((int)side, sigma[y], &st);
+                ni++;
+                nis += (uint64_t)st;
+            }
+        }
+    }
+    if (final_out)
+        memcpy(final_out, sigma, n_arrays);
+    if (n_viol) *n_viol = nv;
+    if (first_viol) *first_viol = first;
+    if (n_induced) *n_induced = ni;
+    if (n_induced_stuck) *n_induced_stuck = nis;
+    free(sigma); free(live); free(created); free(list); free(where);
+    return rc;
+}

@@ -37,6 +37,7 @@ S_K, S_ZIPF, S_MODE, S_CSIDE = 10, 11, 12, 13
 S_LEN, S_LO, S_ARR = 20, 21, 22
 S_TLEN, S_TVARS, S_TARR, S_TSEED = 30, 31, 32, 33
 S_ARRIVE = 40
+S_DMOTHER, S_DLEN, S_DLO, S_DLIFE, S_DCPOS, S_DDPOS, S_DVAR = 50, 51, 52, 53, 54, 55, 56
 
 OP_R, OP_W, OP_PUSH, OP_PULL, OP_NOOP = 0, 1, 2, 3, 4
 MODE_R, MODE_W, MODE_RW = 0, 1, 2
@@ -269,6 +270,87 @@ def intervals(n_arrays: int, seed: int, space: int = 1 << 24, max_len: int = 409
     with np.errstate(over="ignore"):
         lo[:] = ((hi32 * bound) >> np.uint64(32)).astype(np.int64)
     return lo.astype(np.uint32), (lo + ln).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------------------
+# partial vectors created and destroyed during a trace
+# --------------------------------------------------------------------------------------
+NO_MOTHER = 0xFFFFFFFF
+OP_CREATE, OP_DESTROY = 6, 7
+
+
+@dataclass
+class DynamicTrace:
+    events: np.ndarray  # uint32 event words (ops 0-4, 6 create, 7 destroy)
+    lo: np.ndarray
+    hi: np.ndarray
+    mother: np.ndarray  # uint32, NO_MOTHER for a vector
+
+
+def dynamic_trace(n: int, n_vectors: int, n_pvectors: int, seed: int, space: int = 1 << 24,
+                  max_len: int = 4096, p_initial: float = 0.25, p_destroyed: float = 0.5) -> DynamicTrace:
+    """Vectors tile the address space (vector v holds [v L, (v + 1) L), L = space /
+    n_vectors) and live for the whole trace.  Each partial vector has a mother drawn
+    uniformly, a length log-uniform in [1, min(max_len, L)] and a start uniform inside
+    its mother.  A fraction ``p_initial`` of partial vectors is live from the start; the
+    others are created at a uniform position; a fraction ``p_destroyed`` of all partial
+    vectors is destroyed at a uniform later position.  Events draw the array uniformly
+    over all ids, op and side as in the plain law; an event whose array is not live at
+    its position goes to the array's mother instead; create and destroy words replace
+    the events at their positions (positions drawn distinct)."""
+    L = space // n_vectors
+    n_ids = n_vectors + n_pvectors
+    lo = np.empty(n_ids, np.int64)
+    hi = np.empty(n_ids, np.int64)
+    mother = np.full(n_ids, NO_MOTHER, np.uint32)
+    lo[:n_vectors] = np.arange(n_vectors, dtype=np.int64) * L
+    hi[:n_vectors] = lo[:n_vectors] + L
+    m = below(draws(seed, S_DMOTHER, 0, n_pvectors), n_vectors).astype(np.int64)
+    cap = min(max_len, L)
+    u = unit(draws(seed, S_DLEN, 0, n_pvectors))
+    ln = np.clip(np.floor(np.exp(u * math.log(cap + 1))).astype(np.int64), 1, cap)
+    off = (unit(draws(seed, S_DLO, 0, n_pvectors)) * (L - ln + 1)).astype(np.int64)
+    off = np.minimum(off, L - ln)
+    lo[n_vectors:] = lo[m] + off
+    hi[n_vectors:] = lo[n_vectors:] + ln
+    mother[n_vectors:] = m.astype(np.uint32)
+    # lifetimes: create / destroy positions, all distinct
+    ul = unit(draws(seed, S_DLIFE, 0, 2 * n_pvectors)).reshape(2, n_pvectors)
+    created = ul[0] >= p_initial
+    destroyed = ul[1] < p_destroyed
+    k = int(created.sum() + destroyed.sum())
+    assert k <= n, "more lifetime events than positions"
+    # distinct positions: a random subset of size k in increasing order, dealt out in a
+    # seeded order
+    pool = np.unique(below(draws(seed, S_DCPOS, 0, 4 * k + 16), n))
+    while pool.size < k:
+        pool = np.unique(np.concatenate([pool, below(draws(seed, S_DDPOS, pool.size, 4 * k + 16), n)]))
+    order = np.argsort(draws(seed, S_DDPOS, 1 << 40, pool.size))
+    pos = pool[order][:k]
+    ids = np.nonzero(created)[0]
+    cpos = np.full(n_pvectors, -1, np.int64)
+    cpos[ids] = pos[:ids.size]
+    dids = np.nonzero(destroyed)[0]
+    dcand = pos[ids.size:ids.size + dids.size]
+    dpos = np.full(n_pvectors, n + 1, np.int64)
+    # a destroy goes after the create: swap the two positions when drawn the other way
+    c_of_d = cpos[dids]
+    swap = c_of_d > dcand
+    dpos[dids] = np.where(swap, c_of_d, dcand)
+    cpos[dids[swap]] = dcand[swap]
+    ev = plain_events(n, n_ids, seed)
+    x = (ev & np.uint32(0xFFFFFF)).astype(np.int64)
+    t = np.arange(n, dtype=np.int64)
+    pv = x >= n_vectors
+    j = np.where(pv, x - n_vectors, 0)
+    dead = pv & ((cpos[j] >= t) | (dpos[j] <= t))
+    x = np.where(dead, mother[np.where(pv, x, 0)].astype(np.int64), x)
+    ev = (ev & np.uint32(0xFF000000)) | x.astype(np.uint32)
+    cw = np.nonzero(cpos >= 0)[0]
+    ev[cpos[cw]] = (n_vectors + cw).astype(np.uint32) | np.uint32(OP_CREATE << 24)
+    dw = np.nonzero(dpos <= n)[0]
+    ev[dpos[dw]] = (n_vectors + dw).astype(np.uint32) | np.uint32(OP_DESTROY << 24)
+    return DynamicTrace(ev, lo.astype(np.uint32), hi.astype(np.uint32), mother)
 
 
 # --------------------------------------------------------------------------------------

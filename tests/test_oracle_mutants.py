@@ -7,6 +7,7 @@ import tempfile
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_dynamic as D
 from tests import test_oracle_pins as T
 from tests.helpers import load_yaml
 
@@ -31,6 +32,15 @@ MUTANTS = {
     "overlap-rw-not-inferred": ("if (mode == 2) /* RW x# */\n                    need_rw = 1;", "\n"),
     "induced-rw-wrong-side": ("cur = apply_effect(OP_W, side, cur, &st2);", "cur = apply_effect(OP_W, !side, cur, &st2);"),
     "repeated-variable-accepted": ("if ((decls[e] & 0xFFFFFFu) == v) {", "if (0) {"),
+    "dynamic-inherits-initial": ("sigma[x] = mother[x] != NO_MOTHER ? sigma[mother[x]] : (init ? init[x] : 1);",
+                                 "sigma[x] = init ? init[x] : 1;"),
+    "dynamic-registry-keeps-destroyed": ("uint32_t last = list[--n_live]; /* remove x from the registry */\n"
+                                         "            list[where[x]] = last;\n            where[last] = where[x];",
+                                         ""),
+    "dynamic-registry-misses-created": ("created[x] = 1;\n            where[x] = n_live;\n            list[n_live++] = x;",
+                                        "created[x] = 1;"),
+    "dynamic-induced-ignores-liveness": ("for (uint32_t k = 0; k < n_live; k++) {\n                uint32_t y = list[k];",
+                                         "for (uint32_t k = 0; k < n_arrays; k++) {\n                uint32_t y = k;"),
     "overlap-inclusive-upper": ("return x != y && lo[x] < hi[y] && lo[y] < hi[x];",
                                 "return x != y && lo[x] <= hi[y] && lo[y] <= hi[x];"),
 }
@@ -51,6 +61,10 @@ def _pins():
     T.test_overlap_rules_keep_element_model_consistent_pvector()
     T.test_overlap_sets_brute_force_small()
     T.test_repeated_variable_in_a_component_is_rejected()
+    D.test_dynamic_worked_scenario()
+    D.test_dynamic_without_lifecycle_is_the_static_overlap_check()
+    D.test_dynamic_statuses_abstract_the_elements()
+    D.test_dynamic_scenario_statuses_abstract_the_elements()
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
