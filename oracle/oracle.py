@@ -65,7 +65,7 @@ def load(path: str):
     L.oracle_overlap_sets.restype = u64
     L.oracle_check_overlap.argtypes = [P, u64, u32, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
     L.oracle_check_overlap.restype = i32
-    L.oracle_check_dynamic.argtypes = [P, u64, u32, P, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
+    L.oracle_check_dynamic.argtypes = [P, u64, u32, P, P, P, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
     L.oracle_check_dynamic.restype = i32
     L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
     L.oracle_overlap_extend.restype = i32
@@ -189,10 +189,11 @@ OP_CREATE, OP_DESTROY = 6, 7
 
 
 def check_dynamic(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, mother: np.ndarray,
-                  init: np.ndarray | None = None) -> CheckResult:
+                  init: np.ndarray | None = None, sets=None) -> CheckResult:
     """Check with partial vectors created (op 6) and destroyed (op 7) during the trace:
     a created partial vector inherits its mother's status; a write induces RW on the
-    arrays live at that point that overlap it."""
+    arrays live at that point that overlap it (found in the list of live arrays, or,
+    with sets = overlap_sets(lo, hi), among the overlapping arrays)."""
     ev = np.ascontiguousarray(events, dtype=np.uint32)
     lo = np.ascontiguousarray(lo, dtype=np.uint32)
     hi = np.ascontiguousarray(hi, dtype=np.uint32)
@@ -204,7 +205,12 @@ def check_dynamic(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, mother: np
     fin = np.empty(max(n_arrays, 1), dtype=np.uint8)
     viol = np.empty(max(n, 1), dtype=np.uint32)
     nv, first, ni, nis, bad = (C.c_uint64() for _ in range(5))
-    rc = lib().oracle_check_dynamic(_p(ev), n, n_arrays, _p(lo), _p(hi), _p(mo), _p(ini), _p(st), _p(fin),
+    off = nbr = None
+    if sets is not None:
+        off = np.ascontiguousarray(sets[0], dtype=np.uint64)
+        nbr = np.ascontiguousarray(sets[1] if sets[1].size else np.zeros(1, np.uint32), dtype=np.uint32)
+    rc = lib().oracle_check_dynamic(_p(ev), n, n_arrays, _p(lo), _p(hi), _p(mo), _p(off), _p(nbr), _p(ini), _p(st),
+                                    _p(fin),
                                     _p(viol), viol.size, C.byref(nv), C.byref(first), C.byref(ni), C.byref(nis),
                                     C.byref(bad))
     if rc == -1:

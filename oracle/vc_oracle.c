@@ -491,7 +491,8 @@ int oracle_overlap_extend(const uint32_t *m, int n_m, const uint32_t *lo, const 
  *   writes    : w_s x is followed by the induced RW_s y for every array y != x that
  *               is live at that point and overlaps x (the registry is a plain list of
  *               the live arrays, searched in full: the "unordered list" the paper
- *               names for few pvectors).
+ *               names for few pvectors; or, when off/nbr are given, the overlap
+ *               sets of oracle_overlap_sets filtered by liveness, the same targets).
  *   outputs   : as in the plain method; the byte of a create or destroy event holds
  *               the array's status after it as both post and pre, never stuck.
  * Returns -1 (with *bad = event index) for a malformed word, an access to an array
@@ -503,7 +504,8 @@ int oracle_overlap_extend(const uint32_t *m, int n_m, const uint32_t *lo, const 
 enum { OP_CREATE = 6, OP_DESTROY = 7 };
 
 int oracle_check_dynamic(const uint32_t *events, uint64_t n, uint32_t n_arrays, const uint32_t *lo,
-                         const uint32_t *hi, const uint32_t *mother, const uint8_t *init, uint8_t *status_out,
+                         const uint32_t *hi, const uint32_t *mother, const uint64_t *off, const uint32_t *nbr,
+                         const uint8_t *init, uint8_t *status_out,
                          uint8_t *final_out, uint32_t *viol_out, uint64_t viol_cap, uint64_t *n_viol,
                          uint64_t *first_viol, uint64_t *n_induced, uint64_t *n_induced_stuck, uint64_t *bad)
 {
@@ -592,10 +594,22 @@ int oracle_check_dynamic(const uint32_t *events, uint64_t n, uint32_t n_arrays, 
                 first = i;
             nv++;
         }
-        if (op == OP_W) {
+        if (op == OP_W && !off) {
             for (uint32_t k = 0; k < n_live; k++) {
                 uint32_t y = list[k];
                 if (!overlaps(lo, hi, x, y))
+                    continue;
+                int st = 0;
+                sigma[y] = (uint8_t)apply_induced_rw((int)side, sigma[y], &st);
+                ni++;
+                nis += (uint64_t)st;
+            }
+        } else if (op == OP_W) {
+            /* the same targets from the overlap sets of oracle_overlap_sets: the live
+             * arrays among the ones overlapping x */
+            for (uint64_t j = off[x]; j < off[x + 1]; j++) {
+                uint32_t y = nbr[j];
+                if (!live[y])
                     continue;
                 int st = 0;
                 sigma[y] = (uint8_t)apply_induced_rw((int)side, sigma[y], &st);

@@ -50,6 +50,17 @@ def test_dynamic_without_lifecycle_is_the_static_overlap_check():
         assert np.array_equal(a.violations, b.violations) and a.n_induced == b.n_induced
 
 
+def test_dynamic_registry_list_and_overlap_sets_agree():
+    """The two ways of finding the induced targets (the live list searched in full, the
+    overlap sets filtered by liveness) give the same results."""
+    for seed in range(3):
+        d = gen.dynamic_trace(40_000, 8, 600, seed, space=1 << 14, max_len=512)
+        a = O.check_dynamic(d.events, d.lo, d.hi, d.mother)
+        b = O.check_dynamic(d.events, d.lo, d.hi, d.mother, sets=O.overlap_sets(d.lo, d.hi))
+        assert np.array_equal(a.status, b.status) and np.array_equal(a.final, b.final)
+        assert np.array_equal(a.violations, b.violations) and a.n_induced == b.n_induced > 0
+
+
 def _element_replay(ev, lo, hi, mo, r):
     """Replays a dynamic trace on an element-level model (every address has its own
     status pair; an array-level r, w, Push or Pull acts on every element of the array,
