@@ -9,10 +9,11 @@ Inputs are generated on the host, copied to HBM once, and stay resident; the tim
 region covers only device work.
 
 Prints one JSON line.  By default the line also carries, under "also", the plain
-single-trace workload at 2^28 events over 64 ids, the batched workload (4,096 traces)
-and the served workload (an open-loop Poisson replay), each with its own roofline,
-oracle baseline and, for batched and served, the same traces checked one after
-another by the per-trace path on the same GPU.
+single-trace workload at 2^28 events over 64 ids, the overlapping-array workload, the
+workload with partial vectors created and destroyed during the trace, the batched
+workload (4,096 traces) and the served workload (an open-loop Poisson replay), each
+with its own roofline, oracle baseline and, for batched and served, the same traces
+checked one after another by the per-trace path on the same GPU.
 """
 from __future__ import annotations
 
@@ -233,6 +234,42 @@ def wl_overlap(args, V, ctx, stream):
     cfg = {"workload": "overlap-2^16-arrays-2^24-events", "n_events": n, "n_arrays": n_arr, "violations": int(viol),
            "interval_sweep_ms_incl_host": round(sweep_s * 1e3, 3)}
     return dict(step=step, units=n, unit="event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te))
+
+
+def wl_dynamic(args, V, ctx, stream):
+    """Partial vectors created and destroyed during the trace: 2^24 events over 2^10
+    vectors (tiling a 2^24-element address space) and 64,512 partial vectors (lengths
+    log-uniform in [1, 4096], a quarter live from the start, half destroyed)."""
+    from paper_1910_11110_amd import gen
+    n, nv = 1 << 24, 1 << 10
+    log(f"[bench] dynamic: generating {n} events over {1 << 16} arrays")
+    d = gen.dynamic_trace(n, nv, (1 << 16) - nv, args.seed)
+    t = V.Trace.load(ctx, d.events, d.lo.size, lifetimes=True)
+    t.set_dynamic_arrays(d.lo, d.hi, d.mother)
+    t.check()
+    ctx.sync()
+    viol = t.violations().total
+    n_ids = int(d.lo.size)
+
+    def step():
+        t.check()
+
+    def bytes_alg():
+        # events in, status bytes out, violation indices, final table; intervals and
+        # mothers read once
+        return 4 * n + n + 4 * viol + n_ids + 12 * n_ids
+
+    def cpu_sample():
+        from oracle import oracle as O
+        sets = O.overlap_sets(d.lo, d.hi)
+        return (_median_rate(n, lambda: O.check_dynamic(d.events, d.lo, d.hi, d.mother, sets=sets)),
+                "oracle dynamic check of the full workload (overlap sets precomputed), median of 3", None)
+
+    cfg = {"workload": "dynamic-2^16-arrays-2^24-events", "n_events": n, "n_vectors": nv, "n_arrays": n_ids,
+           "creates": int(((d.events >> 24) & 7 == 6).sum()), "destroys": int(((d.events >> 24) & 7 == 7).sum()),
+           "violations": int(viol)}
+    return dict(step=step, units=n, unit="event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, d),
+                multi_pass=("sort_pass", "hist"))
 
 
 def _oracle_job(inp, sets):
@@ -470,7 +507,7 @@ def copy_probe(torch, n_words=1 << 28):
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
              "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
              "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap,
-             "batched": wl_batched}
+             "batched": wl_batched, "dynamic": wl_dynamic}
 
 
 def measure(name, args, V, ctx, stream, steps, warmup, cpu=True):
@@ -554,7 +591,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="components", choices=sorted(WORKLOADS) + ["served"])
-    ap.add_argument("--also", default="plain-large,batched,served",
+    ap.add_argument("--also", default="plain-large,overlap,dynamic,batched,served",
                     help="workloads reported beside the headline one (comma separated; empty for none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--comp-log2", type=int, default=23)

@@ -64,6 +64,8 @@ enum vc_status {
 #define VC_DEVICE_INPUT 1u  /* input pointers are device pointers (borrowed) */
 #define VC_DEVICE_INIT 2u   /* init pointer is a device pointer (borrowed) */
 #define VC_TRANSLATE_CHECK 4u /* vc_translate also checks the translated trace */
+#define VC_LIFETIME_EVENTS 8u /* vc_trace_load: host events may also be op 6 (create) and
+                                 op 7 (destroy), for vc_trace_set_dynamic_arrays */
 
 typedef struct vc_ctx vc_ctx;
 typedef struct vc_trace vc_trace;
@@ -105,6 +107,26 @@ int vc_trace_load(vc_ctx *ctx, const uint32_t *events, uint64_t n, uint32_t n_id
  * the one-declaration component of each event.  The overlap sets are computed on the
  * device by an interval sweep and stay resident with the trace. */
 int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi, uint32_t flags);
+
+/* Arrays created and destroyed during the trace: partial vectors of a vector (Section
+ * 4.3, "Towards an implementation in VectorPU", and the appendix on partial vectors).
+ * lo/hi   : n_ids half-open intervals (host), as for vc_trace_set_arrays.
+ * mother  : n_ids entries (host): the vector array x lies in (a partial vector), or
+ *           0xFFFFFFFF for a vector.  A mother is a vector, and its interval holds the
+ *           partial vector's.
+ * The events (loaded with VC_LIFETIME_EVENTS) may then also be op 6 "create x" and op
+ * 7 "destroy x" (side bit 0).  An array with no create event is live from the start;
+ * each array is created at most once and destroyed at most once; every other event
+ * needs its array live, and a partial vector's create needs its mother live.  A
+ * created partial vector starts at its mother's status at that point (a created vector
+ * at its initial status); a write w_s x induces RW_s y on every array y that is live at
+ * that point and overlaps x (the registry of live arrays, queried at each write).  The
+ * byte of a create or destroy event holds the array's status after it as post and pre.
+ * Lifetime errors are reported as malformed input at the first offending event
+ * (VC_EINVAL here for the trace's current events; at vc_sync if device events change).
+ * n must be < 2^30. */
+int vc_trace_set_dynamic_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi, const uint32_t *mother,
+                                uint32_t flags);
 
 /* Overlap sets computed for the arrays, as CSR: off has n_ids + 1 entries (host),
  * nbr receives off[n_ids] ascending neighbour ids per array. */

@@ -291,11 +291,13 @@ static int trace_alloc_common(vc_ctx *c, vc_trace *t)
     return VC_OK;
 }
 
-static int validate_events_host(const uint32_t *ev, uint64_t n, uint32_t n_ids)
+static int validate_events_host(const uint32_t *ev, uint64_t n, uint32_t n_ids, bool lifetimes)
 {
     for (uint64_t i = 0; i < n; i++) {
         uint32_t w = ev[i];
-        if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= n_ids)
+        const uint32_t op = (w >> 24) & 7u;
+        const bool op_ok = op <= 4 || (lifetimes && op >= 6 && ((w >> 27) & 1u) == 0);
+        if ((w >> 28) != 0 || !op_ok || (w & 0xFFFFFFu) >= n_ids)
             return vc_fail(VC_EINVAL, "malformed event word 0x%08x at index %llu (n_ids %u)", w,
                            (unsigned long long)i, n_ids);
     }
@@ -340,7 +342,7 @@ extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint
         return vc_fail(VC_EINVAL, "vc_trace_load: events but n_ids is 0");
     (void)hipSetDevice(c->device);
     if (!(flags & VC_DEVICE_INPUT)) {
-        int r = validate_events_host(events, n, n_ids);
+        int r = validate_events_host(events, n, n_ids, (flags & VC_LIFETIME_EVENTS) != 0);
         if (r != VC_OK)
             return r;
     }
@@ -479,6 +481,8 @@ int enqueue_check(vc_trace *t, hipStream_t s)
                             t->scratch.p, t->ctl, s, t->ctx->cu_count, t->init ? nullptr : &fill);
         return VC_OK;
     }
+    if (t->dynamic)
+        return dynamic_enqueue(t, s);
     uint64_t m = t->n;
     if (t->has_arrays) {
         m = overlap_combined_size(t);

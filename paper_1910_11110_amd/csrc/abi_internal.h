@@ -88,6 +88,12 @@ struct vc_trace {
     bool own_arrays = false;
     vc::OverlapSets sets{};
     uint64_t n_induced = 0; // induced events of the last expansion
+    // arrays created and destroyed during the trace: the mother of every array, and
+    // the lifetimes, initial statuses of the second scan and probe statuses
+    bool dynamic = false;
+    uint32_t *mother = nullptr;
+    uint64_t n_items = 0; // combined items (events, probes, induced) of the last sizing
+    DevBuf dyn;
 
     // outputs
     DevBuf status, fin, viol;
@@ -115,6 +121,7 @@ void enqueue_check_items(vc_trace *t, uint64_t m, hipStream_t s);
 int enqueue_check(vc_trace *t, hipStream_t s);
 
 // overlap (overlap_abi.cpp)
+int dynamic_enqueue(vc_trace *t, hipStream_t s);
 uint64_t overlap_combined_size(vc_trace *t);
 void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s);
 void overlap_release(vc_trace *t);

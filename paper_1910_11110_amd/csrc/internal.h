@@ -170,6 +170,22 @@ void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, 
                                      const uint64_t *chunk_prefix, uint32_t *out, uint8_t *status, Control *tr_ctl,
                                      Control *ctl, hipStream_t s);
 
+// ------------------------------- arrays created during the trace ------------------
+// lifetimes: first create / destroy position of every array (NO_POS if none)
+void launch_dyn_life(const uint32_t *ev, uint64_t n, uint32_t n_ids, uint32_t *cpos, uint32_t *dpos, hipStream_t s);
+struct OverlapSets;
+// per event: items it contributes (itself, a probe on its mother at a create, one
+// induced RW per live neighbour at a write); errors to ctl's error index
+void launch_dyn_count(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
+                      const uint32_t *dpos, const OverlapSets *o, uint32_t *cnt, Control *ctl, hipStream_t s);
+void launch_dyn_emit(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
+                     const uint32_t *dpos, const OverlapSets *o, const uint64_t *pos, uint64_t *items, uint64_t cap,
+                     Control *ctl, hipStream_t s);
+// initial statuses of the second scan (inherited by created partial vectors) into
+// init2 and fin
+void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint8_t *probe_pre, uint64_t n,
+                        const uint8_t *init, uint32_t n_ids, uint8_t *init2, uint8_t *fin, hipStream_t s);
+
 // ------------------------------- overlap ------------------------------------------
 struct OverlapSets {
     uint64_t *off = nullptr; // n_arrays + 1

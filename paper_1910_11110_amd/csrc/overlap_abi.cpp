@@ -46,15 +46,16 @@ int size_expansion(vc_trace *t)
 
 } // namespace
 
-extern "C" int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi, uint32_t flags)
+// intervals to the device (copied or borrowed) and their overlap sets by the sweep
+static int set_intervals(vc_trace *t, const uint32_t *lo, const uint32_t *hi, uint32_t flags, const char *fn)
 {
     if (!lo || !hi)
-        return vc_fail(VC_EINVAL, "vc_trace_set_arrays: NULL argument");
-    int r0 = trace_usable(t, "vc_trace_set_arrays");
+        return vc_fail(VC_EINVAL, "%s: NULL argument", fn);
+    int r0 = trace_usable(t, fn);
     if (r0 != VC_OK)
         return r0;
     if (t->tr)
-        return vc_fail(VC_EINVAL, "vc_trace_set_arrays: arrays apply to loaded traces, not translations");
+        return vc_fail(VC_EINVAL, "%s: arrays apply to loaded traces, not translations", fn);
     vc_ctx *c = t->ctx;
     (void)hipSetDevice(c->device);
     if (t->pending) {
@@ -100,11 +101,169 @@ extern "C" int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32
         return vc_fail(VC_EINVAL, "array %llu is not a non-empty interval below 2^28", (unsigned long long)bad);
     }
     t->has_arrays = true;
-    int r = size_expansion(t);
+    return VC_OK;
+}
+
+extern "C" int vc_trace_set_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi, uint32_t flags)
+{
+    int r = set_intervals(t, lo, hi, flags, "vc_trace_set_arrays");
+    if (r != VC_OK)
+        return r;
+    r = size_expansion(t);
     if (r != VC_OK) {
         overlap_release(t);
         return r;
     }
+    return VC_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// arrays created and destroyed during the trace
+// ------------------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t NO_MOTHER = 0xFFFFFFFFu;
+
+struct DynLayout {
+    uint32_t *cpos, *dpos;
+    uint8_t *init2, *pre;
+    size_t bytes;
+};
+
+DynLayout dyn_layout(void *base, uint64_t n, uint32_t n_ids)
+{
+    char *p = (char *)base;
+    size_t off = 0;
+    auto take = [&](size_t sz) {
+        char *r = p ? p + off : nullptr;
+        off += (sz + 255) & ~size_t(255);
+        return r;
+    };
+    DynLayout L;
+    L.cpos = (uint32_t *)take((size_t)(n_ids ? n_ids : 1) * 4);
+    L.dpos = (uint32_t *)take((size_t)(n_ids ? n_ids : 1) * 4);
+    L.init2 = (uint8_t *)take(n_ids ? n_ids : 1);
+    L.pre = (uint8_t *)take(2 * n + 1);
+    L.bytes = off;
+    return L;
+}
+
+// lifetimes, item counts and their scan (cnt and pos in t->aux), on the stream
+int dyn_count_items(vc_trace *t, hipStream_t s)
+{
+    int r;
+    const uint64_t n = t->n;
+    if ((r = devbuf_reserve(t->aux, n * 4 + (n + 1) * 8 + 16)) != VC_OK ||
+        (r = devbuf_reserve(t->scratch, std::max(t->scratch.bytes, excl_scan_scratch_bytes(n)))) != VC_OK ||
+        (r = devbuf_reserve(t->dyn, dyn_layout(nullptr, n, t->n_ids).bytes)) != VC_OK)
+        return r;
+    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids);
+    uint32_t *cnt = (uint32_t *)t->aux.p;
+    uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
+    launch_dyn_life(t->events, n, t->n_ids, L.cpos, L.dpos, s);
+    launch_dyn_count(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, cnt, t->ctl, s);
+    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, t->ctl->tickets[5], s);
+    return VC_OK;
+}
+
+// sizes the combined items of the trace's current events (one sync)
+int dyn_size(vc_trace *t)
+{
+    hipStream_t s = t->ctx->stream;
+    const uint64_t n = t->n;
+    launch_reset_control(t->ctl, s);
+    int r = dyn_count_items(t, s);
+    if (r != VC_OK)
+        return r;
+    uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
+    uint64_t total = 0;
+    Control h;
+    hipError_t e = hipMemcpyAsync(&total, pos + n, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&h, t->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return vc_hip_fail(e, "sizing of the dynamic trace");
+    uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
+    if (bad != ~0ull)
+        return vc_fail(VC_EINVAL, "malformed event word or lifetime error at index %llu", (unsigned long long)bad);
+    if (total >= (1ull << 31))
+        return vc_fail(VC_EINVAL, "dynamic trace with probes and induced events (%llu) exceeds 2^31 - 1",
+                       (unsigned long long)total);
+    t->n_items = total;
+    return VC_OK;
+}
+
+} // namespace
+
+extern "C" int vc_trace_set_dynamic_arrays(vc_trace *t, const uint32_t *lo, const uint32_t *hi,
+                                           const uint32_t *mother, uint32_t flags)
+{
+    if (!mother || !lo || !hi)
+        return vc_fail(VC_EINVAL, "vc_trace_set_dynamic_arrays: NULL argument");
+    if (flags & VC_DEVICE_INPUT)
+        return vc_fail(VC_EINVAL, "vc_trace_set_dynamic_arrays: the arrays are host buffers");
+    int r0 = trace_usable(t, "vc_trace_set_dynamic_arrays");
+    if (r0 != VC_OK)
+        return r0;
+    if (t->n >= (1ull << 30))
+        return vc_fail(VC_EINVAL, "vc_trace_set_dynamic_arrays: n %llu must be < 2^30", (unsigned long long)t->n);
+    const uint32_t n = t->n_ids;
+    for (uint32_t x = 0; x < n; x++) {
+        const uint32_t m = mother[x];
+        if (m == NO_MOTHER)
+            continue;
+        if (m >= n || m == x || mother[m] != NO_MOTHER || !(lo[m] <= lo[x] && hi[x] <= hi[m]))
+            return vc_fail(VC_EINVAL,
+                           "array %u: its mother %u must be a vector (no mother of its own) whose interval holds it",
+                           x, m);
+    }
+    int r = set_intervals(t, lo, hi, 0, "vc_trace_set_dynamic_arrays");
+    if (r != VC_OK)
+        return r;
+    hipError_t e;
+    if ((e = hipMalloc(&t->mother, (size_t)(n ? n : 1) * 4)) != hipSuccess) {
+        overlap_release(t);
+        return vc_hip_fail(e, "hipMalloc(mother)");
+    }
+    if (n && (e = hipMemcpy(t->mother, mother, (size_t)n * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+        overlap_release(t);
+        return vc_hip_fail(e, "hipMemcpy(mother)");
+    }
+    t->dynamic = true;
+    if ((r = dyn_size(t)) != VC_OK) {
+        overlap_release(t);
+        return r;
+    }
+    return VC_OK;
+}
+
+// the check of a dynamic trace: items, sort, the scan for the inherited statuses, the
+// scan for every status, violations
+int dynamic_enqueue(vc_trace *t, hipStream_t s)
+{
+    const uint64_t n = t->n, m = t->n_items;
+    int r;
+    if ((r = trace_reserve(t, m)) != VC_OK)
+        return r;
+    // probes write their bytes past the trace's n (payload n + t)
+    if ((r = devbuf_reserve(t->status, 2 * n + 1)) != VC_OK)
+        return r;
+    launch_reset_control(t->ctl, s);
+    if ((r = dyn_count_items(t, s)) != VC_OK)
+        return r;
+    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids);
+    uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
+    launch_dyn_emit(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, pos, (uint64_t *)t->items_a.p, m,
+                    t->ctl, s);
+    uint64_t *sorted = sort_items((uint64_t *)t->items_a.p, (uint64_t *)t->items_b.p, m,
+                                  (int)key_bits_for(t->n_ids), t->scratch.p, t->ctl, s);
+    launch_segscan(sorted, m, t->init, t->n_ids, SCAN_PRE, L.pre, nullptr, t->scratch.p, t->ctl, s);
+    launch_dyn_inherit(t->mother, L.cpos, L.pre, n, t->init, t->n_ids, L.init2, (uint8_t *)t->fin.p, s);
+    launch_segscan(sorted, m, L.init2, t->n_ids, SCAN_STATUS, (uint8_t *)t->status.p, (uint8_t *)t->fin.p,
+                   t->scratch.p, t->ctl, s);
+    launch_compact((uint8_t *)t->status.p, n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
     return VC_OK;
 }
 
@@ -141,6 +300,12 @@ void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s)
 void overlap_release(vc_trace *t)
 {
     free_overlap_sets(&t->sets);
+    if (t->mother)
+        (void)hipFree(t->mother);
+    t->mother = nullptr;
+    t->dynamic = false;
+    t->n_items = 0;
+    devbuf_free(t->dyn);
     if (t->own_arrays) {
         if (t->lo) (void)hipFree(t->lo);
         if (t->hi) (void)hipFree(t->hi);

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
                 out[pay[j]] = (uint8_t)(post | (pre << 2) | (flag << 7));
             else if (flag)
                 atomicAdd(&ind_counts[pay[j] & ~INDUCED_BIT], 1ull);
-        } else {
+        } else if (!(pay[j] & INDUCED_BIT)) {
             out[pay[j]] = (uint8_t)pre;
         }
         uint32_t kn = j + 1 < SCAN_ITEMS ? key[j + 1] : knext;

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvcheck.so")
 
 VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE, VC_ESTATE, VC_ETRUNC, VC_EBUDGET, VC_EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
-VC_DEVICE_INPUT, VC_DEVICE_INIT, VC_TRANSLATE_CHECK = 1, 2, 4
+VC_DEVICE_INPUT, VC_DEVICE_INIT, VC_TRANSLATE_CHECK, VC_LIFETIME_EVENTS = 1, 2, 4, 8
+NO_MOTHER = 0xFFFFFFFF
 
 _lib = None
 
@@ -56,6 +57,7 @@ def lib():
             "vc_sync": ([P], i32),
             "vc_trace_load": ([P, P, u64, u32, P, u32, pP], i32),
             "vc_trace_set_arrays": ([P, P, P, u32], i32),
+            "vc_trace_set_dynamic_arrays": ([P, P, P, P, u32], i32),
             "vc_read_overlap_sets": ([P, P, P, u64, pu64], i32),
             "vc_translate": ([P, P, u64, P, u32, P, P, u32, pP], i32),
             "vc_check": ([P], i32),
@@ -170,11 +172,12 @@ class Trace:
         self._keep = list(keep)
 
     @classmethod
-    def load(cls, ctx: Context, events, n_ids: int, init=None) -> "Trace":
+    def load(cls, ctx: Context, events, n_ids: int, init=None, lifetimes: bool = False) -> "Trace":
         p, keep, dev = _buf(events, np.uint32)
         n = int(keep.numel() if dev else keep.size)
         ip, ikeep, idev = _buf(init, np.uint8)
-        flags = (VC_DEVICE_INPUT if dev else 0) | (VC_DEVICE_INIT if idev else 0)
+        flags = (VC_DEVICE_INPUT if dev else 0) | (VC_DEVICE_INIT if idev else 0) | \
+            (VC_LIFETIME_EVENTS if lifetimes else 0)
         h = C.c_void_p()
         _check(lib().vc_trace_load(ctx.h, p, n, n_ids, ip, flags, C.byref(h)))
         return cls(ctx, h, (keep, ikeep) if (dev or idev) else ())
@@ -186,6 +189,15 @@ class Trace:
         _check(lib().vc_trace_set_arrays(self.h, lp, hp, VC_DEVICE_INPUT if ld else 0))
         if ld:
             self._keep += [lk, hk]
+
+    def set_dynamic_arrays(self, lo, hi, mother):
+        """Arrays created (op 6) and destroyed (op 7) during the trace; mother[x] is the
+        vector a partial vector lies in, NO_MOTHER for a vector (host arrays)."""
+        lo = np.ascontiguousarray(lo, dtype=np.uint32)
+        hi = np.ascontiguousarray(hi, dtype=np.uint32)
+        mo = np.ascontiguousarray(mother, dtype=np.uint32)
+        _check(lib().vc_trace_set_dynamic_arrays(self.h, lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p),
+                                                 mo.ctypes.data_as(C.c_void_p), 0))
 
     def check(self):
         _check(lib().vc_check(self.h))
