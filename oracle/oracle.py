@@ -67,6 +67,8 @@ def load(path: str):
     L.oracle_check_overlap.restype = i32
     L.oracle_check_dynamic.argtypes = [P, u64, u32, P, P, P, P, P, P, P, P, P, u64, pu64, pu64, pu64, pu64, pu64]
     L.oracle_check_dynamic.restype = i32
+    L.oracle_check_spaces.argtypes = [P, u64, u32, u32, P, P, P, P, u64, pu64, pu64, pu64]
+    L.oracle_check_spaces.restype = i32
     L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
     L.oracle_overlap_extend.restype = i32
     return L
@@ -220,6 +222,25 @@ def check_dynamic(events: np.ndarray, lo: np.ndarray, hi: np.ndarray, mother: np
     if rc != 0:
         raise OracleError(f"oracle_check_dynamic failed: {rc}")
     return CheckResult(st[:n], fin[:n_arrays], viol[:nv.value].copy(), first.value, ni.value, nis.value)
+
+
+def check_spaces(events: np.ndarray, n_ids: int, k: int, init: np.ndarray | None = None) -> CheckResult:
+    """Check over k memory spaces: status is uint16 per event (post | pre << 4 |
+    stuck << 15), final one k-bit code per id."""
+    ev = np.ascontiguousarray(events, dtype=np.uint32)
+    n = ev.size
+    ini = None if init is None else np.ascontiguousarray(init, dtype=np.uint8)
+    st = np.empty(max(n, 1), dtype=np.uint16)
+    fin = np.empty(max(n_ids, 1), dtype=np.uint8)
+    viol = np.empty(max(n, 1), dtype=np.uint32)
+    nv, first, bad = C.c_uint64(), C.c_uint64(), C.c_uint64()
+    rc = lib().oracle_check_spaces(_p(ev), n, n_ids, k, _p(ini), _p(st), _p(fin), _p(viol), viol.size,
+                                   C.byref(nv), C.byref(first), C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed event at index {bad.value}")
+    if rc != 0:
+        raise OracleError(f"oracle_check_spaces failed: {rc}")
+    return CheckResult(st[:n], fin[:n_ids], viol[:nv.value].copy(), first.value)
 
 
 def overlap_extend(m: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:

@@ -627,3 +627,126 @@ int oracle_check_dynamic(const uint32_t *events, uint64_t n, uint32_t n_arrays, 
     free(sigma); free(live); free(created); free(list); free(where);
     return rc;
 }
+
+/* ------------------------------------------------------------------------------
+ * More than two memory spaces (the extension the paper announces: the model "could
+ * be extended to multiple memory locations", Section 3, and the many-space case of
+ * Section 6, "Conclusion and future works").  Reading taken here: k locations
+ * (2 <= k <= 4, location 0 the CPU), the status of a variable is the k-tuple of the
+ * locations' V/I statuses (bit j of a status code = location j valid), and the five
+ * effects generalise as signatures over k-tuples, written with one quantified
+ * variable per location:
+ *   r_j      : tuple with V at j                 -> unchanged          (read at j)
+ *   w_j      : any tuple                         -> V at j, I elsewhere (write at j)
+ *   copy_a,b : tuple with V at a                 -> same tuple, V at b  (transfer a to b)
+ *   Noop     : any tuple                         -> unchanged
+ * With k = 2, Push = copy_0,1 and Pull = copy_1,0 (the local transfers), and the
+ * remote effects are the same signatures on the other location, so the two-space
+ * calculus is the case k = 2.  A step that does not unify is flagged and skipped,
+ * as in the plain method.
+ * Event word: bits 0-23 variable, bits 24-25 op (0 r, 1 w, 2 copy, 3 Noop), bits
+ * 26-27 location a (r/w: the location; copy: the source), bits 28-29 location b (the
+ * copy's target; 0 for the other ops), bits 30-31 zero; locations below k.
+ * Status (uint16 per event): post | pre << 4 | stuck << 15; final: one code per id.
+ * ------------------------------------------------------------------------------ */
+#define KMAX 4
+enum { KT_I = 0, KT_V = 1, KT_X0 = 2 }; /* KT_X0 + j: the quantified variable of location j */
+
+struct ksig { int in[KMAX], out[KMAX]; };
+
+/* the signature of (op, a, b) over k locations */
+static struct ksig k_signature(int op, int a, int b, int k)
+{
+    struct ksig s;
+    for (int j = 0; j < k; j++) {
+        s.in[j] = KT_X0 + j;
+        s.out[j] = KT_X0 + j;
+    }
+    if (op == 0) {            /* r_a */
+        s.in[a] = KT_V;
+        s.out[a] = KT_V;
+    } else if (op == 1) {     /* w_a */
+        for (int j = 0; j < k; j++)
+            s.out[j] = j == a ? KT_V : KT_I;
+    } else if (op == 2) {     /* copy a -> b */
+        s.in[a] = KT_V;
+        s.out[a] = KT_V;
+        s.out[b] = KT_V;
+    }
+    return s;
+}
+
+/* unify the status tuple with the input pattern and instantiate the output pattern;
+ * returns 0 (and leaves *post alone) when no unification exists */
+static int k_apply(const struct ksig *s, int k, int pre, int *post)
+{
+    int bind[KT_X0 + KMAX];
+    for (int j = 0; j < KT_X0 + KMAX; j++)
+        bind[j] = -1;
+    for (int j = 0; j < k; j++) {
+        int val = (pre >> j) & 1 ? KT_V : KT_I, p = s->in[j];
+        if (p == KT_V || p == KT_I) {
+            if (val != p)
+                return 0;
+        } else if (bind[p] < 0) {
+            bind[p] = val;
+        } else if (bind[p] != val) {
+            return 0;
+        }
+    }
+    int r = 0;
+    for (int j = 0; j < k; j++) {
+        int p = s->out[j];
+        int val = (p == KT_V || p == KT_I) ? p : bind[p];
+        r |= (val == KT_V) << j;
+    }
+    *post = r;
+    return 1;
+}
+
+int oracle_check_spaces(const uint32_t *events, uint64_t n, uint32_t n_ids, uint32_t k, const uint8_t *init,
+                        uint16_t *status_out, uint8_t *final_out, uint32_t *viol_out, uint64_t viol_cap,
+                        uint64_t *n_viol, uint64_t *first_viol, uint64_t *bad)
+{
+    if (k < 2 || k > KMAX)
+        return -3;
+    uint8_t *sigma = (uint8_t *)malloc(n_ids ? n_ids : 1);
+    if (!sigma)
+        return -2;
+    for (uint32_t v = 0; v < n_ids; v++)
+        sigma[v] = init ? init[v] : 1; /* data starts on the CPU only */
+    uint64_t nv = 0, first = n;
+    int rc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t e = events[i];
+        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 3u, a = (e >> 26) & 3u, b = (e >> 28) & 3u;
+        if ((e >> 30) != 0 || x >= n_ids || a >= k || b >= k || (op != 2 && b != 0) || (op == 3 && a != 0)) {
+            if (bad) *bad = i;
+            free(sigma);
+            return -1;
+        }
+        struct ksig s = k_signature((int)op, (int)a, (int)b, (int)k);
+        int pre = sigma[x], post = pre;
+        int stuck = !k_apply(&s, (int)k, pre, &post);
+        if (stuck)
+            post = pre;
+        sigma[x] = (uint8_t)post;
+        if (status_out)
+            status_out[i] = (uint16_t)(post | (pre << 4) | (stuck << 15));
+        if (stuck) {
+            if (viol_out && nv < viol_cap)
+                viol_out[nv] = (uint32_t)i;
+            else if (viol_out)
+                rc = -5;
+            if (first == n)
+                first = i;
+            nv++;
+        }
+    }
+    if (final_out)
+        memcpy(final_out, sigma, n_ids);
+    if (n_viol) *n_viol = nv;
+    if (first_viol) *first_viol = first;
+    free(sigma);
+    return rc;
+}

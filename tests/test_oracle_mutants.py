@@ -9,6 +9,7 @@ import pytest
 from oracle import oracle as O
 from tests import test_oracle_dynamic as D
 from tests import test_oracle_pins as T
+from tests import test_oracle_spaces as K
 from tests.helpers import load_yaml
 
 MUTANTS = {
@@ -41,6 +42,10 @@ MUTANTS = {
                                         "created[x] = 1;"),
     "dynamic-induced-ignores-liveness": ("for (uint32_t k = 0; k < n_live; k++) {\n                uint32_t y = list[k];",
                                          "for (uint32_t k = 0; k < n_arrays; k++) {\n                uint32_t y = k;"),
+    "spaces-copy-misses-target": ("        s.out[b] = KT_V;\n", ""),
+    "spaces-write-keeps-others": ("s.out[j] = j == a ? KT_V : KT_I;", "s.out[j] = j == a ? KT_V : KT_X0 + j;"),
+    "spaces-read-at-location-0": ("        s.in[a] = KT_V;\n        s.out[a] = KT_V;\n    } else if (op == 1)",
+                                  "        s.in[0] = KT_V;\n        s.out[0] = KT_V;\n    } else if (op == 1)"),
     "overlap-inclusive-upper": ("return x != y && lo[x] < hi[y] && lo[y] < hi[x];",
                                 "return x != y && lo[x] <= hi[y] && lo[y] <= hi[x];"),
 }
@@ -65,6 +70,8 @@ def _pins():
     D.test_dynamic_without_lifecycle_is_the_static_overlap_check()
     D.test_dynamic_statuses_abstract_the_elements()
     D.test_dynamic_scenario_statuses_abstract_the_elements()
+    K.test_two_spaces_is_the_paper_calculus()
+    K.test_every_program_up_to_length_3_at_k3()
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
