@@ -272,6 +272,39 @@ def wl_dynamic(args, V, ctx, stream):
                 multi_pass=("sort_pass", "hist"))
 
 
+def wl_spaces(args, V, ctx, stream):
+    """Four memory spaces: 2^26 events over 2^20 variables, op uniform over {r, w, copy,
+    Noop}, locations uniform."""
+    import torch
+    from paper_1910_11110_amd import gen
+    n, n_ids, k = 1 << 26, 1 << 20, 4
+    log(f"[bench] spaces: generating {n} events over {n_ids} ids, k = {k}")
+    e = gen.space_events(n, n_ids, k, args.seed)
+    te = torch.from_numpy(e.view(np.int32)).cuda()
+    torch.cuda.synchronize()
+    t = V.Trace.load_spaces(ctx, te, n_ids, k)
+    t.check()
+    ctx.sync()
+    viol = t.violations().total
+
+    def step():
+        t.check()
+
+    def bytes_alg():
+        # events in (4 B), uint16 statuses out, violation indices, final codes
+        return 4 * n + 2 * n + 4 * viol + n_ids
+
+    def cpu_sample():
+        from oracle import oracle as O
+        m = 1 << 25
+        return (_median_rate(m, lambda: O.check_spaces(e[:m], n_ids, k)),
+                f"oracle check of the first {m} events, median of 3 runs", None)
+
+    cfg = {"workload": f"spaces-k{k}-2^26x2^20", "n_events": n, "n_ids": n_ids, "k": k, "violations": int(viol)}
+    return dict(step=step, units=n, unit="event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg, keep=(t, te),
+                multi_pass=("sort_pass", "hist"))
+
+
 def _oracle_job(inp, sets):
     from oracle import oracle as O
     ev, nv, lo, hi = inp
@@ -507,7 +540,7 @@ def copy_probe(torch, n_words=1 << 28):
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
              "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
              "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap,
-             "batched": wl_batched, "dynamic": wl_dynamic}
+             "batched": wl_batched, "dynamic": wl_dynamic, "spaces": wl_spaces}
 
 
 def measure(name, args, V, ctx, stream, steps, warmup, cpu=True):
@@ -591,7 +624,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="components", choices=sorted(WORKLOADS) + ["served"])
-    ap.add_argument("--also", default="plain-large,overlap,dynamic,batched,served",
+    ap.add_argument("--also", default="plain-large,overlap,dynamic,spaces,batched,served",
                     help="workloads reported beside the headline one (comma separated; empty for none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--comp-log2", type=int, default=23)

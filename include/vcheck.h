@@ -98,6 +98,24 @@ int vc_sync(vc_ctx *ctx);
 int vc_trace_load(vc_ctx *ctx, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
                   uint32_t flags, vc_trace **out);
 
+/* More than two memory spaces: the extension to more memory locations the paper
+ * announces (Section 3: the results "could be extended to multiple memory locations";
+ * Section 6, future work).  k locations, 2 <= k <= 4, location 0 the CPU; a status
+ * code is the set of valid locations (bit j = location j valid; every variable starts
+ * valid at location 0 only, code 1, unless init says otherwise: codes < 2^k).
+ * Event word: bits 0-23 variable, bits 24-25 op (0 r: read at location a, 1 w: write
+ * at a, which leaves only a valid, 2 copy: transfer from a to b, 3 Noop), bits 26-27
+ * location a, bits 28-29 location b (copies only; 0 otherwise; a = 0 for Noop), bits
+ * 30-31 zero.  A read at a or a copy from a with location a invalid is stuck (flagged,
+ * status unchanged).  With k = 2, Push is a copy from 0 to 1 and Pull a copy from 1 to 0
+ * (their remote forms the other way), which is the plain method.
+ * The trace is then checked by vc_check; its statuses are read with
+ * vc_read_event_status16 (post | pre << 4 | stuck << 15); violations and the final
+ * codes as for any trace.  Other arguments as vc_trace_load. */
+int vc_trace_load_spaces(vc_ctx *ctx, const uint32_t *events, uint64_t n, uint32_t n_ids, uint32_t k,
+                         const uint8_t *init, uint32_t flags, vc_trace **out);
+int vc_read_event_status16(vc_trace *t, uint16_t *out, uint64_t cap);
+
 /* Arrays as half-open intervals [lo[i], hi[i]) with lo < hi, one per id (Section 4:
  * one status per array; arrays x != y overlap iff lo_x < hi_y and lo_y < hi_x).
  * Once set, vc_check applies the overlapping-array rule to core events: a write

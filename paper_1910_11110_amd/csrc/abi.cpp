@@ -304,7 +304,7 @@ static int validate_events_host(const uint32_t *ev, uint64_t n, uint32_t n_ids, 
     return VC_OK;
 }
 
-int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags)
+int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags, uint32_t max_code)
 {
     if (!init) {
         t->init = nullptr;
@@ -316,7 +316,7 @@ int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags)
         return VC_OK;
     }
     for (uint32_t i = 0; i < t->n_ids; i++)
-        if (init[i] > 3)
+        if (init[i] > max_code)
             return vc_fail(VC_EINVAL, "init status %u at id %u is not a status code", init[i], i);
     hipError_t e;
     if ((e = hipMalloc(&t->init, t->n_ids ? t->n_ids : 1)) != hipSuccess)
@@ -327,8 +327,37 @@ int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags)
     return VC_OK;
 }
 
+static int validate_space_events_host(const uint32_t *ev, uint64_t n, uint32_t n_ids, uint32_t k)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        const uint32_t w = ev[i], op = (w >> 24) & 3u, a = (w >> 26) & 3u, b = (w >> 28) & 3u;
+        if ((w >> 30) != 0 || (w & 0xFFFFFFu) >= n_ids || a >= k || b >= k || (op != 2 && b != 0) ||
+            (op == 3 && a != 0))
+            return vc_fail(VC_EINVAL, "malformed k-space event word 0x%08x at index %llu (n_ids %u, k %u)", w,
+                           (unsigned long long)i, n_ids, k);
+    }
+    return VC_OK;
+}
+
+static int trace_load_impl(vc_ctx *c, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
+                           uint32_t flags, uint32_t spaces, vc_trace **out);
+
+extern "C" int vc_trace_load_spaces(vc_ctx *c, const uint32_t *events, uint64_t n, uint32_t n_ids, uint32_t k,
+                                    const uint8_t *init, uint32_t flags, vc_trace **out)
+{
+    if (k < 2 || k > 4)
+        return vc_fail(VC_EINVAL, "vc_trace_load_spaces: k %u must be in [2, 4]", k);
+    return trace_load_impl(c, events, n, n_ids, init, flags, k, out);
+}
+
 extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
                              uint32_t flags, vc_trace **out)
+{
+    return trace_load_impl(c, events, n, n_ids, init, flags, 0, out);
+}
+
+static int trace_load_impl(vc_ctx *c, const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init,
+                           uint32_t flags, uint32_t spaces, vc_trace **out)
 {
     if (!c || !out)
         return vc_fail(VC_EINVAL, "vc_trace_load: NULL argument");
@@ -342,7 +371,8 @@ extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint
         return vc_fail(VC_EINVAL, "vc_trace_load: events but n_ids is 0");
     (void)hipSetDevice(c->device);
     if (!(flags & VC_DEVICE_INPUT)) {
-        int r = validate_events_host(events, n, n_ids, (flags & VC_LIFETIME_EVENTS) != 0);
+        int r = spaces ? validate_space_events_host(events, n, n_ids, spaces)
+                       : validate_events_host(events, n, n_ids, (flags & VC_LIFETIME_EVENTS) != 0);
         if (r != VC_OK)
             return r;
     }
@@ -351,9 +381,10 @@ extern "C" int vc_trace_load(vc_ctx *c, const uint32_t *events, uint64_t n, uint
     c->traces.push_back(t);
     t->n = n;
     t->n_ids = n_ids;
+    t->spaces = spaces;
     int r = trace_alloc_common(c, t);
     if (r == VC_OK)
-        r = trace_set_init(t, init, flags);
+        r = trace_set_init(t, init, flags, spaces ? (1u << spaces) - 1u : 3u);
     if (r == VC_OK) {
         if (flags & VC_DEVICE_INPUT) {
             t->events = const_cast<uint32_t *>(events);
@@ -449,9 +480,40 @@ static bool use_bucket_path(const vc_trace *t)
     return !t->has_arrays && t->n_ids <= bucket_max_ids() && t->n <= 0xFFFFFFFFull && !getenv("VC_GENERAL_PATH");
 }
 
+// check over k memory spaces: items, sort by variable, segmented scan, violations
+static int spaces_enqueue(vc_trace *t, hipStream_t s)
+{
+    const uint64_t n = t->n;
+    int r;
+    if ((r = devbuf_reserve(t->status, n ? n : 1)) != VC_OK ||
+        (r = devbuf_reserve(t->status16, (n ? n : 1) * 2)) != VC_OK ||
+        (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
+        (r = devbuf_reserve(t->viol, (n ? n : 1) * 4)) != VC_OK ||
+        (r = devbuf_reserve(t->items_a, (n ? n : 1) * 8)) != VC_OK ||
+        (r = devbuf_reserve(t->items_b, (n ? n : 1) * 8)) != VC_OK ||
+        (r = devbuf_reserve(t->scratch, std::max({sort_scratch_bytes(n), spaces_scan_scratch_bytes(n),
+                                                  compact_scratch_bytes(n)}))) != VC_OK)
+        return r;
+    uint8_t *fin = (uint8_t *)t->fin.p;
+    if (t->init)
+        (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
+    else
+        launch_fill_u8(fin, 1, t->n_ids, s);
+    launch_reset_control(t->ctl, s);
+    launch_items_k(t->events, n, t->n_ids, t->spaces, (uint64_t *)t->items_a.p, t->ctl, s);
+    uint64_t *sorted = sort_items((uint64_t *)t->items_a.p, (uint64_t *)t->items_b.p, n, (int)key_bits_for(t->n_ids),
+                                  t->scratch.p, t->ctl, s);
+    launch_segscan_k(sorted, n, t->init, t->n_ids, (uint16_t *)t->status16.p, (uint8_t *)t->status.p, fin,
+                     t->scratch.p, t->ctl, s);
+    launch_compact((uint8_t *)t->status.p, n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
+    return VC_OK;
+}
+
 int enqueue_check(vc_trace *t, hipStream_t s)
 {
     int r;
+    if (t->spaces)
+        return spaces_enqueue(t, s);
     if (use_small_path(t)) {
         if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK ||
             (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
@@ -570,11 +632,30 @@ extern "C" int vc_read_events(vc_trace *t, uint32_t *out, uint64_t cap, uint64_t
                       : VC_OK;
 }
 
+extern "C" int vc_read_event_status16(vc_trace *t, uint16_t *out, uint64_t cap)
+{
+    int r = require_checked(t, "vc_read_event_status16");
+    if (r != VC_OK)
+        return r;
+    if (!t->spaces)
+        return vc_fail(VC_ESTATE, "vc_read_event_status16: not a k-space trace (use vc_read_event_status)");
+    uint64_t k = std::min(cap, t->n);
+    if (k && out) {
+        hipError_t e = hipMemcpy(out, t->status16.p, k * 2, hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            return vc_hip_fail(e, "hipMemcpy(status16)");
+    }
+    return cap < t->n ? vc_fail(VC_ETRUNC, "vc_read_event_status16: capacity too small") : VC_OK;
+}
+
 extern "C" int vc_read_event_status(vc_trace *t, uint8_t *out, uint64_t cap)
 {
     int r = require_checked(t, "vc_read_event_status");
     if (r != VC_OK)
         return r;
+    if (t->spaces)
+        return vc_fail(VC_ESTATE, "vc_read_event_status: a k-space trace has uint16 statuses "
+                                  "(vc_read_event_status16)");
     uint64_t k = std::min(cap, t->n);
     if (k && out) {
         hipError_t e = hipMemcpy(out, t->status.p, k, hipMemcpyDeviceToHost);
@@ -664,6 +745,7 @@ extern "C" int vc_trace_free(vc_trace *t)
     overlap_release(t);
     translate_release(t);
     devbuf_free(t->status);
+    devbuf_free(t->status16);
     devbuf_free(t->fin);
     devbuf_free(t->viol);
     devbuf_free(t->items_a);

@@ -95,6 +95,10 @@ struct vc_trace {
     uint64_t n_items = 0; // combined items (events, probes, induced) of the last sizing
     DevBuf dyn;
 
+    // k memory spaces (0: the two-space encoding); their uint16 statuses
+    uint32_t spaces = 0;
+    DevBuf status16;
+
     // outputs
     DevBuf status, fin, viol;
     // scratch
@@ -116,7 +120,7 @@ void devbuf_free(DevBuf &b);
 uint32_t key_bits_for(uint32_t n_ids);
 int trace_collect(vc_trace *t);
 int trace_reserve(vc_trace *t, uint64_t m);
-int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags);
+int trace_set_init(vc_trace *t, const uint8_t *init, uint32_t flags, uint32_t max_code = 3);
 void enqueue_check_items(vc_trace *t, uint64_t m, hipStream_t s);
 int enqueue_check(vc_trace *t, hipStream_t s);
 

@@ -186,6 +186,17 @@ void launch_dyn_emit(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint3
 void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint8_t *probe_pre, uint64_t n,
                         const uint8_t *init, uint32_t n_ids, uint8_t *init2, uint8_t *fin, hipStream_t s);
 
+// ------------------------------- k memory spaces -----------------------------------
+// items of a k-space trace (key word = op byte << 24 | variable; malformed words are
+// reported and become Noop on variable 0)
+void launch_items_k(const uint32_t *ev, uint64_t n, uint32_t n_ids, uint32_t k, uint64_t *items, Control *ctl,
+                    hipStream_t s);
+size_t spaces_scan_scratch_bytes(uint64_t n);
+// sorted k-space items -> st16[i] = post | pre << 4 | stuck << 15, flag[i] = stuck << 7,
+// final[var] = last post (fin must hold the initial statuses of untouched variables)
+void launch_segscan_k(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, uint16_t *st16,
+                      uint8_t *flag, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s);
+
 // ------------------------------- overlap ------------------------------------------
 struct OverlapSets {
     uint64_t *off = nullptr; // n_arrays + 1

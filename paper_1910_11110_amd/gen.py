@@ -38,6 +38,7 @@ S_LEN, S_LO, S_ARR = 20, 21, 22
 S_TLEN, S_TVARS, S_TARR, S_TSEED = 30, 31, 32, 33
 S_ARRIVE = 40
 S_DMOTHER, S_DLEN, S_DLO, S_DLIFE, S_DCPOS, S_DDPOS, S_DVAR = 50, 51, 52, 53, 54, 55, 56
+S_KVAR, S_KOP, S_KA, S_KB = 60, 61, 62, 63
 
 OP_R, OP_W, OP_PUSH, OP_PULL, OP_NOOP = 0, 1, 2, 3, 4
 MODE_R, MODE_W, MODE_RW = 0, 1, 2
@@ -270,6 +271,21 @@ def intervals(n_arrays: int, seed: int, space: int = 1 << 24, max_len: int = 409
     with np.errstate(over="ignore"):
         lo[:] = ((hi32 * bound) >> np.uint64(32)).astype(np.int64)
     return lo.astype(np.uint32), (lo + ln).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------------------
+# k memory spaces
+# --------------------------------------------------------------------------------------
+def space_events(n: int, n_ids: int, k: int, seed: int) -> np.ndarray:
+    """k-space event words: variable uniform in [0, n_ids), op uniform over {r, w, copy,
+    Noop}, location a uniform in [0, k) (0 for Noop), copy target b uniform in [0, k)."""
+    x = below(draws(seed, S_KVAR, 0, n), n_ids).astype(np.uint32)
+    op = below(draws(seed, S_KOP, 0, n), 4).astype(np.uint32)
+    a = below(draws(seed, S_KA, 0, n), k).astype(np.uint32)
+    b = below(draws(seed, S_KB, 0, n), k).astype(np.uint32)
+    a = np.where(op == 3, np.uint32(0), a)
+    b = np.where(op == 2, b, np.uint32(0))
+    return x | (op << np.uint32(24)) | (a << np.uint32(26)) | (b << np.uint32(28))
 
 
 # --------------------------------------------------------------------------------------

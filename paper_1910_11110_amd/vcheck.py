@@ -58,6 +58,8 @@ def lib():
             "vc_trace_load": ([P, P, u64, u32, P, u32, pP], i32),
             "vc_trace_set_arrays": ([P, P, P, u32], i32),
             "vc_trace_set_dynamic_arrays": ([P, P, P, P, u32], i32),
+            "vc_trace_load_spaces": ([P, P, u64, u32, u32, P, u32, pP], i32),
+            "vc_read_event_status16": ([P, P, u64], i32),
             "vc_read_overlap_sets": ([P, P, P, u64, pu64], i32),
             "vc_translate": ([P, P, u64, P, u32, P, P, u32, pP], i32),
             "vc_check": ([P], i32),
@@ -181,6 +183,23 @@ class Trace:
         h = C.c_void_p()
         _check(lib().vc_trace_load(ctx.h, p, n, n_ids, ip, flags, C.byref(h)))
         return cls(ctx, h, (keep, ikeep) if (dev or idev) else ())
+
+    @classmethod
+    def load_spaces(cls, ctx: Context, events, n_ids: int, k: int, init=None) -> "Trace":
+        """A trace over k memory spaces (k-space event words)."""
+        p, keep, dev = _buf(events, np.uint32)
+        n = int(keep.numel() if dev else keep.size)
+        ip, ikeep, idev = _buf(init, np.uint8)
+        flags = (VC_DEVICE_INPUT if dev else 0) | (VC_DEVICE_INIT if idev else 0)
+        h = C.c_void_p()
+        _check(lib().vc_trace_load_spaces(ctx.h, p, n, n_ids, k, ip, flags, C.byref(h)))
+        return cls(ctx, h, (keep, ikeep) if (dev or idev) else ())
+
+    def status16(self) -> np.ndarray:
+        n, _ = self.info()
+        out = np.empty(max(n, 1), np.uint16)
+        _check(lib().vc_read_event_status16(self.h, out.ctypes.data_as(C.c_void_p), n))
+        return out[:n]
 
     def set_arrays(self, lo, hi):
         lp, lk, ld = _buf(lo, np.uint32)
