@@ -69,6 +69,8 @@ def load(path: str):
     L.oracle_check_dynamic.restype = i32
     L.oracle_check_spaces.argtypes = [P, u64, u32, u32, P, P, P, P, u64, pu64, pu64, pu64]
     L.oracle_check_spaces.restype = i32
+    L.oracle_check_declared.argtypes = [P, u64, P, u32, P, P, P, P, P, i32, P, pu64]
+    L.oracle_check_declared.restype = i32
     L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
     L.oracle_overlap_extend.restype = i32
     return L
@@ -241,6 +243,33 @@ def check_spaces(events: np.ndarray, n_ids: int, k: int, init: np.ndarray | None
     if rc != 0:
         raise OracleError(f"oracle_check_spaces failed: {rc}")
     return CheckResult(st[:n], fin[:n_ids], viol[:nv.value].copy(), first.value)
+
+
+WD_TRANSFER, WD_READ, WD_WRITE, WD_UNWRITTEN, WD_OVERLAP, WD_ILL = 1, 2, 4, 8, 16, 128
+
+
+def check_declared(comp_off, decls, n_vars: int, body_off, body, idx=None, lo=None, hi=None,
+                   extend: bool = False) -> np.ndarray:
+    """Verdict byte per component of the well-declaredness conditions (bits WD_*)."""
+    co = np.ascontiguousarray(comp_off, dtype=np.uint64)
+    de = np.ascontiguousarray(decls, dtype=np.uint32)
+    bo = np.ascontiguousarray(body_off, dtype=np.uint64)
+    bd = np.ascontiguousarray(body, dtype=np.uint32)
+    ix = None if idx is None else np.ascontiguousarray(idx, dtype=np.uint32)
+    l = None if lo is None else np.ascontiguousarray(lo, dtype=np.uint32)
+    h = None if hi is None else np.ascontiguousarray(hi, dtype=np.uint32)
+    n_comp = co.size - 1
+    out = np.empty(max(n_comp, 1), np.uint8)
+    bad = C.c_uint64()
+    rc = lib().oracle_check_declared(_p(co), n_comp, _p(de), n_vars, _p(bo), _p(bd), _p(ix), _p(l), _p(h),
+                                     1 if extend else 0, _p(out), C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed declaration at index {bad.value}")
+    if rc == -4:
+        raise OracleError(f"malformed body word at index {bad.value}")
+    if rc != 0:
+        raise OracleError(f"oracle_check_declared failed: {rc}")
+    return out[:n_comp]
 
 
 def overlap_extend(m: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:

@@ -750,3 +750,125 @@ int oracle_check_spaces(const uint32_t *events, uint64_t n, uint32_t n_ids, uint
     free(sigma);
     return rc;
 }
+
+/* ------------------------------------------------------------------------------
+ * Well-declared programs (Definition "Well-declared program", Section 3.4; with
+ * arrays, Definition "Well-declared program with array access", Section 3.5; with
+ * overlapping arrays, the naive rule of Section 4.1).  A program is a list of
+ * components, each with its declarations M (decl words) and its body S (event words,
+ * and for arrays an element index per body event).  For every component the checker
+ * reports which conditions fail, as bits of a verdict byte:
+ *   bit 0  a Push or Pull in S
+ *   bit 1  a read r_s x (x[i]) in S without R or RW on x on side s in M
+ *   bit 2  a write w_s x (x[i]) in S without W or RW on x on side s in M
+ *   bit 3  W on x on side s in M, and some element of x (a scalar: x itself) is not
+ *          written on side s in S (bodies are straight-line, so "occurs in all
+ *          execution paths" is "occurs")
+ *   bit 4  (arrays) a write w_s x[i] in S whose address lo_x + i lies in an array y !=
+ *          x that is not declared W or RW on side s in M (the naive rule)
+ *   bit 7  set when any of bits 0-4 is
+ * With extend, M is first replaced by O(M), its extension for overlapping arrays
+ * (Table "Extension of access mode annotations to deal with overlapping arrays").
+ * Scalars: lo/hi/idx are NULL and every variable has one element.
+ * Returns -1 (*bad = index) for a malformed declaration (a variable repeated in a
+ * component: the declarations are a conjunction over distinct variables, Section 3.3),
+ * -4 (*bad = index) for a malformed body word or element index.
+ * ------------------------------------------------------------------------------ */
+static int find_var_side(const uint32_t *set, int n, uint32_t x, uint32_t side)
+{
+    for (int i = 0; i < n; i++)
+        if ((set[i] & 0xFFFFFFu) == x && ((set[i] >> 27) & 1u) == side)
+            return i;
+    return -1;
+}
+
+int oracle_check_declared(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
+                          const uint64_t *body_off, const uint32_t *body, const uint32_t *idx, const uint32_t *lo,
+                          const uint32_t *hi, int extend, uint8_t *verdict, uint64_t *bad)
+{
+    int cap = 64 + 2 * (int)n_vars;
+    uint32_t *m = (uint32_t *)malloc((size_t)cap * sizeof(uint32_t));
+    if (!m)
+        return -2;
+    for (uint64_t c = 0; c < n_comp; c++) {
+        uint64_t a = comp_off[c], b = comp_off[c + 1];
+        /* declarations, checked as in the translation */
+        for (uint64_t d = a; d < b; d++) {
+            uint32_t w = decls[d], v = w & 0xFFFFFFu;
+            int dup = 0;
+            for (uint64_t e = a; e < d; e++)
+                if ((decls[e] & 0xFFFFFFu) == v)
+                    dup = 1;
+            if ((w >> 28) != 0 || ((w >> 26) & 1u) || ((w >> 24) & 3u) == 3 || v >= n_vars || dup) {
+                if (bad) *bad = d;
+                free(m);
+                return -1;
+            }
+        }
+        int nm = (int)(b - a);
+        if (extend && lo) {
+            nm = oracle_overlap_extend(decls + a, (int)(b - a), lo, hi, n_vars, m, cap);
+            if (nm < 0) {
+                free(m);
+                return -2;
+            }
+        } else {
+            for (int i = 0; i < nm; i++)
+                m[i] = decls[a + i];
+        }
+        uint8_t v8 = 0;
+        for (uint64_t j = body_off[c]; j < body_off[c + 1]; j++) {
+            uint32_t e = body[j], x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+            uint32_t i = idx ? idx[j] : 0, len = lo ? hi[x] - lo[x] : 1;
+            if ((e >> 28) != 0 || op > 4 || x >= n_vars || (lo && !(i < hi[x] - lo[x])) || (!lo && idx && i != 0)) {
+                if (bad) *bad = j;
+                free(m);
+                return -4;
+            }
+            (void)len;
+            int k = find_var_side(m, nm, x, side);
+            int mode = k >= 0 ? (int)((m[k] >> 24) & 3u) : -1;
+            if (op == OP_PUSH || op == OP_PULL)
+                v8 |= 1;
+            if (op == OP_R && !(mode == 0 || mode == 2))
+                v8 |= 2;
+            if (op == OP_W && !(mode == 1 || mode == 2))
+                v8 |= 4;
+            if (op == OP_W && lo) {
+                uint32_t addr = lo[x] + i;
+                for (uint32_t y = 0; y < n_vars; y++) {
+                    if (y == x || !(lo[y] <= addr && addr < hi[y]))
+                        continue;
+                    int ky = find_var_side(m, nm, y, side);
+                    int my = ky >= 0 ? (int)((m[ky] >> 24) & 3u) : -1;
+                    if (!(my == 1 || my == 2))
+                        v8 |= 16;
+                }
+            }
+        }
+        /* W obligations: every element of x written on the declaration's side */
+        for (int k = 0; k < nm; k++) {
+            uint32_t x = m[k] & 0xFFFFFFu, side = (m[k] >> 27) & 1u;
+            if (((m[k] >> 24) & 3u) != 1)
+                continue;
+            uint32_t len = lo ? hi[x] - lo[x] : 1;
+            uint8_t *seen = (uint8_t *)calloc(len ? len : 1, 1);
+            if (!seen) {
+                free(m);
+                return -2;
+            }
+            for (uint64_t j = body_off[c]; j < body_off[c + 1]; j++) {
+                uint32_t e = body[j];
+                if ((e & 0xFFFFFFu) == x && ((e >> 24) & 7u) == OP_W && ((e >> 27) & 1u) == side)
+                    seen[idx ? idx[j] : 0] = 1;
+            }
+            for (uint32_t q = 0; q < len; q++)
+                if (!seen[q])
+                    v8 |= 8;
+            free(seen);
+        }
+        verdict[c] = (uint8_t)(v8 | (v8 ? 0x80 : 0));
+    }
+    free(m);
+    return 0;
+}

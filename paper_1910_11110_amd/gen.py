@@ -39,6 +39,7 @@ S_TLEN, S_TVARS, S_TARR, S_TSEED = 30, 31, 32, 33
 S_ARRIVE = 40
 S_DMOTHER, S_DLEN, S_DLO, S_DLIFE, S_DCPOS, S_DDPOS, S_DVAR = 50, 51, 52, 53, 54, 55, 56
 S_KVAR, S_KOP, S_KA, S_KB = 60, 61, 62, 63
+S_WK, S_WVAR, S_WMODE, S_WSIDE, S_WEL, S_WERR, S_WERRK = 70, 71, 72, 73, 74, 75, 76
 
 OP_R, OP_W, OP_PUSH, OP_PULL, OP_NOOP = 0, 1, 2, 3, 4
 MODE_R, MODE_W, MODE_RW = 0, 1, 2
@@ -271,6 +272,95 @@ def intervals(n_arrays: int, seed: int, space: int = 1 << 24, max_len: int = 409
     with np.errstate(over="ignore"):
         lo[:] = ((hi32 * bound) >> np.uint64(32)).astype(np.int64)
     return lo.astype(np.uint32), (lo + ln).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------------------
+# component programs with explicit bodies (for the well-declaredness check)
+# --------------------------------------------------------------------------------------
+@dataclass
+class DeclaredProgram:
+    comp_off: np.ndarray
+    decls: np.ndarray
+    n_vars: int
+    body_off: np.ndarray
+    body: np.ndarray
+    idx: np.ndarray | None   # element index per body event (arrays), else None
+    lo: np.ndarray | None
+    hi: np.ndarray | None
+
+
+def declared_program(n_comp: int, n_vars: int, seed: int, arrays: bool = True, space: int = 1 << 24,
+                     max_len: int = 64, kmax: int = 4, p_err: float = 0.05) -> DeclaredProgram:
+    """Components declaring k ~ U{1..kmax} distinct variables (uniform ids, redrawn until
+    distinct), modes R/W/RW with p 0.5/0.3/0.2, one side per component (p = 0.5).  The body
+    visits every element of every declared variable in declaration order: R reads it with
+    p = 0.5, W writes it, RW reads it with p = 0.5 and writes it with p = 0.5 (a read before
+    the write).  With arrays, variables are intervals (lengths log-uniform in [1, max_len])
+    and body events carry element indices; without, every variable has one element.  A
+    fraction p_err of components has its first body event altered: its side flipped, or
+    (one in three) turned into a Push."""
+    k = below(draws(seed, S_WK, 0, n_comp), kmax) + 1
+    cols = below(draws(seed, S_WVAR, 0, n_comp * kmax), n_vars).reshape(n_comp, kmax).T.copy()
+    attempt = 1
+    for j in range(1, kmax):
+        rows = np.nonzero(k > j)[0]
+        while rows.size:
+            cj = cols[j, rows]
+            dup = np.zeros(rows.size, dtype=bool)
+            for i in range(j):
+                dup |= cj == cols[i, rows]
+            rows = rows[dup]
+            if rows.size == 0:
+                break
+            cols[j, rows] = below(draws_at(seed, S_WVAR + 1000 * attempt,
+                                           rows.astype(np.uint64) * np.uint64(kmax) + np.uint64(j)), n_vars)
+            attempt += 1
+    mask = np.arange(kmax)[None, :] < k[:, None]
+    var = cols.T[mask].astype(np.int64)
+    n_decl = var.size
+    mu = unit(draws(seed, S_WMODE, 0, n_decl))
+    mode = np.where(mu < 0.5, MODE_R, np.where(mu < 0.8, MODE_W, MODE_RW))
+    cside = (draws(seed, S_WSIDE, 0, n_comp) >> np.uint64(63)).astype(np.int64)
+    side = np.repeat(cside, k)
+    comp_off = np.zeros(n_comp + 1, dtype=np.uint64)
+    np.cumsum(k, out=comp_off[1:])
+    if arrays:
+        lo, hi = intervals(n_vars, seed, space, max_len)
+        ln = (hi.astype(np.int64) - lo.astype(np.int64))[var]
+    else:
+        lo = hi = None
+        ln = np.ones(n_decl, np.int64)
+    # one entry per (declaration, element), in declaration order
+    de = np.repeat(np.arange(n_decl), ln)
+    start = np.cumsum(ln) - ln
+    el = np.arange(de.size) - np.repeat(start, ln)
+    u = unit(draws(seed, S_WEL, 0, 2 * de.size)).reshape(2, de.size)
+    m = mode[de]
+    rd = ((m == MODE_R) & (u[0] < 0.5)) | ((m == MODE_RW) & (u[0] < 0.5))
+    wr = (m == MODE_W) | ((m == MODE_RW) & (u[1] < 0.5))
+    # each entry gives a read then a write
+    cnt = rd.astype(np.int64) + wr.astype(np.int64)
+    ent = np.repeat(np.arange(de.size), cnt)
+    first_of = np.cumsum(cnt) - cnt
+    is_second = (np.arange(ent.size) - first_of[ent]) == 1
+    op = np.where(rd[ent] & ~is_second, OP_R, OP_W)
+    bd = de[ent]
+    body = pack_events(var[bd], op, side[bd])
+    idx = el[ent].astype(np.uint32)
+    comp_of_decl = np.repeat(np.arange(n_comp), k)
+    body_cnt = np.bincount(comp_of_decl[bd], minlength=n_comp)
+    body_off = np.zeros(n_comp + 1, dtype=np.uint64)
+    np.cumsum(body_cnt, out=body_off[1:])
+    # faults: the first body event of a few components
+    ue = unit(draws(seed, S_WERR, 0, n_comp))
+    uk = below(draws(seed, S_WERRK, 0, n_comp), 3)
+    bad = np.nonzero((ue < p_err) & (body_cnt > 0))[0]
+    fpos = body_off[bad].astype(np.int64)
+    push = uk[bad] == 0
+    w = body[fpos]
+    body[fpos] = np.where(push, (w & np.uint32(0x08FFFFFF)) | np.uint32(OP_PUSH << 24), w ^ np.uint32(1 << 27))
+    decls = pack_decls(var, mode, side)
+    return DeclaredProgram(comp_off, decls, n_vars, body_off, body, idx if arrays else None, lo, hi)
 
 
 # --------------------------------------------------------------------------------------

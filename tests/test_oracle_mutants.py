@@ -10,6 +10,7 @@ from oracle import oracle as O
 from tests import test_oracle_dynamic as D
 from tests import test_oracle_pins as T
 from tests import test_oracle_spaces as K
+from tests import test_oracle_declared as W
 from tests.helpers import load_yaml
 
 MUTANTS = {
@@ -46,6 +47,14 @@ MUTANTS = {
     "spaces-write-keeps-others": ("s.out[j] = j == a ? KT_V : KT_I;", "s.out[j] = j == a ? KT_V : KT_X0 + j;"),
     "spaces-read-at-location-0": ("        s.in[a] = KT_V;\n        s.out[a] = KT_V;\n    } else if (op == 1)",
                                   "        s.in[0] = KT_V;\n        s.out[0] = KT_V;\n    } else if (op == 1)"),
+    "declared-ignores-side": ("if ((set[i] & 0xFFFFFFu) == x && ((set[i] >> 27) & 1u) == side)",
+                              "if ((set[i] & 0xFFFFFFu) == x)"),
+    "declared-obligation-any-side": ("((e >> 24) & 7u) == OP_W && ((e >> 27) & 1u) == side)",
+                                     "((e >> 24) & 7u) == OP_W)"),
+    "declared-naive-rule-inclusive": ("if (y == x || !(lo[y] <= addr && addr < hi[y]))",
+                                      "if (y == x || !(lo[y] <= addr && addr <= hi[y]))"),
+    "declared-rw-not-for-writes": ("if (op == OP_W && !(mode == 1 || mode == 2))", "if (op == OP_W && !(mode == 1))"),
+    "declared-transfer-allowed": ("            if (op == OP_PUSH || op == OP_PULL)\n                v8 |= 1;", ""),
     "overlap-inclusive-upper": ("return x != y && lo[x] < hi[y] && lo[y] < hi[x];",
                                 "return x != y && lo[x] <= hi[y] && lo[y] <= hi[x];"),
 }
@@ -72,6 +81,10 @@ def _pins():
     D.test_dynamic_scenario_statuses_abstract_the_elements()
     K.test_two_spaces_is_the_paper_calculus()
     K.test_every_program_up_to_length_3_at_k3()
+    for ex in load_yaml("declared_examples.yaml"):
+        W.test_declared_examples(ex)
+    W.test_accepted_programs_run_without_a_stuck_step(0)
+    W.test_extension_makes_the_naive_overlap_rule_hold(0)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
