@@ -69,7 +69,7 @@ def load(path: str):
     L.oracle_check_dynamic.restype = i32
     L.oracle_check_spaces.argtypes = [P, u64, u32, u32, P, P, P, P, u64, pu64, pu64, pu64]
     L.oracle_check_spaces.restype = i32
-    L.oracle_check_declared.argtypes = [P, u64, P, u32, P, P, P, P, P, i32, P, pu64]
+    L.oracle_check_declared.argtypes = [P, u64, P, u32, P, P, P, P, P, P, P, i32, P, pu64]
     L.oracle_check_declared.restype = i32
     L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
     L.oracle_overlap_extend.restype = i32
@@ -249,8 +249,9 @@ WD_TRANSFER, WD_READ, WD_WRITE, WD_UNWRITTEN, WD_OVERLAP, WD_ILL = 1, 2, 4, 8, 1
 
 
 def check_declared(comp_off, decls, n_vars: int, body_off, body, idx=None, lo=None, hi=None,
-                   extend: bool = False) -> np.ndarray:
-    """Verdict byte per component of the well-declaredness conditions (bits WD_*)."""
+                   extend: bool = False, sets=None) -> np.ndarray:
+    """Verdict byte per component of the well-declaredness conditions (bits WD_*);
+    sets = overlap_sets(lo, hi) looks overlapping arrays up there (large inputs)."""
     co = np.ascontiguousarray(comp_off, dtype=np.uint64)
     de = np.ascontiguousarray(decls, dtype=np.uint32)
     bo = np.ascontiguousarray(body_off, dtype=np.uint64)
@@ -261,8 +262,12 @@ def check_declared(comp_off, decls, n_vars: int, body_off, body, idx=None, lo=No
     n_comp = co.size - 1
     out = np.empty(max(n_comp, 1), np.uint8)
     bad = C.c_uint64()
+    off = nbr = None
+    if sets is not None:
+        off = np.ascontiguousarray(sets[0], dtype=np.uint64)
+        nbr = np.ascontiguousarray(sets[1] if sets[1].size else np.zeros(1, np.uint32), dtype=np.uint32)
     rc = lib().oracle_check_declared(_p(co), n_comp, _p(de), n_vars, _p(bo), _p(bd), _p(ix), _p(l), _p(h),
-                                     1 if extend else 0, _p(out), C.byref(bad))
+                                     _p(off), _p(nbr), 1 if extend else 0, _p(out), C.byref(bad))
     if rc == -1:
         raise OracleError(f"malformed declaration at index {bad.value}")
     if rc == -4:

@@ -769,6 +769,8 @@ int oracle_check_spaces(const uint32_t *events, uint64_t n, uint32_t n_ids, uint
  *   bit 7  set when any of bits 0-4 is
  * With extend, M is first replaced by O(M), its extension for overlapping arrays
  * (Table "Extension of access mode annotations to deal with overlapping arrays").
+ * off/nbr (optional): the overlap sets of oracle_overlap_sets; the arrays overlapping
+ * a cell or a declared array are then looked up there instead of among all arrays.
  * Scalars: lo/hi/idx are NULL and every variable has one element.
  * Returns -1 (*bad = index) for a malformed declaration (a variable repeated in a
  * component: the declarations are a conjunction over distinct variables, Section 3.3),
@@ -782,9 +784,82 @@ static int find_var_side(const uint32_t *set, int n, uint32_t x, uint32_t side)
     return -1;
 }
 
+/* O(M) as oracle_overlap_extend computes it, with the candidate arrays y taken from
+ * the overlap sets of M's arrays (off/nbr of oracle_overlap_sets) instead of all
+ * arrays: only an array that overlaps a declared one can be inferred.  Candidates are
+ * visited per side in ascending order, as there. */
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+static int overlap_extend_sets(const uint32_t *m, int n_m, const uint32_t *lo, const uint32_t *hi,
+                               const uint64_t *off, const uint32_t *nbr, uint32_t *out, int out_cap)
+{
+    int n = 0;
+    if (n_m > out_cap)
+        return -1;
+    for (int i = 0; i < n_m; i++)
+        out[n++] = m[i];
+    for (uint32_t side = 0; side < 2; side++) {
+        uint64_t nc = 0;
+        for (int i = 0; i < n_m; i++) {
+            uint32_t x = m[i] & 0xFFFFFFu;
+            if (((m[i] >> 27) & 1u) == side)
+                nc += off[x + 1] - off[x];
+        }
+        uint32_t *cand = (uint32_t *)malloc((nc ? nc : 1) * sizeof(uint32_t));
+        if (!cand)
+            return -1;
+        uint64_t k = 0;
+        for (int i = 0; i < n_m; i++) {
+            uint32_t x = m[i] & 0xFFFFFFu;
+            if (((m[i] >> 27) & 1u) == side)
+                for (uint64_t j = off[x]; j < off[x + 1]; j++)
+                    cand[k++] = nbr[j];
+        }
+        qsort(cand, k, sizeof(uint32_t), cmp_u32);
+        for (uint64_t q = 0; q < k; q++) {
+            uint32_t y = cand[q];
+            if (q > 0 && cand[q - 1] == y)
+                continue;
+            int need_rw = 0;
+            for (int i = 0; i < n_m; i++) {
+                uint32_t x = m[i] & 0xFFFFFFu, mode = (m[i] >> 24) & 3u, s = (m[i] >> 27) & 1u;
+                if (s != side || !overlaps(lo, hi, x, y))
+                    continue;
+                if (mode == 2)
+                    need_rw = 1;
+                if (mode == 1) {
+                    int j = find_decl(m, n_m, y, side);
+                    if (!(j >= 0 && ((m[j] >> 24) & 3u) == 1))
+                        need_rw = 1;
+                }
+            }
+            if (!need_rw)
+                continue;
+            uint32_t rw = y | (2u << 24) | (side << 27);
+            int j = find_decl(out, n, y, side);
+            if (j >= 0) {
+                out[j] = rw;
+            } else {
+                if (n >= out_cap) {
+                    free(cand);
+                    return -1;
+                }
+                out[n++] = rw;
+            }
+        }
+        free(cand);
+    }
+    return n;
+}
+
 int oracle_check_declared(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
                           const uint64_t *body_off, const uint32_t *body, const uint32_t *idx, const uint32_t *lo,
-                          const uint32_t *hi, int extend, uint8_t *verdict, uint64_t *bad)
+                          const uint32_t *hi, const uint64_t *off, const uint32_t *nbr, int extend, uint8_t *verdict,
+                          uint64_t *bad)
 {
     int cap = 64 + 2 * (int)n_vars;
     uint32_t *m = (uint32_t *)malloc((size_t)cap * sizeof(uint32_t));
@@ -807,7 +882,8 @@ int oracle_check_declared(const uint64_t *comp_off, uint64_t n_comp, const uint3
         }
         int nm = (int)(b - a);
         if (extend && lo) {
-            nm = oracle_overlap_extend(decls + a, (int)(b - a), lo, hi, n_vars, m, cap);
+            nm = off ? overlap_extend_sets(decls + a, (int)(b - a), lo, hi, off, nbr, m, cap)
+                     : oracle_overlap_extend(decls + a, (int)(b - a), lo, hi, n_vars, m, cap);
             if (nm < 0) {
                 free(m);
                 return -2;
@@ -836,7 +912,10 @@ int oracle_check_declared(const uint64_t *comp_off, uint64_t n_comp, const uint3
                 v8 |= 4;
             if (op == OP_W && lo) {
                 uint32_t addr = lo[x] + i;
-                for (uint32_t y = 0; y < n_vars; y++) {
+                /* every other array holding the cell: all arrays, or the ones in O(x) */
+                uint64_t nq = off ? off[x + 1] - off[x] : n_vars;
+                for (uint64_t q = 0; q < nq; q++) {
+                    uint32_t y = off ? nbr[off[x] + q] : (uint32_t)q;
                     if (y == x || !(lo[y] <= addr && addr < hi[y]))
                         continue;
                     int ky = find_var_side(m, nm, y, side);

@@ -86,6 +86,18 @@ def test_extension_makes_the_naive_overlap_rule_hold(seed):
     assert (v1 == 0).all()
 
 
+def test_overlap_sets_lookup_agrees():
+    """Looking the overlapping arrays up in the overlap sets gives the same verdicts as
+    scanning every array."""
+    for seed in range(2):
+        p = gen.declared_program(6000, 1500, seed, arrays=True, space=1 << 14, max_len=32, p_err=0.1)
+        sets = O.overlap_sets(p.lo, p.hi)
+        for ext in (False, True):
+            a = O.check_declared(p.comp_off, p.decls, p.n_vars, p.body_off, p.body, p.idx, p.lo, p.hi, ext)
+            b = O.check_declared(p.comp_off, p.decls, p.n_vars, p.body_off, p.body, p.idx, p.lo, p.hi, ext, sets)
+            assert np.array_equal(a, b) and (ext or (a & O.WD_OVERLAP).any())
+
+
 def test_malformed_inputs():
     co = np.array([0, 2], np.uint64)
     with pytest.raises(O.OracleError, match="declaration at index 1"):
