@@ -305,6 +305,45 @@ def wl_spaces(args, V, ctx, stream):
                 multi_pass=("sort_pass", "hist"))
 
 
+def wl_declared(args, V, ctx, stream):
+    """Well-declaredness of 2^20 components over 2^16 arrays (lengths log-uniform in
+    [1, 64] in a 2^22-element space), bodies of explicit element accesses, 5 % of the
+    components altered, checked against the declarations extended for overlaps."""
+    import torch
+    from paper_1910_11110_amd import gen
+    n_comp, n_vars = 1 << 20, 1 << 16
+    log(f"[bench] declared: generating {n_comp} components over {n_vars} arrays")
+    p = gen.declared_program(n_comp, n_vars, args.seed, arrays=True, space=1 << 22, max_len=64)
+    dev = [torch.from_numpy(a.view(np.int64 if a.dtype == np.uint64 else np.int32)).cuda()
+           for a in (p.comp_off, p.decls, p.body_off, p.body, p.idx)]
+    torch.cuda.synchronize()
+    t = V.check_declared(ctx, dev[0], dev[1], n_vars, dev[2], dev[3], dev[4], p.lo, p.hi, extend=True)
+    ctx.sync()
+    ill = t.violations().total
+    nb, nd = int(p.body.size), int(p.decls.size)
+
+    def step():
+        t.check()
+
+    def bytes_alg():
+        # offsets, declarations, body words and element indices read once, intervals
+        # once; one verdict byte per component and the ill-declared indices written
+        return 16 * (n_comp + 1) + 4 * nd + 8 * nb + 8 * n_vars + n_comp + 4 * ill
+
+    def cpu_sample():
+        from oracle import oracle as O
+        sets = O.overlap_sets(p.lo, p.hi)
+        return (_median_rate(nb, lambda: O.check_declared(p.comp_off, p.decls, n_vars, p.body_off, p.body, p.idx,
+                                                           p.lo, p.hi, extend=True, sets=sets)),
+                "oracle well-declaredness check of the full workload (overlap sets precomputed), median of 3 "
+                "(body events/s)", None)
+
+    cfg = {"workload": "declared-2^20-components-2^16-arrays", "n_components": n_comp, "n_arrays": n_vars,
+           "n_declarations": nd, "n_body_events": nb, "ill_declared": int(ill), "extend": True}
+    return dict(step=step, units=nb, unit="body event", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg,
+                keep=(t, dev, p))
+
+
 def _oracle_job(inp, sets):
     from oracle import oracle as O
     ev, nv, lo, hi = inp
@@ -540,7 +579,7 @@ def copy_probe(torch, n_words=1 << 28):
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
              "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
              "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap,
-             "batched": wl_batched, "dynamic": wl_dynamic, "spaces": wl_spaces}
+             "batched": wl_batched, "dynamic": wl_dynamic, "spaces": wl_spaces, "declared": wl_declared}
 
 
 def measure(name, args, V, ctx, stream, steps, warmup, cpu=True):
@@ -624,7 +663,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="components", choices=sorted(WORKLOADS) + ["served"])
-    ap.add_argument("--also", default="plain-large,overlap,dynamic,spaces,batched,served",
+    ap.add_argument("--also", default="plain-large,overlap,dynamic,spaces,declared,batched,served",
                     help="workloads reported beside the headline one (comma separated; empty for none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--comp-log2", type=int, default=23)

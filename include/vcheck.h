@@ -64,6 +64,8 @@ enum vc_status {
 #define VC_DEVICE_INPUT 1u  /* input pointers are device pointers (borrowed) */
 #define VC_DEVICE_INIT 2u   /* init pointer is a device pointer (borrowed) */
 #define VC_TRANSLATE_CHECK 4u /* vc_translate also checks the translated trace */
+#define VC_DECLARED_EXTEND 16u /* vc_check_declared: check against O(M), the extension of each
+                                   component's declarations for overlapping arrays */
 #define VC_LIFETIME_EVENTS 8u /* vc_trace_load: host events may also be op 6 (create) and
                                  op 7 (destroy), for vc_trace_set_dynamic_arrays */
 
@@ -178,6 +180,31 @@ int vc_read_overlap_sets(vc_trace *t, uint64_t *off, uint32_t *nbr, uint64_t cap
  * --------------------------------------------------------------------------------- */
 int vc_translate(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
                  const uint64_t *body_off, const uint32_t *body, uint32_t flags, vc_trace **out);
+
+/* Well-declaredness of a component program with explicit bodies (Definition
+ * "Well-declared program", Section 3.4; "Well-declared program with array access",
+ * Section 3.5; the naive rule for overlapping arrays, Section 4.1).  Returns a handle
+ * whose "events" are the components: vc_read_event_status gives one verdict byte per
+ * component, vc_read_violations the ascending indices of the components that are not
+ * well-declared (vc_check re-runs it; there is no final table).  Verdict bits:
+ *   1 a Push or Pull in the body; 2 a read without R or RW on that side; 4 a write
+ *   without W or RW on that side; 8 a W declaration some element of whose variable is
+ *   not written on that side; 16 (arrays) a write into a cell of another array that is
+ *   not declared W or RW on that side; 128 set when any other bit is.
+ * comp_off / decls / n_vars : as for vc_translate (declarations of a component name
+ *            distinct variables).
+ * body_off / body : CSR offsets (n_comp + 1) and event words (ops r, w, Push, Pull, Noop
+ *            on variables < n_vars) of each component's body, straight-line.
+ * body_idx : with arrays, the element index of every body event (< the array's
+ *            length); NULL for scalars.
+ * lo / hi  : n_vars host intervals [lo, hi) when variables are arrays, else NULL.
+ * flags    : VC_DEVICE_INPUT (comp_off, decls, body_off, body, body_idx are device
+ *            pointers, borrowed), VC_DECLARED_EXTEND (check against O(M)).
+ * Malformed declarations or body words give VC_EINVAL naming the first one in program
+ * order (a component's declarations before its body). */
+int vc_check_declared(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
+                      const uint64_t *body_off, const uint32_t *body, const uint32_t *body_idx, const uint32_t *lo,
+                      const uint32_t *hi, uint32_t flags, vc_trace **out);
 
 /* Re-runs the translation of a trace made by vc_translate (and its check if it was
  * created with VC_TRANSLATE_CHECK) on the same inputs, reusing every buffer.  Borrowed

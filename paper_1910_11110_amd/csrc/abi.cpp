@@ -268,6 +268,8 @@ int trace_collect_check(vc_trace *t, const Control &h, uint32_t first_viol)
         t->checked = false;
         t->check_pending = false;
         t->error = VC_EINVAL;
+        if (t->wd)
+            return declared_error(bad);
         return vc_fail(VC_EINVAL, "malformed input word at index %llu", (unsigned long long)bad);
     }
     if (t->check_pending) {
@@ -514,6 +516,8 @@ int enqueue_check(vc_trace *t, hipStream_t s)
     int r;
     if (t->spaces)
         return spaces_enqueue(t, s);
+    if (t->wd)
+        return declared_enqueue(t, s);
     if (use_small_path(t)) {
         if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK ||
             (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
@@ -744,6 +748,7 @@ extern "C" int vc_trace_free(vc_trace *t)
         (void)hipFree(t->ctl);
     overlap_release(t);
     translate_release(t);
+    declared_release(t);
     devbuf_free(t->status);
     devbuf_free(t->status16);
     devbuf_free(t->fin);

@@ -16,6 +16,7 @@ struct DevBuf {
 };
 
 struct BatchState; // batched pipeline: captured graphs and descriptor buffers
+struct DeclaredState; // inputs and work buffers of a well-declaredness check
 namespace vc {
 struct Profiler;
 }
@@ -95,6 +96,8 @@ struct vc_trace {
     uint64_t n_items = 0; // combined items (events, probes, induced) of the last sizing
     DevBuf dyn;
 
+    // a well-declaredness check (events are components; statuses their verdicts)
+    DeclaredState *wd = nullptr;
     // k memory spaces (0: the two-space encoding); their uint16 statuses
     uint32_t spaces = 0;
     DevBuf status16;
@@ -129,6 +132,11 @@ int dynamic_enqueue(vc_trace *t, hipStream_t s);
 uint64_t overlap_combined_size(vc_trace *t);
 void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s);
 void overlap_release(vc_trace *t);
+
+// well-declaredness (declared_abi.cpp)
+int declared_enqueue(vc_trace *t, hipStream_t s);
+int declared_error(uint64_t key);
+void declared_release(vc_trace *t);
 
 // translation (translate_abi.cpp)
 int translate_enqueue(vc_trace *t, hipStream_t s);

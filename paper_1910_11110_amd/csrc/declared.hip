@@ -1,0 +1,270 @@
+// declared.hip -- well-declaredness of component programs with explicit bodies (gfx950).
+//
+// Definition "Well-declared program" (Section 3.4), its array form (Section 3.5) and
+// the naive rule for overlapping arrays (Section 4.1), checked for every component at
+// once.  Every body event is checked on its own against its component's declarations
+// (transfers, undeclared reads and writes, and, for arrays, cells shared with an
+// overlapping array that is not declared for writing); the obligation of a W
+// declaration (every element written on its side) is a coverage question, answered
+// with one bit per element of every W declaration: the body's writes set their bits,
+// and the component's pass finds any bit left clear.  With the extension O(M) (Table
+// "Extension of access mode annotations to deal with overlapping arrays"), whether a
+// variable is declared for reading or writing in O(M) is decided from M directly:
+//   W or RW y in O(M)  iff  W or RW y in M, or some W or RW x in M overlaps y;
+//   R or RW y in O(M)  iff  R or RW y in M, or some RW x in M overlaps y, or some
+//                           W x in M overlaps y while y is not declared W;
+//   W y stays W        iff  no RW x in M overlaps y  (else it is upgraded to RW);
+// all on the same side.  Errors are reported with a key that orders them as a
+// sequential reading does: component, then declarations before body, then index.
+#include "device.h"
+#include "internal.h"
+#include "prof.h"
+
+namespace vc {
+
+constexpr uint32_t WD_TRANSFER = 1, WD_READ = 2, WD_WRITE = 4, WD_UNWRITTEN = 8, WD_OVERLAP = 16, WD_ILL = 128;
+
+namespace {
+
+// error key: component << 33 | (0 declaration, 1 body word) << 32 | index
+__device__ __forceinline__ void report_key(Control *ctl, uint64_t c, uint32_t kind, uint64_t index)
+{
+    const unsigned long long key = ((unsigned long long)c << 33) | ((unsigned long long)kind << 32) | (index & 0xFFFFFFFFull);
+    atomicMin(reinterpret_cast<unsigned long long *>(&ctl->err_index_lo), key);
+}
+
+__device__ __forceinline__ bool overlap_iv(const uint32_t *lo, const uint32_t *hi, uint32_t x, uint32_t y)
+{
+    return x != y && lo[x] < hi[y] && lo[y] < hi[x];
+}
+
+struct Decl {
+    uint32_t var, mode, side;
+};
+__device__ __forceinline__ Decl decl_of(uint32_t w) { return Decl{w & 0xFFFFFFu, (w >> 24) & 3u, (w >> 27) & 1u}; }
+
+// the declaration of y on side s in M (index in [a, b)), or b if none
+__device__ __forceinline__ uint64_t find_decl(const uint32_t *decls, uint64_t a, uint64_t b, uint32_t y, uint32_t s)
+{
+    for (uint64_t d = a; d < b; d++) {
+        const Decl q = decl_of(decls[d]);
+        if (q.var == y && q.side == s)
+            return d;
+    }
+    return b;
+}
+
+// is y declared for writing (W or RW) on side s, in M or in O(M)
+__device__ __forceinline__ bool writable(const uint32_t *decls, uint64_t a, uint64_t b, uint32_t y, uint32_t s,
+                                         const uint32_t *lo, const uint32_t *hi, bool extend)
+{
+    bool ok = false;
+    for (uint64_t d = a; d < b; d++) {
+        const Decl q = decl_of(decls[d]);
+        if (q.side != s || q.mode == 0)
+            continue;
+        ok |= q.var == y || (extend && overlap_iv(lo, hi, q.var, y));
+    }
+    return ok;
+}
+
+// is y declared for reading (R or RW) on side s, in M or in O(M)
+__device__ __forceinline__ bool readable(const uint32_t *decls, uint64_t a, uint64_t b, uint32_t y, uint32_t s,
+                                         const uint32_t *lo, const uint32_t *hi, bool extend)
+{
+    bool own_r = false, own_w = false, by_rw = false, by_w = false;
+    for (uint64_t d = a; d < b; d++) {
+        const Decl q = decl_of(decls[d]);
+        if (q.side != s)
+            continue;
+        if (q.var == y) {
+            own_r |= q.mode == 0 || q.mode == 2;
+            own_w |= q.mode == 1;
+        } else if (extend && overlap_iv(lo, hi, q.var, y)) {
+            by_rw |= q.mode == 2;
+            by_w |= q.mode == 1;
+        }
+    }
+    return own_r || by_rw || (by_w && !own_w);
+}
+
+// W declaration d of component [a, b) that keeps its obligation (not upgraded)
+__device__ __forceinline__ bool obliged(const uint32_t *decls, uint64_t a, uint64_t b, uint64_t d,
+                                        const uint32_t *lo, const uint32_t *hi, bool extend)
+{
+    const Decl q = decl_of(decls[d]);
+    if (q.mode != 1)
+        return false;
+    if (!extend)
+        return true;
+    for (uint64_t e = a; e < b; e++) {
+        const Decl r = decl_of(decls[e]);
+        if (r.side == q.side && r.mode == 2 && overlap_iv(lo, hi, r.var, q.var))
+            return false;
+    }
+    return true;
+}
+
+// per component: declarations checked (as the translation does), and the number of
+// coverage bits of every declaration (the length of a W declaration's variable)
+__global__ void k_wd_decls(const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls,
+                           uint64_t n_decl, uint32_t n_vars, const uint32_t *__restrict__ lo,
+                           const uint32_t *__restrict__ hi, int extend, uint32_t *__restrict__ wlen, Control *ctl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_comp; c += stride) {
+        const uint64_t a = comp_off[c], b = comp_off[c + 1];
+        if (b < a || b > n_decl) {
+            report_key(ctl, c, 0, c);
+            continue;
+        }
+        bool bad = false;
+        for (uint64_t d = a; d < b && !bad; d++) {
+            const uint32_t w = decls[d];
+            bool ok = (w >> 28) == 0 && ((w >> 26) & 1u) == 0 && ((w >> 24) & 3u) != 3 && (w & 0xFFFFFFu) < n_vars;
+            for (uint64_t e = a; e < d && ok; e++)
+                ok = ((decls[e] ^ w) & 0xFFFFFFu) != 0;
+            if (!ok) {
+                report_key(ctl, c, 0, d);
+                bad = true;
+            }
+        }
+        for (uint64_t d = a; d < b; d++) {
+            uint32_t len = 0;
+            if (!bad && obliged(decls, a, b, d, lo, hi, extend != 0 && lo)) {
+                const uint32_t x = decls[d] & 0xFFFFFFu;
+                len = lo ? hi[x] - lo[x] : 1u;
+            }
+            wlen[d] = len;
+        }
+    }
+}
+
+// the component of body event j: the last c with body_off[c] <= j (non-empty components)
+__device__ __forceinline__ uint64_t comp_of(const uint64_t *body_off, uint64_t n_comp, uint64_t j)
+{
+    uint64_t lo_c = 0, hi_c = n_comp; // body_off[lo_c] <= j < body_off[hi_c]
+    while (hi_c - lo_c > 1) {
+        const uint64_t mid = (lo_c + hi_c) / 2;
+        if (body_off[mid] <= j)
+            lo_c = mid;
+        else
+            hi_c = mid;
+    }
+    return lo_c;
+}
+
+// per body event: its conditions, and its coverage bit when it writes an obliged variable
+__global__ void k_wd_body(const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls,
+                          const uint64_t *__restrict__ body_off, const uint32_t *__restrict__ body, uint64_t n_body,
+                          const uint32_t *__restrict__ idx, uint32_t n_vars, const uint32_t *__restrict__ lo,
+                          const uint32_t *__restrict__ hi, const uint64_t *__restrict__ off,
+                          const uint32_t *__restrict__ nbr, int extend, const uint64_t *__restrict__ boff,
+                          uint32_t *__restrict__ bits, uint64_t nbits, uint32_t *__restrict__ verdict, Control *ctl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const bool ext = extend != 0 && lo;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_body; j += stride) {
+        const uint64_t c = comp_of(body_off, n_comp, j);
+        const uint64_t a = comp_off[c], b = comp_off[c + 1];
+        const uint32_t e = body[j], x = e & 0xFFFFFFu, op = (e >> 24) & 7u, s = (e >> 27) & 1u;
+        const uint32_t i = idx ? idx[j] : 0u;
+        if ((e >> 28) != 0 || op > OP_NOOP || x >= n_vars || (lo ? i >= hi[x] - lo[x] : i != 0)) {
+            report_key(ctl, c, 1, j);
+            continue;
+        }
+        if (b < a || b > comp_off[n_comp]) // reported by the declaration pass
+            continue;
+        uint32_t v = 0;
+        if (op == OP_PUSH || op == OP_PULL)
+            v |= WD_TRANSFER;
+        if (op == OP_R && !readable(decls, a, b, x, s, lo, hi, ext))
+            v |= WD_READ;
+        if (op == OP_W) {
+            if (!writable(decls, a, b, x, s, lo, hi, ext))
+                v |= WD_WRITE;
+            if (lo) {
+                // the naive rule: every other array holding the written cell
+                const uint32_t addr = lo[x] + i;
+                for (uint64_t q = off[x]; q < off[x + 1]; q++) {
+                    const uint32_t y = nbr[q];
+                    if (lo[y] <= addr && addr < hi[y] && !writable(decls, a, b, y, s, lo, hi, ext))
+                        v |= WD_OVERLAP;
+                }
+            }
+            const uint64_t d = find_decl(decls, a, b, x, s);
+            if (d < b && obliged(decls, a, b, d, lo, hi, ext)) {
+                const uint64_t bit = boff[d] + i;
+                if (bit < nbits)
+                    atomicOr(&bits[bit >> 5], 1u << (bit & 31u));
+            }
+        }
+        if (v)
+            atomicOr(&verdict[c], v);
+    }
+}
+
+// per component: obligations met, and the verdict byte
+__global__ void k_wd_finish(const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ wlen,
+                            const uint64_t *__restrict__ boff, const uint32_t *__restrict__ bits, uint64_t nbits,
+                            const uint32_t *__restrict__ verdict, uint8_t *__restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_comp; c += stride) {
+        uint32_t v = verdict[c];
+        const uint64_t a = comp_off[c], b = comp_off[c + 1];
+        if (b >= a && b <= comp_off[n_comp])
+            for (uint64_t d = a; d < b && !(v & WD_UNWRITTEN); d++) {
+                const uint64_t p0 = boff[d], p1 = p0 + wlen[d];
+                for (uint64_t p = p0; p < p1 && p < nbits; p++)
+                    if (!((bits[p >> 5] >> (p & 31u)) & 1u)) {
+                        v |= WD_UNWRITTEN;
+                        break;
+                    }
+            }
+        out[c] = (uint8_t)(v | (v ? WD_ILL : 0u));
+    }
+}
+
+unsigned grid_w(uint64_t n)
+{
+    uint64_t g = ceil_div(n ? n : 1, (uint64_t)BLOCK * 4);
+    return (unsigned)(g > 16384 ? 16384 : g);
+}
+
+} // namespace
+
+void launch_wd_decls(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint64_t n_decl,
+                     uint32_t n_vars, const uint32_t *lo, const uint32_t *hi, bool extend, uint32_t *wlen, Control *ctl,
+                     hipStream_t s)
+{
+    if (n_comp) {
+        ProfScope p(s, "wd_decls");
+        k_wd_decls<<<grid_w(n_comp), BLOCK, 0, s>>>(comp_off, n_comp, decls, n_decl, n_vars, lo, hi, extend ? 1 : 0,
+                                                    wlen, ctl);
+    }
+}
+
+void launch_wd_body(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, const uint64_t *body_off,
+                    const uint32_t *body, uint64_t n_body, const uint32_t *idx, uint32_t n_vars, const uint32_t *lo,
+                    const uint32_t *hi, const OverlapSets *o, bool extend, const uint64_t *boff, uint32_t *bits,
+                    uint64_t nbits, uint32_t *verdict, Control *ctl, hipStream_t s)
+{
+    if (n_body && n_comp) {
+        ProfScope p(s, "wd_body");
+        k_wd_body<<<grid_w(n_body), BLOCK, 0, s>>>(comp_off, n_comp, decls, body_off, body, n_body, idx, n_vars, lo, hi,
+                                                   o ? o->off : nullptr, o ? o->nbr : nullptr, extend ? 1 : 0, boff,
+                                                   bits, nbits, verdict, ctl);
+    }
+}
+
+void launch_wd_finish(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *wlen, const uint64_t *boff,
+                      const uint32_t *bits, uint64_t nbits, const uint32_t *verdict, uint8_t *out, hipStream_t s)
+{
+    if (n_comp) {
+        ProfScope p(s, "wd_finish");
+        k_wd_finish<<<grid_w(n_comp), BLOCK, 0, s>>>(comp_off, n_comp, wlen, boff, bits, nbits, verdict, out);
+    }
+}
+
+} // namespace vc

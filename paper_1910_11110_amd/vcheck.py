@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvcheck.so")
 
 VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE, VC_ESTATE, VC_ETRUNC, VC_EBUDGET, VC_EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
-VC_DEVICE_INPUT, VC_DEVICE_INIT, VC_TRANSLATE_CHECK, VC_LIFETIME_EVENTS = 1, 2, 4, 8
+VC_DEVICE_INPUT, VC_DEVICE_INIT, VC_TRANSLATE_CHECK, VC_LIFETIME_EVENTS, VC_DECLARED_EXTEND = 1, 2, 4, 8, 16
 NO_MOTHER = 0xFFFFFFFF
 
 _lib = None
@@ -60,6 +60,7 @@ def lib():
             "vc_trace_set_dynamic_arrays": ([P, P, P, P, u32], i32),
             "vc_trace_load_spaces": ([P, P, u64, u32, u32, P, u32, pP], i32),
             "vc_read_event_status16": ([P, P, u64], i32),
+            "vc_check_declared": ([P, P, u64, P, u32, P, P, P, P, P, u32, pP], i32),
             "vc_read_overlap_sets": ([P, P, P, u64, pu64], i32),
             "vc_translate": ([P, P, u64, P, u32, P, P, u32, pP], i32),
             "vc_check": ([P], i32),
@@ -313,6 +314,29 @@ def check_small_noalloc(ctx: Context, events, n_ids: int, init, status, final, v
     _check(lib().vc_check_small_noalloc(ctx.h, C.c_void_p(events.data_ptr()), events.numel(), n_ids, ip,
                                         C.c_void_p(status.data_ptr()), C.c_void_p(final.data_ptr()),
                                         C.c_void_p(violations.data_ptr()), C.c_void_p(counts.data_ptr())))
+
+
+def check_declared(ctx: Context, comp_off, decls, n_vars: int, body_off, body, idx=None, lo=None, hi=None,
+                   extend: bool = False) -> Trace:
+    """Well-declaredness of a component program with explicit bodies: the returned
+    trace's status() is the verdict byte of every component, violations() the
+    components that are not well-declared."""
+    cp, ck, cd = _buf(comp_off, np.uint64)
+    dp, dk, dd = _buf(decls, np.uint32)
+    bp, bk, bdv = _buf(body_off, np.uint64)
+    yp, yk, yd = _buf(body, np.uint32)
+    ip, ik, idv = _buf(idx, np.uint32)
+    dev = cd or dd or bdv or yd or idv
+    n_comp = int(ck.numel() if cd else ck.size) - 1
+    lp = hp = None
+    if lo is not None:
+        lo = np.ascontiguousarray(lo, dtype=np.uint32)
+        hi = np.ascontiguousarray(hi, dtype=np.uint32)
+        lp, hp = lo.ctypes.data_as(C.c_void_p), hi.ctypes.data_as(C.c_void_p)
+    flags = (VC_DEVICE_INPUT if dev else 0) | (VC_DECLARED_EXTEND if extend else 0)
+    h = C.c_void_p()
+    _check(lib().vc_check_declared(ctx.h, cp, n_comp, dp, n_vars, bp, yp, ip, lp, hp, flags, C.byref(h)))
+    return Trace(ctx, h, (ck, dk, bk, yk, ik) if dev else ())
 
 
 def batch_check(ctx: Context, traces):
