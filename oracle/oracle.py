@@ -71,6 +71,8 @@ def load(path: str):
     L.oracle_check_spaces.restype = i32
     L.oracle_check_declared.argtypes = [P, u64, P, u32, P, P, P, P, P, P, P, i32, P, pu64]
     L.oracle_check_declared.restype = i32
+    L.oracle_run_programs.argtypes = [P, u64, P, u32, P, P, u64, P, P, P, P, P, P, pu64]
+    L.oracle_run_programs.restype = i32
     L.oracle_overlap_extend.argtypes = [P, i32, P, P, u32, P, i32]
     L.oracle_overlap_extend.restype = i32
     return L
@@ -275,6 +277,36 @@ def check_declared(comp_off, decls, n_vars: int, body_off, body, idx=None, lo=No
     if rc != 0:
         raise OracleError(f"oracle_check_declared failed: {rc}")
     return out[:n_comp]
+
+
+@dataclass
+class ProgramRuns:
+    steps: np.ndarray    # reductions taken
+    effects: np.ndarray  # effects run
+    stuck: np.ndarray    # stuck effects
+    first: np.ndarray    # effect index of the first stuck one (effects if none)
+    done: np.ndarray     # 1 if the program completed within the fuel
+    final: np.ndarray    # (n_prog, n_vars) final statuses
+
+
+def run_programs(prog_off, words, n_vars: int, choice=None, init=None, fuel: int = 1 << 12) -> ProgramRuns:
+    """Structured programs (While / If / sequence over effects), one per CSR range."""
+    po = np.ascontiguousarray(prog_off, dtype=np.uint64)
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    ch = None if choice is None else np.ascontiguousarray(choice, dtype=np.uint64)
+    ini = None if init is None else np.ascontiguousarray(init, dtype=np.uint8)
+    n = po.size - 1
+    out = [np.empty(max(n, 1), np.uint64) for _ in range(4)]
+    done = np.empty(max(n, 1), np.uint8)
+    fin = np.empty(max(n * n_vars, 1), np.uint8)
+    bad = C.c_uint64()
+    rc = lib().oracle_run_programs(_p(po), n, _p(w), n_vars, _p(ch), _p(ini), fuel, *[_p(o) for o in out], _p(done),
+                                   _p(fin), C.byref(bad))
+    if rc == -1:
+        raise OracleError(f"malformed program word at index {bad.value}")
+    if rc != 0:
+        raise OracleError(f"oracle_run_programs failed: {rc}")
+    return ProgramRuns(*[o[:n] for o in out], done[:n], fin[:n * n_vars].reshape(n, n_vars))
 
 
 def overlap_extend(m: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:

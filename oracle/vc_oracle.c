@@ -951,3 +951,155 @@ int oracle_check_declared(const uint64_t *comp_off, uint64_t n_comp, const uint3
     free(m);
     return 0;
 }
+
+/* ------------------------------------------------------------------------------
+ * Structured programs (Section 3.2: S ::= E x | rem(E x) | S; S' | While(c) S |
+ * If c S S' | Noop, c ::= isValid x | remIsValid x | x (+) y; Figure "Operational
+ * semantics of validity status": rules valid / invalid / rem-valid / rem-invalid,
+ * Effect, Remote Effect, While-True / While-False, IF-True / IF-False).
+ * Wire format of one program (a prefix serialisation of its syntax tree, a sequence
+ * being a run of statements):
+ *   effect : the event word (bits 30-31 = 0)
+ *   While  : word (1 << 30) | kind << 24 | x, then n = the body's length in words
+ *   If     : word (2 << 30) | kind << 24 | x, then n (then-branch words), m (else)
+ *   kind   : 0 isValid x, 1 remIsValid x, 2 x (+) y (x is unused)
+ * The paper leaves (+) to extra rules that always succeed; here its outcomes are an
+ * input: the k-th evaluation of a (+) condition in a program (k = 0, 1, ...) is bit
+ * k mod 64 of the program's choice word.
+ * Each reduction (an effect, While-True, While-False, IF-True, IF-False) takes one
+ * step of fuel; a program stops after `fuel` steps.  A stuck effect is flagged and
+ * skipped as in the plain method.  Per program: steps taken, effects, stuck effects,
+ * the effect index of the first stuck one (the effect count if none), 1 if it ran
+ * to completion (0 if the fuel ran out), and the final statuses of its variables
+ * (ids below n_vars, all starting at init or (V,I)).
+ * Returns -1 (*bad = word index) for a malformed word or a length that leaves its
+ * enclosing statement.
+ * ------------------------------------------------------------------------------ */
+struct prog_run {
+    const uint32_t *w;
+    uint32_t n_vars;
+    uint8_t *sigma;
+    uint64_t choice, n_choice;
+    uint64_t fuel, steps, effects, stuck, first;
+    int done; /* 0 while fuel remains */
+};
+
+static int eval_cond(struct prog_run *r, uint32_t word)
+{
+    uint32_t kind = (word >> 24) & 3u, x = word & 0xFFFFFFu;
+    if (kind == 0)
+        return is_valid(r->sigma[x]);
+    if (kind == 1)
+        return rem_is_valid(r->sigma[x]);
+    int v = (int)((r->choice >> (r->n_choice % 64)) & 1u);
+    r->n_choice++;
+    return v;
+}
+
+/* runs the statements in words [a, b); returns 0, or -1 when the fuel runs out */
+static int run_seq(struct prog_run *r, uint64_t a, uint64_t b)
+{
+    uint64_t pc = a;
+    while (pc < b) {
+        uint32_t word = r->w[pc], kind = word >> 30;
+        if (kind == 0) { /* rule Effect / Remote Effect */
+            if (r->steps == r->fuel)
+                return -1;
+            r->steps++;
+            uint32_t x = word & 0xFFFFFFu, op = (word >> 24) & 7u, side = (word >> 27) & 1u;
+            int stuck = 0;
+            r->sigma[x] = (uint8_t)apply_effect((int)op, (int)side, r->sigma[x], &stuck);
+            if (stuck) {
+                if (r->stuck == 0)
+                    r->first = r->effects;
+                r->stuck++;
+            }
+            r->effects++;
+            pc++;
+        } else if (kind == 1) { /* While: While-True runs the body then the While again */
+            uint64_t n = r->w[pc + 1];
+            for (;;) {
+                if (r->steps == r->fuel)
+                    return -1;
+                r->steps++;
+                if (!eval_cond(r, word))
+                    break; /* While-False */
+                if (run_seq(r, pc + 2, pc + 2 + n) < 0)
+                    return -1;
+            }
+            pc += 2 + n;
+        } else { /* If: IF-True runs the first branch, IF-False the second */
+            uint64_t n = r->w[pc + 1], m = r->w[pc + 2];
+            if (r->steps == r->fuel)
+                return -1;
+            r->steps++;
+            int c = eval_cond(r, word);
+            if (run_seq(r, c ? pc + 3 : pc + 3 + n, c ? pc + 3 + n : pc + 3 + n + m) < 0)
+                return -1;
+            pc += 3 + n + m;
+        }
+    }
+    return 0;
+}
+
+/* structural check of words [a, b): every statement well formed and inside [a, b) */
+static int prog_valid(const uint32_t *w, uint64_t a, uint64_t b, uint32_t n_vars, int depth, uint64_t *bad)
+{
+    uint64_t pc = a;
+    while (pc < b) {
+        uint32_t word = w[pc], kind = word >> 30, x = word & 0xFFFFFFu;
+        if (kind == 0) {
+            if (((word >> 28) & 3u) != 0 || ((word >> 24) & 7u) > 4 || x >= n_vars) {
+                *bad = pc;
+                return 0;
+            }
+            pc++;
+            continue;
+        }
+        uint32_t ck = (word >> 24) & 3u;
+        uint64_t hdr = kind == 1 ? 2 : 3;
+        if (kind == 3 || ck == 3 || ((word >> 26) & 15u) != 0 || (ck < 2 && x >= n_vars) || pc + hdr > b ||
+            depth >= 32) {
+            *bad = pc;
+            return 0;
+        }
+        uint64_t n = w[pc + 1], m = kind == 2 ? w[pc + 2] : 0;
+        if (pc + hdr + n + m > b) {
+            *bad = pc;
+            return 0;
+        }
+        if (!prog_valid(w, pc + hdr, pc + hdr + n, n_vars, depth + 1, bad) ||
+            !prog_valid(w, pc + hdr + n, pc + hdr + n + m, n_vars, depth + 1, bad))
+            return 0;
+        pc += hdr + n + m;
+    }
+    return 1;
+}
+
+int oracle_run_programs(const uint64_t *prog_off, uint64_t n_prog, const uint32_t *words, uint32_t n_vars,
+                        const uint64_t *choice, const uint8_t *init, uint64_t fuel, uint64_t *steps_out,
+                        uint64_t *effects_out, uint64_t *stuck_out, uint64_t *first_out, uint8_t *done_out,
+                        uint8_t *final_out, uint64_t *bad)
+{
+    uint8_t *sigma = (uint8_t *)malloc(n_vars ? n_vars : 1);
+    if (!sigma)
+        return -2;
+    for (uint64_t p = 0; p < n_prog; p++) {
+        if (!prog_valid(words, prog_off[p], prog_off[p + 1], n_vars, 0, bad)) {
+            free(sigma);
+            return -1;
+        }
+        for (uint32_t v = 0; v < n_vars; v++)
+            sigma[v] = init ? init[p * n_vars + v] : 1;
+        struct prog_run r = { words, n_vars, sigma, choice ? choice[p] : 0, 0, fuel, 0, 0, 0, 0, 0 };
+        int rc = run_seq(&r, prog_off[p], prog_off[p + 1]);
+        steps_out[p] = r.steps;
+        effects_out[p] = r.effects;
+        stuck_out[p] = r.stuck;
+        first_out[p] = r.stuck ? r.first : r.effects;
+        done_out[p] = rc == 0;
+        memcpy(final_out + p * n_vars, sigma, n_vars);
+    }
+    free(sigma);
+    return 0;
+}

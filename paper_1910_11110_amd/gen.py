@@ -40,6 +40,7 @@ S_ARRIVE = 40
 S_DMOTHER, S_DLEN, S_DLO, S_DLIFE, S_DCPOS, S_DDPOS, S_DVAR = 50, 51, 52, 53, 54, 55, 56
 S_KVAR, S_KOP, S_KA, S_KB = 60, 61, 62, 63
 S_WK, S_WVAR, S_WMODE, S_WSIDE, S_WEL, S_WERR, S_WERRK = 70, 71, 72, 73, 74, 75, 76
+S_PT, S_PPICK, S_PCHOICE, S_PINIT = 80, 81, 82, 83
 
 OP_R, OP_W, OP_PUSH, OP_PULL, OP_NOOP = 0, 1, 2, 3, 4
 MODE_R, MODE_W, MODE_RW = 0, 1, 2
@@ -361,6 +362,82 @@ def declared_program(n_comp: int, n_vars: int, seed: int, arrays: bool = True, s
     body[fpos] = np.where(push, (w & np.uint32(0x08FFFFFF)) | np.uint32(OP_PUSH << 24), w ^ np.uint32(1 << 27))
     decls = pack_decls(var, mode, side)
     return DeclaredProgram(comp_off, decls, n_vars, body_off, body, idx if arrays else None, lo, hi)
+
+
+# --------------------------------------------------------------------------------------
+# structured programs (While / If / sequences of effects)
+# --------------------------------------------------------------------------------------
+K_VALID, K_REMVALID, K_CHOICE = 0, 1, 2
+
+
+def program_words(stmts) -> list:
+    """Prefix serialisation of a statement list: an effect is its event word; While is
+    (1 << 30 | kind << 24 | x, body length) then the body; If is (2 << 30 | kind << 24 |
+    x, then length, else length) then both branches.  Statements are tuples ("E", op,
+    side, x), ("W", (kind, x), body), ("I", (kind, x), then, else)."""
+    out = []
+    for st in stmts:
+        if st[0] == "E":
+            out.append(int(st[3]) | (int(st[1]) << 24) | (int(st[2]) << 27))
+        elif st[0] == "W":
+            body = program_words(st[2])
+            out += [(1 << 30) | (st[1][0] << 24) | st[1][1], len(body)] + body
+        else:
+            a, b = program_words(st[2]), program_words(st[3])
+            out += [(2 << 30) | (st[1][0] << 24) | st[1][1], len(a), len(b)] + a + b
+    return out
+
+
+def random_program(rng: np.random.Generator, n_vars: int, max_words: int, depth: int = 0) -> list:
+    """A random statement list of at most about max_words words: effects (op uniform,
+    side and variable uniform), While and If on isValid / remIsValid / choice
+    conditions, nested up to depth 3."""
+    out, used = [], 0
+    while used < max_words:
+        u = rng.random()
+        if depth < 3 and u < 0.12 and max_words - used > 6:
+            cond = (int(rng.choice(3, p=[0.4, 0.4, 0.2])), int(rng.integers(n_vars)))
+            body = random_program(rng, n_vars, int(rng.integers(1, max(2, (max_words - used) // 3))), depth + 1)
+            out.append(("W", cond, body))
+        elif depth < 3 and u < 0.3 and max_words - used > 8:
+            cond = (int(rng.choice(3, p=[0.4, 0.4, 0.2])), int(rng.integers(n_vars)))
+            k = max(2, (max_words - used) // 4)
+            out.append(("I", cond, random_program(rng, n_vars, int(rng.integers(0, k)), depth + 1),
+                        random_program(rng, n_vars, int(rng.integers(0, k)), depth + 1)))
+        else:
+            out.append(("E", int(rng.integers(5)), int(rng.integers(2)), int(rng.integers(n_vars))))
+        used = len(program_words(out))
+    return out
+
+
+@dataclass
+class Programs:
+    prog_off: np.ndarray
+    words: np.ndarray
+    n_vars: int
+    choice: np.ndarray   # uint64 per program: outcomes of its choice conditions
+    init: np.ndarray     # (n_prog * n_vars) initial statuses
+
+
+def structured_programs(n_prog: int, n_vars: int, seed: int, n_templates: int = 4096,
+                        max_words: int = 64) -> Programs:
+    """n_prog programs over n_vars variables each, drawn uniformly from n_templates
+    random templates, each with its own choice word and initial statuses drawn
+    uniformly from (V,I), (I,V), (V,V)."""
+    rng = np.random.default_rng(seed)
+    temps = [np.array(program_words(random_program(rng, n_vars, max_words)), np.uint32) for _ in range(n_templates)]
+    pick = below(draws(seed, S_PPICK, 0, n_prog), n_templates)
+    lens = np.array([t.size for t in temps], np.int64)[pick]
+    prog_off = np.zeros(n_prog + 1, np.uint64)
+    np.cumsum(lens, out=prog_off[1:])
+    flat = np.concatenate(temps)
+    toff = np.zeros(n_templates + 1, np.int64)
+    np.cumsum([t.size for t in temps], out=toff[1:])
+    src = np.repeat(toff[pick], lens) + (np.arange(int(lens.sum())) - np.repeat(prog_off[:-1].astype(np.int64), lens))
+    words = flat[src]
+    choice = draws(seed, S_PCHOICE, 0, n_prog)
+    init = (below(draws(seed, S_PINIT, 0, n_prog * n_vars), 3) + 1).astype(np.uint8)
+    return Programs(prog_off, words, n_vars, choice, init)
 
 
 # --------------------------------------------------------------------------------------

@@ -166,3 +166,43 @@ class ElementModel:
 def all_programs(length: int, n_vars: int = 2):
     alphabet = [(op, remote, v) for v in range(n_vars) for op in OPS for remote in (False, True)]
     return itertools.product(alphabet, repeat=length)
+
+
+# -------------------------------------------------------------------------------------
+# structured programs, reduced literally
+# -------------------------------------------------------------------------------------
+def structured_run(stmts, store, choice: int, fuel: int):
+    """The small-step rules of Figure "Operational semantics of validity status" on a
+    statement list (tuples ("E", op, side, x), ("W", (kind, x), body), ("I", (kind, x),
+    then, else); kind 0 isValid, 1 remIsValid, 2 the k-th choice is bit k of `choice`):
+    the first statement of the configuration is reduced until the list is empty, a
+    step is stuck, or `fuel` steps were taken.  Returns (steps, effects run, index of
+    the stuck effect or None, completed, store)."""
+    conf, store = list(stmts), dict(store)
+    steps = effects = n_choice = 0
+    while conf:
+        if steps == fuel:
+            return steps, effects, None, False, store
+        st = conf.pop(0)
+        if st[0] == "E":
+            nxt = _fire(store[st[3]], OPS[st[1]], bool(st[2]))
+            if nxt is None:
+                return steps, effects, effects, False, store
+            store[st[3]] = nxt
+            steps += 1
+            effects += 1
+            continue
+        kind, x = st[1]
+        if kind == 0:
+            c = store[x][0] == "V"       # rules valid / invalid
+        elif kind == 1:
+            c = store[x][1] == "V"       # rules rem-valid / rem-invalid
+        else:
+            c = bool((choice >> (n_choice % 64)) & 1)
+            n_choice += 1
+        steps += 1
+        if st[0] == "W":                 # While-True / While-False
+            conf = (list(st[2]) + [st] + conf) if c else conf
+        else:                            # IF-True / IF-False
+            conf = list(st[2] if c else st[3]) + conf
+    return steps, effects, None, True, store

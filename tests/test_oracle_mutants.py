@@ -11,6 +11,7 @@ from tests import test_oracle_dynamic as D
 from tests import test_oracle_pins as T
 from tests import test_oracle_spaces as K
 from tests import test_oracle_declared as W
+from tests import test_oracle_programs as G
 from tests.helpers import load_yaml
 
 MUTANTS = {
@@ -55,6 +56,15 @@ MUTANTS = {
                                       "if (y == x || !(lo[y] <= addr && addr <= hi[y]))"),
     "declared-rw-not-for-writes": ("if (op == OP_W && !(mode == 1 || mode == 2))", "if (op == OP_W && !(mode == 1))"),
     "declared-transfer-allowed": ("            if (op == OP_PUSH || op == OP_PULL)\n                v8 |= 1;", ""),
+    "programs-while-runs-once": ("                if (run_seq(r, pc + 2, pc + 2 + n) < 0)\n                    return -1;\n            }",
+                                 "                if (run_seq(r, pc + 2, pc + 2 + n) < 0)\n                    return -1;\n"
+                                 "                break;\n            }"),
+    "programs-if-branches-swapped": ("if (run_seq(r, c ? pc + 3 : pc + 3 + n, c ? pc + 3 + n : pc + 3 + n + m) < 0)",
+                                     "if (run_seq(r, !c ? pc + 3 : pc + 3 + n, !c ? pc + 3 + n : pc + 3 + n + m) < 0)"),
+    "programs-remvalid-reads-local": ("    if (kind == 1)\n        return rem_is_valid(r->sigma[x]);",
+                                      "    if (kind == 1)\n        return is_valid(r->sigma[x]);"),
+    "programs-choice-bits-reversed": ("int v = (int)((r->choice >> (r->n_choice % 64)) & 1u);",
+                                      "int v = (int)((r->choice >> (63 - r->n_choice % 64)) & 1u);"),
     "overlap-inclusive-upper": ("return x != y && lo[x] < hi[y] && lo[y] < hi[x];",
                                 "return x != y && lo[x] <= hi[y] && lo[y] <= hi[x];"),
 }
@@ -85,6 +95,10 @@ def _pins():
         W.test_declared_examples(ex)
     W.test_accepted_programs_run_without_a_stuck_step(0)
     W.test_extension_makes_the_naive_overlap_rule_hold(0)
+    G.test_random_programs_follow_the_small_step_rules(0)
+    G.test_straight_line_programs_are_the_plain_check()
+    G.test_translation_with_its_if_statements()
+    G.test_choice_conditions_and_fuel()
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
