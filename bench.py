@@ -344,6 +344,41 @@ def wl_declared(args, V, ctx, stream):
                 keep=(t, dev, p))
 
 
+def wl_programs(args, V, ctx, stream):
+    """Structured programs: 2^20 programs over 16 variables each, drawn from 4,096 random
+    templates of up to 64 words (While and If on isValid, remIsValid and choice
+    conditions, nested up to 4 deep), own choice words and initial statuses, fuel 4096
+    reductions."""
+    from paper_1910_11110_amd import gen
+    n_prog, n_vars, fuel = 1 << 20, 16, 1 << 12
+    log(f"[bench] programs: generating {n_prog} programs")
+    P = gen.structured_programs(n_prog, n_vars, args.seed)
+    g = V.Programs(ctx, P.prog_off, P.words, n_vars, P.choice, P.init, fuel)
+    steps = int(g.read()[0].sum())
+
+    def step():
+        g.run()
+
+    def bytes_alg():
+        # program words, offsets, choice words and initial statuses read once; five
+        # counters and the final statuses of every program written once
+        return 4 * int(P.words.size) + 8 * (n_prog + 1) + 8 * n_prog + n_vars * n_prog + 33 * n_prog + n_vars * n_prog
+
+    def cpu_sample():
+        from oracle import oracle as O
+        m = 1 << 17
+        po = P.prog_off[:m + 1]
+        return (_median_rate(int(O.run_programs(po, P.words, n_vars, P.choice[:m], P.init[:m * n_vars],
+                                                fuel).steps.sum()),
+                             lambda: O.run_programs(po, P.words, n_vars, P.choice[:m], P.init[:m * n_vars], fuel)),
+                f"oracle run of the first {m} programs, median of 3 (reductions/s)", None)
+
+    cfg = {"workload": "programs-2^20x16-fuel-4096", "n_programs": n_prog, "n_vars": n_vars, "fuel": fuel,
+           "n_words": int(P.words.size), "reductions": steps}
+    return dict(step=step, units=steps, unit="reduction", bytes_alg=bytes_alg, cpu=cpu_sample, config=cfg,
+                keep=(g, P))
+
+
 def _oracle_job(inp, sets):
     from oracle import oracle as O
     ev, nv, lo, hi = inp
@@ -579,7 +614,8 @@ def copy_probe(torch, n_words=1 << 28):
 WORKLOADS = {"components": wl_components, "plain-large": wl_plain,
              "plain-wide": lambda a, V, c, s: wl_plain(a, V, c, s, n=1 << 26, n_ids=1 << 20),
              "plain-small": lambda a, V, c, s: wl_plain(a, V, c, s, n=10_000), "overlap": wl_overlap,
-             "batched": wl_batched, "dynamic": wl_dynamic, "spaces": wl_spaces, "declared": wl_declared}
+             "batched": wl_batched, "dynamic": wl_dynamic, "spaces": wl_spaces, "declared": wl_declared,
+             "programs": wl_programs}
 
 
 def measure(name, args, V, ctx, stream, steps, warmup, cpu=True):
@@ -663,7 +699,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="components", choices=sorted(WORKLOADS) + ["served"])
-    ap.add_argument("--also", default="plain-large,overlap,dynamic,spaces,declared,batched,served",
+    ap.add_argument("--also", default="plain-large,overlap,dynamic,spaces,declared,programs,batched,served",
                     help="workloads reported beside the headline one (comma separated; empty for none)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--comp-log2", type=int, default=23)

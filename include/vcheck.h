@@ -72,6 +72,7 @@ enum vc_status {
 typedef struct vc_ctx vc_ctx;
 typedef struct vc_trace vc_trace;
 typedef struct vc_server vc_server;
+typedef struct vc_programs vc_programs;
 
 /* ---------------------------------------------------------------------------------
  * Context: one HIP device and one stream.
@@ -205,6 +206,36 @@ int vc_translate(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const u
 int vc_check_declared(vc_ctx *ctx, const uint64_t *comp_off, uint64_t n_comp, const uint32_t *decls, uint32_t n_vars,
                       const uint64_t *body_off, const uint32_t *body, const uint32_t *body_idx, const uint32_t *lo,
                       const uint32_t *hi, uint32_t flags, vc_trace **out);
+
+/* Structured programs (Section 3.2: S ::= E x | rem(E x) | S; S' | While(c) S |
+ * If c S S' | Noop, c ::= isValid x | remIsValid x | x (+) y), run by the rules of
+ * Figure "Operational semantics of validity status" (valid / invalid / rem-valid /
+ * rem-invalid, Effect / Remote Effect, While-True / While-False, IF-True / IF-False).
+ * Each program has its own n_vars variables (1..64) starting at init (n_prog * n_vars
+ * status codes, program-major) or (V,I).
+ * words    : each program's syntax tree in prefix order, program p in words
+ *            [prog_off[p], prog_off[p + 1]): an effect is its event word (bits 30-31
+ *            zero); While is (1 << 30 | kind << 24 | x) followed by n (the body's length
+ *            in words) and the body; If is (2 << 30 | kind << 24 | x) followed by n, m and
+ *            the two branches (n and m words; an empty branch is Noop); kind 0 isValid x,
+ *            1 remIsValid x, 2 a choice.  At most 16 nested While / If.
+ * choice   : per program a word whose bit k mod 64 is the outcome of the program's k-th
+ *            choice evaluation (the paper leaves (+) to rules of its own that always
+ *            succeed), or NULL for all false.
+ * fuel     : reductions each program may take (an effect, or one While / If decision).
+ * A stuck effect is flagged and skipped, as in the plain method.  Host buffers, copied;
+ * the run is enqueued on the context's stream (vc_programs_run repeats it).  Malformed
+ * words give VC_EINVAL with the first one's index. */
+int vc_run_programs(vc_ctx *ctx, const uint64_t *prog_off, uint64_t n_prog, const uint32_t *words, uint32_t n_vars,
+                    const uint64_t *choice, const uint8_t *init, uint64_t fuel, vc_programs **out);
+int vc_programs_run(vc_programs *p);
+/* waits for the run; per program (any pointer may be NULL): reductions taken, effects
+ * run, stuck effects, the effect index of the first stuck one (the effect count if
+ * none), 1 if the program completed within its fuel, and its final statuses
+ * (n_prog * n_vars) */
+int vc_programs_read(vc_programs *p, uint64_t *steps, uint64_t *effects, uint64_t *stuck, uint64_t *first,
+                     uint8_t *done, uint8_t *final_status);
+int vc_programs_free(vc_programs *p);
 
 /* Re-runs the translation of a trace made by vc_translate (and its check if it was
  * created with VC_TRANSLATE_CHECK) on the same inputs, reusing every buffer.  Borrowed

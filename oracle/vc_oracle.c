@@ -972,8 +972,8 @@ int oracle_check_declared(const uint64_t *comp_off, uint64_t n_comp, const uint3
  * the effect index of the first stuck one (the effect count if none), 1 if it ran
  * to completion (0 if the fuel ran out), and the final statuses of its variables
  * (ids below n_vars, all starting at init or (V,I)).
- * Returns -1 (*bad = word index) for a malformed word or a length that leaves its
- * enclosing statement.
+ * Returns -1 (*bad = word index) for a malformed word, a length that leaves its
+ * enclosing statement, or statements nested more than 16 deep.
  * ------------------------------------------------------------------------------ */
 struct prog_run {
     const uint32_t *w;
@@ -1059,7 +1059,7 @@ static int prog_valid(const uint32_t *w, uint64_t a, uint64_t b, uint32_t n_vars
         uint32_t ck = (word >> 24) & 3u;
         uint64_t hdr = kind == 1 ? 2 : 3;
         if (kind == 3 || ck == 3 || ((word >> 26) & 15u) != 0 || (ck < 2 && x >= n_vars) || pc + hdr > b ||
-            depth >= 32) {
+            depth >= 16) {
             *bad = pc;
             return 0;
         }

@@ -61,6 +61,11 @@ def lib():
             "vc_trace_load_spaces": ([P, P, u64, u32, u32, P, u32, pP], i32),
             "vc_read_event_status16": ([P, P, u64], i32),
             "vc_check_declared": ([P, P, u64, P, u32, P, P, P, P, P, u32, pP], i32),
+            "vc_run_programs": ([P, P, u64, P, u32, P, P, u64, pP], i32),
+            "vc_programs_run": ([P], i32),
+            "vc_programs_read": ([P, P, P, P, P, P, P], i32),
+            "vc_programs_free": ([P], i32),
+            "vc_batch_info": ([P, P, P, P, P], i32),
             "vc_read_overlap_sets": ([P, P, P, u64, pu64], i32),
             "vc_translate": ([P, P, u64, P, u32, P, P, u32, pP], i32),
             "vc_check": ([P], i32),
@@ -337,6 +342,46 @@ def check_declared(ctx: Context, comp_off, decls, n_vars: int, body_off, body, i
     h = C.c_void_p()
     _check(lib().vc_check_declared(ctx.h, cp, n_comp, dp, n_vars, bp, yp, ip, lp, hp, flags, C.byref(h)))
     return Trace(ctx, h, (ck, dk, bk, yk, ik) if dev else ())
+
+
+class Programs:
+    """Structured programs run on the GPU (one lane per program)."""
+
+    def __init__(self, ctx: Context, prog_off, words, n_vars: int, choice=None, init=None, fuel: int = 1 << 12):
+        po = np.ascontiguousarray(prog_off, dtype=np.uint64)
+        w = np.ascontiguousarray(words, dtype=np.uint32)
+        ch = None if choice is None else np.ascontiguousarray(choice, dtype=np.uint64)
+        ini = None if init is None else np.ascontiguousarray(init, dtype=np.uint8)
+        self.n, self.n_vars, self.ctx = po.size - 1, n_vars, ctx
+        h = C.c_void_p()
+        _check(lib().vc_run_programs(ctx.h, po.ctypes.data_as(C.c_void_p), self.n, w.ctypes.data_as(C.c_void_p),
+                                     n_vars, None if ch is None else ch.ctypes.data_as(C.c_void_p),
+                                     None if ini is None else ini.ctypes.data_as(C.c_void_p), fuel, C.byref(h)))
+        self.h = h
+
+    def run(self):
+        _check(lib().vc_programs_run(self.h))
+
+    def read(self):
+        """(steps, effects, stuck, first, done, final[n, n_vars])"""
+        n = max(self.n, 1)
+        outs = [np.empty(n, np.uint64) for _ in range(4)]
+        done = np.empty(n, np.uint8)
+        fin = np.empty(n * self.n_vars, np.uint8)
+        _check(lib().vc_programs_read(self.h, *[o.ctypes.data_as(C.c_void_p) for o in outs],
+                                      done.ctypes.data_as(C.c_void_p), fin.ctypes.data_as(C.c_void_p)))
+        return tuple(o[:self.n] for o in outs) + (done[:self.n], fin[:self.n * self.n_vars].reshape(self.n, self.n_vars))
+
+    def free(self):
+        if self.h:
+            lib().vc_programs_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def batch_check(ctx: Context, traces):

@@ -37,6 +37,15 @@ def test_library_exports_every_declared_symbol():
         getattr(so, n)
 
 
+def test_binding_declares_every_signature():
+    """Every function of the header has its argument and result types declared in the
+    binding (an undeclared one would pass 64-bit arguments as C ints)."""
+    from paper_1910_11110_amd import vcheck as V
+    lib = V.lib()
+    missing = [n for n in declared_functions() if getattr(lib, n).argtypes is None]
+    assert not missing, f"no argtypes: {missing}"
+
+
 def test_null_arguments_rejected_without_gpu():
     from paper_1910_11110_amd import vcheck as V
     L = V.lib()
