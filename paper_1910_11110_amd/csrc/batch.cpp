@@ -34,11 +34,14 @@ struct BatchState {
     // host copies of the uploaded descriptor tables (alive until the next upload)
     std::vector<TraceDesc> h_desc;
     std::vector<uint64_t> h_ev_off, h_key_off;
+    std::vector<ChunkDesc> h_chunks;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     bool graph_ok = false;
     // device buffers
-    DevBuf desc, ev_off, key_off, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind;
+    DevBuf desc, ev_off, key_off, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind,
+        chunks;
+    uint64_t n_chunks = 0;
     Control *ctl = nullptr;
     uint64_t N = 0, K = 0, M = 0;
     uint32_t n_traces = 0;
@@ -48,6 +51,16 @@ struct BatchState {
 };
 
 namespace {
+
+// the chunks of every trace (BATCH_CHUNK events at most, never across traces)
+void build_chunks(BatchState &b, const std::vector<TraceDesc> &desc)
+{
+    b.h_chunks.clear();
+    for (uint32_t t = 0; t < (uint32_t)desc.size(); t++)
+        for (uint64_t a = 0; a < desc[t].n; a += BATCH_CHUNK)
+            b.h_chunks.push_back(ChunkDesc{a, t, (uint32_t)std::min<uint64_t>(BATCH_CHUNK, desc[t].n - a)});
+    b.n_chunks = b.h_chunks.size();
+}
 
 std::string tune_cache_path()
 {
@@ -152,11 +165,13 @@ int reserve_all(BatchState &b, uint32_t n)
     if ((r = devbuf_reserve(b.viol_all, 4 * (N ? N : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.items_a, 8 * (M ? M : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.items_b, 8 * (M ? M : 1))) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.cnt, 4 * (N ? N : 1))) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.pos, 8 * (N + 1))) != VC_OK) return r;
+    const uint64_t nc = b.n_chunks;
+    if ((r = devbuf_reserve(b.cnt, 4 * (nc ? nc : 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.pos, 8 * (nc + 1))) != VC_OK) return r;
+    if ((r = devbuf_reserve(b.chunks, sizeof(ChunkDesc) * (nc ? nc : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.ind, 8 * (n ? n : 1))) != VC_OK) return r;
     size_t sc = std::max({ sort_scratch_bytes(M), scan_scratch_bytes(M), compact_scratch_bytes(N),
-                           excl_scan_scratch_bytes(N) });
+                           excl_scan_scratch_bytes(nc) });
     if ((r = devbuf_reserve(b.scratch, sc)) != VC_OK) return r;
     if (!b.ctl) {
         hipError_t e = hipMalloc(&b.ctl, sizeof(Control));
@@ -174,10 +189,10 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
     launch_reset_control(b.ctl, s);
     launch_batch_reset(d, n, (unsigned long long *)b.ind.p, s);
     launch_batch_init(d, (const uint64_t *)b.key_off.p, n, b.K, (uint8_t *)b.init_all.p, (uint8_t *)b.fin_all.p, s);
-    launch_batch_count(d, (const uint64_t *)b.ev_off.p, n, b.N, (uint32_t *)b.cnt.p, s);
-    launch_excl_scan((uint32_t *)b.cnt.p, b.N, (uint64_t *)b.pos.p, nullptr, b.scratch.p, b.ctl->tickets[6], s);
-    launch_batch_emit(d, (const uint64_t *)b.ev_off.p, n, b.N, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M,
-                      s);
+    const ChunkDesc *ch = (const ChunkDesc *)b.chunks.p;
+    launch_batch_chunk_count(d, ch, b.n_chunks, (uint32_t *)b.cnt.p, s);
+    launch_excl_scan((uint32_t *)b.cnt.p, b.n_chunks, (uint64_t *)b.pos.p, nullptr, b.scratch.p, b.ctl->tickets[6], s);
+    launch_batch_chunk_emit(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M, s);
     uint64_t *sorted = sort_items((uint64_t *)b.items_a.p, (uint64_t *)b.items_b.p, b.M, (int)key_bits_for((uint32_t)b.K),
                                   b.scratch.p, b.ctl, s, &b.tune);
     launch_segscan(sorted, b.M, (const uint8_t *)b.init_all.p, (uint32_t)b.K, SCAN_STATUS, (uint8_t *)b.status_all.p,
@@ -272,7 +287,7 @@ void batch_free(BatchState *b)
         return;
     drop_graph(*b);
     for (DevBuf *d : { &b->desc, &b->ev_off, &b->key_off, &b->init_all, &b->fin_all, &b->status_all, &b->viol_all,
-                       &b->items_a, &b->items_b, &b->cnt, &b->pos, &b->scratch, &b->ind })
+                       &b->items_a, &b->items_b, &b->cnt, &b->pos, &b->scratch, &b->ind, &b->chunks })
         devbuf_free(*d);
     if (b->ctl)
         (void)hipFree(b->ctl);
@@ -307,6 +322,7 @@ int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M,
     b.K = K;
     b.M = M;
     b.n_traces = n;
+    build_chunks(b, desc);
     int r = reserve_all(b, n);
     if (r != VC_OK)
         return r;
@@ -321,7 +337,9 @@ int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M,
     if ((e = hipMemcpyAsync(b.desc.p, b.h_desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(b.ev_off.p, b.h_ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(b.key_off.p, b.h_key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess)
+        (e = hipMemcpyAsync(b.key_off.p, b.h_key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (b.n_chunks && (e = hipMemcpyAsync(b.chunks.p, b.h_chunks.data(), sizeof(ChunkDesc) * b.n_chunks,
+                                           hipMemcpyHostToDevice, s)) != hipSuccess))
         return vc_hip_fail(e, "hipMemcpyAsync(batch descriptors)");
     return VC_OK;
 }
@@ -406,13 +424,16 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
         b.K = K;
         b.M = M;
         b.n_traces = n;
+        build_chunks(b, desc);
         int r = reserve_all(b, n);
         if (r != VC_OK)
             return r;
         hipError_t e;
         if ((e = hipMemcpy(b.desc.p, desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(b.ev_off.p, ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(b.key_off.p, key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess)
+            (e = hipMemcpy(b.key_off.p, key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+            (b.n_chunks && (e = hipMemcpy(b.chunks.p, b.h_chunks.data(), sizeof(ChunkDesc) * b.n_chunks,
+                                          hipMemcpyHostToDevice)) != hipSuccess))
             return vc_hip_fail(e, "hipMemcpy(batch descriptors)");
         b.signature = sig;
         b.tuned = false;

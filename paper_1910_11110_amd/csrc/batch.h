@@ -22,13 +22,25 @@ struct TraceDesc {
     uint32_t *viol;
 };
 
+// a run of at most BATCH_CHUNK consecutive events of one trace: the unit of work of
+// the relocation passes (a chunk never straddles two traces)
+constexpr uint32_t BATCH_CHUNK = 4096;
+struct ChunkDesc {
+    uint64_t start; // first event, trace-relative
+    uint32_t trace;
+    uint32_t len;
+};
+// per chunk: induced items its events add (chunks of traces without arrays add none)
+void launch_batch_chunk_count(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, uint32_t *chunk_cnt,
+                              hipStream_t s);
+// items of every chunk at its events' global indices shifted by the induced items of
+// the chunks before it (chunk_pos) and of its own events before each one
+void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                             uint64_t *items, uint64_t cap, hipStream_t s);
+
 void launch_batch_reset(const TraceDesc *d, uint32_t n_traces, unsigned long long *ind, hipStream_t s);
 void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_traces, uint64_t K, uint8_t *init_all,
                        uint8_t *fin_all, hipStream_t s);
-void launch_batch_count(const TraceDesc *d, const uint64_t *ev_off, uint32_t n_traces, uint64_t N, uint32_t *cnt,
-                        hipStream_t s);
-void launch_batch_emit(const TraceDesc *d, const uint64_t *ev_off, uint32_t n_traces, uint64_t N, const uint64_t *pos,
-                       uint64_t *items, uint64_t cap, hipStream_t s);
 void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_t *status_all, const uint8_t *fin_all,
                              const uint32_t *viol_all, const Control *bctl, const unsigned long long *ind,
                              hipStream_t s);

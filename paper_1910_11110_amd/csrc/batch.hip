@@ -3,8 +3,9 @@
 // Each trace's ids are relocated to a private key range and its events to a private
 // index range, so one sort / scan / compaction over the concatenation evaluates every
 // trace as if it were alone: no state crosses a key range, and the segmented scan
-// restarts at every key.  A descriptor table tells each kernel which trace an event,
-// an id or a violation belongs to (binary search over the prefix arrays).
+// restarts at every key.  Events are relocated by chunks of one trace each (the chunk
+// table is built once per batch shape), so no event searches for its trace; ids search
+// the key prefix array once when the initial statuses are gathered.
 #include "batch.h"
 #include "device.h"
 #include "internal.h"
@@ -34,6 +35,21 @@ __device__ __forceinline__ void report_bad(Control *ctl, uint64_t i)
     atomicMin(w, (unsigned long long)i);
 }
 
+// exclusive sum over the workgroup (BLOCK threads)
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *s_tmp)
+{
+    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    const uint32_t inc = wave_scan_add(v, lane);
+    if (lane == WAVE - 1)
+        s_tmp[wave] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t w = 0; w < wave; w++)
+        off += s_tmp[w];
+    __syncthreads();
+    return off + inc - v;
+}
+
 __global__ void k_batch_reset(const TraceDesc *__restrict__ d, uint32_t n_traces, unsigned long long *ind)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,6 +58,7 @@ __global__ void k_batch_reset(const TraceDesc *__restrict__ d, uint32_t n_traces
     Control *c = d[i].ctl;
     c->err_index_lo = 0xFFFFFFFFu;
     c->err_index_hi = 0xFFFFFFFFu;
+    c->err_code = 0;
     c->n_viol = 0;
     c->n_induced_stuck = 0;
     ind[i] = 0;
@@ -60,48 +77,104 @@ __global__ void k_batch_init(const TraceDesc *__restrict__ d, const uint64_t *__
     }
 }
 
-__global__ void k_batch_count(const TraceDesc *__restrict__ d, const uint64_t *__restrict__ ev_off, uint32_t n_traces,
-                              uint64_t N, uint32_t *__restrict__ cnt)
+// ---- relocation by chunks (a chunk belongs to one trace: no search per event) ----
+constexpr int CH_ITEMS = BATCH_CHUNK / BLOCK; // events per thread
+static_assert(CH_ITEMS * BLOCK == (int)BATCH_CHUNK, "a chunk is one workgroup's events");
+
+__device__ __forceinline__ uint32_t induced_of(const TraceDesc &td, uint32_t e)
 {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
-        uint32_t t = find_range(ev_off, n_traces, g);
-        const TraceDesc &td = d[t];
-        uint64_t i = g - ev_off[t];
-        uint32_t e = td.events[i];
-        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
-        bool bad = (e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids;
-        if (bad)
-            report_bad(td.ctl, i);
-        cnt[g] = (!bad && op == OP_W && td.off) ? (uint32_t)(td.off[x + 1] - td.off[x]) : 0u;
+    const uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
+    const bool bad = (e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids;
+    return (!bad && op == OP_W) ? (uint32_t)(td.off[x + 1] - td.off[x]) : 0u;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_count(const TraceDesc *__restrict__ d,
+                                                             const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                             uint32_t *__restrict__ chunk_cnt)
+{
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const ChunkDesc cd = ch[c];
+        const TraceDesc &td = d[cd.trace];
+        if (!td.off) { // no arrays: no induced items (uniform per workgroup)
+            if (threadIdx.x == 0)
+                chunk_cnt[c] = 0;
+            continue;
+        }
+        uint32_t k = 0;
+        for (uint32_t j = threadIdx.x; j < cd.len; j += BLOCK)
+            k += induced_of(td, td.events[cd.start + j]);
+        const uint32_t ex = block_excl_sum(k, s_tmp);
+        if (threadIdx.x == BLOCK - 1)
+            chunk_cnt[c] = ex + k;
     }
 }
 
-__global__ void k_batch_emit(const TraceDesc *__restrict__ d, const uint64_t *__restrict__ ev_off, uint32_t n_traces,
-                             uint64_t N, const uint64_t *__restrict__ pos, uint64_t *__restrict__ items, uint64_t cap)
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_emit(const TraceDesc *__restrict__ d,
+                                                            const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                            const uint64_t *__restrict__ chunk_pos,
+                                                            uint64_t *__restrict__ items, uint64_t cap)
 {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
-        uint32_t t = find_range(ev_off, n_traces, g);
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const ChunkDesc cd = ch[c];
+        const uint32_t t = cd.trace;
         const TraceDesc &td = d[t];
-        uint64_t i = g - ev_off[t];
-        uint32_t e = td.events[i];
-        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
-        if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
-            x = 0;
-            op = OP_NOOP;
-        }
-        uint64_t p = g + pos[g];
-        uint64_t c = (op == OP_W && td.off) ? td.off[x + 1] - td.off[x] : 0;
-        if (p + c >= cap) {
-            report_bad(td.ctl, i);
+        const uint64_t shift = chunk_pos[c];
+        if (!td.off) {
+            // every item at its event's global index plus the chunk's shift; coalesced
+            for (uint32_t j = tid; j < cd.len; j += BLOCK) {
+                const uint64_t i = cd.start + j, g = td.ev_base + i;
+                const uint32_t e = td.events[i];
+                uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+                if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
+                    report_bad(td.ctl, i);
+                    x = 0;
+                    op = OP_NOOP;
+                }
+                const uint64_t p = g + shift;
+                if (p < cap)
+                    items[p] = make_item(td.key_base + x, fcode(op, side), (uint32_t)g);
+                else
+                    report_bad(td.ctl, i);
+            }
             continue;
         }
-        items[p] = make_item(td.key_base + x, fcode(op, side), (uint32_t)g);
-        if (c) {
-            uint64_t o = td.off[x];
-            for (uint64_t k = 0; k < c; k++)
-                items[p + 1 + k] = make_item(td.key_base + td.nbr[o + k], fcode(OP_RWIND, side), INDUCED_BIT | t);
+        // thread tid owns CH_ITEMS consecutive events; their induced counts are scanned
+        // over the workgroup to place each event's items
+        const uint32_t j0 = tid * CH_ITEMS;
+        uint32_t ev[CH_ITEMS], k = 0;
+#pragma unroll
+        for (int q = 0; q < CH_ITEMS; q++) {
+            const uint32_t j = j0 + q;
+            ev[q] = j < cd.len ? td.events[cd.start + j] : (OP_NOOP << 24);
+            k += j < cd.len ? induced_of(td, ev[q]) : 0u;
+        }
+        uint64_t p = td.ev_base + cd.start + j0 + shift + block_excl_sum(k, s_tmp);
+#pragma unroll
+        for (int q = 0; q < CH_ITEMS; q++) {
+            const uint32_t j = j0 + q;
+            if (j >= cd.len)
+                break;
+            const uint64_t i = cd.start + j, g = td.ev_base + i;
+            const uint32_t e = ev[q];
+            uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+            if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
+                report_bad(td.ctl, i);
+                x = 0;
+                op = OP_NOOP;
+            }
+            const uint64_t n_ind = op == OP_W ? td.off[x + 1] - td.off[x] : 0;
+            if (p + n_ind >= cap) {
+                report_bad(td.ctl, i);
+                continue;
+            }
+            items[p] = make_item(td.key_base + x, fcode(op, side), (uint32_t)g);
+            const uint64_t o = td.off[x];
+            for (uint64_t m = 0; m < n_ind; m++)
+                items[p + 1 + m] = make_item(td.key_base + td.nbr[o + m], fcode(OP_RWIND, side), INDUCED_BIT | t);
+            p += 1 + n_ind;
         }
     }
 }
@@ -174,24 +247,22 @@ void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_t
         }
 }
 
-void launch_batch_count(const TraceDesc *d, const uint64_t *ev_off, uint32_t n_traces, uint64_t N, uint32_t *cnt,
-                        hipStream_t s)
+void launch_batch_chunk_count(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, uint32_t *chunk_cnt,
+                              hipStream_t s)
 {
-    if (N)
-        {
-            ProfScope prof_(s, "batch_count");
-            k_batch_count<<<gridn(N, 256 * 8), 256, 0, s>>>(d, ev_off, n_traces, N, cnt);
-        }
+    if (n_chunks) {
+        ProfScope prof_(s, "batch_chunk_count");
+        k_batch_chunk_count<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_cnt);
+    }
 }
 
-void launch_batch_emit(const TraceDesc *d, const uint64_t *ev_off, uint32_t n_traces, uint64_t N, const uint64_t *pos,
-                       uint64_t *items, uint64_t cap, hipStream_t s)
+void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                             uint64_t *items, uint64_t cap, hipStream_t s)
 {
-    if (N)
-        {
-            ProfScope prof_(s, "batch_emit");
-            k_batch_emit<<<gridn(N, 256 * 8), 256, 0, s>>>(d, ev_off, n_traces, N, pos, items, cap);
-        }
+    if (n_chunks) {
+        ProfScope prof_(s, "batch_chunk_emit");
+        k_batch_chunk_emit<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, items, cap);
+    }
 }
 
 void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_t *status_all, const uint8_t *fin_all,
