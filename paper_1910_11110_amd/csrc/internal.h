@@ -86,6 +86,7 @@ void launch_excl_scan(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *t
 struct SortTuning {
     int max_bits = RADIX_BITS_MAX; // digit bits per pass (4..8)
     unsigned grid_cap = 0;         // persistent grid bound (0 = one workgroup per tile)
+    bool beside = false;           // runs beside another pipeline: tiles from one ticket counter
 };
 size_t sort_scratch_bytes(uint64_t n);
 uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *scratch, Control *ctl,
@@ -208,6 +209,20 @@ struct OverlapSets {
 int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n_arrays, int key_bits, OverlapSets *out,
                        Control *ctl, hipStream_t s);
 void free_overlap_sets(OverlapSets *o);
+// the sweep from a reusable workspace: its buffers grow and are never freed by the
+// sweep (release_overlap_work frees them); the sets are left in off / nbr of the
+// workspace (n + 1 offsets, *n_nbr neighbours).  Synchronizes the stream.
+struct OverlapWork {
+    void *a = nullptr, *b = nullptr, *fwd = nullptr, *pofs = nullptr, *scratch = nullptr, *pa = nullptr,
+         *pb = nullptr, *off = nullptr, *nbr = nullptr;
+    size_t a_cap = 0, b_cap = 0, fwd_cap = 0, pofs_cap = 0, scratch_cap = 0, pa_cap = 0, pb_cap = 0, off_cap = 0,
+           nbr_cap = 0;
+};
+// (beside: the sweep runs beside another pipeline, its sort and scan take tiles from
+// one ticket counter)
+int build_overlap_sets_into(const uint32_t *lo, const uint32_t *hi, uint32_t n, int key_bits, OverlapWork &w,
+                            uint64_t *n_nbr, Control *ctl, hipStream_t s, bool beside = false);
+void release_overlap_work(OverlapWork &w);
 // cnt[i] = number of induced events after event i
 void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, uint32_t *cnt,
                           uint64_t index_base, Control *ctl, hipStream_t s);

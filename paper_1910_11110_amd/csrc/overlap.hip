@@ -146,90 +146,111 @@ unsigned blocks_for(uint64_t n, unsigned per = BLOCK)
 
 } // namespace
 
-int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int key_bits, OverlapSets *out,
-                       Control *ctl, hipStream_t s)
+namespace {
+
+// grow-only device buffer of the sweep's workspace (never shrunk or freed here)
+bool grow(void *&p, size_t &cap, size_t bytes)
 {
-    *out = OverlapSets{};
-    hipError_t e;
-    uint64_t *a = nullptr, *b = nullptr, *pofs = nullptr;
-    uint32_t *fwd = nullptr;
-    void *scratch = nullptr;
-    uint64_t *pa = nullptr, *pb = nullptr;
-    int rc = 0;
-    uint64_t npairs = 0, m = 0;
-    size_t sc = std::max(sort_scratch_bytes(n), excl_scan_scratch_bytes(n));
-#define VC_TRY(x)                                                                                                   \
-    do {                                                                                                            \
-        if ((e = (x)) != hipSuccess) {                                                                              \
-            rc = -3;                                                                                                \
-            goto done;                                                                                              \
-        }                                                                                                           \
-    } while (0)
-    VC_TRY(hipMalloc(&out->off, (size_t)(n + 1) * 8));
-    if (n == 0) {
-        launch_fill_u64(out->off, 0, 1, s);
-        VC_TRY(hipMalloc(&out->nbr, 4));
-        goto done;
+    if (p && bytes <= cap)
+        return true;
+    if (p)
+        (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    const size_t want = bytes ? bytes : 256;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        p = nullptr;
+        return false;
     }
-    VC_TRY(hipMalloc(&a, (size_t)n * 8));
-    VC_TRY(hipMalloc(&b, (size_t)n * 8));
-    VC_TRY(hipMalloc(&fwd, (size_t)n * 4));
-    VC_TRY(hipMalloc(&pofs, (size_t)(n + 1) * 8));
-    VC_TRY(hipMalloc(&scratch, sc));
+    cap = want;
+    return true;
+}
+
+} // namespace
+
+int build_overlap_sets_into(const uint32_t *lo, const uint32_t *hi, uint32_t n, int key_bits, OverlapWork &w,
+                            uint64_t *n_nbr, Control *ctl, hipStream_t s, bool beside)
+{
+    SortTuning tune;
+    tune.beside = beside;
+    *n_nbr = 0;
+    if (!grow(w.off, w.off_cap, (size_t)(n + 1) * 8))
+        return -3;
+    if (n == 0) {
+        launch_fill_u64((uint64_t *)w.off, 0, 1, s);
+        return grow(w.nbr, w.nbr_cap, 4) && hipStreamSynchronize(s) == hipSuccess ? 0 : -3;
+    }
+    const size_t sc = std::max(sort_scratch_bytes(n), excl_scan_scratch_bytes(n));
+    if (!grow(w.a, w.a_cap, (size_t)n * 8) || !grow(w.b, w.b_cap, (size_t)n * 8) ||
+        !grow(w.fwd, w.fwd_cap, (size_t)n * 4) || !grow(w.pofs, w.pofs_cap, (size_t)(n + 1) * 8) ||
+        !grow(w.scratch, w.scratch_cap, sc))
+        return -3;
+    uint64_t *a = (uint64_t *)w.a, *b = (uint64_t *)w.b, *pofs = (uint64_t *)w.pofs;
+    uint32_t *fwd = (uint32_t *)w.fwd;
     {
         ProfScope prof_(s, "interval_items");
         k_interval_items<<<blocks_for(n), BLOCK, 0, s>>>(lo, hi, n, a, ctl);
     }
+    uint64_t *sorted = sort_items(a, b, n, key_bits, w.scratch, ctl, s, &tune);
     {
-        uint64_t *sorted = sort_items(a, b, n, key_bits, scratch, ctl, s);
-        {
-            ProfScope prof_(s, "sweep_count");
-            k_sweep_count<<<blocks_for(n), BLOCK, 0, s>>>(sorted, hi, n, fwd);
-        }
-        launch_excl_scan(fwd, n, pofs, nullptr, scratch, ctl->tickets[3], s);
-        VC_TRY(hipMemcpyAsync(&npairs, pofs + n, 8, hipMemcpyDeviceToHost, s));
-        VC_TRY(hipStreamSynchronize(s));
-        m = 2 * npairs;
-        out->n_nbr = m;
-        VC_TRY(hipMalloc(&out->nbr, (size_t)(m ? m : 1) * 4));
-        if (m) {
-            size_t sc2 = sort_scratch_bytes(m);
-            VC_TRY(hipMalloc(&pa, (size_t)m * 8));
-            VC_TRY(hipMalloc(&pb, (size_t)m * 8));
-            if (sc2 > sc) {
-                VC_TRY(hipFree(scratch));
-                scratch = nullptr;
-                VC_TRY(hipMalloc(&scratch, sc2));
-            }
-            {
-                ProfScope prof_(s, "sweep_pairs");
-                k_sweep_pairs<<<blocks_for(n), BLOCK, 0, s>>>(sorted, pofs, n, pa);
-            }
-            int idb = 32 - __builtin_clz(n > 1 ? n - 1 : 1);
-            uint64_t *by_nbr = sort_items(pa, pb, m, idb, scratch, ctl, s);
-            k_swap_key_payload<<<blocks_for(m), BLOCK, 0, s>>>(by_nbr, m);
-            uint64_t *other = by_nbr == pa ? pb : pa;
-            uint64_t *by_owner = sort_items(by_nbr, other, m, idb, scratch, ctl, s);
-            {
-                ProfScope prof_(s, "csr");
-                k_csr<<<blocks_for(m + 1), BLOCK, 0, s>>>(by_owner, m, n, out->off, out->nbr);
-            }
-        } else {
-            launch_fill_u64(out->off, 0, (size_t)n + 1, s);
-        }
-        VC_TRY(hipStreamSynchronize(s));
+        ProfScope prof_(s, "sweep_count");
+        k_sweep_count<<<blocks_for(n), BLOCK, 0, s>>>(sorted, hi, n, fwd);
     }
-done:
-#undef VC_TRY
-    if (a) (void)hipFree(a);
-    if (b) (void)hipFree(b);
-    if (fwd) (void)hipFree(fwd);
-    if (pofs) (void)hipFree(pofs);
-    if (scratch) (void)hipFree(scratch);
-    if (pa) (void)hipFree(pa);
-    if (pb) (void)hipFree(pb);
-    if (rc)
-        free_overlap_sets(out);
+    launch_excl_scan(fwd, n, pofs, nullptr, w.scratch, ctl->tickets[3], s, false, beside);
+    uint64_t npairs = 0;
+    if (hipMemcpyAsync(&npairs, pofs + n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return -3;
+    const uint64_t m = 2 * npairs;
+    *n_nbr = m;
+    if (!grow(w.nbr, w.nbr_cap, (size_t)(m ? m : 1) * 4))
+        return -3;
+    if (m) {
+        if (!grow(w.pa, w.pa_cap, (size_t)m * 8) || !grow(w.pb, w.pb_cap, (size_t)m * 8) ||
+            !grow(w.scratch, w.scratch_cap, std::max(sc, sort_scratch_bytes(m))))
+            return -3;
+        uint64_t *pa = (uint64_t *)w.pa, *pb = (uint64_t *)w.pb;
+        {
+            ProfScope prof_(s, "sweep_pairs");
+            k_sweep_pairs<<<blocks_for(n), BLOCK, 0, s>>>(sorted, pofs, n, pa);
+        }
+        const int idb = 32 - __builtin_clz(n > 1 ? n - 1 : 1);
+        uint64_t *by_nbr = sort_items(pa, pb, m, idb, w.scratch, ctl, s, &tune);
+        k_swap_key_payload<<<blocks_for(m), BLOCK, 0, s>>>(by_nbr, m);
+        uint64_t *other = by_nbr == pa ? pb : pa;
+        uint64_t *by_owner = sort_items(by_nbr, other, m, idb, w.scratch, ctl, s, &tune);
+        {
+            ProfScope prof_(s, "csr");
+            k_csr<<<blocks_for(m + 1), BLOCK, 0, s>>>(by_owner, m, n, (uint64_t *)w.off, (uint32_t *)w.nbr);
+        }
+    } else {
+        launch_fill_u64((uint64_t *)w.off, 0, (size_t)n + 1, s);
+    }
+    return hipStreamSynchronize(s) == hipSuccess ? 0 : -3;
+}
+
+void release_overlap_work(OverlapWork &w)
+{
+    for (void *p : {w.a, w.b, w.fwd, w.pofs, w.scratch, w.pa, w.pb, w.off, w.nbr})
+        if (p)
+            (void)hipFree(p);
+    w = OverlapWork{};
+}
+
+int build_overlap_sets(const uint32_t *lo, const uint32_t *hi, uint32_t n, int key_bits, OverlapSets *out,
+                       Control *ctl, hipStream_t s)
+{
+    *out = OverlapSets{};
+    OverlapWork w;
+    uint64_t m = 0;
+    const int rc = build_overlap_sets_into(lo, hi, n, key_bits, w, &m, ctl, s);
+    if (rc == 0) { // the result buffers become the sets'
+        out->off = (uint64_t *)w.off;
+        out->nbr = (uint32_t *)w.nbr;
+        out->n_nbr = m;
+        w.off = w.nbr = nullptr;
+    }
+    release_overlap_work(w);
     return rc;
 }
 

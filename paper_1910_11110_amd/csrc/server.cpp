@@ -65,6 +65,7 @@ struct Stream {
     uint32_t n_ids = 0;
     uint8_t *table = nullptr; // resident statuses
     OverlapSets sets{};
+    int table_cls = 0, off_cls = 0, nbr_cls = 0; // size classes of the pooled buffers
     bool has_arrays = false;
     uint64_t events_seen = 0; // events submitted so far
     std::deque<Chunk *> queue;
@@ -110,6 +111,43 @@ struct Pool {
     void put(void *p, int k) { free_list[k].push_back(p); }
 };
 
+// device buffers of streams (status tables, overlap sets) by power-of-two size class,
+// recycled when a stream closes: opening and closing streams frees no device memory
+struct BytePool {
+    std::map<int, std::vector<void *>> free_list;
+    static int cls(uint64_t bytes)
+    {
+        int k = 8;
+        while ((1ull << k) < bytes)
+            k++;
+        return k;
+    }
+    void *get(uint64_t bytes, int *out_cls)
+    {
+        const int k = cls(bytes);
+        *out_cls = k;
+        auto &fl = free_list[k];
+        if (!fl.empty()) {
+            void *p = fl.back();
+            fl.pop_back();
+            return p;
+        }
+        void *p = nullptr;
+        return hipMalloc(&p, 1ull << k) == hipSuccess ? p : nullptr;
+    }
+    void put(void *p, int k)
+    {
+        if (p)
+            free_list[k].push_back(p);
+    }
+    ~BytePool()
+    {
+        for (auto &kv : free_list)
+            for (void *p : kv.second)
+                (void)hipFree(p);
+    }
+};
+
 struct Slot {
     hipStream_t s = nullptr;        // copies of this slot's batch
     hipEvent_t done = nullptr;      // results copied back
@@ -138,6 +176,15 @@ struct vc_server {
     hipStream_t compute = nullptr; // kernels of both slots, in launch order
     std::string error;
     Pool *pool = nullptr;
+    // stream set-up and tear-down (callers' threads): its own stream, the interval
+    // sweep's reusable workspace, staging for intervals, and the pool of stream buffers
+    std::mutex open_mu;
+    hipStream_t open_s = nullptr;
+    OverlapWork ow;
+    Control *open_ctl = nullptr;
+    void *dlo = nullptr, *dhi = nullptr;
+    size_t div_cap = 0;
+    BytePool *bpool = nullptr;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -453,6 +500,13 @@ extern "C" int vc_server_create(vc_ctx *c, uint64_t budget, uint32_t max_batch_e
         }
         sl.b = batch_new();
     }
+    S->bpool = new BytePool();
+    if ((e = hipStreamCreateWithFlags(&S->open_s, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipMalloc(&S->open_ctl, sizeof(Control))) != hipSuccess) {
+        S->worker = std::thread(server_loop, S);
+        vc_server_destroy(S);
+        return vc_hip_fail(e, "server set-up stream");
+    }
     S->worker = std::thread(server_loop, S);
     *out = S;
     return VC_OK;
@@ -476,6 +530,12 @@ extern "C" int vc_server_destroy(vc_server *S)
         free_overlap_sets(&st->sets);
         delete st;
     }
+    release_overlap_work(S->ow);
+    if (S->dlo) (void)hipFree(S->dlo);
+    if (S->dhi) (void)hipFree(S->dhi);
+    if (S->open_ctl) (void)hipFree(S->open_ctl);
+    if (S->open_s) (void)hipStreamDestroy(S->open_s);
+    delete S->bpool;
     for (Slot &sl : S->slots) {
         batch_free(sl.b);
         (void)hipEventDestroy(sl.computed);
@@ -510,61 +570,98 @@ extern "C" int vc_stream_open(vc_server *S, uint32_t n_ids, const uint32_t *lo, 
             if (init[i] > 3)
                 return vc_fail(VC_EINVAL, "vc_stream_open: init %u at id %u is not a status code", init[i], i);
     (void)hipSetDevice(S->ctx->device);
+    std::vector<uint64_t> deg;
     Stream *st = new Stream();
     st->n_ids = n_ids;
-    hipError_t e;
-    if ((e = hipMalloc(&st->table, n_ids)) != hipSuccess) {
-        delete st;
-        return vc_hip_fail(e, "hipMalloc(stream table)");
-    }
-    std::vector<uint8_t> ini(n_ids, 1);
-    if (init)
-        memcpy(ini.data(), init, n_ids);
-    (void)hipMemcpy(st->table, ini.data(), n_ids, hipMemcpyHostToDevice);
-    std::vector<uint64_t> deg;
-    if (lo) {
-        // the stream's overlap sets, built once by the interval sweep
-        uint32_t maxlo = 0;
-        for (uint32_t i = 0; i < n_ids; i++) {
-            if (!(lo[i] < hi[i]) || hi[i] > (1u << 28)) {
-                (void)hipFree(st->table);
-                delete st;
-                return vc_fail(VC_EINVAL, "vc_stream_open: array %u is not a non-empty interval below 2^28", i);
+    {
+        // set-up on the server's own stream from pooled buffers: no device memory is
+        // freed (a free would wait for the whole device), and the batches running on the
+        // compute stream are not waited for.  The interval sweep runs beside them: its
+        // sort and scan take their tiles from one ticket counter (no two grouped-ticket
+        // grids ever run together; opens are serialized)
+        std::lock_guard<std::mutex> ok(S->open_mu);
+        hipStream_t s = S->open_s;
+        std::vector<uint8_t> ini(n_ids, 1);
+        if (init)
+            memcpy(ini.data(), init, n_ids);
+        st->table = (uint8_t *)S->bpool->get(n_ids, &st->table_cls);
+        hipError_t e = st->table ? hipMemcpyAsync(st->table, ini.data(), n_ids, hipMemcpyHostToDevice, s)
+                                 : hipErrorOutOfMemory;
+        int rc = e == hipSuccess ? 0 : -3;
+        if (rc == 0 && lo) {
+            // the stream's overlap sets, built once by the interval sweep
+            uint32_t maxlo = 0;
+            for (uint32_t i = 0; i < n_ids; i++) {
+                if (!(lo[i] < hi[i]) || hi[i] > (1u << 28)) {
+                    (void)hipStreamSynchronize(s);
+                    S->bpool->put(st->table, st->table_cls);
+                    delete st;
+                    return vc_fail(VC_EINVAL, "vc_stream_open: array %u is not a non-empty interval below 2^28", i);
+                }
+                maxlo = std::max(maxlo, lo[i]);
             }
-            maxlo = std::max(maxlo, lo[i]);
+            const size_t bytes = (size_t)n_ids * 4;
+            if (bytes > S->div_cap) {
+                (void)hipStreamSynchronize(s);
+                if (S->dlo) (void)hipFree(S->dlo);
+                if (S->dhi) (void)hipFree(S->dhi);
+                S->dlo = S->dhi = nullptr;
+                S->div_cap = 0;
+                if (hipMalloc(&S->dlo, bytes) == hipSuccess && hipMalloc(&S->dhi, bytes) == hipSuccess)
+                    S->div_cap = bytes;
+            }
+            uint64_t m = 0;
+            rc = S->div_cap >= bytes &&
+                         hipMemcpyAsync(S->dlo, lo, bytes, hipMemcpyHostToDevice, s) == hipSuccess &&
+                         hipMemcpyAsync(S->dhi, hi, bytes, hipMemcpyHostToDevice, s) == hipSuccess
+                     ? 0
+                     : -3;
+            if (rc == 0) {
+                launch_reset_control(S->open_ctl, s);
+                rc = build_overlap_sets_into((const uint32_t *)S->dlo, (const uint32_t *)S->dhi, n_ids,
+                                             maxlo ? 32 - __builtin_clz(maxlo) : 1, S->ow, &m, S->open_ctl, s, true);
+            }
+            if (rc == 0) {
+                st->sets.off = (uint64_t *)S->bpool->get((uint64_t)(n_ids + 1) * 8, &st->off_cls);
+                st->sets.nbr = (uint32_t *)S->bpool->get((m ? m : 1) * 4, &st->nbr_cls);
+                st->sets.n_nbr = m;
+                std::vector<uint64_t> off(n_ids + 1);
+                rc = st->sets.off && st->sets.nbr &&
+                             hipMemcpyAsync(st->sets.off, S->ow.off, (size_t)(n_ids + 1) * 8, hipMemcpyDeviceToDevice,
+                                            s) == hipSuccess &&
+                             (!m || hipMemcpyAsync(st->sets.nbr, S->ow.nbr, m * 4, hipMemcpyDeviceToDevice, s) ==
+                                        hipSuccess) &&
+                             hipMemcpyAsync(off.data(), S->ow.off, (size_t)(n_ids + 1) * 8, hipMemcpyDeviceToHost,
+                                            s) == hipSuccess &&
+                             hipStreamSynchronize(s) == hipSuccess
+                         ? 0
+                         : -3;
+                if (rc == 0) {
+                    st->has_arrays = true;
+                    deg.resize(n_ids);
+                    for (uint32_t i = 0; i < n_ids; i++)
+                        deg[i] = off[i + 1] - off[i];
+                }
+            }
         }
-        uint32_t *dlo = nullptr, *dhi = nullptr;
-        Control *ctl = nullptr;
-        hipStream_t s = nullptr;
-        (void)hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-        (void)hipMalloc(&dlo, n_ids * 4);
-        (void)hipMalloc(&dhi, n_ids * 4);
-        (void)hipMalloc(&ctl, sizeof(Control));
-        (void)hipMemcpy(dlo, lo, n_ids * 4, hipMemcpyHostToDevice);
-        (void)hipMemcpy(dhi, hi, n_ids * 4, hipMemcpyHostToDevice);
-        launch_reset_control(ctl, s);
-        int rc = build_overlap_sets(dlo, dhi, n_ids, maxlo ? 32 - __builtin_clz(maxlo) : 1, &st->sets, ctl, s);
-        std::vector<uint64_t> off(n_ids + 1);
-        if (rc == 0)
-            (void)hipMemcpy(off.data(), st->sets.off, (n_ids + 1) * 8, hipMemcpyDeviceToHost);
-        (void)hipFree(dlo);
-        (void)hipFree(dhi);
-        (void)hipFree(ctl);
-        (void)hipStreamDestroy(s);
+        if (rc == 0 && hipStreamSynchronize(s) != hipSuccess)
+            rc = -3;
         if (rc != 0) {
-            (void)hipFree(st->table);
+            (void)hipStreamSynchronize(s);
+            S->bpool->put(st->table, st->table_cls);
+            S->bpool->put(st->sets.off, st->off_cls);
+            S->bpool->put(st->sets.nbr, st->nbr_cls);
             delete st;
-            return vc_fail(VC_EDEVICE, "vc_stream_open: interval sweep failed");
+            return vc_fail(lo ? VC_EDEVICE : VC_ENOMEM, "vc_stream_open: %s",
+                           lo ? "interval sweep failed" : "status table");
         }
-        st->has_arrays = true;
-        deg.resize(n_ids);
-        for (uint32_t i = 0; i < n_ids; i++)
-            deg[i] = off[i + 1] - off[i];
     }
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->used + n_ids > S->budget) {
-        (void)hipFree(st->table);
-        free_overlap_sets(&st->sets);
+        std::lock_guard<std::mutex> ok(S->open_mu);
+        S->bpool->put(st->table, st->table_cls);
+        S->bpool->put(st->sets.off, st->off_cls);
+        S->bpool->put(st->sets.nbr, st->nbr_cls);
         delete st;
         return vc_fail(VC_EBUDGET, "vc_stream_open: the status table does not fit the budget");
     }
@@ -655,13 +752,23 @@ extern "C" int vc_stream_close(vc_server *S, uint64_t stream, uint8_t *final_out
     }
     (void)hipSetDevice(S->ctx->device);
     int rc = VC_OK;
-    if (final_out) {
-        hipError_t e = hipMemcpy(final_out, st->table, st->n_ids, hipMemcpyDeviceToHost);
-        if (e != hipSuccess)
-            rc = vc_hip_fail(e, "hipMemcpy(stream table)");
+    {
+        // the stream's last chunk has completed (its results were copied back): the table
+        // is final; its buffers go back to the pool
+        std::lock_guard<std::mutex> ok(S->open_mu);
+        if (final_out) {
+            hipError_t e = hipMemcpyAsync(final_out, st->table, st->n_ids, hipMemcpyDeviceToHost, S->open_s);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(S->open_s);
+            if (e != hipSuccess)
+                rc = vc_hip_fail(e, "copy of the stream table");
+        }
+        S->bpool->put(st->table, st->table_cls);
+        S->bpool->put(st->sets.off, st->off_cls);
+        S->bpool->put(st->sets.nbr, st->nbr_cls);
+        st->table = nullptr;
+        st->sets = OverlapSets{};
     }
-    (void)hipFree(st->table);
-    free_overlap_sets(&st->sets);
     {
         std::lock_guard<std::mutex> lk2(g_deg_mu);
         g_degrees.erase(stream);

@@ -176,7 +176,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp,
 __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict__ in, uint64_t *__restrict__ out,
                                                      uint64_t n, int shift, int bits,
                                                      const uint32_t *__restrict__ hist, uint64_t *__restrict__ lb,
-                                                     uint32_t *__restrict__ ticket, uint64_t ntiles)
+                                                     uint32_t *__restrict__ ticket, uint64_t ntiles, uint32_t groups)
 {
     __shared__ uint64_t s_items[SORT_TILE];
     __shared__ uint32_t s_cnt[BLOCK / WAVE][RADIX];
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(BLOCK) void k_sort_pass(const uint64_t *__restrict_
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / WAVE;
     const uint32_t dmask = (1u << bits) - 1u;
     for (;;) {
-    const uint32_t tile = take_ticket(ticket, &s_tile);
+    const uint32_t tile = take_ticket(ticket, &s_tile, groups);
     if (tile >= ntiles)
         break;
     const uint64_t base = (uint64_t)tile * SORT_TILE;
@@ -408,7 +408,8 @@ uint64_t *sort_items(uint64_t *a, uint64_t *b, uint64_t n, int key_bits, void *s
         unsigned grid = resident_grid((const void *)k_sort_pass, tiles, grid_cap);
         {
             ProfScope prof_(s, "sort_pass");
-            k_sort_pass<<<grid, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket, tiles);
+            k_sort_pass<<<grid, BLOCK, 0, s>>>(src, dst, n, p * bits, bits, sc->hist[p], lb, ticket, tiles,
+                                               tune && tune->beside ? 1u : TICKET_GROUPS);
         }
         uint64_t *t = src;
         src = dst;
