@@ -549,6 +549,8 @@ int enqueue_check(vc_trace *t, hipStream_t s)
     }
     if (t->dynamic)
         return dynamic_enqueue(t, s);
+    if (overlap_bucket_path(t))
+        return overlap_bucket_enqueue(t, s);
     uint64_t m = t->n;
     if (t->has_arrays) {
         m = overlap_combined_size(t);

@@ -129,6 +129,8 @@ int enqueue_check(vc_trace *t, hipStream_t s);
 
 // overlap (overlap_abi.cpp)
 int dynamic_enqueue(vc_trace *t, hipStream_t s);
+bool overlap_bucket_path(const vc_trace *t);
+int overlap_bucket_enqueue(vc_trace *t, hipStream_t s);
 uint64_t overlap_combined_size(vc_trace *t);
 void overlap_enqueue_items(vc_trace *t, uint64_t m, hipStream_t s);
 void overlap_release(vc_trace *t);

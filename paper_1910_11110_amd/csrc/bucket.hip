@@ -44,6 +44,21 @@ struct EventWords {
     __device__ static uint32_t arity(uint32_t, uint32_t) { return 0; }
 };
 
+// the combined stream of a trace over overlapping arrays: its events and, after every
+// write, the induced RW items (op 5) on the arrays it overlaps
+struct CombinedWords {
+    __device__ static bool ok(uint32_t w, uint32_t n_ids)
+    {
+        return (w >> 28) == 0 && ((w >> 24) & 7u) <= OP_RWIND && (w & 0xFFFFFFu) < n_ids;
+    }
+    __device__ static uint32_t key(uint32_t w, uint32_t n_ids) { return ok(w, n_ids) ? (w & 0xFFFFFFu) : 0u; }
+    __device__ static uint32_t fc(uint32_t w, uint32_t n_ids)
+    {
+        return ok(w, n_ids) ? fcode((w >> 24) & 7u, (w >> 27) & 1u) : fcode(OP_NOOP, 0);
+    }
+    __device__ static uint32_t arity(uint32_t, uint32_t) { return 0; }
+};
+
 // a declaration acts on its abstract variable: R = guarded transfer toward its side,
 // W and RW end with w on its side
 struct DeclWords {
@@ -1176,7 +1191,8 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     }
 }
 
-void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
+template <class SRC>
+static void bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
                          uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu,
                          const FillJob *fin_fill)
 {
@@ -1196,8 +1212,7 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     launch_prep(ctl, nullptr, jobs, nj, s);
     if (n == 0)
         return;
-    partition_and_scan<EventWords>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu, nullptr, 0,
-                                   true);
+    partition_and_scan<SRC>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu, nullptr, 0, true);
     if (L.nb == 1) {
         launch_compact(status, n, viol, L.fw, ctl, s, nullptr, nullptr, true);
         return;
@@ -1212,6 +1227,20 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
     launch_excl_scan(L.tcnt, L.ptiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan,
                      ctl->tickets[10], s, true);
     launch_flag_scatter(L.fw, L.offs, L.ptiles, BLOCK, viol, s);
+}
+
+void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, const uint8_t *init, uint8_t *status,
+                         uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl, hipStream_t s, int cu,
+                         const FillJob *fin_fill)
+{
+    bucket_check<EventWords>(events, n, n_ids, init, status, final_out, viol, scratch, ctl, s, cu, fin_fill);
+}
+
+void launch_bucket_check_combined(const uint32_t *words, uint64_t m, uint32_t n_ids, const uint8_t *init,
+                                  uint8_t *status, uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl,
+                                  hipStream_t s, int cu, const FillJob *fin_fill)
+{
+    bucket_check<CombinedWords>(words, m, n_ids, init, status, final_out, viol, scratch, ctl, s, cu, fin_fill);
 }
 
 void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre, uint8_t *final_out,

@@ -226,6 +226,17 @@ void release_overlap_work(OverlapWork &w);
 // cnt[i] = number of induced events after event i
 void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, uint32_t *cnt,
                           uint64_t index_base, Control *ctl, hipStream_t s);
+// the combined stream as 32-bit words (induced items are op 5) at i + pos[i]
+void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
+                          uint32_t *words, uint64_t cap, Control *ctl, hipStream_t s);
+// status[i] = comb[i + pos[i]]; ctl->n_induced_stuck = ctl->n_viol (the combined
+// stream's flagged items); after the primaries' compaction, launch_induced_finish
+// subtracts the flagged primaries
+void launch_extract_primary(const uint8_t *comb, const uint64_t *pos, uint64_t n, uint8_t *status, Control *ctl,
+                            hipStream_t s);
+void launch_induced_finish(Control *ctl, hipStream_t s);
+// folds src's error index and code into dst's
+void launch_merge_errors(Control *dst, const Control *src, hipStream_t s);
 // combined items at position i + pos[i] (pos = exclusive scan of cnt); cap = item capacity
 void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
                          uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, uint32_t trace_index,

@@ -138,6 +138,54 @@ __global__ void k_expand_emit(const uint32_t *__restrict__ ev, uint64_t n, uint3
     }
 }
 
+// the combined stream as 32-bit words: event i at i + pos[i], then one induced RW word
+// (op 5, the write's side) per array overlapping a write's array
+__global__ void k_expand_words(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_arrays,
+                               const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
+                               const uint64_t *__restrict__ pos, uint32_t *__restrict__ words, uint64_t cap,
+                               Control *ctl)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t e = ev[i];
+        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
+        if ((e >> 28) != 0 || op > OP_NOOP || x >= n_arrays) { // reported by the count pass
+            x = 0;
+            op = OP_NOOP;
+            side = 0;
+        }
+        const uint64_t p = i + pos[i];
+        const uint64_t c = op == OP_W ? off[x + 1] - off[x] : 0;
+        if (p + c >= cap) {
+            atomicMin(reinterpret_cast<unsigned long long *>(&ctl->err_index_lo), (unsigned long long)i);
+            continue;
+        }
+        words[p] = x | (op << 24) | (side << 27);
+        const uint32_t ind = (OP_RWIND << 24) | (side << 27);
+        const uint64_t o = off[x];
+        for (uint64_t k = 0; k < c; k++)
+            words[p + 1 + k] = nbr[o + k] | ind;
+    }
+}
+
+// primary status bytes from the combined stream's (event i sits at i + pos[i]); the
+// stuck induced items are the combined stream's flagged items less the primaries'
+__global__ void k_extract_primary(const uint8_t *__restrict__ comb, const uint64_t *__restrict__ pos, uint64_t n,
+                                  uint8_t *__restrict__ status, Control *ctl)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ctl->n_induced_stuck = ctl->n_viol; // the combined stream's flagged items
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        status[i] = comb[i + pos[i]];
+}
+
+__global__ void k_induced_finish(Control *ctl)
+{
+    if (threadIdx.x == 0)
+        ctl->n_induced_stuck -= ctl->n_viol; // less the flagged primaries
+}
+
 unsigned blocks_for(uint64_t n, unsigned per = BLOCK)
 {
     uint64_t b = ceil_div(n ? n : 1, per);
@@ -272,6 +320,37 @@ void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
             k_expand_count<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, cnt, index_base, ctl);
         }
 }
+
+void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
+                          uint32_t *words, uint64_t cap, Control *ctl, hipStream_t s)
+{
+    if (n) {
+        ProfScope prof_(s, "expand_words");
+        k_expand_words<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, pos, words, cap, ctl);
+    }
+}
+
+void launch_extract_primary(const uint8_t *comb, const uint64_t *pos, uint64_t n, uint8_t *status, Control *ctl,
+                            hipStream_t s)
+{
+    ProfScope prof_(s, "extract_primary");
+    k_extract_primary<<<blocks_for(n ? n : 1, BLOCK * 8), BLOCK, 0, s>>>(comb, pos, n, status, ctl);
+}
+
+void launch_induced_finish(Control *ctl, hipStream_t s) { k_induced_finish<<<1, 64, 0, s>>>(ctl); }
+
+namespace {
+__global__ void k_merge_errors(Control *dst, const Control *src)
+{
+    if (threadIdx.x == 0) {
+        const unsigned long long e = ((unsigned long long)src->err_index_hi << 32) | src->err_index_lo;
+        atomicMin(reinterpret_cast<unsigned long long *>(&dst->err_index_lo), e);
+        atomicOr(&dst->err_code, src->err_code);
+    }
+}
+} // namespace
+
+void launch_merge_errors(Control *dst, const Control *src, hipStream_t s) { k_merge_errors<<<1, 64, 0, s>>>(dst, src); }
 
 void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
                          uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, uint32_t trace_index,

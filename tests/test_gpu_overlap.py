@@ -90,3 +90,38 @@ def test_overlap_workload_full_size(ctx):
     lo, hi = gen.intervals(1 << 16, 0)
     e = gen.plain_events(1 << 24, 1 << 16, 0)
     assert_overlap(ctx, e, lo, hi, label="full 2^16 x 2^24")
+
+
+@pytest.mark.parametrize("n,n_arr,space,maxlen", [(1, 1, 64, 8), (4097, 50, 1024, 64), (300_001, 4000, 1 << 18, 512),
+                                                  (2_000_003, 1 << 16, 1 << 24, 4096)])
+def test_bucket_and_general_overlap_paths_agree(n, n_arr, space, maxlen):
+    """The bucket-engine route (the combined stream as 32-bit words) and the general sorted
+    route give identical bytes, violations and stuck induced counts, also from initial
+    (I,I) statuses, where induced acquisitions get stuck."""
+    import os
+
+    from paper_1910_11110_amd import vcheck as V
+    lo, hi = gen.intervals(n_arr, n + 1, space=space, max_len=maxlen)
+    e = gen.plain_events(n, n_arr, n + 2)
+    init = (np.arange(n_arr) % 4).astype(np.uint8)
+    outs = []
+    for general in (False, True):
+        if general:
+            os.environ["VC_GENERAL_PATH"] = "1"
+        try:
+            c = V.Context(0)
+            t = V.Trace.load(c, e, n_arr, init)
+            t.set_arrays(lo, hi)
+            t.check()
+            c.sync()
+            v = t.violations()
+            outs.append((t.status(), t.final(), v.indices, v.first, t.induced_stuck()))
+            t.free()
+            c.close()
+        finally:
+            os.environ.pop("VC_GENERAL_PATH", None)
+    a, b = outs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert a[3] == b[3] and a[4] == b[4]
+    ref = O.check_overlap(e, lo, hi, init)
+    assert np.array_equal(a[0], ref.status) and a[4] == ref.n_induced_stuck
