@@ -767,7 +767,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         // look-back on the dense per-id state of the bucket: 20 ids per 64-bit word as bit
         // planes; an inclusive word holds the statuses after the tile as constants.  A
         // round reads LB_WIN predecessors at once and folds them up to the nearest
-        // inclusive word.
+        // inclusive word, or until the folded functions are all constant (the tiles before
+        // then no longer matter).  A tile whose own functions are all constant publishes
+        // them at once as its inclusive word.
         uint64_t *tilew = lbv + (uint64_t)g * LB_WORDS;
         for (uint32_t wi = tid; wi < LB_WORDS; wi += BLOCK) {
             Planes agg{0, 0, 0};
@@ -788,7 +790,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                     st.y |= ((s0 >> 1) & 1u) << k;
                 }
             } else {
-                lb_store(&tilew[wi], LB_AGG | pl_pack(agg));
+                lb_store(&tilew[wi], (agg.t == PL_MASK ? LB_INC : LB_AGG) | pl_pack(agg));
                 const int64_t first_tile = (int64_t)g - ti;
                 int64_t t = (int64_t)g - 1;
                 Planes acc{0, 0, 0}; // composition of the aggregates walked so far
@@ -809,7 +811,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                             } else {
                                 acc = pl_compose(acc, pl_unpack(v[q]));
                                 adv++;
-                                if (fl == 2)
+                                if (fl == 2 || acc.t == PL_MASK)
                                     done = stop = true;
                             }
                         }
@@ -823,7 +825,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                 st = acc;
             }
             const Planes inc = pl_compose(agg, st);
-            lb_store(&tilew[wi], LB_INC | pl_pack(inc));
+            if (ti == 0 || agg.t != PL_MASK)
+                lb_store(&tilew[wi], LB_INC | pl_pack(inc));
             uint32_t *st4 = reinterpret_cast<uint32_t *>(s_state) + wi * 5;
 #pragma unroll
             for (int q = 0; q < 5; q++)
