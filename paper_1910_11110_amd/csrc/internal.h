@@ -226,14 +226,21 @@ void release_overlap_work(OverlapWork &w);
 // cnt[i] = number of induced events after event i
 void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, uint32_t *cnt,
                           uint64_t index_base, Control *ctl, hipStream_t s);
-// the combined stream as 32-bit words (induced items are op 5) at i + pos[i]
-void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
-                          uint32_t *words, uint64_t cap, Control *ctl, hipStream_t s);
-// status[i] = comb[i + pos[i]]; ctl->n_induced_stuck = ctl->n_viol (the combined
-// stream's flagged items); after the primaries' compaction, launch_induced_finish
-// subtracts the flagged primaries
-void launch_extract_primary(const uint8_t *comb, const uint64_t *pos, uint64_t n, uint8_t *status, Control *ctl,
-                            hipStream_t s);
+// the combined stream as 32-bit words (induced items are op 5), by tiles of events:
+// overlap_word_tiles(n) tiles; the count pass writes every tile's length (malformed
+// events reported with their index), their exclusive scan (tpos, n_tiles + 1 entries)
+// places the tiles, and the word pass writes the stream (cap words) and, when pos32 is
+// given, every event's position in it
+uint64_t overlap_word_tiles(uint64_t n);
+void launch_overlap_tile_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o,
+                               uint32_t *tcnt, Control *ctl, hipStream_t s);
+void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *tpos,
+                          uint32_t *words, uint64_t cap, uint32_t *pos32, Control *ctl, hipStream_t s);
+// status[i] = comb[pos32[i]] (m bytes of comb); ctl->n_induced_stuck = ctl->n_viol (the
+// combined stream's flagged items); after the primaries' compaction,
+// launch_induced_finish subtracts the flagged primaries
+void launch_extract_primary(const uint8_t *comb, const uint32_t *pos32, uint64_t n, uint64_t m, uint8_t *status,
+                            Control *ctl, hipStream_t s);
 void launch_induced_finish(Control *ctl, hipStream_t s);
 // folds src's error index and code into dst's
 void launch_merge_errors(Control *dst, const Control *src, hipStream_t s);

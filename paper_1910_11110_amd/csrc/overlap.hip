@@ -9,9 +9,11 @@
 //
 // Expansion: each write w_s x of a trace is followed, at its position, by one
 // induced read-write RW_s y for every y overlapping x (the extension O(M) of the
-// overlapping-array rules applied to the write's one-declaration component).  Counts
-// are scanned into positions, and the combined stream is written as sort items whose
-// payload is the primary event's index (INDUCED_BIT | trace index for induced items).
+// overlapping-array rules applied to the write's one-declaration component).  For the
+// general sorted path, per-event counts are scanned into positions and the combined
+// stream is written as sort items whose payload is the primary event's index
+// (INDUCED_BIT | trace index for induced items); for the bucket engine, it is written
+// as 32-bit words by tiles of events.
 #include <algorithm>
 
 #include "device.h"
@@ -138,46 +140,144 @@ __global__ void k_expand_emit(const uint32_t *__restrict__ ev, uint64_t n, uint3
     }
 }
 
-// the combined stream as 32-bit words: event i at i + pos[i], then one induced RW word
-// (op 5, the write's side) per array overlapping a write's array
-__global__ void k_expand_words(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_arrays,
-                               const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
-                               const uint64_t *__restrict__ pos, uint32_t *__restrict__ words, uint64_t cap,
-                               Control *ctl)
+// The combined stream as 32-bit words, by wave tiles of XTILE events: each event, then
+// one induced RW word (op 5, the write's side) per array overlapping a write's array.
+// A count pass gives every tile its length (the events plus their induced words), a scan
+// of those gives the tiles' output positions, and the word pass recomputes each event's
+// length, scans them inside the tile, and writes the tile's output 64 consecutive
+// words at a time: the lane of output slot q finds the event that covers it (the last
+// one starting at or before q) from a ballot of the event starts inside the 64 slots.
+constexpr int XW_PER = 8;                              // events per lane
+constexpr uint32_t XTILE = WAVE * XW_PER;              // events per wave tile
+constexpr uint32_t XWAVES = BLOCK / WAVE;
+
+// an event word as (array, op, side); a malformed event (reported by the count pass)
+// is a no-op on array 0
+__device__ __forceinline__ uint32_t clean_event(uint32_t e, uint32_t n_arrays, bool &bad)
 {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        uint32_t e = ev[i];
-        uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
-        if ((e >> 28) != 0 || op > OP_NOOP || x >= n_arrays) { // reported by the count pass
-            x = 0;
-            op = OP_NOOP;
-            side = 0;
+    const uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
+    bad = (e >> 28) != 0 || op > OP_NOOP || x >= n_arrays;
+    return bad ? (uint32_t)OP_NOOP << 24 : e;
+}
+
+// per wave tile: its output length.  A tile's length is below 2^31: every array has
+// fewer than n_arrays <= 2^22 neighbours and a tile has 2^9 events.
+__global__ __launch_bounds__(BLOCK) void k_xw_count(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_arrays,
+                                                    const uint64_t *__restrict__ off, uint64_t ntiles,
+                                                    uint32_t *__restrict__ tcnt, Control *ctl)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t t = (uint64_t)blockIdx.x * XWAVES + threadIdx.x / WAVE;
+    if (t >= ntiles)
+        return; // whole waves
+    const uint64_t i0 = t * XTILE;
+    uint32_t len = 0;
+#pragma unroll
+    for (int j = 0; j < XW_PER; j++) {
+        const uint64_t i = i0 + (uint64_t)j * WAVE + lane;
+        if (i < n) {
+            bool bad;
+            const uint32_t e = clean_event(ev[i], n_arrays, bad);
+            if (bad)
+                atomicMin(reinterpret_cast<unsigned long long *>(&ctl->err_index_lo), (unsigned long long)i);
+            const uint32_t x = e & 0xFFFFFFu;
+            len += 1u + (((e >> 24) & 7u) == OP_W ? (uint32_t)(off[x + 1] - off[x]) : 0u);
         }
-        const uint64_t p = i + pos[i];
-        const uint64_t c = op == OP_W ? off[x + 1] - off[x] : 0;
-        if (p + c >= cap) {
-            atomicMin(reinterpret_cast<unsigned long long *>(&ctl->err_index_lo), (unsigned long long)i);
-            continue;
+    }
+    const uint32_t total = wave_total_u32(len);
+    if (lane == 0)
+        tcnt[t] = total;
+}
+
+// the words of every wave tile from tpos[tile] on; pos32[i], when given, receives the
+// position of event i in the combined stream (below 2^32 on this path)
+__global__ __launch_bounds__(BLOCK) void k_xw_words(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_arrays,
+                                                    const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
+                                                    const uint64_t *__restrict__ tpos, uint64_t ntiles,
+                                                    uint32_t *__restrict__ words, uint64_t cap,
+                                                    uint32_t *__restrict__ pos32, Control *ctl)
+{
+    __shared__ uint32_t s_start[XWAVES][XTILE + 1]; // tile-relative start of every event
+    __shared__ uint32_t s_word[XWAVES][XTILE];      // its primary word
+    __shared__ uint64_t s_nb[XWAVES][XTILE];        // where its neighbour list starts
+    __shared__ uint32_t s_mark[XWAVES][WAVE];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
+    const uint64_t t = (uint64_t)blockIdx.x * XWAVES + wv;
+    if (t >= ntiles)
+        return; // whole waves; no workgroup barriers below
+    const uint64_t i0 = t * XTILE;
+    const uint64_t base = tpos[t];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < XW_PER; j++) {
+        const uint32_t k = j * WAVE + lane;
+        const uint64_t i = i0 + k;
+        uint32_t len = 0, w = 0;
+        uint64_t o = 0;
+        if (i < n) {
+            bool bad;
+            w = clean_event(ev[i], n_arrays, bad);
+            const uint32_t x = w & 0xFFFFFFu;
+            len = 1;
+            if (((w >> 24) & 7u) == OP_W) {
+                o = off[x];
+                len += (uint32_t)(off[x + 1] - o);
+            }
         }
-        words[p] = x | (op << 24) | (side << 27);
-        const uint32_t ind = (OP_RWIND << 24) | (side << 27);
-        const uint64_t o = off[x];
-        for (uint64_t k = 0; k < c; k++)
-            words[p + 1 + k] = nbr[o + k] | ind;
+        const uint32_t inc = wave_scan_add(len, lane);
+        const uint32_t st = carry + inc - len; // the tile's length for events past n
+        s_start[wv][k] = st;
+        s_word[wv][k] = w;
+        s_nb[wv][k] = o;
+        if (pos32 && i < n)
+            pos32[i] = (uint32_t)(base + st);
+        carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
+    }
+    const uint32_t total = carry;
+    if (lane == 0)
+        s_start[wv][XTILE] = total;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t ec = 0; // the event covering slot qc - 1 (event 0 for qc = 0: it starts at 0)
+    for (uint32_t qc = 0; qc < total; qc += WAVE) {
+        // events ec + 1 .. ec + 64 hold every start inside [qc, qc + 64): each event
+        // covers at least one slot
+        const uint32_t e = ec + 1 + lane;
+        const uint32_t st = e <= XTILE ? s_start[wv][e] : total;
+        s_mark[wv][lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (st < total && st < qc + WAVE)
+            s_mark[wv][st - qc] = 1; // st >= qc: ec covers qc - 1
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t heads = __ballot(s_mark[wv][lane] != 0);
+        const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
+        const uint32_t q = qc + lane;
+        if (q < total) {
+            const uint32_t k = q - s_start[wv][own];
+            const uint32_t w0 = s_word[wv][own];
+            const uint32_t w = k == 0 ? w0 : nbr[s_nb[wv][own] + k - 1] | ((uint32_t)OP_RWIND << 24) | (w0 & (1u << 27));
+            const uint64_t p = base + q;
+            if (p < cap)
+                words[p] = w;
+            else // the events changed since the stream was sized: refused, in bounds
+                atomicMin(reinterpret_cast<unsigned long long *>(&ctl->err_index_lo), (unsigned long long)(i0 + own));
+        }
+        ec += (uint32_t)__builtin_popcountll(heads);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// primary status bytes from the combined stream's (event i sits at i + pos[i]); the
-// stuck induced items are the combined stream's flagged items less the primaries'
-__global__ void k_extract_primary(const uint8_t *__restrict__ comb, const uint64_t *__restrict__ pos, uint64_t n,
-                                  uint8_t *__restrict__ status, Control *ctl)
+// primary status bytes from the combined stream (event i sits at pos32[i]); the stuck
+// induced items are the combined stream's flagged items less the primaries'
+__global__ void k_extract_primary(const uint8_t *__restrict__ comb, const uint32_t *__restrict__ pos32, uint64_t n,
+                                  uint64_t m, uint8_t *__restrict__ status, Control *ctl)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0)
         ctl->n_induced_stuck = ctl->n_viol; // the combined stream's flagged items
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        status[i] = comb[i + pos[i]];
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t p = pos32[i];
+        status[i] = comb[p < m ? p : m - 1];
+    }
 }
 
 __global__ void k_induced_finish(Control *ctl)
@@ -321,20 +421,35 @@ void launch_overlap_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
         }
 }
 
-void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *pos,
-                          uint32_t *words, uint64_t cap, Control *ctl, hipStream_t s)
+uint64_t overlap_word_tiles(uint64_t n) { return ceil_div(n, (uint64_t)XTILE); }
+
+void launch_overlap_tile_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o,
+                               uint32_t *tcnt, Control *ctl, hipStream_t s)
 {
-    if (n) {
-        ProfScope prof_(s, "expand_words");
-        k_expand_words<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, pos, words, cap, ctl);
-    }
+    const uint64_t ntiles = overlap_word_tiles(n);
+    if (!ntiles)
+        return;
+    ProfScope prof_(s, "xw_count");
+    k_xw_count<<<(unsigned)ceil_div(ntiles, (uint64_t)XWAVES), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, ntiles, tcnt,
+                                                                              ctl);
 }
 
-void launch_extract_primary(const uint8_t *comb, const uint64_t *pos, uint64_t n, uint8_t *status, Control *ctl,
-                            hipStream_t s)
+void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *tpos,
+                          uint32_t *words, uint64_t cap, uint32_t *pos32, Control *ctl, hipStream_t s)
+{
+    const uint64_t ntiles = overlap_word_tiles(n);
+    if (!ntiles)
+        return;
+    ProfScope prof_(s, "xw_words");
+    k_xw_words<<<(unsigned)ceil_div(ntiles, (uint64_t)XWAVES), BLOCK, 0, s>>>(ev, n, n_arrays, o->off, o->nbr, tpos,
+                                                                              ntiles, words, cap, pos32, ctl);
+}
+
+void launch_extract_primary(const uint8_t *comb, const uint32_t *pos32, uint64_t n, uint64_t m, uint8_t *status,
+                            Control *ctl, hipStream_t s)
 {
     ProfScope prof_(s, "extract_primary");
-    k_extract_primary<<<blocks_for(n ? n : 1, BLOCK * 8), BLOCK, 0, s>>>(comb, pos, n, status, ctl);
+    k_extract_primary<<<blocks_for(n ? n : 1, BLOCK * 8), BLOCK, 0, s>>>(comb, pos32, n, m ? m : 1, status, ctl);
 }
 
 void launch_induced_finish(Control *ctl, hipStream_t s) { k_induced_finish<<<1, 64, 0, s>>>(ctl); }

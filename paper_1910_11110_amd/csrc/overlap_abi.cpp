@@ -300,35 +300,37 @@ bool overlap_bucket_path(const vc_trace *t)
 // second control block (the bucket check resets the trace's)
 int overlap_bucket_enqueue(vc_trace *t, hipStream_t s)
 {
-    const uint64_t n = t->n, m = t->n + t->n_induced;
+    const uint64_t n = t->n, m = t->n + t->n_induced, ntiles = overlap_word_tiles(n);
     int r;
-    const size_t cnt_bytes = (n * 4 + 15) & ~size_t(15), pos_bytes = ((n + 1) * 8 + 255) & ~size_t(255);
-    if ((r = devbuf_reserve(t->aux, cnt_bytes + pos_bytes + CONTROL_BYTES)) != VC_OK ||
+    const size_t pos_bytes = (n * 4 + 255) & ~size_t(255), tcnt_bytes = (ntiles * 4 + 255) & ~size_t(255),
+                 tpos_bytes = ((ntiles + 1) * 8 + 255) & ~size_t(255);
+    if ((r = devbuf_reserve(t->aux, pos_bytes + tcnt_bytes + tpos_bytes + CONTROL_BYTES)) != VC_OK ||
         (r = devbuf_reserve(t->status, n ? n : 1)) != VC_OK ||
         (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
         (r = devbuf_reserve(t->viol, (n ? n : 1) * 4)) != VC_OK ||
         (r = devbuf_reserve(t->items_a, (m ? m : 1) * 4)) != VC_OK ||
         (r = devbuf_reserve(t->items_b, ((m + 255) & ~uint64_t(255)) + (m ? m : 1) * 4)) != VC_OK ||
-        (r = devbuf_reserve(t->scratch, std::max({bucket_scratch_bytes(m, t->n_ids), excl_scan_scratch_bytes(n),
+        (r = devbuf_reserve(t->scratch, std::max({bucket_scratch_bytes(m, t->n_ids), excl_scan_scratch_bytes(ntiles),
                                                   compact_scratch_bytes(n)}))) != VC_OK)
         return r;
-    uint32_t *cnt = (uint32_t *)t->aux.p;
-    uint64_t *pos = (uint64_t *)((char *)t->aux.p + cnt_bytes);
-    Control *xctl = (Control *)((char *)t->aux.p + cnt_bytes + pos_bytes);
+    uint32_t *pos32 = (uint32_t *)t->aux.p;
+    uint32_t *tcnt = (uint32_t *)((char *)t->aux.p + pos_bytes);
+    uint64_t *tpos = (uint64_t *)((char *)t->aux.p + pos_bytes + tcnt_bytes);
+    Control *xctl = (Control *)((char *)t->aux.p + pos_bytes + tcnt_bytes + tpos_bytes);
     uint32_t *words = (uint32_t *)t->items_a.p;
     uint8_t *comb = (uint8_t *)t->items_b.p;
     uint32_t *comb_viol = (uint32_t *)((char *)t->items_b.p + ((m + 255) & ~uint64_t(255)));
     launch_reset_control(xctl, s);
-    launch_overlap_count(t->events, n, t->n_ids, &t->sets, cnt, 0, xctl, s);
-    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, xctl->tickets[5], s);
-    launch_overlap_words(t->events, n, t->n_ids, &t->sets, pos, words, m, xctl, s);
+    launch_overlap_tile_count(t->events, n, t->n_ids, &t->sets, tcnt, xctl, s);
+    launch_excl_scan(tcnt, ntiles, tpos, nullptr, t->scratch.p, xctl->tickets[5], s);
+    launch_overlap_words(t->events, n, t->n_ids, &t->sets, tpos, words, m, pos32, xctl, s);
     uint8_t *fin = (uint8_t *)t->fin.p;
     const FillJob fill{fin, t->n_ids, 1};
     if (t->init)
         (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
     launch_bucket_check_combined(words, m, t->n_ids, t->init, comb, fin, comb_viol, t->scratch.p, t->ctl, s,
                                  t->ctx->cu_count, t->init ? nullptr : &fill);
-    launch_extract_primary(comb, pos, n, (uint8_t *)t->status.p, t->ctl, s);
+    launch_extract_primary(comb, pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
     launch_compact((uint8_t *)t->status.p, n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
     launch_induced_finish(t->ctl, s);
     launch_merge_errors(t->ctl, xctl, s);
