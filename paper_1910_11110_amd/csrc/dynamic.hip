@@ -70,76 +70,163 @@ __global__ void k_dyn_life(const uint32_t *__restrict__ ev, uint64_t n, uint32_t
     }
 }
 
-// items each event contributes: itself, a probe on its mother (a partial vector's
-// create) and one induced RW per live neighbour (a write); malformed words and
-// liveness errors are reported at their index (the smallest one is the first error of
-// a sequential reading)
-__global__ void k_dyn_count(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
-                            const uint32_t *__restrict__ mother, const uint32_t *__restrict__ cpos,
-                            const uint32_t *__restrict__ dpos, const uint64_t *__restrict__ off,
-                            const uint32_t *__restrict__ nbr, uint32_t *__restrict__ cnt, Control *ctl)
+// lifetime of every neighbour entry of the overlap CSR: (create, destroy) position of
+// nbr[j], so that the candidates of a write read their neighbours' lifetimes in order
+// instead of gathering them
+__global__ void k_dyn_nbr_life(const uint32_t *__restrict__ nbr, uint64_t n_nbr, const uint32_t *__restrict__ cpos,
+                               const uint32_t *__restrict__ dpos, uint2 *__restrict__ life)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
-        const uint32_t e = ev[t], op = (e >> 24) & 7u, x = e & 0xFFFFFFu;
-        uint32_t k = 1;
-        bool bad = !word_ok(e, n_ids);
-        if (!bad) {
-            if (op == OP_CREATE) {
-                const uint32_t m = mother[x];
-                bad = cpos[x] != (uint32_t)t || (m != NO_MOTHER && !live_at(cpos, dpos, m, t));
-                k += m != NO_MOTHER ? 1u : 0u;
-            } else if (op == OP_DESTROY) {
-                bad = dpos[x] != (uint32_t)t || !(cpos[x] == NO_POS || cpos[x] < t);
-            } else {
-                bad = !live_at(cpos, dpos, x, t);
-                if (!bad && op == OP_W)
-                    for (uint64_t j = off[x]; j < off[x + 1]; j++)
-                        k += live_at(cpos, dpos, nbr[j], t) ? 1u : 0u;
-            }
-        }
-        if (bad) {
-            report_bad(ctl, t);
-            k = 1;
-        }
-        cnt[t] = k;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_nbr; j += stride) {
+        const uint32_t y = nbr[j];
+        life[j] = make_uint2(cpos[y], dpos[y]);
     }
 }
 
-// the combined items at their positions (pos = exclusive scan of the counts); probes
-// carry payload n + t, induced items INDUCED_BIT
-__global__ void k_dyn_emit(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
-                           const uint32_t *__restrict__ mother, const uint32_t *__restrict__ cpos,
-                           const uint32_t *__restrict__ dpos, const uint64_t *__restrict__ off,
-                           const uint32_t *__restrict__ nbr, const uint64_t *__restrict__ pos,
-                           uint64_t *__restrict__ items, uint64_t cap, Control *ctl)
+// The combined items by wave tiles of DTILE events.  Each event has a run of candidate
+// items: itself, a probe on its mother (a partial vector's create) and, at a write, one
+// candidate per neighbour of its array; a neighbour's candidate becomes an induced RW
+// item when the neighbour is live at the write.  The candidates of a tile are walked
+// 64 consecutive ones at a time (the lane of a candidate finds its event from a ballot
+// of the event starts among the 64), and the items kept are compacted in order by a
+// ballot.  The count pass gives every tile its number of items; the emit pass, with
+// the tiles' scanned positions, writes them.
+constexpr int D_PER = 8;                   // events per lane
+constexpr uint32_t DTILE = WAVE * D_PER;   // events per wave tile
+constexpr uint32_t DWAVES = BLOCK / WAVE;
+
+// an event's candidate run and its checks: malformed words and liveness errors are
+// reported at their index (the smallest one is the first error of a sequential
+// reading) and keep only the event itself (a malformed word as a no-op on array 0)
+__device__ __forceinline__ uint32_t dyn_event(uint32_t e, uint64_t t, uint32_t n_ids, const uint32_t *mother,
+                                              const uint32_t *cpos, const uint32_t *dpos, const uint64_t *off,
+                                              bool report, Control *ctl, uint32_t &w, uint64_t &o)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
-        const uint32_t e = ev[t];
-        uint32_t op = (e >> 24) & 7u, x = e & 0xFFFFFFu, side = (e >> 27) & 1u;
-        const uint64_t p = pos[t], q = pos[t + 1];
-        if (q > cap || q < p + 1) {
-            report_bad(ctl, t); // the events changed since the items were sized
-            continue;
-        }
-        if (!word_ok(e, n_ids)) { // reported by the count pass; a harmless item
-            x = 0;
-            op = OP_NOOP;
-            side = 0;
-        }
-        const uint32_t fc = op >= OP_CREATE ? fcode(OP_NOOP, 0) : fcode(op, side);
-        items[p] = make_item(x, fc, (uint32_t)t);
-        uint64_t o = p + 1;
-        if (op == OP_CREATE && mother[x] != NO_MOTHER && o < q)
-            items[o++] = make_item(mother[x], fcode(OP_NOOP, 0), (uint32_t)(n + t));
-        if (op == OP_W)
-            for (uint64_t j = off[x]; j < off[x + 1] && o < q; j++)
-                if (live_at(cpos, dpos, nbr[j], t))
-                    items[o++] = make_item(nbr[j], fcode(OP_RWIND, side), INDUCED_BIT);
-        while (o < q) // only when the count pass saw other events: identity items
-            items[o++] = make_item(x, fcode(OP_NOOP, 0), INDUCED_BIT);
+    const uint32_t op = (e >> 24) & 7u, x = e & 0xFFFFFFu;
+    w = e;
+    o = 0;
+    if (!word_ok(e, n_ids)) {
+        if (report)
+            report_bad(ctl, t);
+        w = (uint32_t)OP_NOOP << 24;
+        return 1;
     }
+    bool bad;
+    uint32_t len = 1;
+    if (op == OP_CREATE) {
+        const uint32_t m = mother[x];
+        bad = cpos[x] != (uint32_t)t || (m != NO_MOTHER && !live_at(cpos, dpos, m, t));
+        len += m != NO_MOTHER ? 1u : 0u;
+    } else if (op == OP_DESTROY) {
+        bad = dpos[x] != (uint32_t)t || !(cpos[x] == NO_POS || cpos[x] < t);
+    } else {
+        bad = !live_at(cpos, dpos, x, t);
+        if (!bad && op == OP_W) {
+            o = off[x];
+            len += (uint32_t)(off[x + 1] - o);
+        }
+    }
+    if (bad) {
+        if (report)
+            report_bad(ctl, t);
+        return 1;
+    }
+    return len;
+}
+
+// EMIT = false: tcnt[tile] = the tile's items; EMIT = true: the items at tpos[tile] on
+// (cap items; probes carry payload n + t, induced items INDUCED_BIT)
+template <bool EMIT>
+__global__ __launch_bounds__(BLOCK) void k_dyn_tiles(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
+                                                     const uint32_t *__restrict__ mother,
+                                                     const uint32_t *__restrict__ cpos,
+                                                     const uint32_t *__restrict__ dpos,
+                                                     const uint64_t *__restrict__ off,
+                                                     const uint32_t *__restrict__ nbr,
+                                                     const uint2 *__restrict__ life, uint64_t ntiles,
+                                                     uint32_t *__restrict__ tcnt, const uint64_t *__restrict__ tpos,
+                                                     uint64_t *__restrict__ items, uint64_t cap, Control *ctl)
+{
+    __shared__ uint32_t s_start[DWAVES][DTILE + 1];
+    __shared__ uint32_t s_word[DWAVES][DTILE];
+    __shared__ uint64_t s_nb[DWAVES][DTILE];
+    __shared__ uint32_t s_mark[DWAVES][WAVE];
+    const uint32_t lane = lane_id(), wv = threadIdx.x / WAVE;
+    const uint64_t tile = (uint64_t)blockIdx.x * DWAVES + wv;
+    if (tile >= ntiles)
+        return; // whole waves; no workgroup barriers below
+    const uint64_t i0 = tile * DTILE;
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < D_PER; j++) {
+        const uint32_t k = j * WAVE + lane;
+        const uint64_t t = i0 + k;
+        uint32_t len = 0, w = 0;
+        uint64_t o = 0;
+        if (t < n)
+            len = dyn_event(ev[t], t, n_ids, mother, cpos, dpos, off, !EMIT, ctl, w, o);
+        const uint32_t inc = wave_scan_add(len, lane);
+        s_start[wv][k] = carry + inc - len;
+        s_word[wv][k] = w;
+        s_nb[wv][k] = o;
+        carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
+    }
+    const uint32_t total = carry; // candidates of the tile (below 2^31: fewer than 2^22 neighbours each)
+    if (lane == 0)
+        s_start[wv][DTILE] = total;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t base = EMIT ? tpos[tile] : 0;
+    uint32_t kept = 0;
+    uint32_t ec = 0; // the event covering candidate qc - 1 (event 0 for qc = 0)
+    for (uint32_t qc = 0; qc < total; qc += WAVE) {
+        // events ec + 1 .. ec + 64 hold every start inside [qc, qc + 64)
+        const uint32_t e = ec + 1 + lane;
+        const uint32_t st = e <= DTILE ? s_start[wv][e] : total;
+        s_mark[wv][lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (st < total && st < qc + WAVE)
+            s_mark[wv][st - qc] = 1;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t heads = __ballot(s_mark[wv][lane] != 0);
+        const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
+        const uint32_t q = qc + lane;
+        bool keep = false;
+        uint64_t item = 0;
+        if (q < total) {
+            const uint32_t k = q - s_start[wv][own];
+            const uint32_t w = s_word[wv][own], op = (w >> 24) & 7u, x = w & 0xFFFFFFu, side = (w >> 27) & 1u;
+            const uint64_t t = i0 + own;
+            keep = true;
+            if (k == 0) {
+                if (EMIT)
+                    item = make_item(x, op >= OP_CREATE ? fcode(OP_NOOP, 0) : fcode(op, side), (uint32_t)t);
+            } else if (op == OP_CREATE) {
+                if (EMIT)
+                    item = make_item(mother[x], fcode(OP_NOOP, 0), (uint32_t)(n + t));
+            } else {
+                const uint64_t j = s_nb[wv][own] + k - 1;
+                const uint2 lf = life[j];
+                keep = (lf.x == NO_POS || lf.x < t) && (lf.y == NO_POS || t < lf.y);
+                if (EMIT)
+                    item = make_item(nbr[j], fcode(OP_RWIND, side), INDUCED_BIT);
+            }
+        }
+        const uint64_t km = __ballot(keep);
+        if (EMIT && keep) {
+            const uint64_t p = base + kept + mask_rank(km);
+            if (p < cap)
+                items[p] = item;
+            else // the events changed since the items were sized: refused, in bounds
+                report_bad(ctl, i0 + own);
+        }
+        kept += (uint32_t)__builtin_popcountll(km);
+        ec += (uint32_t)__builtin_popcountll(heads);
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (!EMIT && lane == 0)
+        tcnt[tile] = kept;
+    if (EMIT && lane == 0 && base + kept != tpos[tile + 1])
+        report_bad(ctl, i0); // the events changed since the items were sized
 }
 
 // initial statuses of the second scan: a created partial vector starts at the status
@@ -179,23 +266,33 @@ void launch_dyn_life(const uint32_t *ev, uint64_t n, uint32_t n_ids, uint32_t *c
     }
 }
 
+uint64_t dyn_tiles(uint64_t n) { return ceil_div(n, (uint64_t)DTILE); }
+
 void launch_dyn_count(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
-                      const uint32_t *dpos, const OverlapSets *o, uint32_t *cnt, Control *ctl, hipStream_t s)
+                      const uint32_t *dpos, const OverlapSets *o, uint2 *life, uint32_t *tcnt, Control *ctl,
+                      hipStream_t s)
 {
-    if (n) {
+    if (o->n_nbr) {
+        ProfScope p(s, "dyn_nbr_life");
+        k_dyn_nbr_life<<<grid_of(o->n_nbr), BLOCK, 0, s>>>(o->nbr, o->n_nbr, cpos, dpos, life);
+    }
+    const uint64_t ntiles = dyn_tiles(n);
+    if (ntiles) {
         ProfScope p(s, "dyn_count");
-        k_dyn_count<<<grid_of(n), BLOCK, 0, s>>>(ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, cnt, ctl);
+        k_dyn_tiles<false><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
+            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, tcnt, nullptr, nullptr, 0, ctl);
     }
 }
 
 void launch_dyn_emit(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
-                     const uint32_t *dpos, const OverlapSets *o, const uint64_t *pos, uint64_t *items, uint64_t cap,
-                     Control *ctl, hipStream_t s)
+                     const uint32_t *dpos, const OverlapSets *o, const uint2 *life, const uint64_t *tpos,
+                     uint64_t *items, uint64_t cap, Control *ctl, hipStream_t s)
 {
-    if (n) {
+    const uint64_t ntiles = dyn_tiles(n);
+    if (ntiles) {
         ProfScope p(s, "dyn_emit");
-        k_dyn_emit<<<grid_of(n), BLOCK, 0, s>>>(ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, pos, items, cap,
-                                                ctl);
+        k_dyn_tiles<true><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
+            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, nullptr, tpos, items, cap, ctl);
     }
 }
 

@@ -175,13 +175,19 @@ void launch_translate_emit_fused_dev(const uint64_t *comp_off, uint64_t n_comp, 
 // lifetimes: first create / destroy position of every array (NO_POS if none)
 void launch_dyn_life(const uint32_t *ev, uint64_t n, uint32_t n_ids, uint32_t *cpos, uint32_t *dpos, hipStream_t s);
 struct OverlapSets;
-// per event: items it contributes (itself, a probe on its mother at a create, one
-// induced RW per live neighbour at a write); errors to ctl's error index
+// the combined items (each event, a probe on its mother at a create, one induced RW
+// per live neighbour at a write) by tiles of events, dyn_tiles(n) of them: the count
+// pass writes every tile's number of items (errors to ctl's error index), the emit pass
+// writes the items at the tiles' positions (tpos: exclusive scan of the counts,
+// dyn_tiles(n) + 1 entries), cap items at most.  The count pass first writes `life`
+// (one (create, destroy) pair per entry of the overlap CSR), which the emit pass reads.
+uint64_t dyn_tiles(uint64_t n);
 void launch_dyn_count(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
-                      const uint32_t *dpos, const OverlapSets *o, uint32_t *cnt, Control *ctl, hipStream_t s);
+                      const uint32_t *dpos, const OverlapSets *o, uint2 *life, uint32_t *tcnt, Control *ctl,
+                      hipStream_t s);
 void launch_dyn_emit(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
-                     const uint32_t *dpos, const OverlapSets *o, const uint64_t *pos, uint64_t *items, uint64_t cap,
-                     Control *ctl, hipStream_t s);
+                     const uint32_t *dpos, const OverlapSets *o, const uint2 *life, const uint64_t *tpos,
+                     uint64_t *items, uint64_t cap, Control *ctl, hipStream_t s);
 // initial statuses of the second scan (inherited by created partial vectors) into
 // init2 and fin
 void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint8_t *probe_pre, uint64_t n,

@@ -128,10 +128,11 @@ constexpr uint32_t NO_MOTHER = 0xFFFFFFFFu;
 struct DynLayout {
     uint32_t *cpos, *dpos;
     uint8_t *init2, *pre;
+    uint2 *life;
     size_t bytes;
 };
 
-DynLayout dyn_layout(void *base, uint64_t n, uint32_t n_ids)
+DynLayout dyn_layout(void *base, uint64_t n, uint32_t n_ids, uint64_t n_nbr)
 {
     char *p = (char *)base;
     size_t off = 0;
@@ -145,25 +146,28 @@ DynLayout dyn_layout(void *base, uint64_t n, uint32_t n_ids)
     L.dpos = (uint32_t *)take((size_t)(n_ids ? n_ids : 1) * 4);
     L.init2 = (uint8_t *)take(n_ids ? n_ids : 1);
     L.pre = (uint8_t *)take(2 * n + 1);
+    L.life = (uint2 *)take((size_t)(n_nbr ? n_nbr : 1) * sizeof(uint2));
     L.bytes = off;
     return L;
 }
 
-// lifetimes, item counts and their scan (cnt and pos in t->aux), on the stream
+// the tiles' item positions in t->aux (after their counts)
+uint64_t *dyn_tile_pos(vc_trace *t) { return (uint64_t *)((char *)t->aux.p + ((dyn_tiles(t->n) * 4 + 255) & ~255ull)); }
+
+// lifetimes, item counts per tile of events and their scan (in t->aux), on the stream
 int dyn_count_items(vc_trace *t, hipStream_t s)
 {
     int r;
-    const uint64_t n = t->n;
-    if ((r = devbuf_reserve(t->aux, n * 4 + (n + 1) * 8 + 16)) != VC_OK ||
-        (r = devbuf_reserve(t->scratch, std::max(t->scratch.bytes, excl_scan_scratch_bytes(n)))) != VC_OK ||
-        (r = devbuf_reserve(t->dyn, dyn_layout(nullptr, n, t->n_ids).bytes)) != VC_OK)
+    const uint64_t n = t->n, ntiles = dyn_tiles(n);
+    if ((r = devbuf_reserve(t->aux, ((ntiles * 4 + 255) & ~255ull) + (ntiles + 1) * 8)) != VC_OK ||
+        (r = devbuf_reserve(t->scratch, std::max(t->scratch.bytes, excl_scan_scratch_bytes(ntiles)))) != VC_OK ||
+        (r = devbuf_reserve(t->dyn, dyn_layout(nullptr, n, t->n_ids, t->sets.n_nbr).bytes)) != VC_OK)
         return r;
-    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids);
-    uint32_t *cnt = (uint32_t *)t->aux.p;
-    uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
+    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids, t->sets.n_nbr);
+    uint32_t *tcnt = (uint32_t *)t->aux.p;
     launch_dyn_life(t->events, n, t->n_ids, L.cpos, L.dpos, s);
-    launch_dyn_count(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, cnt, t->ctl, s);
-    launch_excl_scan(cnt, n, pos, nullptr, t->scratch.p, t->ctl->tickets[5], s);
+    launch_dyn_count(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, tcnt, t->ctl, s);
+    launch_excl_scan(tcnt, ntiles, dyn_tile_pos(t), nullptr, t->scratch.p, t->ctl->tickets[5], s);
     return VC_OK;
 }
 
@@ -176,10 +180,9 @@ int dyn_size(vc_trace *t)
     int r = dyn_count_items(t, s);
     if (r != VC_OK)
         return r;
-    uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
     uint64_t total = 0;
     Control h;
-    hipError_t e = hipMemcpyAsync(&total, pos + n, 8, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(&total, dyn_tile_pos(t) + dyn_tiles(n), 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(&h, t->ctl, CONTROL_HEADER, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
@@ -254,10 +257,9 @@ int dynamic_enqueue(vc_trace *t, hipStream_t s)
     launch_reset_control(t->ctl, s);
     if ((r = dyn_count_items(t, s)) != VC_OK)
         return r;
-    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids);
-    uint64_t *pos = (uint64_t *)((char *)t->aux.p + ((n * 4 + 15) & ~15ull));
-    launch_dyn_emit(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, pos, (uint64_t *)t->items_a.p, m,
-                    t->ctl, s);
+    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids, t->sets.n_nbr);
+    launch_dyn_emit(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, dyn_tile_pos(t),
+                    (uint64_t *)t->items_a.p, m, t->ctl, s);
     uint64_t *sorted = sort_items((uint64_t *)t->items_a.p, (uint64_t *)t->items_b.p, m,
                                   (int)key_bits_for(t->n_ids), t->scratch.p, t->ctl, s);
     launch_segscan(sorted, m, t->init, t->n_ids, SCAN_PRE, L.pre, nullptr, t->scratch.p, t->ctl, s);
