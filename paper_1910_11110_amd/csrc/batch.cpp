@@ -1,9 +1,12 @@
 // batch.cpp -- vc_batch_check: independent traces checked in one captured pipeline.
 //
 // The traces' events are relocated into one key space (ids of trace i start at the
-// sum of the id counts before it) and one index space, evaluated by the same
-// sort / segmented scan / compaction as a single trace, and the results are split
-// back into each trace's buffers by one kernel.  The launch sequence of a batch is
+// sum of the id counts before it) and one index space, and the results are split back
+// into each trace's buffers by one kernel.  When every trace fits the bucket engine, the
+// combined stream (events and induced items) is written as 32-bit words and the traces
+// are checked by groups of consecutive traces whose ids fit one bucket engine's key
+// space, one bucket check per group over its slice of the stream; otherwise the whole
+// batch goes through the sort / segmented scan / compaction of a single trace.  The launch sequence of a batch is
 // captured once in a hipGraph and replayed while the batch (its traces, their sizes
 // and buffers) is unchanged.  The sort's digit width and the persistent grid bound
 // come from an autotuner that times candidate settings on the batch itself, keeps
@@ -24,6 +27,7 @@
 
 #include "abi_internal.h"
 #include "batch.h"
+#include "bucket.h"
 #include "internal.h"
 
 using namespace vc;
@@ -40,9 +44,18 @@ struct BatchState {
     bool graph_ok = false;
     // device buffers
     DevBuf desc, ev_off, key_off, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind,
-        chunks;
+        chunks, words, comb;
     uint64_t n_chunks = 0;
     Control *ctl = nullptr;
+    // bucket route: groups of consecutive traces (their slice of the combined stream and
+    // of the key space) and the control block their checks share
+    struct Group {
+        uint64_t item_lo, m;
+        uint32_t key_lo, k;
+    };
+    bool bucket = false;
+    std::vector<Group> groups;
+    Control *gctl = nullptr;
     uint64_t N = 0, K = 0, M = 0;
     uint32_t n_traces = 0;
     SortTuning tune;
@@ -52,13 +65,16 @@ struct BatchState {
 
 namespace {
 
-// the chunks of every trace (BATCH_CHUNK events at most, never across traces)
-void build_chunks(BatchState &b, const std::vector<TraceDesc> &desc)
+// the chunks of every trace (BATCH_CHUNK events at most, never across traces), and
+// every trace's first chunk
+void build_chunks(BatchState &b, std::vector<TraceDesc> &desc)
 {
     b.h_chunks.clear();
-    for (uint32_t t = 0; t < (uint32_t)desc.size(); t++)
+    for (uint32_t t = 0; t < (uint32_t)desc.size(); t++) {
+        desc[t].first_chunk = b.h_chunks.size();
         for (uint64_t a = 0; a < desc[t].n; a += BATCH_CHUNK)
             b.h_chunks.push_back(ChunkDesc{a, t, (uint32_t)std::min<uint64_t>(BATCH_CHUNK, desc[t].n - a)});
+    }
     b.n_chunks = b.h_chunks.size();
 }
 
@@ -152,6 +168,37 @@ void tune_store(const std::string &key, const SortTuning &t, unsigned scan_grid)
     }
 }
 
+// chooses the route: the bucket engine when every trace has between 1 and
+// bucket_max_ids() ids and its items fit 32-bit positions; then every trace's first
+// combined position and first key inside its group, and the groups (consecutive traces
+// whose ids fit one key space)
+void plan_groups(BatchState &b, std::vector<TraceDesc> &desc)
+{
+    b.groups.clear();
+    const uint64_t kmax = bucket_max_ids();
+    bool ok = !getenv("VC_GENERAL_PATH") && !desc.empty();
+    uint64_t item = 0;
+    for (TraceDesc &d : desc) {
+        ok = ok && d.n_ids >= 1 && d.n_ids <= kmax && d.m < (1ull << 32);
+        d.item_base = item;
+        item += d.m;
+    }
+    b.bucket = ok && item == b.M;
+    if (!b.bucket)
+        return;
+    BatchState::Group g{0, 0, 0, 0};
+    for (TraceDesc &d : desc) {
+        if (g.k && (g.k + d.n_ids > kmax || g.m + d.m >= (1ull << 32))) {
+            b.groups.push_back(g);
+            g = BatchState::Group{d.item_base, 0, d.key_base, 0};
+        }
+        d.key_local = g.k;
+        g.k += d.n_ids;
+        g.m += d.m;
+    }
+    b.groups.push_back(g);
+}
+
 int reserve_all(BatchState &b, uint32_t n)
 {
     int r;
@@ -163,21 +210,29 @@ int reserve_all(BatchState &b, uint32_t n)
     if ((r = devbuf_reserve(b.fin_all, K ? K : 1)) != VC_OK) return r;
     if ((r = devbuf_reserve(b.status_all, N ? N : 1)) != VC_OK) return r;
     if ((r = devbuf_reserve(b.viol_all, 4 * (N ? N : 1))) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.items_a, 8 * (M ? M : 1))) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.items_b, 8 * (M ? M : 1))) != VC_OK) return r;
     const uint64_t nc = b.n_chunks;
     if ((r = devbuf_reserve(b.cnt, 4 * (nc ? nc : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.pos, 8 * (nc + 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.chunks, sizeof(ChunkDesc) * (nc ? nc : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.ind, 8 * (n ? n : 1))) != VC_OK) return r;
-    size_t sc = std::max({ sort_scratch_bytes(M), scan_scratch_bytes(M), compact_scratch_bytes(N),
-                           excl_scan_scratch_bytes(nc) });
-    if ((r = devbuf_reserve(b.scratch, sc)) != VC_OK) return r;
-    if (!b.ctl) {
-        hipError_t e = hipMalloc(&b.ctl, sizeof(Control));
-        if (e != hipSuccess)
-            return vc_hip_fail(e, "hipMalloc(batch control)");
+    size_t sc = std::max(compact_scratch_bytes(N), excl_scan_scratch_bytes(nc));
+    if (b.bucket) {
+        if ((r = devbuf_reserve(b.words, 4 * (M ? M : 1))) != VC_OK) return r;
+        if ((r = devbuf_reserve(b.comb, M ? M : 1)) != VC_OK) return r;
+        for (const BatchState::Group &g : b.groups)
+            sc = std::max(sc, bucket_scratch_bytes(g.m, g.k));
+    } else {
+        if ((r = devbuf_reserve(b.items_a, 8 * (M ? M : 1))) != VC_OK) return r;
+        if ((r = devbuf_reserve(b.items_b, 8 * (M ? M : 1))) != VC_OK) return r;
+        sc = std::max({ sc, sort_scratch_bytes(M), scan_scratch_bytes(M) });
     }
+    if ((r = devbuf_reserve(b.scratch, sc)) != VC_OK) return r;
+    for (Control **c : { &b.ctl, &b.gctl })
+        if (!*c) {
+            hipError_t e = hipMalloc(c, sizeof(Control));
+            if (e != hipSuccess)
+                return vc_hip_fail(e, "hipMalloc(batch control)");
+        }
     return VC_OK;
 }
 
@@ -192,6 +247,24 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
     const ChunkDesc *ch = (const ChunkDesc *)b.chunks.p;
     launch_batch_chunk_count(d, ch, b.n_chunks, (uint32_t *)b.cnt.p, s);
     launch_excl_scan((uint32_t *)b.cnt.p, b.n_chunks, (uint64_t *)b.pos.p, nullptr, b.scratch.p, b.ctl->tickets[6], s);
+    if (b.bucket) {
+        uint32_t *words = (uint32_t *)b.words.p;
+        uint8_t *comb = (uint8_t *)b.comb.p, *init_all = (uint8_t *)b.init_all.p, *fin_all = (uint8_t *)b.fin_all.p;
+        launch_batch_chunk_words(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, words, b.M, s);
+        // one bucket check per group (final statuses into the group's slice of fin_all,
+        // which holds the initial statuses); their errors are folded into the batch's
+        for (const BatchState::Group &g : b.groups) {
+            launch_bucket_check_combined(words + g.item_lo, g.m, g.k, init_all + g.key_lo, comb + g.item_lo,
+                                         fin_all + g.key_lo, nullptr, b.scratch.p, b.gctl, s, 0, nullptr);
+            launch_merge_errors(b.ctl, b.gctl, s);
+        }
+        launch_batch_chunk_gather(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, comb, b.M, (uint8_t *)b.status_all.p,
+                                  (unsigned long long *)b.ind.p, s);
+        launch_compact((uint8_t *)b.status_all.p, b.N, (uint32_t *)b.viol_all.p, b.scratch.p, b.ctl, s);
+        launch_batch_distribute(d, n, (const uint8_t *)b.status_all.p, (const uint8_t *)b.fin_all.p,
+                                (const uint32_t *)b.viol_all.p, b.ctl, (const unsigned long long *)b.ind.p, s);
+        return;
+    }
     launch_batch_chunk_emit(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M, s);
     uint64_t *sorted = sort_items((uint64_t *)b.items_a.p, (uint64_t *)b.items_b.p, b.M, (int)key_bits_for((uint32_t)b.K),
                                   b.scratch.p, b.ctl, s, &b.tune);
@@ -224,7 +297,7 @@ int autotune(vc_ctx *c, BatchState &b)
         b.tuned = true;
         return VC_OK;
     }
-    if (!getenv("VC_AUTOTUNE")) { // default settings unless tuning is requested
+    if (!getenv("VC_AUTOTUNE") || b.bucket) { // default settings unless tuning the sorted route is requested
         b.tune = SortTuning{};
         b.scan_grid = 0;
         b.tuned = true;
@@ -287,10 +360,13 @@ void batch_free(BatchState *b)
         return;
     drop_graph(*b);
     for (DevBuf *d : { &b->desc, &b->ev_off, &b->key_off, &b->init_all, &b->fin_all, &b->status_all, &b->viol_all,
-                       &b->items_a, &b->items_b, &b->cnt, &b->pos, &b->scratch, &b->ind, &b->chunks })
+                       &b->items_a, &b->items_b, &b->cnt, &b->pos, &b->scratch, &b->ind, &b->chunks, &b->words,
+                       &b->comb })
         devbuf_free(*d);
     if (b->ctl)
         (void)hipFree(b->ctl);
+    if (b->gctl)
+        (void)hipFree(b->gctl);
     delete b;
 }
 
@@ -322,7 +398,8 @@ int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M,
     b.K = K;
     b.M = M;
     b.n_traces = n;
-    build_chunks(b, desc);
+    build_chunks(b, b.h_desc);
+    plan_groups(b, b.h_desc);
     int r = reserve_all(b, n);
     if (r != VC_OK)
         return r;
@@ -402,9 +479,10 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
         d.status = (uint8_t *)t->status.p;
         d.fin = (uint8_t *)t->fin.p;
         d.viol = (uint32_t *)t->viol.p;
+        d.m = t->n + (t->has_arrays ? t->n_induced : 0);
         N += t->n;
         K += t->n_ids;
-        M += t->n + (t->has_arrays ? t->n_induced : 0);
+        M += d.m;
         for (uint64_t v : { (uint64_t)(uintptr_t)t, (uint64_t)(uintptr_t)t->events, t->n, (uint64_t)t->n_ids,
                             (uint64_t)(uintptr_t)t->init, (uint64_t)(uintptr_t)d.off, (uint64_t)(uintptr_t)d.status,
                             (uint64_t)(uintptr_t)d.fin, (uint64_t)(uintptr_t)d.viol, (uint64_t)t->n_induced })
@@ -425,6 +503,7 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
         b.M = M;
         b.n_traces = n;
         build_chunks(b, desc);
+        plan_groups(b, desc);
         int r = reserve_all(b, n);
         if (r != VC_OK)
             return r;

@@ -20,6 +20,10 @@ struct TraceDesc {
     uint8_t *status;        // the trace's result buffers
     uint8_t *fin;
     uint32_t *viol;
+    uint64_t m;             // its combined items (events and induced items)
+    uint64_t item_base;     // bucket route: first combined position
+    uint64_t first_chunk;   // index of its first chunk
+    uint32_t key_local;     // bucket route: first key inside its group
 };
 
 // a run of at most BATCH_CHUNK consecutive events of one trace: the unit of work of
@@ -37,6 +41,17 @@ void launch_batch_chunk_count(const TraceDesc *d, const ChunkDesc *ch, uint64_t 
 // the chunks before it (chunk_pos) and of its own events before each one
 void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
                              uint64_t *items, uint64_t cap, hipStream_t s);
+
+// bucket route: every chunk's items as 32-bit words (group-local keys, induced items op
+// 5), each trace's at item_base on; an item past the trace's range is not written and
+// reported, and slots of the range that no item reaches get a no-op word
+void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                              uint32_t *words, uint64_t cap, hipStream_t s);
+// bucket route: the primaries' status bytes from the combined status bytes into
+// status_all (global event order), and per trace the flagged induced items into ind
+void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                               const uint8_t *comb, uint64_t cap, uint8_t *status_all, unsigned long long *ind,
+                               hipStream_t s);
 
 void launch_batch_reset(const TraceDesc *d, uint32_t n_traces, unsigned long long *ind, hipStream_t s);
 void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_traces, uint64_t K, uint8_t *init_all,

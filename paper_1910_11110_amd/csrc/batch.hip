@@ -110,6 +110,123 @@ __global__ __launch_bounds__(BLOCK) void k_batch_chunk_count(const TraceDesc *__
     }
 }
 
+// Walks a chunk's events with their combined positions (the chunk's shift plus the
+// event's global index plus, with arrays, the induced items of the chunk's events before
+// it): f(i, g, p, e, n_ind, o) per event, with e cleaned (a malformed word, reported, as
+// a no-op on id 0), n_ind its induced items and o where its neighbour list starts.
+// Without arrays a thread takes events tid, tid + BLOCK, ... (coalesced); with arrays
+// CH_ITEMS consecutive events, placed by a scan over the workgroup.  Called by the whole
+// workgroup.
+template <class F>
+__device__ __forceinline__ void walk_chunk(const TraceDesc &td, const ChunkDesc &cd, uint64_t shift, uint32_t *s_tmp,
+                                           bool report, F &&f)
+{
+    const uint32_t tid = threadIdx.x;
+    auto clean = [&](uint32_t e, uint64_t i) -> uint32_t {
+        const uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
+        if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
+            if (report)
+                report_bad(td.ctl, i);
+            return (uint32_t)OP_NOOP << 24;
+        }
+        return e;
+    };
+    if (!td.off) {
+        for (uint32_t j = tid; j < cd.len; j += BLOCK) {
+            const uint64_t i = cd.start + j, g = td.ev_base + i;
+            f(i, g, g + shift, clean(td.events[i], i), (uint64_t)0, (uint64_t)0);
+        }
+        return;
+    }
+    const uint32_t j0 = tid * CH_ITEMS;
+    uint32_t ev[CH_ITEMS], k = 0;
+#pragma unroll
+    for (int q = 0; q < CH_ITEMS; q++) {
+        const uint32_t j = j0 + q;
+        ev[q] = j < cd.len ? clean(td.events[cd.start + j], cd.start + j) : ((uint32_t)OP_NOOP << 24);
+        k += j < cd.len ? induced_of(td, ev[q]) : 0u;
+    }
+    uint64_t p = td.ev_base + cd.start + j0 + shift + block_excl_sum(k, s_tmp);
+#pragma unroll
+    for (int q = 0; q < CH_ITEMS; q++) {
+        const uint32_t j = j0 + q;
+        if (j >= cd.len)
+            break;
+        const uint64_t i = cd.start + j;
+        const uint32_t e = ev[q], x = e & 0xFFFFFFu;
+        const uint64_t n_ind = ((e >> 24) & 7u) == OP_W ? td.off[x + 1] - td.off[x] : 0;
+        f(i, td.ev_base + i, p, e, n_ind, n_ind ? td.off[x] : (uint64_t)0);
+        p += 1 + n_ind;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_words(const TraceDesc *__restrict__ d,
+                                                             const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                             const uint64_t *__restrict__ chunk_pos,
+                                                             uint32_t *__restrict__ words, uint64_t cap)
+{
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const ChunkDesc cd = ch[c];
+        const TraceDesc &td = d[cd.trace];
+        const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
+        // the trace's items from item_base on: the chunk's shift counts only the induced
+        // items of the trace's own chunks before it
+        const uint64_t induced0 = chunk_pos[td.first_chunk];
+        const uint64_t shift = (td.item_base + chunk_pos[c]) - (td.ev_base + induced0);
+        walk_chunk(td, cd, shift, s_tmp, true,
+                   [&](uint64_t i, uint64_t, uint64_t p, uint32_t e, uint64_t n_ind, uint64_t o) {
+                       if (p < lo || p + n_ind >= hi) { // the events changed since the batch was sized
+                           report_bad(td.ctl, i);
+                           return;
+                       }
+                       const uint32_t side = e & (1u << 27);
+                       words[p] = (td.key_local + (e & 0xFFFFFFu)) | (e & (7u << 24)) | side;
+                       for (uint64_t m = 0; m < n_ind; m++)
+                           words[p + 1 + m] = (td.key_local + td.nbr[o + m]) | ((uint32_t)OP_RWIND << 24) | side;
+                   });
+        if (cd.start + cd.len == td.n) {
+            // the trace's last chunk: slots its items leave in the range (only when the
+            // events changed since the batch was sized) get a no-op on its first key
+            const uint64_t end = td.item_base + td.n + (chunk_pos[c + 1] - induced0);
+            if (end < hi && threadIdx.x == 0)
+                report_bad(td.ctl, cd.start);
+            for (uint64_t p = (end > lo ? end : lo) + threadIdx.x; p < hi; p += BLOCK)
+                words[p] = td.key_local | ((uint32_t)OP_NOOP << 24);
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_gather(const TraceDesc *__restrict__ d,
+                                                              const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                              const uint64_t *__restrict__ chunk_pos,
+                                                              const uint8_t *__restrict__ comb, uint64_t cap,
+                                                              uint8_t *__restrict__ status_all,
+                                                              unsigned long long *__restrict__ ind)
+{
+    __shared__ uint32_t s_tmp[BLOCK / WAVE];
+    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const ChunkDesc cd = ch[c];
+        const TraceDesc &td = d[cd.trace];
+        const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
+        const uint64_t shift = (td.item_base + chunk_pos[c]) - (td.ev_base + chunk_pos[td.first_chunk]);
+        uint32_t stuck = 0;
+        walk_chunk(td, cd, shift, s_tmp, false,
+                   [&](uint64_t, uint64_t g, uint64_t p, uint32_t, uint64_t n_ind, uint64_t) {
+                       if (p < lo || p + n_ind >= hi)
+                           return; // reported by the word pass
+                       status_all[g] = comb[p];
+                       for (uint64_t m = 1; m <= n_ind; m++)
+                           stuck += comb[p + m] >> 7;
+                   });
+        if (td.off) { // uniform per workgroup
+            const uint32_t ex = block_excl_sum(stuck, s_tmp);
+            if (threadIdx.x == BLOCK - 1 && ex + stuck)
+                atomicAdd(&ind[cd.trace], (unsigned long long)(ex + stuck));
+        }
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_batch_chunk_emit(const TraceDesc *__restrict__ d,
                                                             const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
                                                             const uint64_t *__restrict__ chunk_pos,
@@ -218,6 +335,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch_distribute(const TraceDesc *__r
         s_hi = a;
         td.ctl->n_viol = a - lo;
         td.ctl->n_induced_stuck = ind[blockIdx.x];
+        if (bctl->err_code) // an internal error of the shared pipeline concerns every trace
+            atomicOr(&td.ctl->err_code, bctl->err_code);
     }
     __syncthreads();
     for (uint64_t j = s_lo + tid; j < s_hi; j += BLOCK)
@@ -262,6 +381,26 @@ void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n
     if (n_chunks) {
         ProfScope prof_(s, "batch_chunk_emit");
         k_batch_chunk_emit<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, items, cap);
+    }
+}
+
+void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                              uint32_t *words, uint64_t cap, hipStream_t s)
+{
+    if (n_chunks) {
+        ProfScope prof_(s, "batch_chunk_words");
+        k_batch_chunk_words<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, words, cap);
+    }
+}
+
+void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                               const uint8_t *comb, uint64_t cap, uint8_t *status_all, unsigned long long *ind,
+                               hipStream_t s)
+{
+    if (n_chunks) {
+        ProfScope prof_(s, "batch_chunk_gather");
+        k_batch_chunk_gather<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, comb, cap, status_all,
+                                                                  ind);
     }
 }
 

@@ -55,7 +55,8 @@ void launch_bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
                          const FillJob *fin_fill);
 
 // the same over the combined stream of a trace over overlapping arrays (its events
-// with the induced RW items, op 5, after every write): one status byte per item
+// with the induced RW items, op 5, after every write): one status byte per item.  With
+// viol null (either entry point), no violation list is made and ctl->n_viol stays 0.
 void launch_bucket_check_combined(const uint32_t *words, uint64_t m, uint32_t n_ids, const uint8_t *init,
                                   uint8_t *status, uint8_t *final_out, uint32_t *viol, void *scratch, Control *ctl,
                                   hipStream_t s, int cu, const FillJob *fin_fill);

@@ -1217,7 +1217,8 @@ static void bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
         return;
     partition_and_scan<SRC>(events, n, n_ids, init, BK_STATUS, final_out, L, status, ctl, s, cu, nullptr, 0, true);
     if (L.nb == 1) {
-        launch_compact(status, n, viol, L.fw, ctl, s, nullptr, nullptr, true);
+        if (viol)
+            launch_compact(status, n, viol, L.fw, ctl, s, nullptr, nullptr, true);
         return;
     }
     {
@@ -1226,6 +1227,8 @@ static void bucket_check(const uint32_t *events, uint64_t n, uint32_t n_ids, con
         k_replay_status<<<grid, BLOCK, 0, s>>>(L.li16, L.tpre, L.base, L.nb, n, L.res, status, L.fw, L.tcnt,
                                                L.ptiles);
     }
+    if (!viol)
+        return;
     // the violation count lands in ctl->n_viol
     launch_excl_scan(L.tcnt, L.ptiles, L.offs, reinterpret_cast<uint64_t *>(&ctl->n_viol), L.xscan,
                      ctl->tickets[10], s, true);

@@ -231,8 +231,8 @@ uint64_t count_induced(const std::vector<uint32_t> &ev, const std::vector<uint64
     if (deg.empty())
         return 0;
     uint64_t k = 0;
-    for (uint32_t w : ev)
-        if (((w >> 24) & 7u) == vc::OP_W && (w & 0xFFFFFFu) < deg.size())
+    for (uint32_t w : ev) // well-formed writes only, as the device counts them
+        if ((w >> 28) == 0 && ((w >> 24) & 7u) == vc::OP_W && (w & 0xFFFFFFu) < deg.size())
             k += deg[w & 0xFFFFFFu];
     return k;
 }
@@ -353,7 +353,8 @@ static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
         d.status = c->d_status;
         d.fin = st->table; // the chunk leaves its final statuses in the resident table
         d.viol = c->d_viol;
-        M += n + c->induced;
+        d.m = n + c->induced;
+        M += d.m;
     }
     uint64_t N = 0, K = 0;
     for (auto &d : desc) {

@@ -129,12 +129,14 @@ def test_batch_edge_cases(ctx):
 
 
 def test_batch_autotuner_is_parity_clean(ctx, tmp_path):
-    """With tuning on, every candidate setting runs on the batch; the chosen one gives the
-    oracle's bytes and is cached per shape."""
+    """With tuning on, every candidate setting of the sorted route (the one with a sort to
+    tune) runs on the batch; the chosen one gives the oracle's bytes and is cached per
+    shape."""
     from paper_1910_11110_amd import vcheck as V
     cache = tmp_path / "tune.json"
     os.environ["VC_AUTOTUNE"] = "1"
     os.environ["VC_TUNE_CACHE"] = str(cache)
+    os.environ["VC_GENERAL_PATH"] = "1"
     try:
         inputs = make_traces(25, 3)
         traces = load_all(ctx, inputs)
@@ -149,6 +151,7 @@ def test_batch_autotuner_is_parity_clean(ctx, tmp_path):
     finally:
         del os.environ["VC_AUTOTUNE"]
         del os.environ["VC_TUNE_CACHE"]
+        del os.environ["VC_GENERAL_PATH"]
 
 
 # array traces are compared with the oracle while the oracle's O(n^2) overlap-set
@@ -213,5 +216,55 @@ def test_batch_workload_full_size(ctx):
         assert np.array_equal(traces[i].status(), s0) and np.array_equal(traces[i].final(), f0), f"alone {i}"
         v1 = traces[i].violations()
         assert v1.total == v0.total and np.array_equal(v1.indices, v0.indices) and v1.first == v0.first
+    for t in traces:
+        t.free()
+
+
+def _route_results(ctx, inputs, general):
+    from paper_1910_11110_amd import vcheck as V
+    if general:
+        os.environ["VC_GENERAL_PATH"] = "1"
+    try:
+        traces = load_all(ctx, inputs)
+        V.batch_check(ctx, traces)
+        ctx.sync()
+        out = [(t.status().copy(), t.final().copy(), t.violations().indices.copy(), t.induced_stuck()) for t in traces]
+    finally:
+        os.environ.pop("VC_GENERAL_PATH", None)
+    for t in traces:
+        t.free()
+    return out
+
+
+def test_batch_bucket_and_sorted_routes_agree(ctx):
+    """The bucket-engine route (groups of traces as 32-bit words) and the sorted route give
+    the same bytes on a mixed batch with arrays and initial statuses."""
+    inputs = make_traces(30, 7)
+    say("[batch] 30 traces through both routes")
+    a = _route_results(ctx, inputs, False)
+    b = _route_results(ctx, inputs, True)
+    for i, (x, y) in enumerate(zip(a, b)):
+        assert np.array_equal(x[0], y[0]), f"trace {i}: statuses"
+        assert np.array_equal(x[1], y[1]), f"trace {i}: final"
+        assert np.array_equal(x[2], y[2]), f"trace {i}: violations"
+        assert x[3] == y[3], f"trace {i}: induced stuck"
+
+
+def test_batch_groups_split_at_the_key_space(ctx):
+    """Traces whose ids together exceed one bucket engine's key space (2^22) are checked in
+    several groups; every trace equals the oracle, the one with arrays included."""
+    from paper_1910_11110_amd import vcheck as V
+    big = 3 << 19  # three of these exceed 2^22 together
+    inputs = [(gen.plain_events(200_000, big, 11 + k), big, None, None,
+               gen.below(gen.draws(11 + k, 400, 0, big), 4).astype(np.uint8) if k == 1 else None) for k in range(3)]
+    n_arr = 300
+    lo, hi = gen.intervals(n_arr, 21)
+    inputs.insert(2, (gen.plain_events(50_000, n_arr, 22), n_arr, lo, hi, None))
+    traces = load_all(ctx, inputs)
+    say("[batch] 4 traces over more than 2^22 ids")
+    V.batch_check(ctx, traces)
+    ctx.sync()
+    for i, (t, inp) in enumerate(zip(traces, inputs)):
+        assert_trace(t, oracle_of(*inp), f"trace {i}")
     for t in traces:
         t.free()
