@@ -65,15 +65,15 @@ struct BatchState {
 
 namespace {
 
-// the chunks of every trace (BATCH_CHUNK events at most, never across traces), and
-// every trace's first chunk
+// the chunks of every trace (never across traces), and every trace's first chunk
 void build_chunks(BatchState &b, std::vector<TraceDesc> &desc)
 {
     b.h_chunks.clear();
     for (uint32_t t = 0; t < (uint32_t)desc.size(); t++) {
         desc[t].first_chunk = b.h_chunks.size();
-        for (uint64_t a = 0; a < desc[t].n; a += BATCH_CHUNK)
-            b.h_chunks.push_back(ChunkDesc{a, t, (uint32_t)std::min<uint64_t>(BATCH_CHUNK, desc[t].n - a)});
+        const uint64_t len = desc[t].off ? BATCH_CHUNK : BATCH_CHUNK_PLAIN;
+        for (uint64_t a = 0; a < desc[t].n; a += len)
+            b.h_chunks.push_back(ChunkDesc{a, t, (uint32_t)std::min<uint64_t>(len, desc[t].n - a)});
     }
     b.n_chunks = b.h_chunks.size();
 }
@@ -261,8 +261,8 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
         launch_batch_chunk_gather(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, comb, b.M, (uint8_t *)b.status_all.p,
                                   (unsigned long long *)b.ind.p, s);
         launch_compact((uint8_t *)b.status_all.p, b.N, (uint32_t *)b.viol_all.p, b.scratch.p, b.ctl, s);
-        launch_batch_distribute(d, n, (const uint8_t *)b.status_all.p, (const uint8_t *)b.fin_all.p,
-                                (const uint32_t *)b.viol_all.p, b.ctl, (const unsigned long long *)b.ind.p, s);
+        launch_batch_distribute(d, n, nullptr, (const uint8_t *)b.fin_all.p, (const uint32_t *)b.viol_all.p, b.ctl,
+                                (const unsigned long long *)b.ind.p, s);
         return;
     }
     launch_batch_chunk_emit(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M, s);

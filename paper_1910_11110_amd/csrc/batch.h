@@ -26,9 +26,11 @@ struct TraceDesc {
     uint32_t key_local;     // bucket route: first key inside its group
 };
 
-// a run of at most BATCH_CHUNK consecutive events of one trace: the unit of work of
-// the relocation passes (a chunk never straddles two traces)
-constexpr uint32_t BATCH_CHUNK = 4096;
+// a run of consecutive events of one trace: the unit of work of the relocation passes,
+// one wave each (a chunk never straddles two traces).  At most BATCH_CHUNK events for a
+// trace with arrays (its items are staged per event), BATCH_CHUNK_PLAIN otherwise.
+constexpr uint32_t BATCH_CHUNK = 512;
+constexpr uint32_t BATCH_CHUNK_PLAIN = 4096;
 struct ChunkDesc {
     uint64_t start; // first event, trace-relative
     uint32_t trace;
@@ -48,7 +50,8 @@ void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n
 void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
                               uint32_t *words, uint64_t cap, hipStream_t s);
 // bucket route: the primaries' status bytes from the combined status bytes into
-// status_all (global event order), and per trace the flagged induced items into ind
+// status_all (global event order) and the traces' own status buffers, and per trace the
+// flagged induced items into ind
 void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
                                const uint8_t *comb, uint64_t cap, uint8_t *status_all, unsigned long long *ind,
                                hipStream_t s);
@@ -56,6 +59,8 @@ void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t
 void launch_batch_reset(const TraceDesc *d, uint32_t n_traces, unsigned long long *ind, hipStream_t s);
 void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_traces, uint64_t K, uint8_t *init_all,
                        uint8_t *fin_all, hipStream_t s);
+// every trace's final statuses, violations and counts (and its status bytes unless
+// status_all is null: the bucket route's gather has written them)
 void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_t *status_all, const uint8_t *fin_all,
                              const uint32_t *viol_all, const Control *bctl, const unsigned long long *ind,
                              hipStream_t s);

@@ -35,21 +35,6 @@ __device__ __forceinline__ void report_bad(Control *ctl, uint64_t i)
     atomicMin(w, (unsigned long long)i);
 }
 
-// exclusive sum over the workgroup (BLOCK threads)
-__device__ __forceinline__ uint32_t block_excl_sum(uint32_t v, uint32_t *s_tmp)
-{
-    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
-    const uint32_t inc = wave_scan_add(v, lane);
-    if (lane == WAVE - 1)
-        s_tmp[wave] = inc;
-    __syncthreads();
-    uint32_t off = 0;
-    for (uint32_t w = 0; w < wave; w++)
-        off += s_tmp[w];
-    __syncthreads();
-    return off + inc - v;
-}
-
 __global__ void k_batch_reset(const TraceDesc *__restrict__ d, uint32_t n_traces, unsigned long long *ind)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,86 +63,197 @@ __global__ void k_batch_init(const TraceDesc *__restrict__ d, const uint64_t *__
 }
 
 // ---- relocation by chunks (a chunk belongs to one trace: no search per event) ----
-constexpr int CH_ITEMS = BATCH_CHUNK / BLOCK; // events per thread
-static_assert(CH_ITEMS * BLOCK == (int)BATCH_CHUNK, "a chunk is one workgroup's events");
+// One wave per chunk (up to BATCH_CHUNK events, CH_PER per lane, for a trace with
+// arrays; up to BATCH_CHUNK_PLAIN otherwise).  A chunk's items sit at
+// consecutive positions: each event, then (a write of a trace with arrays) one induced
+// item per neighbour of its array.
+constexpr int CH_PER = BATCH_CHUNK / WAVE; // events per lane
+constexpr uint32_t CH_WAVES = BLOCK / WAVE;
+static_assert(CH_PER * WAVE == (int)BATCH_CHUNK, "a chunk is one wave's events");
+
+// a well-formed event word, or a no-op on id 0 for a malformed one (reported when asked)
+__device__ __forceinline__ uint32_t clean_word(const TraceDesc &td, uint32_t e, uint64_t i, bool report)
+{
+    const uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
+    if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
+        if (report)
+            report_bad(td.ctl, i);
+        return (uint32_t)OP_NOOP << 24;
+    }
+    return e;
+}
 
 __device__ __forceinline__ uint32_t induced_of(const TraceDesc &td, uint32_t e)
 {
-    const uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
-    const bool bad = (e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids;
-    return (!bad && op == OP_W) ? (uint32_t)(td.off[x + 1] - td.off[x]) : 0u;
+    const uint32_t x = e & 0xFFFFFFu;
+    return ((e >> 24) & 7u) == OP_W ? (uint32_t)(td.off[x + 1] - td.off[x]) : 0u;
+}
+
+// the wave's index in its workgroup, as a wave-uniform (scalar) value: chunk indices,
+// chunk and trace descriptors then live in scalar registers
+__device__ __forceinline__ uint32_t wave_index()
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+}
+
+// per-wave staging of a chunk of a trace with arrays
+struct ChunkStage {
+    uint32_t start[BATCH_CHUNK + 1]; // chunk-relative first item of every event
+    uint32_t word[BATCH_CHUNK];      // its cleaned word
+    uint64_t nb[BATCH_CHUNK];        // where its neighbour list starts
+    uint32_t mark[WAVE];
+};
+
+// Walks the items of chunk cd (events from cd.start, items from position base on; at
+// most BATCH_CHUNK events when the trace has arrays) with the whole wave: f(q, p, i, e, y) per item, q = 0 for the event itself and q > 0 for its
+// q-th induced item (on neighbour y), p its position, i the event's index in its trace,
+// e the event's cleaned word.  Without arrays lane l takes events l, l + 64, ...; with
+// arrays the events' item counts are scanned over the wave and the items walked 64
+// consecutive ones at a time, the lane of an item finding its event from a ballot of the
+// event starts among the 64.  Returns the chunk's number of items.
+template <class F>
+__device__ __forceinline__ uint32_t walk_chunk(const TraceDesc &td, const ChunkDesc &cd, uint64_t base, bool report,
+                                               ChunkStage &S, F &&f)
+{
+    const uint32_t lane = lane_id();
+    if (!td.off) {
+        // batches of CH_PER events per lane: the loads of a batch are issued together
+        for (uint32_t k0 = 0; k0 < cd.len; k0 += BATCH_CHUNK) {
+            uint32_t ev[CH_PER];
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++) {
+                const uint32_t k = k0 + j * WAVE + lane;
+                ev[j] = k < cd.len ? td.events[cd.start + k] : 0u;
+            }
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++) {
+                const uint32_t k = k0 + j * WAVE + lane;
+                if (k < cd.len)
+                    f(0u, base + k, cd.start + k, clean_word(td, ev[j], cd.start + k, report), 0u);
+            }
+        }
+        return cd.len;
+    }
+    // the chunk's events, then the neighbour-list bounds of its writes (loads issued
+    // together)
+    uint32_t ev[CH_PER];
+    uint64_t ob[CH_PER], oe[CH_PER];
+#pragma unroll
+    for (int j = 0; j < CH_PER; j++) {
+        const uint32_t k = j * WAVE + lane;
+        ev[j] = k < cd.len ? td.events[cd.start + k] : ((uint32_t)OP_NOOP << 24);
+    }
+#pragma unroll
+    for (int j = 0; j < CH_PER; j++) {
+        const uint32_t k = j * WAVE + lane;
+        if (k < cd.len)
+            ev[j] = clean_word(td, ev[j], cd.start + k, report);
+        const uint32_t x = ev[j] & 0xFFFFFFu;
+        const bool wr = ((ev[j] >> 24) & 7u) == OP_W;
+        ob[j] = wr ? td.off[x] : 0;
+        oe[j] = wr ? td.off[x + 1] : 0;
+    }
+    uint32_t carry = 0;
+#pragma unroll
+    for (int j = 0; j < CH_PER; j++) {
+        const uint32_t k = j * WAVE + lane;
+        const uint32_t len = k < cd.len ? 1u + (uint32_t)(oe[j] - ob[j]) : 0u;
+        const uint32_t w = k < cd.len ? ev[j] : 0u;
+        const uint64_t o = ob[j];
+        const uint32_t inc = wave_scan_add(len, lane);
+        S.start[k] = carry + inc - len;
+        S.word[k] = w;
+        S.nb[k] = o;
+        carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
+    }
+    const uint32_t total = carry; // below 2^31: fewer than 2^22 neighbours per event
+    if (lane == 0)
+        S.start[BATCH_CHUNK] = total;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t ec = 0; // the event covering item qc - 1 (event 0 for qc = 0)
+    for (uint32_t qc = 0; qc < total; qc += WAVE) {
+        // events ec + 1 .. ec + 64 hold every start inside [qc, qc + 64)
+        const uint32_t e = ec + 1 + lane;
+        const uint32_t st = e <= BATCH_CHUNK ? S.start[e] : total;
+        S.mark[lane] = 0;
+        __builtin_amdgcn_wave_barrier();
+        if (st < total && st < qc + WAVE)
+            S.mark[st - qc] = 1;
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t heads = __ballot(S.mark[lane] != 0);
+        const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
+        const uint32_t q = qc + lane;
+        if (q < total) {
+            const uint32_t kq = q - S.start[own], w = S.word[own];
+            f(kq, base + q, cd.start + own, w, kq ? td.nbr[S.nb[own] + kq - 1] : 0u);
+        }
+        ec += (uint32_t)__builtin_popcountll(heads);
+        __builtin_amdgcn_wave_barrier();
+    }
+    return total;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_batch_chunk_count(const TraceDesc *__restrict__ d,
                                                              const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
                                                              uint32_t *__restrict__ chunk_cnt)
 {
-    __shared__ uint32_t s_tmp[BLOCK / WAVE];
-    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    const uint32_t lane = lane_id();
+    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+         c += (uint64_t)gridDim.x * CH_WAVES) {
         const ChunkDesc cd = ch[c];
-        const TraceDesc &td = d[cd.trace];
-        if (!td.off) { // no arrays: no induced items (uniform per workgroup)
-            if (threadIdx.x == 0)
-                chunk_cnt[c] = 0;
-            continue;
-        }
+        const TraceDesc td = d[cd.trace];
         uint32_t k = 0;
-        for (uint32_t j = threadIdx.x; j < cd.len; j += BLOCK)
-            k += induced_of(td, td.events[cd.start + j]);
-        const uint32_t ex = block_excl_sum(k, s_tmp);
-        if (threadIdx.x == BLOCK - 1)
-            chunk_cnt[c] = ex + k;
+        if (td.off) { // uniform per wave
+            uint32_t ev[CH_PER];
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++) {
+                const uint32_t q = j * WAVE + lane;
+                ev[j] = q < cd.len ? clean_word(td, td.events[cd.start + q], 0, false) : ((uint32_t)OP_NOOP << 24);
+            }
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++)
+                k += induced_of(td, ev[j]);
+        }
+        const uint32_t total = wave_total_u32(k);
+        if (lane == 0)
+            chunk_cnt[c] = total;
     }
 }
 
-// Walks a chunk's events with their combined positions (the chunk's shift plus the
-// event's global index plus, with arrays, the induced items of the chunk's events before
-// it): f(i, g, p, e, n_ind, o) per event, with e cleaned (a malformed word, reported, as
-// a no-op on id 0), n_ind its induced items and o where its neighbour list starts.
-// Without arrays a thread takes events tid, tid + BLOCK, ... (coalesced); with arrays
-// CH_ITEMS consecutive events, placed by a scan over the workgroup.  Called by the whole
-// workgroup.
-template <class F>
-__device__ __forceinline__ void walk_chunk(const TraceDesc &td, const ChunkDesc &cd, uint64_t shift, uint32_t *s_tmp,
-                                           bool report, F &&f)
+// general route: 64-bit sort items at the event's global index plus the chunk's shift
+// (payload: the global event index, or INDUCED_BIT | trace for induced items)
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_emit(const TraceDesc *__restrict__ d,
+                                                            const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                            const uint64_t *__restrict__ chunk_pos,
+                                                            uint64_t *__restrict__ items, uint64_t cap)
 {
-    const uint32_t tid = threadIdx.x;
-    auto clean = [&](uint32_t e, uint64_t i) -> uint32_t {
-        const uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u;
-        if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
-            if (report)
+    __shared__ ChunkStage s_stage[CH_WAVES];
+    ChunkStage &S = s_stage[wave_index()];
+    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+         c += (uint64_t)gridDim.x * CH_WAVES) {
+        const ChunkDesc cd = ch[c];
+        const uint32_t t = cd.trace;
+        const TraceDesc td = d[t];
+        const uint64_t base = td.ev_base + cd.start + chunk_pos[c];
+        walk_chunk(td, cd, base, true, S, [&](uint32_t q, uint64_t p, uint64_t i, uint32_t e, uint32_t y) {
+            if (p >= cap) { // the events changed since the batch was sized
                 report_bad(td.ctl, i);
-            return (uint32_t)OP_NOOP << 24;
-        }
-        return e;
-    };
-    if (!td.off) {
-        for (uint32_t j = tid; j < cd.len; j += BLOCK) {
-            const uint64_t i = cd.start + j, g = td.ev_base + i;
-            f(i, g, g + shift, clean(td.events[i], i), (uint64_t)0, (uint64_t)0);
-        }
-        return;
+                return;
+            }
+            const uint32_t side = (e >> 27) & 1u;
+            items[p] = q == 0 ? make_item(td.key_base + (e & 0xFFFFFFu), fcode((e >> 24) & 7u, side),
+                                          (uint32_t)(td.ev_base + i))
+                              : make_item(td.key_base + y, fcode(OP_RWIND, side), INDUCED_BIT | t);
+        });
     }
-    const uint32_t j0 = tid * CH_ITEMS;
-    uint32_t ev[CH_ITEMS], k = 0;
-#pragma unroll
-    for (int q = 0; q < CH_ITEMS; q++) {
-        const uint32_t j = j0 + q;
-        ev[q] = j < cd.len ? clean(td.events[cd.start + j], cd.start + j) : ((uint32_t)OP_NOOP << 24);
-        k += j < cd.len ? induced_of(td, ev[q]) : 0u;
-    }
-    uint64_t p = td.ev_base + cd.start + j0 + shift + block_excl_sum(k, s_tmp);
-#pragma unroll
-    for (int q = 0; q < CH_ITEMS; q++) {
-        const uint32_t j = j0 + q;
-        if (j >= cd.len)
-            break;
-        const uint64_t i = cd.start + j;
-        const uint32_t e = ev[q], x = e & 0xFFFFFFu;
-        const uint64_t n_ind = ((e >> 24) & 7u) == OP_W ? td.off[x + 1] - td.off[x] : 0;
-        f(i, td.ev_base + i, p, e, n_ind, n_ind ? td.off[x] : (uint64_t)0);
-        p += 1 + n_ind;
-    }
+}
+
+// bucket route: the trace's items from item_base on (the chunk's shift counts only the
+// induced items of the trace's own chunks before it)
+__device__ __forceinline__ uint64_t bucket_base(const TraceDesc &td, const ChunkDesc &cd,
+                                                const uint64_t *__restrict__ chunk_pos, uint64_t c)
+{
+    return td.item_base + cd.start + (chunk_pos[c] - chunk_pos[td.first_chunk]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_batch_chunk_words(const TraceDesc *__restrict__ d,
@@ -165,33 +261,30 @@ __global__ __launch_bounds__(BLOCK) void k_batch_chunk_words(const TraceDesc *__
                                                              const uint64_t *__restrict__ chunk_pos,
                                                              uint32_t *__restrict__ words, uint64_t cap)
 {
-    __shared__ uint32_t s_tmp[BLOCK / WAVE];
-    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    __shared__ ChunkStage s_stage[CH_WAVES];
+    ChunkStage &S = s_stage[wave_index()];
+    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+         c += (uint64_t)gridDim.x * CH_WAVES) {
         const ChunkDesc cd = ch[c];
-        const TraceDesc &td = d[cd.trace];
+        const TraceDesc td = d[cd.trace];
         const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
-        // the trace's items from item_base on: the chunk's shift counts only the induced
-        // items of the trace's own chunks before it
-        const uint64_t induced0 = chunk_pos[td.first_chunk];
-        const uint64_t shift = (td.item_base + chunk_pos[c]) - (td.ev_base + induced0);
-        walk_chunk(td, cd, shift, s_tmp, true,
-                   [&](uint64_t i, uint64_t, uint64_t p, uint32_t e, uint64_t n_ind, uint64_t o) {
-                       if (p < lo || p + n_ind >= hi) { // the events changed since the batch was sized
-                           report_bad(td.ctl, i);
-                           return;
-                       }
-                       const uint32_t side = e & (1u << 27);
-                       words[p] = (td.key_local + (e & 0xFFFFFFu)) | (e & (7u << 24)) | side;
-                       for (uint64_t m = 0; m < n_ind; m++)
-                           words[p + 1 + m] = (td.key_local + td.nbr[o + m]) | ((uint32_t)OP_RWIND << 24) | side;
-                   });
+        const uint64_t base = bucket_base(td, cd, chunk_pos, c);
+        walk_chunk(td, cd, base, true, S, [&](uint32_t q, uint64_t p, uint64_t i, uint32_t e, uint32_t y) {
+            if (p < lo || p >= hi) { // the events changed since the batch was sized
+                report_bad(td.ctl, i);
+                return;
+            }
+            const uint32_t side = e & (1u << 27);
+            words[p] = q == 0 ? (td.key_local + (e & 0xFFFFFFu)) | (e & (7u << 24)) | side
+                              : (td.key_local + y) | ((uint32_t)OP_RWIND << 24) | side;
+        });
         if (cd.start + cd.len == td.n) {
             // the trace's last chunk: slots its items leave in the range (only when the
             // events changed since the batch was sized) get a no-op on its first key
-            const uint64_t end = td.item_base + td.n + (chunk_pos[c + 1] - induced0);
-            if (end < hi && threadIdx.x == 0)
+            const uint64_t end = td.item_base + td.n + (chunk_pos[c + 1] - chunk_pos[td.first_chunk]);
+            if (end < hi && lane_id() == 0)
                 report_bad(td.ctl, cd.start);
-            for (uint64_t p = (end > lo ? end : lo) + threadIdx.x; p < hi; p += BLOCK)
+            for (uint64_t p = (end > lo ? end : lo) + lane_id(); p < hi; p += WAVE)
                 words[p] = td.key_local | ((uint32_t)OP_NOOP << 24);
         }
     }
@@ -204,94 +297,30 @@ __global__ __launch_bounds__(BLOCK) void k_batch_chunk_gather(const TraceDesc *_
                                                               uint8_t *__restrict__ status_all,
                                                               unsigned long long *__restrict__ ind)
 {
-    __shared__ uint32_t s_tmp[BLOCK / WAVE];
-    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    __shared__ ChunkStage s_stage[CH_WAVES];
+    ChunkStage &S = s_stage[wave_index()];
+    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+         c += (uint64_t)gridDim.x * CH_WAVES) {
         const ChunkDesc cd = ch[c];
-        const TraceDesc &td = d[cd.trace];
+        const TraceDesc td = d[cd.trace];
         const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
-        const uint64_t shift = (td.item_base + chunk_pos[c]) - (td.ev_base + chunk_pos[td.first_chunk]);
         uint32_t stuck = 0;
-        walk_chunk(td, cd, shift, s_tmp, false,
-                   [&](uint64_t, uint64_t g, uint64_t p, uint32_t, uint64_t n_ind, uint64_t) {
-                       if (p < lo || p + n_ind >= hi)
+        walk_chunk(td, cd, bucket_base(td, cd, chunk_pos, c), false, S,
+                   [&](uint32_t q, uint64_t p, uint64_t i, uint32_t, uint32_t) {
+                       if (p < lo || p >= hi)
                            return; // reported by the word pass
-                       status_all[g] = comb[p];
-                       for (uint64_t m = 1; m <= n_ind; m++)
-                           stuck += comb[p + m] >> 7;
+                       const uint8_t v = comb[p];
+                       if (q == 0) {
+                           status_all[td.ev_base + i] = v;
+                           td.status[i] = v;
+                       } else {
+                           stuck += v >> 7;
+                       }
                    });
-        if (td.off) { // uniform per workgroup
-            const uint32_t ex = block_excl_sum(stuck, s_tmp);
-            if (threadIdx.x == BLOCK - 1 && ex + stuck)
-                atomicAdd(&ind[cd.trace], (unsigned long long)(ex + stuck));
-        }
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void k_batch_chunk_emit(const TraceDesc *__restrict__ d,
-                                                            const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
-                                                            const uint64_t *__restrict__ chunk_pos,
-                                                            uint64_t *__restrict__ items, uint64_t cap)
-{
-    __shared__ uint32_t s_tmp[BLOCK / WAVE];
-    const uint32_t tid = threadIdx.x;
-    for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-        const ChunkDesc cd = ch[c];
-        const uint32_t t = cd.trace;
-        const TraceDesc &td = d[t];
-        const uint64_t shift = chunk_pos[c];
-        if (!td.off) {
-            // every item at its event's global index plus the chunk's shift; coalesced
-            for (uint32_t j = tid; j < cd.len; j += BLOCK) {
-                const uint64_t i = cd.start + j, g = td.ev_base + i;
-                const uint32_t e = td.events[i];
-                uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
-                if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
-                    report_bad(td.ctl, i);
-                    x = 0;
-                    op = OP_NOOP;
-                }
-                const uint64_t p = g + shift;
-                if (p < cap)
-                    items[p] = make_item(td.key_base + x, fcode(op, side), (uint32_t)g);
-                else
-                    report_bad(td.ctl, i);
-            }
-            continue;
-        }
-        // thread tid owns CH_ITEMS consecutive events; their induced counts are scanned
-        // over the workgroup to place each event's items
-        const uint32_t j0 = tid * CH_ITEMS;
-        uint32_t ev[CH_ITEMS], k = 0;
-#pragma unroll
-        for (int q = 0; q < CH_ITEMS; q++) {
-            const uint32_t j = j0 + q;
-            ev[q] = j < cd.len ? td.events[cd.start + j] : (OP_NOOP << 24);
-            k += j < cd.len ? induced_of(td, ev[q]) : 0u;
-        }
-        uint64_t p = td.ev_base + cd.start + j0 + shift + block_excl_sum(k, s_tmp);
-#pragma unroll
-        for (int q = 0; q < CH_ITEMS; q++) {
-            const uint32_t j = j0 + q;
-            if (j >= cd.len)
-                break;
-            const uint64_t i = cd.start + j, g = td.ev_base + i;
-            const uint32_t e = ev[q];
-            uint32_t x = e & 0xFFFFFFu, op = (e >> 24) & 7u, side = (e >> 27) & 1u;
-            if ((e >> 28) != 0 || op > OP_NOOP || x >= td.n_ids) {
-                report_bad(td.ctl, i);
-                x = 0;
-                op = OP_NOOP;
-            }
-            const uint64_t n_ind = op == OP_W ? td.off[x + 1] - td.off[x] : 0;
-            if (p + n_ind >= cap) {
-                report_bad(td.ctl, i);
-                continue;
-            }
-            items[p] = make_item(td.key_base + x, fcode(op, side), (uint32_t)g);
-            const uint64_t o = td.off[x];
-            for (uint64_t m = 0; m < n_ind; m++)
-                items[p + 1 + m] = make_item(td.key_base + td.nbr[o + m], fcode(OP_RWIND, side), INDUCED_BIT | t);
-            p += 1 + n_ind;
+        if (td.off) { // uniform per wave
+            const uint32_t k = wave_total_u32(stuck);
+            if (lane_id() == 0 && k)
+                atomicAdd(&ind[cd.trace], (unsigned long long)k);
         }
     }
 }
@@ -306,8 +335,9 @@ __global__ __launch_bounds__(BLOCK) void k_batch_distribute(const TraceDesc *__r
 {
     const TraceDesc &td = d[blockIdx.x];
     const uint32_t tid = threadIdx.x;
-    for (uint64_t i = tid; i < td.n; i += BLOCK)
-        td.status[i] = status_all[td.ev_base + i];
+    if (status_all)
+        for (uint64_t i = tid; i < td.n; i += BLOCK)
+            td.status[i] = status_all[td.ev_base + i];
     for (uint64_t k = tid; k < td.n_ids; k += BLOCK)
         td.fin[k] = fin_all[td.key_base + k];
     __shared__ uint64_t s_lo, s_hi;
@@ -371,7 +401,7 @@ void launch_batch_chunk_count(const TraceDesc *d, const ChunkDesc *ch, uint64_t 
 {
     if (n_chunks) {
         ProfScope prof_(s, "batch_chunk_count");
-        k_batch_chunk_count<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_cnt);
+        k_batch_chunk_count<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_cnt);
     }
 }
 
@@ -380,7 +410,7 @@ void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n
 {
     if (n_chunks) {
         ProfScope prof_(s, "batch_chunk_emit");
-        k_batch_chunk_emit<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, items, cap);
+        k_batch_chunk_emit<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, items, cap);
     }
 }
 
@@ -389,7 +419,7 @@ void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t 
 {
     if (n_chunks) {
         ProfScope prof_(s, "batch_chunk_words");
-        k_batch_chunk_words<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, words, cap);
+        k_batch_chunk_words<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, words, cap);
     }
 }
 
@@ -399,7 +429,7 @@ void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t
 {
     if (n_chunks) {
         ProfScope prof_(s, "batch_chunk_gather");
-        k_batch_chunk_gather<<<gridn(n_chunks, 1), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, comb, cap, status_all,
+        k_batch_chunk_gather<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, comb, cap, status_all,
                                                                   ind);
     }
 }
