@@ -21,17 +21,21 @@ namespace {
 
 constexpr EffectTable TABLE = make_table();
 
+// a resume point: program-relative word offsets, 16-bit when every program is shorter
+// than 2^16 words (half the LDS per lane: more waves in flight)
+template <class T>
 struct Frame {
-    uint32_t resume, end; // program-relative word offsets
+    T resume, end;
 };
 
+template <class T>
 __global__ __launch_bounds__(PROG_BLOCK) void k_run_programs(
     const uint64_t *__restrict__ prog_off, uint64_t n_prog, const uint32_t *__restrict__ words, uint32_t n_vars,
     const uint64_t *__restrict__ choice, const uint8_t *__restrict__ init, uint64_t fuel,
     uint64_t *__restrict__ steps_out, uint64_t *__restrict__ effects_out, uint64_t *__restrict__ stuck_out,
     uint64_t *__restrict__ first_out, uint8_t *__restrict__ done_out, uint8_t *__restrict__ final_out)
 {
-    __shared__ Frame s_stack[PROG_DEPTH][PROG_BLOCK];
+    __shared__ Frame<T> s_stack[PROG_DEPTH][PROG_BLOCK];
     __shared__ uint32_t s_f4[16], s_stuck[16];
     if (threadIdx.x < 16) {
         s_f4[threadIdx.x] = TABLE.f4[threadIdx.x];
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(PROG_BLOCK) void k_run_programs(
             const uint32_t n = w[pc + 1];
             if (kind == 1) { // While-True enters the body, resuming at the header
                 if (c) {
-                    s_stack[depth][me] = Frame{pc, end};
+                    s_stack[depth][me] = Frame<T>{(T)pc, (T)end};
                     depth++;
                     end = pc + 2 + n;
                     pc = pc + 2;
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(PROG_BLOCK) void k_run_programs(
                 }
             } else { // IF-True / IF-False: the branch, resuming after the If
                 const uint32_t m2 = w[pc + 2];
-                s_stack[depth][me] = Frame{pc + 3 + n + m2, end};
+                s_stack[depth][me] = Frame<T>{(T)(pc + 3 + n + m2), (T)end};
                 depth++;
                 end = c ? pc + 3 + n : pc + 3 + n + m2;
                 pc = c ? pc + 3 : pc + 3 + n;
@@ -129,15 +133,19 @@ __global__ __launch_bounds__(PROG_BLOCK) void k_run_programs(
 void launch_run_programs(const uint64_t *prog_off, uint64_t n_prog, const uint32_t *words, uint32_t n_vars,
                          const uint64_t *choice, const uint8_t *init, uint64_t fuel, uint64_t *steps,
                          uint64_t *effects, uint64_t *stuck, uint64_t *first, uint8_t *done, uint8_t *final_out,
-                         hipStream_t s)
+                         bool short_programs, hipStream_t s)
 {
     if (!n_prog)
         return;
     uint64_t g = ceil_div(n_prog, PROG_BLOCK);
     const unsigned grid = (unsigned)(g > 65535 ? 65535 : g);
     ProfScope p(s, "run_programs");
-    k_run_programs<<<grid, PROG_BLOCK, 0, s>>>(prog_off, n_prog, words, n_vars, choice, init, fuel, steps, effects,
-                                               stuck, first, done, final_out);
+    if (short_programs)
+        k_run_programs<uint16_t><<<grid, PROG_BLOCK, 0, s>>>(prog_off, n_prog, words, n_vars, choice, init, fuel, steps,
+                                                             effects, stuck, first, done, final_out);
+    else
+        k_run_programs<uint32_t><<<grid, PROG_BLOCK, 0, s>>>(prog_off, n_prog, words, n_vars, choice, init, fuel, steps,
+                                                             effects, stuck, first, done, final_out);
 }
 
 } // namespace vc

@@ -2,6 +2,7 @@
 // syntax trees on the host, device buffers, launch and read-back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "abi_internal.h"
@@ -13,13 +14,14 @@ namespace vc {
 void launch_run_programs(const uint64_t *prog_off, uint64_t n_prog, const uint32_t *words, uint32_t n_vars,
                          const uint64_t *choice, const uint8_t *init, uint64_t fuel, uint64_t *steps,
                          uint64_t *effects, uint64_t *stuck, uint64_t *first, uint8_t *done, uint8_t *final_out,
-                         hipStream_t s);
+                         bool short_programs, hipStream_t s);
 }
 
 struct vc_programs {
     vc_ctx *ctx = nullptr;
     uint64_t n_prog = 0, n_words = 0, fuel = 0;
     uint32_t n_vars = 0;
+    bool short_programs = false; // every program shorter than 2^16 words
     uint64_t *prog_off = nullptr, *choice = nullptr;
     uint32_t *words = nullptr;
     uint8_t *init = nullptr;
@@ -100,7 +102,7 @@ extern "C" int vc_programs_run(vc_programs *p)
     ProfGuard pg(p->ctx);
     const uint64_t n = p->n_prog;
     launch_run_programs(p->prog_off, n, p->words, p->n_vars, p->choice, p->init, p->fuel, p->out, p->out + n,
-                        p->out + 2 * n, p->out + 3 * n, p->done, p->fin, p->ctx->stream);
+                        p->out + 2 * n, p->out + 3 * n, p->done, p->fin, p->short_programs, p->ctx->stream);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? VC_OK : vc_hip_fail(e, "kernel launch");
 }
@@ -115,9 +117,11 @@ extern "C" int vc_run_programs(vc_ctx *c, const uint64_t *prog_off, uint64_t n_p
         return vc_fail(VC_EINVAL, "vc_run_programs: n_vars %u must be in [1, 64]", n_vars);
     if (prog_off[0] != 0)
         return vc_fail(VC_EINVAL, "vc_run_programs: offsets must start at 0");
+    uint64_t longest = 0;
     for (uint64_t i = 0; i < n_prog; i++) {
         if (prog_off[i + 1] < prog_off[i] || prog_off[i + 1] - prog_off[i] >= (1ull << 31))
             return vc_fail(VC_EINVAL, "vc_run_programs: offsets of program %llu", (unsigned long long)i);
+        longest = std::max<uint64_t>(longest, prog_off[i + 1] - prog_off[i]);
         uint64_t bad = 0;
         if (!valid_block(words, prog_off[i], prog_off[i + 1], n_vars, 0, &bad))
             return vc_fail(VC_EINVAL, "malformed program word at index %llu", (unsigned long long)bad);
@@ -134,6 +138,7 @@ extern "C" int vc_run_programs(vc_ctx *c, const uint64_t *prog_off, uint64_t n_p
     p->n_words = prog_off[n_prog];
     p->n_vars = n_vars;
     p->fuel = fuel;
+    p->short_programs = longest < (1ull << 16);
     int r;
     if ((r = upload(&p->prog_off, prog_off, n_prog + 1)) != VC_OK || (r = upload(&p->words, words, p->n_words)) != VC_OK ||
         (choice && (r = upload(&p->choice, choice, n_prog)) != VC_OK) ||
