@@ -140,67 +140,131 @@ __global__ void k_wd_decls(const uint64_t *__restrict__ comp_off, uint64_t n_com
     }
 }
 
-// the component of body event j: the last c with body_off[c] <= j (non-empty components)
-__device__ __forceinline__ uint64_t comp_of(const uint64_t *body_off, uint64_t n_comp, uint64_t j)
+// body event j of component c (declarations [a, b)): its conditions, and its coverage
+// bit when it writes an obliged variable
+__device__ __forceinline__ void check_body_event(uint64_t c, uint64_t a, uint64_t b, uint64_t j,
+                                                 const uint32_t *__restrict__ decls, const uint32_t *__restrict__ body,
+                                                 const uint32_t *__restrict__ idx, uint32_t n_vars,
+                                                 const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
+                                                 const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
+                                                 bool ext, const uint64_t *__restrict__ boff, uint32_t *__restrict__ bits,
+                                                 uint64_t nbits, uint32_t *__restrict__ verdict, Control *ctl,
+                                                 uint64_t n_decl_total)
 {
-    uint64_t lo_c = 0, hi_c = n_comp; // body_off[lo_c] <= j < body_off[hi_c]
-    while (hi_c - lo_c > 1) {
-        const uint64_t mid = (lo_c + hi_c) / 2;
-        if (body_off[mid] <= j)
-            lo_c = mid;
-        else
-            hi_c = mid;
+    const uint32_t e = body[j], x = e & 0xFFFFFFu, op = (e >> 24) & 7u, s = (e >> 27) & 1u;
+    const uint32_t i = idx ? idx[j] : 0u;
+    if ((e >> 28) != 0 || op > OP_NOOP || x >= n_vars || (lo ? i >= hi[x] - lo[x] : i != 0)) {
+        report_key(ctl, c, 1, j);
+        return;
     }
-    return lo_c;
+    if (b < a || b > n_decl_total) // reported by the declaration pass
+        return;
+    uint32_t v = 0;
+    if (op == OP_PUSH || op == OP_PULL)
+        v |= WD_TRANSFER;
+    if (op == OP_R && !readable(decls, a, b, x, s, lo, hi, ext))
+        v |= WD_READ;
+    if (op == OP_W) {
+        if (!writable(decls, a, b, x, s, lo, hi, ext))
+            v |= WD_WRITE;
+        if (lo) {
+            // the naive rule: every other array holding the written cell
+            const uint32_t addr = lo[x] + i;
+            for (uint64_t q = off[x]; q < off[x + 1]; q++) {
+                const uint32_t y = nbr[q];
+                if (lo[y] <= addr && addr < hi[y] && !writable(decls, a, b, y, s, lo, hi, ext))
+                    v |= WD_OVERLAP;
+            }
+        }
+        const uint64_t d = find_decl(decls, a, b, x, s);
+        if (d < b && obliged(decls, a, b, d, lo, hi, ext)) {
+            const uint64_t bit = boff[d] + i;
+            if (bit < nbits)
+                atomicOr(&bits[bit >> 5], 1u << (bit & 31u));
+        }
+    }
+    if (v)
+        atomicOr(&verdict[c], v);
 }
 
-// per body event: its conditions, and its coverage bit when it writes an obliged variable
-__global__ void k_wd_body(const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls,
-                          const uint64_t *__restrict__ body_off, const uint32_t *__restrict__ body, uint64_t n_body,
-                          const uint32_t *__restrict__ idx, uint32_t n_vars, const uint32_t *__restrict__ lo,
-                          const uint32_t *__restrict__ hi, const uint64_t *__restrict__ off,
-                          const uint32_t *__restrict__ nbr, int extend, const uint64_t *__restrict__ boff,
-                          uint32_t *__restrict__ bits, uint64_t nbits, uint32_t *__restrict__ verdict, Control *ctl)
+// Body events by wave tiles of 64 components (one per lane): the lengths of the
+// components' body ranges are scanned over the wave (components with an empty or
+// malformed range take no slot; a malformed range is reported), and the tile's body
+// events are walked 64 consecutive ones at a time, the lane of each finding its
+// component from a ballot of the components' starts among the 64 slots.
+constexpr uint32_t WD_WAVES = BLOCK / WAVE;
+__global__ __launch_bounds__(BLOCK) void k_wd_body(const uint64_t *__restrict__ comp_off, uint64_t n_comp,
+                                                   const uint32_t *__restrict__ decls,
+                                                   const uint64_t *__restrict__ body_off,
+                                                   const uint32_t *__restrict__ body, uint64_t n_body,
+                                                   const uint32_t *__restrict__ idx, uint32_t n_vars,
+                                                   const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
+                                                   const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
+                                                   int extend, const uint64_t *__restrict__ boff,
+                                                   uint32_t *__restrict__ bits, uint64_t nbits,
+                                                   uint32_t *__restrict__ verdict, Control *ctl)
 {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    struct Tile {
+        uint32_t start[WAVE + 1]; // tile-relative first slot of the r-th non-empty component
+        uint32_t lane[WAVE];      // its lane
+        uint64_t bo[WAVE];        // its first body event
+        uint32_t mark[WAVE];
+    };
+    __shared__ Tile s_tiles[WD_WAVES];
+    const uint32_t lane = lane_id(), wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    Tile &T = s_tiles[wv];
     const bool ext = extend != 0 && lo;
-    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_body; j += stride) {
-        const uint64_t c = comp_of(body_off, n_comp, j);
-        const uint64_t a = comp_off[c], b = comp_off[c + 1];
-        const uint32_t e = body[j], x = e & 0xFFFFFFu, op = (e >> 24) & 7u, s = (e >> 27) & 1u;
-        const uint32_t i = idx ? idx[j] : 0u;
-        if ((e >> 28) != 0 || op > OP_NOOP || x >= n_vars || (lo ? i >= hi[x] - lo[x] : i != 0)) {
-            report_key(ctl, c, 1, j);
-            continue;
+    const uint64_t n_decl_total = comp_off[n_comp];
+    const uint64_t ntiles = ceil_div(n_comp, (uint64_t)WAVE);
+    for (uint64_t tile = (uint64_t)blockIdx.x * WD_WAVES + wv; tile < ntiles; tile += (uint64_t)gridDim.x * WD_WAVES) {
+        const uint64_t c = tile * WAVE + lane;
+        uint64_t a = 0, b = 0, j0 = 0;
+        uint32_t len = 0;
+        if (c < n_comp) {
+            a = comp_off[c];
+            b = comp_off[c + 1];
+            j0 = body_off[c];
+            const uint64_t j1 = body_off[c + 1];
+            if (j1 < j0 || j1 > n_body)
+                report_key(ctl, c, 1, j0);
+            else
+                len = (uint32_t)(j1 - j0); // below 2^32 (n_body < 2^32)
         }
-        if (b < a || b > comp_off[n_comp]) // reported by the declaration pass
-            continue;
-        uint32_t v = 0;
-        if (op == OP_PUSH || op == OP_PULL)
-            v |= WD_TRANSFER;
-        if (op == OP_R && !readable(decls, a, b, x, s, lo, hi, ext))
-            v |= WD_READ;
-        if (op == OP_W) {
-            if (!writable(decls, a, b, x, s, lo, hi, ext))
-                v |= WD_WRITE;
-            if (lo) {
-                // the naive rule: every other array holding the written cell
-                const uint32_t addr = lo[x] + i;
-                for (uint64_t q = off[x]; q < off[x + 1]; q++) {
-                    const uint32_t y = nbr[q];
-                    if (lo[y] <= addr && addr < hi[y] && !writable(decls, a, b, y, s, lo, hi, ext))
-                        v |= WD_OVERLAP;
-                }
-            }
-            const uint64_t d = find_decl(decls, a, b, x, s);
-            if (d < b && obliged(decls, a, b, d, lo, hi, ext)) {
-                const uint64_t bit = boff[d] + i;
-                if (bit < nbits)
-                    atomicOr(&bits[bit >> 5], 1u << (bit & 31u));
-            }
+        const uint64_t ne = __ballot(len > 0);
+        const uint32_t r = mask_rank(ne);
+        const uint32_t inc = wave_scan_add(len, lane);
+        const uint32_t total = __builtin_amdgcn_readlane(inc, WAVE - 1);
+        const uint32_t nne = (uint32_t)__builtin_popcountll(ne);
+        if (len > 0) {
+            T.start[r] = inc - len;
+            T.lane[r] = lane;
+            T.bo[r] = j0;
         }
-        if (v)
-            atomicOr(&verdict[c], v);
+        if (lane == 0)
+            T.start[nne] = total;
+        __builtin_amdgcn_wave_barrier();
+        uint32_t ec = 0; // the component (by rank) covering slot qc - 1
+        for (uint32_t qc = 0; qc < total; qc += WAVE) {
+            // ranks ec + 1 .. ec + 64 hold every start inside [qc, qc + 64)
+            const uint32_t e = ec + 1 + lane;
+            const uint32_t st = e <= nne ? T.start[e] : total;
+            T.mark[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (st < total && st < qc + WAVE)
+                T.mark[st - qc] = 1;
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t heads = __ballot(T.mark[lane] != 0);
+            const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
+            const uint32_t q = qc + lane;
+            // the owner's declaration range, from its lane
+            const uint32_t ol = q < total ? T.lane[own] : 0u;
+            const uint64_t oa = __shfl(a, (int)ol), ob = __shfl(b, (int)ol);
+            if (q < total)
+                check_body_event(tile * WAVE + ol, oa, ob, T.bo[own] + (q - T.start[own]), decls, body, idx, n_vars,
+                                 lo, hi, off, nbr, ext, boff, bits, nbits, verdict, ctl, n_decl_total);
+            ec += (uint32_t)__builtin_popcountll(heads);
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 }
 
@@ -252,7 +316,9 @@ void launch_wd_body(const uint64_t *comp_off, uint64_t n_comp, const uint32_t *d
 {
     if (n_body && n_comp) {
         ProfScope p(s, "wd_body");
-        k_wd_body<<<grid_w(n_body), BLOCK, 0, s>>>(comp_off, n_comp, decls, body_off, body, n_body, idx, n_vars, lo, hi,
+        const uint64_t tiles = ceil_div(n_comp, (uint64_t)WAVE * WD_WAVES);
+        k_wd_body<<<(unsigned)(tiles > 16384 ? 16384 : tiles), BLOCK, 0, s>>>(comp_off, n_comp, decls, body_off, body,
+                                                                             n_body, idx, n_vars, lo, hi,
                                                    o ? o->off : nullptr, o ? o->nbr : nullptr, extend ? 1 : 0, boff,
                                                    bits, nbits, verdict, ctl);
     }
