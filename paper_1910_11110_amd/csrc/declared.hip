@@ -33,54 +33,81 @@ __device__ __forceinline__ void report_key(Control *ctl, uint64_t c, uint32_t ki
     atomicMin(reinterpret_cast<unsigned long long *>(&ctl->err_index_lo), key);
 }
 
-__device__ __forceinline__ bool overlap_iv(const uint32_t *lo, const uint32_t *hi, uint32_t x, uint32_t y)
-{
-    return x != y && lo[x] < hi[y] && lo[y] < hi[x];
-}
 
 struct Decl {
     uint32_t var, mode, side;
 };
 __device__ __forceinline__ Decl decl_of(uint32_t w) { return Decl{w & 0xFFFFFFu, (w >> 24) & 3u, (w >> 27) & 1u}; }
 
+// A component's declarations with the intervals of their variables: read from global
+// memory (GlobalDecls) or staged in LDS for a tile of components (StagedDecls, with the
+// obligation of every declaration worked out when it is staged).
+// (a malformed declaration's variable, reported by the declaration pass, has the empty
+// interval [0, 0))
+struct GlobalDecls {
+    const uint32_t *w, *lo, *hi;
+    uint32_t n_vars;
+    __device__ __forceinline__ uint32_t word(uint64_t d) const { return w[d]; }
+    __device__ __forceinline__ uint32_t vlo(uint64_t d) const
+    {
+        const uint32_t x = w[d] & 0xFFFFFFu;
+        return x < n_vars ? lo[x] : 0u;
+    }
+    __device__ __forceinline__ uint32_t vhi(uint64_t d) const
+    {
+        const uint32_t x = w[d] & 0xFFFFFFu;
+        return x < n_vars ? hi[x] : 0u;
+    }
+};
+struct StagedDecls {
+    const uint32_t *w, *lo, *hi;
+    const uint8_t *obl;
+    __device__ __forceinline__ uint32_t word(uint64_t d) const { return w[d]; }
+    __device__ __forceinline__ uint32_t vlo(uint64_t d) const { return lo[d]; }
+    __device__ __forceinline__ uint32_t vhi(uint64_t d) const { return hi[d]; }
+};
+
 // the declaration of y on side s in M (index in [a, b)), or b if none
-__device__ __forceinline__ uint64_t find_decl(const uint32_t *decls, uint64_t a, uint64_t b, uint32_t y, uint32_t s)
+template <class D>
+__device__ __forceinline__ uint64_t find_decl(const D &M, uint64_t a, uint64_t b, uint32_t y, uint32_t s)
 {
     for (uint64_t d = a; d < b; d++) {
-        const Decl q = decl_of(decls[d]);
+        const Decl q = decl_of(M.word(d));
         if (q.var == y && q.side == s)
             return d;
     }
     return b;
 }
 
-// is y declared for writing (W or RW) on side s, in M or in O(M)
-__device__ __forceinline__ bool writable(const uint32_t *decls, uint64_t a, uint64_t b, uint32_t y, uint32_t s,
-                                         const uint32_t *lo, const uint32_t *hi, bool extend)
+// is y (interval [ylo, yhi)) declared for writing (W or RW) on side s, in M or in O(M)
+template <class D>
+__device__ __forceinline__ bool writable(const D &M, uint64_t a, uint64_t b, uint32_t y, uint32_t s, uint32_t ylo,
+                                         uint32_t yhi, bool extend)
 {
     bool ok = false;
     for (uint64_t d = a; d < b; d++) {
-        const Decl q = decl_of(decls[d]);
+        const Decl q = decl_of(M.word(d));
         if (q.side != s || q.mode == 0)
             continue;
-        ok |= q.var == y || (extend && overlap_iv(lo, hi, q.var, y));
+        ok |= q.var == y || (extend && M.vlo(d) < yhi && ylo < M.vhi(d));
     }
     return ok;
 }
 
-// is y declared for reading (R or RW) on side s, in M or in O(M)
-__device__ __forceinline__ bool readable(const uint32_t *decls, uint64_t a, uint64_t b, uint32_t y, uint32_t s,
-                                         const uint32_t *lo, const uint32_t *hi, bool extend)
+// is y (interval [ylo, yhi)) declared for reading (R or RW) on side s, in M or in O(M)
+template <class D>
+__device__ __forceinline__ bool readable(const D &M, uint64_t a, uint64_t b, uint32_t y, uint32_t s, uint32_t ylo,
+                                         uint32_t yhi, bool extend)
 {
     bool own_r = false, own_w = false, by_rw = false, by_w = false;
     for (uint64_t d = a; d < b; d++) {
-        const Decl q = decl_of(decls[d]);
+        const Decl q = decl_of(M.word(d));
         if (q.side != s)
             continue;
         if (q.var == y) {
             own_r |= q.mode == 0 || q.mode == 2;
             own_w |= q.mode == 1;
-        } else if (extend && overlap_iv(lo, hi, q.var, y)) {
+        } else if (extend && M.vlo(d) < yhi && ylo < M.vhi(d)) {
             by_rw |= q.mode == 2;
             by_w |= q.mode == 1;
         }
@@ -89,20 +116,29 @@ __device__ __forceinline__ bool readable(const uint32_t *decls, uint64_t a, uint
 }
 
 // W declaration d of component [a, b) that keeps its obligation (not upgraded)
-__device__ __forceinline__ bool obliged(const uint32_t *decls, uint64_t a, uint64_t b, uint64_t d,
-                                        const uint32_t *lo, const uint32_t *hi, bool extend)
+template <class D>
+__device__ __forceinline__ bool obliged_scan(const D &M, uint64_t a, uint64_t b, uint64_t d, bool extend)
 {
-    const Decl q = decl_of(decls[d]);
+    const Decl q = decl_of(M.word(d));
     if (q.mode != 1)
         return false;
     if (!extend)
         return true;
+    const uint32_t qlo = M.vlo(d), qhi = M.vhi(d);
     for (uint64_t e = a; e < b; e++) {
-        const Decl r = decl_of(decls[e]);
-        if (r.side == q.side && r.mode == 2 && overlap_iv(lo, hi, r.var, q.var))
+        const Decl r = decl_of(M.word(e));
+        if (r.side == q.side && r.mode == 2 && r.var != q.var && M.vlo(e) < qhi && qlo < M.vhi(e))
             return false;
     }
     return true;
+}
+__device__ __forceinline__ bool obliged(const GlobalDecls &M, uint64_t a, uint64_t b, uint64_t d, bool extend)
+{
+    return obliged_scan(M, a, b, d, extend);
+}
+__device__ __forceinline__ bool obliged(const StagedDecls &M, uint64_t, uint64_t, uint64_t d, bool)
+{
+    return M.obl[d] != 0;
 }
 
 // per component: declarations checked (as the translation does), and the number of
@@ -131,7 +167,7 @@ __global__ void k_wd_decls(const uint64_t *__restrict__ comp_off, uint64_t n_com
         }
         for (uint64_t d = a; d < b; d++) {
             uint32_t len = 0;
-            if (!bad && obliged(decls, a, b, d, lo, hi, extend != 0 && lo)) {
+            if (!bad && obliged(GlobalDecls{decls, lo, hi, n_vars}, a, b, d, extend != 0 && lo)) {
                 const uint32_t x = decls[d] & 0xFFFFFFu;
                 len = lo ? hi[x] - lo[x] : 1u;
             }
@@ -140,45 +176,48 @@ __global__ void k_wd_decls(const uint64_t *__restrict__ comp_off, uint64_t n_com
     }
 }
 
-// body event j of component c (declarations [a, b)): its conditions, and its coverage
-// bit when it writes an obliged variable
-__device__ __forceinline__ void check_body_event(uint64_t c, uint64_t a, uint64_t b, uint64_t j,
-                                                 const uint32_t *__restrict__ decls, const uint32_t *__restrict__ body,
+// body event j of component c (declarations [a, b) of M, whose index d is declaration
+// db + d of the program): its conditions, and its coverage bit when it writes an obliged
+// variable
+template <class D>
+__device__ __forceinline__ void check_body_event(uint64_t c, const D &M, uint64_t a, uint64_t b, uint64_t db,
+                                                 uint64_t j, const uint32_t *__restrict__ body,
                                                  const uint32_t *__restrict__ idx, uint32_t n_vars,
                                                  const uint32_t *__restrict__ lo, const uint32_t *__restrict__ hi,
                                                  const uint64_t *__restrict__ off, const uint32_t *__restrict__ nbr,
                                                  bool ext, const uint64_t *__restrict__ boff, uint32_t *__restrict__ bits,
                                                  uint64_t nbits, uint32_t *__restrict__ verdict, Control *ctl,
-                                                 uint64_t n_decl_total)
+                                                 bool decls_ok)
 {
     const uint32_t e = body[j], x = e & 0xFFFFFFu, op = (e >> 24) & 7u, s = (e >> 27) & 1u;
     const uint32_t i = idx ? idx[j] : 0u;
-    if ((e >> 28) != 0 || op > OP_NOOP || x >= n_vars || (lo ? i >= hi[x] - lo[x] : i != 0)) {
+    const uint32_t xlo = lo && x < n_vars ? lo[x] : 0u, xhi = lo && x < n_vars ? hi[x] : 1u;
+    if ((e >> 28) != 0 || op > OP_NOOP || x >= n_vars || (lo ? i >= xhi - xlo : i != 0)) {
         report_key(ctl, c, 1, j);
         return;
     }
-    if (b < a || b > n_decl_total) // reported by the declaration pass
+    if (!decls_ok) // a malformed declaration range, reported by the declaration pass
         return;
     uint32_t v = 0;
     if (op == OP_PUSH || op == OP_PULL)
         v |= WD_TRANSFER;
-    if (op == OP_R && !readable(decls, a, b, x, s, lo, hi, ext))
+    if (op == OP_R && !readable(M, a, b, x, s, xlo, xhi, ext))
         v |= WD_READ;
     if (op == OP_W) {
-        if (!writable(decls, a, b, x, s, lo, hi, ext))
+        if (!writable(M, a, b, x, s, xlo, xhi, ext))
             v |= WD_WRITE;
         if (lo) {
             // the naive rule: every other array holding the written cell
-            const uint32_t addr = lo[x] + i;
+            const uint32_t addr = xlo + i;
             for (uint64_t q = off[x]; q < off[x + 1]; q++) {
-                const uint32_t y = nbr[q];
-                if (lo[y] <= addr && addr < hi[y] && !writable(decls, a, b, y, s, lo, hi, ext))
+                const uint32_t y = nbr[q], ylo = lo[y], yhi = hi[y];
+                if (ylo <= addr && addr < yhi && !writable(M, a, b, y, s, ylo, yhi, ext))
                     v |= WD_OVERLAP;
             }
         }
-        const uint64_t d = find_decl(decls, a, b, x, s);
-        if (d < b && obliged(decls, a, b, d, lo, hi, ext)) {
-            const uint64_t bit = boff[d] + i;
+        const uint64_t d = find_decl(M, a, b, x, s);
+        if (d < b && obliged(M, a, b, d, ext)) {
+            const uint64_t bit = boff[db + d] + i;
             if (bit < nbits)
                 atomicOr(&bits[bit >> 5], 1u << (bit & 31u));
         }
@@ -191,8 +230,12 @@ __device__ __forceinline__ void check_body_event(uint64_t c, uint64_t a, uint64_
 // components' body ranges are scanned over the wave (components with an empty or
 // malformed range take no slot; a malformed range is reported), and the tile's body
 // events are walked 64 consecutive ones at a time, the lane of each finding its
-// component from a ballot of the components' starts among the 64 slots.
+// component from a ballot of the components' starts among the 64 slots.  The tile's
+// declarations (consecutive in the program) are staged in LDS with the intervals of
+// their variables and their obligations, unless they are more than WD_STAGE or their
+// offsets are malformed; then the checks read them from global memory.
 constexpr uint32_t WD_WAVES = BLOCK / WAVE;
+constexpr uint32_t WD_STAGE = 512;
 __global__ __launch_bounds__(BLOCK) void k_wd_body(const uint64_t *__restrict__ comp_off, uint64_t n_comp,
                                                    const uint32_t *__restrict__ decls,
                                                    const uint64_t *__restrict__ body_off,
@@ -209,6 +252,8 @@ __global__ __launch_bounds__(BLOCK) void k_wd_body(const uint64_t *__restrict__ 
         uint32_t lane[WAVE];      // its lane
         uint64_t bo[WAVE];        // its first body event
         uint32_t mark[WAVE];
+        uint32_t w[WD_STAGE], dlo[WD_STAGE], dhi[WD_STAGE]; // staged declarations
+        uint8_t obl[WD_STAGE];
     };
     __shared__ Tile s_tiles[WD_WAVES];
     const uint32_t lane = lane_id(), wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
@@ -216,8 +261,11 @@ __global__ __launch_bounds__(BLOCK) void k_wd_body(const uint64_t *__restrict__ 
     const bool ext = extend != 0 && lo;
     const uint64_t n_decl_total = comp_off[n_comp];
     const uint64_t ntiles = ceil_div(n_comp, (uint64_t)WAVE);
+    const GlobalDecls G{decls, lo, hi, n_vars};
+    const StagedDecls S{T.w, T.dlo, T.dhi, T.obl};
     for (uint64_t tile = (uint64_t)blockIdx.x * WD_WAVES + wv; tile < ntiles; tile += (uint64_t)gridDim.x * WD_WAVES) {
-        const uint64_t c = tile * WAVE + lane;
+        const uint64_t c0 = tile * WAVE, c = c0 + lane;
+        const uint32_t nc = (uint32_t)(n_comp - c0 < (uint64_t)WAVE ? n_comp - c0 : (uint64_t)WAVE);
         uint64_t a = 0, b = 0, j0 = 0;
         uint32_t len = 0;
         if (c < n_comp) {
@@ -229,6 +277,26 @@ __global__ __launch_bounds__(BLOCK) void k_wd_body(const uint64_t *__restrict__ 
                 report_key(ctl, c, 1, j0);
             else
                 len = (uint32_t)(j1 - j0); // below 2^32 (n_body < 2^32)
+        }
+        const bool ok = c >= n_comp || (a <= b && b <= n_decl_total);
+        // stage the tile's declarations [A, B) when the offsets are well formed: every
+        // component's range starts where the one before it ends
+        const uint64_t A = __shfl(a, 0), B = __shfl(b, (int)(nc - 1));
+        const uint64_t prev_b = __shfl(b, (int)(lane ? lane - 1 : 0));
+        const bool inside = c >= n_comp || (ok && (lane == 0 || a == prev_b));
+        const bool staged = __ballot(!inside) == 0 && A <= B && B - A <= (uint64_t)WD_STAGE;
+        if (staged) {
+            const uint32_t nd = (uint32_t)(B - A);
+            for (uint32_t k = lane; k < nd; k += WAVE) {
+                const uint32_t w = decls[A + k], x = w & 0xFFFFFFu;
+                T.w[k] = w;
+                T.dlo[k] = lo && x < n_vars ? lo[x] : 0u;
+                T.dhi[k] = lo && x < n_vars ? hi[x] : 0u;
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (c < n_comp)
+                for (uint64_t d = a - A; d < b - A; d++)
+                    T.obl[d] = obliged_scan(S, a - A, b - A, d, ext) ? 1 : 0;
         }
         const uint64_t ne = __ballot(len > 0);
         const uint32_t r = mask_rank(ne);
@@ -259,9 +327,16 @@ __global__ __launch_bounds__(BLOCK) void k_wd_body(const uint64_t *__restrict__ 
             // the owner's declaration range, from its lane
             const uint32_t ol = q < total ? T.lane[own] : 0u;
             const uint64_t oa = __shfl(a, (int)ol), ob = __shfl(b, (int)ol);
-            if (q < total)
-                check_body_event(tile * WAVE + ol, oa, ob, T.bo[own] + (q - T.start[own]), decls, body, idx, n_vars,
-                                 lo, hi, off, nbr, ext, boff, bits, nbits, verdict, ctl, n_decl_total);
+            const bool ook = __shfl(ok ? 1 : 0, (int)ol) != 0;
+            if (q < total) {
+                const uint64_t j = T.bo[own] + (q - T.start[own]);
+                if (staged)
+                    check_body_event(c0 + ol, S, oa - A, ob - A, A, j, body, idx, n_vars, lo, hi, off, nbr, ext, boff,
+                                     bits, nbits, verdict, ctl, true);
+                else
+                    check_body_event(c0 + ol, G, oa, ob, 0, j, body, idx, n_vars, lo, hi, off, nbr, ext, boff, bits,
+                                     nbits, verdict, ctl, ook);
+            }
             ec += (uint32_t)__builtin_popcountll(heads);
             __builtin_amdgcn_wave_barrier();
         }
