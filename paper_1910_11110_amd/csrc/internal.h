@@ -199,8 +199,9 @@ void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint
 void launch_items_k(const uint32_t *ev, uint64_t n, uint32_t n_ids, uint32_t k, uint64_t *items, Control *ctl,
                     hipStream_t s);
 size_t spaces_scan_scratch_bytes(uint64_t n);
-// sorted k-space items -> st16[i] = post | pre << 4 | stuck << 15, flag[i] = stuck << 7,
-// final[var] = last post (fin must hold the initial statuses of untouched variables)
+// sorted k-space items -> st16[i] = post | pre << 4 | stuck << 15, then flag[i] = stuck
+// << 7 in a pass of its own, final[var] = last post (fin must hold the initial statuses
+// of untouched variables); st16 and flag 16-byte and 8-byte aligned
 void launch_segscan_k(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, uint16_t *st16,
                       uint8_t *flag, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s);
 

@@ -35,33 +35,37 @@ __device__ __forceinline__ uint32_t kf_of(uint32_t ob)
     return KF_ID;
 }
 
-// the locations a set reaches through a relation (rows selected by the set)
+// the locations a set reaches through a relation (the rows the set selects): each bit a
+// of the set is spread to a mask of row a (bit a to bit 4a, times 15), and the selected
+// rows are folded together
 __device__ __forceinline__ uint32_t kf_reach(uint32_t rel, uint32_t s)
 {
-    uint32_t r = 0;
-#pragma unroll
-    for (uint32_t a = 0; a < 4; a++)
-        r |= ((rel >> (4u * a)) & 15u) & (0u - ((s >> a) & 1u));
-    return r;
+    const uint32_t t = (s | (s << 3) | (s << 6) | (s << 9)) & 0x1111u;
+    uint32_t r = rel & (t * 15u);
+    r |= r >> 8;
+    r |= r >> 4;
+    return r & 15u;
 }
 
 __device__ __forceinline__ uint32_t kf_apply(uint32_t f, uint32_t s)
 {
-    return (f & KF_CONST) ? (f & 15u) : (s | kf_reach(f, s));
+    return (f & KF_CONST) ? (f & 15u) : (s | kf_reach(f & 0xFFFFu, s));
 }
 
-// g o f (f first)
+// g o f (f first).  For two relations, row a of the product is the union of the rows b
+// of g that row a of f selects: column b of f (bits 4a + b, shifted to 4a) times row b
+// of g places row b of g in every row a that selects it, without carries.
 __device__ __forceinline__ uint32_t kf_compose(uint32_t g, uint32_t f)
 {
     if (g & KF_CONST)
         return g;
     if (f & KF_CONST)
         return KF_CONST | kf_apply(g, f & 15u);
-    uint32_t r = f | g;
+    uint32_t p = 0;
 #pragma unroll
-    for (uint32_t a = 0; a < 4; a++)
-        r |= kf_reach(g, (f >> (4u * a)) & 15u) << (4u * a);
-    return r;
+    for (uint32_t b = 0; b < 4; b++)
+        p |= ((f >> b) & 0x1111u) * ((g >> (4u * b)) & 15u);
+    return f | g | p;
 }
 
 // stuck: a read at a, or a copy from a, with location a invalid
@@ -153,11 +157,12 @@ constexpr int KTILE = BLOCK * KITEMS;
 constexpr int KPAD = 16;
 __device__ __forceinline__ uint32_t kpad(uint32_t i) { return i + i / KPAD; }
 
-// sorted items -> status16[payload] = post | pre << 4 | stuck << 15, flag[payload] =
-// stuck << 7 (for the compaction), final[var] = the last post of each variable
+// sorted items -> status16[payload] = post | pre << 4 | stuck << 15 (one scattered
+// store per item: these stores to program order cost most of the scan), final[var] =
+// the last post of each variable
 __global__ __launch_bounds__(BLOCK) void k_segscan_k(const uint64_t *__restrict__ items, uint64_t n,
                                                      const uint8_t *__restrict__ init, uint32_t n_ids,
-                                                     uint16_t *__restrict__ st16, uint8_t *__restrict__ flag,
+                                                     uint16_t *__restrict__ st16,
                                                      uint8_t *__restrict__ final_out, uint64_t *__restrict__ lb,
                                                      uint32_t *__restrict__ ticket, uint64_t ntiles)
 {
@@ -237,12 +242,33 @@ __global__ __launch_bounds__(BLOCK) void k_segscan_k(const uint64_t *__restrict_
             const uint32_t post = stuck ? pre : kf_apply(kf_of(ob[j]), pre);
             state = post;
             st16[pay[j]] = (uint16_t)(post | (pre << 4) | (stuck << 15));
-            flag[pay[j]] = (uint8_t)(stuck << 7);
             const uint32_t kn = j + 1 < KITEMS ? var[j + 1] : knext;
             if ((kn != var[j] || g + 1 == n) && var[j] < n_ids)
                 final_out[var[j]] = (uint8_t)post;
         }
         __syncthreads();
+    }
+}
+
+// flag[i] = stuck << 7 from the status words, in program order (8 events a thread)
+__global__ void k_flags_k(const uint16_t *__restrict__ st16, uint64_t n, uint8_t *__restrict__ flag)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 8;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8; i0 < n; i0 += stride) {
+        if (i0 + 8 <= n) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(st16 + i0);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+            uint32_t lo = 0, hi = 0;
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+                lo |= ((w[k] >> 8) & 0x80u) << (16 * k) | ((w[k] >> 24) & 0x80u) << (16 * k + 8);
+                hi |= ((w[k + 2] >> 8) & 0x80u) << (16 * k) | ((w[k + 2] >> 24) & 0x80u) << (16 * k + 8);
+            }
+            *reinterpret_cast<uint2 *>(flag + i0) = make_uint2(lo, hi);
+        } else {
+            for (uint64_t i = i0; i < n; i++)
+                flag[i] = (uint8_t)((st16[i] >> 8) & 0x80u);
+        }
     }
 }
 
@@ -274,8 +300,12 @@ void launch_segscan_k(const uint64_t *sorted, uint64_t n, const uint8_t *init, u
     uint64_t *lb = reinterpret_cast<uint64_t *>(scratch);
     launch_clear_lookback(lb, tiles, ctl->tickets[1], s);
     const unsigned grid = resident_grid((const void *)k_segscan_k, tiles);
-    ProfScope p(s, "segscan_k");
-    k_segscan_k<<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, st16, flag, final_out, lb, ctl->tickets[1], tiles);
+    {
+        ProfScope p(s, "segscan_k");
+        k_segscan_k<<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, st16, final_out, lb, ctl->tickets[1], tiles);
+    }
+    ProfScope p(s, "flags_k");
+    k_flags_k<<<grid_k(ceil_div(n, (uint64_t)8)), BLOCK, 0, s>>>(st16, n, flag);
 }
 
 } // namespace vc
