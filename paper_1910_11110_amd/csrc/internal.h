@@ -103,12 +103,12 @@ size_t scan_scratch_bytes(uint64_t n);
 // Evaluates sorted items segment by segment (segment = equal key) from init[key]
 // (1 = (V,I) when init is null).  mode SCAN_STATUS: status[payload] = post|pre<<2|flag<<7
 // for primary items, stuck induced items counted per trace; final[key] = last post.
-// mode SCAN_PRE: pre[payload] = status before the item.
+// mode SCAN_PRE: pre[payload] = status before the item, for payloads from pre_from on.
 // ind_counts: per-trace counters of stuck induced items (payload low bits index it),
 // &ctl->n_induced_stuck when null.  grid_cap bounds the persistent grid.
 void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, int mode,
                     uint8_t *out, uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s,
-                    unsigned long long *ind_counts = nullptr, unsigned grid_cap = 1u << 30);
+                    unsigned long long *ind_counts = nullptr, unsigned grid_cap = 1u << 30, uint32_t pre_from = 0);
 
 // ------------------------------- small id spaces ----------------------------------
 // single-kernel check of a trace over at most small_max_ids() ids (events 16-byte

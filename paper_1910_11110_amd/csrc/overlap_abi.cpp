@@ -262,7 +262,9 @@ int dynamic_enqueue(vc_trace *t, hipStream_t s)
                     (uint64_t *)t->items_a.p, m, t->ctl, s);
     uint64_t *sorted = sort_items((uint64_t *)t->items_a.p, (uint64_t *)t->items_b.p, m,
                                   (int)key_bits_for(t->n_ids), t->scratch.p, t->ctl, s);
-    launch_segscan(sorted, m, t->init, t->n_ids, SCAN_PRE, L.pre, nullptr, t->scratch.p, t->ctl, s);
+    // the first scan is read only at the probes (payloads n + t)
+    launch_segscan(sorted, m, t->init, t->n_ids, SCAN_PRE, L.pre, nullptr, t->scratch.p, t->ctl, s, nullptr, 1u << 30,
+                   (uint32_t)n);
     launch_dyn_inherit(t->mother, L.cpos, L.pre, n, t->init, t->n_ids, L.init2, (uint8_t *)t->fin.p, s);
     launch_segscan(sorted, m, L.init2, t->n_ids, SCAN_STATUS, (uint8_t *)t->status.p, (uint8_t *)t->fin.p,
                    t->scratch.p, t->ctl, s);

@@ -26,7 +26,8 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
                                                    const uint8_t *__restrict__ init, uint32_t n_ids,
                                                    uint8_t *__restrict__ out, uint8_t *__restrict__ final_out,
                                                    uint64_t *__restrict__ lb, uint32_t *__restrict__ ticket,
-                                                   uint64_t ntiles, unsigned long long *__restrict__ ind_counts)
+                                                   uint64_t ntiles, unsigned long long *__restrict__ ind_counts,
+                                                   uint32_t pre_from)
 {
     __shared__ uint64_t s_it[SCAN_TILE + SCAN_TILE / PAD + 1];
     __shared__ uint32_t s_f4[16], s_stuck[16];
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(BLOCK) void k_segscan(const uint64_t *__restrict__ 
                 out[pay[j]] = (uint8_t)(post | (pre << 2) | (flag << 7));
             else if (flag)
                 atomicAdd(&ind_counts[pay[j] & ~INDUCED_BIT], 1ull);
-        } else if (!(pay[j] & INDUCED_BIT)) {
+        } else if (!(pay[j] & INDUCED_BIT) && pay[j] >= pre_from) {
             out[pay[j]] = (uint8_t)pre;
         }
         uint32_t kn = j + 1 < SCAN_ITEMS ? key[j + 1] : knext;
@@ -137,7 +138,7 @@ size_t scan_scratch_bytes(uint64_t n) { return ceil_div(n ? n : 1, SCAN_TILE) * 
 
 void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uint32_t n_ids, int mode, uint8_t *out,
                     uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, unsigned long long *ind_counts,
-                    unsigned grid_cap)
+                    unsigned grid_cap, uint32_t pre_from)
 {
     if (n == 0)
         return;
@@ -153,13 +154,13 @@ void launch_segscan(const uint64_t *sorted, uint64_t n, const uint8_t *init, uin
         {
             ProfScope prof_(s, "segscan");
             k_segscan<SCAN_STATUS><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, ctl->tickets[1],
-                                                          tiles, ind_counts);
+                                                          tiles, ind_counts, 0u);
         }
     else
         {
             ProfScope prof_(s, "segscan_pre");
             k_segscan<SCAN_PRE><<<grid, BLOCK, 0, s>>>(sorted, n, init, n_ids, out, final_out, lb, ctl->tickets[1], tiles,
-                                                       ind_counts);
+                                                       ind_counts, pre_from);
         }
 }
 
