@@ -685,13 +685,22 @@ __device__ __forceinline__ uint32_t pre_status(const uint8_t *__restrict__ res, 
     return res[j < n_decl ? j : n_decl - 1];
 }
 
+// a wave-uniform 64-bit value in scalar registers (the compiler cannot tell that values
+// read from the wave's own LDS are uniform)
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (uint64_t)hi << 32 | lo;
+}
+
 __device__ __forceinline__ uint32_t decl_arity(uint32_t wd, uint32_t n_vars)
 {
     const uint32_t mode = decl_ok(wd, n_vars) ? (wd >> 24) & 3u : 0u;
     return slot_arity(mode) + body_arity(mode);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(6))) void k_translate_emit_wave(
     const uint64_t *__restrict__ comp_off, uint64_t n_comp, const uint32_t *__restrict__ decls, uint64_t n_decl,
     uint32_t n_vars, const uint8_t *__restrict__ res, const uint32_t *__restrict__ dstidx,
     const uint64_t *__restrict__ chunk_prefix, uint32_t *__restrict__ out, uint8_t *__restrict__ status,
@@ -699,7 +708,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
 {
     __shared__ WaveTile s_tiles[BLOCK / WAVE];
     __shared__ uint32_t s_decl_tab[32];
-    const uint32_t lane = lane_id(), wave = threadIdx.x / WAVE;
+    const uint32_t lane = lane_id(), wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     if (threadIdx.x < 32)
         s_decl_tab[threadIdx.x] = decl_table_entry(threadIdx.x);
     __syncthreads();
@@ -708,6 +717,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
     // vector write-out needs 16-byte aligned events and 4-byte aligned statuses
     const bool vec_out = (reinterpret_cast<uintptr_t>(out) & 15u) == 0 && (reinterpret_cast<uintptr_t>(status) & 3u) == 0;
     const uint64_t nw = (uint64_t)gridDim.x * (BLOCK / WAVE);
+    const uint32_t last_decl = n_decl ? (uint32_t)(n_decl - 1) : 0u;
     // the next tile's component offsets are loaded while this tile is processed
     auto load_coff = [&](uint64_t t) -> uint64_t {
         const uint64_t c = t * WCOMPS + lane;
@@ -722,7 +732,7 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         coff_next = load_coff(wt + nw);
         reinterpret_cast<uint32_t *>(L.start)[lane] = 0u;
         __builtin_amdgcn_wave_barrier();
-        const uint64_t d_lo = L.coff[0], d_hi = L.coff[nc];
+        const uint64_t d_lo = uniform64(L.coff[0]), d_hi = uniform64(L.coff[nc]);
         // malformed offsets: reported; such a component has no events
         uint64_t a = 0, b = 0;
         bool bad = false;
@@ -746,16 +756,19 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
         if (d_lo <= n_decl) {
             const uint64_t first = d_lo - d_lo % HCHUNK;
             static_assert(HCHUNK <= WAVE, "one declaration of the chunk per lane");
-            const uint64_t pi = first + lane;
-            const uint32_t pw = pi < d_lo ? decls[pi] : 0u;
+            const uint32_t back = (uint32_t)(d_lo - first); // the chunk's declarations before d_lo
+            const uint32_t pw = lane < back ? decls[first + lane] : 0u;
+            // the tile's declarations and destinations from uniform bases, 32-bit offsets
+            const uint32_t *dp = decls + d_lo;
+            const uint32_t *xp = dstidx ? dstidx + d_lo : nullptr;
 #pragma unroll
             for (int k = 0; k < WROUNDS; k++) {
                 const uint32_t i = k * WAVE + lane;
-                dw[k] = i < nd ? decls[d_lo + i] : 0u;
-                ix[k] = i < nd ? (dstidx ? dstidx[d_lo + i] : (uint32_t)(d_lo + i)) : 0u;
+                dw[k] = i < nd ? dp[i] : 0u;
+                ix[k] = i < nd ? (xp ? xp[i] : (uint32_t)d_lo + i) : 0u;
             }
             const uint64_t cb = chunk_prefix[d_lo / HCHUNK];
-            base = cb + wave_total_u32(pi < d_lo ? decl_arity(pw, n_vars) : 0u);
+            base = cb + wave_total_u32(lane < back ? decl_arity(pw, n_vars) : 0u);
         }
         // events per component (lane = component)
         uint32_t cnt = 0;
@@ -787,8 +800,8 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
             if (lane == 0)
                 L.scan[nd] = carry;
 #pragma unroll
-            for (int k = 0; k < WROUNDS; k++)
-                pr[k] = k * WAVE + lane < nd ? (uint32_t)res[ix[k] < n_decl ? ix[k] : n_decl - 1] : 0u;
+            for (int k = 0; k < WROUNDS; k++) // (n_decl < 2^32 on this path)
+                pr[k] = k * WAVE + lane < nd ? (uint32_t)res[ix[k] < last_decl ? ix[k] : last_decl] : 0u;
             __builtin_amdgcn_wave_barrier();
             // a component declares each variable once (their statuses would otherwise be
             // evaluated as if only one existed): the lane of each component compares its
@@ -877,21 +890,24 @@ __global__ __launch_bounds__(BLOCK) void k_translate_emit_wave(
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            // write-out by groups of four staged entries (output index base - off + j)
-            const uint64_t gb = base - off;
+            // write-out by groups of four staged entries (output index base - off + j),
+            // from uniform bases with 32-bit offsets
+            const uint64_t gb = uniform64(base - off);
+            uint32_t *const ob = out + gb;
+            uint8_t *const sb = status + gb;
             const uint32_t ngroups = (lim + 3u) / 4u;
             for (uint32_t q = lane; q < ngroups; q += WAVE) {
                 const uint32_t j0 = 4u * q;
                 if (vec_out && j0 >= off && j0 + 4u <= lim) {
-                    *reinterpret_cast<uint4 *>(out + gb + j0) = *reinterpret_cast<const uint4 *>(&L.ev[j0]);
-                    *reinterpret_cast<uint32_t *>(status + gb + j0) = *reinterpret_cast<const uint32_t *>(&L.st[j0]);
+                    *reinterpret_cast<uint4 *>(ob + j0) = *reinterpret_cast<const uint4 *>(&L.ev[j0]);
+                    *reinterpret_cast<uint32_t *>(sb + j0) = *reinterpret_cast<const uint32_t *>(&L.st[j0]);
                 } else {
 #pragma unroll
                     for (uint32_t e = 0; e < 4; e++) {
                         const uint32_t j = j0 + e;
                         if (j >= off && j < lim) {
-                            out[gb + j] = L.ev[j];
-                            status[gb + j] = L.st[j];
+                            ob[j] = L.ev[j];
+                            sb[j] = L.st[j];
                         }
                     }
                 }
