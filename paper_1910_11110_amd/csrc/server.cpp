@@ -148,6 +148,33 @@ struct BytePool {
     }
 };
 
+// grow-only buffer (device, or pinned host memory from hipHostMalloc); never shrunk
+struct Stage {
+    void *p = nullptr;
+    size_t cap = 0;
+    bool host = false;
+    bool reserve(size_t bytes)
+    {
+        if (p && bytes <= cap)
+            return true;
+        release();
+        const size_t want = bytes > 256 ? bytes : 256;
+        if ((host ? hipHostMalloc(&p, want, hipHostMallocDefault) : hipMalloc(&p, want)) != hipSuccess) {
+            p = nullptr;
+            return false;
+        }
+        cap = want;
+        return true;
+    }
+    void release()
+    {
+        if (p)
+            (void)(host ? hipHostFree(p) : hipFree(p));
+        p = nullptr;
+        cap = 0;
+    }
+};
+
 struct Slot {
     hipStream_t s = nullptr;        // copies of this slot's batch
     hipEvent_t done = nullptr;      // results copied back
@@ -156,6 +183,11 @@ struct Slot {
     std::vector<Chunk *> chunks;
     BatchState *b = nullptr;
     bool busy = false;
+    // the batch's inputs and results in one piece each way: the chunks' events (and the
+    // pointers the header gather reads) copied in with one transfer from pinned memory,
+    // their status bytes and gathered headers copied back with one transfer each
+    Stage h_in{nullptr, 0, true}, d_in, d_out, h_out{nullptr, 0, true};
+    std::vector<uint64_t> ev_off; // each chunk's first event inside the staged events
 };
 
 } // namespace
@@ -242,33 +274,38 @@ uint64_t count_induced(const std::vector<uint32_t> &ev, const std::vector<uint64
 static std::map<uint64_t, std::vector<uint64_t>> g_degrees; // stream -> overlap degree per array (host)
 static std::mutex g_deg_mu;
 
+// bytes of a slot's gathered headers (the status bytes follow them, 16-byte aligned)
+static size_t slot_header_bytes(size_t n_chunks) { return (n_chunks * GATHER_WORDS * 4 + 15) & ~size_t(15); }
+
 static void finish_slot(vc_server *S, Slot &sl)
 {
-    // results of every chunk of the slot: status bytes to the caller, counters
-    std::vector<Control> h(sl.chunks.size());
-    for (size_t i = 0; i < sl.chunks.size(); i++) {
+    // the gathered headers and the status bytes are in the slot's pinned buffer (copied
+    // by the slot's stream after the kernels, before its done event)
+    hipError_t e = hipEventSynchronize(sl.done);
+    const size_t nc = sl.chunks.size();
+    const uint32_t *hdr = reinterpret_cast<const uint32_t *>(sl.h_out.p);
+    const uint8_t *stat = reinterpret_cast<const uint8_t *>(sl.h_out.p) + slot_header_bytes(nc);
+    for (size_t i = 0; i < nc; i++) {
         Chunk *c = sl.chunks[i];
-        (void)hipMemcpyAsync(&h[i], c->d_ctl, CONTROL_HEADER, hipMemcpyDeviceToHost, sl.s);
-        if (c->status_out && !c->events.empty())
-            (void)hipMemcpyAsync(c->status_out, c->d_status, c->events.size(), hipMemcpyDeviceToHost, sl.s);
+        if (e == hipSuccess && c->status_out && !c->events.empty())
+            memcpy(c->status_out, stat + sl.ev_off[i], c->events.size());
     }
-    std::vector<uint32_t> first(sl.chunks.size(), 0);
-    for (size_t i = 0; i < sl.chunks.size(); i++)
-        (void)hipMemcpyAsync(&first[i], sl.chunks[i]->d_viol, 4, hipMemcpyDeviceToHost, sl.s);
-    hipError_t e = hipStreamSynchronize(sl.s);
     double t = S->now();
     std::lock_guard<std::mutex> lk(S->mu);
-    for (size_t i = 0; i < sl.chunks.size(); i++) {
+    for (size_t i = 0; i < nc; i++) {
         Chunk *c = sl.chunks[i];
+        Control h;
+        memcpy(&h, hdr + i * GATHER_WORDS, CONTROL_HEADER);
+        const uint32_t first = hdr[i * GATHER_WORDS + CONTROL_HEADER / 4];
         vc_completion comp{};
         comp.stream = c->stream;
         comp.chunk = c->id;
         comp.first_event = c->first_event;
         comp.n_events = c->events.size();
-        uint64_t bad = ((uint64_t)h[i].err_index_hi << 32) | h[i].err_index_lo;
-        comp.status = e != hipSuccess || h[i].err_code ? VC_EDEVICE : (bad != ~0ull ? VC_EINVAL : VC_OK);
-        comp.n_violations = h[i].n_viol;
-        comp.first_violation = h[i].n_viol ? c->first_event + first[i] : c->first_event + c->events.size();
+        uint64_t bad = ((uint64_t)h.err_index_hi << 32) | h.err_index_lo;
+        comp.status = e != hipSuccess || h.err_code ? VC_EDEVICE : (bad != ~0ull ? VC_EINVAL : VC_OK);
+        comp.n_violations = h.n_viol;
+        comp.first_violation = h.n_viol ? c->first_event + first : c->first_event + c->events.size();
         comp.t_submit = c->t_submit;
         comp.t_start = c->t_start;
         comp.t_done = t;
@@ -330,9 +367,26 @@ static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
             fail_batch(S, batch, VC_ENOMEM, vc_last_error());
             return false;
         }
-    std::vector<TraceDesc> desc(batch.size());
+    // staging: the batch's events, then the header gather's pointer arrays (control
+    // blocks, violation lists), 16-byte aligned pieces
+    const size_t nc = batch.size();
+    sl.ev_off.assign(nc + 1, 0);
+    for (size_t i = 0; i < nc; i++)
+        sl.ev_off[i + 1] = sl.ev_off[i] + ((batch[i]->events.size() + 3) & ~size_t(3));
+    const size_t ev_bytes = 4 * sl.ev_off[nc], ptr_bytes = 16 * nc;
+    const size_t hdr_bytes = slot_header_bytes(nc), st_bytes = sl.ev_off[nc];
+    if (!sl.h_in.reserve(ev_bytes + ptr_bytes) || !sl.d_in.reserve(ev_bytes + ptr_bytes) ||
+        !sl.d_out.reserve(hdr_bytes + st_bytes) || !sl.h_out.reserve(hdr_bytes + st_bytes)) {
+        fail_batch(S, batch, VC_ENOMEM, "server: staging buffers");
+        return false;
+    }
+    uint32_t *h_ev = (uint32_t *)sl.h_in.p, *d_ev = (uint32_t *)sl.d_in.p;
+    const Control **h_ctl = (const Control **)((char *)sl.h_in.p + ev_bytes);
+    const uint32_t **h_vl = (const uint32_t **)((char *)sl.h_in.p + ev_bytes + 8 * nc);
+    uint8_t *d_st = (uint8_t *)sl.d_out.p + hdr_bytes;
+    std::vector<TraceDesc> desc(nc);
     uint64_t M = 0;
-    for (size_t i = 0; i < batch.size(); i++) {
+    for (size_t i = 0; i < nc; i++) {
         Chunk *c = batch[i];
         Stream *st;
         {
@@ -341,16 +395,18 @@ static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
         }
         uint64_t n = c->events.size();
         if (n)
-            (void)hipMemcpyAsync(c->d_events, c->events.data(), n * 4, hipMemcpyHostToDevice, sl.s);
+            memcpy(h_ev + sl.ev_off[i], c->events.data(), n * 4);
+        h_ctl[i] = c->d_ctl;
+        h_vl[i] = c->d_viol;
         TraceDesc &d = desc[i];
-        d.events = c->d_events;
+        d.events = d_ev + sl.ev_off[i];
         d.init = st->table;
         d.off = st->has_arrays ? st->sets.off : nullptr;
         d.nbr = st->has_arrays ? st->sets.nbr : nullptr;
         d.n = n;
         d.n_ids = st->n_ids;
         d.ctl = c->d_ctl;
-        d.status = c->d_status;
+        d.status = d_st + sl.ev_off[i];
         d.fin = st->table; // the chunk leaves its final statuses in the resident table
         d.viol = c->d_viol;
         d.m = n + c->induced;
@@ -366,6 +422,10 @@ static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
     double t = S->now();
     for (Chunk *c : batch)
         c->t_start = t;
+    // (the pinned staging is rewritten only after the slot's done event: a slot is
+    // reused once finish_slot has retired it)
+    if (ev_bytes + ptr_bytes)
+        (void)hipMemcpyAsync(sl.d_in.p, sl.h_in.p, ev_bytes + ptr_bytes, hipMemcpyHostToDevice, sl.s);
     const int r = batch_prepare(*sl.b, desc, M, sl.s);
     if (r != VC_OK) {
         // nothing was enqueued that reads the chunks' buffers on the compute stream; the
@@ -384,6 +444,12 @@ static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
     batch_enqueue(*sl.b, S->compute);
     (void)hipEventRecord(sl.computed, S->compute);
     (void)hipStreamWaitEvent(sl.s, sl.computed, 0);
+    // results: every chunk's header and first violation gathered by one launch, then the
+    // headers and the status bytes back in one transfer
+    launch_gather_headers((const Control *const *)((char *)sl.d_in.p + ev_bytes),
+                          (const uint32_t *const *)((char *)sl.d_in.p + ev_bytes + 8 * nc), (uint32_t)nc,
+                          (uint32_t *)sl.d_out.p, sl.s);
+    (void)hipMemcpyAsync(sl.h_out.p, sl.d_out.p, hdr_bytes + st_bytes, hipMemcpyDeviceToHost, sl.s);
     (void)hipEventRecord(sl.done, sl.s);
     sl.chunks = batch;
     sl.busy = true;
@@ -539,6 +605,10 @@ extern "C" int vc_server_destroy(vc_server *S)
     delete S->bpool;
     for (Slot &sl : S->slots) {
         batch_free(sl.b);
+        sl.h_in.release();
+        sl.d_in.release();
+        sl.d_out.release();
+        sl.h_out.release();
         (void)hipEventDestroy(sl.computed);
         (void)hipEventDestroy(sl.staged);
         (void)hipEventDestroy(sl.done);
@@ -682,32 +752,40 @@ extern "C" int vc_stream_submit(vc_server *S, uint64_t stream, const uint32_t *e
 {
     if (!S || (n && !events) || !chunk)
         return vc_fail(VC_EINVAL, "vc_stream_submit: NULL argument");
+    // the chunk is validated and sized without the server's lock (the server thread
+    // takes it to admit and launch batches); only the stream's id count is read under it
+    uint32_t n_ids = 0;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->streams.find(stream);
+        if (it == S->streams.end() || it->second->closing)
+            return vc_fail(VC_EINVAL, "vc_stream_submit: unknown or closing stream %llu", (unsigned long long)stream);
+        n_ids = it->second->n_ids;
+    }
+    for (uint32_t i = 0; i < n; i++) {
+        uint32_t w = events[i];
+        if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= n_ids)
+            return vc_fail(VC_EINVAL, "vc_stream_submit: malformed event 0x%08x at index %u", w, i);
+    }
     Chunk *c = new Chunk();
     c->events.assign(events, events + n);
     c->status_out = status_out;
-    std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->streams.find(stream);
-    if (it == S->streams.end() || it->second->closing) {
-        delete c;
-        return vc_fail(VC_EINVAL, "vc_stream_submit: unknown or closing stream %llu", (unsigned long long)stream);
-    }
-    Stream *st = it->second;
-    for (uint32_t i = 0; i < n; i++) {
-        uint32_t w = events[i];
-        if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= st->n_ids) {
-            delete c;
-            return vc_fail(VC_EINVAL, "vc_stream_submit: malformed event 0x%08x at index %u", w, i);
-        }
-    }
     {
         std::lock_guard<std::mutex> lk2(g_deg_mu);
         c->induced = count_induced(c->events, g_degrees[stream]);
     }
     c->bytes = chunk_bytes(n, c->induced);
-    if (c->bytes + st->n_ids > S->budget) {
+    if (c->bytes + n_ids > S->budget) {
         delete c;
         return vc_fail(VC_EBUDGET, "vc_stream_submit: a chunk of %u events can never fit the budget", n);
     }
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->streams.find(stream);
+    if (it == S->streams.end() || it->second->closing) { // closed meanwhile
+        delete c;
+        return vc_fail(VC_EINVAL, "vc_stream_submit: unknown or closing stream %llu", (unsigned long long)stream);
+    }
+    Stream *st = it->second;
     c->id = S->next_chunk++;
     c->stream = stream;
     c->first_event = st->events_seen;
