@@ -52,8 +52,6 @@ struct Chunk {
     uint64_t induced = 0;
     uint64_t bytes = 0;
     // device side
-    uint32_t *d_events = nullptr;
-    uint8_t *d_status = nullptr;
     uint32_t *d_viol = nullptr;
     Control *d_ctl = nullptr;
     void *pool_block = nullptr;
@@ -102,8 +100,9 @@ struct Pool {
             return p;
         }
         void *p = nullptr;
-        // events (4 B), status (1 B), violations (4 B) per event, and the counters
-        if (hipMalloc(&p, (9ull << k) + CONTROL_BYTES) != hipSuccess)
+        // violations (4 B per event) and the counters (events and status bytes live in
+        // the slot's staging)
+        if (hipMalloc(&p, (4ull << k) + CONTROL_BYTES) != hipSuccess)
             return nullptr;
         all.push_back(p);
         return p;
@@ -243,10 +242,8 @@ int alloc_chunk(Pool &pool, Chunk *c)
     c->pool_block = p;
     c->pool_cls = k;
     uint64_t cap = 1ull << k;
-    c->d_events = (uint32_t *)p;
-    c->d_viol = (uint32_t *)(p + 4 * cap);
-    c->d_ctl = (Control *)(p + 8 * cap);
-    c->d_status = (uint8_t *)(p + 8 * cap + CONTROL_BYTES);
+    c->d_viol = (uint32_t *)p;
+    c->d_ctl = (Control *)(p + 4 * cap);
     return VC_OK;
 }
 
