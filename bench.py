@@ -573,7 +573,12 @@ def served_report(args, V, ctx):
             t.free()
         s = time.perf_counter() - a
         seq = s if seq is None else min(seq, s)
-    one, allc, k, nt, m = _oracle_traces([p[:4] for p in pool], 1 << 25)
+    cpu = None
+    if not args.no_cpu_baseline:
+        one, allc, k, nt, m = _oracle_traces([p[:4] for p in pool], 1 << 25)
+        cpu = {"value": round(one, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle check of the first {nt} pool traces ({m} events), overlap sets precomputed",
+               "host": host_info(), "all_cores": {"value": round(allc, 1), "threads": k}}
     rec = {
         "config": {"workload": "served-poisson", "rate_traces_per_s": args.served_rate,
                    "duration_s": args.served_seconds, "chunk_events": chunk, "budget_bytes": 64 << 30,
@@ -587,10 +592,7 @@ def served_report(args, V, ctx):
         "sequential_per_trace": {"value": round(pool_events / seq, 1), "unit": "events/s", "ms": round(seq * 1e3, 3),
                                  "how": "per pool trace: load from host, set arrays, vc_check, sync, read the "
                                         "status bytes, free; best of 2"},
-        "cpu_baseline": {"value": round(one, 1), "unit": "events/s", "cores": 1, "kind": "oracle",
-                         "sample": f"oracle check of the first {nt} pool traces ({m} events), overlap sets "
-                                   f"precomputed", "host": host_info(),
-                         "all_cores": {"value": round(allc, 1), "threads": k}},
+        "cpu_baseline": cpu,
         "note": "latencies are submit-to-completion on the server clock, queueing included; a trace's latency "
                 "runs from its arrival to its last chunk's completion; the replay includes the chunks' copies "
                 "from host memory and the status bytes' copies back",
