@@ -134,9 +134,12 @@ __device__ __forceinline__ uint32_t dyn_event(uint32_t e, uint64_t t, uint32_t n
     return len;
 }
 
-// EMIT = false: tcnt[tile] = the tile's items; EMIT = true: the items at tpos[tile] on
-// (cap items; probes carry payload n + t, induced items INDUCED_BIT)
-template <bool EMIT>
+// MODE D_COUNT: tcnt[tile] = the tile's items.  D_ITEMS: 64-bit sort items at tpos[tile]
+// on (cap items; probes carry payload n + t, induced items INDUCED_BIT).  D_WORDS: the
+// same items as 32-bit words for the bucket engine (a create, a destroy and a probe are
+// no-ops on their array, induced items op 5), and pos32[t] = event t's position.
+enum { D_COUNT = 0, D_ITEMS = 1, D_WORDS = 2 };
+template <int MODE>
 __global__ __launch_bounds__(BLOCK) void k_dyn_tiles(const uint32_t *__restrict__ ev, uint64_t n, uint32_t n_ids,
                                                      const uint32_t *__restrict__ mother,
                                                      const uint32_t *__restrict__ cpos,
@@ -145,8 +148,10 @@ __global__ __launch_bounds__(BLOCK) void k_dyn_tiles(const uint32_t *__restrict_
                                                      const uint32_t *__restrict__ nbr,
                                                      const uint2 *__restrict__ life, uint64_t ntiles,
                                                      uint32_t *__restrict__ tcnt, const uint64_t *__restrict__ tpos,
-                                                     uint64_t *__restrict__ items, uint64_t cap, Control *ctl)
+                                                     uint64_t *__restrict__ items, uint32_t *__restrict__ words,
+                                                     uint32_t *__restrict__ pos32, uint64_t cap, Control *ctl)
 {
+    constexpr bool EMIT = MODE != D_COUNT;
     __shared__ uint32_t s_start[DWAVES][DTILE + 1];
     __shared__ uint32_t s_word[DWAVES][DTILE];
     __shared__ uint64_t s_nb[DWAVES][DTILE];
@@ -190,34 +195,47 @@ __global__ __launch_bounds__(BLOCK) void k_dyn_tiles(const uint32_t *__restrict_
         const uint64_t heads = __ballot(s_mark[wv][lane] != 0);
         const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
         const uint32_t q = qc + lane;
-        bool keep = false;
+        bool keep = false, primary = false;
         uint64_t item = 0;
+        uint32_t word = 0;
         if (q < total) {
             const uint32_t k = q - s_start[wv][own];
             const uint32_t w = s_word[wv][own], op = (w >> 24) & 7u, x = w & 0xFFFFFFu, side = (w >> 27) & 1u;
             const uint64_t t = i0 + own;
             keep = true;
             if (k == 0) {
-                if (EMIT)
+                primary = true;
+                if (MODE == D_ITEMS)
                     item = make_item(x, op >= OP_CREATE ? fcode(OP_NOOP, 0) : fcode(op, side), (uint32_t)t);
+                if (MODE == D_WORDS)
+                    word = x | (op >= OP_CREATE ? (uint32_t)OP_NOOP << 24 : (w & (15u << 24)));
             } else if (op == OP_CREATE) {
-                if (EMIT)
+                if (MODE == D_ITEMS)
                     item = make_item(mother[x], fcode(OP_NOOP, 0), (uint32_t)(n + t));
+                if (MODE == D_WORDS)
+                    word = mother[x] | (uint32_t)OP_NOOP << 24;
             } else {
                 const uint64_t j = s_nb[wv][own] + k - 1;
                 const uint2 lf = life[j];
                 keep = (lf.x == NO_POS || lf.x < t) && (lf.y == NO_POS || t < lf.y);
-                if (EMIT)
+                if (MODE == D_ITEMS)
                     item = make_item(nbr[j], fcode(OP_RWIND, side), INDUCED_BIT);
+                if (MODE == D_WORDS)
+                    word = nbr[j] | (uint32_t)OP_RWIND << 24 | (side << 27);
             }
         }
         const uint64_t km = __ballot(keep);
         if (EMIT && keep) {
             const uint64_t p = base + kept + mask_rank(km);
-            if (p < cap)
-                items[p] = item;
-            else // the events changed since the items were sized: refused, in bounds
+            if (p >= cap) { // the events changed since the items were sized: refused, in bounds
                 report_bad(ctl, i0 + own);
+            } else if (MODE == D_ITEMS) {
+                items[p] = item;
+            } else {
+                words[p] = word;
+                if (primary)
+                    pos32[i0 + own] = (uint32_t)p; // below 2^32 on this route
+            }
         }
         kept += (uint32_t)__builtin_popcountll(km);
         ec += (uint32_t)__builtin_popcountll(heads);
@@ -241,6 +259,25 @@ __global__ void k_dyn_inherit(const uint32_t *__restrict__ mother, const uint32_
         uint8_t s = init ? init[x] : (uint8_t)1;
         if (c != NO_POS && c < n && mother[x] != NO_MOTHER)
             s = probe_pre[n + c];
+        init2[x] = s;
+        fin[x] = s;
+    }
+}
+
+// the same from the first bucket check's status bytes (post | pre << 2 | flag << 7): a
+// create's probe sits right after the create, at pos32[c] + 1
+__global__ void k_dyn_inherit_words(const uint32_t *__restrict__ mother, const uint32_t *__restrict__ cpos,
+                                    const uint8_t *__restrict__ comb, const uint32_t *__restrict__ pos32, uint64_t n,
+                                    uint64_t m, const uint8_t *__restrict__ init, uint32_t n_ids,
+                                    uint8_t *__restrict__ init2, uint8_t *__restrict__ fin)
+{
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n_ids; x += gridDim.x * blockDim.x) {
+        const uint32_t c = cpos[x];
+        uint8_t s = init ? init[x] : (uint8_t)1;
+        if (c != NO_POS && c < n && mother[x] != NO_MOTHER) {
+            const uint64_t p = (uint64_t)pos32[c] + 1;
+            s = (uint8_t)((comb[p < m ? p : m - 1] >> 2) & 3u);
+        }
         init2[x] = s;
         fin[x] = s;
     }
@@ -279,8 +316,9 @@ void launch_dyn_count(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint
     const uint64_t ntiles = dyn_tiles(n);
     if (ntiles) {
         ProfScope p(s, "dyn_count");
-        k_dyn_tiles<false><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
-            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, tcnt, nullptr, nullptr, 0, ctl);
+        k_dyn_tiles<D_COUNT><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
+            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, tcnt, nullptr, nullptr, nullptr, nullptr, 0,
+            ctl);
     }
 }
 
@@ -291,9 +329,32 @@ void launch_dyn_emit(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint3
     const uint64_t ntiles = dyn_tiles(n);
     if (ntiles) {
         ProfScope p(s, "dyn_emit");
-        k_dyn_tiles<true><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
-            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, nullptr, tpos, items, cap, ctl);
+        k_dyn_tiles<D_ITEMS><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
+            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, nullptr, tpos, items, nullptr, nullptr, cap,
+            ctl);
     }
+}
+
+void launch_dyn_words(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
+                      const uint32_t *dpos, const OverlapSets *o, const uint2 *life, const uint64_t *tpos,
+                      uint32_t *words, uint32_t *pos32, uint64_t cap, Control *ctl, hipStream_t s)
+{
+    const uint64_t ntiles = dyn_tiles(n);
+    if (ntiles) {
+        ProfScope p(s, "dyn_words");
+        k_dyn_tiles<D_WORDS><<<(unsigned)ceil_div(ntiles, (uint64_t)DWAVES), BLOCK, 0, s>>>(
+            ev, n, n_ids, mother, cpos, dpos, o->off, o->nbr, life, ntiles, nullptr, tpos, nullptr, words, pos32, cap,
+            ctl);
+    }
+}
+
+void launch_dyn_inherit_words(const uint32_t *mother, const uint32_t *cpos, const uint8_t *comb, const uint32_t *pos32,
+                              uint64_t n, uint64_t m, const uint8_t *init, uint32_t n_ids, uint8_t *init2, uint8_t *fin,
+                              hipStream_t s)
+{
+    ProfScope p(s, "dyn_inherit");
+    k_dyn_inherit_words<<<grid_of(n_ids), BLOCK, 0, s>>>(mother, cpos, comb, pos32, n, m ? m : 1, init, n_ids, init2,
+                                                         fin);
 }
 
 void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint8_t *probe_pre, uint64_t n,

@@ -151,23 +151,54 @@ DynLayout dyn_layout(void *base, uint64_t n, uint32_t n_ids, uint64_t n_nbr)
     return L;
 }
 
-// the tiles' item positions in t->aux (after their counts)
-uint64_t *dyn_tile_pos(vc_trace *t) { return (uint64_t *)((char *)t->aux.p + ((dyn_tiles(t->n) * 4 + 255) & ~255ull)); }
+// t->aux of a dynamic trace: per tile of events its item count and their scan, per
+// event its position among the words of the bucket route, and the control block of the
+// expansion's errors on that route
+struct DynAux {
+    uint32_t *tcnt;
+    uint64_t *tpos;
+    uint32_t *pos32;
+    Control *xctl;
+    size_t bytes;
+};
 
-// lifetimes, item counts per tile of events and their scan (in t->aux), on the stream
-int dyn_count_items(vc_trace *t, hipStream_t s)
+DynAux dyn_aux(void *base, uint64_t n)
+{
+    char *p = (char *)base;
+    size_t off = 0;
+    auto take = [&](size_t sz) {
+        char *r = p ? p + off : nullptr;
+        off += (sz + 255) & ~size_t(255);
+        return r;
+    };
+    const uint64_t ntiles = dyn_tiles(n);
+    DynAux A;
+    A.tcnt = (uint32_t *)take((ntiles ? ntiles : 1) * 4);
+    A.tpos = (uint64_t *)take((ntiles + 1) * 8);
+    A.pos32 = (uint32_t *)take((n ? n : 1) * 4);
+    A.xctl = (Control *)take(CONTROL_BYTES);
+    A.bytes = off;
+    return A;
+}
+
+// the tiles' item positions in t->aux (after their counts)
+uint64_t *dyn_tile_pos(vc_trace *t) { return dyn_aux(t->aux.p, t->n).tpos; }
+
+// lifetimes, item counts per tile of events and their scan (in t->aux), on the stream;
+// errors to ctl
+int dyn_count_items(vc_trace *t, hipStream_t s, Control *ctl)
 {
     int r;
     const uint64_t n = t->n, ntiles = dyn_tiles(n);
-    if ((r = devbuf_reserve(t->aux, ((ntiles * 4 + 255) & ~255ull) + (ntiles + 1) * 8)) != VC_OK ||
+    if ((r = devbuf_reserve(t->aux, dyn_aux(nullptr, n).bytes)) != VC_OK ||
         (r = devbuf_reserve(t->scratch, std::max(t->scratch.bytes, excl_scan_scratch_bytes(ntiles)))) != VC_OK ||
         (r = devbuf_reserve(t->dyn, dyn_layout(nullptr, n, t->n_ids, t->sets.n_nbr).bytes)) != VC_OK)
         return r;
     const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids, t->sets.n_nbr);
-    uint32_t *tcnt = (uint32_t *)t->aux.p;
+    const DynAux A = dyn_aux(t->aux.p, n);
     launch_dyn_life(t->events, n, t->n_ids, L.cpos, L.dpos, s);
-    launch_dyn_count(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, tcnt, t->ctl, s);
-    launch_excl_scan(tcnt, ntiles, dyn_tile_pos(t), nullptr, t->scratch.p, t->ctl->tickets[5], s);
+    launch_dyn_count(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, A.tcnt, ctl, s);
+    launch_excl_scan(A.tcnt, ntiles, A.tpos, nullptr, t->scratch.p, ctl->tickets[5], s);
     return VC_OK;
 }
 
@@ -177,7 +208,7 @@ int dyn_size(vc_trace *t)
     hipStream_t s = t->ctx->stream;
     const uint64_t n = t->n;
     launch_reset_control(t->ctl, s);
-    int r = dyn_count_items(t, s);
+    int r = dyn_count_items(t, s, t->ctl);
     if (r != VC_OK)
         return r;
     uint64_t total = 0;
@@ -243,10 +274,54 @@ extern "C" int vc_trace_set_dynamic_arrays(vc_trace *t, const uint32_t *lo, cons
     return VC_OK;
 }
 
+// the check of a dynamic trace through the bucket engine: the items as 32-bit words, a
+// first check for the statuses the probes see (the inherited statuses), a second from
+// them for every status byte and the final table; the primaries' bytes gathered back
+// and compacted.  The expansion reports its errors into a control block of its own
+// (each check resets the trace's), merged at the end.
+static int dynamic_bucket_enqueue(vc_trace *t, hipStream_t s)
+{
+    const uint64_t n = t->n, m = t->n_items;
+    int r;
+    if ((r = devbuf_reserve(t->status, n ? n : 1)) != VC_OK ||
+        (r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK ||
+        (r = devbuf_reserve(t->viol, (n ? n : 1) * 4)) != VC_OK ||
+        (r = devbuf_reserve(t->items_a, (m ? m : 1) * 4)) != VC_OK ||
+        (r = devbuf_reserve(t->items_b, ((m + 255) & ~uint64_t(255)) + (m ? m : 1) * 4)) != VC_OK ||
+        (r = devbuf_reserve(t->scratch, std::max({bucket_scratch_bytes(m, t->n_ids), compact_scratch_bytes(n),
+                                                  t->scratch.bytes}))) != VC_OK ||
+        (r = devbuf_reserve(t->aux, dyn_aux(nullptr, n).bytes)) != VC_OK)
+        return r;
+    const DynAux A = dyn_aux(t->aux.p, n);
+    launch_reset_control(A.xctl, s);
+    if ((r = dyn_count_items(t, s, A.xctl)) != VC_OK)
+        return r;
+    const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids, t->sets.n_nbr);
+    uint32_t *words = (uint32_t *)t->items_a.p;
+    uint8_t *comb = (uint8_t *)t->items_b.p, *fin = (uint8_t *)t->fin.p;
+    uint32_t *comb_viol = (uint32_t *)((char *)t->items_b.p + ((m + 255) & ~uint64_t(255)));
+    launch_dyn_words(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, A.tpos, words, A.pos32, m,
+                     A.xctl, s);
+    const int cu = t->ctx->cu_count;
+    launch_bucket_check_combined(words, m, t->n_ids, t->init, comb, nullptr, nullptr, t->scratch.p, t->ctl, s, cu,
+                                 nullptr);
+    launch_dyn_inherit_words(t->mother, L.cpos, comb, A.pos32, n, m, t->init, t->n_ids, L.init2, fin, s);
+    launch_bucket_check_combined(words, m, t->n_ids, L.init2, comb, fin, comb_viol, t->scratch.p, t->ctl, s, cu,
+                                 nullptr);
+    launch_extract_primary(comb, A.pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
+    launch_compact((uint8_t *)t->status.p, n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
+    launch_induced_finish(t->ctl, s);
+    launch_merge_errors(t->ctl, A.xctl, s);
+    return VC_OK;
+}
+
 // the check of a dynamic trace: items, sort, the scan for the inherited statuses, the
-// scan for every status, violations
+// scan for every status, violations (the bucket engine's route when the ids and the
+// items fit it)
 int dynamic_enqueue(vc_trace *t, hipStream_t s)
 {
+    if (t->n_ids <= bucket_max_ids() && t->n_items < (1ull << 32) && !getenv("VC_GENERAL_PATH"))
+        return dynamic_bucket_enqueue(t, s);
     const uint64_t n = t->n, m = t->n_items;
     int r;
     if ((r = trace_reserve(t, m)) != VC_OK)
@@ -255,7 +330,7 @@ int dynamic_enqueue(vc_trace *t, hipStream_t s)
     if ((r = devbuf_reserve(t->status, 2 * n + 1)) != VC_OK)
         return r;
     launch_reset_control(t->ctl, s);
-    if ((r = dyn_count_items(t, s)) != VC_OK)
+    if ((r = dyn_count_items(t, s, t->ctl)) != VC_OK)
         return r;
     const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids, t->sets.n_nbr);
     launch_dyn_emit(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, dyn_tile_pos(t),

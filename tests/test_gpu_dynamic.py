@@ -162,3 +162,23 @@ def test_dynamic_workload_full_size(ctx):
     d = gen.dynamic_trace(1 << 24, 1 << 10, (1 << 16) - (1 << 10), 0)
     sets = O.overlap_sets(d.lo, d.hi)
     assert_parity(ctx, d.events, d.lo, d.hi, d.mother, label="dynamic full size", sets=sets)
+
+
+@pytest.mark.parametrize("n,nv,npv,space,maxlen", [(70_000, 4, 60, 1 << 12, 512), (600_000, 32, 2000, 1 << 16, 4096)])
+def test_dynamic_bucket_and_sorted_routes_agree(ctx, n, nv, npv, space, maxlen):
+    """The bucket-engine route (items as 32-bit words, two checks) and the sorted route
+    (64-bit items, two scans) give the same bytes, from initial (I,I) statuses too."""
+    import os
+    d = gen.dynamic_trace(n, nv, npv, n + 3 * nv, space=space, max_len=maxlen)
+    init = (np.arange(d.lo.size) % 4).astype(np.uint8)
+    for ini in (None, init):
+        a = run_gpu(ctx, d.events, d.lo, d.hi, d.mother, ini)
+        os.environ["VC_GENERAL_PATH"] = "1"
+        try:
+            b = run_gpu(ctx, d.events, d.lo, d.hi, d.mother, ini)
+        finally:
+            del os.environ["VC_GENERAL_PATH"]
+        assert np.array_equal(a[0], b[0]), "status bytes"
+        assert np.array_equal(a[1], b[1]), "final statuses"
+        assert a[2].total == b[2].total and np.array_equal(a[2].indices, b[2].indices), "violations"
+        assert a[3] == b[3], "stuck induced"
