@@ -268,3 +268,30 @@ def test_batch_groups_split_at_the_key_space(ctx):
         assert_trace(t, oracle_of(*inp), f"trace {i}")
     for t in traces:
         t.free()
+
+
+def test_batch_malformed_device_event_reported_alone(ctx):
+    """A malformed event word in one trace's device memory is reported for that trace
+    (with its index) by the sync after a batched check; the other traces of the batch,
+    one with arrays, still equal the oracle."""
+    import torch
+    from paper_1910_11110_amd import vcheck as V
+    inputs = make_traces(6, 9, len_range=(5000, 40000), with_init=False)
+    ev, nv, lo, hi, init = inputs[2]
+    bad = ev.copy()
+    bad[77] = (bad[77] & 0xFFFFFF) | (6 << 24)  # op 6 does not exist
+    tb = torch.from_numpy(bad.view(np.int32)).cuda()
+    torch.cuda.synchronize()
+    traces = load_all(ctx, inputs[:2]) + [V.Trace.load(ctx, tb, nv)] + load_all(ctx, inputs[3:])
+    if lo is not None:
+        traces[2].set_arrays(lo, hi)
+    say("[batch] 6 traces, one with a malformed device event")
+    V.batch_check(ctx, traces)
+    with pytest.raises(V.VCError) as ex:
+        ctx.sync()
+    assert "77" in str(ex.value)
+    for i, (t, inp) in enumerate(zip(traces, inputs)):
+        if i != 2:
+            assert_trace(t, oracle_of(*inp), f"trace {i}")
+    for t in traces:
+        t.free()
