@@ -118,3 +118,15 @@ def test_declared_workload_full_size(ctx):
     say("[declared] generating the full-size workload")
     p = gen.declared_program(1 << 20, 1 << 16, 0, arrays=True, space=1 << 22, max_len=64)
     assert_parity(ctx, p, True, label="full size")
+
+
+@pytest.mark.parametrize("kmax", [12, 16, 24])
+def test_declared_wide_components(ctx, kmax):
+    """Components with many declarations: a tile of 64 components then has fewer than the
+    512 declarations the body walk stages in LDS (kmax 12), more (kmax 24), or either
+    (kmax 16), so both the staged and the global reading of the declarations run;
+    scalars, arrays, and arrays with the extension."""
+    for arrays, extend in ((False, False), (True, False), (True, True)):
+        p = gen.declared_program(6_001, 2000, 7 + kmax, arrays=arrays, space=1 << 14, max_len=32, kmax=kmax,
+                                 p_err=0.1)
+        assert_parity(ctx, p, extend, label=f"kmax {kmax} arrays {arrays} extend {extend}")
