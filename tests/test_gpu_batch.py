@@ -295,3 +295,28 @@ def test_batch_malformed_device_event_reported_alone(ctx):
             assert_trace(t, oracle_of(*inp), f"trace {i}")
     for t in traces:
         t.free()
+
+
+def test_batch_dense_overlaps(ctx):
+    """A batch with a trace whose arrays nearly all overlap (hundreds of induced items per
+    write, spanning several steps of a chunk's 64-item walk) between plain traces: every
+    trace equals the oracle, through the bucket route and the sorted route."""
+    rng = np.random.default_rng(6)
+    lo = rng.integers(0, 500, 300).astype(np.uint32)
+    hi = (lo + rng.integers(300, 500, 300)).astype(np.uint32)
+    inputs = make_traces(4, 10, len_range=(3000, 30000), with_init=False)
+    inputs.insert(2, (gen.plain_events(9_000, 300, 15), 300, lo, hi, None))
+    for general in (False, True):
+        if general:
+            os.environ["VC_GENERAL_PATH"] = "1"
+        try:
+            from paper_1910_11110_amd import vcheck as V
+            traces = load_all(ctx, inputs)
+            V.batch_check(ctx, traces)
+            ctx.sync()
+            for i, (t, inp) in enumerate(zip(traces, inputs)):
+                assert_trace(t, oracle_of(*inp), f"trace {i} (general {general})")
+            for t in traces:
+                t.free()
+        finally:
+            os.environ.pop("VC_GENERAL_PATH", None)

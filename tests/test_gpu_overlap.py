@@ -125,3 +125,14 @@ def test_bucket_and_general_overlap_paths_agree(n, n_arr, space, maxlen):
     assert a[3] == b[3] and a[4] == b[4]
     ref = O.check_overlap(e, lo, hi, init)
     assert np.array_equal(a[0], ref.status) and a[4] == ref.n_induced_stuck
+
+
+def test_overlap_dense_overlaps(ctx):
+    """Every array overlaps most others (300 arrays of 300-700 elements in 1,000
+    addresses): a write induces hundreds of items, so one event's items span several
+    steps of the expansion's 64-item walk."""
+    rng = np.random.default_rng(5)
+    lo = rng.integers(0, 500, 300).astype(np.uint32)
+    hi = (lo + rng.integers(300, 500, 300)).astype(np.uint32)
+    e = gen.plain_events(20_000, 300, 14)
+    assert_overlap(ctx, e, lo, hi, label="dense overlaps")
