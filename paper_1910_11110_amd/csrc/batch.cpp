@@ -56,6 +56,10 @@ struct BatchState {
     bool bucket = false;
     std::vector<Group> groups;
     Control *gctl = nullptr;
+    // settings of the bucket route the autotuner chooses: ids per group (2^group_bits at
+    // most; 2^20 or fewer take the 256-bucket tables) and events per chunk of a trace
+    // without arrays
+    uint32_t group_bits = 22, plain_chunk = BATCH_CHUNK_PLAIN;
     uint64_t N = 0, K = 0, M = 0;
     uint32_t n_traces = 0;
     SortTuning tune;
@@ -71,7 +75,7 @@ void build_chunks(BatchState &b, std::vector<TraceDesc> &desc)
     b.h_chunks.clear();
     for (uint32_t t = 0; t < (uint32_t)desc.size(); t++) {
         desc[t].first_chunk = b.h_chunks.size();
-        const uint64_t len = desc[t].off ? BATCH_CHUNK : BATCH_CHUNK_PLAIN;
+        const uint64_t len = desc[t].off ? BATCH_CHUNK : b.plain_chunk;
         for (uint64_t a = 0; a < desc[t].n; a += len)
             b.h_chunks.push_back(ChunkDesc{a, t, (uint32_t)std::min<uint64_t>(len, desc[t].n - a)});
     }
@@ -175,11 +179,11 @@ void tune_store(const std::string &key, const SortTuning &t, unsigned scan_grid)
 void plan_groups(BatchState &b, std::vector<TraceDesc> &desc)
 {
     b.groups.clear();
-    const uint64_t kmax = bucket_max_ids();
+    const uint64_t kmax = std::min<uint64_t>(bucket_max_ids(), 1ull << b.group_bits);
     bool ok = !getenv("VC_GENERAL_PATH") && !desc.empty();
     uint64_t item = 0;
     for (TraceDesc &d : desc) {
-        ok = ok && d.n_ids >= 1 && d.n_ids <= kmax && d.m < (1ull << 32);
+        ok = ok && d.n_ids >= 1 && d.n_ids <= bucket_max_ids() && d.m < (1ull << 32);
         d.item_base = item;
         item += d.m;
     }
@@ -188,7 +192,7 @@ void plan_groups(BatchState &b, std::vector<TraceDesc> &desc)
         return;
     BatchState::Group g{0, 0, 0, 0};
     for (TraceDesc &d : desc) {
-        if (g.k && (g.k + d.n_ids > kmax || g.m + d.m >= (1ull << 32))) {
+        if (g.k && (g.k + d.n_ids > kmax || g.m + d.m >= (1ull << 32))) { // (a trace above kmax: a group alone)
             b.groups.push_back(g);
             g = BatchState::Group{d.item_base, 0, d.key_base, 0};
         }
@@ -287,17 +291,107 @@ void drop_graph(BatchState &b)
     b.graph_ok = false;
 }
 
+// chunks and groups of the batch in b.h_desc for the current settings, buffers, and the
+// descriptors on the device (synchronous: the set-up of a new batch shape)
+int configure(BatchState &b)
+{
+    const uint32_t n = b.n_traces;
+    build_chunks(b, b.h_desc);
+    plan_groups(b, b.h_desc);
+    int r = reserve_all(b, n);
+    if (r != VC_OK)
+        return r;
+    hipError_t e;
+    if ((e = hipMemcpy(b.desc.p, b.h_desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b.ev_off.p, b.h_ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b.key_off.p, b.h_key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
+        (b.n_chunks && (e = hipMemcpy(b.chunks.p, b.h_chunks.data(), sizeof(ChunkDesc) * b.n_chunks,
+                                      hipMemcpyHostToDevice)) != hipSuccess))
+        return vc_hip_fail(e, "hipMemcpy(batch descriptors)");
+    return VC_OK;
+}
+
+bool tuning_on() { return !getenv("VC_NO_AUTOTUNE"); }
+
+std::string bucket_key(uint64_t N, uint64_t K) { return "bucket:" + shape_key(N, K); }
+
+// the bucket route's settings for this batch: the cached choice, or every candidate
+// timed on the batch itself, keeping only those whose status bytes equal the first
+// candidate's (a race or a tiling bug would change bytes)
+int autotune_bucket(vc_ctx *c, BatchState &b)
+{
+    hipStream_t s = c->stream;
+    const std::string key = bucket_key(b.N, b.K);
+    struct Cand {
+        uint32_t group_bits, plain_chunk;
+    };
+    const std::vector<Cand> cands = { { 22, BATCH_CHUNK_PLAIN }, { 20, BATCH_CHUNK_PLAIN }, { 21, BATCH_CHUNK_PLAIN },
+                                      { 22, 4 * BATCH_CHUNK_PLAIN }, { 20, 4 * BATCH_CHUNK_PLAIN } };
+    std::vector<uint8_t> ref, got;
+    float best = 1e30f;
+    Cand pick = cands[0];
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int r = VC_OK;
+    for (size_t i = 0; i < cands.size() && r == VC_OK; i++) {
+        b.group_bits = cands[i].group_bits;
+        b.plain_chunk = cands[i].plain_chunk;
+        if ((r = configure(b)) != VC_OK)
+            break;
+        if (!b.bucket)
+            break; // (the route does not depend on these settings)
+        enqueue_pipeline(b, s); // warm
+        (void)hipEventRecord(e0, s);
+        enqueue_pipeline(b, s);
+        (void)hipEventRecord(e1, s);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            r = vc_fail(VC_EDEVICE, "autotune run failed");
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        got.resize(b.N);
+        if (b.N && hipMemcpy(got.data(), b.status_all.p, b.N, hipMemcpyDeviceToHost) != hipSuccess) {
+            r = vc_fail(VC_EDEVICE, "autotune read-back failed");
+            break;
+        }
+        if (i == 0)
+            ref = got;
+        else if (got != ref)
+            continue; // not parity-clean: never chosen
+        if (ms < best) {
+            best = ms;
+            pick = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != VC_OK)
+        return r;
+    b.group_bits = pick.group_bits;
+    b.plain_chunk = pick.plain_chunk;
+    b.tuned = true;
+    SortTuning t{};
+    t.max_bits = (int)pick.group_bits;
+    t.grid_cap = pick.plain_chunk;
+    tune_store(key, t, 0);
+    return configure(b);
+}
+
 // times candidate settings on this batch; keeps those whose status bytes equal the
 // first candidate's (a race or a tiling bug would change bytes)
 int autotune(vc_ctx *c, BatchState &b)
 {
     hipStream_t s = c->stream;
+    if (b.bucket)
+        return autotune_bucket(c, b);
     std::string key = shape_key(b.N, b.K);
     if (tune_lookup(key, b.tune, b.scan_grid)) {
         b.tuned = true;
         return VC_OK;
     }
-    if (!getenv("VC_AUTOTUNE") || b.bucket) { // default settings unless tuning the sorted route is requested
+    if (!tuning_on()) { // default settings when tuning is switched off
         b.tune = SortTuning{};
         b.scan_grid = 0;
         b.tuned = true;
@@ -502,20 +596,25 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
         b.K = K;
         b.M = M;
         b.n_traces = n;
-        build_chunks(b, desc);
-        plan_groups(b, desc);
-        int r = reserve_all(b, n);
+        b.h_desc = desc;
+        b.h_ev_off = ev_off;
+        b.h_key_off = key_off;
+        // the bucket route's settings: cached for this shape, else the defaults until
+        // the autotuner has run
+        SortTuning cached{};
+        unsigned unused = 0;
+        const bool hit = tune_lookup(bucket_key(N, K), cached, unused);
+        b.group_bits = hit ? (uint32_t)cached.max_bits : 22u;
+        b.plain_chunk = hit ? cached.grid_cap : BATCH_CHUNK_PLAIN;
+        if (b.group_bits < 12 || b.group_bits > 22 || b.plain_chunk < BATCH_CHUNK || b.plain_chunk > (1u << 20)) {
+            b.group_bits = 22; // a cache entry from elsewhere: ignored
+            b.plain_chunk = BATCH_CHUNK_PLAIN;
+        }
+        int r = configure(b);
         if (r != VC_OK)
             return r;
-        hipError_t e;
-        if ((e = hipMemcpy(b.desc.p, desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(b.ev_off.p, ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(b.key_off.p, key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
-            (b.n_chunks && (e = hipMemcpy(b.chunks.p, b.h_chunks.data(), sizeof(ChunkDesc) * b.n_chunks,
-                                          hipMemcpyHostToDevice)) != hipSuccess))
-            return vc_hip_fail(e, "hipMemcpy(batch descriptors)");
         b.signature = sig;
-        b.tuned = false;
+        b.tuned = b.bucket ? (hit || !tuning_on()) : false;
     }
     if (n == 0)
         return VC_OK;

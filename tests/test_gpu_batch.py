@@ -320,3 +320,33 @@ def test_batch_dense_overlaps(ctx):
                 t.free()
         finally:
             os.environ.pop("VC_GENERAL_PATH", None)
+
+
+def test_batch_bucket_route_autotuner(ctx, tmp_path):
+    """The bucket route's settings (ids per group, events per chunk) are chosen by timing
+    every candidate on the batch itself and cached per shape; the chosen one gives the
+    oracle's bytes, and a second batch of the same shape takes the cached choice."""
+    from paper_1910_11110_amd import vcheck as V
+    cache = tmp_path / "tune.json"
+    os.environ["VC_TUNE_CACHE"] = str(cache)
+    try:
+        inputs = make_traces(25, 4)
+        traces = load_all(ctx, inputs)
+        V.batch_check(ctx, traces)
+        ctx.sync()
+        for i, (t, inp) in enumerate(zip(traces, inputs)):
+            assert_trace(t, oracle_of(*inp), f"tuned trace {i}")
+        text = cache.read_text()
+        assert "bucket:gfx950" in text, text
+        say(f"[batch] bucket route tuned: {text.strip()}")
+        for t in traces:
+            t.free()
+        traces = load_all(ctx, inputs)  # same shape, new handles: the cached choice
+        V.batch_check(ctx, traces)
+        ctx.sync()
+        for i, (t, inp) in enumerate(zip(traces, inputs)):
+            assert_trace(t, oracle_of(*inp), f"cached trace {i}")
+        for t in traces:
+            t.free()
+    finally:
+        del os.environ["VC_TUNE_CACHE"]
