@@ -89,6 +89,8 @@ def test_served_streams_match_oracle(ctx):
             assert min(firsts) == ref.first
         for c in comps.get(i, []):
             assert c.t_submit <= c.t_start <= c.t_done
+        # a stream's chunks complete in order (one of them in flight at a time)
+        assert [c.first_event for c in comps.get(i, [])] == sorted(c.first_event for c in comps.get(i, []))
     srv.close()
 
 
