@@ -44,7 +44,7 @@ struct BatchState {
     bool graph_ok = false;
     // device buffers
     DevBuf desc, ev_off, key_off, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind,
-        chunks, words, comb;
+        chunks, words, comb, vcnt, vpos;
     uint64_t n_chunks = 0;
     Control *ctl = nullptr;
     // bucket route: groups of consecutive traces (their slice of the combined stream and
@@ -54,6 +54,7 @@ struct BatchState {
         uint32_t key_lo, k;
     };
     bool bucket = false;
+    uint64_t MB = 0; // combined slots: every trace's range padded to a multiple of 16
     std::vector<Group> groups;
     Control *gctl = nullptr;
     // settings of the bucket route the autotuner chooses: ids per group (2^group_bits at
@@ -174,31 +175,35 @@ void tune_store(const std::string &key, const SortTuning &t, unsigned scan_grid)
 
 // chooses the route: the bucket engine when every trace has between 1 and
 // bucket_max_ids() ids and its items fit 32-bit positions; then every trace's first
-// combined position and first key inside its group, and the groups (consecutive traces
-// whose ids fit one key space)
+// combined position (its range padded to a multiple of 16 slots, so that every trace's
+// items start 16-byte aligned in the status bytes) and first key inside its group, and
+// the groups (consecutive traces whose ids fit one key space)
 void plan_groups(BatchState &b, std::vector<TraceDesc> &desc)
 {
     b.groups.clear();
     const uint64_t kmax = std::min<uint64_t>(bucket_max_ids(), 1ull << b.group_bits);
     bool ok = !getenv("VC_GENERAL_PATH") && !desc.empty();
-    uint64_t item = 0;
+    uint64_t item = 0, m_all = 0;
+    auto padded = [](uint64_t m) { return (m + 15) & ~(uint64_t)15; };
     for (TraceDesc &d : desc) {
-        ok = ok && d.n_ids >= 1 && d.n_ids <= bucket_max_ids() && d.m < (1ull << 32);
+        ok = ok && d.n_ids >= 1 && d.n_ids <= bucket_max_ids() && padded(d.m) < (1ull << 32);
         d.item_base = item;
-        item += d.m;
+        item += padded(d.m);
+        m_all += d.m;
     }
-    b.bucket = ok && item == b.M;
+    b.bucket = ok && m_all == b.M;
+    b.MB = item;
     if (!b.bucket)
         return;
     BatchState::Group g{0, 0, 0, 0};
     for (TraceDesc &d : desc) {
-        if (g.k && (g.k + d.n_ids > kmax || g.m + d.m >= (1ull << 32))) { // (a trace above kmax: a group alone)
+        if (g.k && (g.k + d.n_ids > kmax || g.m + padded(d.m) >= (1ull << 32))) { // (a trace above kmax: a group alone)
             b.groups.push_back(g);
             g = BatchState::Group{d.item_base, 0, d.key_base, 0};
         }
         d.key_local = g.k;
         g.k += d.n_ids;
-        g.m += d.m;
+        g.m += padded(d.m);
     }
     b.groups.push_back(g);
 }
@@ -212,20 +217,26 @@ int reserve_all(BatchState &b, uint32_t n)
     if ((r = devbuf_reserve(b.key_off, 8 * (n + 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.init_all, K ? K : 1)) != VC_OK) return r;
     if ((r = devbuf_reserve(b.fin_all, K ? K : 1)) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.status_all, N ? N : 1)) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.viol_all, 4 * (N ? N : 1))) != VC_OK) return r;
     const uint64_t nc = b.n_chunks;
     if ((r = devbuf_reserve(b.cnt, 4 * (nc ? nc : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.pos, 8 * (nc + 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.chunks, sizeof(ChunkDesc) * (nc ? nc : 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.ind, 8 * (n ? n : 1))) != VC_OK) return r;
-    size_t sc = std::max(compact_scratch_bytes(N), excl_scan_scratch_bytes(nc));
+    size_t sc = excl_scan_scratch_bytes(nc);
     if (b.bucket) {
-        if ((r = devbuf_reserve(b.words, 4 * (M ? M : 1))) != VC_OK) return r;
-        if ((r = devbuf_reserve(b.comb, M ? M : 1)) != VC_OK) return r;
+        // the status bytes go straight to the traces: no batch-wide status or violation
+        // arrays
+        const uint64_t MB = b.MB;
+        if ((r = devbuf_reserve(b.words, 4 * (MB ? MB : 1))) != VC_OK) return r;
+        if ((r = devbuf_reserve(b.comb, MB ? MB : 1)) != VC_OK) return r;
+        if ((r = devbuf_reserve(b.vcnt, 4 * (nc ? nc : 1))) != VC_OK) return r;
+        if ((r = devbuf_reserve(b.vpos, 8 * (nc + 1))) != VC_OK) return r;
         for (const BatchState::Group &g : b.groups)
             sc = std::max(sc, bucket_scratch_bytes(g.m, g.k));
     } else {
+        if ((r = devbuf_reserve(b.status_all, N ? N : 1)) != VC_OK) return r;
+        if ((r = devbuf_reserve(b.viol_all, 4 * (N ? N : 1))) != VC_OK) return r;
+        sc = std::max(sc, compact_scratch_bytes(N));
         if ((r = devbuf_reserve(b.items_a, 8 * (M ? M : 1))) != VC_OK) return r;
         if ((r = devbuf_reserve(b.items_b, 8 * (M ? M : 1))) != VC_OK) return r;
         sc = std::max({ sc, sort_scratch_bytes(M), scan_scratch_bytes(M) });
@@ -254,7 +265,7 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
     if (b.bucket) {
         uint32_t *words = (uint32_t *)b.words.p;
         uint8_t *comb = (uint8_t *)b.comb.p, *init_all = (uint8_t *)b.init_all.p, *fin_all = (uint8_t *)b.fin_all.p;
-        launch_batch_chunk_words(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, words, b.M, s);
+        launch_batch_chunk_words(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, words, b.MB, s);
         // one bucket check per group (final statuses into the group's slice of fin_all,
         // which holds the initial statuses); their errors are folded into the batch's
         for (const BatchState::Group &g : b.groups) {
@@ -262,11 +273,16 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
                                          fin_all + g.key_lo, nullptr, b.scratch.p, b.gctl, s, 0, nullptr);
             launch_merge_errors(b.ctl, b.gctl, s);
         }
-        launch_batch_chunk_gather(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, comb, b.M, (uint8_t *)b.status_all.p,
+        // status bytes to the traces, flagged events counted per chunk, their offsets,
+        // then the violation lists and the counts
+        uint32_t *vcnt = (uint32_t *)b.vcnt.p;
+        uint64_t *vpos = (uint64_t *)b.vpos.p;
+        launch_batch_chunk_status(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, comb, b.MB, vcnt,
                                   (unsigned long long *)b.ind.p, s);
-        launch_compact((uint8_t *)b.status_all.p, b.N, (uint32_t *)b.viol_all.p, b.scratch.p, b.ctl, s);
-        launch_batch_distribute(d, n, nullptr, (const uint8_t *)b.fin_all.p, (const uint32_t *)b.viol_all.p, b.ctl,
-                                (const unsigned long long *)b.ind.p, s);
+        launch_excl_scan(vcnt, b.n_chunks, vpos, nullptr, b.scratch.p, b.ctl->tickets[7], s);
+        launch_batch_chunk_viol(d, ch, b.n_chunks, vcnt, vpos, s);
+        launch_batch_finish(d, n, b.n_chunks, vpos, (const uint8_t *)b.fin_all.p, b.ctl,
+                            (const unsigned long long *)b.ind.p, s);
         return;
     }
     launch_batch_chunk_emit(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, (uint64_t *)b.items_a.p, b.M, s);
@@ -351,8 +367,9 @@ int autotune_bucket(vc_ctx *c, BatchState &b)
         }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        got.resize(b.N);
-        if (b.N && hipMemcpy(got.data(), b.status_all.p, b.N, hipMemcpyDeviceToHost) != hipSuccess) {
+        // the combined status bytes (their layout does not depend on these settings)
+        got.resize(b.MB);
+        if (b.MB && hipMemcpy(got.data(), b.comb.p, b.MB, hipMemcpyDeviceToHost) != hipSuccess) {
             r = vc_fail(VC_EDEVICE, "autotune read-back failed");
             break;
         }

@@ -21,7 +21,7 @@ struct TraceDesc {
     uint8_t *fin;
     uint32_t *viol;
     uint64_t m;             // its combined items (events and induced items)
-    uint64_t item_base;     // bucket route: first combined position
+    uint64_t item_base;     // bucket route: first combined position (a multiple of 16)
     uint64_t first_chunk;   // index of its first chunk
     uint32_t key_local;     // bucket route: first key inside its group
 };
@@ -46,21 +46,28 @@ void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n
 
 // bucket route: every chunk's items as 32-bit words (group-local keys, induced items op
 // 5), each trace's at item_base on; an item past the trace's range is not written and
-// reported, and slots of the range that no item reaches get a no-op word
+// reported, and slots of the range that no item reaches, and those after it up to the
+// next multiple of 16 (below cap), get a no-op word
 void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
                               uint32_t *words, uint64_t cap, hipStream_t s);
-// bucket route: the primaries' status bytes from the combined status bytes into
-// status_all (global event order) and the traces' own status buffers, and per trace the
-// flagged induced items into ind
-void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
-                               const uint8_t *comb, uint64_t cap, uint8_t *status_all, unsigned long long *ind,
+// bucket route: every chunk's primaries' status bytes from the combined status bytes
+// into its trace's status buffer, the number of them flagged into vcnt[chunk], and per
+// trace the flagged induced items into ind
+void launch_batch_chunk_status(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                               const uint8_t *comb, uint64_t cap, uint32_t *vcnt, unsigned long long *ind,
                                hipStream_t s);
+// bucket route: every chunk's flagged events into its trace's violation list (ascending,
+// trace-relative), from vpos = the exclusive prefix of vcnt over the batch
+void launch_batch_chunk_viol(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint32_t *vcnt,
+                             const uint64_t *vpos, hipStream_t s);
+// bucket route: every trace's final statuses and counts
+void launch_batch_finish(const TraceDesc *d, uint32_t n_traces, uint64_t n_chunks, const uint64_t *vpos,
+                         const uint8_t *fin_all, const Control *bctl, const unsigned long long *ind, hipStream_t s);
 
 void launch_batch_reset(const TraceDesc *d, uint32_t n_traces, unsigned long long *ind, hipStream_t s);
 void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_traces, uint64_t K, uint8_t *init_all,
                        uint8_t *fin_all, hipStream_t s);
-// every trace's final statuses, violations and counts (and its status bytes unless
-// status_all is null: the bucket route's gather has written them)
+// general route: every trace's status bytes, final statuses, violations and counts
 void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_t *status_all, const uint8_t *fin_all,
                              const uint32_t *viol_all, const Control *bctl, const unsigned long long *ind,
                              hipStream_t s);

@@ -256,72 +256,284 @@ __device__ __forceinline__ uint64_t bucket_base(const TraceDesc &td, const Chunk
     return td.item_base + cd.start + (chunk_pos[c] - chunk_pos[td.first_chunk]);
 }
 
+// bits 7, 15, 23 and 31 of v as bits 0..3 (the partial products of the multiply land on
+// distinct bits: no carries)
+__device__ __forceinline__ uint32_t byte_msbs(uint32_t v) { return ((v & 0x80808080u) * 0x00204081u) >> 28; }
+
+// the trace's last chunk: slots its items leave in the range (only when the events
+// changed since the batch was sized) and the padding after the range (up to a multiple
+// of 16 slots, inside the capacity) get a no-op on its first key
+__device__ __forceinline__ void fill_trace_tail(const TraceDesc &td, const ChunkDesc &cd, uint64_t c,
+                                                const uint64_t *__restrict__ chunk_pos, uint32_t *__restrict__ words,
+                                                uint64_t lo, uint64_t hi, uint64_t cap)
+{
+    if (cd.start + cd.len != td.n)
+        return;
+    const uint64_t end = td.item_base + td.n + (chunk_pos[c + 1] - chunk_pos[td.first_chunk]);
+    if (end < hi && lane_id() == 0)
+        report_bad(td.ctl, cd.start);
+    const uint64_t pad = (hi + 15u) & ~(uint64_t)15u, fill_hi = pad < cap ? pad : cap;
+    for (uint64_t p = (end > lo ? end : lo) + lane_id(); p < fill_hi; p += WAVE)
+        words[p] = td.key_local | ((uint32_t)OP_NOOP << 24);
+}
+
+__device__ __forceinline__ uint32_t word_of(const TraceDesc &td, uint32_t e)
+{
+    return (td.key_local + (e & 0xFFFFFFu)) | (e & (7u << 24)) | (e & (1u << 27));
+}
+
+// 16-byte accesses in flight per lane in the passes over traces without arrays
+constexpr int CH_ILP = 4;
+
+// Words of every chunk.  The chunks of traces without arrays (PLAIN; no LDS) and those
+// of traces with arrays (the wave walks its chunk's items through LDS) are two launches,
+// each skipping the other's chunks.
+template <bool PLAIN>
 __global__ __launch_bounds__(BLOCK) void k_batch_chunk_words(const TraceDesc *__restrict__ d,
                                                              const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
                                                              const uint64_t *__restrict__ chunk_pos,
                                                              uint32_t *__restrict__ words, uint64_t cap)
 {
-    __shared__ ChunkStage s_stage[CH_WAVES];
-    ChunkStage &S = s_stage[wave_index()];
+    const uint32_t lane = lane_id();
+    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+         c += (uint64_t)gridDim.x * CH_WAVES) {
+        const ChunkDesc cd = ch[c];
+        const TraceDesc td = d[cd.trace];
+        if (PLAIN == (td.off != nullptr))
+            continue; // the other launch's chunk (uniform)
+        const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
+        const uint64_t base = bucket_base(td, cd, chunk_pos, c);
+        if constexpr (PLAIN) {
+            // the items are the events: CH_ILP groups of four per lane per step
+            const uint32_t *src = td.events + cd.start;
+            uint32_t *dst = words + base;
+            if (base >= lo && base + cd.len <= hi &&
+                ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0) {
+                for (uint32_t k0 = 0; k0 < cd.len; k0 += 4 * WAVE * CH_ILP) {
+                    uint4 v[CH_ILP];
+#pragma unroll
+                    for (int q = 0; q < CH_ILP; q++) {
+                        const uint32_t k = k0 + 4 * (q * WAVE + lane);
+                        v[q] = k + 4 <= cd.len ? *reinterpret_cast<const uint4 *>(src + k) : make_uint4(0, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < CH_ILP; q++) {
+                        const uint32_t k = k0 + 4 * (q * WAVE + lane);
+                        const uint64_t i = cd.start + k;
+                        if (k + 4 <= cd.len) {
+                            *reinterpret_cast<uint4 *>(dst + k) = make_uint4(
+                                word_of(td, clean_word(td, v[q].x, i, true)), word_of(td, clean_word(td, v[q].y, i + 1, true)),
+                                word_of(td, clean_word(td, v[q].z, i + 2, true)), word_of(td, clean_word(td, v[q].w, i + 3, true)));
+                        } else {
+                            for (uint32_t j = k; j < cd.len; j++)
+                                dst[j] = word_of(td, clean_word(td, src[j], cd.start + j, true));
+                        }
+                    }
+                }
+            } else {
+                for (uint32_t k = lane; k < cd.len; k += WAVE) {
+                    const uint64_t p = base + k;
+                    if (p < lo || p >= hi) { // the events changed since the batch was sized
+                        report_bad(td.ctl, cd.start + k);
+                        continue;
+                    }
+                    words[p] = word_of(td, clean_word(td, src[k], cd.start + k, true));
+                }
+            }
+        } else {
+            __shared__ ChunkStage s_stage[CH_WAVES];
+            ChunkStage &S = s_stage[wave_index()];
+            walk_chunk(td, cd, base, true, S, [&](uint32_t q, uint64_t p, uint64_t i, uint32_t e, uint32_t y) {
+                if (p < lo || p >= hi) { // the events changed since the batch was sized
+                    report_bad(td.ctl, i);
+                    return;
+                }
+                words[p] = q == 0 ? word_of(td, e) : (td.key_local + y) | ((uint32_t)OP_RWIND << 24) | (e & (1u << 27));
+            });
+        }
+        fill_trace_tail(td, cd, c, chunk_pos, words, lo, hi, cap);
+    }
+}
+
+// flagged bytes of comb[a, b) counted by the wave from the 16-byte blocks covering the
+// range (comb 16-byte aligned, its size a multiple of 16 and at least b)
+__device__ __forceinline__ uint32_t count_flags(const uint8_t *__restrict__ comb, uint64_t a, uint64_t b)
+{
+    uint32_t n = 0;
+    for (uint64_t blk = (a & ~(uint64_t)15) + 16u * lane_id(); blk < b; blk += 16u * WAVE) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(comb + blk);
+        const uint32_t m = byte_msbs(v.x) | byte_msbs(v.y) << 4 | byte_msbs(v.z) << 8 | byte_msbs(v.w) << 12;
+        const uint32_t lo_cut = a > blk ? (uint32_t)(a - blk) : 0u;
+        const uint32_t hi_cut = b < blk + 16 ? (uint32_t)(b - blk) : 16u;
+        n += __builtin_popcount(m & ((1u << hi_cut) - 1u) & ~((1u << lo_cut) - 1u));
+    }
+    return n;
+}
+
+// bucket route: every chunk's primaries' status bytes from the combined bytes into the
+// trace's status buffer, the number of them flagged (vcnt), and per trace the flagged
+// induced items (ind).  A trace without arrays copies its chunk 16 bytes per lane
+// (CH_ILP loads in flight) when both sides are 16-byte aligned.  A trace with arrays
+// finds each event's slot from a wave scan of the events' item counts, and counts its
+// flagged induced items as the flagged bytes of the chunk's item range less the flagged
+// primaries.
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_status(const TraceDesc *__restrict__ d,
+                                                              const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                              const uint64_t *__restrict__ chunk_pos,
+                                                              const uint8_t *__restrict__ comb, uint64_t cap,
+                                                              uint32_t *__restrict__ vcnt,
+                                                              unsigned long long *__restrict__ ind)
+{
+    const uint32_t lane = lane_id();
     for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
          c += (uint64_t)gridDim.x * CH_WAVES) {
         const ChunkDesc cd = ch[c];
         const TraceDesc td = d[cd.trace];
         const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
         const uint64_t base = bucket_base(td, cd, chunk_pos, c);
-        walk_chunk(td, cd, base, true, S, [&](uint32_t q, uint64_t p, uint64_t i, uint32_t e, uint32_t y) {
-            if (p < lo || p >= hi) { // the events changed since the batch was sized
-                report_bad(td.ctl, i);
-                return;
+        uint8_t *dst = td.status + cd.start;
+        uint32_t flagged = 0;
+        if (!td.off) {
+            const uint8_t *src = comb + base;
+            if (base >= lo && base + cd.len <= hi &&
+                ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0) {
+                for (uint32_t k0 = 0; k0 < cd.len; k0 += 16 * WAVE * CH_ILP) {
+                    uint4 v[CH_ILP];
+#pragma unroll
+                    for (int q = 0; q < CH_ILP; q++) {
+                        const uint32_t k = k0 + 16 * (q * WAVE + lane);
+                        v[q] = k + 16 <= cd.len ? *reinterpret_cast<const uint4 *>(src + k) : make_uint4(0, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < CH_ILP; q++) {
+                        const uint32_t k = k0 + 16 * (q * WAVE + lane);
+                        if (k + 16 <= cd.len) {
+                            *reinterpret_cast<uint4 *>(dst + k) = v[q];
+                            flagged += __builtin_popcount(byte_msbs(v[q].x) | byte_msbs(v[q].y) << 4 |
+                                                          byte_msbs(v[q].z) << 8 | byte_msbs(v[q].w) << 12);
+                        } else {
+                            for (uint32_t j = k; j < cd.len; j++) {
+                                const uint8_t b = src[j];
+                                dst[j] = b;
+                                flagged += b >> 7;
+                            }
+                        }
+                    }
+                }
+            } else {
+                for (uint32_t k = lane; k < cd.len; k += WAVE) {
+                    const uint64_t p = base + k;
+                    if (p < lo || p >= hi)
+                        continue; // reported by the word pass
+                    const uint8_t b = comb[p];
+                    dst[k] = b;
+                    flagged += b >> 7;
+                }
             }
-            const uint32_t side = e & (1u << 27);
-            words[p] = q == 0 ? (td.key_local + (e & 0xFFFFFFu)) | (e & (7u << 24)) | side
-                              : (td.key_local + y) | ((uint32_t)OP_RWIND << 24) | side;
-        });
-        if (cd.start + cd.len == td.n) {
-            // the trace's last chunk: slots its items leave in the range (only when the
-            // events changed since the batch was sized) get a no-op on its first key
-            const uint64_t end = td.item_base + td.n + (chunk_pos[c + 1] - chunk_pos[td.first_chunk]);
-            if (end < hi && lane_id() == 0)
-                report_bad(td.ctl, cd.start);
-            for (uint64_t p = (end > lo ? end : lo) + lane_id(); p < hi; p += WAVE)
-                words[p] = td.key_local | ((uint32_t)OP_NOOP << 24);
+        } else {
+            // the events (at most BATCH_CHUNK, CH_PER per lane) and the neighbour counts of
+            // their writes (loads issued together), then their slots by a wave scan
+            uint32_t ev[CH_PER], nb[CH_PER];
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++) {
+                const uint32_t k = j * WAVE + lane;
+                ev[j] = k < cd.len ? clean_word(td, td.events[cd.start + k], 0, false) : ((uint32_t)OP_NOOP << 24);
+            }
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++)
+                nb[j] = induced_of(td, ev[j]);
+            uint32_t carry = 0;
+#pragma unroll
+            for (int j = 0; j < CH_PER; j++) {
+                const uint32_t k = j * WAVE + lane;
+                const uint32_t len = k < cd.len ? 1u + nb[j] : 0u;
+                const uint32_t inc = wave_scan_add(len, lane);
+                if (k < cd.len) {
+                    const uint64_t p = base + carry + inc - len;
+                    if (p >= lo && p < hi) { // (else reported by the word pass)
+                        const uint8_t v = comb[p];
+                        dst[k] = v;
+                        flagged += v >> 7;
+                    }
+                }
+                carry += __builtin_amdgcn_readlane(inc, WAVE - 1);
+            }
+            // the chunk's items, clamped to the trace's range
+            const uint64_t a = base > lo ? base : lo, b = base + carry < hi ? base + carry : hi;
+            const uint32_t all = a < b ? wave_total_u32(count_flags(comb, a, b)) : 0u;
+            const uint32_t prim = wave_total_u32(flagged);
+            if (lane == 0 && all > prim)
+                atomicAdd(&ind[cd.trace], (unsigned long long)(all - prim));
+        }
+        const uint32_t nf = wave_total_u32(flagged);
+        if (lane == 0)
+            vcnt[c] = nf;
+    }
+}
+
+// bucket route: every chunk's flagged events, ascending, as trace-relative indices into
+// its trace's violation list, from the chunk's offset among the trace's flagged events
+// (vpos: exclusive prefix of the chunks' counts over the batch; a trace's chunks are
+// consecutive).  The status bytes are read back 16 per lane (16-byte loads when aligned).
+__global__ __launch_bounds__(BLOCK) void k_batch_chunk_viol(const TraceDesc *__restrict__ d,
+                                                            const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
+                                                            const uint32_t *__restrict__ vcnt,
+                                                            const uint64_t *__restrict__ vpos)
+{
+    const uint32_t lane = lane_id();
+    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+         c += (uint64_t)gridDim.x * CH_WAVES) {
+        if (vcnt[c] == 0)
+            continue; // uniform
+        const ChunkDesc cd = ch[c];
+        const TraceDesc td = d[cd.trace];
+        uint64_t off = vpos[c] - vpos[td.first_chunk];
+        const uint8_t *src = td.status + cd.start;
+        const bool vec = (reinterpret_cast<uintptr_t>(src) & 15u) == 0;
+        for (uint32_t k0 = 0; k0 < cd.len; k0 += 16 * WAVE) {
+            const uint32_t k = k0 + 16 * lane;
+            uint32_t m = 0; // bit j: event k + j flagged
+            if (vec && k + 16 <= cd.len) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(src + k);
+                m = byte_msbs(v.x) | byte_msbs(v.y) << 4 | byte_msbs(v.z) << 8 | byte_msbs(v.w) << 12;
+            } else {
+                for (uint32_t j = 0; j < 16; j++)
+                    if (k + j < cd.len)
+                        m |= (uint32_t)(src[k + j] >> 7) << j;
+            }
+            const uint32_t cnt = __builtin_popcount(m);
+            const uint32_t inc = wave_scan_add(cnt, lane);
+            uint64_t pos = off + (inc - cnt);
+            while (m) {
+                const uint32_t j = (uint32_t)__builtin_ctz(m);
+                if (pos < td.n) // always, for consistent counts
+                    td.viol[pos] = (uint32_t)(cd.start + k + j);
+                pos++;
+                m &= m - 1;
+            }
+            off += __builtin_amdgcn_readlane(inc, WAVE - 1);
         }
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_batch_chunk_gather(const TraceDesc *__restrict__ d,
-                                                              const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
-                                                              const uint64_t *__restrict__ chunk_pos,
-                                                              const uint8_t *__restrict__ comb, uint64_t cap,
-                                                              uint8_t *__restrict__ status_all,
-                                                              unsigned long long *__restrict__ ind)
+// bucket route, one workgroup per trace: its final statuses and its counts (violations:
+// the span of its chunks in vpos)
+__global__ __launch_bounds__(BLOCK) void k_batch_finish(const TraceDesc *__restrict__ d, uint32_t n_traces,
+                                                        uint64_t n_chunks, const uint64_t *__restrict__ vpos,
+                                                        const uint8_t *__restrict__ fin_all,
+                                                        const Control *__restrict__ bctl,
+                                                        const unsigned long long *__restrict__ ind)
 {
-    __shared__ ChunkStage s_stage[CH_WAVES];
-    ChunkStage &S = s_stage[wave_index()];
-    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
-         c += (uint64_t)gridDim.x * CH_WAVES) {
-        const ChunkDesc cd = ch[c];
-        const TraceDesc td = d[cd.trace];
-        const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
-        uint32_t stuck = 0;
-        walk_chunk(td, cd, bucket_base(td, cd, chunk_pos, c), false, S,
-                   [&](uint32_t q, uint64_t p, uint64_t i, uint32_t, uint32_t) {
-                       if (p < lo || p >= hi)
-                           return; // reported by the word pass
-                       const uint8_t v = comb[p];
-                       if (q == 0) {
-                           status_all[td.ev_base + i] = v;
-                           td.status[i] = v;
-                       } else {
-                           stuck += v >> 7;
-                       }
-                   });
-        if (td.off) { // uniform per wave
-            const uint32_t k = wave_total_u32(stuck);
-            if (lane_id() == 0 && k)
-                atomicAdd(&ind[cd.trace], (unsigned long long)k);
-        }
+    const uint32_t t = blockIdx.x;
+    const TraceDesc &td = d[t];
+    for (uint64_t k = threadIdx.x; k < td.n_ids; k += BLOCK)
+        td.fin[k] = fin_all[td.key_base + k];
+    if (threadIdx.x == 0) {
+        const uint64_t c1 = t + 1 < n_traces ? d[t + 1].first_chunk : n_chunks;
+        td.ctl->n_viol = vpos[c1] - vpos[td.first_chunk];
+        td.ctl->n_induced_stuck = ind[t];
+        if (bctl->err_code) // an internal error of the shared pipeline concerns every trace
+            atomicOr(&td.ctl->err_code, bctl->err_code);
     }
 }
 
@@ -335,9 +547,8 @@ __global__ __launch_bounds__(BLOCK) void k_batch_distribute(const TraceDesc *__r
 {
     const TraceDesc &td = d[blockIdx.x];
     const uint32_t tid = threadIdx.x;
-    if (status_all)
-        for (uint64_t i = tid; i < td.n; i += BLOCK)
-            td.status[i] = status_all[td.ev_base + i];
+    for (uint64_t i = tid; i < td.n; i += BLOCK)
+        td.status[i] = status_all[td.ev_base + i];
     for (uint64_t k = tid; k < td.n_ids; k += BLOCK)
         td.fin[k] = fin_all[td.key_base + k];
     __shared__ uint64_t s_lo, s_hi;
@@ -419,18 +630,37 @@ void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t 
 {
     if (n_chunks) {
         ProfScope prof_(s, "batch_chunk_words");
-        k_batch_chunk_words<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, words, cap);
+        k_batch_chunk_words<true><<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, words, cap);
+        k_batch_chunk_words<false><<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, words, cap);
     }
 }
 
-void launch_batch_chunk_gather(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
-                               const uint8_t *comb, uint64_t cap, uint8_t *status_all, unsigned long long *ind,
+void launch_batch_chunk_status(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
+                               const uint8_t *comb, uint64_t cap, uint32_t *vcnt, unsigned long long *ind,
                                hipStream_t s)
 {
     if (n_chunks) {
-        ProfScope prof_(s, "batch_chunk_gather");
-        k_batch_chunk_gather<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, comb, cap, status_all,
-                                                                  ind);
+        ProfScope prof_(s, "batch_chunk_status");
+        k_batch_chunk_status<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, comb, cap, vcnt,
+                                                                         ind);
+    }
+}
+
+void launch_batch_chunk_viol(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint32_t *vcnt,
+                             const uint64_t *vpos, hipStream_t s)
+{
+    if (n_chunks) {
+        ProfScope prof_(s, "batch_chunk_viol");
+        k_batch_chunk_viol<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, vcnt, vpos);
+    }
+}
+
+void launch_batch_finish(const TraceDesc *d, uint32_t n_traces, uint64_t n_chunks, const uint64_t *vpos,
+                         const uint8_t *fin_all, const Control *bctl, const unsigned long long *ind, hipStream_t s)
+{
+    if (n_traces) {
+        ProfScope prof_(s, "batch_finish");
+        k_batch_finish<<<n_traces, BLOCK, 0, s>>>(d, n_traces, n_chunks, vpos, fin_all, bctl, ind);
     }
 }
 

@@ -367,9 +367,11 @@ static bool launch_slot(vc_server *S, Slot &sl, std::vector<Chunk *> &batch)
     // staging: the batch's events, then the header gather's pointer arrays (control
     // blocks, violation lists), 16-byte aligned pieces
     const size_t nc = batch.size();
+    // (each chunk's events and status bytes 16-byte aligned: the batched pipeline copies
+    // a chunk's status bytes 16 at a time)
     sl.ev_off.assign(nc + 1, 0);
     for (size_t i = 0; i < nc; i++)
-        sl.ev_off[i + 1] = sl.ev_off[i] + ((batch[i]->events.size() + 3) & ~size_t(3));
+        sl.ev_off[i + 1] = sl.ev_off[i] + ((batch[i]->events.size() + 15) & ~size_t(15));
     const size_t ev_bytes = 4 * sl.ev_off[nc], ptr_bytes = 16 * nc;
     const size_t hdr_bytes = slot_header_bytes(nc), st_bytes = sl.ev_off[nc];
     if (!sl.h_in.reserve(ev_bytes + ptr_bytes) || !sl.d_in.reserve(ev_bytes + ptr_bytes) ||
