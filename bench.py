@@ -37,10 +37,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_digest() -> str:
+def source_digest(label: str | None = None) -> str:
+    """Digest of the kernel sources: all of them, or, for a kernel's profiling label, the
+    headers and the source files that launch a kernel under that label (a change
+    elsewhere leaves that kernel's counters valid)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1910_11110_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    files = sorted(os.listdir(d))
+    if label is not None:
+        key = f'"{label}"'.encode()
+        srcs = []
+        for f in files:
+            if not f.endswith(".h"):
+                with open(os.path.join(d, f), "rb") as fh:
+                    if key in fh.read():
+                        srcs.append(f)
+        if srcs:
+            files = sorted([f for f in files if f.endswith(".h")] + srcs)
+    for f in files:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -56,7 +70,7 @@ def traffic_for(kernel: str, workload: str):
         with open(p) as f:
             t = json.load(f)
         e = t.get(workload, {}).get(kernel)
-        if e and e.get("source_digest") == source_digest():
+        if e and e.get("source_digest") == source_digest(kernel):
             return e["bytes_per_launch"]
     except Exception:
         return None

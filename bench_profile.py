@@ -11,7 +11,8 @@
       into WRITE_DIR).  Each counter is scaled by what it reads for the copy probe (one
       elementwise kernel that reads and writes a known number of bytes).  Writes the
       per-kernel figures into profiles/traffic.json under W, keyed by the kernel labels
-      bench.py reports, with the digest of the kernel sources they were taken on.
+      bench.py reports, each with the digest of the sources it was taken on (the headers
+      and the files that launch a kernel under that label).
 """
 from __future__ import annotations
 
@@ -89,7 +90,6 @@ def cmd_traffic(a):
                  ", ".join(sorted({short_name(k)[:60] for k in fetch if 'vc::' not in k})))
     kf = PROBE_BYTES / (probe_f[0] * 1024.0)
     kw = PROBE_BYTES / (probe_w[0] * 1024.0)
-    digest = source_digest()
     res = {}
     print(f"copy probe: FETCH_SIZE {probe_f[0]:.0f} KiB, WRITE_SIZE {probe_w[0]:.0f} KiB for "
           f"{PROBE_BYTES} bytes each way; scale factors fetch {kf:.4f}, write {kw:.4f}\n")
@@ -110,7 +110,7 @@ def cmd_traffic(a):
         fb, wb = f / n, w / n
         bytes_ = fb * 1024 * kf + wb * 1024 * kw
         res[lab] = {"bytes_per_launch": round(bytes_), "fetch_kib": round(fb, 1), "write_kib": round(wb, 1),
-                    "dispatches": n, "source_digest": digest}
+                    "dispatches": n, "source_digest": source_digest(lab)}
         print(f"| {lab} | {lab} | {n} | {fb:.1f} | {wb:.1f} | {bytes_:.0f} |")
     p = os.path.join(ROOT, "profiles", "traffic.json")
     t = {}
