@@ -25,13 +25,16 @@ HIP_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", 
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")) +
+                  glob.glob(os.path.join(CSRC, "*.cc")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip"] + HIP_FLAGS + COMMON + ["-c", src, "-o", obj]
+    elif src.endswith(".cc"):  # host-only C++ (no device pass)
+        cmd = [HIPCC, "-x", "c++"] + COMMON + ["-c", src, "-o", obj]
     else:
         cmd = [HIPCC, "-x", "hip", f"--offload-arch={ARCH}"] + COMMON + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)

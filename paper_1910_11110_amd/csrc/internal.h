@@ -266,4 +266,11 @@ void launch_overlap_emit(const uint32_t *ev, uint64_t n, uint32_t n_arrays, cons
                          uint64_t *items, uint64_t cap, uint32_t key_base, uint64_t payload_base, uint32_t trace_index,
                          Control *ctl, hipStream_t s);
 
+// ---------------------------------------------------------------------------------
+// host-only helpers (host_scan.cc)
+// ---------------------------------------------------------------------------------
+// whether any of n events is malformed (a reserved bit set, an op above Noop, or an id at
+// or above n_ids <= 2^24), in one vectorized pass
+bool any_malformed(const uint32_t *ev, uint32_t n, uint32_t n_ids);
+
 } // namespace vc

@@ -761,11 +761,12 @@ extern "C" int vc_stream_submit(vc_server *S, uint64_t stream, const uint32_t *e
             return vc_fail(VC_EINVAL, "vc_stream_submit: unknown or closing stream %llu", (unsigned long long)stream);
         n_ids = it->second->n_ids;
     }
-    for (uint32_t i = 0; i < n; i++) {
-        uint32_t w = events[i];
-        if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= n_ids)
-            return vc_fail(VC_EINVAL, "vc_stream_submit: malformed event 0x%08x at index %u", w, i);
-    }
+    if (vc::any_malformed(events, n, n_ids)) // then the first malformed event, for the message
+        for (uint32_t i = 0; i < n; i++) {
+            uint32_t w = events[i];
+            if ((w >> 28) != 0 || ((w >> 24) & 7u) > 4 || (w & 0xFFFFFFu) >= n_ids)
+                return vc_fail(VC_EINVAL, "vc_stream_submit: malformed event 0x%08x at index %u", w, i);
+        }
     Chunk *c = new Chunk();
     c->events.assign(events, events + n);
     c->status_out = status_out;
