@@ -37,13 +37,12 @@ struct BatchState {
     std::vector<uint64_t> signature;
     // host copies of the uploaded descriptor tables (alive until the next upload)
     std::vector<TraceDesc> h_desc;
-    std::vector<uint64_t> h_ev_off, h_key_off;
     std::vector<ChunkDesc> h_chunks;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     bool graph_ok = false;
     // device buffers
-    DevBuf desc, ev_off, key_off, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind,
+    DevBuf desc, init_all, fin_all, status_all, viol_all, items_a, items_b, cnt, pos, scratch, ind,
         chunks, words, comb, vcnt, vpos;
     uint64_t n_chunks = 0;
     Control *ctl = nullptr;
@@ -213,8 +212,6 @@ int reserve_all(BatchState &b, uint32_t n)
     int r;
     uint64_t N = b.N, K = b.K, M = b.M;
     if ((r = devbuf_reserve(b.desc, sizeof(TraceDesc) * (n ? n : 1))) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.ev_off, 8 * (n + 1))) != VC_OK) return r;
-    if ((r = devbuf_reserve(b.key_off, 8 * (n + 1))) != VC_OK) return r;
     if ((r = devbuf_reserve(b.init_all, K ? K : 1)) != VC_OK) return r;
     if ((r = devbuf_reserve(b.fin_all, K ? K : 1)) != VC_OK) return r;
     const uint64_t nc = b.n_chunks;
@@ -258,7 +255,7 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
     uint32_t n = b.n_traces;
     launch_reset_control(b.ctl, s);
     launch_batch_reset(d, n, (unsigned long long *)b.ind.p, s);
-    launch_batch_init(d, (const uint64_t *)b.key_off.p, n, b.K, (uint8_t *)b.init_all.p, (uint8_t *)b.fin_all.p, s);
+    launch_batch_init(d, n, b.K, (uint8_t *)b.init_all.p, (uint8_t *)b.fin_all.p, s);
     const ChunkDesc *ch = (const ChunkDesc *)b.chunks.p;
     launch_batch_chunk_count(d, ch, b.n_chunks, (uint32_t *)b.cnt.p, s);
     launch_excl_scan((uint32_t *)b.cnt.p, b.n_chunks, (uint64_t *)b.pos.p, nullptr, b.scratch.p, b.ctl->tickets[6], s);
@@ -319,8 +316,6 @@ int configure(BatchState &b)
         return r;
     hipError_t e;
     if ((e = hipMemcpy(b.desc.p, b.h_desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(b.ev_off.p, b.h_ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(b.key_off.p, b.h_key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice)) != hipSuccess ||
         (b.n_chunks && (e = hipMemcpy(b.chunks.p, b.h_chunks.data(), sizeof(ChunkDesc) * b.n_chunks,
                                       hipMemcpyHostToDevice)) != hipSuccess))
         return vc_hip_fail(e, "hipMemcpy(batch descriptors)");
@@ -470,7 +465,7 @@ void batch_free(BatchState *b)
     if (!b)
         return;
     drop_graph(*b);
-    for (DevBuf *d : { &b->desc, &b->ev_off, &b->key_off, &b->init_all, &b->fin_all, &b->status_all, &b->viol_all,
+    for (DevBuf *d : { &b->desc, &b->init_all, &b->fin_all, &b->status_all, &b->viol_all,
                        &b->items_a, &b->items_b, &b->cnt, &b->pos, &b->scratch, &b->ind, &b->chunks, &b->words,
                        &b->comb })
         devbuf_free(*d);
@@ -492,17 +487,11 @@ int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M,
 {
     uint32_t n = (uint32_t)desc.size();
     b.h_desc = desc;
-    b.h_ev_off.assign(n + 1, 0);
-    b.h_key_off.assign(n + 1, 0);
     uint64_t N = 0, K = 0;
     for (uint32_t i = 0; i < n; i++) {
-        b.h_ev_off[i] = N;
-        b.h_key_off[i] = K;
         N += desc[i].n;
         K += desc[i].n_ids;
     }
-    b.h_ev_off[n] = N;
-    b.h_key_off[n] = K;
     if (N >= (1ull << 31) || K > (1ull << 28))
         return vc_fail(VC_EINVAL, "batch too large");
     b.N = N;
@@ -524,8 +513,6 @@ int batch_prepare(BatchState &b, const std::vector<TraceDesc> &desc, uint64_t M,
     hipError_t e;
     if ((e = hipMemcpyAsync(b.desc.p, b.h_desc.data(), sizeof(TraceDesc) * n, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
-        (e = hipMemcpyAsync(b.ev_off.p, b.h_ev_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(b.key_off.p, b.h_key_off.data(), 8 * (n + 1), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (b.n_chunks && (e = hipMemcpyAsync(b.chunks.p, b.h_chunks.data(), sizeof(ChunkDesc) * b.n_chunks,
                                            hipMemcpyHostToDevice, s)) != hipSuccess))
         return vc_hip_fail(e, "hipMemcpyAsync(batch descriptors)");
@@ -550,7 +537,7 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
     hipStream_t s = c->stream;
     // shape and descriptors
     std::vector<TraceDesc> desc(n);
-    std::vector<uint64_t> ev_off(n + 1), key_off(n + 1), sig;
+    std::vector<uint64_t> sig;
     uint64_t N = 0, K = 0, M = 0;
     {
         // each trace at most once (sorted handles: neighbours)
@@ -575,8 +562,6 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
         if ((r = devbuf_reserve(t->status, t->n ? t->n : 1)) != VC_OK) return r;
         if ((r = devbuf_reserve(t->fin, t->n_ids ? t->n_ids : 1)) != VC_OK) return r;
         if ((r = devbuf_reserve(t->viol, 4 * (t->n ? t->n : 1))) != VC_OK) return r;
-        ev_off[i] = N;
-        key_off[i] = K;
         TraceDesc &d = desc[i];
         d.events = t->events;
         d.init = t->init;
@@ -599,8 +584,6 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
                             (uint64_t)(uintptr_t)d.fin, (uint64_t)(uintptr_t)d.viol, (uint64_t)t->n_induced })
             sig.push_back(v);
     }
-    ev_off[n] = N;
-    key_off[n] = K;
     if (N >= (1ull << 31))
         return vc_fail(VC_EINVAL, "vc_batch_check: %llu events in the batch exceed 2^31 - 1", (unsigned long long)N);
     if (K > (1ull << 28))
@@ -614,8 +597,6 @@ extern "C" int vc_batch_check(vc_ctx *c, vc_trace *const *traces, uint32_t n)
         b.M = M;
         b.n_traces = n;
         b.h_desc = desc;
-        b.h_ev_off = ev_off;
-        b.h_key_off = key_off;
         // the bucket route's settings: cached for this shape, else the defaults until
         // the autotuner has run
         SortTuning cached{};

@@ -65,8 +65,9 @@ void launch_batch_finish(const TraceDesc *d, uint32_t n_traces, uint64_t n_chunk
                          const uint8_t *fin_all, const Control *bctl, const unsigned long long *ind, hipStream_t s);
 
 void launch_batch_reset(const TraceDesc *d, uint32_t n_traces, unsigned long long *ind, hipStream_t s);
-void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_traces, uint64_t K, uint8_t *init_all,
-                       uint8_t *fin_all, hipStream_t s);
+// every trace's initial statuses into its key range of init_all and fin_all (K keys)
+void launch_batch_init(const TraceDesc *d, uint32_t n_traces, uint64_t K, uint8_t *init_all, uint8_t *fin_all,
+                       hipStream_t s);
 // general route: every trace's status bytes, final statuses, violations and counts
 void launch_batch_distribute(const TraceDesc *d, uint32_t n_traces, const uint8_t *status_all, const uint8_t *fin_all,
                              const uint32_t *viol_all, const Control *bctl, const unsigned long long *ind,

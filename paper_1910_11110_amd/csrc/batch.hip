@@ -4,8 +4,8 @@
 // index range, so one sort / scan / compaction over the concatenation evaluates every
 // trace as if it were alone: no state crosses a key range, and the segmented scan
 // restarts at every key.  Events are relocated by chunks of one trace each (the chunk
-// table is built once per batch shape), so no event searches for its trace; ids search
-// the key prefix array once when the initial statuses are gathered.
+// table is built once per batch shape), so no event searches for its trace; each
+// trace's initial statuses are copied into its key range by a workgroup of its own.
 #include "batch.h"
 #include "device.h"
 #include "internal.h"
@@ -14,20 +14,6 @@
 namespace vc {
 
 namespace {
-
-__device__ __forceinline__ uint32_t find_range(const uint64_t *__restrict__ off, uint32_t n, uint64_t x)
-{
-    // largest i with off[i] <= x, for off non-decreasing with off[0] = 0
-    uint32_t lo = 0, hi = n; // invariant: off[lo] <= x < off[hi] (off[n] = total)
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= x)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ void report_bad(Control *ctl, uint64_t i)
 {
@@ -49,16 +35,17 @@ __global__ void k_batch_reset(const TraceDesc *__restrict__ d, uint32_t n_traces
     ind[i] = 0;
 }
 
-__global__ void k_batch_init(const TraceDesc *__restrict__ d, const uint64_t *__restrict__ key_off, uint32_t n_traces,
-                             uint64_t K, uint8_t *__restrict__ init_all, uint8_t *__restrict__ fin_all)
+// one workgroup per trace: its initial statuses (or (V,I)) into its key range of both
+// tables (the final table starts as the initial one: ids no event touches keep it)
+__global__ __launch_bounds__(BLOCK) void k_batch_init(const TraceDesc *__restrict__ d, uint8_t *__restrict__ init_all,
+                                                      uint8_t *__restrict__ fin_all)
 {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += stride) {
-        uint32_t t = find_range(key_off, n_traces, k);
-        const uint8_t *ini = d[t].init;
-        uint8_t v = ini ? ini[k - key_off[t]] : (uint8_t)1;
-        init_all[k] = v;
-        fin_all[k] = v;
+    const TraceDesc &td = d[blockIdx.x];
+    const uint8_t *ini = td.init;
+    for (uint32_t k = threadIdx.x; k < td.n_ids; k += BLOCK) {
+        const uint8_t v = ini ? ini[k] : (uint8_t)1;
+        init_all[td.key_base + k] = v;
+        fin_all[td.key_base + k] = v;
     }
 }
 
@@ -597,14 +584,13 @@ void launch_batch_reset(const TraceDesc *d, uint32_t n_traces, unsigned long lon
     k_batch_reset<<<gridn(n_traces, 256), 256, 0, s>>>(d, n_traces, ind);
 }
 
-void launch_batch_init(const TraceDesc *d, const uint64_t *key_off, uint32_t n_traces, uint64_t K, uint8_t *init_all,
-                       uint8_t *fin_all, hipStream_t s)
+void launch_batch_init(const TraceDesc *d, uint32_t n_traces, uint64_t K, uint8_t *init_all, uint8_t *fin_all,
+                       hipStream_t s)
 {
-    if (K)
-        {
-            ProfScope prof_(s, "batch_init");
-            k_batch_init<<<gridn(K, 256 * 8), 256, 0, s>>>(d, key_off, n_traces, K, init_all, fin_all);
-        }
+    if (K && n_traces) {
+        ProfScope prof_(s, "batch_init");
+        k_batch_init<<<n_traces, BLOCK, 0, s>>>(d, init_all, fin_all);
+    }
 }
 
 void launch_batch_chunk_count(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, uint32_t *chunk_cnt,
