@@ -55,6 +55,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_init(const TraceDesc *__restric
 // consecutive positions: each event, then (a write of a trace with arrays) one induced
 // item per neighbour of its array.
 constexpr int CH_PER = BATCH_CHUNK / WAVE; // events per lane
+constexpr int WALK_U = 4;                  // steps of 64 items whose loads a walk issues together
 constexpr uint32_t CH_WAVES = BLOCK / WAVE;
 static_assert(CH_PER * WAVE == (int)BATCH_CHUNK, "a chunk is one wave's events");
 
@@ -97,7 +98,8 @@ struct ChunkStage {
 // e the event's cleaned word.  Without arrays lane l takes events l, l + 64, ...; with
 // arrays the events' item counts are scanned over the wave and the items walked 64
 // consecutive ones at a time, the lane of an item finding its event from a ballot of the
-// event starts among the 64.  Returns the chunk's number of items.
+// event starts among the 64 (WALK_U such steps find their events before their
+// neighbour loads are issued together).  Returns the chunk's number of items.
 template <class F>
 __device__ __forceinline__ uint32_t walk_chunk(const TraceDesc &td, const ChunkDesc &cd, uint64_t base, bool report,
                                                ChunkStage &S, F &&f)
@@ -157,25 +159,50 @@ __device__ __forceinline__ uint32_t walk_chunk(const TraceDesc &td, const ChunkD
     if (lane == 0)
         S.start[BATCH_CHUNK] = total;
     __builtin_amdgcn_wave_barrier();
+    // WALK_U steps of 64 items at a time: their events first (LDS only), then their
+    // neighbour loads issued together, then f
     uint32_t ec = 0; // the event covering item qc - 1 (event 0 for qc = 0)
-    for (uint32_t qc = 0; qc < total; qc += WAVE) {
-        // events ec + 1 .. ec + 64 hold every start inside [qc, qc + 64)
-        const uint32_t e = ec + 1 + lane;
-        const uint32_t st = e <= BATCH_CHUNK ? S.start[e] : total;
-        S.mark[lane] = 0;
-        __builtin_amdgcn_wave_barrier();
-        if (st < total && st < qc + WAVE)
-            S.mark[st - qc] = 1;
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t heads = __ballot(S.mark[lane] != 0);
-        const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
-        const uint32_t q = qc + lane;
-        if (q < total) {
-            const uint32_t kq = q - S.start[own], w = S.word[own];
-            f(kq, base + q, cd.start + own, w, kq ? td.nbr[S.nb[own] + kq - 1] : 0u);
+    for (uint32_t qc = 0; qc < total; qc += WALK_U * WAVE) {
+        uint32_t own[WALK_U];
+#pragma unroll
+        for (int u = 0; u < WALK_U; u++) {
+            const uint32_t q0 = qc + u * WAVE;
+            own[u] = 0;
+            if (q0 >= total)
+                continue; // uniform
+            // events ec + 1 .. ec + 64 hold every start inside [q0, q0 + 64)
+            const uint32_t e = ec + 1 + lane;
+            const uint32_t st = e <= BATCH_CHUNK ? S.start[e] : total;
+            S.mark[lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (st < total && st < q0 + WAVE)
+                S.mark[st - q0] = 1;
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t heads = __ballot(S.mark[lane] != 0);
+            own[u] = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
+            ec += (uint32_t)__builtin_popcountll(heads);
+            __builtin_amdgcn_wave_barrier();
         }
-        ec += (uint32_t)__builtin_popcountll(heads);
-        __builtin_amdgcn_wave_barrier();
+        uint32_t kq[WALK_U], w[WALK_U], y[WALK_U];
+#pragma unroll
+        for (int u = 0; u < WALK_U; u++) {
+            const uint32_t q = qc + u * WAVE + lane;
+            kq[u] = 0;
+            w[u] = 0;
+            y[u] = 0;
+            if (q < total) {
+                kq[u] = q - S.start[own[u]];
+                w[u] = S.word[own[u]];
+                if (kq[u])
+                    y[u] = td.nbr[S.nb[own[u]] + kq[u] - 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < WALK_U; u++) {
+            const uint32_t q = qc + u * WAVE + lane;
+            if (q < total)
+                f(kq[u], base + q, cd.start + own[u], w[u], y[u]);
+        }
     }
     return total;
 }
