@@ -88,12 +88,13 @@ __global__ void k_dyn_nbr_life(const uint32_t *__restrict__ nbr, uint64_t n_nbr,
 // candidate per neighbour of its array; a neighbour's candidate becomes an induced RW
 // item when the neighbour is live at the write.  The candidates of a tile are walked
 // 64 consecutive ones at a time (the lane of a candidate finds its event from a ballot
-// of the event starts among the 64), and the items kept are compacted in order by a
-// ballot.  The count pass gives every tile its number of items; the emit pass, with
+// of the event starts among the 64; four such steps find their events before their
+// loads are issued together), and the items kept are compacted in order by a ballot.  The count pass gives every tile its number of items; the emit pass, with
 // the tiles' scanned positions, writes them.
 constexpr int D_PER = 8;                   // events per lane
 constexpr uint32_t DTILE = WAVE * D_PER;   // events per wave tile
 constexpr uint32_t DWAVES = BLOCK / WAVE;
+constexpr int DWALK_U = 4;                 // steps of 64 candidates whose loads are issued together
 
 // an event's candidate run and its checks: malformed words and liveness errors are
 // reported at their index (the smallest one is the first error of a sequential
@@ -183,63 +184,99 @@ __global__ __launch_bounds__(BLOCK) void k_dyn_tiles(const uint32_t *__restrict_
     const uint64_t base = EMIT ? tpos[tile] : 0;
     uint32_t kept = 0;
     uint32_t ec = 0; // the event covering candidate qc - 1 (event 0 for qc = 0)
-    for (uint32_t qc = 0; qc < total; qc += WAVE) {
-        // events ec + 1 .. ec + 64 hold every start inside [qc, qc + 64)
-        const uint32_t e = ec + 1 + lane;
-        const uint32_t st = e <= DTILE ? s_start[wv][e] : total;
-        s_mark[wv][lane] = 0;
-        __builtin_amdgcn_wave_barrier();
-        if (st < total && st < qc + WAVE)
-            s_mark[wv][st - qc] = 1;
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t heads = __ballot(s_mark[wv][lane] != 0);
-        const uint32_t own = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
-        const uint32_t q = qc + lane;
-        bool keep = false, primary = false;
-        uint64_t item = 0;
-        uint32_t word = 0;
-        if (q < total) {
-            const uint32_t k = q - s_start[wv][own];
-            const uint32_t w = s_word[wv][own], op = (w >> 24) & 7u, x = w & 0xFFFFFFu, side = (w >> 27) & 1u;
-            const uint64_t t = i0 + own;
-            keep = true;
-            if (k == 0) {
-                primary = true;
-                if (MODE == D_ITEMS)
-                    item = make_item(x, op >= OP_CREATE ? fcode(OP_NOOP, 0) : fcode(op, side), (uint32_t)t);
-                if (MODE == D_WORDS)
-                    word = x | (op >= OP_CREATE ? (uint32_t)OP_NOOP << 24 : (w & (15u << 24)));
-            } else if (op == OP_CREATE) {
-                if (MODE == D_ITEMS)
-                    item = make_item(mother[x], fcode(OP_NOOP, 0), (uint32_t)(n + t));
-                if (MODE == D_WORDS)
-                    word = mother[x] | (uint32_t)OP_NOOP << 24;
-            } else {
-                const uint64_t j = s_nb[wv][own] + k - 1;
-                const uint2 lf = life[j];
-                keep = (lf.x == NO_POS || lf.x < t) && (lf.y == NO_POS || t < lf.y);
-                if (MODE == D_ITEMS)
-                    item = make_item(nbr[j], fcode(OP_RWIND, side), INDUCED_BIT);
-                if (MODE == D_WORDS)
-                    word = nbr[j] | (uint32_t)OP_RWIND << 24 | (side << 27);
+    for (uint32_t qc = 0; qc < total; qc += DWALK_U * WAVE) {
+        // DWALK_U steps of 64 candidates: their events first (LDS only), then their
+        // neighbours' lifetimes and ids loaded together, then the items kept, in order
+        uint32_t own[DWALK_U];
+#pragma unroll
+        for (int u = 0; u < DWALK_U; u++) {
+            const uint32_t q0 = qc + u * WAVE;
+            own[u] = 0;
+            if (q0 >= total)
+                continue; // uniform
+            // events ec + 1 .. ec + 64 hold every start inside [q0, q0 + 64)
+            const uint32_t e = ec + 1 + lane;
+            const uint32_t st = e <= DTILE ? s_start[wv][e] : total;
+            s_mark[wv][lane] = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (st < total && st < q0 + WAVE)
+                s_mark[wv][st - q0] = 1;
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t heads = __ballot(s_mark[wv][lane] != 0);
+            own[u] = ec + mask_rank(heads) + (uint32_t)((heads >> lane) & 1u);
+            ec += (uint32_t)__builtin_popcountll(heads);
+            __builtin_amdgcn_wave_barrier();
+        }
+        uint32_t kk[DWALK_U], y[DWALK_U];
+        uint2 lf[DWALK_U];
+#pragma unroll
+        for (int u = 0; u < DWALK_U; u++) {
+            const uint32_t q = qc + u * WAVE + lane;
+            kk[u] = 0;
+            y[u] = 0;
+            lf[u] = make_uint2(NO_POS, NO_POS);
+            if (q < total) {
+                kk[u] = q - s_start[wv][own[u]];
+                const uint32_t w = s_word[wv][own[u]];
+                if (kk[u] != 0) {
+                    if (((w >> 24) & 7u) == OP_CREATE) {
+                        if (EMIT)
+                            y[u] = mother[w & 0xFFFFFFu];
+                    } else {
+                        const uint64_t j = s_nb[wv][own[u]] + kk[u] - 1;
+                        lf[u] = life[j];
+                        if (EMIT)
+                            y[u] = nbr[j];
+                    }
+                }
             }
         }
-        const uint64_t km = __ballot(keep);
-        if (EMIT && keep) {
-            const uint64_t p = base + kept + mask_rank(km);
-            if (p >= cap) { // the events changed since the items were sized: refused, in bounds
-                report_bad(ctl, i0 + own);
-            } else if (MODE == D_ITEMS) {
-                items[p] = item;
-            } else {
-                words[p] = word;
-                if (primary)
-                    pos32[i0 + own] = (uint32_t)p; // below 2^32 on this route
+#pragma unroll
+        for (int u = 0; u < DWALK_U; u++) {
+            const uint32_t q = qc + u * WAVE + lane;
+            bool keep = false, primary = false;
+            uint64_t item = 0;
+            uint32_t word = 0;
+            const uint32_t o = own[u];
+            if (q < total) {
+                const uint32_t k = kk[u];
+                const uint32_t w = s_word[wv][o], op = (w >> 24) & 7u, x = w & 0xFFFFFFu, side = (w >> 27) & 1u;
+                const uint64_t t = i0 + o;
+                keep = true;
+                if (k == 0) {
+                    primary = true;
+                    if (MODE == D_ITEMS)
+                        item = make_item(x, op >= OP_CREATE ? fcode(OP_NOOP, 0) : fcode(op, side), (uint32_t)t);
+                    if (MODE == D_WORDS)
+                        word = x | (op >= OP_CREATE ? (uint32_t)OP_NOOP << 24 : (w & (15u << 24)));
+                } else if (op == OP_CREATE) {
+                    if (MODE == D_ITEMS)
+                        item = make_item(y[u], fcode(OP_NOOP, 0), (uint32_t)(n + t));
+                    if (MODE == D_WORDS)
+                        word = y[u] | (uint32_t)OP_NOOP << 24;
+                } else {
+                    keep = (lf[u].x == NO_POS || lf[u].x < t) && (lf[u].y == NO_POS || t < lf[u].y);
+                    if (MODE == D_ITEMS)
+                        item = make_item(y[u], fcode(OP_RWIND, side), INDUCED_BIT);
+                    if (MODE == D_WORDS)
+                        word = y[u] | (uint32_t)OP_RWIND << 24 | (side << 27);
+                }
             }
+            const uint64_t km = __ballot(keep);
+            if (EMIT && keep) {
+                const uint64_t p = base + kept + mask_rank(km);
+                if (p >= cap) { // the events changed since the items were sized: refused, in bounds
+                    report_bad(ctl, i0 + o);
+                } else if (MODE == D_ITEMS) {
+                    items[p] = item;
+                } else {
+                    words[p] = word;
+                    if (primary)
+                        pos32[i0 + o] = (uint32_t)p; // below 2^32 on this route
+                }
+            }
+            kept += (uint32_t)__builtin_popcountll(km);
         }
-        kept += (uint32_t)__builtin_popcountll(km);
-        ec += (uint32_t)__builtin_popcountll(heads);
-        __builtin_amdgcn_wave_barrier();
     }
     if (!EMIT && lane == 0)
         tcnt[tile] = kept;
