@@ -289,10 +289,13 @@ int vc_profile_read(vc_ctx *ctx, char *names, uint32_t names_cap, double *ms, ui
  * The launch sequence is captured once per batch shape in a hipGraph and replayed.
  * --------------------------------------------------------------------------------- */
 int vc_batch_check(vc_ctx *ctx, vc_trace *const *traces, uint32_t n);
-/* settings of the last batch: whether it runs from a captured hipGraph, and the
- * autotuned sort digit width / persistent grid bounds (0 = one workgroup per tile).
- * Tuning runs when VC_AUTOTUNE is set in the environment and is cached per shape in
- * $VC_TUNE_CACHE (default ~/.cache/vcheck_tune.json); VC_NO_GRAPH disables capture. */
+/* settings of the last batch: whether it runs from a captured hipGraph; on the bucket
+ * route (every trace with 1 to 2^22 ids) the ids per group as a power of two (max_bits)
+ * and the events per chunk of a trace without arrays (grid_cap), scan_grid 0; on the
+ * sorted route the sort digit width and the persistent grid bounds (0 = one workgroup
+ * per tile).  The autotuner runs on a batch shape's first check unless VC_NO_AUTOTUNE
+ * is set in the environment, and caches its choice per shape in $VC_TUNE_CACHE
+ * (default ~/.cache/vcheck_tune.json); VC_NO_GRAPH disables capture. */
 int vc_batch_info(vc_ctx *ctx, int *graph, int *max_bits, unsigned *grid_cap, unsigned *scan_grid);
 
 /* ---------------------------------------------------------------------------------

@@ -666,13 +666,14 @@ extern "C" int vc_batch_info(vc_ctx *c, int *graph, int *max_bits, unsigned *gri
     if (!c)
         return vc_fail(VC_EINVAL, "vc_batch_info: NULL context");
     BatchState *b = c->batch;
+    const bool bucket = b && b->bucket;
     if (graph)
         *graph = b && b->graph_ok;
     if (max_bits)
-        *max_bits = b ? b->tune.max_bits : 0;
+        *max_bits = !b ? 0 : bucket ? (int)b->group_bits : b->tune.max_bits;
     if (grid_cap)
-        *grid_cap = b ? b->tune.grid_cap : 0;
+        *grid_cap = !b ? 0u : bucket ? b->plain_chunk : b->tune.grid_cap;
     if (scan_grid)
-        *scan_grid = b ? b->scan_grid : 0;
+        *scan_grid = b && !bucket ? b->scan_grid : 0u;
     return VC_OK;
 }
