@@ -83,6 +83,12 @@ DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_dec
                                            uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
                                            uint32_t *chunk_sum, bool lookback_cleared = false,
                                            hipEvent_t after_hist = nullptr);
+// the status before every word of a combined stream (bits 0-1 of its byte), the way the
+// declarations' pre-statuses come: in the partitioned order with every word's
+// destination there (res, dstidx), or in program order in pre (m bytes) when all ids
+// fall in one bucket (dstidx null).  No final table, no violations; ctl is reset first.
+DeclPre launch_bucket_pre_combined(const uint32_t *words, uint64_t m, uint32_t n_ids, const uint8_t *init,
+                                   uint8_t *pre, void *scratch, Control *ctl, hipStream_t s, int cu);
 // the look-back words of the bucket scan inside `scratch` (as a job that zeroes them)
 FillJob bucket_lookback(void *scratch, uint64_t n, uint32_t n_ids);
 

@@ -1263,6 +1263,19 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
     k_replay_bytes<<<grid, BLOCK, 0, s>>>(L.dstidx, n_decl, L.res, pre);
 }
 
+DeclPre launch_bucket_pre_combined(const uint32_t *words, uint64_t m, uint32_t n_ids, const uint8_t *init,
+                                   uint8_t *pre, void *scratch, Control *ctl, hipStream_t s, int cu)
+{
+    launch_reset_control(ctl, s);
+    if (m == 0)
+        return DeclPre{pre, nullptr};
+    BucketLayout L = bucket_layout(scratch, m, n_ids);
+    partition_and_scan<CombinedWords>(words, m, n_ids, init, BK_PRE, nullptr, L, pre, ctl, s, cu);
+    if (L.nb == 1)
+        return DeclPre{pre, nullptr};
+    return DeclPre{L.res, L.dstidx};
+}
+
 DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_decl, uint32_t n_vars, uint8_t *pre,
                                            uint8_t *final_out, void *scratch, Control *ctl, hipStream_t s, int cu,
                                            uint32_t *chunk_sum, bool lookback_cleared, hipEvent_t after_hist)

@@ -301,19 +301,25 @@ __global__ void k_dyn_inherit(const uint32_t *__restrict__ mother, const uint32_
     }
 }
 
-// the same from the first bucket check's status bytes (post | pre << 2 | flag << 7): a
-// create's probe sits right after the create, at pos32[c] + 1
+// the same from the words' pre-statuses (bits 0-1 of pre[i], through dstidx[i] when it
+// is given): a create's probe sits right after the create, at pos32[c] + 1
 __global__ void k_dyn_inherit_words(const uint32_t *__restrict__ mother, const uint32_t *__restrict__ cpos,
-                                    const uint8_t *__restrict__ comb, const uint32_t *__restrict__ pos32, uint64_t n,
-                                    uint64_t m, const uint8_t *__restrict__ init, uint32_t n_ids,
-                                    uint8_t *__restrict__ init2, uint8_t *__restrict__ fin)
+                                    const uint8_t *__restrict__ pre, const uint32_t *__restrict__ dstidx,
+                                    const uint32_t *__restrict__ pos32, uint64_t n, uint64_t m,
+                                    const uint8_t *__restrict__ init, uint32_t n_ids, uint8_t *__restrict__ init2,
+                                    uint8_t *__restrict__ fin)
 {
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n_ids; x += gridDim.x * blockDim.x) {
         const uint32_t c = cpos[x];
         uint8_t s = init ? init[x] : (uint8_t)1;
         if (c != NO_POS && c < n && mother[x] != NO_MOTHER) {
-            const uint64_t p = (uint64_t)pos32[c] + 1;
-            s = (uint8_t)((comb[p < m ? p : m - 1] >> 2) & 3u);
+            uint64_t p = (uint64_t)pos32[c] + 1;
+            p = p < m ? p : m - 1;
+            if (dstidx) {
+                p = dstidx[p];
+                p = p < m ? p : m - 1; // (in range for consistent counts)
+            }
+            s = (uint8_t)(pre[p] & 3u);
         }
         init2[x] = s;
         fin[x] = s;
@@ -385,13 +391,13 @@ void launch_dyn_words(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint
     }
 }
 
-void launch_dyn_inherit_words(const uint32_t *mother, const uint32_t *cpos, const uint8_t *comb, const uint32_t *pos32,
-                              uint64_t n, uint64_t m, const uint8_t *init, uint32_t n_ids, uint8_t *init2, uint8_t *fin,
-                              hipStream_t s)
+void launch_dyn_inherit_words(const uint32_t *mother, const uint32_t *cpos, const uint8_t *pre, const uint32_t *dstidx,
+                              const uint32_t *pos32, uint64_t n, uint64_t m, const uint8_t *init, uint32_t n_ids,
+                              uint8_t *init2, uint8_t *fin, hipStream_t s)
 {
     ProfScope p(s, "dyn_inherit");
-    k_dyn_inherit_words<<<grid_of(n_ids), BLOCK, 0, s>>>(mother, cpos, comb, pos32, n, m ? m : 1, init, n_ids, init2,
-                                                         fin);
+    k_dyn_inherit_words<<<grid_of(n_ids), BLOCK, 0, s>>>(mother, cpos, pre, dstidx, pos32, n, m ? m : 1, init, n_ids,
+                                                         init2, fin);
 }
 
 void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint8_t *probe_pre, uint64_t n,

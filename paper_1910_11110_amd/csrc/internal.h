@@ -193,11 +193,12 @@ void launch_dyn_emit(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint3
 void launch_dyn_words(const uint32_t *ev, uint64_t n, uint32_t n_ids, const uint32_t *mother, const uint32_t *cpos,
                       const uint32_t *dpos, const OverlapSets *o, const uint2 *life, const uint64_t *tpos,
                       uint32_t *words, uint32_t *pos32, uint64_t cap, Control *ctl, hipStream_t s);
-// bucket route: the initial statuses of the second check from the first check's status
-// bytes over the m words (a create's probe right after it)
-void launch_dyn_inherit_words(const uint32_t *mother, const uint32_t *cpos, const uint8_t *comb, const uint32_t *pos32,
-                              uint64_t n, uint64_t m, const uint8_t *init, uint32_t n_ids, uint8_t *init2, uint8_t *fin,
-                              hipStream_t s);
+// bucket route: the initial statuses of the second check from the words' pre-statuses
+// (bits 0-1 of pre[i], read through dstidx[i] when it is given; a create's probe right
+// after it)
+void launch_dyn_inherit_words(const uint32_t *mother, const uint32_t *cpos, const uint8_t *pre, const uint32_t *dstidx,
+                              const uint32_t *pos32, uint64_t n, uint64_t m, const uint8_t *init, uint32_t n_ids,
+                              uint8_t *init2, uint8_t *fin, hipStream_t s);
 // initial statuses of the second scan (inherited by created partial vectors) into
 // init2 and fin
 void launch_dyn_inherit(const uint32_t *mother, const uint32_t *cpos, const uint8_t *probe_pre, uint64_t n,

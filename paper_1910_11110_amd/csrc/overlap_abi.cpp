@@ -303,9 +303,10 @@ static int dynamic_bucket_enqueue(vc_trace *t, hipStream_t s)
     launch_dyn_words(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, A.tpos, words, A.pos32, m,
                      A.xctl, s);
     const int cu = t->ctx->cu_count;
-    launch_bucket_check_combined(words, m, t->n_ids, t->init, comb, nullptr, nullptr, t->scratch.p, t->ctl, s, cu,
-                                 nullptr);
-    launch_dyn_inherit_words(t->mother, L.cpos, comb, A.pos32, n, m, t->init, t->n_ids, L.init2, fin, s);
+    // the first pass needs only the probes' pre-statuses: read through the partition's
+    // destinations, with no replay to program order
+    const DeclPre pre = launch_bucket_pre_combined(words, m, t->n_ids, t->init, comb, t->scratch.p, t->ctl, s, cu);
+    launch_dyn_inherit_words(t->mother, L.cpos, pre.res, pre.dstidx, A.pos32, n, m, t->init, t->n_ids, L.init2, fin, s);
     launch_bucket_check_combined(words, m, t->n_ids, L.init2, comb, fin, comb_viol, t->scratch.p, t->ctl, s, cu,
                                  nullptr);
     launch_extract_primary(comb, A.pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
