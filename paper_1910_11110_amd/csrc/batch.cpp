@@ -51,6 +51,7 @@ struct BatchState {
     struct Group {
         uint64_t item_lo, m;
         uint32_t key_lo, k;
+        uint32_t t_lo, t_hi; // its traces
     };
     bool bucket = false;
     uint64_t MB = 0; // combined slots: every trace's range padded to a multiple of 16
@@ -194,16 +195,19 @@ void plan_groups(BatchState &b, std::vector<TraceDesc> &desc)
     b.MB = item;
     if (!b.bucket)
         return;
-    BatchState::Group g{0, 0, 0, 0};
-    for (TraceDesc &d : desc) {
+    BatchState::Group g{0, 0, 0, 0, 0, 0};
+    for (uint32_t t = 0; t < (uint32_t)desc.size(); t++) {
+        TraceDesc &d = desc[t];
         if (g.k && (g.k + d.n_ids > kmax || g.m + padded(d.m) >= (1ull << 32))) { // (a trace above kmax: a group alone)
+            g.t_hi = t;
             b.groups.push_back(g);
-            g = BatchState::Group{d.item_base, 0, d.key_base, 0};
+            g = BatchState::Group{d.item_base, 0, d.key_base, 0, t, t};
         }
         d.key_local = g.k;
         g.k += d.n_ids;
         g.m += padded(d.m);
     }
+    g.t_hi = (uint32_t)desc.size();
     b.groups.push_back(g);
 }
 
@@ -263,19 +267,24 @@ void enqueue_pipeline(BatchState &b, hipStream_t s)
         uint32_t *words = (uint32_t *)b.words.p;
         uint8_t *comb = (uint8_t *)b.comb.p, *init_all = (uint8_t *)b.init_all.p, *fin_all = (uint8_t *)b.fin_all.p;
         launch_batch_chunk_words(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, words, b.MB, s);
-        // one bucket check per group (final statuses into the group's slice of fin_all,
-        // which holds the initial statuses); their errors are folded into the batch's
-        for (const BatchState::Group &g : b.groups) {
-            launch_bucket_check_combined(words + g.item_lo, g.m, g.k, init_all + g.key_lo, comb + g.item_lo,
-                                         fin_all + g.key_lo, nullptr, b.scratch.p, b.gctl, s, 0, nullptr);
-            launch_merge_errors(b.ctl, b.gctl, s);
-        }
-        // status bytes to the traces, flagged events counted per chunk, their offsets,
-        // then the violation lists and the counts
+        // one bucket pass per group (final statuses into the group's slice of fin_all,
+        // which holds the initial statuses; their errors are folded into the batch's);
+        // its results stay in the partitioned order, and the group's chunks take their
+        // status bytes from there into the traces' buffers before the next pass reuses
+        // the scratch, counting flagged events per chunk
         uint32_t *vcnt = (uint32_t *)b.vcnt.p;
         uint64_t *vpos = (uint64_t *)b.vpos.p;
-        launch_batch_chunk_status(d, ch, b.n_chunks, (const uint64_t *)b.pos.p, comb, b.MB, vcnt,
-                                  (unsigned long long *)b.ind.p, s);
+        for (const BatchState::Group &g : b.groups) {
+            const DeclPre r = launch_bucket_status_partitioned_combined(
+                words + g.item_lo, g.m, g.k, init_all + g.key_lo, comb + g.item_lo, fin_all + g.key_lo, b.scratch.p,
+                b.gctl, s, 0);
+            launch_merge_errors(b.ctl, b.gctl, s);
+            const uint64_t c_lo = b.h_desc[g.t_lo].first_chunk;
+            const uint64_t c_hi = g.t_hi < n ? b.h_desc[g.t_hi].first_chunk : b.n_chunks;
+            launch_batch_chunk_status(d, ch, c_lo, c_hi, (const uint64_t *)b.pos.p, r.res, r.dstidx, g.item_lo, g.m,
+                                      vcnt, (unsigned long long *)b.ind.p, s);
+        }
+        // the flagged events' offsets, then the violation lists and the counts
         launch_excl_scan(vcnt, b.n_chunks, vpos, nullptr, b.scratch.p, b.ctl->tickets[7], s);
         launch_batch_chunk_viol(d, ch, b.n_chunks, vcnt, vpos, s);
         launch_batch_finish(d, n, b.n_chunks, vpos, (const uint8_t *)b.fin_all.p, b.ctl,
@@ -326,6 +335,27 @@ bool tuning_on() { return !getenv("VC_NO_AUTOTUNE"); }
 
 std::string bucket_key(uint64_t N, uint64_t K) { return "bucket:" + shape_key(N, K); }
 
+// FNV-1a digest of every trace's status bytes (read back from the device, one trace at
+// a time)
+bool status_digests(const BatchState &b, std::vector<uint64_t> &out)
+{
+    out.assign(b.h_desc.size(), 0);
+    std::vector<uint8_t> buf;
+    for (size_t t = 0; t < b.h_desc.size(); t++) {
+        const TraceDesc &d = b.h_desc[t];
+        buf.resize(d.n);
+        if (d.n && hipMemcpy(buf.data(), d.status, d.n, hipMemcpyDeviceToHost) != hipSuccess)
+            return false;
+        uint64_t h = 0xcbf29ce484222325ull;
+        for (uint8_t v : buf) {
+            h ^= v;
+            h *= 0x100000001b3ull;
+        }
+        out[t] = h;
+    }
+    return true;
+}
+
 // the bucket route's settings for this batch: the cached choice, or every candidate
 // timed on the batch itself, keeping only those whose status bytes equal the first
 // candidate's (a race or a tiling bug would change bytes)
@@ -338,7 +368,7 @@ int autotune_bucket(vc_ctx *c, BatchState &b)
     };
     const std::vector<Cand> cands = { { 22, BATCH_CHUNK_PLAIN }, { 20, BATCH_CHUNK_PLAIN }, { 21, BATCH_CHUNK_PLAIN },
                                       { 22, 4 * BATCH_CHUNK_PLAIN }, { 20, 4 * BATCH_CHUNK_PLAIN } };
-    std::vector<uint8_t> ref, got;
+    std::vector<uint64_t> ref, got;
     float best = 1e30f;
     Cand pick = cands[0];
     hipEvent_t e0, e1;
@@ -362,9 +392,8 @@ int autotune_bucket(vc_ctx *c, BatchState &b)
         }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        // the combined status bytes (their layout does not depend on these settings)
-        got.resize(b.MB);
-        if (b.MB && hipMemcpy(got.data(), b.comb.p, b.MB, hipMemcpyDeviceToHost) != hipSuccess) {
+        // a digest of every trace's status bytes
+        if (!status_digests(b, got)) {
             r = vc_fail(VC_EDEVICE, "autotune read-back failed");
             break;
         }

@@ -50,12 +50,14 @@ void launch_batch_chunk_emit(const TraceDesc *d, const ChunkDesc *ch, uint64_t n
 // next multiple of 16 (below cap), get a no-op word
 void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
                               uint32_t *words, uint64_t cap, hipStream_t s);
-// bucket route: every chunk's primaries' status bytes from the combined status bytes
-// into its trace's status buffer, the number of them flagged into vcnt[chunk], and per
-// trace the flagged induced items into ind
-void launch_batch_chunk_status(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
-                               const uint8_t *comb, uint64_t cap, uint32_t *vcnt, unsigned long long *ind,
-                               hipStream_t s);
+// bucket route, after the bucket pass of one group (items [g_lo, g_lo + g_m), results
+// res in the partitioned order through dstidx, or in combined order when dstidx is
+// null), for the chunks [c_lo, c_hi) of its traces: every chunk's primaries' status
+// bytes into its trace's status buffer, the number of them flagged into vcnt[chunk], and
+// per trace the flagged induced items into ind
+void launch_batch_chunk_status(const TraceDesc *d, const ChunkDesc *ch, uint64_t c_lo, uint64_t c_hi,
+                               const uint64_t *chunk_pos, const uint8_t *res, const uint32_t *dstidx, uint64_t g_lo,
+                               uint64_t g_m, uint32_t *vcnt, unsigned long long *ind, hipStream_t s);
 // bucket route: every chunk's flagged events into its trace's violation list (ascending,
 // trace-relative), from vpos = the exclusive prefix of vcnt over the batch
 void launch_batch_chunk_viol(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint32_t *vcnt,

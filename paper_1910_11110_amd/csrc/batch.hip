@@ -384,33 +384,49 @@ __device__ __forceinline__ uint32_t count_flags(const uint8_t *__restrict__ comb
     return n;
 }
 
-// bucket route: every chunk's primaries' status bytes from the combined bytes into the
-// trace's status buffer, the number of them flagged (vcnt), and per trace the flagged
-// induced items (ind).  A trace without arrays copies its chunk 16 bytes per lane
-// (CH_ILP loads in flight) when both sides are 16-byte aligned.  A trace with arrays
-// finds each event's slot from a wave scan of the events' item counts, and counts its
-// flagged induced items as the flagged bytes of the chunk's item range less the flagged
-// primaries.
+// the status byte of the item at position rel of a group (relative to the group's first
+// item): from the group's results in the partitioned order through its destinations, or
+// in combined order when dstidx is null (gm: the group's items; rel < gm)
+__device__ __forceinline__ uint8_t group_status(const uint8_t *__restrict__ res, const uint32_t *__restrict__ dstidx,
+                                                uint64_t rel, uint64_t gm)
+{
+    const uint64_t j = dstidx ? dstidx[rel] : rel;
+    return res[j < gm ? j : gm - 1]; // (in range for consistent counts)
+}
+
+// bucket route, after one group's bucket pass, for the chunks [c_lo, c_hi) of its
+// traces: every chunk's primaries' status bytes into the trace's status buffer, the
+// number of them flagged (vcnt), and per trace the flagged induced items (ind).  A trace
+// without arrays takes 16 events per lane: a 16-byte copy when the group's results are
+// in combined order, else four 16-byte loads of destinations and 16 byte gathers (the
+// partition keeps program order inside a bucket, so a trace's events read runs).  A
+// trace with arrays finds each event's slot from a wave scan of the events' item
+// counts, and counts its flagged induced items as the flagged items of the chunk's
+// range less its flagged primaries.
 __global__ __launch_bounds__(BLOCK) void k_batch_chunk_status(const TraceDesc *__restrict__ d,
-                                                              const ChunkDesc *__restrict__ ch, uint64_t n_chunks,
-                                                              const uint64_t *__restrict__ chunk_pos,
-                                                              const uint8_t *__restrict__ comb, uint64_t cap,
-                                                              uint32_t *__restrict__ vcnt,
+                                                              const ChunkDesc *__restrict__ ch, uint64_t c_lo,
+                                                              uint64_t c_hi, const uint64_t *__restrict__ chunk_pos,
+                                                              const uint8_t *__restrict__ res,
+                                                              const uint32_t *__restrict__ dstidx, uint64_t g_lo,
+                                                              uint64_t g_m, uint32_t *__restrict__ vcnt,
                                                               unsigned long long *__restrict__ ind)
 {
     const uint32_t lane = lane_id();
-    for (uint64_t c = (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < n_chunks;
+    const uint64_t g_hi = g_lo + g_m;
+    for (uint64_t c = c_lo + (uint64_t)blockIdx.x * CH_WAVES + wave_index(); c < c_hi;
          c += (uint64_t)gridDim.x * CH_WAVES) {
         const ChunkDesc cd = ch[c];
         const TraceDesc td = d[cd.trace];
-        const uint64_t lo = td.item_base, hi = td.item_base + td.m < cap ? td.item_base + td.m : cap;
+        const uint64_t lo = td.item_base, hi = td.item_base + td.m < g_hi ? td.item_base + td.m : g_hi;
         const uint64_t base = bucket_base(td, cd, chunk_pos, c);
         uint8_t *dst = td.status + cd.start;
         uint32_t flagged = 0;
         if (!td.off) {
-            const uint8_t *src = comb + base;
-            if (base >= lo && base + cd.len <= hi &&
-                ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u) == 0) {
+            const uint64_t r0 = base - g_lo; // (meaningful when the chunk is in range)
+            const bool in_range = base >= lo && base + cd.len <= hi;
+            const bool dst16 = (reinterpret_cast<uintptr_t>(dst) & 15u) == 0;
+            if (in_range && !dstidx && dst16 && (reinterpret_cast<uintptr_t>(res + r0) & 15u) == 0) {
+                const uint8_t *src = res + r0;
                 for (uint32_t k0 = 0; k0 < cd.len; k0 += 16 * WAVE * CH_ILP) {
                     uint4 v[CH_ILP];
 #pragma unroll
@@ -434,12 +450,42 @@ __global__ __launch_bounds__(BLOCK) void k_batch_chunk_status(const TraceDesc *_
                         }
                     }
                 }
+            } else if (in_range && dstidx && dst16 && (r0 & 3u) == 0) {
+                const uint32_t *ix = dstidx + r0;
+                for (uint32_t k = 16 * lane; k < cd.len; k += 16 * WAVE) {
+                    if (k + 16 <= cd.len) {
+                        uint32_t j[16];
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            const uint4 v = *reinterpret_cast<const uint4 *>(ix + k + 4 * q);
+                            j[4 * q] = v.x;
+                            j[4 * q + 1] = v.y;
+                            j[4 * q + 2] = v.z;
+                            j[4 * q + 3] = v.w;
+                        }
+                        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+                        for (int e = 0; e < 16; e++) {
+                            const uint32_t b = res[j[e] < g_m ? j[e] : g_m - 1];
+                            w[e >> 2] |= b << (8 * (e & 3));
+                        }
+                        *reinterpret_cast<uint4 *>(dst + k) = make_uint4(w[0], w[1], w[2], w[3]);
+                        flagged += __builtin_popcount(byte_msbs(w[0]) | byte_msbs(w[1]) << 4 | byte_msbs(w[2]) << 8 |
+                                                      byte_msbs(w[3]) << 12);
+                    } else {
+                        for (uint32_t e = k; e < cd.len; e++) {
+                            const uint8_t b = group_status(res, dstidx, r0 + e, g_m);
+                            dst[e] = b;
+                            flagged += b >> 7;
+                        }
+                    }
+                }
             } else {
                 for (uint32_t k = lane; k < cd.len; k += WAVE) {
                     const uint64_t p = base + k;
                     if (p < lo || p >= hi)
                         continue; // reported by the word pass
-                    const uint8_t b = comb[p];
+                    const uint8_t b = group_status(res, dstidx, p - g_lo, g_m);
                     dst[k] = b;
                     flagged += b >> 7;
                 }
@@ -465,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_chunk_status(const TraceDesc *_
                 if (k < cd.len) {
                     const uint64_t p = base + carry + inc - len;
                     if (p >= lo && p < hi) { // (else reported by the word pass)
-                        const uint8_t v = comb[p];
+                        const uint8_t v = group_status(res, dstidx, p - g_lo, g_m);
                         dst[k] = v;
                         flagged += v >> 7;
                     }
@@ -474,7 +520,16 @@ __global__ __launch_bounds__(BLOCK) void k_batch_chunk_status(const TraceDesc *_
             }
             // the chunk's items, clamped to the trace's range
             const uint64_t a = base > lo ? base : lo, b = base + carry < hi ? base + carry : hi;
-            const uint32_t all = a < b ? wave_total_u32(count_flags(comb, a, b)) : 0u;
+            uint32_t all = 0;
+            if (a < b) { // uniform
+                uint32_t f = 0;
+                if (!dstidx)
+                    f = count_flags(res, a - g_lo, b - g_lo); // (res and g_m 16-byte multiples)
+                else
+                    for (uint64_t q = a + lane; q < b; q += WAVE)
+                        f += group_status(res, dstidx, q - g_lo, g_m) >> 7;
+                all = wave_total_u32(f);
+            }
             const uint32_t prim = wave_total_u32(flagged);
             if (lane == 0 && all > prim)
                 atomicAdd(&ind[cd.trace], (unsigned long long)(all - prim));
@@ -648,14 +703,14 @@ void launch_batch_chunk_words(const TraceDesc *d, const ChunkDesc *ch, uint64_t 
     }
 }
 
-void launch_batch_chunk_status(const TraceDesc *d, const ChunkDesc *ch, uint64_t n_chunks, const uint64_t *chunk_pos,
-                               const uint8_t *comb, uint64_t cap, uint32_t *vcnt, unsigned long long *ind,
-                               hipStream_t s)
+void launch_batch_chunk_status(const TraceDesc *d, const ChunkDesc *ch, uint64_t c_lo, uint64_t c_hi,
+                               const uint64_t *chunk_pos, const uint8_t *res, const uint32_t *dstidx, uint64_t g_lo,
+                               uint64_t g_m, uint32_t *vcnt, unsigned long long *ind, hipStream_t s)
 {
-    if (n_chunks) {
+    if (c_hi > c_lo && g_m) {
         ProfScope prof_(s, "batch_chunk_status");
-        k_batch_chunk_status<<<gridn(n_chunks, CH_WAVES), BLOCK, 0, s>>>(d, ch, n_chunks, chunk_pos, comb, cap, vcnt,
-                                                                         ind);
+        k_batch_chunk_status<<<gridn(c_hi - c_lo, CH_WAVES), BLOCK, 0, s>>>(d, ch, c_lo, c_hi, chunk_pos, res, dstidx,
+                                                                             g_lo, g_m, vcnt, ind);
     }
 }
 

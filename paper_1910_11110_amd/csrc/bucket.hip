@@ -1127,7 +1127,7 @@ template <class SRC>
 static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, const uint8_t *init, int mode,
                                uint8_t *final_out, const BucketLayout &L, uint8_t *direct_out, Control *ctl,
                                hipStream_t s, int cu, uint32_t *chunk_sum = nullptr, uint32_t final_dup = 0,
-                               bool lookback_cleared = false, hipEvent_t after_hist = nullptr)
+                               bool lookback_cleared = false, hipEvent_t after_hist = nullptr, bool dest = false)
 {
     if (!lookback_cleared)
         launch_clear_lookback(L.lbv, L.btiles_max * LB_WORDS, ctl->tickets[9], s);
@@ -1162,8 +1162,9 @@ static void partition_and_scan(const uint32_t *src, uint64_t n, uint32_t n_ids, 
     uint8_t *res = direct_out;
     if (L.nb > 1) {
         ProfScope p(s, "partition");
-        // the trace check replays by tile runs, the translation by destinations
-        const bool runs = mode == BK_STATUS;
+        // the trace check replays by tile runs, the translation (and a reader of the
+        // partitioned results, dest) by destinations
+        const bool runs = mode == BK_STATUS && !dest;
         if (small_nb)
             k_partition<SRC, 256><<<nranges, BLOCK, 0, s>>>(src, n, n_ids, L.bits, L.base, L.gpre, nranges,
                                                             L.part, runs ? nullptr : L.dstidx,
@@ -1261,6 +1262,22 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
     ProfScope p(s, "replay_bytes");
     const unsigned grid = resident_grid((const void *)k_replay_bytes, ceil_div(n_decl, (uint64_t)BLOCK * 16));
     k_replay_bytes<<<grid, BLOCK, 0, s>>>(L.dstidx, n_decl, L.res, pre);
+}
+
+DeclPre launch_bucket_status_partitioned_combined(const uint32_t *words, uint64_t m, uint32_t n_ids,
+                                                  const uint8_t *init, uint8_t *direct_out, uint8_t *final_out,
+                                                  void *scratch, Control *ctl, hipStream_t s, int cu)
+{
+    BucketLayout L = bucket_layout(scratch, m, n_ids);
+    const FillJob job{L.lbv, (size_t)L.btiles_max * LB_WORDS * sizeof(uint64_t), 0};
+    launch_prep(ctl, nullptr, &job, 1, s);
+    if (m == 0)
+        return DeclPre{direct_out, nullptr};
+    partition_and_scan<CombinedWords>(words, m, n_ids, init, BK_STATUS, final_out, L, direct_out, ctl, s, cu, nullptr,
+                                      0, true, nullptr, true);
+    if (L.nb == 1)
+        return DeclPre{direct_out, nullptr};
+    return DeclPre{L.res, L.dstidx};
 }
 
 DeclPre launch_bucket_pre_combined(const uint32_t *words, uint64_t m, uint32_t n_ids, const uint8_t *init,
