@@ -86,10 +86,13 @@ DeclPre launch_bucket_decl_pre_partitioned(const uint32_t *decls, uint64_t n_dec
 // the status byte of every word of a combined stream (as launch_bucket_check_combined),
 // left in the partitioned order with every word's destination there (res, dstidx), or
 // in program order in direct_out (m bytes) when all ids fall in one bucket (dstidx
-// null); final statuses into final_out; no violations, no replay.  ctl is reset first.
+// null); final statuses into final_out; no violations, no replay.  ctl is reset first,
+// in the same launch as fin_fill when given (the fill of final_out for ids no word
+// touches).
 DeclPre launch_bucket_status_partitioned_combined(const uint32_t *words, uint64_t m, uint32_t n_ids,
                                                   const uint8_t *init, uint8_t *direct_out, uint8_t *final_out,
-                                                  void *scratch, Control *ctl, hipStream_t s, int cu);
+                                                  void *scratch, Control *ctl, hipStream_t s, int cu,
+                                                  const FillJob *fin_fill = nullptr);
 // the status before every word of a combined stream (bits 0-1 of its byte), the way the
 // declarations' pre-statuses come: in the partitioned order with every word's
 // destination there (res, dstidx), or in program order in pre (m bytes) when all ids

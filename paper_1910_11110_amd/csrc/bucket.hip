@@ -1266,11 +1266,14 @@ void launch_bucket_decl_pre(const uint32_t *decls, uint64_t n_decl, uint32_t n_v
 
 DeclPre launch_bucket_status_partitioned_combined(const uint32_t *words, uint64_t m, uint32_t n_ids,
                                                   const uint8_t *init, uint8_t *direct_out, uint8_t *final_out,
-                                                  void *scratch, Control *ctl, hipStream_t s, int cu)
+                                                  void *scratch, Control *ctl, hipStream_t s, int cu,
+                                                  const FillJob *fin_fill)
 {
     BucketLayout L = bucket_layout(scratch, m, n_ids);
-    const FillJob job{L.lbv, (size_t)L.btiles_max * LB_WORDS * sizeof(uint64_t), 0};
-    launch_prep(ctl, nullptr, &job, 1, s);
+    FillJob jobs[2] = {FillJob{L.lbv, (size_t)L.btiles_max * LB_WORDS * sizeof(uint64_t), 0}, FillJob{}};
+    if (fin_fill)
+        jobs[1] = *fin_fill;
+    launch_prep(ctl, nullptr, jobs, fin_fill ? 2 : 1, s);
     if (m == 0)
         return DeclPre{direct_out, nullptr};
     partition_and_scan<CombinedWords>(words, m, n_ids, init, BK_STATUS, final_out, L, direct_out, ctl, s, cu, nullptr,

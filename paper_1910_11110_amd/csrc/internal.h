@@ -260,6 +260,11 @@ void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
 void launch_extract_primary(const uint8_t *comb, const uint32_t *pos32, uint64_t n, uint64_t m, uint8_t *status,
                             Control *ctl, hipStream_t s);
 void launch_induced_finish(Control *ctl, hipStream_t s);
+// the combined stream's flagged items counted into ctl->n_induced_stuck (from zero), and
+// the primaries' status bytes through pos32 and, when the results are in the
+// partitioned order, the destinations there (dstidx)
+void launch_extract_primary_dest(const uint8_t *res, const uint32_t *dstidx, const uint32_t *pos32, uint64_t n,
+                                 uint64_t m, uint8_t *status, Control *ctl, hipStream_t s);
 // folds src's error index and code into dst's
 void launch_merge_errors(Control *dst, const Control *src, hipStream_t s);
 // combined items at position i + pos[i] (pos = exclusive scan of cnt); cap = item capacity

@@ -280,6 +280,55 @@ __global__ void k_extract_primary(const uint8_t *__restrict__ comb, const uint32
     }
 }
 
+// the primaries' status bytes through their combined positions and, when the results
+// are in the partitioned order, the destinations there (dstidx)
+__global__ void k_extract_primary_dest(const uint8_t *__restrict__ res, const uint32_t *__restrict__ dstidx,
+                                       const uint32_t *__restrict__ pos32, uint64_t n, uint64_t m,
+                                       uint8_t *__restrict__ status)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t p = pos32[i];
+        p = p < m ? p : m - 1;
+        if (dstidx) {
+            p = dstidx[p];
+            p = p < m ? p : m - 1; // (in range for consistent counts)
+        }
+        status[i] = res[p];
+    }
+}
+
+// flagged bytes of res[0, m) (any order) added to *count: 16 bytes per thread and step
+// (res 16-byte aligned), one add per workgroup
+__global__ __launch_bounds__(BLOCK) void k_count_flagged(const uint8_t *__restrict__ res, uint64_t m,
+                                                         unsigned long long *__restrict__ count)
+{
+    __shared__ uint32_t s_w[BLOCK / WAVE];
+    uint32_t c = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 16;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16; i0 < m; i0 += stride) {
+        if (i0 + 16 <= m) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(res + i0);
+            c += __builtin_popcount(v.x & 0x80808080u) + __builtin_popcount(v.y & 0x80808080u) +
+                 __builtin_popcount(v.z & 0x80808080u) + __builtin_popcount(v.w & 0x80808080u);
+        } else {
+            for (uint64_t i = i0; i < m; i++)
+                c += res[i] >> 7;
+        }
+    }
+    c = wave_total_u32(c);
+    if (lane_id() == 0)
+        s_w[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t w = 0; w < BLOCK / WAVE; w++)
+            t += s_w[w];
+        if (t)
+            atomicAdd(count, (unsigned long long)t);
+    }
+}
+
 __global__ void k_induced_finish(Control *ctl)
 {
     if (threadIdx.x == 0)
@@ -453,6 +502,20 @@ void launch_extract_primary(const uint8_t *comb, const uint32_t *pos32, uint64_t
 }
 
 void launch_induced_finish(Control *ctl, hipStream_t s) { k_induced_finish<<<1, 64, 0, s>>>(ctl); }
+
+void launch_extract_primary_dest(const uint8_t *res, const uint32_t *dstidx, const uint32_t *pos32, uint64_t n,
+                                 uint64_t m, uint8_t *status, Control *ctl, hipStream_t s)
+{
+    if (m) {
+        ProfScope p(s, "count_flagged");
+        k_count_flagged<<<blocks_for(ceil_div(m, (uint64_t)16), BLOCK * 16), BLOCK, 0, s>>>(res, m,
+                                                                                            &ctl->n_induced_stuck);
+    }
+    if (n) {
+        ProfScope p(s, "extract_primary");
+        k_extract_primary_dest<<<blocks_for(n, BLOCK * 8), BLOCK, 0, s>>>(res, dstidx, pos32, n, m ? m : 1, status);
+    }
+}
 
 namespace {
 __global__ void k_merge_errors(Control *dst, const Control *src)

@@ -399,7 +399,6 @@ int overlap_bucket_enqueue(vc_trace *t, hipStream_t s)
     Control *xctl = (Control *)((char *)t->aux.p + pos_bytes + tcnt_bytes + tpos_bytes);
     uint32_t *words = (uint32_t *)t->items_a.p;
     uint8_t *comb = (uint8_t *)t->items_b.p;
-    uint32_t *comb_viol = (uint32_t *)((char *)t->items_b.p + ((m + 255) & ~uint64_t(255)));
     launch_reset_control(xctl, s);
     launch_overlap_tile_count(t->events, n, t->n_ids, &t->sets, tcnt, xctl, s);
     launch_excl_scan(tcnt, ntiles, tpos, nullptr, t->scratch.p, xctl->tickets[5], s);
@@ -408,9 +407,13 @@ int overlap_bucket_enqueue(vc_trace *t, hipStream_t s)
     const FillJob fill{fin, t->n_ids, 1};
     if (t->init)
         (void)hipMemcpyAsync(fin, t->init, t->n_ids, hipMemcpyDeviceToDevice, s);
-    launch_bucket_check_combined(words, m, t->n_ids, t->init, comb, fin, comb_viol, t->scratch.p, t->ctl, s,
-                                 t->ctx->cu_count, t->init ? nullptr : &fill);
-    launch_extract_primary(comb, pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
+    // the results stay in the partitioned order (no replay to combined order): the
+    // primaries' bytes come through their destinations, and the flagged items of the
+    // combined stream are counted there
+    const DeclPre res = launch_bucket_status_partitioned_combined(words, m, t->n_ids, t->init, comb, fin,
+                                                                  t->scratch.p, t->ctl, s, t->ctx->cu_count,
+                                                                  t->init ? nullptr : &fill);
+    launch_extract_primary_dest(res.res, res.dstidx, pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
     launch_compact((uint8_t *)t->status.p, n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
     launch_induced_finish(t->ctl, s);
     launch_merge_errors(t->ctl, xctl, s);
