@@ -254,11 +254,7 @@ void launch_overlap_tile_count(const uint32_t *ev, uint64_t n, uint32_t n_arrays
                                uint32_t *tcnt, Control *ctl, hipStream_t s);
 void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, const OverlapSets *o, const uint64_t *tpos,
                           uint32_t *words, uint64_t cap, uint32_t *pos32, Control *ctl, hipStream_t s);
-// status[i] = comb[pos32[i]] (m bytes of comb); ctl->n_induced_stuck = ctl->n_viol (the
-// combined stream's flagged items); after the primaries' compaction,
-// launch_induced_finish subtracts the flagged primaries
-void launch_extract_primary(const uint8_t *comb, const uint32_t *pos32, uint64_t n, uint64_t m, uint8_t *status,
-                            Control *ctl, hipStream_t s);
+// after the primaries' compaction: ctl->n_induced_stuck less the flagged primaries
 void launch_induced_finish(Control *ctl, hipStream_t s);
 // the combined stream's flagged items counted into ctl->n_induced_stuck (from zero), and
 // the primaries' status bytes through pos32 and, when the results are in the

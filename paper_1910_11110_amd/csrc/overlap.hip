@@ -266,20 +266,6 @@ __global__ __launch_bounds__(BLOCK) void k_xw_words(const uint32_t *__restrict__
     }
 }
 
-// primary status bytes from the combined stream (event i sits at pos32[i]); the stuck
-// induced items are the combined stream's flagged items less the primaries'
-__global__ void k_extract_primary(const uint8_t *__restrict__ comb, const uint32_t *__restrict__ pos32, uint64_t n,
-                                  uint64_t m, uint8_t *__restrict__ status, Control *ctl)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        ctl->n_induced_stuck = ctl->n_viol; // the combined stream's flagged items
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t p = pos32[i];
-        status[i] = comb[p < m ? p : m - 1];
-    }
-}
-
 // the primaries' status bytes through their combined positions and, when the results
 // are in the partitioned order, the destinations there (dstidx)
 __global__ void k_extract_primary_dest(const uint8_t *__restrict__ res, const uint32_t *__restrict__ dstidx,
@@ -494,12 +480,6 @@ void launch_overlap_words(const uint32_t *ev, uint64_t n, uint32_t n_arrays, con
                                                                               ntiles, words, cap, pos32, ctl);
 }
 
-void launch_extract_primary(const uint8_t *comb, const uint32_t *pos32, uint64_t n, uint64_t m, uint8_t *status,
-                            Control *ctl, hipStream_t s)
-{
-    ProfScope prof_(s, "extract_primary");
-    k_extract_primary<<<blocks_for(n ? n : 1, BLOCK * 8), BLOCK, 0, s>>>(comb, pos32, n, m ? m : 1, status, ctl);
-}
 
 void launch_induced_finish(Control *ctl, hipStream_t s) { k_induced_finish<<<1, 64, 0, s>>>(ctl); }
 

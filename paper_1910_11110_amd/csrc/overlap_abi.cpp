@@ -299,7 +299,6 @@ static int dynamic_bucket_enqueue(vc_trace *t, hipStream_t s)
     const DynLayout L = dyn_layout(t->dyn.p, n, t->n_ids, t->sets.n_nbr);
     uint32_t *words = (uint32_t *)t->items_a.p;
     uint8_t *comb = (uint8_t *)t->items_b.p, *fin = (uint8_t *)t->fin.p;
-    uint32_t *comb_viol = (uint32_t *)((char *)t->items_b.p + ((m + 255) & ~uint64_t(255)));
     launch_dyn_words(t->events, n, t->n_ids, t->mother, L.cpos, L.dpos, &t->sets, L.life, A.tpos, words, A.pos32, m,
                      A.xctl, s);
     const int cu = t->ctx->cu_count;
@@ -307,9 +306,11 @@ static int dynamic_bucket_enqueue(vc_trace *t, hipStream_t s)
     // destinations, with no replay to program order
     const DeclPre pre = launch_bucket_pre_combined(words, m, t->n_ids, t->init, comb, t->scratch.p, t->ctl, s, cu);
     launch_dyn_inherit_words(t->mother, L.cpos, pre.res, pre.dstidx, A.pos32, n, m, t->init, t->n_ids, L.init2, fin, s);
-    launch_bucket_check_combined(words, m, t->n_ids, L.init2, comb, fin, comb_viol, t->scratch.p, t->ctl, s, cu,
-                                 nullptr);
-    launch_extract_primary(comb, A.pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
+    // the second pass's results stay in the partitioned order too: the primaries' bytes
+    // come through the destinations, and the combined flagged items are counted there
+    const DeclPre res = launch_bucket_status_partitioned_combined(words, m, t->n_ids, L.init2, comb, fin,
+                                                                  t->scratch.p, t->ctl, s, cu);
+    launch_extract_primary_dest(res.res, res.dstidx, A.pos32, n, m, (uint8_t *)t->status.p, t->ctl, s);
     launch_compact((uint8_t *)t->status.p, n, (uint32_t *)t->viol.p, t->scratch.p, t->ctl, s);
     launch_induced_finish(t->ctl, s);
     launch_merge_errors(t->ctl, A.xctl, s);
