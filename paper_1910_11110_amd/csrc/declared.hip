@@ -354,12 +354,18 @@ __global__ void k_wd_finish(const uint64_t *__restrict__ comp_off, uint64_t n_co
         const uint64_t a = comp_off[c], b = comp_off[c + 1];
         if (b >= a && b <= comp_off[n_comp])
             for (uint64_t d = a; d < b && !(v & WD_UNWRITTEN); d++) {
-                const uint64_t p0 = boff[d], p1 = p0 + wlen[d];
-                for (uint64_t p = p0; p < p1 && p < nbits; p++)
-                    if (!((bits[p >> 5] >> (p & 31u)) & 1u)) {
+                // the declaration's obligation bits [p0, p1), a 32-bit word at a time
+                const uint64_t p0 = boff[d], e = p0 + wlen[d], p1 = e < nbits ? e : nbits;
+                for (uint64_t p = p0; p < p1;) {
+                    const uint32_t b0 = (uint32_t)(p & 31u);
+                    const uint64_t span = p1 - p < 32u - b0 ? p1 - p : 32u - b0;
+                    const uint32_t mask = (span == 32 ? ~0u : ((1u << span) - 1u)) << b0;
+                    if ((bits[p >> 5] & mask) != mask) {
                         v |= WD_UNWRITTEN;
                         break;
                     }
+                    p += span;
+                }
             }
         out[c] = (uint8_t)(v | (v ? WD_ILL : 0u));
     }
