@@ -1,17 +1,20 @@
 // batch.cpp -- vc_batch_check: independent traces checked in one captured pipeline.
 //
 // The traces' events are relocated into one key space (ids of trace i start at the
-// sum of the id counts before it) and one index space, and the results are split back
-// into each trace's buffers by one kernel.  When every trace fits the bucket engine, the
-// combined stream (events and induced items) is written as 32-bit words and the traces
-// are checked by groups of consecutive traces whose ids fit one bucket engine's key
-// space, one bucket check per group over its slice of the stream; otherwise the whole
-// batch goes through the sort / segmented scan / compaction of a single trace.  The launch sequence of a batch is
-// captured once in a hipGraph and replayed while the batch (its traces, their sizes
-// and buffers) is unchanged.  The sort's digit width and the persistent grid bound
-// come from an autotuner that times candidate settings on the batch itself, keeps
-// only settings whose output bytes equal the first candidate's, and caches the choice
-// per shape in a small JSON file.
+// sum of the id counts before it) and one index space.  When every trace fits the
+// bucket engine, the combined stream (events and induced items) is written as 32-bit
+// words and the traces are checked by groups of consecutive traces whose ids fit one
+// bucket engine's key space, one bucket pass per group over its slice of the stream,
+// each followed by a pass that takes the group's status bytes through the partition's
+// destinations into the traces' buffers; violation lists and counts then go straight
+// to the traces.  Otherwise the whole batch goes through the sort / segmented scan /
+// compaction of a single trace and one kernel splits the results back into each
+// trace's buffers.  The launch sequence of a batch is captured once in a hipGraph and
+// replayed while the batch (its traces, their sizes and buffers) is unchanged.  The
+// settings (ids per group and events per chunk on the bucket route, the sort's digit
+// width and persistent grid bound otherwise) come from an autotuner that times
+// candidate settings on the batch itself, keeps only settings whose results equal the
+// first candidate's, and caches the choice per shape in a small JSON file.
 #include <hip/hip_runtime.h>
 
 #include <stdio.h>
