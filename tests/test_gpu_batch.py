@@ -339,6 +339,10 @@ def test_batch_bucket_route_autotuner(ctx, tmp_path):
         text = cache.read_text()
         assert "bucket:gfx950" in text, text
         say(f"[batch] bucket route tuned: {text.strip()}")
+        # the batch info gives the bucket route's settings: ids per group (a power of two)
+        # and events per chunk of a trace without arrays, among the candidates
+        graph, bits, chunk, scan = C_info(V, ctx)
+        assert bits in (20, 21, 22) and chunk in (4096, 16384) and scan == 0, (bits, chunk, scan)
         for t in traces:
             t.free()
         traces = load_all(ctx, inputs)  # same shape, new handles: the cached choice
